@@ -1,0 +1,159 @@
+"""FP64 CPU oracle for exemplar-based clustering (EBC).
+
+TEST INFRASTRUCTURE ONLY. Nothing on the product path may import, call or
+link this module; only the test-suite, the smoke check and the CPU-baseline
+leg of the benchmark use it. It shares no code with the HIP library.
+
+Everything here is the plain definition from the paper, in float64, with
+direct differences (never the norm expansion), so that it can be checked
+against the paper by eye:
+
+* k-medoids loss, Sec. 4, Definition "k-medoids loss" (Eq. k_medoids_loss):
+  L(S) = |V|^-1 sum_{v in V} min_{s in S} d(v, s).
+* Exemplar-based clustering, Sec. 4, Definition "Exemplar-based clustering"
+  (Eq. exemplar_based_clustering): f(S) = L({e0}) - L(S u {e0}), e0 = 0.
+* CPU evaluation, Sec. 4.1, Algorithm 1: per ground point a running minimum
+  over the set, a sum over the ground points, division by |V|.
+* Discrete derivative, Sec. 3, Definition "Discrete derivative":
+  Delta(e | S) = f(S u {e}) - f(S).
+* Greedy for the cardinality-constrained problem, Sec. 3 (Eq.
+  submodular_function_optimization_cardinality_constraint and the text after
+  it) and Sec. 4.1 (greedy picks the not-yet-selected item of largest
+  marginal gain).
+* The dissimilarity is the squared Euclidean distance, Sec. 5 (experimental
+  setup).
+
+Readings where the paper is silent (each listed in the design notes):
+e0 is the zero vector; ties in the greedy argmax go to the lowest index;
+greedy keeps picking (gain 0) once every point is covered; sets are lists of
+row indices into V, may be empty and may repeat an index.
+
+Pins: tests/test_oracle_pins.py checks every function here against closed
+forms, hand-derived tiny cases, exhaustive search, a library distance
+routine and the submodularity/monotonicity invariants.
+"""
+from __future__ import annotations
+
+import itertools
+
+import numpy as np
+
+__all__ = [
+    "sqdist",
+    "loss",
+    "f_value",
+    "eval_sets",
+    "marginal_gain",
+    "gains",
+    "greedy",
+    "exhaustive",
+    "min_dist_to_set",
+]
+
+
+def sqdist(a: np.ndarray, b: np.ndarray) -> np.ndarray:
+    """Squared Euclidean distance d(a, b) = sum_k (a_k - b_k)^2 (Sec. 5), in
+    float64 by direct differences. ``a`` is [n, d] or [d]; ``b`` is [d]."""
+    diff = np.asarray(a, dtype=np.float64) - np.asarray(b, dtype=np.float64)
+    return np.sum(diff * diff, axis=-1)
+
+
+def loss(x: np.ndarray, s_vectors) -> float:
+    """k-medoids loss L(V, S) as in Algorithm 1 (function L): for every ground
+    point v a running minimum t over the vectors of S, then the sum of the t's
+    divided by |V|. The running minimum starts at +inf (Algorithm 1 uses the
+    largest float). ``s_vectors`` is an iterable of d-vectors; S must be
+    non-empty for the result to be finite."""
+    x = np.asarray(x, dtype=np.float64)
+    t = np.full(x.shape[0], np.inf)
+    for s in s_vectors:
+        t = np.minimum(t, sqdist(x, s))
+    return float(np.sum(t) / x.shape[0])
+
+
+def f_value(x: np.ndarray, s_idx) -> float:
+    """f(S) = L({e0}) - L(S u {e0}) with e0 the zero vector (Eq.
+    exemplar_based_clustering; Algorithm 1, return statement). ``s_idx`` lists
+    row indices of x forming S (may be empty)."""
+    x = np.asarray(x, dtype=np.float64)
+    e0 = np.zeros(x.shape[1])
+    members = [x[int(i)] for i in s_idx]
+    return loss(x, [e0]) - loss(x, [e0] + members)
+
+
+def eval_sets(x: np.ndarray, offsets: np.ndarray, idx: np.ndarray) -> np.ndarray:
+    """f(S_j) for every set of a CSR-packed family S_multi = {S_1, .., S_l}
+    (Sec. 4.1: optimisers score many sets per step). Set j holds
+    idx[offsets[j]:offsets[j+1]]."""
+    l = len(offsets) - 1
+    out = np.empty(l)
+    for j in range(l):
+        out[j] = f_value(x, idx[offsets[j]:offsets[j + 1]])
+    return out
+
+
+def min_dist_to_set(x: np.ndarray, s_idx) -> np.ndarray:
+    """m_v = min(d(v, e0), min_{s in S} d(v, s)) for every v: the per-point
+    term inside L(S u {e0}) (Eq. loss_decomposed, times |V|)."""
+    x = np.asarray(x, dtype=np.float64)
+    m = sqdist(x, np.zeros(x.shape[1]))
+    for i in s_idx:
+        m = np.minimum(m, sqdist(x, x[int(i)]))
+    return m
+
+
+def marginal_gain(x: np.ndarray, m: np.ndarray, c: int) -> float:
+    """Delta(c | S) given m = min_dist_to_set(x, S).
+
+    From the definitions: f(S u {c}) - f(S) = L(S u {e0}) - L(S u {c} u {e0})
+    = |V|^-1 sum_v [m_v - min(m_v, d(v, c))] = |V|^-1 sum_v max(0, m_v - d(v, c)).
+    The tests check this against the literal difference of two f_value calls.
+    """
+    x = np.asarray(x, dtype=np.float64)
+    dist = sqdist(x, x[int(c)])
+    return float(np.sum(np.maximum(0.0, m - dist)) / x.shape[0])
+
+
+def gains(x: np.ndarray, m: np.ndarray, cand=None) -> np.ndarray:
+    """Delta(c | S) for every candidate c (default: every row of x)."""
+    n = x.shape[0]
+    cand = range(n) if cand is None else cand
+    return np.array([marginal_gain(x, m, c) for c in cand], dtype=np.float64)
+
+
+def greedy(x: np.ndarray, k: int):
+    """Greedy maximisation of f under |S| <= k (Sec. 3; Sec. 4.1).
+
+    Each step scores every not-yet-selected point by its marginal gain,
+    picks the largest (lowest index among equal float64 values), and extends
+    S. Returns (selected indices [k], f(S_1..S_k) [k], gains [k])."""
+    x = np.asarray(x, dtype=np.float64)
+    n = x.shape[0]
+    l0 = float(np.sum(sqdist(x, np.zeros(x.shape[1]))) / n)
+    m = min_dist_to_set(x, [])
+    chosen = np.zeros(n, dtype=bool)
+    sel, fs, gs = [], [], []
+    for _ in range(k):
+        g = gains(x, m)
+        g[chosen] = -np.inf
+        c = int(np.argmax(g))  # first maximum = lowest index on ties
+        sel.append(c)
+        gs.append(float(g[c]))
+        chosen[c] = True
+        m = np.minimum(m, sqdist(x, x[c]))
+        fs.append(l0 - float(np.sum(m) / n))
+    return np.array(sel, dtype=np.int64), np.array(fs), np.array(gs)
+
+
+def exhaustive(x: np.ndarray, k: int):
+    """max_{S subset V, |S| <= k} f(S) by enumerating every subset (Eq.
+    submodular_function_optimization_cardinality_constraint). Tiny n only.
+    Returns (best value, best subset as a tuple)."""
+    n = x.shape[0]
+    best, arg = 0.0, ()
+    for size in range(0, k + 1):
+        for s in itertools.combinations(range(n), size):
+            v = f_value(x, s)
+            if v > best:
+                best, arg = v, s
+    return best, arg

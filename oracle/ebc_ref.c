@@ -1,0 +1,156 @@
+/*
+ * FP64 CPU oracle for exemplar-based clustering (EBC), plain C99 + OpenMP.
+ *
+ * TEST INFRASTRUCTURE ONLY: used by the test-suite, the smoke check and the
+ * CPU-baseline leg of the benchmark, never by the product path. It shares no
+ * source, header or helper with the HIP library.
+ *
+ * These are the same definitions as oracle/ebc_oracle.py, written as loops so
+ * that they finish at the benchmark sizes:
+ *   - squared Euclidean dissimilarity (Sec. 5), direct differences in double;
+ *   - k-medoids loss and f(S) = L({e0}) - L(S u {e0}) with e0 = 0
+ *     (Sec. 4, Eqs. k_medoids_loss and exemplar_based_clustering; Alg. 1);
+ *   - marginal gain Delta(c|S) = |V|^-1 sum_v max(0, m_v - d(v,c)), where
+ *     m_v = min(d(v,e0), min_{s in S} d(v,s)) (Sec. 3, discrete derivative);
+ *   - greedy over all not-yet-selected points (Sec. 3 and Sec. 4.1), ties to
+ *     the lowest index.
+ * The only parallelism is over independent candidates or sets, as in the
+ * paper's multi-threaded CPU variant (Sec. 5); every sum over ground points
+ * runs sequentially in index order, so results do not depend on threads.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+static double sqd(const float* a, const float* b, int d)
+{
+    double s = 0.0;
+    for (int k = 0; k < d; ++k) {
+        double t = (double)a[k] - (double)b[k];
+        s += t * t;
+    }
+    return s;
+}
+
+static double sqn(const float* a, int d)
+{
+    double s = 0.0;
+    for (int k = 0; k < d; ++k) s += (double)a[k] * (double)a[k];
+    return s;
+}
+
+int ebc_ref_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+/* m[v] = min(d(v, e0), min_{s in S} d(v, s)) for all v. */
+void ebc_ref_min_dist(const float* x, int64_t n, int32_t d, const int32_t* s, int64_t ns,
+                      double* m)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t v = 0; v < n; ++v) {
+        const float* xv = x + v * d;
+        double t = sqn(xv, d);
+        for (int64_t j = 0; j < ns; ++j) {
+            double dv = sqd(xv, x + (int64_t)s[j] * d, d);
+            if (dv < t) t = dv;
+        }
+        m[v] = t;
+    }
+}
+
+/* out[i] = |V|^-1 sum_v max(0, m[v] - d(v, cand[i])). */
+void ebc_ref_gains(const float* x, int64_t n, int32_t d, const double* m, const int32_t* cand,
+                   int64_t nc, double* out)
+{
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t i = 0; i < nc; ++i) {
+        const float* xc = x + (int64_t)cand[i] * d;
+        double acc = 0.0;
+        for (int64_t v = 0; v < n; ++v) {
+            double g = m[v] - sqd(x + v * d, xc, d);
+            if (g > 0.0) acc += g;
+        }
+        out[i] = acc / (double)n;
+    }
+}
+
+/* f(S_j) = L({e0}) - L(S_j u {e0}) for CSR sets; set j = idx[off[j] .. off[j+1]). */
+void ebc_ref_eval_sets(const float* x, int64_t n, int32_t d, const int64_t* off,
+                       const int32_t* idx, int64_t l, double* out)
+{
+    double l0 = 0.0;
+    for (int64_t v = 0; v < n; ++v) l0 += sqn(x + v * d, d);
+    l0 /= (double)n;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t j = 0; j < l; ++j) {
+        double sum = 0.0;
+        for (int64_t v = 0; v < n; ++v) {
+            const float* xv = x + v * d;
+            double t = sqn(xv, d); /* e0 = 0 is always in the set */
+            for (int64_t q = off[j]; q < off[j + 1]; ++q) {
+                double dv = sqd(xv, x + (int64_t)idx[q] * d, d);
+                if (dv < t) t = dv;
+            }
+            sum += t;
+        }
+        out[j] = l0 - sum / (double)n;
+    }
+}
+
+/* Greedy to cardinality k. sel[t], f[t] = f(S_{t+1}), g[t] = gain of step t.
+ * Returns 0, -1 if memory runs out, -2 if k > n. */
+int ebc_ref_greedy(const float* x, int64_t n, int32_t d, int32_t k, int32_t* sel, double* f,
+                   double* g)
+{
+    double* m = (double*)malloc(sizeof(double) * (size_t)n);
+    double* gv = (double*)malloc(sizeof(double) * (size_t)n);
+    unsigned char* chosen = (unsigned char*)calloc((size_t)n, 1);
+    if (!m || !gv || !chosen) {
+        free(m); free(gv); free(chosen);
+        return -1;
+    }
+    double l0 = 0.0;
+    for (int64_t v = 0; v < n; ++v) {
+        m[v] = sqn(x + v * d, d);
+        l0 += m[v];
+    }
+    l0 /= (double)n;
+    for (int32_t t = 0; t < k; ++t) {
+#pragma omp parallel for schedule(dynamic, 4)
+        for (int64_t c = 0; c < n; ++c) {
+            if (chosen[c]) { gv[c] = -INFINITY; continue; }
+            const float* xc = x + c * d;
+            double acc = 0.0;
+            for (int64_t v = 0; v < n; ++v) {
+                double q = m[v] - sqd(x + v * d, xc, d);
+                if (q > 0.0) acc += q;
+            }
+            gv[c] = acc / (double)n;
+        }
+        int64_t best = -1;
+        for (int64_t c = 0; c < n; ++c)
+            if (!chosen[c] && (best < 0 || gv[c] > gv[best])) best = c;
+        if (best < 0) { free(m); free(gv); free(chosen); return -2; }
+        chosen[best] = 1;
+        sel[t] = (int32_t)best;
+        g[t] = gv[best];
+        double sum = 0.0;
+        for (int64_t v = 0; v < n; ++v) {
+            double dv = sqd(x + v * d, x + best * d, d);
+            if (dv < m[v]) m[v] = dv;
+            sum += m[v];
+        }
+        f[t] = l0 - sum / (double)n;
+    }
+    free(m); free(gv); free(chosen);
+    return 0;
+}

@@ -1,0 +1,82 @@
+"""ctypes wrapper around the plain-C oracle (oracle/ebc_ref.c).
+
+Test infrastructure only. Inputs are NumPy arrays on the host; every result
+is float64. Build the library first with ``oracle.build_ref.build()``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+from .build_ref import LIB
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            raise RuntimeError(f"oracle C library not built: {LIB} (run oracle.build_ref.build())")
+        L = ctypes.CDLL(LIB)
+        P = ctypes.c_void_p
+        i64, i32 = ctypes.c_int64, ctypes.c_int32
+        L.ebc_ref_threads.restype = ctypes.c_int
+        L.ebc_ref_min_dist.argtypes = [P, i64, i32, P, i64, P]
+        L.ebc_ref_gains.argtypes = [P, i64, i32, P, P, i64, P]
+        L.ebc_ref_eval_sets.argtypes = [P, i64, i32, P, P, i64, P]
+        L.ebc_ref_greedy.argtypes = [P, i64, i32, i32, P, P, P]
+        L.ebc_ref_greedy.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _f32(x):
+    return np.ascontiguousarray(x, dtype=np.float32)
+
+
+def _p(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def threads() -> int:
+    return int(lib().ebc_ref_threads())
+
+
+def min_dist(x, s_idx) -> np.ndarray:
+    x = _f32(x)
+    s = np.ascontiguousarray(s_idx, dtype=np.int32)
+    m = np.empty(x.shape[0])
+    lib().ebc_ref_min_dist(_p(x), x.shape[0], x.shape[1], _p(s), s.size, _p(m))
+    return m
+
+
+def gains(x, m, cand=None) -> np.ndarray:
+    x = _f32(x)
+    m = np.ascontiguousarray(m, dtype=np.float64)
+    cand = np.arange(x.shape[0], dtype=np.int32) if cand is None else np.ascontiguousarray(cand, dtype=np.int32)
+    out = np.empty(cand.size)
+    lib().ebc_ref_gains(_p(x), x.shape[0], x.shape[1], _p(m), _p(cand), cand.size, _p(out))
+    return out
+
+
+def eval_sets(x, offsets, idx) -> np.ndarray:
+    x = _f32(x)
+    off = np.ascontiguousarray(offsets, dtype=np.int64)
+    idx = np.ascontiguousarray(idx, dtype=np.int32)
+    out = np.empty(off.size - 1)
+    lib().ebc_ref_eval_sets(_p(x), x.shape[0], x.shape[1], _p(off), _p(idx), off.size - 1, _p(out))
+    return out
+
+
+def greedy(x, k: int):
+    x = _f32(x)
+    sel = np.empty(k, dtype=np.int32)
+    f = np.empty(k)
+    g = np.empty(k)
+    rc = lib().ebc_ref_greedy(_p(x), x.shape[0], x.shape[1], int(k), _p(sel), _p(f), _p(g))
+    if rc != 0:
+        raise ValueError(f"ebc_ref_greedy failed ({rc})")
+    return sel.astype(np.int64), f, g

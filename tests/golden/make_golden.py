@@ -1,0 +1,67 @@
+"""Write the stored expected values under tests/golden/ by calling only the
+oracle (oracle/ebc_oracle.py and oracle/ebc_ref.c) on the seeded synthetic
+workloads. Nothing here touches the HIP library.
+
+    python tests/golden/make_golden.py small      # seconds
+    python tests/golden/make_golden.py gmm100k    # ~2 h on 8 cores (FP64 greedy, k=50)
+
+Each JSON file records the generator, its seed, the SHA-256 of the float32
+input of record, the oracle entry point used, its thread count and wall time.
+"""
+from __future__ import annotations
+
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+from oracle import build_ref, ebc_oracle, ref  # noqa: E402
+from paper_2105_12026_amd import workloads as W  # noqa: E402
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def _dump(name, obj):
+    path = os.path.join(HERE, name)
+    with open(path, "w") as fh:
+        json.dump(obj, fh, indent=1)
+    print("wrote", path, flush=True)
+
+
+def small():
+    p = W.small_normal(seed=0)
+    t0 = time.time()
+    f_sets = ebc_oracle.eval_sets(p.x, p.offsets, p.idx)
+    sel, f, g = ebc_oracle.greedy(p.x, p.k)
+    _dump("normal_n1000_d16.json", {
+        "workload": "small_normal(seed=0): 1000 x 16 N(0,1), 64 sets of 5, greedy k=5",
+        "sha256_x": W.sha256_of(p.x), "sha256_idx": W.sha256_of(p.idx),
+        "oracle": "oracle.ebc_oracle (NumPy, float64, direct differences)",
+        "seconds": time.time() - t0,
+        "f_sets": f_sets.tolist(), "sel": sel.tolist(), "f": f.tolist(), "gain": g.tolist(),
+    })
+
+
+def gmm100k():
+    p = W.greedy_fp32(seed=2)
+    t0 = time.time()
+    sel, f, g = ref.greedy(p.x, p.k)
+    _dump("gmm20_n100000_d100_k50.json", {
+        "workload": "greedy_fp32(seed=2): 100000 x 100, 20-component Gaussian mixture, greedy k=50",
+        "sha256_x": W.sha256_of(p.x),
+        "oracle": "oracle/ebc_ref.c ebc_ref_greedy (C, float64, direct differences)",
+        "threads": ref.threads(), "seconds": time.time() - t0,
+        "sel": sel.tolist(), "f": f.tolist(), "gain": g.tolist(),
+    })
+
+
+if __name__ == "__main__":
+    build_ref.build()
+    what = sys.argv[1:] or ["small"]
+    for w in what:
+        globals()[w]()

@@ -1,0 +1,258 @@
+"""Pins for the FP64 oracle: each check comes from the paper's definitions or
+from mathematics, never from the oracle itself.
+
+* hand-derived tiny cases (values worked out below, in exact fractions);
+* closed forms: f(empty) = 0, f(V) = L({e0}), f({c}) through dot products;
+* Delta(c|S) from the m-form against the literal difference f(S+c) - f(S)
+  (Sec. 3, Definition "Discrete derivative");
+* monotonicity and submodularity (Sec. 3, Definitions "Submodular function"
+  and "Monotonic submodular functions");
+* greedy against exhaustive search, and the (1 - 1/e) bound (Sec. 3);
+* a library distance routine (scipy cdist) and symmetries (scaling by a
+  power of two, row permutation), plus the lack of translation invariance
+  that the fixed e0 = 0 causes (Sec. 4, Eq. exemplar_based_clustering).
+"""
+import itertools
+import math
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+from oracle import ebc_oracle as O
+
+
+def _x(rows):
+    return np.asarray(rows, dtype=np.float32)
+
+
+# --------------------------------------------------------------------------
+# Hand-derived cases
+# --------------------------------------------------------------------------
+# V = {1, 2, 10} on a line. ||v||^2 = {1, 4, 100}, so L({e0}) = 105/3 = 35.
+#   S={1}:  d = {0, 1, 81},  m = min(n, d) = {0, 1, 81}  -> L = 82/3, f = 23/3
+#   S={2}:  d = {1, 0, 64},  m = {1, 0, 64}              -> L = 65/3, f = 40/3
+#   S={10}: d = {81, 64, 0}, m = {1, 4, 0}               -> L = 5/3,  f = 100/3
+#   S={1,2}: m = {0,0,64} -> f = 41/3;  S={2,10}: m = {1,0,0} -> f = 104/3
+#   S={1,10}: m = {0,1,0} -> f = 104/3; S=V: m = 0 -> f = 35
+# Greedy: step 1 picks 10 (100/3). At m = {1,4,0}: gain(1) = (1+3)/3 = 4/3,
+# gain(2) = (0+4)/3 = 4/3 -> exact tie, lowest index (row 0, value 1) wins.
+# Step 3: m = {0,1,0}, gain(2) = 1/3, f = 35.
+LINE = _x([[1.0], [2.0], [10.0]])
+LINE_F = {(): Fraction(0), (0,): Fraction(23, 3), (1,): Fraction(40, 3), (2,): Fraction(100, 3),
+          (0, 1): Fraction(41, 3), (1, 2): Fraction(104, 3), (0, 2): Fraction(104, 3),
+          (0, 1, 2): Fraction(35)}
+
+
+@pytest.mark.parametrize("s,expected", sorted(LINE_F.items()))
+def test_line_hand_values(s, expected):
+    assert O.f_value(LINE, s) == pytest.approx(float(expected), rel=1e-15, abs=1e-15)
+
+
+def test_line_greedy_tie_breaks_to_lowest_index():
+    sel, f, g = O.greedy(LINE, 3)
+    assert list(sel) == [2, 0, 1]
+    np.testing.assert_allclose(f, [100 / 3, 104 / 3, 35.0], rtol=1e-15)
+    np.testing.assert_allclose(g, [100 / 3, 4 / 3, 1 / 3], rtol=1e-15)
+
+
+# V = {(1,0), (0,2), (1,2)}: n = {1, 4, 5}, L({e0}) = 10/3.
+#   S={(1,0)}: d = {0, 5, 4} -> m = {0, 4, 4} -> f = 10/3 - 8/3 = 2/3
+#   S={(0,2)}: d = {5, 0, 1} -> m = {1, 0, 1} -> f = 8/3
+#   S={(1,2)}: d = {4, 1, 0} -> m = {1, 1, 0} -> f = 8/3
+# A transposed operand or a swapped coordinate changes these values.
+PLANE = _x([[1.0, 0.0], [0.0, 2.0], [1.0, 2.0]])
+
+
+def test_plane_hand_values():
+    assert O.f_value(PLANE, [0]) == pytest.approx(2 / 3, rel=1e-15)
+    assert O.f_value(PLANE, [1]) == pytest.approx(8 / 3, rel=1e-15)
+    assert O.f_value(PLANE, [2]) == pytest.approx(8 / 3, rel=1e-15)
+    sel, f, _ = O.greedy(PLANE, 3)
+    # step 1: tie 8/3 between rows 1 and 2 -> row 1; step 2 at m={1,0,1}:
+    # gain(0) = 1/3 = gain(2) -> row 0; step 3: row 2, f = L({e0}).
+    assert list(sel) == [1, 0, 2]
+    np.testing.assert_allclose(f, [8 / 3, 3.0, 10 / 3], rtol=1e-15)
+
+
+def test_e0_is_part_of_every_set():
+    # V = {3, -3}: L({e0}) = 9. S = {3}: m = min({9,9}, {0,36}) = {0, 9}, f = 9/2.
+    # Without e0 in the running minimum, L(S) would be 18 and f negative.
+    x = _x([[3.0], [-3.0]])
+    assert O.f_value(x, [0]) == pytest.approx(4.5, rel=1e-15)
+    # Shift by +3: V = {6, 0}, L({e0}) = 18, S = {6}: m = {0, 0}, f = 18.
+    # f is not translation invariant because e0 stays at the origin.
+    assert O.f_value(x + 3.0, [0]) == pytest.approx(18.0, rel=1e-15)
+
+
+# --------------------------------------------------------------------------
+# Closed forms and identities on random data
+# --------------------------------------------------------------------------
+def _rand(n, d, seed):
+    return np.random.default_rng(seed).standard_normal((n, d)).astype(np.float32)
+
+
+def test_empty_set_is_zero_and_full_set_is_l0():
+    x = _rand(40, 5, 1)
+    assert O.f_value(x, []) == 0.0
+    l0 = float(np.mean(np.sum(x.astype(np.float64) ** 2, axis=1)))
+    assert O.f_value(x, range(40)) == pytest.approx(l0, rel=1e-14)
+
+
+def test_singleton_closed_form():
+    # n_v - min(n_v, ||v - c||^2) = max(0, 2 v.c - ||c||^2): uses dot products,
+    # not the oracle's direct differences.
+    x = _rand(60, 7, 2)
+    x64 = x.astype(np.float64)
+    for c in [0, 5, 17, 59]:
+        ref = float(np.mean(np.maximum(0.0, 2.0 * x64 @ x64[c] - x64[c] @ x64[c])))
+        assert O.f_value(x, [c]) == pytest.approx(ref, rel=1e-12, abs=1e-14)
+
+
+def test_against_scipy_cdist():
+    cdist = pytest.importorskip("scipy.spatial.distance").cdist
+    x = _rand(50, 6, 3)
+    x64 = x.astype(np.float64)
+    rng = np.random.default_rng(33)
+    for size in [1, 3, 8]:
+        s = rng.choice(50, size, replace=False)
+        dmat = cdist(x64, x64[s], "sqeuclidean")
+        n = cdist(x64, np.zeros((1, 6)), "sqeuclidean")[:, 0]
+        ref = float(np.mean(n) - np.mean(np.minimum(n, dmat.min(axis=1))))
+        assert O.f_value(x, s) == pytest.approx(ref, rel=1e-12)
+
+
+def test_gain_equals_discrete_derivative():
+    x = _rand(30, 4, 4)
+    rng = np.random.default_rng(44)
+    for size in [0, 1, 4]:
+        s = list(rng.choice(30, size, replace=False))
+        m = O.min_dist_to_set(x, s)
+        fs = O.f_value(x, s)
+        for c in [0, 3, 29]:
+            lit = O.f_value(x, s + [c]) - fs
+            assert O.marginal_gain(x, m, c) == pytest.approx(lit, rel=1e-10, abs=1e-13)
+
+
+def test_gain_of_selected_or_duplicate_point_is_zero():
+    x = _rand(20, 3, 5)
+    x = np.concatenate([x, x[[4]]], axis=0)  # row 20 duplicates row 4
+    m = O.min_dist_to_set(x, [4])
+    assert O.marginal_gain(x, m, 4) == 0.0
+    assert O.marginal_gain(x, m, 20) == 0.0
+
+
+def test_monotone_and_submodular():
+    x = _rand(16, 3, 6)
+    rng = np.random.default_rng(66)
+    for _ in range(30):
+        b = list(rng.choice(16, rng.integers(1, 8), replace=False))
+        a = [i for i in b if rng.random() < 0.5]
+        rest = [e for e in range(16) if e not in b]
+        e = int(rng.choice(rest))
+        fa, fb = O.f_value(x, a), O.f_value(x, b)
+        assert fa <= fb + 1e-12                       # monotone
+        da = O.f_value(x, a + [e]) - fa
+        db = O.f_value(x, b + [e]) - fb
+        assert da >= db - 1e-12                       # diminishing returns
+
+
+def test_scaling_by_power_of_two_and_permutation():
+    x = _rand(25, 4, 7)
+    s1, f1, _ = O.greedy(x, 4)
+    s2, f2, _ = O.greedy(2.0 * x, 4)
+    assert list(s1) == list(s2)
+    np.testing.assert_array_equal(f2, 4.0 * f1)       # exact: powers of two
+    perm = np.random.default_rng(77).permutation(25)
+    s3, f3, g3 = O.greedy(x[perm], 4)
+    # Row i of x[perm] is row perm[i]. Two points that cover exactly each
+    # other tie in exact arithmetic (here rows 8 and 17 at step 4), so the
+    # picks may differ only where the gains are equal.
+    s1_g = O.greedy(x, 4)[2]
+    for t in range(4):
+        if perm[s3[t]] != s1[t]:
+            assert g3[t] == pytest.approx(s1_g[t], rel=1e-12)
+    assert list(perm[s3[:3]]) == list(s1[:3])
+    np.testing.assert_allclose(f3, f1, rtol=1e-13)
+
+
+# --------------------------------------------------------------------------
+# Greedy vs exhaustive search
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("seed,n,d,k", [(8, 12, 2, 3), (9, 14, 3, 4), (10, 16, 2, 5)])
+def test_greedy_against_exhaustive(seed, n, d, k):
+    x = _rand(n, d, seed)
+    sel, f, g = O.greedy(x, k)
+    # step 1 is exact: argmax_c f({c})
+    singles = [O.f_value(x, [c]) for c in range(n)]
+    assert sel[0] == int(np.argmax(singles))
+    opt1, _ = O.exhaustive(x, 1)
+    assert f[0] == pytest.approx(opt1, rel=1e-13)
+    # f(S_t) equals the from-scratch value, the gains sum to it and never grow
+    for t in range(k):
+        assert f[t] == pytest.approx(O.f_value(x, sel[:t + 1]), rel=1e-12)
+    np.testing.assert_allclose(np.cumsum(g), f, rtol=1e-12)
+    assert np.all(np.diff(g) <= 1e-12)
+    # the (1 - 1/e) guarantee for every budget, and the certified upper bound
+    # f(OPT_j) <= f(S_t) + sum of the j largest gains at S_t
+    for j in range(1, k + 1):
+        opt, _ = O.exhaustive(x, j)
+        assert f[j - 1] >= (1.0 - 1.0 / math.e) * opt - 1e-12
+        assert f[j - 1] <= opt + 1e-12
+        for t in range(k):
+            m = O.min_dist_to_set(x, sel[:t + 1])
+            top = np.sort(O.gains(x, m))[::-1][:j]
+            assert opt <= f[t] + top.sum() + 1e-12
+
+
+def test_exhaustive_tiny_by_enumeration_of_line():
+    best, arg = O.exhaustive(LINE, 2)
+    assert best == pytest.approx(104 / 3, rel=1e-15)
+    assert arg in [(0, 2), (1, 2)]
+
+
+# --------------------------------------------------------------------------
+# eval_sets (CSR) on edge cases
+# --------------------------------------------------------------------------
+def test_eval_sets_edge_cases():
+    x = _rand(30, 4, 11)
+    offsets = np.array([0, 0, 1, 4, 7, 37], dtype=np.int64)
+    idx = np.array([5,  1, 2, 3,  9, 9, 2] + list(range(30)), dtype=np.int32)
+    out = O.eval_sets(x, offsets, idx)
+    assert out[0] == 0.0                                       # empty set
+    assert out[1] == pytest.approx(O.f_value(x, [5]), rel=1e-15)
+    assert out[3] == pytest.approx(O.f_value(x, [9, 2]), rel=1e-15)  # duplicates
+    l0 = float(np.mean(np.sum(x.astype(np.float64) ** 2, axis=1)))
+    assert out[4] == pytest.approx(l0, rel=1e-14)              # all of V
+
+
+# --------------------------------------------------------------------------
+# The C half of the oracle agrees with the NumPy half
+# --------------------------------------------------------------------------
+def test_c_oracle_matches_numpy_oracle(ref):
+    x = _rand(300, 9, 12)
+    sel_np, f_np, g_np = O.greedy(x, 6)
+    sel_c, f_c, g_c = ref.greedy(x, 6)
+    assert list(sel_c) == list(sel_np)
+    np.testing.assert_allclose(f_c, f_np, rtol=1e-12)
+    np.testing.assert_allclose(g_c, g_np, rtol=1e-12)
+    m = O.min_dist_to_set(x, sel_np[:3])
+    np.testing.assert_allclose(ref.min_dist(x, sel_np[:3]), m, rtol=1e-13)
+    np.testing.assert_allclose(ref.gains(x, m), O.gains(x, m), rtol=1e-11, atol=1e-14)
+    rng = np.random.default_rng(5)
+    off = np.array([0, 0, 3, 8, 9], dtype=np.int64)
+    idx = rng.integers(0, 300, 9).astype(np.int32)
+    np.testing.assert_allclose(ref.eval_sets(x, off, idx), O.eval_sets(x, off, idx), rtol=1e-12, atol=1e-15)
+
+
+def test_c_oracle_hand_cases(ref):
+    sel, f, g = ref.greedy(LINE, 3)
+    assert list(sel) == [2, 0, 1]
+    np.testing.assert_allclose(f, [100 / 3, 104 / 3, 35.0], rtol=1e-15)
+    sel, f, _ = ref.greedy(PLANE, 3)
+    assert list(sel) == [1, 0, 2]
+    off = np.array([0, 1, 2, 3], dtype=np.int64)
+    np.testing.assert_allclose(ref.eval_sets(PLANE, off, np.array([0, 1, 2], np.int32)),
+                               [2 / 3, 8 / 3, 8 / 3], rtol=1e-15)
+    with pytest.raises(ValueError):
+        ref.greedy(LINE, 4)
