@@ -1,0 +1,186 @@
+/*
+ * ebc.h - C ABI of libebc.so: exemplar-based clustering (EBC) on one MI355X.
+ *
+ * The library evaluates the EBC submodular function of Honysz et al.,
+ * "Providing Meaningful Data Summarizations Using Exemplar-based Clustering
+ * in Industry 4.0" (arXiv 2105.12026):
+ *
+ *   L(S)  = |V|^-1 sum_{v in V} min_{s in S} d(v, s)        (Sec. 4, Eq. k_medoids_loss)
+ *   f(S)  = L({e0}) - L(S u {e0}),  e0 = 0                   (Sec. 4, Eq. exemplar_based_clustering)
+ *   d(x,y)= ||x - y||_2^2                                     (Sec. 5, experimental setup)
+ *
+ * over the many sets that an optimiser scores per step (Sec. 4.1: S_multi),
+ * and runs the greedy optimiser (Sec. 3) on the device.
+ *
+ * Conventions (every entry point):
+ *  - Sizes are int64_t; point indices are int32_t, so n < 2^31.
+ *  - Pointers marked [device] are device (HBM) pointers; [host] are host.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *    Every call only enqueues work on `stream` and returns; results are ready
+ *    when the stream has reached them. Nothing blocks except ebc_sync_status.
+ *  - Host-side argument errors return at once with nothing enqueued.
+ *  - Errors the device detects (bad CSR index, non-finite input) set a flag in
+ *    the dataset, write NaN into the affected outputs, and are returned by the
+ *    next ebc_sync_status.
+ *  - No C++ exception crosses this interface.
+ *  - A dataset is not thread-safe: calls on one dataset must be ordered on
+ *    one stream. Distinct datasets may run concurrently on distinct streams.
+ */
+#ifndef EBC_H
+#define EBC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#if defined(__GNUC__)
+#define EBC_API __attribute__((visibility("default")))
+#else
+#define EBC_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ebc_dataset ebc_dataset; /* opaque; host struct owned by the library */
+
+typedef enum {
+    EBC_OK = 0,
+    EBC_E_INVALID_ARG = 1,  /* null pointer, size out of range, workspace too small, k > n */
+    EBC_E_INDEX = 2,        /* device: CSR index outside [0, n) or offsets not non-decreasing */
+    EBC_E_NONFINITE = 3,    /* device: NaN or Inf in the input points */
+    EBC_E_RANGE = 4,        /* device: a value does not fit the distance dtype */
+    EBC_E_NOMEM = 5,        /* host allocation of the dataset struct failed */
+    EBC_E_DEVICE = 6,       /* a HIP runtime call failed */
+    EBC_E_UNSUPPORTED = 7   /* valid request this build does not implement (e.g. d > 128) */
+} ebc_status;
+
+/* Precision in which the candidate-point distances are computed. Norms,
+ * the running minima m_v, f and every cross-block sum stay in FP32/FP64 as
+ * documented per entry point. */
+typedef enum {
+    EBC_DT_F32 = 0
+} ebc_dtype;
+
+/* Largest dimension this build accepts. */
+#define EBC_MAX_DIM 128
+
+/* Exact device workspace that ebc_dataset_create needs for (n, d, dt), in
+ * bytes; 0 if the arguments are invalid. The library allocates no device
+ * memory of its own, so this is the whole device footprint of a dataset
+ * besides the caller's input points. */
+EBC_API size_t ebc_dataset_bytes(int64_t n, int32_t d, ebc_dtype dt);
+
+/* Make the ground set V resident and precompute what every evaluation reuses
+ * (Sec. 4.2: V is copied to the device once; Sec. 4.1: L({e0}) is computed
+ * once): float64 norms ||v||^2, L({e0}) = |V|^-1 sum_v ||v||^2, the greedy
+ * state m_v = ||v||^2 (S = {}), and the padded distance-dtype copy of V.
+ *   x         [device] float32, row-major [n, d]. Borrowed: it must stay valid
+ *             and unchanged until ebc_dataset_destroy (float64 re-scoring and
+ *             the m_v update read it).
+ *   n, d      1 <= n < 2^31, 1 <= d <= EBC_MAX_DIM.
+ *   flags     must be 0.
+ *   workspace [device] at least ebc_dataset_bytes(n, d, dt) bytes, 256-byte
+ *             aligned, owned by the caller, valid until destroy.
+ *   out       [host] receives the dataset handle.
+ * Non-finite input is reported by ebc_sync_status as EBC_E_NONFINITE. */
+EBC_API ebc_status ebc_dataset_create(const float* x, int64_t n, int32_t d, ebc_dtype dt, uint32_t flags,
+                              void* workspace, size_t workspace_bytes, void* stream,
+                              ebc_dataset** out);
+
+/* Free the host struct. Does not touch the caller's workspace or x; the
+ * caller must not free those before enqueued work has finished. */
+EBC_API ebc_status ebc_dataset_destroy(ebc_dataset* ds);
+
+/* f(S_j) for l sets packed as CSR (Sec. 4.1, S_multi = {S_1..S_l}; Alg. 1
+ * per set; Alg. 2 computes the same per-(set, point) minima).
+ *   offsets [device] int64 [l+1], offsets[0] = 0, non-decreasing.
+ *   idx     [device] int32 [offsets[l]]; set j = idx[offsets[j] .. offsets[j+1]).
+ *           Indices are rows of V. Empty sets (f = 0) and repeats are allowed.
+ *   f_out   [device] float64 [l].
+ * Distances are float32 direct differences; each per-point term and every
+ * sum is float64. A bad index or offsets make that set's f NaN and raise
+ * EBC_E_INDEX. l = 0 is a no-op. */
+EBC_API ebc_status ebc_eval_sets(ebc_dataset* ds, const int64_t* offsets, const int32_t* idx, int64_t l,
+                         double* f_out, void* stream);
+
+/* Marginal gains Delta(c|S) = f(S u {c}) - f(S) (Sec. 3, Definition
+ * "Discrete derivative") for candidates c, computed in the form
+ * |V|^-1 sum_v max(0, m_v - d(v, c)) with m_v = min(||v||^2, min_{s in S} d(v,s)).
+ *   m         [device] float64 [n] or NULL. Non-NULL replaces the dataset's
+ *             running minima (the greedy state) by m before computing; NULL
+ *             uses the current state (S = {} after create or greedy's S_k).
+ *   cand      [device] int32 [n_cand] or NULL for all n points in order.
+ *   gains_out [device] float64 [n_cand].
+ * Distances use the dataset dtype with FP32 accumulation; sums are FP64. */
+EBC_API ebc_status ebc_marginal_gains(ebc_dataset* ds, const double* m, const int32_t* cand, int64_t n_cand,
+                              double* gains_out, void* stream);
+
+/* Greedy maximisation of f under |S| <= k (Sec. 3, Eq.
+ * submodular_function_optimization_cardinality_constraint; Sec. 4.1: every
+ * step scores all not-yet-selected points). Starts from S = {} (resets the
+ * dataset state), runs all k steps on the device with no host round trip.
+ * Each step: gains of all n points -> masked argmax -> every candidate
+ * within a window of the best is re-scored in float64 with direct
+ * differences -> the best float64 gain wins, ties to the lowest index ->
+ * m_v <- min(m_v, d(v, c*)) in float64 -> f(S_t) = L({e0}) - |V|^-1 sum m_v.
+ *   k         0 <= k <= n (k = 0 is a no-op).
+ *   sel_out   [device] int32 [k]: selected indices in pick order.
+ *   f_out     [device] float64 [k]: f(S_1) .. f(S_k).
+ *   gain_out  [device] float64 [k] or NULL: float64 gain of each pick.
+ * After the call the dataset state holds S_k (usable by ebc_marginal_gains). */
+EBC_API ebc_status ebc_greedy(ebc_dataset* ds, int32_t k, int32_t* sel_out, double* f_out, double* gain_out,
+                      void* stream);
+
+/* Host-side counters of the last ebc_greedy on this dataset, valid after
+ * ebc_sync_status: window_max = largest number of candidates re-scored in
+ * one step, window_overflow = steps whose window exceeded its capacity. */
+typedef struct {
+    int32_t window_max;
+    int32_t window_overflow;
+    int32_t steps;
+    int32_t reserved;
+} ebc_greedy_stats;
+
+/* Wait for `stream`, then return the first deferred device error of this
+ * dataset (and clear it), or EBC_OK. Fills *stats (may be NULL). */
+EBC_API ebc_status ebc_sync_status(ebc_dataset* ds, void* stream, ebc_greedy_stats* stats);
+
+/* Static English description of a status code. */
+EBC_API const char* ebc_status_string(ebc_status st);
+
+/* Geometry the library chose for a dataset (tile shape of the gains kernel),
+ * for benchmarks and tests. */
+typedef struct {
+    int64_t n;
+    int64_t n_pad;
+    int32_t d;
+    int32_t k_pad;          /* padded row length of the distance-dtype copy */
+    int32_t v_splits;       /* ground-set chunks a candidate tile is split into */
+    int32_t cand_tile;      /* candidates per gains workgroup */
+    int32_t window_cap;     /* most candidates re-scored in float64 per step */
+    int32_t dtype;
+    double l0;              /* L({e0}); valid after the stream passed create */
+} ebc_dataset_info;
+
+EBC_API ebc_status ebc_dataset_get_info(ebc_dataset* ds, ebc_dataset_info* info);
+
+/* Per-kernel timing of ebc_greedy with HIP events recorded on the call's
+ * stream around each step's marginal-gains launch and around the whole step.
+ * Off by default; when on, ebc_greedy records 3 events per step (host-side
+ * event objects, no device memory). ebc_profile_read waits for the last
+ * recorded event and returns the totals since the last reset. */
+typedef struct {
+    double gains_ms;        /* summed duration of the marginal-gains kernel */
+    double select_ms;       /* summed duration of the rest of each step */
+    int32_t gains_launches; /* gains launches timed */
+    int32_t steps;          /* greedy steps timed */
+} ebc_profile;
+
+EBC_API ebc_status ebc_profile_enable(ebc_dataset* ds, int32_t on);
+EBC_API ebc_status ebc_profile_read(ebc_dataset* ds, ebc_profile* out, int32_t reset);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* EBC_H */

@@ -1,0 +1,221 @@
+// Marginal gains of many candidates at once, float32 on the MFMA units.
+//
+// For the current running minima m_v (the per-point terms of L(S u {e0}),
+// Sec. 4.1, Eq. loss_decomposed) the gain of candidate c is
+//     G[c] = sum_v max(0, m_v - d(v, c))               (|V| * Delta(c|S), Sec. 3)
+// With d(v,c) = ||v||^2 + ||c||^2 - 2 v.c and all terms halved (exact in
+// binary floating point):
+//     G[c] / 2 = sum_v med3( v.c + ha_v - hn_c, 0, hm_v )
+// where hn = ||.||^2/2, hm_v = m_v/2, ha_v = hm_v - hn_v, and med3 clamps the
+// per-point term to [0, m_v/2] (the clamp at m_v is the clamp d >= 0).
+//
+// The paper's kernel (Alg. 2) gives every (set, point) cell of the work
+// matrix W its own thread and writes W to global memory before a W*1 sum.
+// Here the dot products v.c are a dense contraction on the matrix cores
+// (v_mfma_f32_32x32x2_f32), the clamp and the sum over v are fused into the
+// accumulator epilogue, and no distance or work matrix is ever written.
+//
+// Work decomposition: a workgroup (4 waves) owns 128 candidates (32 per
+// wave, their rows held in registers for the whole kernel) and one chunk of
+// the ground set; it streams that chunk through LDS in tiles of 64 points.
+// MFMA tile: rows = 32 candidates, columns = 32 ground points, K = the
+// dimension, split in two halves so that every lane reads contiguous K.
+#include "ebc_internal.h"
+
+namespace ebc {
+
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+// The prefetched tile lives in one wide vector value (not an array) so that
+// it stays in registers across the loop.
+template <int PER>
+using PreVec = float __attribute__((ext_vector_type(4 * PER)));
+
+template <int PER, int NV4>
+__device__ __forceinline__ PreVec<PER> load_rows(const float4* __restrict__ src, int tid) {
+    PreVec<PER> pre;
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        const int e = tid + i * 256;
+        const float4 t = src[e < NV4 ? e : NV4 - 1];  // clamped: stays inside the tile
+        pre[4 * i + 0] = t.x;
+        pre[4 * i + 1] = t.y;
+        pre[4 * i + 2] = t.z;
+        pre[4 * i + 3] = t.w;
+    }
+    return pre;
+}
+
+template <int KP>
+__global__ void __launch_bounds__(256)
+k_gains_f32(const float* __restrict__ xq, const float* __restrict__ hn, const float* __restrict__ ha,
+            const float* __restrict__ hm, const int32_t* __restrict__ cand, int64_t n_cand,
+            int64_t n_pad, int32_t v_splits, int64_t chunk, double* __restrict__ part,
+            int64_t part_stride, int* __restrict__ err) {
+    constexpr int KH = KP / 2;        // K values per lane half
+    constexpr int S = KP + 4;         // LDS row stride in floats (S/4 odd: conflict-free b128)
+    constexpr int VT = kGainsVTile;   // ground points per LDS stage
+    constexpr int NV4 = VT * KP / 4;  // float4 per stage
+    constexpr int PER = (NV4 + 255) / 256;
+    static_assert(KP % 8 == 0, "row length must be a multiple of 8");
+
+    __shared__ float4 lds_x4[VT * S / 4];
+    __shared__ float lds_ha[VT];
+    __shared__ float lds_hm[VT];
+    float* lds_x = reinterpret_cast<float*>(lds_x4);
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int col = lane & 31;  // MFMA column within a 32-block
+    const int half = lane >> 5;
+
+    const int64_t bid = blockIdx.x;
+    const int split = int(bid % v_splits);
+    const int64_t ctile = bid / v_splits;
+
+    // ---- candidate rows of this wave, in registers (MFMA A operand) ----
+    const int64_t cpos = ctile * kGainsCandTile + wave * 32 + col;  // position in the candidate list
+    // Candidate rows outside [0, n_pad) (a bad caller list) compute as zero
+    // rows and raise EBC_E_INDEX.
+    int64_t crow = -1;
+    if (cpos < n_cand) crow = cand ? int64_t(cand[cpos]) : cpos;
+    if (crow >= n_pad || crow < -1 || (cpos < n_cand && crow < 0)) {
+        atomicCAS(err, 0, kDevErrIndex);
+        crow = -1;
+    }
+    float a[KH];
+    if (crow >= 0) {
+        const float4* src = reinterpret_cast<const float4*>(xq + crow * KP + half * KH);
+#pragma unroll
+        for (int q = 0; q < KH / 4; ++q) {
+            const float4 t = src[q];
+            a[4 * q + 0] = t.x;
+            a[4 * q + 1] = t.y;
+            a[4 * q + 2] = t.z;
+            a[4 * q + 3] = t.w;
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < KH; ++j) a[j] = 0.0f;
+    }
+    // -hn of the 16 candidate rows this lane holds in the MFMA result.
+    float nhn[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int64_t p = ctile * kGainsCandTile + wave * 32 + 8 * (r / 4) + 4 * half + (r % 4);
+        float v = 0.0f;
+        if (p < n_cand) {
+            const int64_t row = cand ? int64_t(cand[p]) : p;
+            if (row >= 0 && row < n_pad) v = hn[row];
+        }
+        nhn[r] = -v;
+    }
+    float acc_sum[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc_sum[r] = 0.0f;
+
+    // ---- stream the ground-set chunk ----
+    const int64_t v_begin = int64_t(split) * chunk;
+    int64_t v_end = v_begin + chunk;
+    if (v_end > n_pad) v_end = n_pad;
+
+    // Next tile's rows are fetched into registers while the current tile's
+    // MFMAs run, then written to LDS between two barriers.
+    PreVec<PER> pre;
+    float pre_ha = 0.0f, pre_hm = 0.0f;
+    if (v_begin < v_end) {
+        pre = load_rows<PER, NV4>(reinterpret_cast<const float4*>(xq + v_begin * KP), tid);
+        if (tid < VT) {
+            pre_ha = ha[v_begin + tid];
+            pre_hm = hm[v_begin + tid];
+        }
+    }
+    for (int64_t v0 = v_begin; v0 < v_end; v0 += VT) {
+        __syncthreads();  // previous tile fully consumed
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int e = tid + i * 256;
+            if (e < NV4) {
+                const int row = e / (KP / 4);
+                const int q = e % (KP / 4);
+                lds_x4[(row * S) / 4 + q] = make_float4(pre[4 * i], pre[4 * i + 1], pre[4 * i + 2], pre[4 * i + 3]);
+            }
+        }
+        if (tid < VT) {
+            lds_ha[tid] = pre_ha;
+            lds_hm[tid] = pre_hm;
+        }
+        __syncthreads();
+        if (v0 + VT < v_end) {  // in flight during the MFMAs
+            pre = load_rows<PER, NV4>(reinterpret_cast<const float4*>(xq + (v0 + VT) * KP), tid);
+            if (tid < VT) {
+                pre_ha = ha[v0 + VT + tid];
+                pre_hm = hm[v0 + VT + tid];
+            }
+        }
+
+#pragma unroll
+        for (int cb = 0; cb < VT / 32; ++cb) {
+            const int vrow = cb * 32 + col;
+            const float hav = lds_ha[vrow];
+            const float hmv = lds_hm[vrow];
+            floatx16 acc;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[r] = nhn[r] + hav;
+            const float4* b4 = reinterpret_cast<const float4*>(lds_x + vrow * S + half * KH);
+#pragma unroll
+            for (int q = 0; q < KH / 4; ++q) {
+                const float4 bv = b4[q];
+                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a[4 * q + 0], bv.x, acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a[4 * q + 1], bv.y, acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a[4 * q + 2], bv.z, acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a[4 * q + 3], bv.w, acc, 0, 0, 0);
+            }
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc_sum[r] += __builtin_amdgcn_fmed3f(acc[r], 0.0f, hmv);
+        }
+    }
+
+    // ---- sum over the 32 columns (ground points) of each half, in float64 ----
+    // Lane (half*32 + r), r < 16, keeps the total of candidate row
+    // 8*(r/4) + 4*half + r%4.
+    double mine = 0.0;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        double v = double(acc_sum[r]);
+#pragma unroll
+        for (int off = 16; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+        if (col == r) mine = v;
+    }
+    if (col < 16) {
+        const int r = col;
+        const int64_t p = ctile * kGainsCandTile + wave * 32 + 8 * (r / 4) + 4 * half + (r % 4);
+        if (p < n_cand) part[int64_t(split) * part_stride + p] = 2.0 * mine;
+    }
+}
+
+template <int KP>
+static void launch_kp(const ebc_dataset* ds, const int32_t* cand, int64_t n_cand, hipStream_t s) {
+    const int64_t tiles = (n_cand + kGainsCandTile - 1) / kGainsCandTile;
+    const int vs = ds->v_splits;
+    int64_t chunk = (ds->n_pad + vs - 1) / vs;
+    chunk = (chunk + kGainsVTile - 1) / kGainsVTile * kGainsVTile;
+    hipLaunchKernelGGL(k_gains_f32<KP>, dim3(unsigned(tiles * vs)), dim3(256), 0, s, ds->b.xq, ds->b.hn,
+                       ds->b.ha, ds->b.hm, cand, n_cand, ds->n_pad, vs, chunk, ds->b.part, ds->n_pad,
+                       &ds->b.state->error);
+}
+
+hipError_t launch_gains_f32(const ebc_dataset* ds, const int32_t* cand, int64_t n_cand, hipStream_t s) {
+    switch (ds->k_pad) {
+#define EBC_KP(K) \
+    case K: launch_kp<K>(ds, cand, n_cand, s); break;
+        EBC_KP(8) EBC_KP(16) EBC_KP(24) EBC_KP(32) EBC_KP(40) EBC_KP(48) EBC_KP(56) EBC_KP(64)
+        EBC_KP(72) EBC_KP(80) EBC_KP(88) EBC_KP(96) EBC_KP(104) EBC_KP(112) EBC_KP(120) EBC_KP(128)
+#undef EBC_KP
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace ebc

@@ -1,0 +1,349 @@
+// One greedy step after the gains kernel (Sec. 3 and Sec. 4.1: greedy picks
+// the not-yet-selected point of largest marginal gain):
+//   k_gsum     sum the per-chunk gain sums, mask selected points, block maxima
+//   k_wcount   every candidate within tau*|best| of the best enters the window
+//   k_wselect  choose at most kWindowMax window candidates, deterministically
+//   k_rescore  float64 direct-difference gains of the window candidates
+//   k_pick     best float64 gain, ties to the lowest index; record the pick
+//   k_update   m_v <- min(m_v, d(v, c*)) in float64, per-block sums of m_v
+//   k_fsum     f(S_t) = L({e0}) - |V|^-1 sum_v m_v  (Alg. 1: sum, then / |V|)
+// No step reads anything back to the host; all sums run in a fixed order.
+#include <math.h>
+
+#include "ebc_internal.h"
+
+namespace ebc {
+
+__device__ inline bool better(double ga, int ia, double gb, int ib) {
+    return ga > gb || (ga == gb && ia < ib);
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_gsum(int64_t n_pad, int32_t v_splits, Buffers b) {
+    __shared__ double sg[kBlock];
+    __shared__ int si[kBlock];
+    const int64_t c = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+    double g = 0.0;
+    for (int s = 0; s < v_splits; ++s) g += b.part[int64_t(s) * n_pad + c];
+    if (b.selected[c]) g = -INFINITY;
+    b.gsum[c] = g;
+    sg[threadIdx.x] = g;
+    si[threadIdx.x] = int(c);
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w && better(sg[threadIdx.x + w], si[threadIdx.x + w], sg[threadIdx.x], si[threadIdx.x])) {
+            sg[threadIdx.x] = sg[threadIdx.x + w];
+            si[threadIdx.x] = si[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        b.bmax[blockIdx.x] = sg[0];
+        b.barg[blockIdx.x] = si[0];
+    }
+}
+
+// Threshold of the re-score window from the global best float32 gain.
+__device__ double window_threshold(double gmax, const DevState* st) {
+    return gmax - (st->tau * fabs(gmax) + st->tau_abs * st->nmax);
+}
+
+// Block-wide maximum of bmax[0..nb) (every block computes the same value).
+__device__ double block_gmax(const double* bmax, int nb, double* red) {
+    double m = -INFINITY;
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) m = fmax(m, bmax[i]);
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+        __syncthreads();
+    }
+    const double r = red[0];
+    __syncthreads();
+    return r;
+}
+
+__global__ void __launch_bounds__(kBlock) k_wcount(int32_t nb, Buffers b) {
+    __shared__ double red[kBlock];
+    __shared__ int scan[kBlock];
+    const double gmax = block_gmax(b.bmax, nb, red);
+    const double thr = window_threshold(gmax, b.state);
+    const int64_t c = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+    const double g = b.gsum[c];
+    const int q = (g >= thr && g > -INFINITY) ? 1 : 0;
+    // inclusive scan of q across the block (Hillis-Steele), index order kept
+    scan[threadIdx.x] = q;
+    __syncthreads();
+    for (int off = 1; off < kBlock; off <<= 1) {
+        const int add = threadIdx.x >= off ? scan[threadIdx.x - off] : 0;
+        __syncthreads();
+        scan[threadIdx.x] += add;
+        __syncthreads();
+    }
+    if (q) {
+        WindowEntry e;
+        e.g = g;
+        e.idx = int(c);
+        e.pad = 0;
+        b.wstage[int64_t(blockIdx.x) * kBlock + scan[threadIdx.x] - 1] = e;
+    }
+    if (threadIdx.x == kBlock - 1) b.bcnt[blockIdx.x] = scan[kBlock - 1];
+}
+
+// One block of 1024 threads: gather the window entries in index order, then
+// keep at most kWindowMax of them:
+//   total <= kWindowMax          all of them;
+//   total <= kWindowCap          the kWindowMax best by (gain desc, index asc);
+//   otherwise (counted overflow) the best one plus the lowest-index others.
+constexpr int kSelThreads = 1024;
+__global__ void __launch_bounds__(kSelThreads) k_wselect(int32_t nb, Buffers b) {
+    __shared__ WindowEntry list[kWindowCap];
+    __shared__ int scan[kSelThreads];
+    __shared__ double red[kSelThreads];
+    const int tid = threadIdx.x;
+    int total = 0;
+    for (int base = 0; base < nb; base += kSelThreads) {
+        const int blk = base + tid;
+        const int cnt = blk < nb ? b.bcnt[blk] : 0;
+        scan[tid] = cnt;
+        __syncthreads();
+        for (int off = 1; off < kSelThreads; off <<= 1) {
+            const int add = tid >= off ? scan[tid - off] : 0;
+            __syncthreads();
+            scan[tid] += add;
+            __syncthreads();
+        }
+        const int excl = total + scan[tid] - cnt;
+        for (int i = 0; i < cnt; ++i) {
+            const int pos = excl + i;
+            if (pos < kWindowCap) list[pos] = b.wstage[int64_t(blk) * kBlock + i];
+        }
+        total += scan[kSelThreads - 1];
+        __syncthreads();
+    }
+    const int nl = total < kWindowCap ? total : kWindowCap;
+    if (total <= kWindowMax) {
+        if (tid < total) b.wfinal[tid] = list[tid];
+    } else if (total <= kWindowCap) {
+        for (int i = tid; i < nl; i += kSelThreads) {
+            int rank = 0;
+            for (int j = 0; j < nl; ++j)
+                rank += better(list[j].g, list[j].idx, list[i].g, list[i].idx) ? 1 : 0;
+            if (rank < kWindowMax) b.wfinal[rank] = list[i];
+        }
+    } else {
+        // overflow: the global best float32 candidate first ...
+        const double gmax = block_gmax(b.bmax, nb, red);
+        if (tid == 0) {
+            int first = -1;
+            for (int i = 0; i < nb && first < 0; ++i)
+                if (b.bmax[i] == gmax) first = b.barg[i];
+            WindowEntry e;
+            e.g = gmax;
+            e.idx = first;
+            e.pad = 0;
+            b.wfinal[0] = e;
+            int w = 1;
+            for (int i = 0; i < nl && w < kWindowMax; ++i)
+                if (list[i].idx != first) b.wfinal[w++] = list[i];
+        }
+    }
+    if (tid == 0) {
+        const int W = total < kWindowMax ? total : kWindowMax;
+        b.state->window_count = W;
+        if (total > b.state->window_max) b.state->window_max = total;
+        if (total > kWindowCap) b.state->window_overflow += 1;
+    }
+}
+
+// float64 gains of the window candidates with direct differences from the
+// caller's float32 points. One thread per ground point; candidates in groups
+// of 8 staged in LDS; per-block sums in fixed order.
+constexpr int kRescoreGroup = 8;
+__global__ void __launch_bounds__(kBlock)
+k_rescore(const float* __restrict__ x, int64_t n, int32_t d, Buffers b) {
+    __shared__ float cx[kRescoreGroup * EBC_MAX_DIM];
+    __shared__ double red[kRescoreGroup][kBlock];
+    const int W = b.state->window_count;
+    const int64_t v = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+    const bool live = v < n;
+    const double mv = live ? b.m64[v] : 0.0;
+    const float* xv = x + (live ? v : 0) * d;
+    for (int g0 = 0; g0 < W; g0 += kRescoreGroup) {
+        const int gn = (W - g0) < kRescoreGroup ? (W - g0) : kRescoreGroup;
+        __syncthreads();
+        for (int e = threadIdx.x; e < gn * d; e += kBlock) {
+            const int j = e / d, k = e % d;
+            cx[j * EBC_MAX_DIM + k] = x[int64_t(b.wfinal[g0 + j].idx) * d + k];
+        }
+        __syncthreads();
+        double acc[kRescoreGroup];
+#pragma unroll
+        for (int j = 0; j < kRescoreGroup; ++j) acc[j] = 0.0;
+        if (live) {
+            for (int k = 0; k < d; ++k) {
+                const double xk = double(xv[k]);
+#pragma unroll
+                for (int j = 0; j < kRescoreGroup; ++j) {
+                    const double t = xk - double(cx[j * EBC_MAX_DIM + k]);
+                    acc[j] = fma(t, t, acc[j]);
+                }
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < kRescoreGroup; ++j) red[j][threadIdx.x] = live ? fmax(0.0, mv - acc[j]) : 0.0;
+        __syncthreads();
+        for (int w = kBlock / 2; w > 0; w >>= 1) {
+            if (threadIdx.x < w) {
+#pragma unroll
+                for (int j = 0; j < kRescoreGroup; ++j) red[j][threadIdx.x] += red[j][threadIdx.x + w];
+            }
+            __syncthreads();
+        }
+        if (threadIdx.x < gn) b.rpart[int64_t(blockIdx.x) * kWindowMax + g0 + threadIdx.x] = red[threadIdx.x][0];
+    }
+}
+
+// One block: float64 gain of each window candidate = sum of the per-block
+// sums (thread i takes blocks i, i+256, ..., then a fixed tree); best gain
+// wins, ties to the lowest index. Records the pick. A step with no valid
+// candidate (only possible with non-finite input) records -1 and flags it.
+__global__ void __launch_bounds__(kBlock)
+k_pick(int64_t n, int32_t nbv, int32_t t, Buffers b, int32_t* sel_out, double* gain_out) {
+    __shared__ double red[kBlock];
+    __shared__ double sg[kWindowMax];
+    __shared__ int si[kWindowMax];
+    const int W = b.state->window_count;
+    for (int j = 0; j < kWindowMax; ++j) {
+        double s = 0.0;
+        if (j < W)
+            for (int blk = threadIdx.x; blk < nbv; blk += kBlock) s += b.rpart[int64_t(blk) * kWindowMax + j];
+        red[threadIdx.x] = s;
+        __syncthreads();
+        for (int w = kBlock / 2; w > 0; w >>= 1) {
+            if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            sg[j] = j < W ? red[0] : -INFINITY;
+            si[j] = j < W ? b.wfinal[j].idx : 0x7fffffff;
+        }
+        __syncthreads();
+        if (j + 1 >= W) break;
+    }
+    for (int j = W + threadIdx.x; j < kWindowMax; j += kBlock) {
+        sg[j] = -INFINITY;
+        si[j] = 0x7fffffff;
+    }
+    __syncthreads();
+    const int j = threadIdx.x;
+    for (int w = kWindowMax / 2; w > 0; w >>= 1) {
+        if (j < w && better(sg[j + w], si[j + w], sg[j], si[j])) {
+            sg[j] = sg[j + w];
+            si[j] = si[j + w];
+        }
+        __syncthreads();
+    }
+    if (j == 0) {
+        const int c = si[0];
+        if (W > 0 && c >= 0 && int64_t(c) < n) {
+            b.state->cstar = c;
+            b.state->gstar = sg[0];
+            b.selected[c] = 1;
+            sel_out[t] = c;
+            if (gain_out) gain_out[t] = sg[0] / double(n);
+        } else {
+            b.state->cstar = -1;
+            atomicCAS(&b.state->error, 0, kDevErrNonFinite);
+            sel_out[t] = -1;
+            if (gain_out) gain_out[t] = NAN;
+        }
+    }
+}
+
+// m_v <- min(m_v, d(v, c*)) in float64 by direct differences; refresh the
+// float32 terms the gains kernel reads; per-block sums of m_v.
+__global__ void __launch_bounds__(kBlock)
+k_update(const float* __restrict__ x, int64_t n, int32_t d, Buffers b) {
+    __shared__ float cx[EBC_MAX_DIM];
+    __shared__ double red[kBlock];
+    const int c = b.state->cstar;
+    if (c >= 0)
+        for (int k = threadIdx.x; k < d; k += kBlock) cx[k] = x[int64_t(c) * d + k];
+    __syncthreads();
+    const int64_t v = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+    double mv = 0.0;
+    if (v < n && c < 0) {
+        mv = b.m64[v];
+    } else if (v < n) {
+        const float* xv = x + v * d;
+        double acc = 0.0;
+        for (int k = 0; k < d; ++k) {
+            const double t = double(xv[k]) - double(cx[k]);
+            acc = fma(t, t, acc);
+        }
+        mv = b.m64[v];
+        if (acc < mv) {
+            mv = acc;
+            b.m64[v] = mv;
+            b.ha[v] = float(0.5 * mv - double(b.hn[v]));
+            b.hm[v] = float(0.5 * mv);
+        }
+    }
+    red[threadIdx.x] = mv;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) b.fpart[blockIdx.x] = red[0];
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_fsum(int64_t n, int32_t nbv, int32_t t, Buffers b, double* f_out) {
+    __shared__ double red[kBlock];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < nbv; i += kBlock) s += b.fpart[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) f_out[t] = b.state->l0 - red[0] / double(n);
+}
+
+hipError_t launch_greedy_step(const ebc_dataset* ds, int32_t t, int32_t* sel_out, double* f_out,
+                              double* gain_out, hipStream_t s, hipEvent_t ev_gains_done) {
+    hipError_t e = launch_gains_f32(ds, nullptr, ds->n_pad, s);
+    if (e != hipSuccess) return e;
+    if (ev_gains_done && (e = hipEventRecord(ev_gains_done, s)) != hipSuccess) return e;
+    const int nb = int(ds->n_pad / kBlock);
+    hipLaunchKernelGGL(k_gsum, dim3(nb), dim3(kBlock), 0, s, ds->n_pad, ds->v_splits, ds->b);
+    hipLaunchKernelGGL(k_wcount, dim3(nb), dim3(kBlock), 0, s, nb, ds->b);
+    hipLaunchKernelGGL(k_wselect, dim3(1), dim3(kSelThreads), 0, s, nb, ds->b);
+    hipLaunchKernelGGL(k_rescore, dim3(nb), dim3(kBlock), 0, s, ds->x, ds->n, ds->d, ds->b);
+    hipLaunchKernelGGL(k_pick, dim3(1), dim3(kBlock), 0, s, ds->n, nb, t, ds->b, sel_out, gain_out);
+    hipLaunchKernelGGL(k_update, dim3(nb), dim3(kBlock), 0, s, ds->x, ds->n, ds->d, ds->b);
+    hipLaunchKernelGGL(k_fsum, dim3(1), dim3(kBlock), 0, s, ds->n, nb, t, ds->b, f_out);
+    return hipGetLastError();
+}
+
+// Marginal-gains output: sum the per-chunk sums, divide by |V|.
+__global__ void __launch_bounds__(kBlock)
+k_gains_out(int64_t n, int64_t n_cand, int64_t stride, int32_t v_splits, const double* part, double* out) {
+    const int64_t p = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+    if (p >= n_cand) return;
+    double g = 0.0;
+    for (int s = 0; s < v_splits; ++s) g += part[int64_t(s) * stride + p];
+    out[p] = g / double(n);
+}
+
+hipError_t launch_gains_out(const ebc_dataset* ds, int64_t n_cand, double* out, hipStream_t s) {
+    const unsigned nb = unsigned((n_cand + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL(k_gains_out, dim3(nb), dim3(kBlock), 0, s, ds->n, n_cand, ds->n_pad, ds->v_splits,
+                       ds->b.part, out);
+    return hipGetLastError();
+}
+
+}  // namespace ebc

@@ -1,0 +1,193 @@
+"""Thin ctypes binding of libebc.so (C ABI in include/ebc.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of libebc.so. torch provides device memory (the dataset workspace
+and the outputs) and the HIP stream; nothing here falls back to a CPU or
+PyTorch computation. If the library is missing the import of this module
+raises, so a product call can never run without the native code.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch  # loads the process's HIP runtime before libebc.so binds to it
+
+__all__ = ["EBCError", "Dataset", "lib", "status_string", "DTYPES", "LIB_PATH", "ABI_FUNCTIONS"]
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libebc.so")
+DTYPES = {"f32": 0}
+ABI_FUNCTIONS = (
+    "ebc_dataset_bytes", "ebc_dataset_create", "ebc_dataset_destroy", "ebc_eval_sets",
+    "ebc_marginal_gains", "ebc_greedy", "ebc_sync_status", "ebc_status_string",
+    "ebc_dataset_get_info", "ebc_profile_enable", "ebc_profile_read",
+)
+
+
+class EBCError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        super().__init__(f"{what}: {status_string(code)} (status {code})")
+        self.code = code
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [("window_max", ctypes.c_int32), ("window_overflow", ctypes.c_int32),
+                ("steps", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("n_pad", ctypes.c_int64), ("d", ctypes.c_int32),
+                ("k_pad", ctypes.c_int32), ("v_splits", ctypes.c_int32), ("cand_tile", ctypes.c_int32),
+                ("window_cap", ctypes.c_int32), ("dtype", ctypes.c_int32), ("l0", ctypes.c_double)]
+
+
+class _Profile(ctypes.Structure):
+    _fields_ = [("gains_ms", ctypes.c_double), ("select_ms", ctypes.c_double),
+                ("gains_launches", ctypes.c_int32), ("steps", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"libebc.so is not built ({LIB_PATH}); run `python -m paper_2105_12026_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        P, i64, i32, u32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint32
+        L.ebc_dataset_bytes.argtypes = [i64, i32, ctypes.c_int]
+        L.ebc_dataset_bytes.restype = ctypes.c_size_t
+        L.ebc_dataset_create.argtypes = [P, i64, i32, ctypes.c_int, u32, P, ctypes.c_size_t, P,
+                                         ctypes.POINTER(P)]
+        L.ebc_dataset_destroy.argtypes = [P]
+        L.ebc_eval_sets.argtypes = [P, P, P, i64, P, P]
+        L.ebc_marginal_gains.argtypes = [P, P, P, i64, P, P]
+        L.ebc_greedy.argtypes = [P, i32, P, P, P, P]
+        L.ebc_sync_status.argtypes = [P, P, ctypes.POINTER(_Stats)]
+        L.ebc_status_string.argtypes = [ctypes.c_int]
+        L.ebc_status_string.restype = ctypes.c_char_p
+        L.ebc_dataset_get_info.argtypes = [P, ctypes.POINTER(_Info)]
+        L.ebc_profile_enable.argtypes = [P, i32]
+        L.ebc_profile_read.argtypes = [P, ctypes.POINTER(_Profile), i32]
+        for name in ABI_FUNCTIONS:
+            if name not in ("ebc_dataset_bytes", "ebc_status_string"):
+                getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def status_string(code: int) -> str:
+    return lib().ebc_status_string(int(code)).decode()
+
+
+def _check(code: int, what: str):
+    if code != 0:
+        raise EBCError(code, what)
+
+
+def _ptr(t) -> ctypes.c_void_p:
+    return ctypes.c_void_p(0 if t is None else t.data_ptr())
+
+
+def _stream(stream) -> ctypes.c_void_p:
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Dataset:
+    """A ground set V resident on the GPU (ebc_dataset_create).
+
+    ``x`` is a float32 CUDA tensor [n, d]; it is kept alive by this object
+    because the library borrows it. The workspace is a uint8 CUDA tensor of
+    exactly ``ebc_dataset_bytes(n, d, dtype)`` bytes."""
+
+    def __init__(self, x: torch.Tensor, dtype: str = "f32", stream=None):
+        if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == torch.float32 and x.dim() == 2):
+            raise TypeError("x must be a float32 CUDA tensor of shape [n, d]")
+        self.x = x.contiguous()
+        self.n, self.d = map(int, self.x.shape)
+        self.dtype = dtype
+        L = lib()
+        nbytes = L.ebc_dataset_bytes(self.n, self.d, DTYPES[dtype])
+        if nbytes == 0:
+            raise EBCError(1 if self.d <= 128 else 7, f"ebc_dataset_bytes(n={self.n}, d={self.d})")
+        self.workspace_bytes = int(nbytes)
+        self.workspace = torch.empty(self.workspace_bytes, dtype=torch.uint8, device=self.x.device)
+        h = ctypes.c_void_p()
+        _check(L.ebc_dataset_create(_ptr(self.x), self.n, self.d, DTYPES[dtype], 0, _ptr(self.workspace),
+                                    self.workspace_bytes, _stream(stream), ctypes.byref(h)),
+               "ebc_dataset_create")
+        self._h = h
+
+    # -- lifetime ---------------------------------------------------------
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().ebc_dataset_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self) -> ctypes.c_void_p:
+        return self._h
+
+    # -- entry points -----------------------------------------------------
+    def sync(self, stream=None) -> dict:
+        st = _Stats()
+        _check(lib().ebc_sync_status(self._h, _stream(stream), ctypes.byref(st)), "ebc_sync_status")
+        return {"window_max": st.window_max, "window_overflow": st.window_overflow, "steps": st.steps}
+
+    def info(self) -> dict:
+        inf = _Info()
+        _check(lib().ebc_dataset_get_info(self._h, ctypes.byref(inf)), "ebc_dataset_get_info")
+        return {f: getattr(inf, f) for f, _ in _Info._fields_}
+
+    def profile(self, on: bool = True):
+        """Turn per-step HIP-event timing of greedy on or off."""
+        _check(lib().ebc_profile_enable(self._h, int(bool(on))), "ebc_profile_enable")
+
+    def profile_read(self, reset: bool = True) -> dict:
+        pr = _Profile()
+        _check(lib().ebc_profile_read(self._h, ctypes.byref(pr), int(bool(reset))), "ebc_profile_read")
+        return {f: getattr(pr, f) for f, _ in _Profile._fields_}
+
+    def eval_sets(self, offsets: torch.Tensor, idx: torch.Tensor, out: torch.Tensor | None = None,
+                  stream=None) -> torch.Tensor:
+        """f(S_j) for CSR sets (offsets int64 [l+1], idx int32 [nnz]); float64 [l]."""
+        offsets = offsets.to(device=self.x.device, dtype=torch.int64).contiguous()
+        idx = idx.to(device=self.x.device, dtype=torch.int32).contiguous()
+        l = offsets.numel() - 1
+        if out is None:
+            out = torch.empty(max(l, 0), dtype=torch.float64, device=self.x.device)
+        idx_arg = idx if idx.numel() > 0 else offsets  # any valid pointer when there are no members
+        _check(lib().ebc_eval_sets(self._h, _ptr(offsets), _ptr(idx_arg), l, _ptr(out), _stream(stream)),
+               "ebc_eval_sets")
+        return out
+
+    def marginal_gains(self, m: torch.Tensor | None = None, cand: torch.Tensor | None = None,
+                       out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        """Delta(c|S) for candidates (default all n). ``m`` (float64 [n]) replaces the running minima."""
+        if m is not None:
+            m = m.to(device=self.x.device, dtype=torch.float64).contiguous()
+        if cand is not None:
+            cand = cand.to(device=self.x.device, dtype=torch.int32).contiguous()
+        nc = self.n if cand is None else cand.numel()
+        if out is None:
+            out = torch.empty(nc, dtype=torch.float64, device=self.x.device)
+        _check(lib().ebc_marginal_gains(self._h, _ptr(m), _ptr(cand), nc, _ptr(out), _stream(stream)),
+               "ebc_marginal_gains")
+        return out
+
+    def greedy(self, k: int, stream=None, sel=None, f=None, gain=None):
+        """Greedy to cardinality k on the device; returns (sel int32 [k], f float64 [k], gain float64 [k])."""
+        dev = self.x.device
+        sel = torch.empty(k, dtype=torch.int32, device=dev) if sel is None else sel
+        f = torch.empty(k, dtype=torch.float64, device=dev) if f is None else f
+        gain = torch.empty(k, dtype=torch.float64, device=dev) if gain is None else gain
+        _check(lib().ebc_greedy(self._h, int(k), _ptr(sel), _ptr(f), _ptr(gain), _stream(stream)), "ebc_greedy")
+        return sel, f, gain

@@ -1,0 +1,77 @@
+"""Host-only checks of the C ABI (no GPU): the library loads, exports every
+function include/ebc.h declares, and rejects bad arguments on the host before
+touching the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ebc.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"EBC_API\s+[\w\s\*]+?\b(ebc_\w+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2105_12026_amd import ebc
+    if not os.path.exists(ebc.LIB_PATH):
+        from paper_2105_12026_amd import build
+        build.build()
+    return ebc.lib()
+
+
+def test_header_declares_the_binding_functions():
+    from paper_2105_12026_amd import ebc
+    assert _declared() == sorted(ebc.ABI_FUNCTIONS)
+
+
+def test_library_exports_every_declared_symbol(L):
+    for name in _declared():
+        assert hasattr(L, name), name
+        assert ctypes.cast(getattr(L, name), ctypes.c_void_p).value
+
+
+def test_status_strings(L):
+    from paper_2105_12026_amd import ebc
+    assert ebc.status_string(0) == "ok"
+    for code in range(1, 8):
+        assert ebc.status_string(code) != "unknown status"
+    assert ebc.status_string(99) == "unknown status"
+
+
+def test_workspace_size_is_exact_and_monotone(L):
+    a = L.ebc_dataset_bytes(1000, 16, 0)
+    b = L.ebc_dataset_bytes(100000, 100, 0)
+    assert 0 < a < b
+    assert a % 256 == 0 and b % 256 == 0
+    # the padded float32 copy alone is n_pad * k_pad * 4 bytes
+    assert b >= 100096 * 104 * 4
+    assert L.ebc_dataset_bytes(0, 16, 0) == 0
+    assert L.ebc_dataset_bytes(10, 0, 0) == 0
+    assert L.ebc_dataset_bytes(10, 129, 0) == 0
+    assert L.ebc_dataset_bytes(10, 16, 9) == 0
+
+
+def test_host_validation_without_device(L):
+    P = ctypes.c_void_p
+    h = P()
+    # null x, null workspace, bad flags, bad dtype: rejected before any HIP call
+    assert L.ebc_dataset_create(None, 10, 4, 0, 0, P(256), 1 << 20, None, ctypes.byref(h)) == 1
+    assert L.ebc_dataset_create(P(256), 10, 4, 0, 0, None, 1 << 20, None, ctypes.byref(h)) == 1
+    assert L.ebc_dataset_create(P(256), 10, 4, 0, 1, P(256), 1 << 20, None, ctypes.byref(h)) == 1
+    assert L.ebc_dataset_create(P(256), 10, 4, 5, 0, P(256), 1 << 20, None, ctypes.byref(h)) == 1
+    assert L.ebc_dataset_create(P(256), 10, 200, 0, 0, P(256), 1 << 30, None, ctypes.byref(h)) == 7
+    assert L.ebc_dataset_create(P(256), 10, 4, 0, 0, P(128), 1 << 20, None, ctypes.byref(h)) == 1  # misaligned
+    assert L.ebc_dataset_create(P(256), 10, 4, 0, 0, P(256), 16, None, ctypes.byref(h)) == 1  # too small
+    assert L.ebc_dataset_create(P(256), 10, 4, 0, 0, P(256), 1 << 20, None, None) == 1
+    assert not h.value
+    assert L.ebc_dataset_destroy(None) == 1
+    assert L.ebc_greedy(None, 1, None, None, None, None) == 1
+    assert L.ebc_eval_sets(None, None, None, 1, None, None) == 1
+    assert L.ebc_marginal_gains(None, None, None, 1, None, None) == 1
+    assert L.ebc_sync_status(None, None, None) == 1
