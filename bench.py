@@ -61,6 +61,22 @@ def cpu_baseline(x, n: int, target_s: float = 12.0) -> dict:
                       f"(one greedy step's work for {nc} candidates; {dt:.1f} s)"}
 
 
+def counters_traffic(kernel: str, workload: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 --pmc
+    summary (FETCH_SIZE, WRITE_SIZE scaled by a plain-copy calibration), or
+    None if it was taken on another workload or on other kernel source."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "counters.json")
+    try:
+        rec = json.load(open(path))[kernel]
+        src = open(os.path.join(ROOT, rec["source"]), "rb").read()
+    except (OSError, KeyError, ValueError):
+        return None
+    if rec.get("workload") != workload or hashlib.sha256(src).hexdigest()[:16] != rec["source_sha256_16"]:
+        return None
+    return int(rec["hbm_bytes_per_launch"])
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -68,6 +84,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="gmm20_n100000_d100_k50", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one plain 256 MiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is a design note only",
@@ -97,6 +115,13 @@ def main():
         return ds
 
     print(f"# workload {args.workload}: n={n} d={d} k={k}", file=sys.stderr, flush=True)
+    if args.copy_calibration:
+        src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        print("# copy calibration: 268435456 bytes read, 268435456 bytes written", file=sys.stderr, flush=True)
     keep = []
     for _ in range(args.warmup):
         keep.append(one_step(False))
@@ -130,7 +155,8 @@ def main():
     flops_per_launch = 2.0 * d * pairs / k
     achieved = flops_per_launch / (gains_avg_ms * 1e-3) / 1e12
     roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_FP32_MFMA_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_MFMA_TFLOPS, 4), "traffic": None,
+                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_MFMA_TFLOPS, 4),
+                "traffic": counters_traffic("k_gains_f32", args.workload),
                 "kernel": f"k_gains_f32<{(d + 7) // 8 * 8}>", "avg_launch_ms": round(gains_avg_ms, 4),
                 "flops_per_launch": flops_per_launch}
 
