@@ -25,7 +25,8 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_FP32_MFMA_TFLOPS = 157.3   # MI355X dense FP32 matrix, published
+# MI355X published dense matrix peaks (TFLOP/s) per distance dtype
+PEAK_TFLOPS = {"f32": 157.3, "bf16": 2500.0, "f16": 2500.0, "fp8": 5000.0}
 WORKLOADS = {
     # name: (generator kwargs, description)
     "gmm20_n100000_d100_k50": ("greedy_fp32", {"seed": 2}),
@@ -83,6 +84,8 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="gmm20_n100000_d100_k50", choices=sorted(WORKLOADS))
+    ap.add_argument("--dtype", default="f32", choices=sorted(PEAK_TFLOPS))
+    ap.add_argument("--variant", type=int, default=None, help="tile variant of the gains kernel")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 256 MiB device copy (reference for HBM byte counters)")
@@ -108,7 +111,9 @@ def main():
     gain = torch.empty(k, dtype=torch.float64, device=dev)
 
     def one_step(profile: bool):
-        ds = ebc.Dataset(x, stream=stream)
+        ds = ebc.Dataset(x, dtype=args.dtype, stream=stream)
+        if args.variant is not None:
+            ds.set_variant(args.variant)
         if profile:
             ds.profile(True)
         ds.greedy(k, stream=stream, sel=sel, f=f, gain=gain)
@@ -148,16 +153,19 @@ def main():
     pairs = pairs_per_greedy(n, k)
     value = pairs * args.steps / elapsed
 
-    # roofline of the dominant kernel (marginal gains, float32 MFMA):
+    # roofline of the dominant kernel (marginal gains on the MFMA units):
     # algorithmic flops per launch = 2*d per (candidate, point) pair, with
-    # the already-selected candidates not counted, averaged over the steps.
+    # the already-selected candidates not counted, averaged over the steps;
+    # padding of d and the affine chunk are not counted.
     gains_avg_ms = prof["gains_ms"] / max(prof["gains_launches"], 1)
     flops_per_launch = 2.0 * d * pairs / k
     achieved = flops_per_launch / (gains_avg_ms * 1e-3) / 1e12
-    roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_FP32_MFMA_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_MFMA_TFLOPS, 4),
-                "traffic": counters_traffic("k_gains_f32", args.workload),
-                "kernel": f"k_gains_f32<{(d + 7) // 8 * 8}>", "avg_launch_ms": round(gains_avg_ms, 4),
+    peak = PEAK_TFLOPS[args.dtype]
+    kname = "k_gains_f32" if args.dtype == "f32" else "k_gains_lp"
+    roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak,
+                "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
+                "traffic": counters_traffic(kname, args.workload) if args.dtype == "f32" else None,
+                "kernel": kname, "avg_launch_ms": round(gains_avg_ms, 4),
                 "flops_per_launch": flops_per_launch}
 
     sel_host = sel.cpu().numpy().tolist()
@@ -165,8 +173,9 @@ def main():
         "metric": "candidate x point distance evals/s (greedy, all candidates)",
         "value": value, "unit": "pair-evals/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32", "data": "synthetic",
-        "config": {"workload": args.workload, "n": n, "d": d, "k": k, "distance_dtype": "f32",
+        "dtype": args.dtype, "data": "synthetic",
+        "config": {"workload": args.workload, "n": n, "d": d, "k": k, "distance_dtype": args.dtype,
+                   "variant": args.variant,
                    "candidates": "all n points every step", "step": "residency + greedy k"},
         "greedy_ms": ms_per_step, "gains_kernel_ms_total_per_step": prof["gains_ms"] / args.steps,
         "rest_of_step_ms_per_step": prof["select_ms"] / args.steps,

@@ -49,17 +49,29 @@ typedef enum {
     EBC_E_INVALID_ARG = 1,  /* null pointer, size out of range, workspace too small, k > n */
     EBC_E_INDEX = 2,        /* device: CSR index outside [0, n) or offsets not non-decreasing */
     EBC_E_NONFINITE = 3,    /* device: NaN or Inf in the input points */
-    EBC_E_RANGE = 4,        /* device: a value does not fit the distance dtype */
+    EBC_E_RANGE = 4,        /* device: a value does not fit the distance dtype (FP16: |x| > 65504) */
     EBC_E_NOMEM = 5,        /* host allocation of the dataset struct failed */
     EBC_E_DEVICE = 6,       /* a HIP runtime call failed */
     EBC_E_UNSUPPORTED = 7   /* valid request this build does not implement (e.g. d > 128) */
 } ebc_status;
 
-/* Precision in which the candidate-point distances are computed. Norms,
- * the running minima m_v, f and every cross-block sum stay in FP32/FP64 as
- * documented per entry point. */
+/* Precision in which the candidate-point distances of the marginal gains are
+ * computed (Sec. 5 compares FP32 with FP16). Inputs are cast once with
+ * round-to-nearest-even; products accumulate in FP32; the norms are FP32 of
+ * the cast rows; m_v, L({e0}), f, the window re-score and every cross-block
+ * sum stay FP64, so greedy selections are re-scored exactly. ebc_eval_sets
+ * always uses FP32 direct differences.
+ *   EBC_DT_F32       float32 (v_mfma_f32_32x32x2_f32)
+ *   EBC_DT_F16       IEEE half; |x| > 65504 raises EBC_E_RANGE
+ *   EBC_DT_BF16      bfloat16
+ *   EBC_DT_FP8_E4M3  OCP e4m3 with a power-of-two (E8M0) scale per row,
+ *                    s_v = 2^ceil(log2(max_k |x_vk| / 448)), applied by the
+ *                    matrix instruction's scale operands */
 typedef enum {
-    EBC_DT_F32 = 0
+    EBC_DT_F32 = 0,
+    EBC_DT_F16 = 1,
+    EBC_DT_BF16 = 2,
+    EBC_DT_FP8_E4M3 = 3
 } ebc_dtype;
 
 /* Largest dimension this build accepts. */
@@ -132,6 +144,14 @@ EBC_API ebc_status ebc_marginal_gains(ebc_dataset* ds, const double* m, const in
 EBC_API ebc_status ebc_greedy(ebc_dataset* ds, int32_t k, int32_t* sel_out, double* f_out, double* gain_out,
                       void* stream);
 
+/* Graph mode for ebc_greedy (default off): the reset and all k steps are
+ * recorded once into a HIP graph (on a private stream; recording runs
+ * nothing) and the graph is replayed on `stream` by every later call with
+ * the same k, output pointers and gains variant; other calls re-record.
+ * One graph launch replaces 8k+1 kernel launches, which is what bounds small
+ * problems. Results are identical to eager mode. Ignored while profiling. */
+EBC_API ebc_status ebc_set_greedy_graph(ebc_dataset* ds, int32_t on);
+
 /* Host-side counters of the last ebc_greedy on this dataset, valid after
  * ebc_sync_status: window_max = largest number of candidates re-scored in
  * one step, window_overflow = steps whose window exceeded its capacity. */
@@ -164,6 +184,13 @@ typedef struct {
 } ebc_dataset_info;
 
 EBC_API ebc_status ebc_dataset_get_info(ebc_dataset* ds, ebc_dataset_info* info);
+
+/* Tile shape of the marginal-gains kernel for this dataset. Every variant
+ * computes the same sums in the same order per (candidate, ground chunk), so
+ * results do not depend on it; an autotuner picks the fastest per dtype and
+ * size. Variants 0..ebc_gains_variant_count(dt)-1; 0 is the default. */
+EBC_API ebc_status ebc_set_gains_variant(ebc_dataset* ds, int32_t variant);
+EBC_API int32_t ebc_gains_variant_count(ebc_dtype dt);
 
 /* Per-kernel timing of ebc_greedy with HIP events recorded on the call's
  * stream around each step's marginal-gains launch and around the whole step.

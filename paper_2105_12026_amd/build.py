@@ -27,6 +27,9 @@ CFLAGS = [
     "-I", os.path.join(ROOT, "include"),
     # packed FP32 instructions stay off in all device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # matrix-instruction results in VGPRs: the epilogue reads them directly
+    # instead of copying every accumulator out of AGPRs first
+    "-mllvm", "-amdgpu-mfma-vgpr-form",
     "-Wall", "-Wno-unused-function",
 ]
 

@@ -52,11 +52,15 @@ struct Profiler {
 
 namespace {
 
+void drop_graph(ebc_dataset* ds);
+
 hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
 ebc_status from_hip(hipError_t e) { return e == hipSuccess ? EBC_OK : EBC_E_DEVICE; }
 
-bool valid_dtype(ebc_dtype dt) { return dt == EBC_DT_F32; }
+bool valid_dtype(ebc_dtype dt) {
+    return dt == EBC_DT_F32 || dt == EBC_DT_F16 || dt == EBC_DT_BF16 || dt == EBC_DT_FP8_E4M3;
+}
 
 }  // namespace
 
@@ -106,6 +110,9 @@ ebc_status ebc_dataset_create(const float* x, int64_t n, int32_t d, ebc_dtype dt
     char* w = static_cast<char*>(workspace);
     Buffers& b = ds->b;
     b.xq = reinterpret_cast<float*>(w + L.off_xq);
+    b.aug_c = dt == EBC_DT_F32 ? nullptr : reinterpret_cast<uint16_t*>(w + L.off_aug_c);
+    b.aug_v = dt == EBC_DT_F32 ? nullptr : reinterpret_cast<uint16_t*>(w + L.off_aug_v);
+    b.scale = dt == EBC_DT_FP8_E4M3 ? reinterpret_cast<int*>(w + L.off_scale) : nullptr;
     b.n64 = reinterpret_cast<double*>(w + L.off_n64);
     b.m64 = reinterpret_cast<double*>(w + L.off_m64);
     b.hn = reinterpret_cast<float*>(w + L.off_hn);
@@ -134,10 +141,20 @@ ebc_status ebc_dataset_create(const float* x, int64_t n, int32_t d, ebc_dtype dt
 
 ebc_status ebc_dataset_destroy(ebc_dataset* ds) {
     if (!ds) return EBC_E_INVALID_ARG;
+    drop_graph(ds);
+    if (ds->cap_stream) (void)hipStreamDestroy(ds->cap_stream);
     delete ds->prof;
     delete ds;
     return EBC_OK;
 }
+
+ebc_status ebc_set_gains_variant(ebc_dataset* ds, int32_t variant) {
+    if (!ds || variant < 0 || variant >= ebc_gains_variant_count(ds->dt)) return EBC_E_INVALID_ARG;
+    ds->variant = variant;
+    return EBC_OK;
+}
+
+int32_t ebc_gains_variant_count(ebc_dtype dt) { return dt == EBC_DT_F32 ? 1 : 2; }
 
 ebc_status ebc_profile_enable(ebc_dataset* ds, int32_t on) {
     if (!ds) return EBC_E_INVALID_ARG;
@@ -173,7 +190,7 @@ ebc_status ebc_dataset_get_info(ebc_dataset* ds, ebc_dataset_info* info) {
     info->d = ds->d;
     info->k_pad = ds->k_pad;
     info->v_splits = ds->v_splits;
-    info->cand_tile = kGainsCandTile;
+    info->cand_tile = ds->dt == EBC_DT_F32 ? kGainsCandTile : 256;
     info->window_cap = kWindowMax;
     info->dtype = int32_t(ds->dt);
     info->l0 = ds->l0_host;
@@ -203,10 +220,55 @@ ebc_status ebc_marginal_gains(ebc_dataset* ds, const double* m, const int32_t* c
     for (int64_t p0 = 0; p0 < n_cand && e == hipSuccess; p0 += ds->n_pad) {
         const int64_t cnt = (n_cand - p0) < ds->n_pad ? (n_cand - p0) : ds->n_pad;
         const int32_t* c = cand ? cand + p0 : nullptr;
-        e = launch_gains_f32(ds, c, cnt, s);
+        e = launch_gains(ds, c, cnt, s);
         if (e == hipSuccess) e = launch_gains_out(ds, cnt, gains_out + p0, s);
     }
     return from_hip(e);
+}
+
+namespace {
+
+void drop_graph(ebc_dataset* ds) {
+    if (ds->gexec) (void)hipGraphExecDestroy(ds->gexec);
+    ds->gexec = nullptr;
+}
+
+// Record reset + k greedy steps into a graph on the dataset's private stream
+// (recording executes nothing), instantiate it, and keep it for replays with
+// the same k, outputs and gains variant.
+hipError_t capture_greedy(ebc_dataset* ds, int32_t k, int32_t* sel_out, double* f_out, double* gain_out) {
+    drop_graph(ds);
+    hipError_t e = hipSuccess;
+    if (!ds->cap_stream && (e = hipStreamCreateWithFlags(&ds->cap_stream, hipStreamNonBlocking)) != hipSuccess)
+        return e;
+    if ((e = hipStreamBeginCapture(ds->cap_stream, hipStreamCaptureModeRelaxed)) != hipSuccess) return e;
+    hipError_t le = launch_reset_state(ds, ds->cap_stream);
+    for (int32_t t = 0; t < k && le == hipSuccess; ++t)
+        le = launch_greedy_step(ds, t, sel_out, f_out, gain_out, ds->cap_stream, nullptr);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(ds->cap_stream, &g);
+    if (le != hipSuccess) e = le;
+    if (e == hipSuccess) e = hipGraphInstantiate(&ds->gexec, g, nullptr, nullptr, 0);
+    if (g) (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        ds->gexec = nullptr;
+        return e;
+    }
+    ds->g_k = k;
+    ds->g_variant = ds->variant;
+    ds->g_sel = sel_out;
+    ds->g_f = f_out;
+    ds->g_gain = gain_out;
+    return hipSuccess;
+}
+
+}  // namespace
+
+ebc_status ebc_set_greedy_graph(ebc_dataset* ds, int32_t on) {
+    if (!ds) return EBC_E_INVALID_ARG;
+    ds->graph_on = on ? 1 : 0;
+    if (!on) drop_graph(ds);
+    return EBC_OK;
 }
 
 ebc_status ebc_greedy(ebc_dataset* ds, int32_t k, int32_t* sel_out, double* f_out, double* gain_out,
@@ -215,6 +277,15 @@ ebc_status ebc_greedy(ebc_dataset* ds, int32_t k, int32_t* sel_out, double* f_ou
     if (k == 0) return EBC_OK;
     if (!sel_out || !f_out) return EBC_E_INVALID_ARG;
     hipStream_t s = as_stream(stream);
+    ds->stats.steps = k;
+    if (ds->graph_on && !ds->prof) {
+        hipError_t e = hipSuccess;
+        if (!(ds->gexec && ds->g_k == k && ds->g_variant == ds->variant && ds->g_sel == sel_out &&
+              ds->g_f == f_out && ds->g_gain == gain_out))
+            e = capture_greedy(ds, k, sel_out, f_out, gain_out);
+        if (e == hipSuccess) e = hipGraphLaunch(ds->gexec, s);
+        return from_hip(e);
+    }
     hipError_t e = launch_reset_state(ds, s);
     for (int32_t t = 0; t < k && e == hipSuccess; ++t) {
         hipEvent_t ev[3] = {nullptr, nullptr, nullptr};

@@ -42,7 +42,11 @@ struct WindowEntry {
 
 // Pointers into the caller's workspace (see layout()).
 struct Buffers {
-    float* xq;          // [n_pad, k_pad] distance-dtype copy of x; columns d.. are 0
+    float* xq;          // distance-dtype copy of x, columns d.. are 0: float32 row-major [n_pad, k_pad];
+                        // reduced precision: 64-row tiles, 16-byte units unit-major inside a tile
+    uint16_t* aug_c;    // [n_pad, 16] bf16 affine chunk, candidate role, row-major (reduced precision only)
+    uint16_t* aug_v;    // [n_pad, 16] bf16 affine chunk, ground-point role, tiled like xq (reduced precision only)
+    int* scale;         // [n_pad] E8M0 row scales (FP8 only, else null)
     double* n64;        // [n_pad] ||v||^2 in float64 (0 for pad rows)
     double* m64;        // [n_pad] running minima m_v (float64 master copy)
     float* hn;          // [n_pad] ||v||^2 / 2 rounded to float32
@@ -62,7 +66,7 @@ struct Buffers {
 };
 
 struct Layout {
-    size_t off_xq, off_n64, off_m64, off_hn, off_ha, off_hm, off_sel, off_part, off_gsum, off_bmax,
+    size_t off_xq, off_aug_c, off_aug_v, off_scale, off_n64, off_m64, off_hn, off_ha, off_hm, off_sel, off_part, off_gsum, off_bmax,
         off_barg, off_bcnt, off_wstage, off_wfinal, off_rpart, off_fpart, off_state, total;
 };
 
@@ -89,6 +93,13 @@ struct ebc_dataset {
     double l0_host;
     ebc_greedy_stats stats;
     ebc::Profiler* prof;  // non-null while profiling is on
+    int32_t variant;      // tile variant of the gains kernel (0 = default)
+    // captured greedy run (graph mode): replayed while the key matches
+    int32_t graph_on;
+    hipStream_t cap_stream;  // private stream used only to record the graph
+    hipGraphExec_t gexec;
+    int32_t g_k, g_variant;
+    const void *g_sel, *g_f, *g_gain;
 };
 
 namespace ebc {
@@ -98,6 +109,17 @@ hipError_t launch_prep(const ebc_dataset* ds, hipStream_t s);
 hipError_t launch_reset_state(const ebc_dataset* ds, hipStream_t s);
 hipError_t launch_load_m(const ebc_dataset* ds, const double* m, hipStream_t s);
 hipError_t launch_gains_f32(const ebc_dataset* ds, const int32_t* cand, int64_t n_cand, hipStream_t s);
+hipError_t launch_gains_lp(const ebc_dataset* ds, const int32_t* cand, int64_t n_cand, hipStream_t s);
+hipError_t launch_gains(const ebc_dataset* ds, const int32_t* cand, int64_t n_cand, hipStream_t s);
+int elem_bytes(ebc_dtype dt);
+
+// Byte offset of byte `byte` of row r in a tiled reduced-precision array whose
+// rows are `row_units` 16-byte units long (64-row tiles, unit-major).
+__host__ __device__ inline int64_t tiled_offset(int64_t r, int byte, int row_units) {
+    return ((r / 64 * row_units + byte / 16) * 64 + r % 64) * 16 + byte % 16;
+}
+double window_tau(ebc_dtype dt);
+double window_tau_abs(ebc_dtype dt);
 hipError_t launch_gains_out(const ebc_dataset* ds, int64_t n_cand, double* out, hipStream_t s);
 hipError_t launch_greedy_step(const ebc_dataset* ds, int32_t t, int32_t* sel_out, double* f_out,
                               double* gain_out, hipStream_t s, hipEvent_t ev_gains_done);

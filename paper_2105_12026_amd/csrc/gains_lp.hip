@@ -1,0 +1,364 @@
+// Marginal gains with the distances in reduced precision (BF16, FP16 or
+// FP8-e4m3 with a power-of-two scale per row) on the MFMA units, float32
+// accumulation, float64 cross-lane and cross-chunk sums.
+//
+// Same quantity as the float32 kernel (G[c] = sum_v max(0, m_v - d(v,c)),
+// Sec. 3 discrete derivative, Sec. 4.1 per-point decomposition), halved:
+//     G[c]/2 = sum_v med3( x^_v . x^_c + ha_v - hn_c, 0, hm_v )
+// where x^ are the quantised rows, hn = ||x^||^2/2 in float32, hm_v = m_v/2,
+// ha_v = hm_v - hn_v. The affine part ha_v - hn_c is folded into the matrix
+// product through one extra K chunk of 16 bf16 per row, each float32 term
+// split into three bf16 pieces (hi + mid + lo, ~24 significant bits):
+//     candidate row: [1, 1, 1, -hn_hi, -hn_mid, -hn_lo, 0 ...]
+//     ground point:  [ha_hi, ha_mid, ha_lo, 1, 1, 1, 0 ...]
+// so the accumulator leaves the MFMA as the full clamp argument and the
+// epilogue is one v_med3_f32 and one add per (candidate, point) pair.
+//
+// Layout in HBM: the quantised rows are stored in tiles of 64 rows,
+// "unit-major" inside a tile (16-byte unit u of all 64 rows, then unit u+1),
+// and so is the ground-point affine chunk. One wave instruction
+// (global_load_lds_dwordx4) then copies a contiguous kilobyte of a tile
+// straight into LDS with no register staging, and the MFMA operand reads
+// from LDS are 32 consecutive 16-byte units per half-wave (no bank
+// conflicts). A workgroup (4 waves, 32*CB candidates per wave held in
+// registers) streams one chunk of the ground set through a 3-stage LDS ring:
+// the copy of tile t+2 is in flight while tile t is multiplied, with one
+// barrier per tile. MFMA tile: rows = candidates, columns = ground points;
+// each lane reads contiguous K from its half of a row (the order of K
+// inside a dot product is free as long as both operands use the same one).
+#include "ebc_internal.h"
+
+namespace ebc {
+
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 halfx8 __attribute__((ext_vector_type(8)));
+typedef int intx8 __attribute__((ext_vector_type(8)));
+typedef __attribute__((address_space(3))) void lds_void;
+
+template <int DT>
+struct Lp;
+template <>
+struct Lp<EBC_DT_BF16> {
+    static constexpr int kElem = 2, kChunkK = 16, kU4 = 1;  // uint4 per lane-half per chunk
+};
+template <>
+struct Lp<EBC_DT_F16> {
+    static constexpr int kElem = 2, kChunkK = 16, kU4 = 1;
+};
+template <>
+struct Lp<EBC_DT_FP8_E4M3> {
+    static constexpr int kElem = 1, kChunkK = 64, kU4 = 2;
+};
+
+__device__ __forceinline__ floatx16 mfma_aug(uint4 a, uint4 b, floatx16 c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c,
+                                                  0, 0, 0);
+}
+
+template <int DT>
+__device__ __forceinline__ floatx16 mfma_main(const uint4* a, const uint4* b, floatx16 c, int sa, int sb);
+
+template <>
+__device__ __forceinline__ floatx16 mfma_main<EBC_DT_BF16>(const uint4* a, const uint4* b, floatx16 c, int,
+                                                           int) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a[0]), __builtin_bit_cast(bf16x8, b[0]),
+                                                  c, 0, 0, 0);
+}
+template <>
+__device__ __forceinline__ floatx16 mfma_main<EBC_DT_F16>(const uint4* a, const uint4* b, floatx16 c, int, int) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(halfx8, a[0]), __builtin_bit_cast(halfx8, b[0]),
+                                                 c, 0, 0, 0);
+}
+template <>
+__device__ __forceinline__ floatx16 mfma_main<EBC_DT_FP8_E4M3>(const uint4* a, const uint4* b, floatx16 c, int sa,
+                                                               int sb) {
+    const intx8 av = {int(a[0].x), int(a[0].y), int(a[0].z), int(a[0].w), int(a[1].x), int(a[1].y), int(a[1].z),
+                      int(a[1].w)};
+    const intx8 bv = {int(b[0].x), int(b[0].y), int(b[0].z), int(b[0].w), int(b[1].x), int(b[1].y), int(b[1].z),
+                      int(b[1].w)};
+    // format 0 = e4m3 for both operands; E8M0 scales of the lane's row / column
+    return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(av, bv, c, 0, 0, 0, sa, 0, sb);
+}
+
+// s_waitcnt with only the vector-memory counter constrained (<= N).
+template <int N>
+__device__ __forceinline__ void wait_vmcnt() {
+    static_assert(N >= 0 && N < 64, "vmcnt range");
+    __builtin_amdgcn_s_waitcnt((N & 0xF) | ((N >> 4) << 14) | (0x7 << 4) | (0xF << 8));
+}
+
+// Workgroup barrier for the LDS ring without the release/acquire fences of
+// __syncthreads (those would also wait for the copies still in flight into
+// the other stages). The caller has already waited for its own copies of the
+// stage about to be read; here the wave's LDS reads are drained, and the
+// empty asm statements keep the compiler from moving memory accesses across.
+__device__ __forceinline__ void ring_barrier() {
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_waitcnt(0xF | (0x3 << 14) | (0x7 << 4));  // lgkmcnt(0), vmcnt/expcnt untouched
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+}
+
+template <int DT, int KC, int CB>
+struct LpGeom {
+    using T = Lp<DT>;
+    static constexpr int RB = KC * T::kChunkK * T::kElem;  // bytes per quantised row
+    static constexpr int RU = RB / 16;                     // 16-byte units per row
+    static constexpr int HU = RU / 2;                      // units per lane half-row
+    static constexpr int VT = 64;                          // rows per tile
+    static constexpr bool kFp8 = DT == EBC_DT_FP8_E4M3;
+    // LDS stage: [RU units x 64 rows][2 aug units x 64 rows][hm: 64 floats][scale: 64 ints]
+    static constexpr int OFF_AUG = RU * VT;
+    static constexpr int OFF_HM = OFF_AUG + 2 * VT;
+    static constexpr int OFF_SC = OFF_HM + VT / 4;
+    static constexpr int STAGE = OFF_SC + (kFp8 ? VT / 4 : 0);  // uint4 per stage
+    static constexpr int NI = RU + 2 + 1 + (kFp8 ? 1 : 0);     // wave copy instructions per stage
+    static constexpr int L = (NI + 3) / 4;                      // copy instructions per wave per stage
+    static constexpr int NBUF = 3;
+    static constexpr int CAND_TILE = 4 * 32 * CB;
+};
+
+// Wave-wide copy of one piece of ground-set tile `tile` into LDS stage `st`.
+// Piece j: j < RU main unit j; then the two affine units; then the 64 half
+// minima; then (FP8) the 64 row scales.
+template <class G>
+__device__ __forceinline__ void copy_piece(int j, int64_t tile, int lane, const uint4* __restrict__ xqt,
+                                           const uint4* __restrict__ augt, const float* __restrict__ hm,
+                                           const int* __restrict__ sc, uint4* st) {
+    if (j < G::RU) {
+        __builtin_amdgcn_global_load_lds(xqt + (tile * G::RU + j) * G::VT + lane, (lds_void*)(st + j * G::VT), 16,
+                                         0, 0);
+    } else if (j < G::RU + 2) {
+        const int u = j - G::RU;
+        __builtin_amdgcn_global_load_lds(augt + (tile * 2 + u) * G::VT + lane,
+                                         (lds_void*)(st + G::OFF_AUG + u * G::VT), 16, 0, 0);
+    } else if (j == G::RU + 2) {
+        __builtin_amdgcn_global_load_lds(hm + tile * G::VT + lane, (lds_void*)(st + G::OFF_HM), 4, 0, 0);
+    } else {
+        __builtin_amdgcn_global_load_lds(sc + tile * G::VT + lane, (lds_void*)(st + G::OFF_SC), 4, 0, 0);
+    }
+}
+
+// Every wave issues exactly L copy instructions per stage (some repeat a
+// piece another wave also copies: same bytes to the same place), so the
+// vector-memory counter is the same on every wave.
+template <class G>
+__device__ __forceinline__ void copy_stage(int wave, int lane, int64_t tile, const uint4* __restrict__ xqt,
+                                           const uint4* __restrict__ augt, const float* __restrict__ hm,
+                                           const int* __restrict__ sc, uint4* st) {
+#pragma unroll
+    for (int l = 0; l < G::L; ++l) copy_piece<G>((wave + 4 * l) % G::NI, tile, lane, xqt, augt, hm, sc, st);
+}
+
+// One ground-set tile: wait for its copy, start the copy of the tile two
+// ahead into `next2`, then the MFMAs and the fused clamp-and-sum epilogue
+// against the wave's candidate blocks.
+template <class G, int DT, int KC, int CB>
+__device__ __forceinline__ void lp_tile(int64_t t, int64_t nt, int64_t t_begin, int wave, int lane, int col, int half,
+                                        const uint4* __restrict__ xqt, const uint4* __restrict__ augt,
+                                        const float* __restrict__ hm, const int* __restrict__ sc, const uint4* st,
+                                        uint4* next2, const uint4 (&a)[CB][G::HU], const uint4 (&aa)[CB],
+                                        const int (&sa)[CB], float (&acc_sum)[CB][16]) {
+    using T = Lp<DT>;
+    constexpr int HU = G::HU, VT = G::VT;
+    // this wave's copies of tile t are done (those of t+1 may still fly) ...
+    if (t + 1 < nt)
+        wait_vmcnt<G::L>();
+    else
+        wait_vmcnt<0>();
+    // ... and every wave's, and every wave finished reading tile t-1, whose
+    // stage the next copy overwrites
+    ring_barrier();
+    if (t + 2 < nt) copy_stage<G>(wave, lane, t_begin + t + 2, xqt, augt, hm, sc, next2);
+    const float* st_hm = reinterpret_cast<const float*>(st + G::OFF_HM);
+    const int* st_sc = reinterpret_cast<const int*>(st + G::OFF_SC);
+#pragma unroll
+    for (int colb = 0; colb < VT / 32; ++colb) {
+        const int vrow = colb * 32 + col;
+        uint4 b[HU];
+#pragma unroll
+        for (int u = 0; u < HU; ++u) b[u] = st[(half * HU + u) * VT + vrow];
+        const uint4 ba = st[G::OFF_AUG + half * VT + vrow];
+        const float hmv = st_hm[vrow];
+        const int sb = G::kFp8 ? st_sc[vrow] : 127;
+        // CB independent accumulator chains
+        floatx16 acc[CB];
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) acc[cb] = mfma_aug(aa[cb], ba, floatx16{});
+#pragma unroll
+        for (int q = 0; q < KC; ++q)
+#pragma unroll
+            for (int cb = 0; cb < CB; ++cb)
+                acc[cb] = mfma_main<DT>(&a[cb][q * T::kU4], &b[q * T::kU4], acc[cb], sa[cb], sb);
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc_sum[cb][r] += __builtin_amdgcn_fmed3f(acc[cb][r], 0.0f, hmv);
+    }
+}
+
+template <int DT, int KC, int CB>
+__global__ void __launch_bounds__(256)
+k_gains_lp(const uint4* __restrict__ xqt, const uint4* __restrict__ aug_c, const uint4* __restrict__ augt,
+           const int* __restrict__ sc, const float* __restrict__ hm, const int32_t* __restrict__ cand,
+           int64_t n_cand, int64_t n_pad, int32_t v_splits, int64_t chunk, double* __restrict__ part,
+           int64_t part_stride, int* __restrict__ err) {
+    using G = LpGeom<DT, KC, CB>;
+    using T = Lp<DT>;
+    constexpr int RU = G::RU, HU = G::HU, VT = G::VT;
+    static_assert(HU == KC * T::kU4, "lane half-row must hold KC chunks");
+
+    __shared__ uint4 lds0[G::STAGE];
+    __shared__ uint4 lds1[G::STAGE];
+    __shared__ uint4 lds2[G::STAGE];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int col = lane & 31;
+    const int half = lane >> 5;
+    const int64_t bid = blockIdx.x;
+    const int split = int(bid % v_splits);
+    const int64_t ctile = bid / v_splits;
+    const int64_t wbase = ctile * G::CAND_TILE + int64_t(wave) * (32 * CB);
+
+    // ---- candidate rows (A operand) in registers ----
+    uint4 a[CB][HU];
+    uint4 aa[CB];
+    int sa[CB];
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb) {
+        const int64_t cpos = wbase + cb * 32 + col;
+        int64_t crow = -1;
+        if (cpos < n_cand) crow = cand ? int64_t(cand[cpos]) : cpos;
+        if (crow >= n_pad || (cpos < n_cand && crow < 0)) {
+            atomicCAS(err, 0, kDevErrIndex);
+            crow = -1;
+        }
+        if (crow >= 0) {
+            const uint4* src = xqt + (crow / VT) * (RU * VT) + (crow % VT);
+#pragma unroll
+            for (int u = 0; u < HU; ++u) a[cb][u] = src[(half * HU + u) * VT];
+            aa[cb] = aug_c[crow * 2 + half];
+            sa[cb] = G::kFp8 ? sc[crow] : 127;
+        } else {
+#pragma unroll
+            for (int u = 0; u < HU; ++u) a[cb][u] = make_uint4(0, 0, 0, 0);
+            aa[cb] = make_uint4(0, 0, 0, 0);
+            sa[cb] = 127;
+        }
+    }
+    float acc_sum[CB][16];
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc_sum[cb][r] = 0.0f;
+
+    // ---- stream the ground-set chunk through the LDS ring ----
+    const int64_t v_begin = int64_t(split) * chunk;
+    int64_t v_end = v_begin + chunk;
+    if (v_end > n_pad) v_end = n_pad;
+    const int64_t t_begin = v_begin / VT;
+    const int64_t nt = v_end > v_begin ? (v_end - v_begin) / VT : 0;
+
+    if (nt > 0) copy_stage<G>(wave, lane, t_begin, xqt, augt, hm, sc, lds0);
+    if (nt > 1) copy_stage<G>(wave, lane, t_begin + 1, xqt, augt, hm, sc, lds1);
+    // three stages are three distinct LDS objects and the loop is unrolled
+    // by three, so the compiler can see that the copy in flight never
+    // targets the stage being read and does not wait for it
+    for (int64_t t = 0; t < nt; t += 3) {
+        lp_tile<G, DT, KC, CB>(t, nt, t_begin, wave, lane, col, half, xqt, augt, hm, sc, lds0, lds2, a, aa, sa, acc_sum);
+        if (t + 1 < nt)
+            lp_tile<G, DT, KC, CB>(t + 1, nt, t_begin, wave, lane, col, half, xqt, augt, hm, sc, lds1, lds0, a, aa, sa,
+                                   acc_sum);
+        if (t + 2 < nt)
+            lp_tile<G, DT, KC, CB>(t + 2, nt, t_begin, wave, lane, col, half, xqt, augt, hm, sc, lds2, lds1, a, aa, sa,
+                                   acc_sum);
+    }
+
+    // ---- float64 sum over the 32 columns of each half; one lane per row writes ----
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb) {
+        double mine = 0.0;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            double v = double(acc_sum[cb][r]);
+#pragma unroll
+            for (int off = 16; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+            if (col == r) mine = v;
+        }
+        if (col < 16) {
+            const int r = col;
+            const int64_t p = wbase + cb * 32 + 8 * (r / 4) + 4 * half + (r % 4);
+            if (p < n_cand) part[int64_t(split) * part_stride + p] = 2.0 * mine;
+        }
+    }
+}
+
+template <int DT, int KC, int CB>
+static void launch_lp_v(const ebc_dataset* ds, const int32_t* cand, int64_t n_cand, hipStream_t s) {
+    using G = LpGeom<DT, KC, CB>;
+    const int64_t tiles = (n_cand + G::CAND_TILE - 1) / G::CAND_TILE;
+    const int vs = ds->v_splits;
+    // chunk boundaries do not depend on the variant (multiples of 256), so
+    // every variant sums the same terms in the same order
+    int64_t chunk = (ds->n_pad + vs - 1) / vs;
+    chunk = (chunk + 255) / 256 * 256;
+    hipLaunchKernelGGL((k_gains_lp<DT, KC, CB>), dim3(unsigned(tiles * vs)), dim3(256), 0, s,
+                       reinterpret_cast<const uint4*>(ds->b.xq), reinterpret_cast<const uint4*>(ds->b.aug_c),
+                       reinterpret_cast<const uint4*>(ds->b.aug_v), ds->b.scale, ds->b.hm, cand, n_cand, ds->n_pad,
+                       vs, chunk, ds->b.part, ds->n_pad, &ds->b.state->error);
+}
+
+// Variants: 32-row candidate blocks per wave (2 or 4).
+template <int DT, int KC>
+static void launch_lp(const ebc_dataset* ds, const int32_t* cand, int64_t n_cand, hipStream_t s) {
+    if (ds->variant == 1)
+        launch_lp_v<DT, KC, 4>(ds, cand, n_cand, s);
+    else
+        launch_lp_v<DT, KC, 2>(ds, cand, n_cand, s);
+}
+
+hipError_t launch_gains_lp(const ebc_dataset* ds, const int32_t* cand, int64_t n_cand, hipStream_t s) {
+    const int kc = ds->k_pad / (ds->dt == EBC_DT_FP8_E4M3 ? 64 : 16);
+    switch (ds->dt) {
+        case EBC_DT_BF16:
+            switch (kc) {
+                case 1: launch_lp<EBC_DT_BF16, 1>(ds, cand, n_cand, s); break;
+                case 2: launch_lp<EBC_DT_BF16, 2>(ds, cand, n_cand, s); break;
+                case 3: launch_lp<EBC_DT_BF16, 3>(ds, cand, n_cand, s); break;
+                case 4: launch_lp<EBC_DT_BF16, 4>(ds, cand, n_cand, s); break;
+                case 5: launch_lp<EBC_DT_BF16, 5>(ds, cand, n_cand, s); break;
+                case 6: launch_lp<EBC_DT_BF16, 6>(ds, cand, n_cand, s); break;
+                case 7: launch_lp<EBC_DT_BF16, 7>(ds, cand, n_cand, s); break;
+                case 8: launch_lp<EBC_DT_BF16, 8>(ds, cand, n_cand, s); break;
+                default: return hipErrorInvalidValue;
+            }
+            break;
+        case EBC_DT_F16:
+            switch (kc) {
+                case 1: launch_lp<EBC_DT_F16, 1>(ds, cand, n_cand, s); break;
+                case 2: launch_lp<EBC_DT_F16, 2>(ds, cand, n_cand, s); break;
+                case 3: launch_lp<EBC_DT_F16, 3>(ds, cand, n_cand, s); break;
+                case 4: launch_lp<EBC_DT_F16, 4>(ds, cand, n_cand, s); break;
+                case 5: launch_lp<EBC_DT_F16, 5>(ds, cand, n_cand, s); break;
+                case 6: launch_lp<EBC_DT_F16, 6>(ds, cand, n_cand, s); break;
+                case 7: launch_lp<EBC_DT_F16, 7>(ds, cand, n_cand, s); break;
+                case 8: launch_lp<EBC_DT_F16, 8>(ds, cand, n_cand, s); break;
+                default: return hipErrorInvalidValue;
+            }
+            break;
+        case EBC_DT_FP8_E4M3:
+            switch (kc) {
+                case 1: launch_lp<EBC_DT_FP8_E4M3, 1>(ds, cand, n_cand, s); break;
+                case 2: launch_lp<EBC_DT_FP8_E4M3, 2>(ds, cand, n_cand, s); break;
+                default: return hipErrorInvalidValue;
+            }
+            break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace ebc

@@ -4,6 +4,7 @@
 #include <math.h>
 
 #include "ebc_internal.h"
+#include "quant.h"
 
 namespace ebc {
 
@@ -11,11 +12,28 @@ static size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
 int64_t pad_rows(int64_t n) { return (n + kRowAlign - 1) / kRowAlign * kRowAlign; }
 
-int32_t k_pad_for(int32_t d, ebc_dtype) {
-    // Rows are a multiple of 8 floats so that each half of a row is a whole
-    // number of 16-byte vectors; the padding columns hold 0.
-    return (d + 7) / 8 * 8;
+int32_t k_pad_for(int32_t d, ebc_dtype dt) {
+    // Row length of the distance-dtype copy, padded with zeros to the K of
+    // the matrix instruction (each half of a row is whole 16-byte vectors):
+    // float32 32x32x2 -> 8, bf16/f16 32x32x16 -> 16, e4m3 32x32x64 -> 64.
+    const int g = dt == EBC_DT_F32 ? 8 : (dt == EBC_DT_FP8_E4M3 ? 64 : 16);
+    return (d + g - 1) / g * g;
 }
+
+int elem_bytes(ebc_dtype dt) { return dt == EBC_DT_F32 ? 4 : (dt == EBC_DT_FP8_E4M3 ? 1 : 2); }
+
+// Relative and absolute half-widths of the float64 re-score window per
+// distance dtype (see launch_reset_state).
+double window_tau(ebc_dtype dt) {
+    switch (dt) {
+        case EBC_DT_F32: return 1e-4;
+        case EBC_DT_F16: return 2e-3;
+        case EBC_DT_BF16: return 1e-2;
+        case EBC_DT_FP8_E4M3: return 4e-2;
+    }
+    return 1e-2;
+}
+double window_tau_abs(ebc_dtype dt) { return dt == EBC_DT_F32 ? 1e-4 : 1e-2; }
 
 int32_t v_splits_for(int64_t n_pad) {
     // The ground set is cut into one chunk per XCD (8 on MI355X) once there
@@ -33,9 +51,13 @@ Layout layout(int64_t n, int32_t d, ebc_dtype dt) {
     const int64_t np = pad_rows(n);
     const int32_t kp = k_pad_for(d, dt);
     const int64_t nb = np / kBlock + 1;
+    const bool lp = dt != EBC_DT_F32;
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t at = o; o = align256(o + bytes); return at; };
-    L.off_xq = take(size_t(np) * kp * sizeof(float));
+    L.off_xq = take(size_t(np) * kp * elem_bytes(dt));
+    L.off_aug_c = lp ? take(size_t(np) * 16 * sizeof(uint16_t)) : 0;
+    L.off_aug_v = lp ? take(size_t(np) * 16 * sizeof(uint16_t)) : 0;
+    L.off_scale = dt == EBC_DT_FP8_E4M3 ? take(size_t(np) * sizeof(int)) : 0;
     L.off_n64 = take(size_t(np) * sizeof(double));
     L.off_m64 = take(size_t(np) * sizeof(double));
     L.off_hn = take(size_t(np) * sizeof(float));
@@ -110,6 +132,120 @@ __global__ void __launch_bounds__(kBlock) k_prep(const float* __restrict__ x, in
     }
 }
 
+// Reduced-precision copy: one thread per padded row. Exact float64 norm and
+// initial state as in k_prep, then the row cast with round-to-nearest-even
+// (FP8: after a power-of-two row scale), the float32 norm of the cast row,
+// and the two affine-chunk rows. FP16 values beyond its range raise
+// EBC_E_RANGE.
+__global__ void __launch_bounds__(kBlock) k_prep_lp(const float* __restrict__ x, int64_t n, int32_t d,
+                                                    int32_t kp, int dt, Buffers b) {
+    __shared__ double red[kBlock];
+    __shared__ double rmax[kBlock];
+    const int64_t r = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+    double nv = 0.0;
+    if (r < n) {
+        const float* xr = x + r * d;
+        bool bad = false, range = false;
+        float amax = 0.0f;
+        for (int k = 0; k < d; ++k) {
+            const float v = xr[k];
+            bad |= !isfinite(v);
+            nv += double(v) * double(v);
+            amax = fmaxf(amax, fabsf(v));
+        }
+        double nq = 0.0;  // norm of the cast row
+        const int eb = dt == EBC_DT_FP8_E4M3 ? 1 : 2;
+        const int ru = kp * eb / 16;
+        uint8_t* base = reinterpret_cast<uint8_t*>(b.xq);
+        if (dt == EBC_DT_FP8_E4M3) {
+            int se = 0;  // scale exponent: ceil(log2(amax / 448))
+            if (amax > 0.0f) {
+                int e;
+                const float m = frexpf(amax / 448.0f, &e);
+                se = (m == 0.5f) ? e - 1 : e;
+                se = se < -126 ? -126 : (se > 126 ? 126 : se);
+            }
+            b.scale[r] = 127 + se;
+            for (int k = 0; k < kp; ++k) {
+                uint8_t c = 0;
+                if (k < d) {
+                    c = f32_to_e4m3_rne(ldexpf(xr[k], -se));
+                    const double xv = ldexp(double(e4m3_to_f32(c)), se);
+                    nq += xv * xv;
+                }
+                base[tiled_offset(r, k, ru)] = c;
+            }
+        } else {
+            for (int k = 0; k < kp; ++k) {
+                uint16_t c = 0;
+                if (k < d) {
+                    float back;
+                    if (dt == EBC_DT_BF16) {
+                        c = f32_to_bf16_rne(xr[k]);
+                        back = bf16_to_f32(c);
+                    } else {
+                        range |= fabsf(xr[k]) > 65504.0f;
+                        const _Float16 h = _Float16(xr[k]);
+                        c = __builtin_bit_cast(uint16_t, h);
+                        back = float(h);
+                    }
+                    nq += double(back) * double(back);
+                }
+                *reinterpret_cast<uint16_t*>(base + tiled_offset(r, 2 * k, ru)) = c;
+            }
+        }
+        if (bad) atomicCAS(&b.state->error, 0, kDevErrNonFinite);
+        if (range) atomicCAS(&b.state->error, 0, int(EBC_E_RANGE));
+        const float hn = float(0.5 * nq);
+        b.hn[r] = hn;
+        b.n64[r] = nv;
+        b.m64[r] = nv;
+        b.selected[r] = 0;
+        uint16_t p[3];
+        split3_bf16(-hn, p);
+        uint16_t* ac = b.aug_c + r * 16;
+        uint8_t* avb = reinterpret_cast<uint8_t*>(b.aug_v);
+        for (int k = 0; k < 16; ++k) {
+            ac[k] = 0;
+            *reinterpret_cast<uint16_t*>(avb + tiled_offset(r, 2 * k, 2)) = (k >= 3 && k < 6) ? kBf16One : 0;
+        }
+        ac[0] = ac[1] = ac[2] = kBf16One;
+        ac[3] = p[0];
+        ac[4] = p[1];
+        ac[5] = p[2];
+        set_point_terms(b, r, nv);
+    } else {
+        const int eb = dt == EBC_DT_FP8_E4M3 ? 1 : 2;
+        const int ru = kp * eb / 16;
+        uint8_t* base = reinterpret_cast<uint8_t*>(b.xq);
+        for (int k = 0; k < kp * eb; ++k) base[tiled_offset(r, k, ru)] = 0;
+        uint8_t* avb = reinterpret_cast<uint8_t*>(b.aug_v);
+        for (int k = 0; k < 32; ++k) avb[tiled_offset(r, k, 2)] = 0;
+        for (int k = 0; k < 16; ++k) b.aug_c[r * 16 + k] = 0;
+        if (b.scale) b.scale[r] = 127;
+        b.n64[r] = 0.0;
+        b.m64[r] = 0.0;
+        b.hn[r] = 0.0f;
+        b.ha[r] = 0.0f;
+        b.hm[r] = 0.0f;
+        b.selected[r] = 1;
+    }
+    red[threadIdx.x] = nv;
+    rmax[threadIdx.x] = nv;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) {
+            red[threadIdx.x] += red[threadIdx.x + w];
+            rmax[threadIdx.x] = fmax(rmax[threadIdx.x], rmax[threadIdx.x + w]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        b.fpart[blockIdx.x] = red[0];
+        b.bmax[blockIdx.x] = rmax[0];
+    }
+}
+
 // One block: L({e0}) = |V|^-1 sum of the per-block norm sums (fixed order),
 // and the largest norm.
 __global__ void __launch_bounds__(kBlock) k_l0(int64_t n, int32_t nblocks, Buffers b) {
@@ -155,7 +291,11 @@ __global__ void k_state_init(DevState* st) {
 hipError_t launch_prep(const ebc_dataset* ds, hipStream_t s) {
     const int nb = int(ds->n_pad / kBlock);
     hipLaunchKernelGGL(k_state_init, dim3(1), dim3(64), 0, s, ds->b.state);
-    hipLaunchKernelGGL(k_prep, dim3(nb), dim3(kBlock), 0, s, ds->x, ds->n, ds->d, ds->k_pad, ds->b);
+    if (ds->dt == EBC_DT_F32)
+        hipLaunchKernelGGL(k_prep, dim3(nb), dim3(kBlock), 0, s, ds->x, ds->n, ds->d, ds->k_pad, ds->b);
+    else
+        hipLaunchKernelGGL(k_prep_lp, dim3(nb), dim3(kBlock), 0, s, ds->x, ds->n, ds->d, ds->k_pad, int(ds->dt),
+                           ds->b);
     hipLaunchKernelGGL(k_l0, dim3(1), dim3(kBlock), 0, s, ds->n, nb, ds->b);
     return hipGetLastError();
 }
@@ -166,8 +306,7 @@ __global__ void __launch_bounds__(kBlock) k_reset(int64_t n, Buffers b, double t
     if (r < n) {
         const double nv = b.n64[r];
         b.m64[r] = nv;
-        b.ha[r] = float(0.5 * nv - double(b.hn[r]));
-        b.hm[r] = float(0.5 * nv);
+        set_point_terms(b, r, nv);
         b.selected[r] = 0;
     }
     if (r == 0) {
@@ -186,7 +325,7 @@ hipError_t launch_reset_state(const ebc_dataset* ds, hipStream_t s) {
     // is within tau * |best| + tau_abs * max_v ||v||^2 of the best is
     // re-scored in float64. The absolute part keeps every candidate of a
     // zero-gain step (all points already covered) inside the window.
-    const double tau = 1e-4, tau_abs = 1e-4;
+    const double tau = window_tau(ds->dt), tau_abs = window_tau_abs(ds->dt);
     hipLaunchKernelGGL(k_reset, dim3(ds->n_pad / kBlock), dim3(kBlock), 0, s, ds->n, ds->b, tau, tau_abs);
     return hipGetLastError();
 }
@@ -197,8 +336,7 @@ __global__ void __launch_bounds__(kBlock) k_load_m(int64_t n, const double* __re
     if (r < n) {
         const double mv = m[r];
         b.m64[r] = mv;
-        b.ha[r] = float(0.5 * mv - double(b.hn[r]));
-        b.hm[r] = float(0.5 * mv);
+        set_point_terms(b, r, mv);
     }
 }
 

@@ -11,6 +11,7 @@
 #include <math.h>
 
 #include "ebc_internal.h"
+#include "quant.h"
 
 namespace ebc {
 
@@ -286,8 +287,7 @@ k_update(const float* __restrict__ x, int64_t n, int32_t d, Buffers b) {
         if (acc < mv) {
             mv = acc;
             b.m64[v] = mv;
-            b.ha[v] = float(0.5 * mv - double(b.hn[v]));
-            b.hm[v] = float(0.5 * mv);
+            set_point_terms(b, v, mv);
         }
     }
     red[threadIdx.x] = mv;
@@ -315,7 +315,7 @@ k_fsum(int64_t n, int32_t nbv, int32_t t, Buffers b, double* f_out) {
 
 hipError_t launch_greedy_step(const ebc_dataset* ds, int32_t t, int32_t* sel_out, double* f_out,
                               double* gain_out, hipStream_t s, hipEvent_t ev_gains_done) {
-    hipError_t e = launch_gains_f32(ds, nullptr, ds->n_pad, s);
+    hipError_t e = launch_gains(ds, nullptr, ds->n_pad, s);
     if (e != hipSuccess) return e;
     if (ev_gains_done && (e = hipEventRecord(ev_gains_done, s)) != hipSuccess) return e;
     const int nb = int(ds->n_pad / kBlock);
@@ -327,6 +327,10 @@ hipError_t launch_greedy_step(const ebc_dataset* ds, int32_t t, int32_t* sel_out
     hipLaunchKernelGGL(k_update, dim3(nb), dim3(kBlock), 0, s, ds->x, ds->n, ds->d, ds->b);
     hipLaunchKernelGGL(k_fsum, dim3(1), dim3(kBlock), 0, s, ds->n, nb, t, ds->b, f_out);
     return hipGetLastError();
+}
+
+hipError_t launch_gains(const ebc_dataset* ds, const int32_t* cand, int64_t n_cand, hipStream_t s) {
+    return ds->dt == EBC_DT_F32 ? launch_gains_f32(ds, cand, n_cand, s) : launch_gains_lp(ds, cand, n_cand, s);
 }
 
 // Marginal-gains output: sum the per-chunk sums, divide by |V|.

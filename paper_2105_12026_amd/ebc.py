@@ -16,11 +16,12 @@ import torch  # loads the process's HIP runtime before libebc.so binds to it
 __all__ = ["EBCError", "Dataset", "lib", "status_string", "DTYPES", "LIB_PATH", "ABI_FUNCTIONS"]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libebc.so")
-DTYPES = {"f32": 0}
+DTYPES = {"f32": 0, "f16": 1, "bf16": 2, "fp8": 3}
 ABI_FUNCTIONS = (
     "ebc_dataset_bytes", "ebc_dataset_create", "ebc_dataset_destroy", "ebc_eval_sets",
     "ebc_marginal_gains", "ebc_greedy", "ebc_sync_status", "ebc_status_string",
-    "ebc_dataset_get_info", "ebc_profile_enable", "ebc_profile_read",
+    "ebc_dataset_get_info", "ebc_profile_enable", "ebc_profile_read", "ebc_set_gains_variant",
+    "ebc_gains_variant_count", "ebc_set_greedy_graph",
 )
 
 
@@ -69,6 +70,9 @@ def lib() -> ctypes.CDLL:
         L.ebc_status_string.restype = ctypes.c_char_p
         L.ebc_dataset_get_info.argtypes = [P, ctypes.POINTER(_Info)]
         L.ebc_profile_enable.argtypes = [P, i32]
+        L.ebc_set_gains_variant.argtypes = [P, i32]
+        L.ebc_set_greedy_graph.argtypes = [P, i32]
+        L.ebc_gains_variant_count.argtypes = [ctypes.c_int]
         L.ebc_profile_read.argtypes = [P, ctypes.POINTER(_Profile), i32]
         for name in ABI_FUNCTIONS:
             if name not in ("ebc_dataset_bytes", "ebc_status_string"):
@@ -109,6 +113,8 @@ class Dataset:
         self.n, self.d = map(int, self.x.shape)
         self.dtype = dtype
         L = lib()
+        if dtype not in DTYPES:
+            raise ValueError(f"dtype must be one of {sorted(DTYPES)}")
         nbytes = L.ebc_dataset_bytes(self.n, self.d, DTYPES[dtype])
         if nbytes == 0:
             raise EBCError(1 if self.d <= 128 else 7, f"ebc_dataset_bytes(n={self.n}, d={self.d})")
@@ -146,6 +152,18 @@ class Dataset:
         inf = _Info()
         _check(lib().ebc_dataset_get_info(self._h, ctypes.byref(inf)), "ebc_dataset_get_info")
         return {f: getattr(inf, f) for f, _ in _Info._fields_}
+
+    def set_variant(self, variant: int):
+        """Tile shape of the gains kernel (results are identical across variants)."""
+        _check(lib().ebc_set_gains_variant(self._h, int(variant)), "ebc_set_gains_variant")
+
+    def set_graph(self, on: bool = True):
+        """Record greedy runs into a HIP graph and replay it (identical results)."""
+        _check(lib().ebc_set_greedy_graph(self._h, int(bool(on))), "ebc_set_greedy_graph")
+
+    @staticmethod
+    def variant_count(dtype: str) -> int:
+        return int(lib().ebc_gains_variant_count(DTYPES[dtype]))
 
     def profile(self, on: bool = True):
         """Turn per-step HIP-event timing of greedy on or off."""

@@ -1,0 +1,85 @@
+"""Reduced-precision distances (BF16, FP16, FP8-e4m3 with E8M0 row scales)
+against the FP64 oracle.
+
+Bars, per distance dtype (relative to the largest gain of the vector):
+  gains   max_c |G_dt - G_ref| / max_c |G_ref|   <= GAIN_TOL[dt]
+  greedy  f(S_t) is float64 for the chosen set (checked exactly against the
+          oracle's f of that set); quality gap of the final set against the
+          oracle's greedy <= GAP_TOL[dt]; selection agreement is printed.
+"""
+import numpy as np
+import pytest
+
+from paper_2105_12026_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+GAIN_TOL = {"bf16": 1e-2, "f16": 2e-3, "fp8": 8e-2}
+GAP_TOL = {"bf16": 1e-3, "f16": 1e-3, "fp8": 2e-2}
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    from paper_2105_12026_amd import ebc
+    assert torch.cuda.is_available()
+    return torch, ebc
+
+
+def _ds(env, x, dt):
+    torch, ebc = env
+    return ebc.Dataset(torch.from_numpy(np.ascontiguousarray(x, np.float32)).cuda(), dtype=dt)
+
+
+@pytest.mark.parametrize("dt", ["bf16", "f16", "fp8"])
+@pytest.mark.parametrize("n,d,seed", [(3000, 64, 1), (1500, 100, 2), (777, 16, 3), (260, 128, 4), (5, 3, 5)])
+def test_lowprec_gains(env, ref, dt, n, d, seed):
+    torch, _ = env
+    rng = np.random.default_rng(seed)
+    x = W.gaussian_mixture(rng, n, d, 6).astype(np.float32)
+    print(f"[gpu-case] gains {dt} n={n} d={d}", flush=True)
+    ds = _ds(env, x, dt)
+    errs = []
+    for s in ([], list(rng.choice(n, min(n, 4), replace=False))):
+        m = ref.min_dist(x, s)
+        g = ds.marginal_gains(m=torch.from_numpy(m)).cpu().numpy()
+        ds.sync()
+        rg = ref.gains(x, m)
+        errs.append(float(np.max(np.abs(g - rg)) / np.max(np.abs(rg))))
+    print(f"[gpu-result] gains {dt} n={n} d={d} rel err {max(errs):.3e}", flush=True)
+    assert max(errs) <= GAIN_TOL[dt]
+
+
+@pytest.mark.parametrize("dt", ["bf16", "f16", "fp8"])
+def test_lowprec_greedy_quality(env, ref, dt):
+    rng = np.random.default_rng(7)
+    x = W.gaussian_mixture(rng, 4000, 64, 12).astype(np.float32)
+    k = 16
+    print(f"[gpu-case] greedy {dt} n=4000 d=64 k={k}", flush=True)
+    ds = _ds(env, x, dt)
+    sel, f, g = ds.greedy(k)
+    stats = ds.sync()
+    sel = sel.cpu().numpy()
+    rsel, rf, _ = ref.greedy(x, k)
+    # f(S_t) of the chosen sets is float64-exact
+    l0 = float(np.mean(np.sum(x.astype(np.float64) ** 2, axis=1)))
+    for t in (0, k // 2, k - 1):
+        m = ref.min_dist(x, sel[:t + 1])
+        assert f.cpu().numpy()[t] == pytest.approx(l0 - float(np.mean(m)), rel=1e-9)
+    agree = len(set(sel.tolist()) & set(rsel.tolist())) / k
+    prefix = next((i for i in range(k) if sel[i] != rsel[i]), k)
+    gap = (rf[-1] - f.cpu().numpy()[-1]) / rf[-1]
+    print(f"[gpu-result] greedy {dt}: agreement {agree:.2f} common prefix {prefix} quality gap {gap:.2e} "
+          f"window max {stats['window_max']}", flush=True)
+    assert gap <= GAP_TOL[dt]
+
+
+def test_f16_range_is_reported(env):
+    _, ebc = env
+    x = np.ones((40, 4), np.float32)
+    x[3, 1] = 1e5
+    print("[gpu-case] f16 range", flush=True)
+    ds = _ds(env, x, "f16")
+    with pytest.raises(ebc.EBCError) as ei:
+        ds.sync()
+    assert ei.value.code == 4

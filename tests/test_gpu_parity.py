@@ -272,3 +272,37 @@ def test_full_size_greedy_against_golden(ebc, torch_dev, ref, gmm100k):
     cand = np.random.default_rng(82).choice(p.n, 64, replace=False).astype(np.int32)
     rg = ref.gains(p.x, ref.min_dist(p.x, gold["sel"]), cand)
     assert np.max(np.abs(gl[cand] - rg)) <= G_RTOL * max(np.max(gl), np.max(rg))
+
+
+# ---------------------------------------------------------------------------
+# graph mode: every replay equals the eager run (bitwise)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("dt", ["f32", "bf16"])
+def test_graph_replays_match_eager(ebc, torch_dev, dt):
+    torch, dev = torch_dev
+    p = W.small_normal(seed=0)
+    x = torch.from_numpy(p.x).to(dev)
+    _say(f"graph replays {dt} n=1000 d=16 k=5")
+    eager = ebc.Dataset(x, dtype=dt)
+    ref_out = [t.cpu().numpy() for t in eager.greedy(p.k)]
+    eager.sync()
+    ds = ebc.Dataset(x, dtype=dt)
+    ds.set_graph(True)
+    sel = torch.empty(p.k, dtype=torch.int32, device=dev)
+    f = torch.empty(p.k, dtype=torch.float64, device=dev)
+    g = torch.empty(p.k, dtype=torch.float64, device=dev)
+    for rep in range(4):
+        sel.fill_(-7)
+        f.zero_()
+        ds.greedy(p.k, sel=sel, f=f, gain=g)      # first call records, later calls replay
+        ds.sync()
+        for u, v in zip((sel, f, g), ref_out):
+            np.testing.assert_array_equal(u.cpu().numpy(), v)
+        # unrelated eager work between replays
+        ds.marginal_gains()
+        ds.sync()
+    # a different k records a new graph
+    s3, f3, _ = ds.greedy(3)
+    ds.sync()
+    np.testing.assert_array_equal(s3.cpu().numpy(), ref_out[0][:3])
+    np.testing.assert_array_equal(f3.cpu().numpy(), ref_out[1][:3])
