@@ -43,6 +43,7 @@ extern "C" {
 #endif
 
 typedef struct ebc_dataset ebc_dataset; /* opaque; host struct owned by the library */
+typedef struct ebc_batch ebc_batch;     /* opaque; many datasets advanced together */
 
 typedef enum {
     EBC_OK = 0,
@@ -151,6 +152,40 @@ EBC_API ebc_status ebc_greedy(ebc_dataset* ds, int32_t k, int32_t* sel_out, doub
  * One graph launch replaces 8k+1 kernel launches, which is what bounds small
  * problems. Results are identical to eager mode. Ignored while profiling. */
 EBC_API ebc_status ebc_set_greedy_graph(ebc_dataset* ds, int32_t on);
+
+/* Batched greedy over many independent datasets (different n, d, k and
+ * distance dtype). Per step tick the library issues one marginal-gains
+ * launch per kernel bucket (same dtype, row padding and tile variant) and
+ * seven step launches, each covering every instance; instances whose k is
+ * reached skip the remaining ticks. Every instance computes exactly what its
+ * solo ebc_greedy computes (bitwise-identical selections, f and gains),
+ * independent of the batch composition.
+ *
+ * ebc_batch_bytes(count): device workspace of the batch tables (descriptor
+ * table and block maps), 256-byte aligned, caller-owned.
+ * ebc_batch_create: `ds` [host] array of `count` datasets (each keeps its
+ * own workspace and state; all on the same device); copies the block maps to
+ * the device and waits for `stream`. The datasets must outlive the batch and
+ * not be used concurrently with it.
+ * ebc_greedy_batched: k [host] int32 [count] (0 <= k[i] <= n_i); sel_out,
+ * f_out [host] arrays of `count` device pointers as in ebc_greedy (entries
+ * may be NULL where k[i] = 0); gain_out [host] array or NULL (entries may be
+ * NULL). Resets every instance to S = {} first. Errors per instance are
+ * reported by ebc_sync_status on that dataset.
+ * ebc_batch_set_graph: record the reset and all ticks into one HIP graph
+ * and replay it while the number of ticks (max k) is unchanged; the
+ * per-instance k and output pointers live in the device table, so they may
+ * change between replays. */
+EBC_API size_t ebc_batch_bytes(int32_t count);
+EBC_API ebc_status ebc_batch_create(ebc_dataset* const* ds, int32_t count, void* workspace,
+                                    size_t workspace_bytes, void* stream, ebc_batch** out);
+EBC_API ebc_status ebc_batch_destroy(ebc_batch* batch);
+EBC_API ebc_status ebc_batch_set_graph(ebc_batch* batch, int32_t on);
+EBC_API ebc_status ebc_greedy_batched(ebc_batch* batch, const int32_t* k, int32_t* const* sel_out,
+                                      double* const* f_out, double* const* gain_out, void* stream);
+/* Launch geometry of one tick: gains buckets, gains workgroups, row blocks. */
+EBC_API ebc_status ebc_batch_info(ebc_batch* batch, int32_t* buckets, int64_t* gains_workgroups_per_tick,
+                                  int64_t* row_blocks_per_tick);
 
 /* Host-side counters of the last ebc_greedy on this dataset, valid after
  * ebc_sync_status: window_max = largest number of candidates re-scored in

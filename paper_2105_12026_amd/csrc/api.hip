@@ -110,8 +110,6 @@ ebc_status ebc_dataset_create(const float* x, int64_t n, int32_t d, ebc_dtype dt
     char* w = static_cast<char*>(workspace);
     Buffers& b = ds->b;
     b.xq = reinterpret_cast<float*>(w + L.off_xq);
-    b.aug_c = dt == EBC_DT_F32 ? nullptr : reinterpret_cast<uint16_t*>(w + L.off_aug_c);
-    b.aug_v = dt == EBC_DT_F32 ? nullptr : reinterpret_cast<uint16_t*>(w + L.off_aug_v);
     b.scale = dt == EBC_DT_FP8_E4M3 ? reinterpret_cast<int*>(w + L.off_scale) : nullptr;
     b.n64 = reinterpret_cast<double*>(w + L.off_n64);
     b.m64 = reinterpret_cast<double*>(w + L.off_m64);
@@ -154,7 +152,7 @@ ebc_status ebc_set_gains_variant(ebc_dataset* ds, int32_t variant) {
     return EBC_OK;
 }
 
-int32_t ebc_gains_variant_count(ebc_dtype dt) { return dt == EBC_DT_F32 ? 1 : 2; }
+int32_t ebc_gains_variant_count(ebc_dtype dt) { return dt == EBC_DT_F32 ? 1 : 3; }
 
 ebc_status ebc_profile_enable(ebc_dataset* ds, int32_t on) {
     if (!ds) return EBC_E_INVALID_ARG;

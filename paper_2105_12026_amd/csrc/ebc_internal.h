@@ -44,8 +44,6 @@ struct WindowEntry {
 struct Buffers {
     float* xq;          // distance-dtype copy of x, columns d.. are 0: float32 row-major [n_pad, k_pad];
                         // reduced precision: 64-row tiles, 16-byte units unit-major inside a tile
-    uint16_t* aug_c;    // [n_pad, 16] bf16 affine chunk, candidate role, row-major (reduced precision only)
-    uint16_t* aug_v;    // [n_pad, 16] bf16 affine chunk, ground-point role, tiled like xq (reduced precision only)
     int* scale;         // [n_pad] E8M0 row scales (FP8 only, else null)
     double* n64;        // [n_pad] ||v||^2 in float64 (0 for pad rows)
     double* m64;        // [n_pad] running minima m_v (float64 master copy)
@@ -65,8 +63,55 @@ struct Buffers {
     DevState* state;
 };
 
+// Everything a kernel of one greedy step needs about one dataset. Solo
+// launches pass it by value; batched launches read it from a device table
+// and map their blocks onto the instances, so both run the same code on the
+// same per-instance geometry (bitwise-identical results).
+struct InstDesc {
+    Buffers b;
+    const float* x;
+    int64_t n, n_pad;
+    int32_t d, k_pad, v_splits, nb;  // nb = n_pad / kBlock
+    int32_t k;                       // greedy steps of this instance
+    int32_t dt, variant, pad0;
+    int64_t chunk;                   // ground-set chunk of the gains kernel
+    int32_t* sel;
+    double* f;
+    double* gain;
+};
+
+// Arguments of one gains-kernel launch for one instance.
+struct GainsArgs {
+    const void* xq;
+    const float* hn;
+    const float* ha;
+    const float* hm;
+    const int* scale;
+    const int32_t* cand;
+    int64_t n_cand, n_pad;
+    int32_t v_splits, pad0;
+    int64_t chunk;
+    double* part;
+    int64_t part_stride;
+    int* err;
+};
+
+// Block -> instance map of a batched launch: instance i owns blocks
+// [pre[i], pre[i+1]) (pre[0] = 0); `inst` maps slot i to a descriptor.
+__device__ inline int find_slot(const int64_t* __restrict__ pre, int count, int64_t blk) {
+    int lo = 0, hi = count;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (pre[mid] <= blk)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
 struct Layout {
-    size_t off_xq, off_aug_c, off_aug_v, off_scale, off_n64, off_m64, off_hn, off_ha, off_hm, off_sel, off_part, off_gsum, off_bmax,
+    size_t off_xq, off_scale, off_n64, off_m64, off_hn, off_ha, off_hm, off_sel, off_part, off_gsum, off_bmax,
         off_barg, off_bcnt, off_wstage, off_wfinal, off_rpart, off_fpart, off_state, total;
 };
 
@@ -104,6 +149,46 @@ struct ebc_dataset {
 
 namespace ebc {
 
+// Host helpers shared by the solo and batched paths.
+int64_t gains_chunk(const ebc_dataset* ds);
+int64_t gains_cand_tile(const ebc_dataset* ds);
+int32_t gains_bucket(const ebc_dataset* ds);  // datasets with equal keys share a batched gains launch
+void fill_desc(const ebc_dataset* ds, int32_t k, int32_t* sel, double* f, double* gain, InstDesc* out);
+
+// Gains-kernel arguments of one instance (candidates: a list, or all rows).
+__host__ __device__ inline GainsArgs gains_args(const InstDesc& d, const int32_t* cand, int64_t n_cand) {
+    GainsArgs a;
+    a.xq = d.b.xq;
+    a.hn = d.b.hn;
+    a.ha = d.b.ha;
+    a.hm = d.b.hm;
+    a.scale = d.b.scale;
+    a.cand = cand;
+    a.n_cand = n_cand;
+    a.n_pad = d.n_pad;
+    a.v_splits = d.v_splits;
+    a.pad0 = 0;
+    a.chunk = d.chunk;
+    a.part = d.b.part;
+    a.part_stride = d.n_pad;
+    a.err = &d.b.state->error;
+    return a;
+}
+
+// Batched launches over a device table of descriptors (see ebc_batch).
+hipError_t launch_gains_f32_batched(int32_t k_pad, const InstDesc* descs, const int32_t* slot_inst,
+                                    const int64_t* wg_pre, int32_t slots, int64_t total_wgs, int32_t t,
+                                    hipStream_t s);
+hipError_t launch_gains_lp_batched(int32_t dt, int32_t kc, int32_t variant, const InstDesc* descs,
+                                   const int32_t* slot_inst, const int64_t* wg_pre, int32_t slots, int64_t total_wgs,
+                                   int32_t t, hipStream_t s);
+hipError_t launch_gains_batched(int32_t bucket, const InstDesc* descs, const int32_t* slot_inst,
+                                const int64_t* wg_pre, int32_t slots, int64_t total_wgs, int32_t t, hipStream_t s);
+hipError_t launch_step_batched(const InstDesc* descs, const int64_t* row_pre, int32_t count, int64_t total_rows,
+                               int32_t t, hipStream_t s);
+hipError_t launch_reset_batched(const InstDesc* descs, const int64_t* row_pre, int32_t count, int64_t total_rows,
+                                hipStream_t s);
+
 // Launchers (each defined next to its kernels). All return hipGetLastError().
 hipError_t launch_prep(const ebc_dataset* ds, hipStream_t s);
 hipError_t launch_reset_state(const ebc_dataset* ds, hipStream_t s);
@@ -118,8 +203,20 @@ int elem_bytes(ebc_dtype dt);
 __host__ __device__ inline int64_t tiled_offset(int64_t r, int byte, int row_units) {
     return ((r / 64 * row_units + byte / 16) * 64 + r % 64) * 16 + byte % 16;
 }
-double window_tau(ebc_dtype dt);
-double window_tau_abs(ebc_dtype dt);
+// Half-widths of the float64 re-score window per distance dtype: a candidate
+// whose gain sum is within tau * |best| + tau_abs * max_v ||v||^2 of the best
+// is re-scored in float64. The absolute part keeps every candidate of a
+// zero-gain step (all points already covered) inside the window.
+__host__ __device__ inline double window_tau(ebc_dtype dt) {
+    switch (dt) {
+        case EBC_DT_F32: return 1e-4;
+        case EBC_DT_F16: return 2e-3;
+        case EBC_DT_BF16: return 1e-2;
+        case EBC_DT_FP8_E4M3: return 4e-2;
+    }
+    return 1e-2;
+}
+__host__ __device__ inline double window_tau_abs(ebc_dtype dt) { return dt == EBC_DT_F32 ? 1e-4 : 1e-2; }
 hipError_t launch_gains_out(const ebc_dataset* ds, int64_t n_cand, double* out, hipStream_t s);
 hipError_t launch_greedy_step(const ebc_dataset* ds, int32_t t, int32_t* sel_out, double* f_out,
                               double* gain_out, hipStream_t s, hipEvent_t ev_gains_done);

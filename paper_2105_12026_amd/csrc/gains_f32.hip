@@ -47,11 +47,16 @@ __device__ __forceinline__ PreVec<PER> load_rows(const float4* __restrict__ src,
 }
 
 template <int KP>
-__global__ void __launch_bounds__(256)
-k_gains_f32(const float* __restrict__ xq, const float* __restrict__ hn, const float* __restrict__ ha,
-            const float* __restrict__ hm, const int32_t* __restrict__ cand, int64_t n_cand,
-            int64_t n_pad, int32_t v_splits, int64_t chunk, double* __restrict__ part,
-            int64_t part_stride, int* __restrict__ err) {
+__device__ __forceinline__ void gains_f32_body(const GainsArgs& ga, int64_t bid) {
+    const float* __restrict__ xq = static_cast<const float*>(ga.xq);
+    const float* __restrict__ hn = ga.hn;
+    const float* __restrict__ ha = ga.ha;
+    const float* __restrict__ hm = ga.hm;
+    const int32_t* __restrict__ cand = ga.cand;
+    const int64_t n_cand = ga.n_cand, n_pad = ga.n_pad, chunk = ga.chunk, part_stride = ga.part_stride;
+    const int32_t v_splits = ga.v_splits;
+    double* __restrict__ part = ga.part;
+    int* __restrict__ err = ga.err;
     constexpr int KH = KP / 2;        // K values per lane half
     constexpr int S = KP + 4;         // LDS row stride in floats (S/4 odd: conflict-free b128)
     constexpr int VT = kGainsVTile;   // ground points per LDS stage
@@ -70,7 +75,6 @@ k_gains_f32(const float* __restrict__ xq, const float* __restrict__ hn, const fl
     const int col = lane & 31;  // MFMA column within a 32-block
     const int half = lane >> 5;
 
-    const int64_t bid = blockIdx.x;
     const int split = int(bid % v_splits);
     const int64_t ctile = bid / v_splits;
 
@@ -196,22 +200,55 @@ k_gains_f32(const float* __restrict__ xq, const float* __restrict__ hn, const fl
 }
 
 template <int KP>
+__global__ void __launch_bounds__(256) k_gains_f32(GainsArgs ga) {
+    gains_f32_body<KP>(ga, blockIdx.x);
+}
+
+// Batched: workgroups wg_pre[j] .. wg_pre[j+1] serve descriptor slot_inst[j]
+// (all candidates, in the same geometry as a solo launch).
+template <int KP>
+__global__ void __launch_bounds__(256)
+kb_gains_f32(const InstDesc* __restrict__ descs, const int32_t* __restrict__ slot_inst,
+             const int64_t* __restrict__ wg_pre, int32_t slots, int32_t t) {
+    const int j = find_slot(wg_pre, slots, blockIdx.x);
+    const InstDesc c = descs[slot_inst[j]];
+    if (t >= c.k) return;
+    gains_f32_body<KP>(gains_args(c, nullptr, c.n_pad), int64_t(blockIdx.x) - wg_pre[j]);
+}
+
+template <int KP>
 static void launch_kp(const ebc_dataset* ds, const int32_t* cand, int64_t n_cand, hipStream_t s) {
     const int64_t tiles = (n_cand + kGainsCandTile - 1) / kGainsCandTile;
-    const int vs = ds->v_splits;
-    int64_t chunk = (ds->n_pad + vs - 1) / vs;
-    chunk = (chunk + kGainsVTile - 1) / kGainsVTile * kGainsVTile;
-    hipLaunchKernelGGL(k_gains_f32<KP>, dim3(unsigned(tiles * vs)), dim3(256), 0, s, ds->b.xq, ds->b.hn,
-                       ds->b.ha, ds->b.hm, cand, n_cand, ds->n_pad, vs, chunk, ds->b.part, ds->n_pad,
-                       &ds->b.state->error);
+    InstDesc c;
+    fill_desc(ds, 0, nullptr, nullptr, nullptr, &c);
+    hipLaunchKernelGGL(k_gains_f32<KP>, dim3(unsigned(tiles * ds->v_splits)), dim3(256), 0, s,
+                       gains_args(c, cand, n_cand));
 }
+
+#define EBC_F32_KPS(X) \
+    X(8) X(16) X(24) X(32) X(40) X(48) X(56) X(64) X(72) X(80) X(88) X(96) X(104) X(112) X(120) X(128)
 
 hipError_t launch_gains_f32(const ebc_dataset* ds, const int32_t* cand, int64_t n_cand, hipStream_t s) {
     switch (ds->k_pad) {
 #define EBC_KP(K) \
     case K: launch_kp<K>(ds, cand, n_cand, s); break;
-        EBC_KP(8) EBC_KP(16) EBC_KP(24) EBC_KP(32) EBC_KP(40) EBC_KP(48) EBC_KP(56) EBC_KP(64)
-        EBC_KP(72) EBC_KP(80) EBC_KP(88) EBC_KP(96) EBC_KP(104) EBC_KP(112) EBC_KP(120) EBC_KP(128)
+        EBC_F32_KPS(EBC_KP)
+#undef EBC_KP
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_gains_f32_batched(int32_t k_pad, const InstDesc* descs, const int32_t* slot_inst,
+                                    const int64_t* wg_pre, int32_t slots, int64_t total_wgs, int32_t t,
+                                    hipStream_t s) {
+    switch (k_pad) {
+#define EBC_KP(K)                                                                                          \
+    case K:                                                                                                \
+        hipLaunchKernelGGL(kb_gains_f32<K>, dim3(unsigned(total_wgs)), dim3(256), 0, s, descs, slot_inst, \
+                           wg_pre, slots, t);                                                              \
+        break;
+        EBC_F32_KPS(EBC_KP)
 #undef EBC_KP
         default: return hipErrorInvalidValue;
     }

@@ -6,26 +6,25 @@
 // Sec. 3 discrete derivative, Sec. 4.1 per-point decomposition), halved:
 //     G[c]/2 = sum_v med3( x^_v . x^_c + ha_v - hn_c, 0, hm_v )
 // where x^ are the quantised rows, hn = ||x^||^2/2 in float32, hm_v = m_v/2,
-// ha_v = hm_v - hn_v. The affine part ha_v - hn_c is folded into the matrix
-// product through one extra K chunk of 16 bf16 per row, each float32 term
-// split into three bf16 pieces (hi + mid + lo, ~24 significant bits):
-//     candidate row: [1, 1, 1, -hn_hi, -hn_mid, -hn_lo, 0 ...]
-//     ground point:  [ha_hi, ha_mid, ha_lo, 1, 1, 1, 0 ...]
-// so the accumulator leaves the MFMA as the full clamp argument and the
-// epilogue is one v_med3_f32 and one add per (candidate, point) pair.
+// ha_v = hm_v - hn_v. Moving ha_v out of the clamp,
+//     med3(t + ha_v, 0, hm_v) = ha_v + med3(t, -ha_v, hm_v - ha_v),
+// the accumulator starts from the constant tile -hn_c (the MFMA's C operand,
+// the same for every ground point), so the epilogue is one v_med3_f32 with
+// per-column bounds and one add per (candidate, point) pair, and the
+// chunk's sum of ha_v (the same for every candidate) is added once in
+// float64 at the end.
 //
 // Layout in HBM: the quantised rows are stored in tiles of 64 rows,
-// "unit-major" inside a tile (16-byte unit u of all 64 rows, then unit u+1),
-// and so is the ground-point affine chunk. One wave instruction
-// (global_load_lds_dwordx4) then copies a contiguous kilobyte of a tile
-// straight into LDS with no register staging, and the MFMA operand reads
-// from LDS are 32 consecutive 16-byte units per half-wave (no bank
-// conflicts). A workgroup (4 waves, 32*CB candidates per wave held in
-// registers) streams one chunk of the ground set through a 3-stage LDS ring:
-// the copy of tile t+2 is in flight while tile t is multiplied, with one
-// barrier per tile. MFMA tile: rows = candidates, columns = ground points;
-// each lane reads contiguous K from its half of a row (the order of K
-// inside a dot product is free as long as both operands use the same one).
+// "unit-major" inside a tile (16-byte unit u of all 64 rows, then unit u+1).
+// One wave instruction (global_load_lds_dwordx4) copies a contiguous
+// kilobyte of a tile straight into LDS with no register staging, and the
+// MFMA operand reads from LDS are 32 consecutive 16-byte units per half-wave
+// (no bank conflicts). A workgroup (4 waves, 32*CB candidates per wave held
+// in registers) streams one chunk of the ground set through a 3-stage LDS
+// ring: the copy of tile t+2 is in flight while tile t is multiplied, with
+// one barrier per tile. MFMA tile: rows = candidates, columns = ground
+// points; each lane reads contiguous K from its half of a row (the order of
+// K inside a dot product is free as long as both operands use the same one).
 #include "ebc_internal.h"
 
 namespace ebc {
@@ -50,11 +49,6 @@ template <>
 struct Lp<EBC_DT_FP8_E4M3> {
     static constexpr int kElem = 1, kChunkK = 64, kU4 = 2;
 };
-
-__device__ __forceinline__ floatx16 mfma_aug(uint4 a, uint4 b, floatx16 c) {
-    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c,
-                                                  0, 0, 0);
-}
 
 template <int DT>
 __device__ __forceinline__ floatx16 mfma_main(const uint4* a, const uint4* b, floatx16 c, int sa, int sb);
@@ -108,32 +102,30 @@ struct LpGeom {
     static constexpr int HU = RU / 2;                      // units per lane half-row
     static constexpr int VT = 64;                          // rows per tile
     static constexpr bool kFp8 = DT == EBC_DT_FP8_E4M3;
-    // LDS stage: [RU units x 64 rows][2 aug units x 64 rows][hm: 64 floats][scale: 64 ints]
-    static constexpr int OFF_AUG = RU * VT;
-    static constexpr int OFF_HM = OFF_AUG + 2 * VT;
+    // LDS stage: [RU units x 64 rows][ha: 64 floats][hm: 64 floats][scale: 64 ints]
+    static constexpr int OFF_HA = RU * VT;
+    static constexpr int OFF_HM = OFF_HA + VT / 4;
     static constexpr int OFF_SC = OFF_HM + VT / 4;
     static constexpr int STAGE = OFF_SC + (kFp8 ? VT / 4 : 0);  // uint4 per stage
-    static constexpr int NI = RU + 2 + 1 + (kFp8 ? 1 : 0);     // wave copy instructions per stage
+    static constexpr int NI = RU + 2 + (kFp8 ? 1 : 0);         // wave copy instructions per stage
     static constexpr int L = (NI + 3) / 4;                      // copy instructions per wave per stage
     static constexpr int NBUF = 3;
     static constexpr int CAND_TILE = 4 * 32 * CB;
 };
 
 // Wave-wide copy of one piece of ground-set tile `tile` into LDS stage `st`.
-// Piece j: j < RU main unit j; then the two affine units; then the 64 half
-// minima; then (FP8) the 64 row scales.
+// Piece j: j < RU main unit j; then the 64 ha; then the 64 hm; then (FP8)
+// the 64 row scales.
 template <class G>
 __device__ __forceinline__ void copy_piece(int j, int64_t tile, int lane, const uint4* __restrict__ xqt,
-                                           const uint4* __restrict__ augt, const float* __restrict__ hm,
+                                           const float* __restrict__ ha, const float* __restrict__ hm,
                                            const int* __restrict__ sc, uint4* st) {
     if (j < G::RU) {
         __builtin_amdgcn_global_load_lds(xqt + (tile * G::RU + j) * G::VT + lane, (lds_void*)(st + j * G::VT), 16,
                                          0, 0);
-    } else if (j < G::RU + 2) {
-        const int u = j - G::RU;
-        __builtin_amdgcn_global_load_lds(augt + (tile * 2 + u) * G::VT + lane,
-                                         (lds_void*)(st + G::OFF_AUG + u * G::VT), 16, 0, 0);
-    } else if (j == G::RU + 2) {
+    } else if (j == G::RU) {
+        __builtin_amdgcn_global_load_lds(ha + tile * G::VT + lane, (lds_void*)(st + G::OFF_HA), 4, 0, 0);
+    } else if (j == G::RU + 1) {
         __builtin_amdgcn_global_load_lds(hm + tile * G::VT + lane, (lds_void*)(st + G::OFF_HM), 4, 0, 0);
     } else {
         __builtin_amdgcn_global_load_lds(sc + tile * G::VT + lane, (lds_void*)(st + G::OFF_SC), 4, 0, 0);
@@ -145,10 +137,10 @@ __device__ __forceinline__ void copy_piece(int j, int64_t tile, int lane, const 
 // vector-memory counter is the same on every wave.
 template <class G>
 __device__ __forceinline__ void copy_stage(int wave, int lane, int64_t tile, const uint4* __restrict__ xqt,
-                                           const uint4* __restrict__ augt, const float* __restrict__ hm,
+                                           const float* __restrict__ ha, const float* __restrict__ hm,
                                            const int* __restrict__ sc, uint4* st) {
 #pragma unroll
-    for (int l = 0; l < G::L; ++l) copy_piece<G>((wave + 4 * l) % G::NI, tile, lane, xqt, augt, hm, sc, st);
+    for (int l = 0; l < G::L; ++l) copy_piece<G>((wave + 4 * l) % G::NI, tile, lane, xqt, ha, hm, sc, st);
 }
 
 // One ground-set tile: wait for its copy, start the copy of the tile two
@@ -156,10 +148,10 @@ __device__ __forceinline__ void copy_stage(int wave, int lane, int64_t tile, con
 // against the wave's candidate blocks.
 template <class G, int DT, int KC, int CB>
 __device__ __forceinline__ void lp_tile(int64_t t, int64_t nt, int64_t t_begin, int wave, int lane, int col, int half,
-                                        const uint4* __restrict__ xqt, const uint4* __restrict__ augt,
+                                        const uint4* __restrict__ xqt, const float* __restrict__ ha,
                                         const float* __restrict__ hm, const int* __restrict__ sc, const uint4* st,
-                                        uint4* next2, const uint4 (&a)[CB][G::HU], const uint4 (&aa)[CB],
-                                        const int (&sa)[CB], float (&acc_sum)[CB][16]) {
+                                        uint4* next2, const uint4 (&a)[CB][G::HU], const floatx16 (&cinit)[CB],
+                                        const int (&sa)[CB], float (&acc_sum)[CB][16], double& lo_sum) {
     using T = Lp<DT>;
     constexpr int HU = G::HU, VT = G::VT;
     // this wave's copies of tile t are done (those of t+1 may still fly) ...
@@ -170,7 +162,8 @@ __device__ __forceinline__ void lp_tile(int64_t t, int64_t nt, int64_t t_begin, 
     // ... and every wave's, and every wave finished reading tile t-1, whose
     // stage the next copy overwrites
     ring_barrier();
-    if (t + 2 < nt) copy_stage<G>(wave, lane, t_begin + t + 2, xqt, augt, hm, sc, next2);
+    if (t + 2 < nt) copy_stage<G>(wave, lane, t_begin + t + 2, xqt, ha, hm, sc, next2);
+    const float* st_ha = reinterpret_cast<const float*>(st + G::OFF_HA);
     const float* st_hm = reinterpret_cast<const float*>(st + G::OFF_HM);
     const int* st_sc = reinterpret_cast<const int*>(st + G::OFF_SC);
 #pragma unroll
@@ -179,13 +172,14 @@ __device__ __forceinline__ void lp_tile(int64_t t, int64_t nt, int64_t t_begin, 
         uint4 b[HU];
 #pragma unroll
         for (int u = 0; u < HU; ++u) b[u] = st[(half * HU + u) * VT + vrow];
-        const uint4 ba = st[G::OFF_AUG + half * VT + vrow];
-        const float hmv = st_hm[vrow];
+        const float hav = st_ha[vrow];
+        const float lo = -hav, hi = st_hm[vrow] - hav;
         const int sb = G::kFp8 ? st_sc[vrow] : 127;
-        // CB independent accumulator chains
+        lo_sum += double(lo);
+        // CB independent accumulator chains, each starting from -hn_c
         floatx16 acc[CB];
 #pragma unroll
-        for (int cb = 0; cb < CB; ++cb) acc[cb] = mfma_aug(aa[cb], ba, floatx16{});
+        for (int cb = 0; cb < CB; ++cb) acc[cb] = cinit[cb];
 #pragma unroll
         for (int q = 0; q < KC; ++q)
 #pragma unroll
@@ -194,16 +188,87 @@ __device__ __forceinline__ void lp_tile(int64_t t, int64_t nt, int64_t t_begin, 
 #pragma unroll
         for (int cb = 0; cb < CB; ++cb)
 #pragma unroll
-            for (int r = 0; r < 16; ++r) acc_sum[cb][r] += __builtin_amdgcn_fmed3f(acc[cb][r], 0.0f, hmv);
+            for (int r = 0; r < 16; ++r) acc_sum[cb][r] += __builtin_amdgcn_fmed3f(acc[cb][r], lo, hi);
     }
 }
 
-template <int DT, int KC, int CB>
-__global__ void __launch_bounds__(256)
-k_gains_lp(const uint4* __restrict__ xqt, const uint4* __restrict__ aug_c, const uint4* __restrict__ augt,
-           const int* __restrict__ sc, const float* __restrict__ hm, const int32_t* __restrict__ cand,
-           int64_t n_cand, int64_t n_pad, int32_t v_splits, int64_t chunk, double* __restrict__ part,
-           int64_t part_stride, int* __restrict__ err) {
+// Software-pipelined variant of lp_tile: the MFMAs of each column block are
+// issued before the epilogue of the previous block (kept in `prev`, also
+// across tiles), and sched_group_barrier asks the scheduler to interleave one
+// MFMA with a slice of that epilogue, so each wave keeps the matrix unit
+// busy while its VALU clamps and sums the previous block.
+template <class G, int DT, int KC, int CB>
+__device__ __forceinline__ void lp_tile_pipe(int64_t t, int64_t nt, int64_t t_begin, int wave, int lane, int col,
+                                             int half, const uint4* __restrict__ xqt, const float* __restrict__ ha,
+                                             const float* __restrict__ hm, const int* __restrict__ sc,
+                                             const uint4* st, uint4* next2, const uint4 (&a)[CB][G::HU],
+                                             const floatx16 (&cinit)[CB], const int (&sa)[CB],
+                                             float (&acc_sum)[CB][16], double& lo_sum, floatx16 (&prev)[CB],
+                                             float& prev_lo, float& prev_hi, bool& pending) {
+    using T = Lp<DT>;
+    constexpr int HU = G::HU, VT = G::VT;
+    constexpr int NMF = KC * CB;            // matrix instructions per column block
+    constexpr int NVA = 2 * 16 * CB;        // epilogue VALU instructions per column block
+    constexpr int PER = (NVA + NMF - 1) / NMF;
+    if (t + 1 < nt)
+        wait_vmcnt<G::L>();
+    else
+        wait_vmcnt<0>();
+    ring_barrier();
+    if (t + 2 < nt) copy_stage<G>(wave, lane, t_begin + t + 2, xqt, ha, hm, sc, next2);
+    const float* st_ha = reinterpret_cast<const float*>(st + G::OFF_HA);
+    const float* st_hm = reinterpret_cast<const float*>(st + G::OFF_HM);
+    const int* st_sc = reinterpret_cast<const int*>(st + G::OFF_SC);
+#pragma unroll
+    for (int colb = 0; colb < VT / 32; ++colb) {
+        const int vrow = colb * 32 + col;
+        uint4 b[HU];
+#pragma unroll
+        for (int u = 0; u < HU; ++u) b[u] = st[(half * HU + u) * VT + vrow];
+        const float hav = st_ha[vrow];
+        const float lo = -hav, hi = st_hm[vrow] - hav;
+        const int sb = G::kFp8 ? st_sc[vrow] : 127;
+        lo_sum += double(lo);
+        floatx16 acc[CB];
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) acc[cb] = cinit[cb];
+#pragma unroll
+        for (int q = 0; q < KC; ++q)
+#pragma unroll
+            for (int cb = 0; cb < CB; ++cb)
+                acc[cb] = mfma_main<DT>(&a[cb][q * T::kU4], &b[q * T::kU4], acc[cb], sa[cb], sb);
+        if (pending) {
+#pragma unroll
+            for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+                for (int r = 0; r < 16; ++r)
+                    acc_sum[cb][r] += __builtin_amdgcn_fmed3f(prev[cb][r], prev_lo, prev_hi);
+        }
+#pragma unroll
+        for (int i = 0; i < NMF; ++i) {
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);    // one MFMA
+            __builtin_amdgcn_sched_group_barrier(0x002, PER, 0);  // then a slice of VALU
+        }
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) prev[cb] = acc[cb];
+        prev_lo = lo;
+        prev_hi = hi;
+        pending = true;
+    }
+}
+
+template <int DT, int KC, int CB, bool PIPE>
+__device__ __forceinline__ void gains_lp_body(const GainsArgs& ga, int64_t bid) {
+    const uint4* __restrict__ xqt = static_cast<const uint4*>(ga.xq);
+    const float* __restrict__ hn = ga.hn;
+    const float* __restrict__ ha = ga.ha;
+    const float* __restrict__ hm = ga.hm;
+    const int* __restrict__ sc = ga.scale;
+    const int32_t* __restrict__ cand = ga.cand;
+    const int64_t n_cand = ga.n_cand, n_pad = ga.n_pad, chunk = ga.chunk, part_stride = ga.part_stride;
+    const int32_t v_splits = ga.v_splits;
+    double* __restrict__ part = ga.part;
+    int* __restrict__ err = ga.err;
     using G = LpGeom<DT, KC, CB>;
     using T = Lp<DT>;
     constexpr int RU = G::RU, HU = G::HU, VT = G::VT;
@@ -218,14 +283,13 @@ k_gains_lp(const uint4* __restrict__ xqt, const uint4* __restrict__ aug_c, const
     const int wave = tid >> 6;
     const int col = lane & 31;
     const int half = lane >> 5;
-    const int64_t bid = blockIdx.x;
     const int split = int(bid % v_splits);
     const int64_t ctile = bid / v_splits;
     const int64_t wbase = ctile * G::CAND_TILE + int64_t(wave) * (32 * CB);
 
-    // ---- candidate rows (A operand) in registers ----
+    // ---- candidate rows (A operand) and -hn of the result rows, in registers ----
     uint4 a[CB][HU];
-    uint4 aa[CB];
+    floatx16 cinit[CB];
     int sa[CB];
 #pragma unroll
     for (int cb = 0; cb < CB; ++cb) {
@@ -240,13 +304,22 @@ k_gains_lp(const uint4* __restrict__ xqt, const uint4* __restrict__ aug_c, const
             const uint4* src = xqt + (crow / VT) * (RU * VT) + (crow % VT);
 #pragma unroll
             for (int u = 0; u < HU; ++u) a[cb][u] = src[(half * HU + u) * VT];
-            aa[cb] = aug_c[crow * 2 + half];
             sa[cb] = G::kFp8 ? sc[crow] : 127;
         } else {
 #pragma unroll
             for (int u = 0; u < HU; ++u) a[cb][u] = make_uint4(0, 0, 0, 0);
-            aa[cb] = make_uint4(0, 0, 0, 0);
             sa[cb] = 127;
+        }
+        // the lane holds result rows 8*(r/4) + 4*half + r%4 of this block
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int64_t p = wbase + cb * 32 + 8 * (r / 4) + 4 * half + (r % 4);
+            float v = 0.0f;
+            if (p < n_cand) {
+                const int64_t row = cand ? int64_t(cand[p]) : p;
+                if (row >= 0 && row < n_pad) v = hn[row];
+            }
+            cinit[cb][r] = -v;
         }
     }
     float acc_sum[CB][16];
@@ -254,6 +327,7 @@ k_gains_lp(const uint4* __restrict__ xqt, const uint4* __restrict__ aug_c, const
     for (int cb = 0; cb < CB; ++cb)
 #pragma unroll
         for (int r = 0; r < 16; ++r) acc_sum[cb][r] = 0.0f;
+    double lo_sum = 0.0;  // this lane's sum of -ha_v over its columns
 
     // ---- stream the ground-set chunk through the LDS ring ----
     const int64_t v_begin = int64_t(split) * chunk;
@@ -262,28 +336,53 @@ k_gains_lp(const uint4* __restrict__ xqt, const uint4* __restrict__ aug_c, const
     const int64_t t_begin = v_begin / VT;
     const int64_t nt = v_end > v_begin ? (v_end - v_begin) / VT : 0;
 
-    if (nt > 0) copy_stage<G>(wave, lane, t_begin, xqt, augt, hm, sc, lds0);
-    if (nt > 1) copy_stage<G>(wave, lane, t_begin + 1, xqt, augt, hm, sc, lds1);
+    if (nt > 0) copy_stage<G>(wave, lane, t_begin, xqt, ha, hm, sc, lds0);
+    if (nt > 1) copy_stage<G>(wave, lane, t_begin + 1, xqt, ha, hm, sc, lds1);
     // three stages are three distinct LDS objects and the loop is unrolled
     // by three, so the compiler can see that the copy in flight never
     // targets the stage being read and does not wait for it
-    for (int64_t t = 0; t < nt; t += 3) {
-        lp_tile<G, DT, KC, CB>(t, nt, t_begin, wave, lane, col, half, xqt, augt, hm, sc, lds0, lds2, a, aa, sa, acc_sum);
-        if (t + 1 < nt)
-            lp_tile<G, DT, KC, CB>(t + 1, nt, t_begin, wave, lane, col, half, xqt, augt, hm, sc, lds1, lds0, a, aa, sa,
-                                   acc_sum);
-        if (t + 2 < nt)
-            lp_tile<G, DT, KC, CB>(t + 2, nt, t_begin, wave, lane, col, half, xqt, augt, hm, sc, lds2, lds1, a, aa, sa,
-                                   acc_sum);
+    if (PIPE) {
+        floatx16 prev[CB];
+        float prev_lo = 0.0f, prev_hi = 0.0f;
+        bool pending = false;
+        for (int64_t t = 0; t < nt; t += 3) {
+            lp_tile_pipe<G, DT, KC, CB>(t, nt, t_begin, wave, lane, col, half, xqt, ha, hm, sc, lds0, lds2, a,
+                                        cinit, sa, acc_sum, lo_sum, prev, prev_lo, prev_hi, pending);
+            if (t + 1 < nt)
+                lp_tile_pipe<G, DT, KC, CB>(t + 1, nt, t_begin, wave, lane, col, half, xqt, ha, hm, sc, lds1, lds0,
+                                            a, cinit, sa, acc_sum, lo_sum, prev, prev_lo, prev_hi, pending);
+            if (t + 2 < nt)
+                lp_tile_pipe<G, DT, KC, CB>(t + 2, nt, t_begin, wave, lane, col, half, xqt, ha, hm, sc, lds2, lds1,
+                                            a, cinit, sa, acc_sum, lo_sum, prev, prev_lo, prev_hi, pending);
+        }
+        if (pending) {
+#pragma unroll
+            for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) acc_sum[cb][r] += __builtin_amdgcn_fmed3f(prev[cb][r], prev_lo, prev_hi);
+        }
+    } else {
+        for (int64_t t = 0; t < nt; t += 3) {
+            lp_tile<G, DT, KC, CB>(t, nt, t_begin, wave, lane, col, half, xqt, ha, hm, sc, lds0, lds2, a, cinit, sa,
+                                   acc_sum, lo_sum);
+            if (t + 1 < nt)
+                lp_tile<G, DT, KC, CB>(t + 1, nt, t_begin, wave, lane, col, half, xqt, ha, hm, sc, lds1, lds0, a,
+                                       cinit, sa, acc_sum, lo_sum);
+            if (t + 2 < nt)
+                lp_tile<G, DT, KC, CB>(t + 2, nt, t_begin, wave, lane, col, half, xqt, ha, hm, sc, lds2, lds1, a,
+                                       cinit, sa, acc_sum, lo_sum);
+        }
     }
 
-    // ---- float64 sum over the 32 columns of each half; one lane per row writes ----
+    // ---- float64 sums over the 32 columns of each half; one lane per row writes ----
+    // each lane removes the lower bounds of its own columns (sum of -ha_v)
+    // before the sum over the columns
 #pragma unroll
     for (int cb = 0; cb < CB; ++cb) {
         double mine = 0.0;
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
-            double v = double(acc_sum[cb][r]);
+            double v = double(acc_sum[cb][r]) - lo_sum;
 #pragma unroll
             for (int off = 16; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
             if (col == r) mine = v;
@@ -296,28 +395,42 @@ k_gains_lp(const uint4* __restrict__ xqt, const uint4* __restrict__ aug_c, const
     }
 }
 
-template <int DT, int KC, int CB>
+template <int DT, int KC, int CB, bool PIPE>
+__global__ void __launch_bounds__(256) k_gains_lp(GainsArgs ga) {
+    gains_lp_body<DT, KC, CB, PIPE>(ga, blockIdx.x);
+}
+
+// Batched: workgroups wg_pre[j] .. wg_pre[j+1] serve descriptor slot_inst[j]
+// (all candidates, in the same geometry as a solo launch).
+template <int DT, int KC, int CB, bool PIPE>
+__global__ void __launch_bounds__(256)
+kb_gains_lp(const InstDesc* __restrict__ descs, const int32_t* __restrict__ slot_inst,
+            const int64_t* __restrict__ wg_pre, int32_t slots, int32_t t) {
+    const int j = find_slot(wg_pre, slots, blockIdx.x);
+    const InstDesc c = descs[slot_inst[j]];
+    if (t >= c.k) return;
+    gains_lp_body<DT, KC, CB, PIPE>(gains_args(c, nullptr, c.n_pad), int64_t(blockIdx.x) - wg_pre[j]);
+}
+
+template <int DT, int KC, int CB, bool PIPE>
 static void launch_lp_v(const ebc_dataset* ds, const int32_t* cand, int64_t n_cand, hipStream_t s) {
     using G = LpGeom<DT, KC, CB>;
     const int64_t tiles = (n_cand + G::CAND_TILE - 1) / G::CAND_TILE;
-    const int vs = ds->v_splits;
-    // chunk boundaries do not depend on the variant (multiples of 256), so
-    // every variant sums the same terms in the same order
-    int64_t chunk = (ds->n_pad + vs - 1) / vs;
-    chunk = (chunk + 255) / 256 * 256;
-    hipLaunchKernelGGL((k_gains_lp<DT, KC, CB>), dim3(unsigned(tiles * vs)), dim3(256), 0, s,
-                       reinterpret_cast<const uint4*>(ds->b.xq), reinterpret_cast<const uint4*>(ds->b.aug_c),
-                       reinterpret_cast<const uint4*>(ds->b.aug_v), ds->b.scale, ds->b.hm, cand, n_cand, ds->n_pad,
-                       vs, chunk, ds->b.part, ds->n_pad, &ds->b.state->error);
+    InstDesc c;
+    fill_desc(ds, 0, nullptr, nullptr, nullptr, &c);
+    hipLaunchKernelGGL((k_gains_lp<DT, KC, CB, PIPE>), dim3(unsigned(tiles * ds->v_splits)), dim3(256), 0, s,
+                       gains_args(c, cand, n_cand));
 }
 
-// Variants: 32-row candidate blocks per wave (2 or 4).
+// Variants: (32-row candidate blocks per wave, software-pipelined epilogue):
+// 0 = (2, no), 1 = (4, no), 2 = (2, yes).
 template <int DT, int KC>
 static void launch_lp(const ebc_dataset* ds, const int32_t* cand, int64_t n_cand, hipStream_t s) {
-    if (ds->variant == 1)
-        launch_lp_v<DT, KC, 4>(ds, cand, n_cand, s);
-    else
-        launch_lp_v<DT, KC, 2>(ds, cand, n_cand, s);
+    switch (ds->variant) {
+        case 1: launch_lp_v<DT, KC, 4, false>(ds, cand, n_cand, s); break;
+        case 2: launch_lp_v<DT, KC, 2, true>(ds, cand, n_cand, s); break;
+        default: launch_lp_v<DT, KC, 2, false>(ds, cand, n_cand, s); break;
+    }
 }
 
 hipError_t launch_gains_lp(const ebc_dataset* ds, const int32_t* cand, int64_t n_cand, hipStream_t s) {
@@ -358,6 +471,49 @@ hipError_t launch_gains_lp(const ebc_dataset* ds, const int32_t* cand, int64_t n
             break;
         default: return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+template <int DT, int KC>
+static void launch_lp_b(int32_t variant, const InstDesc* descs, const int32_t* slot_inst, const int64_t* wg_pre,
+                        int32_t slots, int64_t total_wgs, int32_t t, hipStream_t s) {
+    const dim3 g = dim3(unsigned(total_wgs)), b = dim3(256);
+    switch (variant) {
+        case 1: hipLaunchKernelGGL((kb_gains_lp<DT, KC, 4, false>), g, b, 0, s, descs, slot_inst, wg_pre, slots, t); break;
+        case 2: hipLaunchKernelGGL((kb_gains_lp<DT, KC, 2, true>), g, b, 0, s, descs, slot_inst, wg_pre, slots, t); break;
+        default: hipLaunchKernelGGL((kb_gains_lp<DT, KC, 2, false>), g, b, 0, s, descs, slot_inst, wg_pre, slots, t); break;
+    }
+}
+
+hipError_t launch_gains_lp_batched(int32_t dt, int32_t kc, int32_t variant, const InstDesc* descs,
+                                   const int32_t* slot_inst, const int64_t* wg_pre, int32_t slots, int64_t total_wgs,
+                                   int32_t t, hipStream_t s) {
+#define EBC_LPB(DTV, K) \
+    case K: launch_lp_b<DTV, K>(variant, descs, slot_inst, wg_pre, slots, total_wgs, t, s); break;
+    switch (dt) {
+        case EBC_DT_BF16:
+            switch (kc) {
+                EBC_LPB(EBC_DT_BF16, 1) EBC_LPB(EBC_DT_BF16, 2) EBC_LPB(EBC_DT_BF16, 3) EBC_LPB(EBC_DT_BF16, 4)
+                EBC_LPB(EBC_DT_BF16, 5) EBC_LPB(EBC_DT_BF16, 6) EBC_LPB(EBC_DT_BF16, 7) EBC_LPB(EBC_DT_BF16, 8)
+                default: return hipErrorInvalidValue;
+            }
+            break;
+        case EBC_DT_F16:
+            switch (kc) {
+                EBC_LPB(EBC_DT_F16, 1) EBC_LPB(EBC_DT_F16, 2) EBC_LPB(EBC_DT_F16, 3) EBC_LPB(EBC_DT_F16, 4)
+                EBC_LPB(EBC_DT_F16, 5) EBC_LPB(EBC_DT_F16, 6) EBC_LPB(EBC_DT_F16, 7) EBC_LPB(EBC_DT_F16, 8)
+                default: return hipErrorInvalidValue;
+            }
+            break;
+        case EBC_DT_FP8_E4M3:
+            switch (kc) {
+                EBC_LPB(EBC_DT_FP8_E4M3, 1) EBC_LPB(EBC_DT_FP8_E4M3, 2)
+                default: return hipErrorInvalidValue;
+            }
+            break;
+        default: return hipErrorInvalidValue;
+    }
+#undef EBC_LPB
     return hipGetLastError();
 }
 

@@ -22,18 +22,51 @@ int32_t k_pad_for(int32_t d, ebc_dtype dt) {
 
 int elem_bytes(ebc_dtype dt) { return dt == EBC_DT_F32 ? 4 : (dt == EBC_DT_FP8_E4M3 ? 1 : 2); }
 
-// Relative and absolute half-widths of the float64 re-score window per
-// distance dtype (see launch_reset_state).
-double window_tau(ebc_dtype dt) {
-    switch (dt) {
-        case EBC_DT_F32: return 1e-4;
-        case EBC_DT_F16: return 2e-3;
-        case EBC_DT_BF16: return 1e-2;
-        case EBC_DT_FP8_E4M3: return 4e-2;
-    }
-    return 1e-2;
+int64_t gains_chunk(const ebc_dataset* ds) {
+    // ground-set chunk per workgroup: a multiple of the kernel's LDS tile
+    // (float32: 64 rows; reduced precision: 256, the same for every variant)
+    const int64_t g = ds->dt == EBC_DT_F32 ? kGainsVTile : 256;
+    const int64_t c = (ds->n_pad + ds->v_splits - 1) / ds->v_splits;
+    return (c + g - 1) / g * g;
 }
-double window_tau_abs(ebc_dtype dt) { return dt == EBC_DT_F32 ? 1e-4 : 1e-2; }
+
+int64_t gains_cand_tile(const ebc_dataset* ds) {
+    if (ds->dt == EBC_DT_F32) return kGainsCandTile;
+    return ds->variant == 1 ? 512 : 256;  // 4 waves x 32 rows x (4 or 2) blocks
+}
+
+int32_t gains_bucket(const ebc_dataset* ds) {
+    return int32_t(ds->dt) * 100000 + ds->k_pad * 10 + (ds->dt == EBC_DT_F32 ? 0 : ds->variant);
+}
+
+void fill_desc(const ebc_dataset* ds, int32_t k, int32_t* sel, double* f, double* gain, InstDesc* out) {
+    InstDesc& c = *out;
+    c.b = ds->b;
+    c.x = ds->x;
+    c.n = ds->n;
+    c.n_pad = ds->n_pad;
+    c.d = ds->d;
+    c.k_pad = ds->k_pad;
+    c.v_splits = ds->v_splits;
+    c.nb = int32_t(ds->n_pad / kBlock);
+    c.k = k;
+    c.dt = int32_t(ds->dt);
+    c.variant = ds->variant;
+    c.pad0 = 0;
+    c.chunk = gains_chunk(ds);
+    c.sel = sel;
+    c.f = f;
+    c.gain = gain;
+}
+
+hipError_t launch_gains_batched(int32_t bucket, const InstDesc* descs, const int32_t* slot_inst,
+                                const int64_t* wg_pre, int32_t slots, int64_t total_wgs, int32_t t, hipStream_t s) {
+    const int32_t dt = bucket / 100000, k_pad = (bucket % 100000) / 10, variant = bucket % 10;
+    if (dt == EBC_DT_F32)
+        return launch_gains_f32_batched(k_pad, descs, slot_inst, wg_pre, slots, total_wgs, t, s);
+    const int32_t kc = k_pad / (dt == EBC_DT_FP8_E4M3 ? 64 : 16);
+    return launch_gains_lp_batched(dt, kc, variant, descs, slot_inst, wg_pre, slots, total_wgs, t, s);
+}
 
 int32_t v_splits_for(int64_t n_pad) {
     // The ground set is cut into one chunk per XCD (8 on MI355X) once there
@@ -51,12 +84,9 @@ Layout layout(int64_t n, int32_t d, ebc_dtype dt) {
     const int64_t np = pad_rows(n);
     const int32_t kp = k_pad_for(d, dt);
     const int64_t nb = np / kBlock + 1;
-    const bool lp = dt != EBC_DT_F32;
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t at = o; o = align256(o + bytes); return at; };
     L.off_xq = take(size_t(np) * kp * elem_bytes(dt));
-    L.off_aug_c = lp ? take(size_t(np) * 16 * sizeof(uint16_t)) : 0;
-    L.off_aug_v = lp ? take(size_t(np) * 16 * sizeof(uint16_t)) : 0;
     L.off_scale = dt == EBC_DT_FP8_E4M3 ? take(size_t(np) * sizeof(int)) : 0;
     L.off_n64 = take(size_t(np) * sizeof(double));
     L.off_m64 = take(size_t(np) * sizeof(double));
@@ -134,8 +164,8 @@ __global__ void __launch_bounds__(kBlock) k_prep(const float* __restrict__ x, in
 
 // Reduced-precision copy: one thread per padded row. Exact float64 norm and
 // initial state as in k_prep, then the row cast with round-to-nearest-even
-// (FP8: after a power-of-two row scale), the float32 norm of the cast row,
-// and the two affine-chunk rows. FP16 values beyond its range raise
+// (FP8: after a power-of-two row scale) into the tiled layout, and the
+// float32 norm of the cast row. FP16 values beyond its range raise
 // EBC_E_RANGE.
 __global__ void __launch_bounds__(kBlock) k_prep_lp(const float* __restrict__ x, int64_t n, int32_t d,
                                                     int32_t kp, int dt, Buffers b) {
@@ -196,32 +226,16 @@ __global__ void __launch_bounds__(kBlock) k_prep_lp(const float* __restrict__ x,
         }
         if (bad) atomicCAS(&b.state->error, 0, kDevErrNonFinite);
         if (range) atomicCAS(&b.state->error, 0, int(EBC_E_RANGE));
-        const float hn = float(0.5 * nq);
-        b.hn[r] = hn;
+        b.hn[r] = float(0.5 * nq);
         b.n64[r] = nv;
         b.m64[r] = nv;
         b.selected[r] = 0;
-        uint16_t p[3];
-        split3_bf16(-hn, p);
-        uint16_t* ac = b.aug_c + r * 16;
-        uint8_t* avb = reinterpret_cast<uint8_t*>(b.aug_v);
-        for (int k = 0; k < 16; ++k) {
-            ac[k] = 0;
-            *reinterpret_cast<uint16_t*>(avb + tiled_offset(r, 2 * k, 2)) = (k >= 3 && k < 6) ? kBf16One : 0;
-        }
-        ac[0] = ac[1] = ac[2] = kBf16One;
-        ac[3] = p[0];
-        ac[4] = p[1];
-        ac[5] = p[2];
         set_point_terms(b, r, nv);
     } else {
         const int eb = dt == EBC_DT_FP8_E4M3 ? 1 : 2;
         const int ru = kp * eb / 16;
         uint8_t* base = reinterpret_cast<uint8_t*>(b.xq);
         for (int k = 0; k < kp * eb; ++k) base[tiled_offset(r, k, ru)] = 0;
-        uint8_t* avb = reinterpret_cast<uint8_t*>(b.aug_v);
-        for (int k = 0; k < 32; ++k) avb[tiled_offset(r, k, 2)] = 0;
-        for (int k = 0; k < 16; ++k) b.aug_c[r * 16 + k] = 0;
         if (b.scale) b.scale[r] = 127;
         b.n64[r] = 0.0;
         b.m64[r] = 0.0;
@@ -301,9 +315,10 @@ hipError_t launch_prep(const ebc_dataset* ds, hipStream_t s) {
 }
 
 // Greedy restart: m_v = ||v||^2, nothing selected, window counters cleared.
-__global__ void __launch_bounds__(kBlock) k_reset(int64_t n, Buffers b, double tau, double tau_abs) {
-    const int64_t r = int64_t(blockIdx.x) * kBlock + threadIdx.x;
-    if (r < n) {
+__device__ void reset_body(const InstDesc& c, int64_t blk) {
+    const Buffers& b = c.b;
+    const int64_t r = blk * kBlock + threadIdx.x;
+    if (r < c.n) {
         const double nv = b.n64[r];
         b.m64[r] = nv;
         set_point_terms(b, r, nv);
@@ -315,18 +330,29 @@ __global__ void __launch_bounds__(kBlock) k_reset(int64_t n, Buffers b, double t
         b.state->window_overflow = 0;
         b.state->cstar = -1;
         b.state->gstar = 0.0;
-        b.state->tau = tau;
-        b.state->tau_abs = tau_abs;
+        b.state->tau = window_tau(ebc_dtype(c.dt));
+        b.state->tau_abs = window_tau_abs(ebc_dtype(c.dt));
     }
 }
 
+__global__ void __launch_bounds__(kBlock) k_reset(InstDesc c) { reset_body(c, blockIdx.x); }
+
+__global__ void __launch_bounds__(kBlock)
+kb_reset(const InstDesc* __restrict__ descs, const int64_t* __restrict__ row_pre, int32_t count) {
+    const int i = find_slot(row_pre, count, blockIdx.x);
+    reset_body(descs[i], int64_t(blockIdx.x) - row_pre[i]);
+}
+
 hipError_t launch_reset_state(const ebc_dataset* ds, hipStream_t s) {
-    // Half-width of the re-score window: a candidate whose float32 gain sum
-    // is within tau * |best| + tau_abs * max_v ||v||^2 of the best is
-    // re-scored in float64. The absolute part keeps every candidate of a
-    // zero-gain step (all points already covered) inside the window.
-    const double tau = window_tau(ds->dt), tau_abs = window_tau_abs(ds->dt);
-    hipLaunchKernelGGL(k_reset, dim3(ds->n_pad / kBlock), dim3(kBlock), 0, s, ds->n, ds->b, tau, tau_abs);
+    InstDesc c;
+    fill_desc(ds, 0, nullptr, nullptr, nullptr, &c);
+    hipLaunchKernelGGL(k_reset, dim3(c.nb), dim3(kBlock), 0, s, c);
+    return hipGetLastError();
+}
+
+hipError_t launch_reset_batched(const InstDesc* descs, const int64_t* row_pre, int32_t count, int64_t total_rows,
+                                hipStream_t s) {
+    hipLaunchKernelGGL(kb_reset, dim3(unsigned(total_rows)), dim3(kBlock), 0, s, descs, row_pre, count);
     return hipGetLastError();
 }
 

@@ -1,7 +1,7 @@
-// Device helpers for the reduced-precision copies of V: round-to-nearest-even
-// conversions, the 3-piece bf16 split of a float32, and the float32 terms the
-// gains kernels read for a ground point (its half running minimum and the
-// affine term of the distance expansion).
+// Device helpers for the reduced-precision copies of V (round-to-nearest-even
+// conversions) and the float32 terms the gains kernels read for a ground
+// point (its half running minimum and the affine term of the distance
+// expansion).
 #pragma once
 
 #include <math.h>
@@ -48,35 +48,11 @@ __device__ inline float e4m3_to_f32(uint8_t b) {
     return (b & 0x80) ? -v : v;
 }
 
-// v ~= hi + mid + lo with each piece a bf16 (about 24 significant bits).
-__device__ inline void split3_bf16(float v, uint16_t* out) {
-    const uint16_t hi = f32_to_bf16_rne(v);
-    const float r1 = v - bf16_to_f32(hi);
-    const uint16_t mid = f32_to_bf16_rne(r1);
-    const float r2 = r1 - bf16_to_f32(mid);
-    out[0] = hi;
-    out[1] = mid;
-    out[2] = f32_to_bf16_rne(r2);
-}
-
-constexpr uint16_t kBf16One = 0x3f80;
-
 // Refresh the float32 terms of ground point v after its running minimum
-// changed to mv: hm = mv/2, ha = mv/2 - hn, and for the reduced-precision
-// copies the ground-point row of the affine chunk [ha_hi, ha_mid, ha_lo, 1, 1, 1, 0..].
+// changed to mv: hm = mv/2 and ha = mv/2 - hn.
 __device__ inline void set_point_terms(const Buffers& b, int64_t v, double mv) {
-    const float ha = float(0.5 * mv - double(b.hn[v]));
-    b.ha[v] = ha;
+    b.ha[v] = float(0.5 * mv - double(b.hn[v]));
     b.hm[v] = float(0.5 * mv);
-    if (b.aug_v) {
-        uint16_t p[3];
-        split3_bf16(ha, p);
-        // elements 0..2 of the tiled ground-point row (unit 0, two rows of units per tile)
-        uint16_t* row = reinterpret_cast<uint16_t*>(reinterpret_cast<uint8_t*>(b.aug_v) + tiled_offset(v, 0, 2));
-        row[0] = p[0];
-        row[1] = p[1];
-        row[2] = p[2];
-    }
 }
 
 }  // namespace ebc

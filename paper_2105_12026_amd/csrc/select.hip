@@ -1,5 +1,7 @@
 // One greedy step after the gains kernel (Sec. 3 and Sec. 4.1: greedy picks
-// the not-yet-selected point of largest marginal gain):
+// the not-yet-selected point of largest marginal gain). Each stage is a
+// device function of (instance descriptor, step, block); the solo kernels
+// run it on one instance, the batched kernels map their blocks onto many.
 //   k_gsum     sum the per-chunk gain sums, mask selected points, block maxima
 //   k_wcount   every candidate within tau*|best| of the best enters the window
 //   k_wselect  choose at most kWindowMax window candidates, deterministically
@@ -17,31 +19,6 @@ namespace ebc {
 
 __device__ inline bool better(double ga, int ia, double gb, int ib) {
     return ga > gb || (ga == gb && ia < ib);
-}
-
-__global__ void __launch_bounds__(kBlock)
-k_gsum(int64_t n_pad, int32_t v_splits, Buffers b) {
-    __shared__ double sg[kBlock];
-    __shared__ int si[kBlock];
-    const int64_t c = int64_t(blockIdx.x) * kBlock + threadIdx.x;
-    double g = 0.0;
-    for (int s = 0; s < v_splits; ++s) g += b.part[int64_t(s) * n_pad + c];
-    if (b.selected[c]) g = -INFINITY;
-    b.gsum[c] = g;
-    sg[threadIdx.x] = g;
-    si[threadIdx.x] = int(c);
-    __syncthreads();
-    for (int w = kBlock / 2; w > 0; w >>= 1) {
-        if (threadIdx.x < w && better(sg[threadIdx.x + w], si[threadIdx.x + w], sg[threadIdx.x], si[threadIdx.x])) {
-            sg[threadIdx.x] = sg[threadIdx.x + w];
-            si[threadIdx.x] = si[threadIdx.x + w];
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-        b.bmax[blockIdx.x] = sg[0];
-        b.barg[blockIdx.x] = si[0];
-    }
 }
 
 // Threshold of the re-score window from the global best float32 gain.
@@ -64,13 +41,41 @@ __device__ double block_gmax(const double* bmax, int nb, double* red) {
     return r;
 }
 
-__global__ void __launch_bounds__(kBlock) k_wcount(int32_t nb, Buffers b) {
+// ---- gsum: per-chunk sums -> gsum, selected masked, block maxima ----
+__device__ void gsum_body(const InstDesc& c, int64_t blk) {
+    __shared__ double sg[kBlock];
+    __shared__ int si[kBlock];
+    const Buffers& b = c.b;
+    const int64_t i = blk * kBlock + threadIdx.x;
+    double g = 0.0;
+    for (int s = 0; s < c.v_splits; ++s) g += b.part[int64_t(s) * c.n_pad + i];
+    if (b.selected[i]) g = -INFINITY;
+    b.gsum[i] = g;
+    sg[threadIdx.x] = g;
+    si[threadIdx.x] = int(i);
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w && better(sg[threadIdx.x + w], si[threadIdx.x + w], sg[threadIdx.x], si[threadIdx.x])) {
+            sg[threadIdx.x] = sg[threadIdx.x + w];
+            si[threadIdx.x] = si[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        b.bmax[blk] = sg[0];
+        b.barg[blk] = si[0];
+    }
+}
+
+// ---- wcount: candidates within the window, compacted per block in index order ----
+__device__ void wcount_body(const InstDesc& c, int64_t blk) {
     __shared__ double red[kBlock];
     __shared__ int scan[kBlock];
-    const double gmax = block_gmax(b.bmax, nb, red);
+    const Buffers& b = c.b;
+    const double gmax = block_gmax(b.bmax, c.nb, red);
     const double thr = window_threshold(gmax, b.state);
-    const int64_t c = int64_t(blockIdx.x) * kBlock + threadIdx.x;
-    const double g = b.gsum[c];
+    const int64_t i = blk * kBlock + threadIdx.x;
+    const double g = b.gsum[i];
     const int q = (g >= thr && g > -INFINITY) ? 1 : 0;
     // inclusive scan of q across the block (Hillis-Steele), index order kept
     scan[threadIdx.x] = q;
@@ -84,23 +89,25 @@ __global__ void __launch_bounds__(kBlock) k_wcount(int32_t nb, Buffers b) {
     if (q) {
         WindowEntry e;
         e.g = g;
-        e.idx = int(c);
+        e.idx = int(i);
         e.pad = 0;
-        b.wstage[int64_t(blockIdx.x) * kBlock + scan[threadIdx.x] - 1] = e;
+        b.wstage[blk * kBlock + scan[threadIdx.x] - 1] = e;
     }
-    if (threadIdx.x == kBlock - 1) b.bcnt[blockIdx.x] = scan[kBlock - 1];
+    if (threadIdx.x == kBlock - 1) b.bcnt[blk] = scan[kBlock - 1];
 }
 
-// One block of 1024 threads: gather the window entries in index order, then
-// keep at most kWindowMax of them:
+// ---- wselect (one block of 1024 threads per instance) ----
+// Gather the window entries in index order, then keep at most kWindowMax:
 //   total <= kWindowMax          all of them;
 //   total <= kWindowCap          the kWindowMax best by (gain desc, index asc);
 //   otherwise (counted overflow) the best one plus the lowest-index others.
 constexpr int kSelThreads = 1024;
-__global__ void __launch_bounds__(kSelThreads) k_wselect(int32_t nb, Buffers b) {
+__device__ void wselect_body(const InstDesc& c) {
     __shared__ WindowEntry list[kWindowCap];
     __shared__ int scan[kSelThreads];
     __shared__ double red[kSelThreads];
+    const Buffers& b = c.b;
+    const int nb = c.nb;
     const int tid = threadIdx.x;
     int total = 0;
     for (int base = 0; base < nb; base += kSelThreads) {
@@ -157,17 +164,19 @@ __global__ void __launch_bounds__(kSelThreads) k_wselect(int32_t nb, Buffers b) 
     }
 }
 
-// float64 gains of the window candidates with direct differences from the
-// caller's float32 points. One thread per ground point; candidates in groups
-// of 8 staged in LDS; per-block sums in fixed order.
+// ---- rescore: float64 direct-difference gains of the window candidates ----
+// One thread per ground point, from the caller's float32 points; candidates
+// in groups of 8 staged in LDS; per-block sums in a fixed order.
 constexpr int kRescoreGroup = 8;
-__global__ void __launch_bounds__(kBlock)
-k_rescore(const float* __restrict__ x, int64_t n, int32_t d, Buffers b) {
+__device__ void rescore_body(const InstDesc& c, int64_t blk) {
     __shared__ float cx[kRescoreGroup * EBC_MAX_DIM];
     __shared__ double red[kRescoreGroup][kBlock];
+    const Buffers& b = c.b;
+    const float* __restrict__ x = c.x;
+    const int d = c.d;
     const int W = b.state->window_count;
-    const int64_t v = int64_t(blockIdx.x) * kBlock + threadIdx.x;
-    const bool live = v < n;
+    const int64_t v = blk * kBlock + threadIdx.x;
+    const bool live = v < c.n;
     const double mv = live ? b.m64[v] : 0.0;
     const float* xv = x + (live ? v : 0) * d;
     for (int g0 = 0; g0 < W; g0 += kRescoreGroup) {
@@ -201,19 +210,21 @@ k_rescore(const float* __restrict__ x, int64_t n, int32_t d, Buffers b) {
             }
             __syncthreads();
         }
-        if (threadIdx.x < gn) b.rpart[int64_t(blockIdx.x) * kWindowMax + g0 + threadIdx.x] = red[threadIdx.x][0];
+        if (threadIdx.x < gn) b.rpart[blk * kWindowMax + g0 + threadIdx.x] = red[threadIdx.x][0];
     }
 }
 
-// One block: float64 gain of each window candidate = sum of the per-block
-// sums (thread i takes blocks i, i+256, ..., then a fixed tree); best gain
-// wins, ties to the lowest index. Records the pick. A step with no valid
-// candidate (only possible with non-finite input) records -1 and flags it.
-__global__ void __launch_bounds__(kBlock)
-k_pick(int64_t n, int32_t nbv, int32_t t, Buffers b, int32_t* sel_out, double* gain_out) {
+// ---- pick (one block per instance) ----
+// float64 gain of each window candidate = sum of the per-block sums (thread
+// i takes blocks i, i+256, ..., then a fixed tree); best gain wins, ties to
+// the lowest index. Records the pick. A step with no valid candidate (only
+// possible with non-finite input) records -1 and flags it.
+__device__ void pick_body(const InstDesc& c, int32_t t) {
     __shared__ double red[kBlock];
     __shared__ double sg[kWindowMax];
     __shared__ int si[kWindowMax];
+    const Buffers& b = c.b;
+    const int nbv = c.nb;
     const int W = b.state->window_count;
     for (int j = 0; j < kWindowMax; ++j) {
         double s = 0.0;
@@ -246,37 +257,38 @@ k_pick(int64_t n, int32_t nbv, int32_t t, Buffers b, int32_t* sel_out, double* g
         __syncthreads();
     }
     if (j == 0) {
-        const int c = si[0];
-        if (W > 0 && c >= 0 && int64_t(c) < n) {
-            b.state->cstar = c;
+        const int cs = si[0];
+        if (W > 0 && cs >= 0 && int64_t(cs) < c.n) {
+            b.state->cstar = cs;
             b.state->gstar = sg[0];
-            b.selected[c] = 1;
-            sel_out[t] = c;
-            if (gain_out) gain_out[t] = sg[0] / double(n);
+            b.selected[cs] = 1;
+            c.sel[t] = cs;
+            if (c.gain) c.gain[t] = sg[0] / double(c.n);
         } else {
             b.state->cstar = -1;
             atomicCAS(&b.state->error, 0, kDevErrNonFinite);
-            sel_out[t] = -1;
-            if (gain_out) gain_out[t] = NAN;
+            c.sel[t] = -1;
+            if (c.gain) c.gain[t] = NAN;
         }
     }
 }
 
-// m_v <- min(m_v, d(v, c*)) in float64 by direct differences; refresh the
-// float32 terms the gains kernel reads; per-block sums of m_v.
-__global__ void __launch_bounds__(kBlock)
-k_update(const float* __restrict__ x, int64_t n, int32_t d, Buffers b) {
+// ---- update: m_v <- min(m_v, d(v, c*)) in float64, per-block sums of m_v ----
+__device__ void update_body(const InstDesc& c, int64_t blk) {
     __shared__ float cx[EBC_MAX_DIM];
     __shared__ double red[kBlock];
-    const int c = b.state->cstar;
-    if (c >= 0)
-        for (int k = threadIdx.x; k < d; k += kBlock) cx[k] = x[int64_t(c) * d + k];
+    const Buffers& b = c.b;
+    const float* __restrict__ x = c.x;
+    const int d = c.d;
+    const int cs = b.state->cstar;
+    if (cs >= 0)
+        for (int k = threadIdx.x; k < d; k += kBlock) cx[k] = x[int64_t(cs) * d + k];
     __syncthreads();
-    const int64_t v = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+    const int64_t v = blk * kBlock + threadIdx.x;
     double mv = 0.0;
-    if (v < n && c < 0) {
+    if (v < c.n && cs < 0) {
         mv = b.m64[v];
-    } else if (v < n) {
+    } else if (v < c.n) {
         const float* xv = x + v * d;
         double acc = 0.0;
         for (int k = 0; k < d; ++k) {
@@ -296,21 +308,60 @@ k_update(const float* __restrict__ x, int64_t n, int32_t d, Buffers b) {
         if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
         __syncthreads();
     }
-    if (threadIdx.x == 0) b.fpart[blockIdx.x] = red[0];
+    if (threadIdx.x == 0) b.fpart[blk] = red[0];
 }
 
-__global__ void __launch_bounds__(kBlock)
-k_fsum(int64_t n, int32_t nbv, int32_t t, Buffers b, double* f_out) {
+// ---- fsum (one block per instance): f(S_t) = L({e0}) - |V|^-1 sum m_v ----
+__device__ void fsum_body(const InstDesc& c, int32_t t) {
     __shared__ double red[kBlock];
     double s = 0.0;
-    for (int i = threadIdx.x; i < nbv; i += kBlock) s += b.fpart[i];
+    for (int i = threadIdx.x; i < c.nb; i += kBlock) s += c.b.fpart[i];
     red[threadIdx.x] = s;
     __syncthreads();
     for (int w = kBlock / 2; w > 0; w >>= 1) {
         if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
         __syncthreads();
     }
-    if (threadIdx.x == 0) f_out[t] = b.state->l0 - red[0] / double(n);
+    if (threadIdx.x == 0) c.f[t] = c.b.state->l0 - red[0] / double(c.n);
+}
+
+// ---- solo kernels ----
+__global__ void __launch_bounds__(kBlock) k_gsum(InstDesc c) { gsum_body(c, blockIdx.x); }
+__global__ void __launch_bounds__(kBlock) k_wcount(InstDesc c) { wcount_body(c, blockIdx.x); }
+__global__ void __launch_bounds__(kSelThreads) k_wselect(InstDesc c) { wselect_body(c); }
+__global__ void __launch_bounds__(kBlock) k_rescore(InstDesc c) { rescore_body(c, blockIdx.x); }
+__global__ void __launch_bounds__(kBlock) k_pick(InstDesc c, int32_t t) { pick_body(c, t); }
+__global__ void __launch_bounds__(kBlock) k_update(InstDesc c) { update_body(c, blockIdx.x); }
+__global__ void __launch_bounds__(kBlock) k_fsum(InstDesc c, int32_t t) { fsum_body(c, t); }
+
+// ---- batched kernels: blocks of row_pre[i] .. row_pre[i+1] belong to instance i;
+// instances whose k is reached skip the step ----
+#define EBC_ROW_KERNEL(NAME, BODY)                                                                     \
+    __global__ void __launch_bounds__(kBlock)                                                          \
+        NAME(const InstDesc* __restrict__ descs, const int64_t* __restrict__ row_pre, int32_t count,   \
+             int32_t t) {                                                                              \
+        const int i = find_slot(row_pre, count, blockIdx.x);                                           \
+        const InstDesc c = descs[i];                                                                   \
+        if (t >= c.k) return;                                                                          \
+        BODY(c, int64_t(blockIdx.x) - row_pre[i]);                                                     \
+    }
+EBC_ROW_KERNEL(kb_gsum, gsum_body)
+EBC_ROW_KERNEL(kb_wcount, wcount_body)
+EBC_ROW_KERNEL(kb_rescore, rescore_body)
+EBC_ROW_KERNEL(kb_update, update_body)
+#undef EBC_ROW_KERNEL
+
+__global__ void __launch_bounds__(kSelThreads) kb_wselect(const InstDesc* __restrict__ descs, int32_t t) {
+    const InstDesc c = descs[blockIdx.x];
+    if (t < c.k) wselect_body(c);
+}
+__global__ void __launch_bounds__(kBlock) kb_pick(const InstDesc* __restrict__ descs, int32_t t) {
+    const InstDesc c = descs[blockIdx.x];
+    if (t < c.k) pick_body(c, t);
+}
+__global__ void __launch_bounds__(kBlock) kb_fsum(const InstDesc* __restrict__ descs, int32_t t) {
+    const InstDesc c = descs[blockIdx.x];
+    if (t < c.k) fsum_body(c, t);
 }
 
 hipError_t launch_greedy_step(const ebc_dataset* ds, int32_t t, int32_t* sel_out, double* f_out,
@@ -318,14 +369,29 @@ hipError_t launch_greedy_step(const ebc_dataset* ds, int32_t t, int32_t* sel_out
     hipError_t e = launch_gains(ds, nullptr, ds->n_pad, s);
     if (e != hipSuccess) return e;
     if (ev_gains_done && (e = hipEventRecord(ev_gains_done, s)) != hipSuccess) return e;
-    const int nb = int(ds->n_pad / kBlock);
-    hipLaunchKernelGGL(k_gsum, dim3(nb), dim3(kBlock), 0, s, ds->n_pad, ds->v_splits, ds->b);
-    hipLaunchKernelGGL(k_wcount, dim3(nb), dim3(kBlock), 0, s, nb, ds->b);
-    hipLaunchKernelGGL(k_wselect, dim3(1), dim3(kSelThreads), 0, s, nb, ds->b);
-    hipLaunchKernelGGL(k_rescore, dim3(nb), dim3(kBlock), 0, s, ds->x, ds->n, ds->d, ds->b);
-    hipLaunchKernelGGL(k_pick, dim3(1), dim3(kBlock), 0, s, ds->n, nb, t, ds->b, sel_out, gain_out);
-    hipLaunchKernelGGL(k_update, dim3(nb), dim3(kBlock), 0, s, ds->x, ds->n, ds->d, ds->b);
-    hipLaunchKernelGGL(k_fsum, dim3(1), dim3(kBlock), 0, s, ds->n, nb, t, ds->b, f_out);
+    InstDesc c;
+    fill_desc(ds, t + 1, sel_out, f_out, gain_out, &c);
+    const int nb = c.nb;
+    hipLaunchKernelGGL(k_gsum, dim3(nb), dim3(kBlock), 0, s, c);
+    hipLaunchKernelGGL(k_wcount, dim3(nb), dim3(kBlock), 0, s, c);
+    hipLaunchKernelGGL(k_wselect, dim3(1), dim3(kSelThreads), 0, s, c);
+    hipLaunchKernelGGL(k_rescore, dim3(nb), dim3(kBlock), 0, s, c);
+    hipLaunchKernelGGL(k_pick, dim3(1), dim3(kBlock), 0, s, c, t);
+    hipLaunchKernelGGL(k_update, dim3(nb), dim3(kBlock), 0, s, c);
+    hipLaunchKernelGGL(k_fsum, dim3(1), dim3(kBlock), 0, s, c, t);
+    return hipGetLastError();
+}
+
+hipError_t launch_step_batched(const InstDesc* descs, const int64_t* row_pre, int32_t count, int64_t total_rows,
+                               int32_t t, hipStream_t s) {
+    const dim3 rows = dim3(unsigned(total_rows)), one = dim3(unsigned(count));
+    hipLaunchKernelGGL(kb_gsum, rows, dim3(kBlock), 0, s, descs, row_pre, count, t);
+    hipLaunchKernelGGL(kb_wcount, rows, dim3(kBlock), 0, s, descs, row_pre, count, t);
+    hipLaunchKernelGGL(kb_wselect, one, dim3(kSelThreads), 0, s, descs, t);
+    hipLaunchKernelGGL(kb_rescore, rows, dim3(kBlock), 0, s, descs, row_pre, count, t);
+    hipLaunchKernelGGL(kb_pick, one, dim3(kBlock), 0, s, descs, t);
+    hipLaunchKernelGGL(kb_update, rows, dim3(kBlock), 0, s, descs, row_pre, count, t);
+    hipLaunchKernelGGL(kb_fsum, one, dim3(kBlock), 0, s, descs, t);
     return hipGetLastError();
 }
 

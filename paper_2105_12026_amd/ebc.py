@@ -13,7 +13,7 @@ import os
 
 import torch  # loads the process's HIP runtime before libebc.so binds to it
 
-__all__ = ["EBCError", "Dataset", "lib", "status_string", "DTYPES", "LIB_PATH", "ABI_FUNCTIONS"]
+__all__ = ["EBCError", "Dataset", "Batch", "lib", "status_string", "DTYPES", "LIB_PATH", "ABI_FUNCTIONS"]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libebc.so")
 DTYPES = {"f32": 0, "f16": 1, "bf16": 2, "fp8": 3}
@@ -21,7 +21,8 @@ ABI_FUNCTIONS = (
     "ebc_dataset_bytes", "ebc_dataset_create", "ebc_dataset_destroy", "ebc_eval_sets",
     "ebc_marginal_gains", "ebc_greedy", "ebc_sync_status", "ebc_status_string",
     "ebc_dataset_get_info", "ebc_profile_enable", "ebc_profile_read", "ebc_set_gains_variant",
-    "ebc_gains_variant_count", "ebc_set_greedy_graph",
+    "ebc_gains_variant_count", "ebc_set_greedy_graph", "ebc_batch_bytes", "ebc_batch_create",
+    "ebc_batch_destroy", "ebc_batch_set_graph", "ebc_greedy_batched", "ebc_batch_info",
 )
 
 
@@ -74,8 +75,15 @@ def lib() -> ctypes.CDLL:
         L.ebc_set_greedy_graph.argtypes = [P, i32]
         L.ebc_gains_variant_count.argtypes = [ctypes.c_int]
         L.ebc_profile_read.argtypes = [P, ctypes.POINTER(_Profile), i32]
+        L.ebc_batch_bytes.argtypes = [i32]
+        L.ebc_batch_bytes.restype = ctypes.c_size_t
+        L.ebc_batch_create.argtypes = [P, i32, P, ctypes.c_size_t, P, ctypes.POINTER(P)]
+        L.ebc_batch_destroy.argtypes = [P]
+        L.ebc_batch_set_graph.argtypes = [P, i32]
+        L.ebc_greedy_batched.argtypes = [P, P, P, P, P, P]
+        L.ebc_batch_info.argtypes = [P, ctypes.POINTER(i32), ctypes.POINTER(i64), ctypes.POINTER(i64)]
         for name in ABI_FUNCTIONS:
-            if name not in ("ebc_dataset_bytes", "ebc_status_string"):
+            if name not in ("ebc_dataset_bytes", "ebc_status_string", "ebc_batch_bytes"):
                 getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -209,3 +217,63 @@ class Dataset:
         gain = torch.empty(k, dtype=torch.float64, device=dev) if gain is None else gain
         _check(lib().ebc_greedy(self._h, int(k), _ptr(sel), _ptr(f), _ptr(gain), _stream(stream)), "ebc_greedy")
         return sel, f, gain
+
+
+class Batch:
+    """Many datasets advanced together by ebc_greedy_batched (one launch per
+    kernel bucket and stage per step tick). Results equal solo runs bitwise."""
+
+    def __init__(self, datasets, stream=None):
+        self.datasets = list(datasets)
+        if not self.datasets:
+            raise ValueError("empty batch")
+        n = len(self.datasets)
+        L = lib()
+        dev = self.datasets[0].x.device
+        self.workspace = torch.empty(int(L.ebc_batch_bytes(n)), dtype=torch.uint8, device=dev)
+        handles = (ctypes.c_void_p * n)(*[d.handle.value for d in self.datasets])
+        h = ctypes.c_void_p()
+        _check(L.ebc_batch_create(ctypes.cast(handles, ctypes.c_void_p), n, _ptr(self.workspace),
+                                  self.workspace.numel(), _stream(stream), ctypes.byref(h)), "ebc_batch_create")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().ebc_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_graph(self, on: bool = True):
+        _check(lib().ebc_batch_set_graph(self._h, int(bool(on))), "ebc_batch_set_graph")
+
+    def info(self) -> dict:
+        b, w, r = ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().ebc_batch_info(self._h, ctypes.byref(b), ctypes.byref(w), ctypes.byref(r)), "ebc_batch_info")
+        return {"buckets": b.value, "gains_workgroups_per_tick": w.value, "row_blocks_per_tick": r.value}
+
+    def greedy(self, ks, stream=None, outs=None):
+        """Greedy on every dataset; ks[i] steps for dataset i. Returns a list
+        of (sel int32 [k], f float64 [k], gain float64 [k]) per dataset."""
+        n = len(self.datasets)
+        if len(ks) != n:
+            raise ValueError("one k per dataset")
+        if outs is None:
+            outs = []
+            for d, k in zip(self.datasets, ks):
+                dev = d.x.device
+                outs.append((torch.empty(max(k, 1), dtype=torch.int32, device=dev),
+                             torch.empty(max(k, 1), dtype=torch.float64, device=dev),
+                             torch.empty(max(k, 1), dtype=torch.float64, device=dev)))
+        karr = (ctypes.c_int32 * n)(*[int(k) for k in ks])
+        sel = (ctypes.c_void_p * n)(*[o[0].data_ptr() for o in outs])
+        f = (ctypes.c_void_p * n)(*[o[1].data_ptr() for o in outs])
+        g = (ctypes.c_void_p * n)(*[o[2].data_ptr() for o in outs])
+        _check(lib().ebc_greedy_batched(self._h, ctypes.cast(karr, ctypes.c_void_p), ctypes.cast(sel, ctypes.c_void_p),
+                                        ctypes.cast(f, ctypes.c_void_p), ctypes.cast(g, ctypes.c_void_p),
+                                        _stream(stream)), "ebc_greedy_batched")
+        return [(o[0][:k], o[1][:k], o[2][:k]) for o, k in zip(outs, ks)]

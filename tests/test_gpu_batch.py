@@ -1,0 +1,85 @@
+"""Batched greedy (many instances, one launch per kernel bucket and stage per
+tick) against solo runs: selections, f and gains bitwise equal, for a mix of
+sizes, dimensions, distance dtypes, tile variants and k (including k = 0),
+eager and graph mode; the float32 instances also against the oracle."""
+import numpy as np
+import pytest
+
+from paper_2105_12026_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+# (n, d, dtype, variant, k)
+MIX = [(300, 16, "f32", 0, 5), (1000, 100, "bf16", 0, 7), (2500, 64, "bf16", 2, 12), (700, 5, "fp8", 0, 3),
+       (1500, 33, "f16", 1, 0), (4000, 128, "f32", 0, 9), (257, 64, "bf16", 0, 4), (2049, 64, "fp8", 2, 6)]
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    from paper_2105_12026_amd import ebc
+    assert torch.cuda.is_available()
+    return torch, ebc
+
+
+def _make(env, spec, seed):
+    torch, ebc = env
+    n, d, dt, var, k = spec
+    x = W.gaussian_mixture(np.random.default_rng(seed), n, d, 6).astype(np.float32)
+    ds = ebc.Dataset(torch.from_numpy(x).cuda(), dtype=dt)
+    if var:
+        ds.set_variant(var)
+    return x, ds
+
+
+def _solo(env, spec, seed):
+    x, ds = _make(env, spec, seed)
+    out = [t.cpu().numpy() for t in ds.greedy(spec[4])]
+    ds.sync()
+    return x, out
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_batched_equals_solo(env, ref, graph):
+    torch, ebc = env
+    print(f"[gpu-case] batched mix of {len(MIX)} instances, graph={graph}", flush=True)
+    solos = [_solo(env, s, 100 + i) for i, s in enumerate(MIX)]
+    dss = [_make(env, s, 100 + i)[1] for i, s in enumerate(MIX)]
+    batch = ebc.Batch(dss)
+    if graph:
+        batch.set_graph(True)
+    info = batch.info()
+    assert info["buckets"] >= 5
+    ks = [s[4] for s in MIX]
+    for rep in range(3 if graph else 1):
+        outs = batch.greedy(ks)
+        for ds in dss:
+            ds.sync()
+        for (x, so), bo, spec in zip(solos, outs, MIX):
+            for a, b in zip(so, bo):
+                np.testing.assert_array_equal(b.cpu().numpy(), a, err_msg=str(spec))
+    # float32 instances against the oracle
+    for (x, so), spec in zip(solos, MIX):
+        if spec[2] == "f32":
+            rsel, rf, _ = ref.greedy(x, spec[4])
+            assert so[0].tolist() == rsel.tolist()
+            np.testing.assert_allclose(so[1], rf, rtol=1e-5)
+
+
+def test_batched_k_change_same_ticks(env):
+    torch, ebc = env
+    print("[gpu-case] batched graph replay with changed k", flush=True)
+    specs = [(600, 16, "bf16", 0, 6), (900, 24, "f32", 0, 2), (1200, 8, "fp8", 0, 4)]
+    dss = [_make(env, s, 200 + i)[1] for i, s in enumerate(specs)]
+    batch = ebc.Batch(dss)
+    batch.set_graph(True)
+    first = batch.greedy([6, 2, 4])
+    firstn = [[t.cpu().numpy() for t in o] for o in first]
+    second = batch.greedy([3, 6, 1])   # same number of ticks: graph replayed
+    for ds in dss:
+        ds.sync()
+    np.testing.assert_array_equal(second[0][0].cpu().numpy(), firstn[0][0][:3])
+    np.testing.assert_array_equal(second[2][0].cpu().numpy(), firstn[2][0][:1])
+    solo = _solo(env, (900, 24, "f32", 0, 6), 201)[1]
+    np.testing.assert_array_equal(second[1][0].cpu().numpy(), solo[0])
+    np.testing.assert_array_equal(second[1][1].cpu().numpy(), solo[1])

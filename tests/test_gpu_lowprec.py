@@ -83,3 +83,31 @@ def test_f16_range_is_reported(env):
     with pytest.raises(ebc.EBCError) as ei:
         ds.sync()
     assert ei.value.code == 4
+
+
+@pytest.fixture(scope="module")
+def sweep200k():
+    return W.precision_sweep(seed=3)
+
+
+@pytest.mark.parametrize("dt", ["bf16", "f16", "fp8"])
+def test_lowprec_full_size_gains_sampled(env, ref, sweep200k, dt):
+    """200000 x 64 mixture with outliers, all candidates in the benchmark's
+    launch configuration; a sample of the outputs against the oracle, at
+    S = {} and at a 30-point S."""
+    torch, _ = env
+    p = sweep200k
+    rng = np.random.default_rng(91)
+    cand = np.sort(rng.choice(p.n, 96, replace=False)).astype(np.int32)
+    print(f"[gpu-case] full-size gains {dt} n=200000 d=64", flush=True)
+    ds = _ds(env, p.x, dt)
+    errs = []
+    for s in ([], rng.choice(p.n, 30, replace=False)):
+        m = ref.min_dist(p.x, s)
+        g = ds.marginal_gains(m=torch.from_numpy(m)).cpu().numpy()
+        ds.sync()
+        rg = ref.gains(p.x, m, cand)
+        scale = max(np.max(np.abs(rg)), np.max(g))
+        errs.append(float(np.max(np.abs(g[cand] - rg)) / scale))
+    print(f"[gpu-result] full-size gains {dt} rel err {max(errs):.3e}", flush=True)
+    assert max(errs) <= GAIN_TOL[dt]
