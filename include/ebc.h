@@ -227,6 +227,20 @@ EBC_API ebc_status ebc_dataset_get_info(ebc_dataset* ds, ebc_dataset_info* info)
 EBC_API ebc_status ebc_set_gains_variant(ebc_dataset* ds, int32_t variant);
 EBC_API int32_t ebc_gains_variant_count(ebc_dtype dt);
 
+/* Autotuner for the gains tile variant. Looks up the process-wide table
+ * keyed by (dtype, padded row length, floor(log2(n_pad))); on a miss (or
+ * with force != 0) times every variant on this dataset (reps launches each,
+ * HIP events on `stream`, blocking), records the fastest and sets it. Does
+ * not change the dataset's greedy state. variant_out and times_ms_out
+ * ([ebc_gains_variant_count(dt)], per-launch milliseconds, only when
+ * measured) may be NULL. The table persists through the text file of
+ * ebc_tune_cache_load/_save (one "dtype k_pad size_bucket variant" per line). */
+EBC_API ebc_status ebc_autotune(ebc_dataset* ds, int32_t reps, int32_t force, void* stream, int32_t* variant_out,
+                                float* times_ms_out);
+EBC_API ebc_status ebc_tune_cache_load(const char* path);
+EBC_API ebc_status ebc_tune_cache_save(const char* path);
+EBC_API int32_t ebc_tune_cache_size(void);
+
 /* Per-kernel timing of ebc_greedy with HIP events recorded on the call's
  * stream around each step's marginal-gains launch and around the whole step.
  * Off by default; when on, ebc_greedy records 3 events per step (host-side

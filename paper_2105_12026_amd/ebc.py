@@ -22,7 +22,8 @@ ABI_FUNCTIONS = (
     "ebc_marginal_gains", "ebc_greedy", "ebc_sync_status", "ebc_status_string",
     "ebc_dataset_get_info", "ebc_profile_enable", "ebc_profile_read", "ebc_set_gains_variant",
     "ebc_gains_variant_count", "ebc_set_greedy_graph", "ebc_batch_bytes", "ebc_batch_create",
-    "ebc_batch_destroy", "ebc_batch_set_graph", "ebc_greedy_batched", "ebc_batch_info",
+    "ebc_batch_destroy", "ebc_batch_set_graph", "ebc_greedy_batched", "ebc_batch_info", "ebc_autotune",
+    "ebc_tune_cache_load", "ebc_tune_cache_save", "ebc_tune_cache_size",
 )
 
 
@@ -82,6 +83,10 @@ def lib() -> ctypes.CDLL:
         L.ebc_batch_set_graph.argtypes = [P, i32]
         L.ebc_greedy_batched.argtypes = [P, P, P, P, P, P]
         L.ebc_batch_info.argtypes = [P, ctypes.POINTER(i32), ctypes.POINTER(i64), ctypes.POINTER(i64)]
+        L.ebc_autotune.argtypes = [P, i32, i32, P, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_float)]
+        L.ebc_tune_cache_load.argtypes = [ctypes.c_char_p]
+        L.ebc_tune_cache_save.argtypes = [ctypes.c_char_p]
+        L.ebc_tune_cache_size.argtypes = []
         for name in ABI_FUNCTIONS:
             if name not in ("ebc_dataset_bytes", "ebc_status_string", "ebc_batch_bytes"):
                 getattr(L, name).restype = ctypes.c_int
@@ -173,6 +178,16 @@ class Dataset:
     def variant_count(dtype: str) -> int:
         return int(lib().ebc_gains_variant_count(DTYPES[dtype]))
 
+    def autotune(self, reps: int = 3, force: bool = False, stream=None) -> dict:
+        """Pick the fastest gains tile variant for this dataset's (dtype, row
+        length, size bucket), from the tuning table or by timing (blocking)."""
+        nv = self.variant_count(self.dtype)
+        v = ctypes.c_int32(-1)
+        times = (ctypes.c_float * nv)(*([float("nan")] * nv))
+        _check(lib().ebc_autotune(self._h, int(reps), int(bool(force)), _stream(stream), ctypes.byref(v), times),
+               "ebc_autotune")
+        return {"variant": v.value, "times_ms": list(times)}
+
     def profile(self, on: bool = True):
         """Turn per-step HIP-event timing of greedy on or off."""
         _check(lib().ebc_profile_enable(self._h, int(bool(on))), "ebc_profile_enable")
@@ -217,6 +232,18 @@ class Dataset:
         gain = torch.empty(k, dtype=torch.float64, device=dev) if gain is None else gain
         _check(lib().ebc_greedy(self._h, int(k), _ptr(sel), _ptr(f), _ptr(gain), _stream(stream)), "ebc_greedy")
         return sel, f, gain
+
+
+def tune_cache_load(path: str) -> bool:
+    return lib().ebc_tune_cache_load(path.encode()) == 0
+
+
+def tune_cache_save(path: str):
+    _check(lib().ebc_tune_cache_save(path.encode()), "ebc_tune_cache_save")
+
+
+def tune_cache_size() -> int:
+    return int(lib().ebc_tune_cache_size())
 
 
 class Batch:

@@ -83,3 +83,28 @@ def test_batched_k_change_same_ticks(env):
     solo = _solo(env, (900, 24, "f32", 0, 6), 201)[1]
     np.testing.assert_array_equal(second[1][0].cpu().numpy(), solo[0])
     np.testing.assert_array_equal(second[1][1].cpu().numpy(), solo[1])
+
+
+@pytest.mark.parametrize("dt", ["bf16", "fp8", "f16"])
+def test_variants_are_bitwise_identical_and_autotune(env, dt, tmp_path):
+    torch, ebc = env
+    print(f"[gpu-case] gains variants {dt} n=3000 d=64 + autotune", flush=True)
+    x = W.gaussian_mixture(np.random.default_rng(300), 3000, 64, 6).astype(np.float32)
+    ds = ebc.Dataset(torch.from_numpy(x).cuda(), dtype=dt)
+    m = torch.from_numpy(np.sum(x.astype(np.float64) ** 2, axis=1) * 0.3)
+    outs = []
+    for v in range(ebc.Dataset.variant_count(dt)):
+        ds.set_variant(v)
+        outs.append(ds.marginal_gains(m=m).cpu().numpy())
+    ds.sync()
+    for o in outs[1:]:
+        np.testing.assert_array_equal(o, outs[0])
+    r = ds.autotune(reps=2, force=True)
+    assert 0 <= r["variant"] < ebc.Dataset.variant_count(dt)
+    assert all(t > 0 for t in r["times_ms"])
+    path = str(tmp_path / "tune.txt")
+    ebc.tune_cache_save(path)
+    assert ebc.tune_cache_load(path)
+    assert ebc.tune_cache_size() >= 1
+    r2 = ds.autotune(reps=2)                  # served from the table
+    assert r2["variant"] == r["variant"]
