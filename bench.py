@@ -33,6 +33,7 @@ WORKLOADS = {
     "gmm50+out_n200000_d64_k100": ("precision_sweep", {"seed": 3}),
     "normal_n1000_d16_k5": ("small_normal", {"seed": 0}),
     "batched512_bf16_k20": ("batched_instances", {"seed": 4}),
+    "serving_curves_d64_bf16": ("serving_requests", {"seed": 5}),
 }
 
 
@@ -138,6 +139,73 @@ def bench_batched(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_serving(args):
+    """Serving: summarisation requests of process curves (n ~ U{5000..100000},
+    d = 64, k ~ U{5..50}, BF16 distances) through the serving core. The
+    closed-loop capacity mu (all requests queued at once) is measured first;
+    then Poisson streams at 0.3, 0.7 and 1.1 mu, each reporting p50/p99
+    latency from arrival to the result on the host and completed req/s.
+    The stream cycles through a pool of distinct seeded requests."""
+    import numpy as np
+    import torch
+
+    from paper_2105_12026_amd import ebc, serving, workloads
+
+    pool_n = args.serving_pool
+    t_gen = time.perf_counter()
+    pool = workloads.serving_requests(seed=5, count=pool_n)
+    print(f"# generated {pool_n} requests in {time.perf_counter() - t_gen:.1f} s", file=sys.stderr, flush=True)
+    dt = args.dtype if args.dtype != "f32" else "bf16"
+    # autotune the gains variant per (dtype, row length, size bucket) seen in the pool
+    for p in pool[:8]:
+        ds = ebc.Dataset(torch.from_numpy(p.x).cuda(), dtype=dt)
+        ds.autotune(reps=2)
+        ds.close()
+    torch.cuda.synchronize()
+    arena_bytes = args.serving_arena_gib << 30
+    sv = ebc.Server(arena_bytes, max_slots=args.serving_slots)
+    payloads = [(p.x, p.k) for p in pool]
+    flops_of = lambda ps: sum(2.0 * 64 * pairs_per_greedy(x.shape[0], k) for x, k in ps)
+    # warm-up, then closed loop
+    serving.run_closed_loop(sv, payloads[:4], dtype=dt)
+    closed = payloads * max(1, args.steps)
+    recs, c0, c1 = serving.run_closed_loop(sv, closed, dtype=dt)
+    closed_s = c1 - c0
+    mu = len(closed) / closed_s
+    closed_sum = serving.summarize(recs, c0)
+    achieved = flops_of(closed) / closed_s / 1e12
+    print(f"# closed loop: {len(closed)} requests in {closed_s:.2f} s, mu = {mu:.1f} req/s", file=sys.stderr,
+          flush=True)
+    rates = {}
+    for j, frac in enumerate((0.3, 0.7, 1.1)):
+        count = args.serving_requests
+        stream = [payloads[i % pool_n] for i in range(count)]
+        arr = workloads.poisson_arrivals(5 + j, frac * mu, count)
+        recs, t0 = serving.run_open_loop(sv, stream, arr, dtype=dt)
+        summ = serving.summarize(recs, t0)
+        summ["offered_req_per_s"] = frac * mu
+        rates[f"{frac}mu"] = {k: (round(v, 5) if isinstance(v, float) else v) for k, v in summ.items()}
+        print(f"# rate {frac} mu: {summ}", file=sys.stderr, flush=True)
+    st = sv.stats()
+    sv.close()
+    out = {
+        "metric": "requests/s (serving, closed-loop capacity), p50/p99 latency at 0.3/0.7/1.1 of it",
+        "value": mu, "unit": "req/s", "n_gpus": 1, "steps": args.steps, "warmup": 1,
+        "ms_per_step": closed_s * 1e3 / max(1, args.steps), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": dt, "data": "synthetic",
+        "config": {"workload": "serving_curves_d64_bf16", "pool": pool_n, "closed_loop_requests": len(closed),
+                   "requests_per_rate": args.serving_requests, "max_slots": args.serving_slots,
+                   "arena_gib": args.serving_arena_gib, "ticks": st["ticks"],
+                   "closed_loop_latency": {k: (round(v, 5) if isinstance(v, float) else v)
+                                           for k, v in closed_sum.items()},
+                   "rates": rates},
+        "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_TFLOPS[dt], "unit": "TFLOP/s",
+                     "frac": round(achieved / PEAK_TFLOPS[dt], 4), "traffic": None,
+                     "kernel": "whole serving loop in the closed-loop run, algorithmic 2*d flops per pair"},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -149,6 +217,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 256 MiB device copy (reference for HBM byte counters)")
+    ap.add_argument("--serving-pool", type=int, default=24, help="distinct requests the serving stream cycles")
+    ap.add_argument("--serving-requests", type=int, default=150, help="requests per arrival rate")
+    ap.add_argument("--serving-slots", type=int, default=64)
+    ap.add_argument("--serving-arena-gib", type=int, default=32)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is a design note only",
@@ -157,6 +229,9 @@ def main():
 
     if args.workload.startswith("batched"):
         bench_batched(args)
+        return
+    if args.workload.startswith("serving"):
+        bench_serving(args)
         return
 
     import numpy as np

@@ -44,6 +44,8 @@ extern "C" {
 
 typedef struct ebc_dataset ebc_dataset; /* opaque; host struct owned by the library */
 typedef struct ebc_batch ebc_batch;     /* opaque; many datasets advanced together */
+typedef struct ebc_server ebc_server;   /* opaque; request loop with continuous batching */
+typedef struct ebc_arena ebc_arena;     /* opaque; first-fit allocator bookkeeping */
 
 typedef enum {
     EBC_OK = 0,
@@ -51,7 +53,7 @@ typedef enum {
     EBC_E_INDEX = 2,        /* device: CSR index outside [0, n) or offsets not non-decreasing */
     EBC_E_NONFINITE = 3,    /* device: NaN or Inf in the input points */
     EBC_E_RANGE = 4,        /* device: a value does not fit the distance dtype (FP16: |x| > 65504) */
-    EBC_E_NOMEM = 5,        /* host allocation of the dataset struct failed */
+    EBC_E_NOMEM = 5,        /* host allocation failed, or an arena block / request does not fit */
     EBC_E_DEVICE = 6,       /* a HIP runtime call failed */
     EBC_E_UNSUPPORTED = 7   /* valid request this build does not implement (e.g. d > 128) */
 } ebc_status;
@@ -186,6 +188,49 @@ EBC_API ebc_status ebc_greedy_batched(ebc_batch* batch, const int32_t* k, int32_
 /* Launch geometry of one tick: gains buckets, gains workgroups, row blocks. */
 EBC_API ebc_status ebc_batch_info(ebc_batch* batch, int32_t* buckets, int64_t* gains_workgroups_per_tick,
                                   int64_t* row_blocks_per_tick);
+
+/* ---- Serving: continuous batching at greedy-step granularity ----
+ * A request is (ground set x [host float32, n x d], greedy bound k, dtype).
+ * ebc_server_create: `arena` [device] block of arena_bytes (256-aligned,
+ * caller-owned) that holds everything the server places on the device: the
+ * batched-tick tables for max_slots requests, and per admitted request its
+ * points, dataset workspace and outputs (ebc_request_bytes), sub-allocated
+ * first-fit. All work is enqueued on `stream`.
+ * ebc_server_submit: copies x into a host buffer (the caller's may be reused
+ * at once) and queues the request; t_arrival is its arrival time on the
+ * server clock (ebc_server_now), or < 0 for now. A request larger than the
+ * whole arena is refused (EBC_E_NOMEM).
+ * ebc_server_step: one scheduler tick: admits queued requests in arrival
+ * order while a slot is free and the head request fits the arena (the head
+ * waits otherwise); advances every active request by one greedy step in one
+ * batched launch set (one gains launch per kernel bucket, seven step
+ * launches); copies out and releases the requests that reached k, waiting
+ * for `stream` only when one did. Each request computes exactly what a solo
+ * ebc_greedy computes, alone or in any mix.
+ * ebc_server_poll: state 0 queued, 1 active, 2 done, 3 failed; on done, the
+ * k selections, f(S_1..S_k) and gains (host pointers, NULL to skip); the
+ * arrival, admission and completion times (seconds, server clock).
+ * The arena functions expose the server's allocator bookkeeping (no device
+ * access) for drivers that plan admission and for tests. */
+EBC_API size_t ebc_request_bytes(int64_t n, int32_t d, int32_t k, ebc_dtype dt);
+EBC_API ebc_status ebc_server_create(void* arena, size_t arena_bytes, int32_t max_slots, void* stream,
+                                     ebc_server** out);
+EBC_API ebc_status ebc_server_destroy(ebc_server* server);
+EBC_API ebc_status ebc_server_submit(ebc_server* server, const float* x_host, int64_t n, int32_t d, int32_t k,
+                                     ebc_dtype dt, double t_arrival, int64_t* req_id);
+EBC_API ebc_status ebc_server_step(ebc_server* server, int32_t* completed);
+EBC_API ebc_status ebc_server_poll(ebc_server* server, int64_t req_id, int32_t* state, int32_t* sel_host,
+                                   double* f_host, double* gain_host, double* t_arrive, double* t_admit,
+                                   double* t_done);
+EBC_API ebc_status ebc_server_stats(ebc_server* server, int32_t* queued, int32_t* active, int64_t* completed,
+                                    int64_t* ticks, size_t* free_bytes);
+EBC_API double ebc_server_now(void);
+EBC_API ebc_status ebc_arena_create(size_t capacity, ebc_arena** out);
+EBC_API ebc_status ebc_arena_alloc(ebc_arena* arena, size_t bytes, size_t* offset);
+EBC_API ebc_status ebc_arena_free(ebc_arena* arena, size_t offset);
+EBC_API size_t ebc_arena_free_bytes(const ebc_arena* arena);
+EBC_API size_t ebc_arena_largest_free(const ebc_arena* arena);
+EBC_API ebc_status ebc_arena_destroy(ebc_arena* arena);
 
 /* Host-side counters of the last ebc_greedy on this dataset, valid after
  * ebc_sync_status: window_max = largest number of candidates re-scored in

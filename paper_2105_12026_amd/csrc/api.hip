@@ -73,7 +73,7 @@ const char* ebc_status_string(ebc_status st) {
         case EBC_E_INDEX: return "set index out of range or offsets not non-decreasing";
         case EBC_E_NONFINITE: return "non-finite value in the input points";
         case EBC_E_RANGE: return "value out of range of the distance dtype";
-        case EBC_E_NOMEM: return "host allocation failed";
+        case EBC_E_NOMEM: return "out of memory (host allocation, or no room in the arena)";
         case EBC_E_DEVICE: return "HIP runtime error";
         case EBC_E_UNSUPPORTED: return "unsupported by this build";
     }

@@ -24,42 +24,22 @@ struct Bucket {
     int64_t total_wgs;
 };
 
-size_t al(size_t v) { return (v + 255) & ~size_t(255); }
-
-struct BatchLayout {
-    size_t desc, row_pre, slot_inst, wg_pre, total;
-};
-
-BatchLayout batch_layout(int32_t count) {
-    BatchLayout L{};
-    size_t o = 0;
-    L.desc = o;
-    o = al(o + size_t(count) * sizeof(InstDesc));
-    L.row_pre = o;
-    o = al(o + size_t(count + 1) * sizeof(int64_t));
-    L.slot_inst = o;
-    o = al(o + size_t(count) * sizeof(int32_t));
-    L.wg_pre = o;
-    o = al(o + size_t(2 * count) * sizeof(int64_t));
-    L.total = o;
-    return L;
-}
-
 }  // namespace
 
 struct ebc_batch {
     int32_t count;
     std::vector<ebc_dataset*> ds;
+    TableLayout tl;
+    char* d_tables;
     InstDesc* d_desc;
     int64_t* d_row_pre;
     int32_t* d_slot_inst;
     int64_t* d_wg_pre;
     int64_t total_rows;
     std::vector<Bucket> buckets;
-    // host staging of the device tables (kept alive for the async copies)
     std::vector<int64_t> h_row_pre, h_wg_pre;
     std::vector<int32_t> h_slot_inst;
-    std::vector<InstDesc> h_desc;
+    PinnedTables staging;
     // graph mode
     int32_t graph_on;
     hipStream_t cap_stream;
@@ -93,7 +73,7 @@ extern "C" {
 
 size_t ebc_batch_bytes(int32_t count) {
     if (count < 1) return 0;
-    return batch_layout(count).total;
+    return table_layout(count).total;
 }
 
 ebc_status ebc_batch_create(ebc_dataset* const* ds, int32_t count, void* workspace, size_t workspace_bytes,
@@ -102,7 +82,7 @@ ebc_status ebc_batch_create(ebc_dataset* const* ds, int32_t count, void* workspa
     *out = nullptr;
     if (!ds || count < 1 || !workspace) return EBC_E_INVALID_ARG;
     if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0) return EBC_E_INVALID_ARG;
-    const BatchLayout L = batch_layout(count);
+    const TableLayout L = table_layout(count);
     if (workspace_bytes < L.total) return EBC_E_INVALID_ARG;
     for (int32_t i = 0; i < count; ++i)
         if (!ds[i]) return EBC_E_INVALID_ARG;
@@ -112,6 +92,8 @@ ebc_status ebc_batch_create(ebc_dataset* const* ds, int32_t count, void* workspa
     bt->count = count;
     bt->ds.assign(ds, ds + count);
     char* w = static_cast<char*>(workspace);
+    bt->tl = L;
+    bt->d_tables = w;
     bt->d_desc = reinterpret_cast<InstDesc*>(w + L.desc);
     bt->d_row_pre = reinterpret_cast<int64_t*>(w + L.row_pre);
     bt->d_slot_inst = reinterpret_cast<int32_t*>(w + L.slot_inst);
@@ -149,17 +131,7 @@ ebc_status ebc_batch_create(ebc_dataset* const* ds, int32_t count, void* workspa
         b.total_wgs = acc;
         bt->buckets.push_back(b);
     }
-    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    hipError_t e = hipMemcpyAsync(bt->d_row_pre, bt->h_row_pre.data(), bt->h_row_pre.size() * sizeof(int64_t),
-                                  hipMemcpyHostToDevice, s);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(bt->d_slot_inst, bt->h_slot_inst.data(), bt->h_slot_inst.size() * sizeof(int32_t),
-                           hipMemcpyHostToDevice, s);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(bt->d_wg_pre, bt->h_wg_pre.data(), bt->h_wg_pre.size() * sizeof(int64_t),
-                           hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e != hipSuccess) {
+    if (bt->staging.init(L.total) != hipSuccess) {
         delete bt;
         return EBC_E_DEVICE;
     }
@@ -192,14 +164,19 @@ ebc_status ebc_greedy_batched(ebc_batch* bt, const int32_t* k, int32_t* const* s
         ticks = std::max(ticks, k[i]);
     }
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    bt->h_desc.resize(bt->count);
+    // descriptors and block maps, staged in pinned memory, one copy
+    hipError_t e = hipSuccess;
+    char* h = bt->staging.acquire(&e);
+    if (e != hipSuccess) return EBC_E_DEVICE;
+    InstDesc* hd = reinterpret_cast<InstDesc*>(h + bt->tl.desc);
     for (int32_t i = 0; i < bt->count; ++i) {
-        fill_desc(bt->ds[i], k[i], sel_out[i], f_out[i], gain_out ? gain_out[i] : nullptr, &bt->h_desc[i]);
+        fill_desc(bt->ds[i], k[i], sel_out[i], f_out[i], gain_out ? gain_out[i] : nullptr, &hd[i]);
         bt->ds[i]->stats.steps = k[i];
     }
-    hipError_t e = hipMemcpyAsync(bt->d_desc, bt->h_desc.data(), bt->h_desc.size() * sizeof(InstDesc),
-                                  hipMemcpyHostToDevice, s);
-    if (e != hipSuccess) return EBC_E_DEVICE;
+    memcpy(h + bt->tl.row_pre, bt->h_row_pre.data(), bt->h_row_pre.size() * sizeof(int64_t));
+    memcpy(h + bt->tl.slot_inst, bt->h_slot_inst.data(), bt->h_slot_inst.size() * sizeof(int32_t));
+    memcpy(h + bt->tl.wg_pre, bt->h_wg_pre.data(), bt->h_wg_pre.size() * sizeof(int64_t));
+    if (bt->staging.submit(bt->d_tables, bt->tl.total, s) != hipSuccess) return EBC_E_DEVICE;
     if (ticks == 0) return EBC_OK;
     if (bt->graph_on) {
         if (!(bt->gexec && bt->g_ticks == ticks)) {

@@ -73,7 +73,8 @@ struct InstDesc {
     int64_t n, n_pad;
     int32_t d, k_pad, v_splits, nb;  // nb = n_pad / kBlock
     int32_t k;                       // greedy steps of this instance
-    int32_t dt, variant, pad0;
+    int32_t t0;                      // steps already done: a batched tick t runs step t0 + t
+    int32_t dt, variant;
     int64_t chunk;                   // ground-set chunk of the gains kernel
     int32_t* sel;
     double* f;
@@ -149,6 +150,66 @@ struct ebc_dataset {
 
 namespace ebc {
 
+// Device table block of a batched launch set: descriptors and block maps for
+// up to `slots` instances, contiguous, filled on the host in pinned memory
+// (double-buffered, each buffer guarded by an event) and copied in one
+// transfer per use.
+struct TableLayout {
+    size_t desc, row_pre, slot_inst, wg_pre, total;
+};
+inline TableLayout table_layout(int32_t slots) {
+    auto al = [](size_t v) { return (v + 255) & ~size_t(255); };
+    TableLayout L{};
+    size_t o = 0;
+    L.desc = o;
+    o = al(o + size_t(slots) * sizeof(InstDesc));
+    L.row_pre = o;
+    o = al(o + size_t(slots + 1) * sizeof(int64_t));
+    L.slot_inst = o;
+    o = al(o + size_t(slots) * sizeof(int32_t));
+    L.wg_pre = o;
+    o = al(o + size_t(2 * slots) * sizeof(int64_t));
+    L.total = o;
+    return L;
+}
+
+struct PinnedTables {
+    char* host[2] = {nullptr, nullptr};
+    hipEvent_t done[2] = {nullptr, nullptr};
+    int next = 0;
+    size_t bytes = 0;
+    hipError_t init(size_t b) {
+        bytes = b;
+        for (int i = 0; i < 2; ++i) {
+            hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&host[i]), b, hipHostMallocDefault);
+            if (e != hipSuccess) return e;
+            if ((e = hipEventCreateWithFlags(&done[i], hipEventDisableTiming)) != hipSuccess) return e;
+        }
+        return hipSuccess;
+    }
+    // a staging buffer whose previous copy has finished
+    char* acquire(hipError_t* e) {
+        *e = hipEventSynchronize(done[next]);
+        return host[next];
+    }
+    // copy the acquired buffer to `dev` on `s` and rotate
+    hipError_t submit(void* dev, size_t n, hipStream_t s) {
+        hipError_t e = hipMemcpyAsync(dev, host[next], n, hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipEventRecord(done[next], s);
+        next ^= 1;
+        return e;
+    }
+    ~PinnedTables() {
+        for (int i = 0; i < 2; ++i) {
+            if (done[i]) {
+                (void)hipEventSynchronize(done[i]);
+                (void)hipEventDestroy(done[i]);
+            }
+            if (host[i]) (void)hipHostFree(host[i]);
+        }
+    }
+};
+
 // Host helpers shared by the solo and batched paths.
 int64_t gains_chunk(const ebc_dataset* ds);
 int64_t gains_cand_tile(const ebc_dataset* ds);
@@ -184,6 +245,8 @@ hipError_t launch_gains_lp_batched(int32_t dt, int32_t kc, int32_t variant, cons
                                    int32_t t, hipStream_t s);
 hipError_t launch_gains_batched(int32_t bucket, const InstDesc* descs, const int32_t* slot_inst,
                                 const int64_t* wg_pre, int32_t slots, int64_t total_wgs, int32_t t, hipStream_t s);
+// Tile variant recorded by the autotuner for this dataset's key, or -1.
+int32_t tuned_variant(const ebc_dataset* ds);
 hipError_t launch_step_batched(const InstDesc* descs, const int64_t* row_pre, int32_t count, int64_t total_rows,
                                int32_t t, hipStream_t s);
 hipError_t launch_reset_batched(const InstDesc* descs, const int64_t* row_pre, int32_t count, int64_t total_rows,

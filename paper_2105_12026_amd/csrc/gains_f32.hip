@@ -212,7 +212,7 @@ kb_gains_f32(const InstDesc* __restrict__ descs, const int32_t* __restrict__ slo
              const int64_t* __restrict__ wg_pre, int32_t slots, int32_t t) {
     const int j = find_slot(wg_pre, slots, blockIdx.x);
     const InstDesc c = descs[slot_inst[j]];
-    if (t >= c.k) return;
+    if (c.t0 + t >= c.k) return;
     gains_f32_body<KP>(gains_args(c, nullptr, c.n_pad), int64_t(blockIdx.x) - wg_pre[j]);
 }
 

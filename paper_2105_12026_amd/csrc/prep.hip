@@ -50,9 +50,9 @@ void fill_desc(const ebc_dataset* ds, int32_t k, int32_t* sel, double* f, double
     c.v_splits = ds->v_splits;
     c.nb = int32_t(ds->n_pad / kBlock);
     c.k = k;
+    c.t0 = 0;
     c.dt = int32_t(ds->dt);
     c.variant = ds->variant;
-    c.pad0 = 0;
     c.chunk = gains_chunk(ds);
     c.sel = sel;
     c.f = f;
@@ -340,7 +340,8 @@ __global__ void __launch_bounds__(kBlock) k_reset(InstDesc c) { reset_body(c, bl
 __global__ void __launch_bounds__(kBlock)
 kb_reset(const InstDesc* __restrict__ descs, const int64_t* __restrict__ row_pre, int32_t count) {
     const int i = find_slot(row_pre, count, blockIdx.x);
-    reset_body(descs[i], int64_t(blockIdx.x) - row_pre[i]);
+    const InstDesc c = descs[i];
+    if (c.t0 == 0) reset_body(c, int64_t(blockIdx.x) - row_pre[i]);
 }
 
 hipError_t launch_reset_state(const ebc_dataset* ds, hipStream_t s) {

@@ -335,14 +335,14 @@ __global__ void __launch_bounds__(kBlock) k_update(InstDesc c) { update_body(c, 
 __global__ void __launch_bounds__(kBlock) k_fsum(InstDesc c, int32_t t) { fsum_body(c, t); }
 
 // ---- batched kernels: blocks of row_pre[i] .. row_pre[i+1] belong to instance i;
-// instances whose k is reached skip the step ----
+// tick t runs step t0 + t of each instance; instances whose k is reached skip ----
 #define EBC_ROW_KERNEL(NAME, BODY)                                                                     \
     __global__ void __launch_bounds__(kBlock)                                                          \
         NAME(const InstDesc* __restrict__ descs, const int64_t* __restrict__ row_pre, int32_t count,   \
              int32_t t) {                                                                              \
         const int i = find_slot(row_pre, count, blockIdx.x);                                           \
         const InstDesc c = descs[i];                                                                   \
-        if (t >= c.k) return;                                                                          \
+        if (c.t0 + t >= c.k) return;                                                                   \
         BODY(c, int64_t(blockIdx.x) - row_pre[i]);                                                     \
     }
 EBC_ROW_KERNEL(kb_gsum, gsum_body)
@@ -353,15 +353,15 @@ EBC_ROW_KERNEL(kb_update, update_body)
 
 __global__ void __launch_bounds__(kSelThreads) kb_wselect(const InstDesc* __restrict__ descs, int32_t t) {
     const InstDesc c = descs[blockIdx.x];
-    if (t < c.k) wselect_body(c);
+    if (c.t0 + t < c.k) wselect_body(c);
 }
 __global__ void __launch_bounds__(kBlock) kb_pick(const InstDesc* __restrict__ descs, int32_t t) {
     const InstDesc c = descs[blockIdx.x];
-    if (t < c.k) pick_body(c, t);
+    if (c.t0 + t < c.k) pick_body(c, c.t0 + t);
 }
 __global__ void __launch_bounds__(kBlock) kb_fsum(const InstDesc* __restrict__ descs, int32_t t) {
     const InstDesc c = descs[blockIdx.x];
-    if (t < c.k) fsum_body(c, t);
+    if (c.t0 + t < c.k) fsum_body(c, c.t0 + t);
 }
 
 hipError_t launch_greedy_step(const ebc_dataset* ds, int32_t t, int32_t* sel_out, double* f_out,

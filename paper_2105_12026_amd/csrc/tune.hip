@@ -47,6 +47,18 @@ hipError_t time_variant(ebc_dataset* ds, int32_t reps, hipStream_t s, float* ms)
 
 }  // namespace
 
+namespace ebc {
+
+// Tuned variant for this dataset's key, or -1 when the table has none (no timing).
+int32_t tuned_variant(const ebc_dataset* ds) {
+    std::lock_guard<std::mutex> lock(g_mu);
+    auto it = g_table.find(key_of(ds));
+    if (it == g_table.end() || it->second >= ebc_gains_variant_count(ds->dt)) return -1;
+    return it->second;
+}
+
+}  // namespace ebc
+
 extern "C" {
 
 ebc_status ebc_autotune(ebc_dataset* ds, int32_t reps, int32_t force, void* stream, int32_t* variant_out,

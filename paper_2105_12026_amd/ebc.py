@@ -11,9 +11,12 @@ from __future__ import annotations
 import ctypes
 import os
 
+import numpy as np
+
 import torch  # loads the process's HIP runtime before libebc.so binds to it
 
-__all__ = ["EBCError", "Dataset", "Batch", "lib", "status_string", "DTYPES", "LIB_PATH", "ABI_FUNCTIONS"]
+__all__ = ["EBCError", "Dataset", "Batch", "Server", "Arena", "request_bytes", "lib", "status_string", "DTYPES",
+           "LIB_PATH", "ABI_FUNCTIONS"]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libebc.so")
 DTYPES = {"f32": 0, "f16": 1, "bf16": 2, "fp8": 3}
@@ -23,8 +26,13 @@ ABI_FUNCTIONS = (
     "ebc_dataset_get_info", "ebc_profile_enable", "ebc_profile_read", "ebc_set_gains_variant",
     "ebc_gains_variant_count", "ebc_set_greedy_graph", "ebc_batch_bytes", "ebc_batch_create",
     "ebc_batch_destroy", "ebc_batch_set_graph", "ebc_greedy_batched", "ebc_batch_info", "ebc_autotune",
-    "ebc_tune_cache_load", "ebc_tune_cache_save", "ebc_tune_cache_size",
+    "ebc_tune_cache_load", "ebc_tune_cache_save", "ebc_tune_cache_size", "ebc_request_bytes",
+    "ebc_server_create", "ebc_server_destroy", "ebc_server_submit", "ebc_server_step", "ebc_server_poll",
+    "ebc_server_stats", "ebc_server_now", "ebc_arena_create", "ebc_arena_alloc", "ebc_arena_free",
+    "ebc_arena_free_bytes", "ebc_arena_largest_free", "ebc_arena_destroy",
 )
+_NON_STATUS = ("ebc_dataset_bytes", "ebc_status_string", "ebc_batch_bytes", "ebc_request_bytes", "ebc_server_now",
+               "ebc_arena_free_bytes", "ebc_arena_largest_free", "ebc_tune_cache_size")
 
 
 class EBCError(RuntimeError):
@@ -87,8 +95,28 @@ def lib() -> ctypes.CDLL:
         L.ebc_tune_cache_load.argtypes = [ctypes.c_char_p]
         L.ebc_tune_cache_save.argtypes = [ctypes.c_char_p]
         L.ebc_tune_cache_size.argtypes = []
+        L.ebc_request_bytes.argtypes = [i64, i32, i32, ctypes.c_int]
+        L.ebc_request_bytes.restype = ctypes.c_size_t
+        L.ebc_server_create.argtypes = [P, ctypes.c_size_t, i32, P, ctypes.POINTER(P)]
+        L.ebc_server_destroy.argtypes = [P]
+        L.ebc_server_submit.argtypes = [P, P, i64, i32, i32, ctypes.c_int, ctypes.c_double, ctypes.POINTER(i64)]
+        L.ebc_server_step.argtypes = [P, ctypes.POINTER(i32)]
+        dp = ctypes.POINTER(ctypes.c_double)
+        L.ebc_server_poll.argtypes = [P, i64, ctypes.POINTER(i32), P, P, P, dp, dp, dp]
+        L.ebc_server_stats.argtypes = [P, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i64),
+                                       ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_size_t)]
+        L.ebc_server_now.argtypes = []
+        L.ebc_server_now.restype = ctypes.c_double
+        L.ebc_arena_create.argtypes = [ctypes.c_size_t, ctypes.POINTER(P)]
+        L.ebc_arena_alloc.argtypes = [P, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]
+        L.ebc_arena_free.argtypes = [P, ctypes.c_size_t]
+        L.ebc_arena_free_bytes.argtypes = [P]
+        L.ebc_arena_free_bytes.restype = ctypes.c_size_t
+        L.ebc_arena_largest_free.argtypes = [P]
+        L.ebc_arena_largest_free.restype = ctypes.c_size_t
+        L.ebc_arena_destroy.argtypes = [P]
         for name in ABI_FUNCTIONS:
-            if name not in ("ebc_dataset_bytes", "ebc_status_string", "ebc_batch_bytes"):
+            if name not in _NON_STATUS:
                 getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -304,3 +332,126 @@ class Batch:
                                         ctypes.cast(f, ctypes.c_void_p), ctypes.cast(g, ctypes.c_void_p),
                                         _stream(stream)), "ebc_greedy_batched")
         return [(o[0][:k], o[1][:k], o[2][:k]) for o, k in zip(outs, ks)]
+
+
+def request_bytes(n: int, d: int, k: int, dtype: str = "bf16") -> int:
+    """Device bytes one serving request occupies in the arena (0 if invalid)."""
+    return int(lib().ebc_request_bytes(int(n), int(d), int(k), DTYPES[dtype]))
+
+
+class Arena:
+    """The serving core's first-fit allocator bookkeeping (host only)."""
+
+    def __init__(self, capacity: int):
+        h = ctypes.c_void_p()
+        _check(lib().ebc_arena_create(int(capacity), ctypes.byref(h)), "ebc_arena_create")
+        self._h = h
+
+    def alloc(self, nbytes: int):
+        """Offset of a new block of nbytes (rounded up to 256), or None when nothing fits."""
+        off = ctypes.c_size_t()
+        rc = lib().ebc_arena_alloc(self._h, int(nbytes), ctypes.byref(off))
+        if rc == 5:  # EBC_E_NOMEM
+            return None
+        _check(rc, "ebc_arena_alloc")
+        return int(off.value)
+
+    def free(self, offset: int):
+        _check(lib().ebc_arena_free(self._h, int(offset)), "ebc_arena_free")
+
+    @property
+    def free_bytes(self) -> int:
+        return int(lib().ebc_arena_free_bytes(self._h))
+
+    @property
+    def largest_free(self) -> int:
+        return int(lib().ebc_arena_largest_free(self._h))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().ebc_arena_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+SERVER_STATES = ("queued", "active", "done", "failed")
+
+
+class Server:
+    """Request loop with continuous batching at greedy-step granularity
+    (ebc_server_*). Requests live in one device arena of ``arena_bytes``,
+    admitted first-come first-served while a slot is free and their footprint
+    fits; each ``step()`` advances every active request by one greedy step."""
+
+    def __init__(self, arena_bytes: int, max_slots: int = 64, device="cuda", stream=None):
+        self.arena_bytes = int(arena_bytes)
+        self.max_slots = int(max_slots)
+        self.arena = torch.empty(self.arena_bytes, dtype=torch.uint8, device=device)
+        self._stream = stream
+        h = ctypes.c_void_p()
+        _check(lib().ebc_server_create(_ptr(self.arena), self.arena_bytes, self.max_slots, _stream(stream),
+                                       ctypes.byref(h)), "ebc_server_create")
+        self._h = h
+        self._k = {}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().ebc_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @staticmethod
+    def now() -> float:
+        return float(lib().ebc_server_now())
+
+    def submit(self, x, k: int, dtype: str = "bf16", t_arrival: float = -1.0) -> int:
+        """Queue a request (x: float32 host array [n, d], copied). Returns its id."""
+        x = np.ascontiguousarray(x, dtype=np.float32)
+        if x.ndim != 2:
+            raise ValueError("x must be [n, d]")
+        rid = ctypes.c_int64()
+        _check(lib().ebc_server_submit(self._h, ctypes.c_void_p(x.ctypes.data), x.shape[0], x.shape[1], int(k),
+                                       DTYPES[dtype], float(t_arrival), ctypes.byref(rid)), "ebc_server_submit")
+        self._k[rid.value] = int(k)
+        return int(rid.value)
+
+    def step(self) -> int:
+        """One scheduler tick; returns how many requests completed in it."""
+        c = ctypes.c_int32()
+        _check(lib().ebc_server_step(self._h, ctypes.byref(c)), "ebc_server_step")
+        return int(c.value)
+
+    def poll(self, rid: int) -> dict:
+        k = self._k[rid]
+        st = ctypes.c_int32()
+        sel = np.empty(k, np.int32)
+        f = np.empty(k, np.float64)
+        g = np.empty(k, np.float64)
+        ta, tb, tc = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        rc = lib().ebc_server_poll(self._h, int(rid), ctypes.byref(st), ctypes.c_void_p(sel.ctypes.data),
+                                   ctypes.c_void_p(f.ctypes.data), ctypes.c_void_p(g.ctypes.data), ctypes.byref(ta),
+                                   ctypes.byref(tb), ctypes.byref(tc))
+        out = {"state": SERVER_STATES[st.value], "status": int(rc), "t_arrive": ta.value, "t_admit": tb.value,
+               "t_done": tc.value}
+        if st.value == 2:
+            out.update(sel=sel, f=f, gain=g)
+        return out
+
+    def stats(self) -> dict:
+        q, a = ctypes.c_int32(), ctypes.c_int32()
+        c, t = ctypes.c_int64(), ctypes.c_int64()
+        fb = ctypes.c_size_t()
+        _check(lib().ebc_server_stats(self._h, ctypes.byref(q), ctypes.byref(a), ctypes.byref(c), ctypes.byref(t),
+                                      ctypes.byref(fb)), "ebc_server_stats")
+        return {"queued": q.value, "active": a.value, "completed": c.value, "ticks": t.value,
+                "free_bytes": int(fb.value)}

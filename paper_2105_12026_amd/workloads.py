@@ -28,6 +28,7 @@ __all__ = [
     "precision_sweep",
     "batched_instances",
     "serving_requests",
+    "poisson_arrivals",
     "sha256_of",
 ]
 
@@ -164,3 +165,13 @@ def serving_requests(seed: int = 5, count: int = 2000, n_lo: int = 5000, n_hi: i
         x = process_curves(rng, n, d).astype(np.float32) if materialize else None
         reqs.append(Problem(x=x, k=k, name=f"req{i}", meta={"seed": [seed, i], "n": n}))
     return reqs
+
+
+def poisson_arrivals(seed: int, rate: float, count: int) -> np.ndarray:
+    """Arrival offsets (seconds from the start) of a Poisson stream of
+    ``count`` requests at ``rate`` per second: cumulative sums of i.i.d.
+    exponential gaps of mean 1/rate, drawn from default_rng([seed, 7])."""
+    if rate <= 0:
+        raise ValueError("rate must be positive")
+    rng = np.random.default_rng([seed, 7])
+    return np.cumsum(rng.exponential(1.0 / rate, count))
