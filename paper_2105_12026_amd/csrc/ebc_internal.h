@@ -245,6 +245,11 @@ hipError_t launch_gains_lp_batched(int32_t dt, int32_t kc, int32_t variant, cons
                                    int32_t t, hipStream_t s);
 hipError_t launch_gains_batched(int32_t bucket, const InstDesc* descs, const int32_t* slot_inst,
                                 const int64_t* wg_pre, int32_t slots, int64_t total_wgs, int32_t t, hipStream_t s);
+// 32-row candidate blocks per wave in the ping-pong gains variant (3):
+// two where the registers allow, one for long rows.
+constexpr int pp_blocks(int dt, int kc) {
+    return dt == EBC_DT_FP8_E4M3 ? (kc <= 1 ? 2 : 1) : (kc <= 6 ? 2 : 1);
+}
 // Tile variant recorded by the autotuner for this dataset's key, or -1.
 int32_t tuned_variant(const ebc_dataset* ds);
 hipError_t launch_step_batched(const InstDesc* descs, const int64_t* row_pre, int32_t count, int64_t total_rows,

@@ -257,21 +257,83 @@ __device__ __forceinline__ void lp_tile_pipe(int64_t t, int64_t nt, int64_t t_be
     }
 }
 
+// Candidate rows of one wave (A operand, 32*CB rows), their E8M0 scales and
+// the constant accumulator tiles -hn_c, in registers.
+template <class G, int DT, int CB>
+__device__ __forceinline__ void load_candidates(const GainsArgs& ga, int64_t wbase, int col, int half,
+                                                uint4 (&a)[CB][G::HU], floatx16 (&cinit)[CB], int (&sa)[CB]) {
+    constexpr int HU = G::HU, RU = G::RU, VT = G::VT;
+    const uint4* __restrict__ xqt = static_cast<const uint4*>(ga.xq);
+    const int32_t* __restrict__ cand = ga.cand;
+    const int64_t n_cand = ga.n_cand, n_pad = ga.n_pad;
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb) {
+        const int64_t cpos = wbase + cb * 32 + col;
+        int64_t crow = -1;
+        if (cpos < n_cand) crow = cand ? int64_t(cand[cpos]) : cpos;
+        if (crow >= n_pad || (cpos < n_cand && crow < 0)) {
+            atomicCAS(ga.err, 0, kDevErrIndex);
+            crow = -1;
+        }
+        if (crow >= 0) {
+            const uint4* src = xqt + (crow / VT) * (RU * VT) + (crow % VT);
+#pragma unroll
+            for (int u = 0; u < HU; ++u) a[cb][u] = src[(half * HU + u) * VT];
+            sa[cb] = G::kFp8 ? ga.scale[crow] : 127;
+        } else {
+#pragma unroll
+            for (int u = 0; u < HU; ++u) a[cb][u] = make_uint4(0, 0, 0, 0);
+            sa[cb] = 127;
+        }
+        // the lane holds result rows 8*(r/4) + 4*half + r%4 of this block
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int64_t p = wbase + cb * 32 + 8 * (r / 4) + 4 * half + (r % 4);
+            float v = 0.0f;
+            if (p < n_cand) {
+                const int64_t row = cand ? int64_t(cand[p]) : p;
+                if (row >= 0 && row < n_pad) v = ga.hn[row];
+            }
+            cinit[cb][r] = -v;
+        }
+    }
+}
+
+// float64 sums over the 32 columns of each half; one lane per row writes.
+// Each lane first removes the lower bounds of its own columns (its sum of
+// -ha_v), then the sum runs over the columns.
+template <int CB>
+__device__ __forceinline__ void store_partials(const GainsArgs& ga, int64_t wbase, int split, int col, int half,
+                                               const float (&acc_sum)[CB][16], double lo_sum) {
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb) {
+        double mine = 0.0;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            double v = double(acc_sum[cb][r]) - lo_sum;
+#pragma unroll
+            for (int off = 16; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+            if (col == r) mine = v;
+        }
+        if (col < 16) {
+            const int r = col;
+            const int64_t p = wbase + cb * 32 + 8 * (r / 4) + 4 * half + (r % 4);
+            if (p < ga.n_cand) ga.part[int64_t(split) * ga.part_stride + p] = 2.0 * mine;
+        }
+    }
+}
+
 template <int DT, int KC, int CB, bool PIPE>
 __device__ __forceinline__ void gains_lp_body(const GainsArgs& ga, int64_t bid) {
     const uint4* __restrict__ xqt = static_cast<const uint4*>(ga.xq);
-    const float* __restrict__ hn = ga.hn;
     const float* __restrict__ ha = ga.ha;
     const float* __restrict__ hm = ga.hm;
     const int* __restrict__ sc = ga.scale;
-    const int32_t* __restrict__ cand = ga.cand;
-    const int64_t n_cand = ga.n_cand, n_pad = ga.n_pad, chunk = ga.chunk, part_stride = ga.part_stride;
+    const int64_t n_pad = ga.n_pad, chunk = ga.chunk;
     const int32_t v_splits = ga.v_splits;
-    double* __restrict__ part = ga.part;
-    int* __restrict__ err = ga.err;
     using G = LpGeom<DT, KC, CB>;
     using T = Lp<DT>;
-    constexpr int RU = G::RU, HU = G::HU, VT = G::VT;
+    constexpr int HU = G::HU, VT = G::VT;
     static_assert(HU == KC * T::kU4, "lane half-row must hold KC chunks");
 
     __shared__ uint4 lds0[G::STAGE];
@@ -291,37 +353,7 @@ __device__ __forceinline__ void gains_lp_body(const GainsArgs& ga, int64_t bid) 
     uint4 a[CB][HU];
     floatx16 cinit[CB];
     int sa[CB];
-#pragma unroll
-    for (int cb = 0; cb < CB; ++cb) {
-        const int64_t cpos = wbase + cb * 32 + col;
-        int64_t crow = -1;
-        if (cpos < n_cand) crow = cand ? int64_t(cand[cpos]) : cpos;
-        if (crow >= n_pad || (cpos < n_cand && crow < 0)) {
-            atomicCAS(err, 0, kDevErrIndex);
-            crow = -1;
-        }
-        if (crow >= 0) {
-            const uint4* src = xqt + (crow / VT) * (RU * VT) + (crow % VT);
-#pragma unroll
-            for (int u = 0; u < HU; ++u) a[cb][u] = src[(half * HU + u) * VT];
-            sa[cb] = G::kFp8 ? sc[crow] : 127;
-        } else {
-#pragma unroll
-            for (int u = 0; u < HU; ++u) a[cb][u] = make_uint4(0, 0, 0, 0);
-            sa[cb] = 127;
-        }
-        // the lane holds result rows 8*(r/4) + 4*half + r%4 of this block
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const int64_t p = wbase + cb * 32 + 8 * (r / 4) + 4 * half + (r % 4);
-            float v = 0.0f;
-            if (p < n_cand) {
-                const int64_t row = cand ? int64_t(cand[p]) : p;
-                if (row >= 0 && row < n_pad) v = hn[row];
-            }
-            cinit[cb][r] = -v;
-        }
-    }
+    load_candidates<G, DT, CB>(ga, wbase, col, half, a, cinit, sa);
     float acc_sum[CB][16];
 #pragma unroll
     for (int cb = 0; cb < CB; ++cb)
@@ -374,25 +406,236 @@ __device__ __forceinline__ void gains_lp_body(const GainsArgs& ga, int64_t bid) 
         }
     }
 
-    // ---- float64 sums over the 32 columns of each half; one lane per row writes ----
-    // each lane removes the lower bounds of its own columns (sum of -ha_v)
-    // before the sum over the columns
+    store_partials<CB>(ga, wbase, split, col, half, acc_sum, lo_sum);
+}
+
+// ---------------------------------------------------------------------------
+// Ping-pong variant: 8 waves, two per SIMD. At d = 64 in BF16 the epilogue
+// (one med3 and one add per pair, 4 cycles per wave instruction) costs as
+// many cycles as the matrix instructions, and a single wave cannot keep
+// both busy because its epilogue depends on its own MFMA results. Here the
+// two waves of a SIMD belong to two groups that run half a period apart:
+// while one group issues the matrix instructions of tile t, the other clamps
+// and sums its tile t-1, and a workgroup barrier swaps the roles. Both groups
+// read the same LDS tiles (so one tile copy now feeds 256 or more
+// candidates), only the leading group issues the copies, and each group
+// prefetches the next tile's operands into registers during its epilogue
+// phase. Per-lane sums run in the same order as in the other variants, so
+// the gains are bitwise identical.
+// ---------------------------------------------------------------------------
+template <class G>
+struct TileRegs {
+    static constexpr int NCB = G::VT / 32;
+    uint4 b[NCB][G::HU];
+    float ha[NCB], hm[NCB];  // raw, so that no instruction waits for these reads before the next phase
+    int sb[NCB];
+};
+
+template <class G>
+__device__ __forceinline__ void read_tile(const uint4* st, int col, int half, TileRegs<G>& r) {
+    const float* st_ha = reinterpret_cast<const float*>(st + G::OFF_HA);
+    const float* st_hm = reinterpret_cast<const float*>(st + G::OFF_HM);
+    const int* st_sc = reinterpret_cast<const int*>(st + G::OFF_SC);
 #pragma unroll
-    for (int cb = 0; cb < CB; ++cb) {
-        double mine = 0.0;
+    for (int colb = 0; colb < TileRegs<G>::NCB; ++colb) {
+        const int vrow = colb * 32 + col;
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            double v = double(acc_sum[cb][r]) - lo_sum;
+        for (int u = 0; u < G::HU; ++u) r.b[colb][u] = st[(half * G::HU + u) * G::VT + vrow];
+        r.ha[colb] = st_ha[vrow];
+        r.hm[colb] = st_hm[vrow];
+        r.sb[colb] = G::kFp8 ? st_sc[vrow] : 127;
+    }
+}
+
+template <class G, int DT, int KC, int CB>
+__device__ __forceinline__ void mfma_tile(const TileRegs<G>& r, const uint4 (&a)[CB][G::HU],
+                                          const floatx16 (&cinit)[CB], const int (&sa)[CB],
+                                          floatx16 (&acc)[TileRegs<G>::NCB][CB]) {
+    using T = Lp<DT>;
 #pragma unroll
-            for (int off = 16; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-            if (col == r) mine = v;
+    for (int colb = 0; colb < TileRegs<G>::NCB; ++colb) {
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) acc[colb][cb] = cinit[cb];
+#pragma unroll
+        for (int q = 0; q < KC; ++q)
+#pragma unroll
+            for (int cb = 0; cb < CB; ++cb)
+                acc[colb][cb] =
+                    mfma_main<DT>(&a[cb][q * T::kU4], &r.b[colb][q * T::kU4], acc[colb][cb], sa[cb], r.sb[colb]);
+    }
+}
+
+template <int NCB, int CB>
+__device__ __forceinline__ void epilogue_tile(const floatx16 (&acc)[NCB][CB], const float (&lo)[NCB],
+                                              const float (&hi)[NCB], float (&acc_sum)[CB][16], double& lo_sum) {
+#pragma unroll
+    for (int colb = 0; colb < NCB; ++colb) {
+        lo_sum += double(lo[colb]);
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc_sum[cb][r] += __builtin_amdgcn_fmed3f(acc[colb][cb][r], lo[colb], hi[colb]);
+    }
+}
+
+// Phase boundary: no instruction is scheduled across it, LDS reads drained,
+// workgroup barrier.
+__device__ __forceinline__ void phase_barrier() {
+    __builtin_amdgcn_sched_barrier(0);
+    ring_barrier();
+    __builtin_amdgcn_sched_barrier(0);
+}
+
+// Leading group, tile t: phase 2t (copies of tile t+2, matrix work of tile
+// t), phase 2t+1 (operands of tile t+1, epilogue of tile t).
+template <class G, int DT, int KC, int CB>
+__device__ __forceinline__ void pp_lead(int64_t t, int64_t nt, int64_t t_begin, int wave, int lane, int col, int half,
+                                        const uint4* __restrict__ xqt, const float* __restrict__ ha,
+                                        const float* __restrict__ hm, const int* __restrict__ sc, const uint4* nxt,
+                                        uint4* nx2, TileRegs<G>& r, const uint4 (&a)[CB][G::HU],
+                                        const floatx16 (&cinit)[CB], const int (&sa)[CB], float (&acc_sum)[CB][16],
+                                        double& lo_sum) {
+    constexpr int NCB = TileRegs<G>::NCB;
+    if (t + 2 < nt) copy_stage<G>(wave, lane, t_begin + t + 2, xqt, ha, hm, sc, nx2);
+    floatx16 acc[NCB][CB];
+    __builtin_amdgcn_s_setprio(1);
+    mfma_tile<G, DT, KC, CB>(r, a, cinit, sa, acc);
+    __builtin_amdgcn_s_setprio(0);
+    float lo[NCB], hi[NCB];
+#pragma unroll
+    for (int c = 0; c < NCB; ++c) {
+        lo[c] = -r.ha[c];
+        hi[c] = r.hm[c] - r.ha[c];
+    }
+    // this wave's copies of tile t+1 have landed (those of t+2 may still fly)
+    if (t + 1 < nt) {
+        if (t + 2 < nt)
+            wait_vmcnt<G::L>();
+        else
+            wait_vmcnt<0>();
+    }
+    phase_barrier();
+    if (t + 1 < nt) read_tile<G>(nxt, col, half, r);
+    epilogue_tile<NCB, CB>(acc, lo, hi, acc_sum, lo_sum);
+    phase_barrier();
+}
+
+// Following group, tile t: phase 2t+1 (matrix work of tile t), phase 2t+2
+// (operands of tile t+1, epilogue of tile t; no barrier after the last).
+template <class G, int DT, int KC, int CB>
+__device__ __forceinline__ void pp_follow(int64_t t, int64_t nt, int col, int half, const uint4* nxt, TileRegs<G>& r,
+                                          const uint4 (&a)[CB][G::HU], const floatx16 (&cinit)[CB],
+                                          const int (&sa)[CB], float (&acc_sum)[CB][16], double& lo_sum) {
+    constexpr int NCB = TileRegs<G>::NCB;
+    floatx16 acc[NCB][CB];
+    __builtin_amdgcn_s_setprio(1);
+    mfma_tile<G, DT, KC, CB>(r, a, cinit, sa, acc);
+    __builtin_amdgcn_s_setprio(0);
+    float lo[NCB], hi[NCB];
+#pragma unroll
+    for (int c = 0; c < NCB; ++c) {
+        lo[c] = -r.ha[c];
+        hi[c] = r.hm[c] - r.ha[c];
+    }
+    phase_barrier();
+    if (t + 1 < nt) read_tile<G>(nxt, col, half, r);
+    epilogue_tile<NCB, CB>(acc, lo, hi, acc_sum, lo_sum);
+    if (t + 1 < nt) phase_barrier();
+}
+
+template <int DT, int KC, int CB>
+__device__ __forceinline__ void gains_lp_pp_body(const GainsArgs& ga, int64_t bid) {
+    const uint4* __restrict__ xqt = static_cast<const uint4*>(ga.xq);
+    const float* __restrict__ ha = ga.ha;
+    const float* __restrict__ hm = ga.hm;
+    const int* __restrict__ sc = ga.scale;
+    using G = LpGeom<DT, KC, CB>;
+    using T = Lp<DT>;
+    constexpr int HU = G::HU, VT = G::VT;
+    static_assert(HU == KC * T::kU4, "lane half-row must hold KC chunks");
+
+    __shared__ uint4 lds0[G::STAGE];
+    __shared__ uint4 lds1[G::STAGE];
+    __shared__ uint4 lds2[G::STAGE];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // 0..7, uniform per wave
+    const int grp = wave >> 2;                                   // waves w and w+4 share a SIMD
+    const int col = lane & 31;
+    const int half = lane >> 5;
+    const int split = int(bid % ga.v_splits);
+    const int64_t ctile = bid / ga.v_splits;
+    const int64_t wbase = ctile * (2 * G::CAND_TILE) + int64_t(wave) * (32 * CB);
+
+    uint4 a[CB][HU];
+    floatx16 cinit[CB];
+    int sa[CB];
+    load_candidates<G, DT, CB>(ga, wbase, col, half, a, cinit, sa);
+    float acc_sum[CB][16];
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc_sum[cb][r] = 0.0f;
+    double lo_sum = 0.0;
+
+    const int64_t v_begin = int64_t(split) * ga.chunk;
+    int64_t v_end = v_begin + ga.chunk;
+    if (v_end > ga.n_pad) v_end = ga.n_pad;
+    const int64_t t_begin = v_begin / VT;
+    const int64_t nt = v_end > v_begin ? (v_end - v_begin) / VT : 0;
+
+    TileRegs<G> r;
+    if (grp == 0) {
+        // leading group: issues every copy; barriers B0 + 2 per tile
+        const int w4 = wave & 3;
+        if (nt > 0) copy_stage<G>(w4, lane, t_begin, xqt, ha, hm, sc, lds0);
+        if (nt > 1) copy_stage<G>(w4, lane, t_begin + 1, xqt, ha, hm, sc, lds1);
+        if (nt > 1)
+            wait_vmcnt<G::L>();
+        else
+            wait_vmcnt<0>();
+        phase_barrier();  // B0: tile 0 in LDS
+        if (nt > 0) read_tile<G>(lds0, col, half, r);
+        for (int64_t t = 0; t < nt; t += 3) {
+            pp_lead<G, DT, KC, CB>(t, nt, t_begin, w4, lane, col, half, xqt, ha, hm, sc, lds1, lds2, r, a, cinit, sa,
+                                   acc_sum, lo_sum);
+            if (t + 1 < nt)
+                pp_lead<G, DT, KC, CB>(t + 1, nt, t_begin, w4, lane, col, half, xqt, ha, hm, sc, lds2, lds0, r, a,
+                                       cinit, sa, acc_sum, lo_sum);
+            if (t + 2 < nt)
+                pp_lead<G, DT, KC, CB>(t + 2, nt, t_begin, w4, lane, col, half, xqt, ha, hm, sc, lds0, lds1, r, a,
+                                       cinit, sa, acc_sum, lo_sum);
         }
-        if (col < 16) {
-            const int r = col;
-            const int64_t p = wbase + cb * 32 + 8 * (r / 4) + 4 * half + (r % 4);
-            if (p < n_cand) part[int64_t(split) * part_stride + p] = 2.0 * mine;
+    } else {
+        // following group, one phase behind: barriers B0 + 1 + 2 per tile - 1
+        phase_barrier();  // B0
+        if (nt > 0) {
+            read_tile<G>(lds0, col, half, r);
+            phase_barrier();  // end of phase 0 (the leading group's first matrix phase)
+            for (int64_t t = 0; t < nt; t += 3) {
+                pp_follow<G, DT, KC, CB>(t, nt, col, half, lds1, r, a, cinit, sa, acc_sum, lo_sum);
+                if (t + 1 < nt) pp_follow<G, DT, KC, CB>(t + 1, nt, col, half, lds2, r, a, cinit, sa, acc_sum, lo_sum);
+                if (t + 2 < nt) pp_follow<G, DT, KC, CB>(t + 2, nt, col, half, lds0, r, a, cinit, sa, acc_sum, lo_sum);
+            }
         }
     }
+    store_partials<CB>(ga, wbase, split, col, half, acc_sum, lo_sum);
+}
+
+template <int DT, int KC, int CB>
+__global__ void __launch_bounds__(512) k_gains_lp_pp(GainsArgs ga) {
+    gains_lp_pp_body<DT, KC, CB>(ga, blockIdx.x);
+}
+
+template <int DT, int KC, int CB>
+__global__ void __launch_bounds__(512)
+kb_gains_lp_pp(const InstDesc* __restrict__ descs, const int32_t* __restrict__ slot_inst,
+               const int64_t* __restrict__ wg_pre, int32_t slots, int32_t t) {
+    const int j = find_slot(wg_pre, slots, blockIdx.x);
+    const InstDesc c = descs[slot_inst[j]];
+    if (c.t0 + t >= c.k) return;
+    gains_lp_pp_body<DT, KC, CB>(gains_args(c, nullptr, c.n_pad), int64_t(blockIdx.x) - wg_pre[j]);
 }
 
 template <int DT, int KC, int CB, bool PIPE>
@@ -422,13 +665,25 @@ static void launch_lp_v(const ebc_dataset* ds, const int32_t* cand, int64_t n_ca
                        gains_args(c, cand, n_cand));
 }
 
-// Variants: (32-row candidate blocks per wave, software-pipelined epilogue):
-// 0 = (2, no), 1 = (4, no), 2 = (2, yes).
+template <int DT, int KC, int CB>
+static void launch_lp_pp(const ebc_dataset* ds, const int32_t* cand, int64_t n_cand, hipStream_t s) {
+    using G = LpGeom<DT, KC, CB>;
+    const int64_t tiles = (n_cand + 2 * G::CAND_TILE - 1) / (2 * G::CAND_TILE);
+    InstDesc c;
+    fill_desc(ds, 0, nullptr, nullptr, nullptr, &c);
+    hipLaunchKernelGGL((k_gains_lp_pp<DT, KC, CB>), dim3(unsigned(tiles * ds->v_splits)), dim3(512), 0, s,
+                       gains_args(c, cand, n_cand));
+}
+
+// Variants: 4 waves with (32-row candidate blocks per wave, software-pipelined
+// epilogue) 0 = (2, no), 1 = (4, no), 2 = (2, yes); 3 = ping-pong, 8 waves
+// with pp_blocks(DT, KC) blocks each.
 template <int DT, int KC>
 static void launch_lp(const ebc_dataset* ds, const int32_t* cand, int64_t n_cand, hipStream_t s) {
     switch (ds->variant) {
         case 1: launch_lp_v<DT, KC, 4, false>(ds, cand, n_cand, s); break;
         case 2: launch_lp_v<DT, KC, 2, true>(ds, cand, n_cand, s); break;
+        case 3: launch_lp_pp<DT, KC, pp_blocks(DT, KC)>(ds, cand, n_cand, s); break;
         default: launch_lp_v<DT, KC, 2, false>(ds, cand, n_cand, s); break;
     }
 }
@@ -481,6 +736,10 @@ static void launch_lp_b(int32_t variant, const InstDesc* descs, const int32_t* s
     switch (variant) {
         case 1: hipLaunchKernelGGL((kb_gains_lp<DT, KC, 4, false>), g, b, 0, s, descs, slot_inst, wg_pre, slots, t); break;
         case 2: hipLaunchKernelGGL((kb_gains_lp<DT, KC, 2, true>), g, b, 0, s, descs, slot_inst, wg_pre, slots, t); break;
+        case 3:
+            hipLaunchKernelGGL((kb_gains_lp_pp<DT, KC, pp_blocks(DT, KC)>), g, dim3(512), 0, s, descs, slot_inst, wg_pre,
+                               slots, t);
+            break;
         default: hipLaunchKernelGGL((kb_gains_lp<DT, KC, 2, false>), g, b, 0, s, descs, slot_inst, wg_pre, slots, t); break;
     }
 }

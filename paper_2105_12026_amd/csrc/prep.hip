@@ -32,7 +32,12 @@ int64_t gains_chunk(const ebc_dataset* ds) {
 
 int64_t gains_cand_tile(const ebc_dataset* ds) {
     if (ds->dt == EBC_DT_F32) return kGainsCandTile;
-    return ds->variant == 1 ? 512 : 256;  // 4 waves x 32 rows x (4 or 2) blocks
+    // variant 1: 4 waves x 32 rows x 4 blocks; 3: 8 waves x 32 x pp_blocks; else 4 x 32 x 2
+    if (ds->variant == 3) {
+        const int kc = ds->k_pad / (ds->dt == EBC_DT_FP8_E4M3 ? 64 : 16);
+        return 8 * 32 * pp_blocks(ds->dt, kc);
+    }
+    return ds->variant == 1 ? 512 : 256;
 }
 
 int32_t gains_bucket(const ebc_dataset* ds) {

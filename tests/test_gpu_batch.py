@@ -11,7 +11,8 @@ pytestmark = pytest.mark.gpu
 
 # (n, d, dtype, variant, k)
 MIX = [(300, 16, "f32", 0, 5), (1000, 100, "bf16", 0, 7), (2500, 64, "bf16", 2, 12), (700, 5, "fp8", 0, 3),
-       (1500, 33, "f16", 1, 0), (4000, 128, "f32", 0, 9), (257, 64, "bf16", 0, 4), (2049, 64, "fp8", 2, 6)]
+       (1500, 33, "f16", 1, 0), (4000, 128, "f32", 0, 9), (257, 64, "bf16", 0, 4), (2049, 64, "fp8", 2, 6),
+       (3100, 64, "bf16", 3, 8), (1800, 128, "fp8", 3, 5), (2300, 112, "f16", 3, 6)]
 
 
 @pytest.fixture(scope="module")

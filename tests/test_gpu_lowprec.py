@@ -111,3 +111,35 @@ def test_lowprec_full_size_gains_sampled(env, ref, sweep200k, dt):
         errs.append(float(np.max(np.abs(g[cand] - rg)) / scale))
     print(f"[gpu-result] full-size gains {dt} rel err {max(errs):.3e}", flush=True)
     assert max(errs) <= GAIN_TOL[dt]
+
+
+@pytest.mark.parametrize("dt", ["bf16", "f16", "fp8"])
+@pytest.mark.parametrize("n,d,seed", [(5, 3, 21), (700, 33, 22), (2049, 64, 23), (5000, 64, 24), (1300, 100, 25),
+                                      (900, 128, 26)])
+def test_every_variant_matches_oracle_and_variant0(env, ref, dt, n, d, seed):
+    """All tile variants (including the 8-wave ping-pong one, with one or two
+    candidate blocks per wave) give bitwise-equal gains, for all candidates
+    and for an unordered candidate list with repeats, within the oracle bar."""
+    torch, ebc = env
+    rng = np.random.default_rng(seed)
+    x = W.gaussian_mixture(rng, n, d, 6).astype(np.float32)
+    ds = _ds(env, x, dt)
+    s = list(rng.choice(n, min(n, 3), replace=False))
+    m = ref.min_dist(x, s)
+    mt = torch.from_numpy(m)
+    cand = rng.integers(0, n, size=max(1, (3 * n) // 5)).astype(np.int32)
+    rg_all = ref.gains(x, m)
+    base = None
+    for v in range(ebc.Dataset.variant_count(dt)):
+        print(f"[gpu-case] gains variant {v} {dt} n={n} d={d}", flush=True)
+        ds.set_variant(v)
+        g_all = ds.marginal_gains(m=mt).cpu().numpy()
+        g_c = ds.marginal_gains(m=mt, cand=torch.from_numpy(cand)).cpu().numpy()
+        ds.sync()
+        err = float(np.max(np.abs(g_all - rg_all)) / np.max(np.abs(rg_all)))
+        assert err <= GAIN_TOL[dt], (v, err)
+        np.testing.assert_array_equal(g_c, g_all[cand])
+        if base is None:
+            base = g_all
+        else:
+            np.testing.assert_array_equal(g_all, base, err_msg=f"variant {v}")
