@@ -34,6 +34,7 @@ WORKLOADS = {
     "normal_n1000_d16_k5": ("small_normal", {"seed": 0}),
     "batched512_bf16_k20": ("batched_instances", {"seed": 4}),
     "serving_curves_d64_bf16": ("serving_requests", {"seed": 5}),
+    "paper_sets_n50000_l5000_k10_d100": ("paper_sets", {"seed": 6}),
 }
 
 
@@ -206,6 +207,75 @@ def bench_serving(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_sets(args):
+    """Multi-set evaluation (ebc_eval_sets) in the shape of the paper's runtime
+    sweep: |V| = 50000 N(0,1) points in d = 100, l = 5000 random sets of 10.
+    One step = one ebc_eval_sets call over all l sets (inputs resident).
+    Metric: (set member, point) pairs per second, l * k_set * |V| per call."""
+    import numpy as np
+    import torch
+
+    from paper_2105_12026_amd import ebc, workloads
+
+    kw = {}
+    for part in (args.sets_shape or "").split(","):
+        if part:
+            key, val = part.split("=")
+            kw[key] = int(val)
+    p = workloads.paper_sets(seed=6, **kw)
+    n, d = p.n, p.d
+    l = len(p.offsets) - 1
+    nnz = int(p.offsets[-1])
+    dev = torch.device("cuda:0")
+    ds = ebc.Dataset(torch.from_numpy(p.x).to(dev), dtype="f32")
+    off = torch.from_numpy(p.offsets).to(dev)
+    idx = torch.from_numpy(p.idx).to(dev)
+    out = torch.empty(l, dtype=torch.float64, device=dev)
+    for _ in range(args.warmup):
+        ds.eval_sets(off, idx, out=out)
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(args.steps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        ds.eval_sets(off, idx, out=out)
+        e1.record()
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+    ds.sync()
+    ms = float(np.median(times))
+    pairs = float(nnz) * n
+    achieved = 2.0 * d * pairs / (ms * 1e-3) / 1e12
+    res = {
+        "metric": "set-member x point distance evals/s (ebc_eval_sets, all sets)",
+        "value": pairs / (ms * 1e-3), "unit": "pair-evals/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": p.name, "n": n, "d": d, "sets": l, "set_size": nnz // max(l, 1),
+                   "ms_min": float(np.min(times)), "ms_max": float(np.max(times)),
+                   "step": "one ebc_eval_sets call over all sets"},
+        "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_TFLOPS["f32"], "unit": "TFLOP/s",
+                     "frac": round(achieved / PEAK_TFLOPS["f32"], 4), "traffic": None,
+                     "kernel": "whole ebc_eval_sets call, algorithmic 2*d flops per (member, point) pair"},
+    }
+    if not args.no_cpu_baseline:
+        from oracle import build_ref, ref
+        if not os.path.exists(build_ref.LIB):
+            build_ref.build()
+        ns = 8
+        while True:
+            t0 = time.perf_counter()
+            ref.eval_sets(p.x, p.offsets[:ns + 1], p.idx[:int(p.offsets[ns])])
+            dt = time.perf_counter() - t0
+            if dt >= 8.0 or ns >= l:
+                break
+            ns = min(l, max(ns * 2, int(ns * 10.0 / max(dt, 1e-3))))
+        res["cpu_baseline"] = {"value": float(p.offsets[ns]) * n / dt, "unit": "pair-evals/s",
+                               "cores": ref.threads(), "kind": "oracle",
+                               "sample": f"float64 f of the first {ns} sets ({dt:.1f} s)"}
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -217,6 +287,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 256 MiB device copy (reference for HBM byte counters)")
+    ap.add_argument("--sets-shape", default="", help="paper_sets overrides, e.g. n=50000,l=5000,set_size=10")
     ap.add_argument("--serving-pool", type=int, default=24, help="distinct requests the serving stream cycles")
     ap.add_argument("--serving-requests", type=int, default=150, help="requests per arrival rate")
     ap.add_argument("--serving-slots", type=int, default=64)
@@ -232,6 +303,9 @@ def main():
         return
     if args.workload.startswith("serving"):
         bench_serving(args)
+        return
+    if args.workload.startswith("paper_sets"):
+        bench_sets(args)
         return
 
     import numpy as np

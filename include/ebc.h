@@ -111,11 +111,16 @@ EBC_API ebc_status ebc_dataset_destroy(ebc_dataset* ds);
  * per set; Alg. 2 computes the same per-(set, point) minima).
  *   offsets [device] int64 [l+1], offsets[0] = 0, non-decreasing.
  *   idx     [device] int32 [offsets[l]]; set j = idx[offsets[j] .. offsets[j+1]).
- *           Indices are rows of V. Empty sets (f = 0) and repeats are allowed.
+ *           Indices are rows of V. Sets of any size; empty sets (f = 0) and
+ *           repeats are allowed.
  *   f_out   [device] float64 [l].
- * Distances are float32 direct differences; each per-point term and every
- * sum is float64. A bad index or offsets make that set's f NaN and raise
- * EBC_E_INDEX. l = 0 is a no-op. */
+ * Uses f(S) = (2/|V|) sum_v max(0, max_{s in S} (v.s - ||s||^2/2)) (the e0 = 0
+ * term folded in): float32 dot products of the caller's float32 rows on the
+ * matrix cores whatever the dataset's distance dtype, float32 maxima, float64
+ * sums. A bad index or offsets make that set's f NaN and raise EBC_E_INDEX.
+ * Scratch of about (9 + 8 * min(8, n/256)) * l bytes is taken from the
+ * stream-ordered allocator (hipMallocAsync) and freed on the same stream.
+ * l = 0 is a no-op. */
 EBC_API ebc_status ebc_eval_sets(ebc_dataset* ds, const int64_t* offsets, const int32_t* idx, int64_t l,
                          double* f_out, void* stream);
 

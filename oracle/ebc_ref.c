@@ -154,3 +154,150 @@ int ebc_ref_greedy(const float* x, int64_t n, int32_t d, int32_t k, int32_t* sel
     free(m); free(gv); free(chosen);
     return 0;
 }
+
+/* ---- Lazy evaluation of the same greedy (Minoux's accelerated greedy) ----
+ * Same selections, f and gains as ebc_ref_greedy, computed by the same gain
+ * routine on the same m (so every gain value is bitwise the one the plain
+ * loop computes), but a candidate is re-evaluated only while its last gain,
+ * an upper bound of its current gain by submodularity, could still beat the
+ * best current gain. Stale bounds within a relative 1e-9 of the best are
+ * refreshed too, so rounding in the recomputed sums cannot change the pick;
+ * exact ties go to the lowest index as in the plain loop. Used to produce
+ * reference runs at sizes where the plain loop takes hours. */
+#define REF_BATCH 256
+
+typedef struct {
+    double key;   /* last computed gain */
+    int32_t idx;
+    int32_t stamp; /* step at which key was computed */
+} ref_entry;
+
+static int ref_before(const ref_entry* a, const ref_entry* b)
+{
+    return a->key > b->key || (a->key == b->key && a->idx < b->idx);
+}
+
+static void ref_sift_down(ref_entry* h, int64_t len, int64_t i)
+{
+    for (;;) {
+        int64_t l = 2 * i + 1, r = l + 1, m = i;
+        if (l < len && ref_before(&h[l], &h[m])) m = l;
+        if (r < len && ref_before(&h[r], &h[m])) m = r;
+        if (m == i) return;
+        ref_entry t = h[i]; h[i] = h[m]; h[m] = t;
+        i = m;
+    }
+}
+
+static void ref_sift_up(ref_entry* h, int64_t i)
+{
+    while (i > 0) {
+        int64_t p = (i - 1) / 2;
+        if (!ref_before(&h[i], &h[p])) return;
+        ref_entry t = h[i]; h[i] = h[p]; h[p] = t;
+        i = p;
+    }
+}
+
+static double ref_gain_one(const float* x, int64_t n, int32_t d, const double* m, int64_t c)
+{
+    const float* xc = x + c * d;
+    double acc = 0.0;
+    for (int64_t v = 0; v < n; ++v) {
+        double q = m[v] - sqd(x + v * d, xc, d);
+        if (q > 0.0) acc += q;
+    }
+    return acc / (double)n;
+}
+
+int ebc_ref_greedy_lazy(const float* x, int64_t n, int32_t d, int32_t k, int32_t* sel, double* f,
+                        double* g, int64_t* evals)
+{
+    if (k > n) return -2;
+    double* m = (double*)malloc(sizeof(double) * (size_t)n);
+    ref_entry* h = (ref_entry*)malloc(sizeof(ref_entry) * (size_t)n);
+    int64_t* stack = (int64_t*)malloc(sizeof(int64_t) * (size_t)n);
+    int64_t* stale = (int64_t*)malloc(sizeof(int64_t) * (size_t)n);
+    ref_entry* batch = (ref_entry*)malloc(sizeof(ref_entry) * REF_BATCH);
+    if (!m || !h || !stack || !stale || !batch) {
+        free(m); free(h); free(stack); free(stale); free(batch);
+        return -1;
+    }
+    double l0 = 0.0;
+    for (int64_t v = 0; v < n; ++v) {
+        m[v] = sqn(x + v * d, d);
+        l0 += m[v];
+    }
+    l0 /= (double)n;
+    /* step 0: every gain, as the plain loop computes it */
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t c = 0; c < n; ++c) {
+        h[c].key = ref_gain_one(x, n, d, m, c);
+        h[c].idx = (int32_t)c;
+        h[c].stamp = 0;
+    }
+    int64_t len = n, count = n;
+    for (int64_t i = len / 2 - 1; i >= 0; --i) ref_sift_down(h, len, i);
+    for (int32_t t = 0; t < k; ++t) {
+        for (;;) {
+            if (h[0].stamp != t) {
+                /* stale top: take up to REF_BATCH stale entries off the top,
+                   refresh them in parallel, put them back */
+                int64_t nb = 0;
+                while (len > 0 && h[0].stamp != t && nb < REF_BATCH) {
+                    batch[nb++] = h[0];
+                    h[0] = h[--len];
+                    ref_sift_down(h, len, 0);
+                }
+#pragma omp parallel for schedule(dynamic, 1)
+                for (int64_t i = 0; i < nb; ++i) {
+                    batch[i].key = ref_gain_one(x, n, d, m, batch[i].idx);
+                    batch[i].stamp = t;
+                }
+                count += nb;
+                for (int64_t i = 0; i < nb; ++i) {
+                    h[len] = batch[i];
+                    ref_sift_up(h, len);
+                    ++len;
+                }
+                continue;
+            }
+            /* fresh top: every stale bound within a relative 1e-9 of it is
+               refreshed first (those entries form the subtree of nodes at or
+               above the threshold), then the top is the plain loop's pick */
+            const double thr = h[0].key - 1e-9 * fabs(h[0].key);
+            int64_t sp = 0, ns = 0;
+            stack[sp++] = 0;
+            while (sp > 0) {
+                const int64_t i = stack[--sp];
+                if (h[i].key < thr) continue;
+                if (h[i].stamp != t) stale[ns++] = i;
+                if (2 * i + 1 < len) stack[sp++] = 2 * i + 1;
+                if (2 * i + 2 < len) stack[sp++] = 2 * i + 2;
+            }
+            if (ns == 0) break;
+#pragma omp parallel for schedule(dynamic, 1)
+            for (int64_t q = 0; q < ns; ++q) {
+                h[stale[q]].key = ref_gain_one(x, n, d, m, h[stale[q]].idx);
+                h[stale[q]].stamp = t;
+            }
+            count += ns;
+            for (int64_t i = len / 2 - 1; i >= 0; --i) ref_sift_down(h, len, i);
+        }
+        const int64_t best = h[0].idx;
+        sel[t] = (int32_t)best;
+        g[t] = h[0].key;
+        h[0] = h[--len];
+        ref_sift_down(h, len, 0);
+        double sum = 0.0;
+        for (int64_t v = 0; v < n; ++v) {
+            double dv = sqd(x + v * d, x + best * d, d);
+            if (dv < m[v]) m[v] = dv;
+            sum += m[v];
+        }
+        f[t] = l0 - sum / (double)n;
+    }
+    if (evals) *evals = count;
+    free(m); free(h); free(stack); free(stale); free(batch);
+    return 0;
+}

@@ -29,6 +29,8 @@ def lib():
         L.ebc_ref_eval_sets.argtypes = [P, i64, i32, P, P, i64, P]
         L.ebc_ref_greedy.argtypes = [P, i64, i32, i32, P, P, P]
         L.ebc_ref_greedy.restype = ctypes.c_int
+        L.ebc_ref_greedy_lazy.argtypes = [P, i64, i32, i32, P, P, P, P]
+        L.ebc_ref_greedy_lazy.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -80,3 +82,17 @@ def greedy(x, k: int):
     if rc != 0:
         raise ValueError(f"ebc_ref_greedy failed ({rc})")
     return sel.astype(np.int64), f, g
+
+
+def greedy_lazy(x, k: int):
+    """Same result as greedy(), by lazy re-evaluation of stale upper bounds.
+    Returns (sel, f, gain, gain evaluations)."""
+    x = _f32(x)
+    sel = np.empty(k, dtype=np.int32)
+    f = np.empty(k)
+    g = np.empty(k)
+    ev = ctypes.c_int64(0)
+    rc = lib().ebc_ref_greedy_lazy(_p(x), x.shape[0], x.shape[1], int(k), _p(sel), _p(f), _p(g), ctypes.byref(ev))
+    if rc != 0:
+        raise ValueError(f"ebc_ref_greedy_lazy failed ({rc})")
+    return sel.astype(np.int64), f, g, int(ev.value)

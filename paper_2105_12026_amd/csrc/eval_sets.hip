@@ -1,95 +1,346 @@
 // f(S_j) for many CSR-packed sets at once (Sec. 4.1: optimisers score a whole
 // family S_multi = {S_1..S_l} per step; Alg. 1 gives f per set as a running
-// minimum per ground point, a sum, and a division by |V|).
+// minimum per ground point, a sum, and a division by |V|; Alg. 2 assigns the
+// (set, point) cells of that computation to GPU threads).
 //
-// A workgroup owns kSetsPerBlock sets and streams every ground point v once:
-// each thread keeps, per owned set, the float64 running sum of
-//     ||v||^2 - min(||v||^2, min_{s in S_j} d(v, s))
-// (the e0 = 0 term of S_j u {e0} is the ||v||^2 start value), so
-//     f(S_j) = |V|^-1 sum_v that term  = L({e0}) - L(S_j u {e0}).
-// Distances are float32 direct differences; the per-point term and every sum
-// are float64; the block sum runs in a fixed tree order.
+// With e0 = 0 in every set, d(v,e0) = ||v||^2 = n_v and d(v,s) = n_v + n_s -
+// 2 v.s, the per-point term of f is
+//     n_v - min(n_v, min_{s in S} d(v,s)) = 2 max(0, max_{s in S} (v.s - n_s/2)),
+// so f(S) = (2/|V|) sum_v max(0, max_{s in S} (v.s - n_s/2)): a dense
+// contraction of set members against ground points (float32 on the matrix
+// cores, v_mfma_f32_32x32x2_f32), a maximum over each set's members, a clamp
+// at 0 and a sum over v. No (set, point) work matrix is ever written.
+//
+// Work decomposition. Each set's members are laid out in units of 8 rows
+// (ceil(|S_j|/8) units, padding rows contribute -inf); units of consecutive
+// sets follow each other, 4 units form a 32-row member block, and a group is
+// every set whose first unit lies in one window of 32 units. A work item is
+// (group, ground-set split); a workgroup (4 waves) walks the group's member
+// blocks through LDS while each wave holds 64 ground points in registers,
+// and keeps a running maximum per (set, point) across the set's units (also
+// across blocks, so sets of any size work). At each set's last unit the
+// clamped maxima of the 32 columns are summed in float64 into a per-wave,
+// per-set accumulator; a final pass adds the splits in a fixed order, so the
+// result does not depend on the schedule.
 #include <math.h>
 
 #include "ebc_internal.h"
 
 namespace ebc {
 
-constexpr int kSetsPerBlock = 4;
+typedef float floatx16 __attribute__((ext_vector_type(16)));
 
-__global__ void __launch_bounds__(kBlock)
-k_eval_sets(const float* __restrict__ x, int64_t n, int32_t d, const double* __restrict__ n64,
-            const int64_t* __restrict__ off, const int32_t* __restrict__ idx, int64_t l,
-            double* __restrict__ f_out, DevState* st) {
-    __shared__ double red[kSetsPerBlock][kBlock];
-    __shared__ int s_bad[kSetsPerBlock];
-    const int64_t j0 = int64_t(blockIdx.x) * kSetsPerBlock;
-    if (threadIdx.x < kSetsPerBlock) {
-        const int64_t j = j0 + threadIdx.x;
-        int bad = 0;
-        if (j < l) {
-            const int64_t a = off[j], z = off[j + 1];
-            if (a < 0 || z < a || z > off[l]) bad = 1;
-            else
-                for (int64_t q = a; q < z; ++q)
-                    if (idx[q] < 0 || int64_t(idx[q]) >= n) { bad = 1; break; }
-        }
-        s_bad[threadIdx.x] = bad;
-        if (bad) atomicCAS(&st->error, 0, kDevErrIndex);
-    }
-    __syncthreads();
-    int64_t beg[kSetsPerBlock], end[kSetsPerBlock];
-#pragma unroll
-    for (int s = 0; s < kSetsPerBlock; ++s) {
-        const int64_t j = j0 + s;
-        const bool ok = j < l && !s_bad[s];
-        beg[s] = ok ? off[j] : 0;
-        end[s] = ok ? off[j + 1] : 0;
-    }
-    double acc[kSetsPerBlock];
-#pragma unroll
-    for (int s = 0; s < kSetsPerBlock; ++s) acc[s] = 0.0;
-    for (int64_t v = threadIdx.x; v < n; v += kBlock) {
-        const float* xv = x + v * d;
-        const double nv = n64[v];
-#pragma unroll
-        for (int s = 0; s < kSetsPerBlock; ++s) {
-            float dmin = INFINITY;
-            for (int64_t q = beg[s]; q < end[s]; ++q) {
-                const float* xs = x + int64_t(idx[q]) * d;
-                float t = 0.0f;
-                for (int k = 0; k < d; ++k) {
-                    const float u = xv[k] - xs[k];
-                    t = fmaf(u, u, t);
-                }
-                dmin = fminf(dmin, t);
+namespace {
+
+constexpr int kUnitRows = 8;    // rows per unit
+constexpr int kBlockUnits = 4;  // units per 32-row member block
+constexpr int kWindow = 32;     // units per group window
+constexpr int kVSub = 256;      // ground points per workgroup pass (4 waves x 64)
+constexpr int kMaxSplits = 8;
+
+// Scratch of one call: unit prefix U[l+1], non-empty prefix E[l+1], set
+// status (0 ok, 1 bad), group count, per-split partial sums [splits][l].
+struct EsScratch {
+    int64_t* U;
+    int32_t* E;
+    int32_t* bad;
+    int64_t* n_groups;
+    double* part;
+};
+
+// One thread per set: validate the offsets and indices, count the units.
+__global__ void __launch_bounds__(256) k_es_units(const int64_t* __restrict__ off, const int32_t* __restrict__ idx,
+                                                   int64_t l, int64_t n, EsScratch sc, DevState* st) {
+    const int64_t j = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (j >= l) return;
+    const int64_t a = off[j], z = off[j + 1];
+    int bad = 0;
+    if (a < 0 || z < a || z > off[l]) bad = 1;
+    else
+        for (int64_t q = a; q < z; ++q)
+            if (idx[q] < 0 || int64_t(idx[q]) >= n) {
+                bad = 1;
+                break;
             }
-            const double m = fmin(nv, double(dmin));
-            acc[s] += nv - m;
-        }
+    if (bad) atomicCAS(&st->error, 0, kDevErrIndex);
+    sc.bad[j] = bad;
+    sc.U[j + 1] = bad ? 0 : (z - a + kUnitRows - 1) / kUnitRows;  // counts, scanned next
+    sc.E[j + 1] = (!bad && z > a) ? 1 : 0;
+}
+
+// Single workgroup: inclusive scans of the unit and non-empty counts (in
+// place, U[0] = E[0] = 0), and the number of group windows.
+__global__ void __launch_bounds__(1024) k_es_scan(int64_t l, EsScratch sc) {
+    __shared__ int64_t su[1024];
+    __shared__ int32_t se[1024];
+    __shared__ int64_t carry_u;
+    __shared__ int32_t carry_e;
+    const int t = threadIdx.x;
+    if (t == 0) {
+        carry_u = 0;
+        carry_e = 0;
+        sc.U[0] = 0;
+        sc.E[0] = 0;
     }
-#pragma unroll
-    for (int s = 0; s < kSetsPerBlock; ++s) red[s][threadIdx.x] = acc[s];
     __syncthreads();
-    for (int w = kBlock / 2; w > 0; w >>= 1) {
-        if (threadIdx.x < w) {
-#pragma unroll
-            for (int s = 0; s < kSetsPerBlock; ++s) red[s][threadIdx.x] += red[s][threadIdx.x + w];
+    for (int64_t base = 0; base < l; base += 1024) {
+        const int64_t j = base + t;
+        su[t] = j < l ? sc.U[j + 1] : 0;
+        se[t] = j < l ? sc.E[j + 1] : 0;
+        __syncthreads();
+        for (int w = 1; w < 1024; w <<= 1) {
+            const int64_t u = t >= w ? su[t - w] : 0;
+            const int32_t e = t >= w ? se[t - w] : 0;
+            __syncthreads();
+            su[t] += u;
+            se[t] += e;
+            __syncthreads();
+        }
+        if (j < l) {
+            sc.U[j + 1] = carry_u + su[t];
+            sc.E[j + 1] = carry_e + se[t];
+        }
+        __syncthreads();
+        if (t == 1023) {
+            carry_u += su[1023];
+            carry_e += se[1023];
         }
         __syncthreads();
     }
-    if (threadIdx.x < kSetsPerBlock) {
-        const int64_t j = j0 + threadIdx.x;
-        if (j < l) f_out[j] = s_bad[threadIdx.x] ? NAN : red[threadIdx.x][0] / double(n);
+    if (t == 0) *sc.n_groups = (carry_u + kWindow - 1) / kWindow;
+}
+
+// first j in [lo, hi) with U[j] >= key (hi if none)
+__device__ __forceinline__ int64_t lower_bound_u(const int64_t* __restrict__ U, int64_t lo, int64_t hi,
+                                                 int64_t key) {
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (U[mid] < key)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+// the set that owns unit u: last j in [lo, hi) with U[j] <= u
+__device__ __forceinline__ int64_t owner_of(const int64_t* __restrict__ U, int64_t lo, int64_t hi, int64_t u) {
+    while (hi - lo > 1) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (U[mid] <= u)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+template <int KP>
+__global__ void __launch_bounds__(256)
+k_es_main(const float* __restrict__ x, int64_t n, int32_t d, const double* __restrict__ n64,
+          const int64_t* __restrict__ off, const int32_t* __restrict__ idx, int64_t l, int32_t splits,
+          EsScratch sc) {
+    constexpr int KH = KP / 2;  // K values per lane half
+    constexpr int S = KP + 4;   // LDS row stride (S/4 odd: conflict-free 16-byte reads)
+    static_assert(KP % 8 == 0, "row length must be a multiple of 8");
+    __shared__ float4 lds_m4[32 * S / 4];
+    __shared__ int64_t row_mem[32];
+    __shared__ float row_c[32];
+    __shared__ int32_t unit_local[kBlockUnits];
+    __shared__ int32_t unit_flags[kBlockUnits];  // bit0 first, bit1 last, bit2 valid
+    __shared__ double acc_set[4][kWindow];
+    float* lds_m = reinterpret_cast<float*>(lds_m4);
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int col = lane & 31;
+    const int half = lane >> 5;
+    const int64_t n_items = *sc.n_groups * splits;
+    const int64_t vchunk = ((n + splits - 1) / splits + kVSub - 1) / kVSub * kVSub;
+
+    for (int64_t item = blockIdx.x; item < n_items; item += gridDim.x) {
+        const int64_t g = item / splits;
+        const int split = int(item % splits);
+        // sets whose first unit lies in window g (empty sets own no unit)
+        const int64_t j0 = lower_bound_u(sc.U, 0, l, g * kWindow);
+        const int64_t j1 = lower_bound_u(sc.U, j0, l, (g + 1) * kWindow);
+        const int64_t u0 = sc.U[j0], u1 = sc.U[j1];
+        const int64_t v_begin = int64_t(split) * vchunk;
+        int64_t v_end = v_begin + vchunk;
+        if (v_end > n) v_end = n;
+        if (tid < 4 * kWindow) acc_set[tid / kWindow][tid % kWindow] = 0.0;
+        __syncthreads();
+        if (u1 > u0 && v_end > v_begin) {
+            const int64_t nblk = (u1 - u0 + kBlockUnits - 1) / kBlockUnits;
+            for (int64_t vs = v_begin; vs < v_end; vs += kVSub) {
+                // this wave's 64 ground points (B operand), K split in lane halves
+                float b[2][KH];
+#pragma unroll
+                for (int cb = 0; cb < 2; ++cb) {
+                    const int64_t v = vs + wave * 64 + cb * 32 + col;
+                    const bool ok = v < v_end;
+#pragma unroll
+                    for (int s = 0; s < KH; ++s) {
+                        const int k = half * KH + s;
+                        b[cb][s] = (ok && k < d) ? x[v * d + k] : 0.0f;
+                    }
+                }
+                float cur[2] = {-INFINITY, -INFINITY};
+                for (int64_t blk = 0; blk < nblk; ++blk) {
+                    __syncthreads();  // the previous block is no longer read
+                    if (tid < 32) {
+                        // row -> member (-1: padding) and its C value -n_s/2
+                        const int64_t u = u0 + blk * kBlockUnits + tid / kUnitRows;
+                        int64_t mem = -1;
+                        if (u < u1) {
+                            const int64_t j = owner_of(sc.U, j0, j1, u);
+                            const int64_t q = (u - sc.U[j]) * kUnitRows + tid % kUnitRows;
+                            if (off[j] + q < off[j + 1]) mem = idx[off[j] + q];
+                        }
+                        row_mem[tid] = mem;
+                        row_c[tid] = mem >= 0 ? -float(0.5 * n64[mem]) : -INFINITY;
+                    } else if (tid < 32 + kBlockUnits) {
+                        const int uu = tid - 32;
+                        const int64_t u = u0 + blk * kBlockUnits + uu;
+                        int flags = 0, loc = 0;
+                        if (u < u1) {
+                            const int64_t j = owner_of(sc.U, j0, j1, u);
+                            flags = 4 | (u == sc.U[j] ? 1 : 0) | (u == sc.U[j + 1] - 1 ? 2 : 0);
+                            loc = sc.E[j] - sc.E[j0];
+                        }
+                        unit_flags[uu] = flags;
+                        unit_local[uu] = loc;
+                    }
+                    __syncthreads();
+                    // gather the 32 member rows into LDS (zero beyond d)
+                    {
+                        const int r = tid >> 3;
+                        const int64_t mem = row_mem[r];
+                        for (int k = tid & 7; k < KP; k += 8)
+                            lds_m[r * S + k] = (mem >= 0 && k < d) ? x[mem * d + k] : 0.0f;
+                    }
+                    __syncthreads();
+                    // member rows x this wave's points
+                    floatx16 acc[2];
+#pragma unroll
+                    for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+                        for (int r = 0; r < 16; ++r) acc[cb][r] = row_c[8 * (r / 4) + 4 * half + (r % 4)];
+                    const float* arow = lds_m + col * S + half * KH;
+#pragma unroll
+                    for (int s4 = 0; s4 < KH / 4; ++s4) {
+                        const float4 a4 = *reinterpret_cast<const float4*>(arow + 4 * s4);
+                        const float av[4] = {a4.x, a4.y, a4.z, a4.w};
+#pragma unroll
+                        for (int i = 0; i < 4; ++i)
+#pragma unroll
+                            for (int cb = 0; cb < 2; ++cb)
+                                acc[cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[i], b[cb][4 * s4 + i], acc[cb], 0,
+                                                                               0, 0);
+                    }
+                    // units: the lane holds rows 8*uu + 4*half + (0..3) of unit uu
+#pragma unroll
+                    for (int uu = 0; uu < kBlockUnits; ++uu) {
+                        const int flags = unit_flags[uu];
+                        if (!(flags & 4)) continue;
+#pragma unroll
+                        for (int cb = 0; cb < 2; ++cb) {
+                            float m = fmaxf(fmaxf(acc[cb][4 * uu + 0], acc[cb][4 * uu + 1]),
+                                            fmaxf(acc[cb][4 * uu + 2], acc[cb][4 * uu + 3]));
+                            m = fmaxf(m, __shfl_xor(m, 32, 64));
+                            cur[cb] = (flags & 1) ? m : fmaxf(cur[cb], m);
+                        }
+                        if (flags & 2) {
+                            // set complete for these 64 points: clamp, sum the columns
+                            double sv = double(fmaxf(cur[0], 0.0f)) + double(fmaxf(cur[1], 0.0f));
+#pragma unroll
+                            for (int o = 16; o > 0; o >>= 1) sv += __shfl_xor(sv, o, 64);
+                            if (lane == 0) acc_set[wave][unit_local[uu]] += sv;
+                        }
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        // fixed-order combination over the waves; one write per non-empty set
+        // of the group and split (zero when the split has no points)
+        for (int64_t j = j0 + tid; j < j1; j += 256) {
+            if (sc.E[j + 1] == sc.E[j]) continue;
+            const int loc = int(sc.E[j] - sc.E[j0]);
+            sc.part[int64_t(split) * l + j] = ((acc_set[0][loc] + acc_set[1][loc]) + acc_set[2][loc]) + acc_set[3][loc];
+        }
+        __syncthreads();
     }
 }
 
+// f_j = (2/|V|) sum over splits (fixed order); empty sets 0; bad sets NaN.
+__global__ void __launch_bounds__(256) k_es_final(int64_t l, int64_t n, int32_t splits, EsScratch sc,
+                                                  double* __restrict__ f_out) {
+    const int64_t j = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (j >= l) return;
+    if (sc.bad[j]) {
+        f_out[j] = NAN;
+        return;
+    }
+    if (sc.E[j + 1] == sc.E[j]) {
+        f_out[j] = 0.0;
+        return;
+    }
+    double s = 0.0;
+    for (int p = 0; p < splits; ++p) s += sc.part[int64_t(p) * l + j];
+    f_out[j] = 2.0 * s / double(n);
+}
+
+template <int KP>
+void launch_es_main(dim3 g, hipStream_t s, const ebc_dataset* ds, const int64_t* off, const int32_t* idx, int64_t l,
+                    int32_t splits, const EsScratch& sc) {
+    hipLaunchKernelGGL((k_es_main<KP>), g, dim3(256), 0, s, ds->x, ds->n, ds->d, ds->b.n64, off, idx, l, splits, sc);
+}
+
+}  // namespace
+
 hipError_t launch_eval_sets(const ebc_dataset* ds, const int64_t* offsets, const int32_t* idx, int64_t l,
                             double* f_out, hipStream_t s) {
-    const int64_t nb = (l + kSetsPerBlock - 1) / kSetsPerBlock;
-    hipLaunchKernelGGL(k_eval_sets, dim3(unsigned(nb)), dim3(kBlock), 0, s, ds->x, ds->n, ds->d, ds->b.n64,
-                       offsets, idx, l, f_out, ds->b.state);
-    return hipGetLastError();
+    // ground-set splits: as many as keep every split at least one pass long
+    int32_t splits = int32_t((ds->n + kVSub - 1) / kVSub);
+    if (splits > kMaxSplits) splits = kMaxSplits;
+    auto a8 = [](size_t v) { return (v + 255) & ~size_t(255); };
+    const size_t bytes = a8((l + 1) * sizeof(int64_t)) + a8((l + 1) * sizeof(int32_t)) + a8(l * sizeof(int32_t)) +
+                         a8(sizeof(int64_t)) + a8(size_t(splits) * l * sizeof(double));
+    char* base = nullptr;
+    hipError_t e = hipMallocAsync(reinterpret_cast<void**>(&base), bytes, s);
+    if (e != hipSuccess) return e;
+    EsScratch sc;
+    char* p = base;
+    sc.U = reinterpret_cast<int64_t*>(p);
+    p += a8((l + 1) * sizeof(int64_t));
+    sc.E = reinterpret_cast<int32_t*>(p);
+    p += a8((l + 1) * sizeof(int32_t));
+    sc.bad = reinterpret_cast<int32_t*>(p);
+    p += a8(l * sizeof(int32_t));
+    sc.n_groups = reinterpret_cast<int64_t*>(p);
+    p += a8(sizeof(int64_t));
+    sc.part = reinterpret_cast<double*>(p);
+
+    const unsigned nb = unsigned((l + 255) / 256);
+    hipLaunchKernelGGL(k_es_units, dim3(nb), dim3(256), 0, s, offsets, idx, l, ds->n, sc, ds->b.state);
+    hipLaunchKernelGGL(k_es_scan, dim3(1), dim3(1024), 0, s, l, sc);
+    // persistent grid over (group, split) items; the item count is read on the device
+    const dim3 g = dim3(2048);
+    const int kp = (ds->d + 7) / 8 * 8;
+    switch (kp) {
+#define EBC_ES(K) \
+    case K: launch_es_main<K>(g, s, ds, offsets, idx, l, splits, sc); break;
+        EBC_ES(8) EBC_ES(16) EBC_ES(24) EBC_ES(32) EBC_ES(40) EBC_ES(48) EBC_ES(56) EBC_ES(64)
+        EBC_ES(72) EBC_ES(80) EBC_ES(88) EBC_ES(96) EBC_ES(104) EBC_ES(112) EBC_ES(120) EBC_ES(128)
+#undef EBC_ES
+        default: (void)hipFreeAsync(base, s); return hipErrorInvalidValue;
+    }
+    hipLaunchKernelGGL(k_es_final, dim3(nb), dim3(256), 0, s, l, ds->n, splits, sc, f_out);
+    e = hipGetLastError();
+    const hipError_t ef = hipFreeAsync(base, s);
+    return e != hipSuccess ? e : ef;
 }
 
 }  // namespace ebc

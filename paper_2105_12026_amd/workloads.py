@@ -29,6 +29,7 @@ __all__ = [
     "batched_instances",
     "serving_requests",
     "poisson_arrivals",
+    "paper_sets",
     "sha256_of",
 ]
 
@@ -175,3 +176,18 @@ def poisson_arrivals(seed: int, rate: float, count: int) -> np.ndarray:
         raise ValueError("rate must be positive")
     rng = np.random.default_rng([seed, 7])
     return np.cumsum(rng.exponential(1.0 / rate, count))
+
+
+def paper_sets(seed: int = 6, n: int = 50_000, l: int = 5000, set_size: int = 10, d: int = 100) -> Problem:
+    """Multi-set evaluation in the shape of the paper's runtime sweep (Sec. 5.1
+    defaults: |V| = 50000, l = 5000 sets of k = 10 points, d = 100; the paper's
+    data is "randomly generated" with no distribution given): i.i.d. N(0,1)
+    points, then l sets of set_size distinct random indices, CSR-packed."""
+    rng = np.random.default_rng(seed)
+    x = rng.standard_normal((n, d)).astype(np.float32)
+    idx = np.empty(l * set_size, dtype=np.int32)
+    for j in range(l):
+        idx[j * set_size:(j + 1) * set_size] = rng.choice(n, set_size, replace=False)
+    offsets = np.arange(l + 1, dtype=np.int64) * set_size
+    return Problem(x=x, k=0, name=f"paper_sets_n{n}_l{l}_k{set_size}_d{d}", offsets=offsets, idx=idx,
+                   meta={"seed": seed, "sets": l, "set_size": set_size})

@@ -202,6 +202,33 @@ def test_eval_sets_edge_cases(ebc, torch_dev, ref):
     assert f0.tolist() == [0.0, 0.0, 0.0]
 
 
+@pytest.mark.parametrize("n,d,dt,seed", [(3000, 100, "f32", 52), (777, 16, "f32", 53), (2049, 33, "bf16", 54),
+                                         (300, 128, "fp8", 55), (5, 3, "f32", 56)])
+def test_eval_sets_many_sizes(ebc, torch_dev, ref, n, d, dt, seed):
+    """Set sizes on both sides of every unit (8 rows), member-block (32) and
+    window (256) boundary, empty sets between others, mixed in one call; the
+    dataset's distance dtype does not matter (float32 rows are used)."""
+    torch, _ = torch_dev
+    rng = np.random.default_rng(seed)
+    x = W.gaussian_mixture(rng, n, d, 5).astype(np.float32)
+    sizes = [0, 1, 7, 8, 9, 0, 15, 16, 17, 31, 32, 33, 0, 0, 64, 100, 255, 256, 257, 431, 3, 10, 10, 10]
+    sizes += list(rng.integers(1, 40, 300))
+    sets = [rng.integers(0, n, sz) for sz in sizes]
+    off = np.cumsum([0] + [len(q) for q in sets]).astype(np.int64)
+    idx = np.concatenate(sets).astype(np.int32)
+    _say(f"eval_sets many sizes n={n} d={d} dtype={dt} l={len(sets)} nnz={idx.size}")
+    ds = ebc.Dataset(torch.from_numpy(x).cuda(), dtype=dt)
+    f1 = ds.eval_sets(torch.from_numpy(off), torch.from_numpy(idx)).cpu().numpy()
+    f2 = ds.eval_sets(torch.from_numpy(off), torch.from_numpy(idx)).cpu().numpy()
+    ds.sync()
+    assert np.array_equal(f1, f2)  # deterministic
+    rf = ref.eval_sets(x, off, idx)
+    l0 = float(np.mean(np.sum(x.astype(np.float64) ** 2, axis=1)))
+    assert np.all(f1[np.array(sizes) == 0] == 0.0)
+    err = np.abs(f1 - rf)
+    assert np.all(err <= F_RTOL * np.abs(rf) + 1e-6 * l0), float(np.max(err / (np.abs(rf) + 1e-300)))
+
+
 def test_eval_sets_bad_index_is_reported(ebc, torch_dev):
     torch, _ = torch_dev
     x = np.random.default_rng(61).standard_normal((50, 4)).astype(np.float32)

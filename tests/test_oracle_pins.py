@@ -256,3 +256,37 @@ def test_c_oracle_hand_cases(ref):
                                [2 / 3, 8 / 3, 8 / 3], rtol=1e-15)
     with pytest.raises(ValueError):
         ref.greedy(LINE, 4)
+
+
+# --------------------------------------------------------------------------
+# The lazy evaluation of greedy returns exactly the plain loop's run
+# --------------------------------------------------------------------------
+def _mixture(seed, n, d, comps):
+    rng = np.random.default_rng(seed)
+    means = rng.normal(0.0, 2.0, (comps, d))
+    lab = rng.integers(0, comps, n)
+    return (means[lab] + rng.normal(0.0, 1.0, (n, d))).astype(np.float32)
+
+
+@pytest.mark.parametrize("name", ["mixture", "duplicates", "line", "exhausted", "outliers"])
+def test_lazy_greedy_equals_plain_greedy(ref, name):
+    if name == "mixture":
+        x, k = _mixture(31, 700, 8, 9), 40
+    elif name == "duplicates":
+        base = _mixture(32, 60, 3, 4)
+        x, k = np.concatenate([base, base[::2], base[:7]]), 50       # exact ties between copies
+    elif name == "line":
+        x, k = np.arange(40, dtype=np.float32).reshape(-1, 1) - 20.0, 40  # symmetric: many exact ties
+    elif name == "exhausted":
+        x, k = _mixture(33, 25, 2, 2), 25                             # gains reach zero before k
+    else:
+        x = _mixture(34, 500, 6, 5)
+        x[::50] = np.random.default_rng(35).uniform(-20, 20, (10, 6)).astype(np.float32)
+        k = 60
+    sel_p, f_p, g_p = ref.greedy(x, k)
+    sel_l, f_l, g_l, evals = ref.greedy_lazy(x, k)
+    assert sel_l.tolist() == sel_p.tolist()
+    assert np.array_equal(f_l, f_p) and np.array_equal(g_l, g_p)  # bitwise: same sums on the same m
+    assert evals <= x.shape[0] * k
+    with pytest.raises(ValueError):
+        ref.greedy_lazy(x, x.shape[0] + 1)
