@@ -65,20 +65,29 @@ def cpu_baseline(x, n: int, target_s: float = 12.0) -> dict:
                       f"(one greedy step's work for {nc} candidates; {dt:.1f} s)"}
 
 
-def counters_traffic(kernel: str, workload: str):
+def counters_traffic(kernel: str, workload: str, dtype: str, variant: int):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 --pmc
     summary (FETCH_SIZE, WRITE_SIZE scaled by a plain-copy calibration), or
-    None if it was taken on another workload or on other kernel source."""
+    None if none was taken on this workload, dtype and variant, or the
+    kernel's source has changed since."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "counters.json")
     try:
-        rec = json.load(open(path))[kernel]
-        src = open(os.path.join(ROOT, rec["source"]), "rb").read()
+        recs = json.load(open(path))["records"]
     except (OSError, KeyError, ValueError):
         return None
-    if rec.get("workload") != workload or hashlib.sha256(src).hexdigest()[:16] != rec["source_sha256_16"]:
-        return None
-    return int(rec["hbm_bytes_per_launch"])
+    for rec in recs:
+        if (rec.get("kernel"), rec.get("workload"), rec.get("dtype"), rec.get("variant")) != \
+                (kernel, workload, dtype, variant):
+            continue
+        try:
+            src = open(os.path.join(ROOT, rec["source"]), "rb").read()
+        except OSError:
+            return None
+        if hashlib.sha256(src).hexdigest()[:16] != rec["source_sha256_16"]:
+            return None
+        return int(rec["hbm_bytes_per_launch"])
+    return None
 
 
 def bench_batched(args):
@@ -323,10 +332,21 @@ def main():
     f = torch.empty(k, dtype=torch.float64, device=dev)
     gain = torch.empty(k, dtype=torch.float64, device=dev)
 
+    # gains tile variant: as given, else the autotuner's choice for this
+    # (dtype, row length, size), timed once before the measured steps
+    variant_used = 0
+    if args.variant is not None:
+        variant_used = args.variant
+    elif args.dtype != "f32":
+        tds = ebc.Dataset(x, dtype=args.dtype, stream=stream)
+        variant_used = tds.autotune(reps=3, stream=stream)["variant"]
+        tds.sync(stream)
+        tds.close()
+
     def one_step(profile: bool):
         ds = ebc.Dataset(x, dtype=args.dtype, stream=stream)
-        if args.variant is not None:
-            ds.set_variant(args.variant)
+        if args.dtype != "f32":
+            ds.set_variant(variant_used)
         if profile:
             ds.profile(True)
         ds.greedy(k, stream=stream, sel=sel, f=f, gain=gain)
@@ -374,10 +394,10 @@ def main():
     flops_per_launch = 2.0 * d * pairs / k
     achieved = flops_per_launch / (gains_avg_ms * 1e-3) / 1e12
     peak = PEAK_TFLOPS[args.dtype]
-    kname = "k_gains_f32" if args.dtype == "f32" else "k_gains_lp"
+    kname = "k_gains_f32" if args.dtype == "f32" else ("k_gains_lp_pp" if variant_used == 3 else "k_gains_lp")
     roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak,
                 "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
-                "traffic": counters_traffic(kname, args.workload) if args.dtype == "f32" else None,
+                "traffic": counters_traffic(kname, args.workload, args.dtype, variant_used),
                 "kernel": kname, "avg_launch_ms": round(gains_avg_ms, 4),
                 "flops_per_launch": flops_per_launch}
 
@@ -388,7 +408,7 @@ def main():
         "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": args.dtype, "data": "synthetic",
         "config": {"workload": args.workload, "n": n, "d": d, "k": k, "distance_dtype": args.dtype,
-                   "variant": args.variant,
+                   "variant": variant_used,
                    "candidates": "all n points every step", "step": "residency + greedy k"},
         "greedy_ms": ms_per_step, "gains_kernel_ms_total_per_step": prof["gains_ms"] / args.steps,
         "rest_of_step_ms_per_step": prof["select_ms"] / args.steps,

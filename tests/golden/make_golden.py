@@ -4,6 +4,7 @@ workloads. Nothing here touches the HIP library.
 
     python tests/golden/make_golden.py small      # seconds
     python tests/golden/make_golden.py gmm100k    # ~2 h on 8 cores (FP64 greedy, k=50)
+    python tests/golden/make_golden.py sweep200k  # ~15 min on 8 cores (lazy FP64 greedy, k=100)
 
 Each JSON file records the generator, its seed, the SHA-256 of the float32
 input of record, the oracle entry point used, its thread count and wall time.
@@ -56,6 +57,22 @@ def gmm100k():
         "sha256_x": W.sha256_of(p.x),
         "oracle": "oracle/ebc_ref.c ebc_ref_greedy (C, float64, direct differences)",
         "threads": ref.threads(), "seconds": time.time() - t0,
+        "sel": sel.tolist(), "f": f.tolist(), "gain": g.tolist(),
+    })
+
+
+def sweep200k():
+    p = W.precision_sweep(seed=3)
+    t0 = time.time()
+    # lazy evaluation of the same greedy: bitwise the plain loop's run (pinned in
+    # tests/test_oracle_pins.py, and on the 100000 x 100 run above)
+    sel, f, g, evals = ref.greedy_lazy(p.x, p.k)
+    _dump("gmm50+out_n200000_d64_k100.json", {
+        "workload": "precision_sweep(seed=3): 198000 x 64 50-component mixture + 2000 uniform [-20,20] outliers, "
+                    "shuffled; greedy k=100",
+        "sha256_x": W.sha256_of(p.x),
+        "oracle": "oracle/ebc_ref.c ebc_ref_greedy_lazy (C, float64, direct differences, lazy re-evaluation)",
+        "threads": ref.threads(), "seconds": time.time() - t0, "gain_evaluations": evals,
         "sel": sel.tolist(), "f": f.tolist(), "gain": g.tolist(),
     })
 

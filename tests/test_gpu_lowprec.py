@@ -7,6 +7,8 @@ Bars, per distance dtype (relative to the largest gain of the vector):
           oracle's f of that set); quality gap of the final set against the
           oracle's greedy <= GAP_TOL[dt]; selection agreement is printed.
 """
+import os
+
 import numpy as np
 import pytest
 
@@ -111,6 +113,46 @@ def test_lowprec_full_size_gains_sampled(env, ref, sweep200k, dt):
         errs.append(float(np.max(np.abs(g[cand] - rg)) / scale))
     print(f"[gpu-result] full-size gains {dt} rel err {max(errs):.3e}", flush=True)
     assert max(errs) <= GAIN_TOL[dt]
+
+
+GOLDEN_SWEEP = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "gmm50+out_n200000_d64_k100.json")
+
+
+@pytest.mark.parametrize("dt", ["f32", "bf16", "f16", "fp8"])
+def test_full_size_greedy_against_oracle_run(env, ref, sweep200k, dt):
+    """Greedy k = 100 on the 200000 x 64 precision-sweep input, in the
+    benchmark's configuration, against the stored float64 oracle run: float32
+    selections identical and f within 1e-5; reduced precision within the
+    quality-gap bar, f(S_t) float64-exact for the chosen sets; agreement
+    printed."""
+    import json
+    if not os.path.exists(GOLDEN_SWEEP):
+        pytest.skip("stored oracle run missing (tests/golden/make_golden.py sweep200k)")
+    gold = json.load(open(GOLDEN_SWEEP))
+    p = sweep200k
+    assert W.sha256_of(p.x) == gold["sha256_x"]
+    print(f"[gpu-case] full-size greedy {dt} n=200000 d=64 k=100", flush=True)
+    ds = _ds(env, p.x, dt)
+    if dt != "f32":
+        ds.set_variant(3)
+    sel, f, g = ds.greedy(p.k)
+    stats = ds.sync()
+    sel, f = sel.cpu().numpy(), f.cpu().numpy()
+    rsel, rf = np.array(gold["sel"]), np.array(gold["f"])
+    agree = len(set(sel.tolist()) & set(rsel.tolist())) / p.k
+    prefix = next((i for i in range(p.k) if sel[i] != rsel[i]), p.k)
+    gap = (rf[-1] - f[-1]) / rf[-1]
+    print(f"[gpu-result] full-size greedy {dt}: agreement {agree:.2f} common prefix {prefix} "
+          f"quality gap {gap:.2e} window max {stats['window_max']}", flush=True)
+    if dt == "f32":
+        assert sel.tolist() == rsel.tolist()
+        np.testing.assert_allclose(f, rf, rtol=1e-5)
+        return
+    l0 = float(np.mean(np.sum(p.x.astype(np.float64) ** 2, axis=1)))
+    for t in (9, p.k - 1):
+        m = ref.min_dist(p.x, sel[:t + 1])
+        assert f[t] == pytest.approx(l0 - float(np.mean(m)), rel=1e-9)
+    assert gap <= GAP_TOL[dt]
 
 
 @pytest.mark.parametrize("dt", ["bf16", "f16", "fp8"])
