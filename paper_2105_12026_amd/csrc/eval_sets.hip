@@ -11,14 +11,17 @@
 // cores, v_mfma_f32_32x32x2_f32), a maximum over each set's members, a clamp
 // at 0 and a sum over v. No (set, point) work matrix is ever written.
 //
-// Work decomposition. Each set's members are laid out in units of 8 rows
-// (ceil(|S_j|/8) units, padding rows contribute -inf); units of consecutive
-// sets follow each other, 4 units form a 32-row member block, and a group is
-// every set whose first unit lies in one window of 32 units. A work item is
-// (group, ground-set split); a workgroup (4 waves) walks the group's member
-// blocks through LDS while each wave holds 64 ground points in registers,
-// and keeps a running maximum per (set, point) across the set's units (also
-// across blocks, so sets of any size work). At each set's last unit the
+// Work decomposition. Each set's members are laid out in units of 4 rows
+// (ceil(|S_j|/4) units, padding rows contribute -inf); units of consecutive
+// sets follow each other, 8 units form a 32-row member block (in the MFMA
+// result a unit is the 4 rows one lane half holds), and a group is every set
+// whose first unit lies in one window of 64 units. A work item is (group,
+// ground-set split); a workgroup (4 waves) walks the group's member blocks
+// through a double-buffered LDS stage (the next block's rows are gathered
+// into registers while the current one is multiplied) while each wave holds
+// 64 ground points in registers, and keeps a running maximum per (set,
+// point) across the set's units (also across blocks, so sets of any size
+// work). At each set's last unit the two lane halves are joined and the
 // clamped maxima of the 32 columns are summed in float64 into a per-wave,
 // per-set accumulator; a final pass adds the splits in a fixed order, so the
 // result does not depend on the schedule.
@@ -32,9 +35,9 @@ typedef float floatx16 __attribute__((ext_vector_type(16)));
 
 namespace {
 
-constexpr int kUnitRows = 8;    // rows per unit
-constexpr int kBlockUnits = 4;  // units per 32-row member block
-constexpr int kWindow = 32;     // units per group window
+constexpr int kUnitRows = 4;    // rows per unit
+constexpr int kBlockUnits = 8;  // units per 32-row member block
+constexpr int kWindow = 64;     // units per group window
 constexpr int kVSub = 256;      // ground points per workgroup pass (4 waves x 64)
 constexpr int kMaxSplits = 8;
 
@@ -135,6 +138,53 @@ __device__ __forceinline__ int64_t owner_of(const int64_t* __restrict__ U, int64
     return lo;
 }
 
+// Row and unit bookkeeping of one 32-row member block.
+struct BlockInfo {
+    int32_t row_mem[32];             // member row of V, -1 for padding
+    float row_c[32];                 // -n_s/2, or -inf for padding
+    int32_t unit_flags[kBlockUnits];  // bit0 first unit of its set, bit1 last, bit2 valid
+    int32_t unit_local[kBlockUnits];  // the set's index within the group
+};
+
+// Set table of the current group: U, E and offsets of sets j0 .. j1, cached
+// in LDS when the group has at most kTab sets (else read from global memory).
+constexpr int kTab = 128;
+
+struct SetTable {
+    const int64_t* U;
+    const int32_t* E;
+    const int64_t* off;
+    int64_t base;  // global index of entry 0
+};
+
+// Threads 0..31 fill the rows, threads 32..39 the units of block blk.
+__device__ __forceinline__ void block_info(int tid, int64_t blk, int64_t u0, int64_t u1, int64_t j0, int64_t j1,
+                                           const SetTable& tb, const int32_t* __restrict__ idx,
+                                           const double* __restrict__ n64, BlockInfo& bi) {
+    if (tid < 32) {
+        const int64_t u = u0 + blk * kBlockUnits + tid / kUnitRows;
+        int32_t mem = -1;
+        if (u < u1) {
+            const int64_t j = owner_of(tb.U, j0 - tb.base, j1 - tb.base, u);
+            const int64_t q = (u - tb.U[j]) * kUnitRows + tid % kUnitRows;
+            if (tb.off[j] + q < tb.off[j + 1]) mem = idx[tb.off[j] + q];
+        }
+        bi.row_mem[tid] = mem;
+        bi.row_c[tid] = mem >= 0 ? -float(0.5 * n64[mem]) : -INFINITY;
+    } else if (tid < 32 + kBlockUnits) {
+        const int uu = tid - 32;
+        const int64_t u = u0 + blk * kBlockUnits + uu;
+        int flags = 0, loc = 0;
+        if (u < u1) {
+            const int64_t j = owner_of(tb.U, j0 - tb.base, j1 - tb.base, u);
+            flags = 4 | (u == tb.U[j] ? 1 : 0) | (u == tb.U[j + 1] - 1 ? 2 : 0);
+            loc = tb.E[j] - tb.E[j0 - tb.base];
+        }
+        bi.unit_flags[uu] = flags;
+        bi.unit_local[uu] = loc;
+    }
+}
+
 template <int KP>
 __global__ void __launch_bounds__(256)
 k_es_main(const float* __restrict__ x, int64_t n, int32_t d, const double* __restrict__ n64,
@@ -142,20 +192,21 @@ k_es_main(const float* __restrict__ x, int64_t n, int32_t d, const double* __res
           EsScratch sc) {
     constexpr int KH = KP / 2;  // K values per lane half
     constexpr int S = KP + 4;   // LDS row stride (S/4 odd: conflict-free 16-byte reads)
+    constexpr int PF = KP / 8;  // member-row values each thread gathers per block
     static_assert(KP % 8 == 0, "row length must be a multiple of 8");
-    __shared__ float4 lds_m4[32 * S / 4];
-    __shared__ int64_t row_mem[32];
-    __shared__ float row_c[32];
-    __shared__ int32_t unit_local[kBlockUnits];
-    __shared__ int32_t unit_flags[kBlockUnits];  // bit0 first, bit1 last, bit2 valid
+    __shared__ float4 lds_m4[2][32 * S / 4];
+    __shared__ BlockInfo info[3];
+    __shared__ int64_t t_u[kTab + 1], t_off[kTab + 1];
+    __shared__ int32_t t_e[kTab + 1];
     __shared__ double acc_set[4][kWindow];
-    float* lds_m = reinterpret_cast<float*>(lds_m4);
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
     const int col = lane & 31;
     const int half = lane >> 5;
+    const int grow = tid >> 3;  // gather: row and first column of this thread
+    const int gk = tid & 7;
     const int64_t n_items = *sc.n_groups * splits;
     const int64_t vchunk = ((n + splits - 1) / splits + kVSub - 1) / kVSub * kVSub;
 
@@ -169,8 +220,16 @@ k_es_main(const float* __restrict__ x, int64_t n, int32_t d, const double* __res
         const int64_t v_begin = int64_t(split) * vchunk;
         int64_t v_end = v_begin + vchunk;
         if (v_end > n) v_end = n;
+        const bool cached = j1 - j0 <= kTab;
+        if (cached)
+            for (int64_t i = tid; i <= j1 - j0; i += 256) {
+                t_u[i] = sc.U[j0 + i];
+                t_e[i] = sc.E[j0 + i];
+                t_off[i] = off[j0 + i];
+            }
         if (tid < 4 * kWindow) acc_set[tid / kWindow][tid % kWindow] = 0.0;
         __syncthreads();
+        const SetTable tb = cached ? SetTable{t_u, t_e, t_off, j0} : SetTable{sc.U, sc.E, off, 0};
         if (u1 > u0 && v_end > v_begin) {
             const int64_t nblk = (u1 - u0 + kBlockUnits - 1) / kBlockUnits;
             for (int64_t vs = v_begin; vs < v_end; vs += kVSub) {
@@ -187,47 +246,43 @@ k_es_main(const float* __restrict__ x, int64_t n, int32_t d, const double* __res
                     }
                 }
                 float cur[2] = {-INFINITY, -INFINITY};
+                // prologue: bookkeeping of blocks 0 and 1, rows of block 0
+                block_info(tid, 0, u0, u1, j0, j1, tb, idx, n64, info[0]);
+                if (nblk > 1) block_info(tid, 1, u0, u1, j0, j1, tb, idx, n64, info[1]);
+                __syncthreads();
+                {
+                    const int32_t mem = info[0].row_mem[grow];
+                    float* dst = reinterpret_cast<float*>(lds_m4[0]) + grow * S;
+#pragma unroll
+                    for (int i = 0; i < PF; ++i) {
+                        const int k = gk + 8 * i;
+                        dst[k] = (mem >= 0 && k < d) ? x[int64_t(mem) * d + k] : 0.0f;
+                    }
+                }
+                __syncthreads();
                 for (int64_t blk = 0; blk < nblk; ++blk) {
-                    __syncthreads();  // the previous block is no longer read
-                    if (tid < 32) {
-                        // row -> member (-1: padding) and its C value -n_s/2
-                        const int64_t u = u0 + blk * kBlockUnits + tid / kUnitRows;
-                        int64_t mem = -1;
-                        if (u < u1) {
-                            const int64_t j = owner_of(sc.U, j0, j1, u);
-                            const int64_t q = (u - sc.U[j]) * kUnitRows + tid % kUnitRows;
-                            if (off[j] + q < off[j + 1]) mem = idx[off[j] + q];
+                    const int rb = int(blk & 1);
+                    const BlockInfo& bi = info[blk % 3];
+                    // rows of block blk+1 into registers (their stores follow the MFMAs)
+                    float pf[PF];
+                    const bool more = blk + 1 < nblk;
+                    if (more) {
+                        const int32_t mem = info[(blk + 1) % 3].row_mem[grow];
+#pragma unroll
+                        for (int i = 0; i < PF; ++i) {
+                            const int k = gk + 8 * i;
+                            pf[i] = (mem >= 0 && k < d) ? x[int64_t(mem) * d + k] : 0.0f;
                         }
-                        row_mem[tid] = mem;
-                        row_c[tid] = mem >= 0 ? -float(0.5 * n64[mem]) : -INFINITY;
-                    } else if (tid < 32 + kBlockUnits) {
-                        const int uu = tid - 32;
-                        const int64_t u = u0 + blk * kBlockUnits + uu;
-                        int flags = 0, loc = 0;
-                        if (u < u1) {
-                            const int64_t j = owner_of(sc.U, j0, j1, u);
-                            flags = 4 | (u == sc.U[j] ? 1 : 0) | (u == sc.U[j + 1] - 1 ? 2 : 0);
-                            loc = sc.E[j] - sc.E[j0];
-                        }
-                        unit_flags[uu] = flags;
-                        unit_local[uu] = loc;
                     }
-                    __syncthreads();
-                    // gather the 32 member rows into LDS (zero beyond d)
-                    {
-                        const int r = tid >> 3;
-                        const int64_t mem = row_mem[r];
-                        for (int k = tid & 7; k < KP; k += 8)
-                            lds_m[r * S + k] = (mem >= 0 && k < d) ? x[mem * d + k] : 0.0f;
-                    }
-                    __syncthreads();
+                    // bookkeeping of block blk+2 (its slot was last read in block blk-1)
+                    if (blk + 2 < nblk) block_info(tid, blk + 2, u0, u1, j0, j1, tb, idx, n64, info[(blk + 2) % 3]);
                     // member rows x this wave's points
                     floatx16 acc[2];
 #pragma unroll
                     for (int cb = 0; cb < 2; ++cb)
 #pragma unroll
-                        for (int r = 0; r < 16; ++r) acc[cb][r] = row_c[8 * (r / 4) + 4 * half + (r % 4)];
-                    const float* arow = lds_m + col * S + half * KH;
+                        for (int r = 0; r < 16; ++r) acc[cb][r] = bi.row_c[8 * (r / 4) + 4 * half + (r % 4)];
+                    const float* arow = reinterpret_cast<const float*>(lds_m4[rb]) + col * S + half * KH;
 #pragma unroll
                     for (int s4 = 0; s4 < KH / 4; ++s4) {
                         const float4 a4 = *reinterpret_cast<const float4*>(arow + 4 * s4);
@@ -239,26 +294,35 @@ k_es_main(const float* __restrict__ x, int64_t n, int32_t d, const double* __res
                                 acc[cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[i], b[cb][4 * s4 + i], acc[cb], 0,
                                                                                0, 0);
                     }
-                    // units: the lane holds rows 8*uu + 4*half + (0..3) of unit uu
+                    // units of 4 rows: unit uu is held by lane half uu%2 in registers 4*(uu/2) .. +3
 #pragma unroll
                     for (int uu = 0; uu < kBlockUnits; ++uu) {
-                        const int flags = unit_flags[uu];
+                        const int flags = bi.unit_flags[uu];
                         if (!(flags & 4)) continue;
+                        const int j4 = 4 * (uu >> 1);
 #pragma unroll
                         for (int cb = 0; cb < 2; ++cb) {
-                            float m = fmaxf(fmaxf(acc[cb][4 * uu + 0], acc[cb][4 * uu + 1]),
-                                            fmaxf(acc[cb][4 * uu + 2], acc[cb][4 * uu + 3]));
-                            m = fmaxf(m, __shfl_xor(m, 32, 64));
-                            cur[cb] = (flags & 1) ? m : fmaxf(cur[cb], m);
+                            if (flags & 1) cur[cb] = -INFINITY;
+                            const float m = fmaxf(fmaxf(acc[cb][j4 + 0], acc[cb][j4 + 1]),
+                                                  fmaxf(acc[cb][j4 + 2], acc[cb][j4 + 3]));
+                            if (half == (uu & 1)) cur[cb] = fmaxf(cur[cb], m);
                         }
                         if (flags & 2) {
-                            // set complete for these 64 points: clamp, sum the columns
-                            double sv = double(fmaxf(cur[0], 0.0f)) + double(fmaxf(cur[1], 0.0f));
+                            // set complete for these 64 points: join the halves, clamp, sum the columns
+                            double sv = 0.0;
+#pragma unroll
+                            for (int cb = 0; cb < 2; ++cb) sv += double(fmaxf(fmaxf(cur[cb], __shfl_xor(cur[cb], 32, 64)), 0.0f));
 #pragma unroll
                             for (int o = 16; o > 0; o >>= 1) sv += __shfl_xor(sv, o, 64);
-                            if (lane == 0) acc_set[wave][unit_local[uu]] += sv;
+                            if (lane == 0) acc_set[wave][bi.unit_local[uu]] += sv;
                         }
                     }
+                    if (more) {
+                        float* dst = reinterpret_cast<float*>(lds_m4[rb ^ 1]) + grow * S;
+#pragma unroll
+                        for (int i = 0; i < PF; ++i) dst[gk + 8 * i] = pf[i];
+                    }
+                    __syncthreads();
                 }
             }
         }
