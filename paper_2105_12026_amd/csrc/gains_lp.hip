@@ -50,6 +50,23 @@ struct Lp<EBC_DT_FP8_E4M3> {
     static constexpr int kElem = 1, kChunkK = 64, kU4 = 2;
 };
 
+// Clamp-and-sum of one 32x32 result tile for this lane: the 16 clamps are
+// issued back to back into 16 registers (the empty asm statement keeps them
+// all live, so the compiler cannot reuse one temporary and make every add
+// wait for the clamp just before it), then the 16 adds. The per-lane sum
+// order is unchanged.
+__device__ __forceinline__ void clamp_sum16(const floatx16& acc, float lo, float hi, float (&sum)[16]) {
+    float t[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) t[r] = __builtin_amdgcn_fmed3f(acc[r], lo, hi);
+    asm volatile(""
+                 : "+v"(t[0]), "+v"(t[1]), "+v"(t[2]), "+v"(t[3]), "+v"(t[4]), "+v"(t[5]), "+v"(t[6]), "+v"(t[7]),
+                   "+v"(t[8]), "+v"(t[9]), "+v"(t[10]), "+v"(t[11]), "+v"(t[12]), "+v"(t[13]), "+v"(t[14]),
+                   "+v"(t[15]));
+#pragma unroll
+    for (int r = 0; r < 16; ++r) sum[r] += t[r];
+}
+
 template <int DT>
 __device__ __forceinline__ floatx16 mfma_main(const uint4* a, const uint4* b, floatx16 c, int sa, int sb);
 
@@ -186,9 +203,7 @@ __device__ __forceinline__ void lp_tile(int64_t t, int64_t nt, int64_t t_begin, 
             for (int cb = 0; cb < CB; ++cb)
                 acc[cb] = mfma_main<DT>(&a[cb][q * T::kU4], &b[q * T::kU4], acc[cb], sa[cb], sb);
 #pragma unroll
-        for (int cb = 0; cb < CB; ++cb)
-#pragma unroll
-            for (int r = 0; r < 16; ++r) acc_sum[cb][r] += __builtin_amdgcn_fmed3f(acc[cb][r], lo, hi);
+        for (int cb = 0; cb < CB; ++cb) clamp_sum16(acc[cb], lo, hi, acc_sum[cb]);
     }
 }
 
@@ -472,9 +487,7 @@ __device__ __forceinline__ void epilogue_tile(const floatx16 (&acc)[NCB][CB], co
     for (int colb = 0; colb < NCB; ++colb) {
         lo_sum += double(lo[colb]);
 #pragma unroll
-        for (int cb = 0; cb < CB; ++cb)
-#pragma unroll
-            for (int r = 0; r < 16; ++r) acc_sum[cb][r] += __builtin_amdgcn_fmed3f(acc[colb][cb][r], lo[colb], hi[colb]);
+        for (int cb = 0; cb < CB; ++cb) clamp_sum16(acc[colb][cb], lo[colb], hi[colb], acc_sum[cb]);
     }
 }
 
