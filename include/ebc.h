@@ -118,7 +118,7 @@ EBC_API ebc_status ebc_dataset_destroy(ebc_dataset* ds);
  * term folded in): float32 dot products of the caller's float32 rows on the
  * matrix cores whatever the dataset's distance dtype, float32 maxima, float64
  * sums. A bad index or offsets make that set's f NaN and raise EBC_E_INDEX.
- * Scratch of about (9 + 8 * min(8, n/256)) * l bytes is taken from the
+ * Scratch of about (9 + 8 * min(16, n/256)) * l bytes is taken from the
  * stream-ordered allocator (hipMallocAsync) and freed on the same stream.
  * l = 0 is a no-op. */
 EBC_API ebc_status ebc_eval_sets(ebc_dataset* ds, const int64_t* offsets, const int32_t* idx, int64_t l,

@@ -15,7 +15,7 @@
 // (ceil(|S_j|/4) units, padding rows contribute -inf); units of consecutive
 // sets follow each other, 8 units form a 32-row member block (in the MFMA
 // result a unit is the 4 rows one lane half holds), and a group is every set
-// whose first unit lies in one window of 64 units. A work item is (group,
+// whose first unit lies in one window of 128 units. A work item is (group,
 // ground-set split); a workgroup (4 waves) walks the group's member blocks
 // through a double-buffered LDS stage (the next block's rows are gathered
 // into registers while the current one is multiplied) while each wave holds
@@ -37,9 +37,9 @@ namespace {
 
 constexpr int kUnitRows = 4;    // rows per unit
 constexpr int kBlockUnits = 8;  // units per 32-row member block
-constexpr int kWindow = 64;     // units per group window
+constexpr int kWindow = 128;    // units per group window
 constexpr int kVSub = 256;      // ground points per workgroup pass (4 waves x 64)
-constexpr int kMaxSplits = 8;
+constexpr int kMaxSplits = 16;
 
 // Scratch of one call: unit prefix U[l+1], non-empty prefix E[l+1], set
 // status (0 ok, 1 bad), group count, per-split partial sums [splits][l].
@@ -227,7 +227,7 @@ k_es_main(const float* __restrict__ x, int64_t n, int32_t d, const double* __res
                 t_e[i] = sc.E[j0 + i];
                 t_off[i] = off[j0 + i];
             }
-        if (tid < 4 * kWindow) acc_set[tid / kWindow][tid % kWindow] = 0.0;
+        for (int i = tid; i < 4 * kWindow; i += 256) acc_set[i / kWindow][i % kWindow] = 0.0;
         __syncthreads();
         const SetTable tb = cached ? SetTable{t_u, t_e, t_off, j0} : SetTable{sc.U, sc.E, off, 0};
         if (u1 > u0 && v_end > v_begin) {
@@ -239,10 +239,25 @@ k_es_main(const float* __restrict__ x, int64_t n, int32_t d, const double* __res
                 for (int cb = 0; cb < 2; ++cb) {
                     const int64_t v = vs + wave * 64 + cb * 32 + col;
                     const bool ok = v < v_end;
+                    if (d % 4 == 0) {
+                        // rows 16-byte aligned: 4 values per load; a 4-group is
+                        // either wholly inside the row or wholly padding
 #pragma unroll
-                    for (int s = 0; s < KH; ++s) {
-                        const int k = half * KH + s;
-                        b[cb][s] = (ok && k < d) ? x[v * d + k] : 0.0f;
+                        for (int s4 = 0; s4 < KH / 4; ++s4) {
+                            const int k = half * KH + 4 * s4;
+                            float4 q = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                            if (ok && k < d) q = *reinterpret_cast<const float4*>(x + v * d + k);
+                            b[cb][4 * s4 + 0] = q.x;
+                            b[cb][4 * s4 + 1] = q.y;
+                            b[cb][4 * s4 + 2] = q.z;
+                            b[cb][4 * s4 + 3] = q.w;
+                        }
+                    } else {
+#pragma unroll
+                        for (int s = 0; s < KH; ++s) {
+                            const int k = half * KH + s;
+                            b[cb][s] = (ok && k < d) ? x[v * d + k] : 0.0f;
+                        }
                     }
                 }
                 float cur[2] = {-INFINITY, -INFINITY};
