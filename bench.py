@@ -35,6 +35,7 @@ WORKLOADS = {
     "batched512_bf16_k20": ("batched_instances", {"seed": 4}),
     "serving_curves_d64_bf16": ("serving_requests", {"seed": 5}),
     "paper_sets_n50000_l5000_k10_d100": ("paper_sets", {"seed": 6}),
+    "paper_sets_sweep_d100": ("paper_sets", {"seed": 6}),
 }
 
 
@@ -285,6 +286,65 @@ def bench_sets(args):
     print(json.dumps(res), flush=True)
 
 
+def bench_sets_sweep(args):
+    """The paper's runtime sweep (Sec. 5.1) on ebc_eval_sets: from the defaults
+    |V| = 50000, l = 5000, k = 10 (d = 100, N(0,1) data, random sets), vary
+    one of N, l, k at a time over the paper's ranges. Each point: median of
+    args.steps calls after args.warmup. One JSON line with every point."""
+    import numpy as np
+    import torch
+
+    from paper_2105_12026_amd import ebc, workloads
+
+    series = {
+        "N": [("n", v) for v in range(1000, 400001, 28500)],
+        "l": [("l", v) for v in range(1000, 26071, 2785)],
+        "k": [("set_size", v) for v in range(10, 431, 35)],
+    }
+    dev = torch.device("cuda:0")
+    points = []
+    for name, pts in series.items():
+        for key, val in pts:
+            kw = {"n": 50000, "l": 5000, "set_size": 10}
+            kw[key] = val
+            p = workloads.paper_sets(seed=6, **kw)
+            ds = ebc.Dataset(torch.from_numpy(p.x).to(dev), dtype="f32")
+            off = torch.from_numpy(p.offsets).to(dev)
+            idx = torch.from_numpy(p.idx).to(dev)
+            out = torch.empty(kw["l"], dtype=torch.float64, device=dev)
+            for _ in range(args.warmup):
+                ds.eval_sets(off, idx, out=out)
+            times = []
+            for _ in range(args.steps):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                ds.eval_sets(off, idx, out=out)
+                e1.record()
+                torch.cuda.synchronize()
+                times.append(e0.elapsed_time(e1))
+            ds.sync()
+            ms = float(np.median(times))
+            pairs = float(kw["n"]) * kw["l"] * kw["set_size"]
+            tf = 2.0 * 100 * pairs / (ms * 1e-3) / 1e12
+            points.append({"vary": name, **kw, "ms": round(ms, 4), "pair_evals_per_s": pairs / (ms * 1e-3),
+                           "tflops": round(tf, 2)})
+            print(f"# {name}={val}: {ms:.3f} ms, {tf:.1f} TFLOP/s", file=sys.stderr, flush=True)
+            del ds, off, idx, out
+    best = max(pt["pair_evals_per_s"] for pt in points)
+    dflt = [pt for pt in points if pt["n"] == 50000 and pt["l"] == 5000 and pt["set_size"] == 10][0]
+    res = {
+        "metric": "set-member x point distance evals/s (ebc_eval_sets, paper sweep)",
+        "value": dflt["pair_evals_per_s"], "unit": "pair-evals/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": dflt["ms"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "paper_sets_sweep_d100", "points": points, "best_pair_evals_per_s": best},
+        "roofline": {"bound": "mfma", "achieved": dflt["tflops"], "peak": PEAK_TFLOPS["f32"], "unit": "TFLOP/s",
+                     "frac": round(dflt["tflops"] / PEAK_TFLOPS["f32"], 4), "traffic": None,
+                     "kernel": "whole ebc_eval_sets call at the defaults, 2*d flops per (member, point) pair"},
+    }
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -312,6 +372,9 @@ def main():
         return
     if args.workload.startswith("serving"):
         bench_serving(args)
+        return
+    if args.workload == "paper_sets_sweep_d100":
+        bench_sets_sweep(args)
         return
     if args.workload.startswith("paper_sets"):
         bench_sets(args)

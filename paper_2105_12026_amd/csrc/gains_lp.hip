@@ -511,9 +511,11 @@ __device__ __forceinline__ void pp_lead(int64_t t, int64_t nt, int64_t t_begin, 
     constexpr int NCB = TileRegs<G>::NCB;
     if (t + 2 < nt) copy_stage<G>(wave, lane, t_begin + t + 2, xqt, ha, hm, sc, nx2);
     floatx16 acc[NCB][CB];
+    // the whole matrix phase at raised priority (lowered after the barrier
+    // that ends it), so each MFMA issues as soon as the matrix pipe takes it
+    // even while the other wave has VALU work
     __builtin_amdgcn_s_setprio(1);
     mfma_tile<G, DT, KC, CB>(r, a, cinit, sa, acc);
-    __builtin_amdgcn_s_setprio(0);
     float lo[NCB], hi[NCB];
 #pragma unroll
     for (int c = 0; c < NCB; ++c) {
@@ -528,6 +530,7 @@ __device__ __forceinline__ void pp_lead(int64_t t, int64_t nt, int64_t t_begin, 
             wait_vmcnt<0>();
     }
     phase_barrier();
+    __builtin_amdgcn_s_setprio(0);
     if (t + 1 < nt) read_tile<G>(nxt, col, half, r);
     epilogue_tile<NCB, CB>(acc, lo, hi, acc_sum, lo_sum);
     phase_barrier();
@@ -541,9 +544,11 @@ __device__ __forceinline__ void pp_follow(int64_t t, int64_t nt, int col, int ha
                                           const int (&sa)[CB], float (&acc_sum)[CB][16], double& lo_sum) {
     constexpr int NCB = TileRegs<G>::NCB;
     floatx16 acc[NCB][CB];
+    // the whole matrix phase at raised priority (lowered after the barrier
+    // that ends it), so each MFMA issues as soon as the matrix pipe takes it
+    // even while the other wave has VALU work
     __builtin_amdgcn_s_setprio(1);
     mfma_tile<G, DT, KC, CB>(r, a, cinit, sa, acc);
-    __builtin_amdgcn_s_setprio(0);
     float lo[NCB], hi[NCB];
 #pragma unroll
     for (int c = 0; c < NCB; ++c) {
@@ -551,6 +556,7 @@ __device__ __forceinline__ void pp_follow(int64_t t, int64_t nt, int col, int ha
         hi[c] = r.hm[c] - r.ha[c];
     }
     phase_barrier();
+    __builtin_amdgcn_s_setprio(0);
     if (t + 1 < nt) read_tile<G>(nxt, col, half, r);
     epilogue_tile<NCB, CB>(acc, lo, hi, acc_sum, lo_sum);
     if (t + 1 < nt) phase_barrier();
