@@ -9,7 +9,7 @@
 namespace ebc {
 
 constexpr int kWindowCap = 1024;   // candidates that may enter the re-score window list
-constexpr int kWindowMax = 64;     // candidates actually re-scored in float64 per step
+constexpr int kWindowMax = 256;    // candidates actually re-scored in float64 per step
 constexpr int kRowAlign = 256;     // rows of every per-point array are padded to this (= kBlock)
 constexpr int kBlock = 256;        // threads of the per-point kernels
 constexpr int kGainsCandTile = 128;  // candidates per gains workgroup (4 waves x 32)
