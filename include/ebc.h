@@ -63,7 +63,8 @@ typedef enum {
  * round-to-nearest-even; products accumulate in FP32; the norms are FP32 of
  * the cast rows; m_v, L({e0}), f, the window re-score and every cross-block
  * sum stay FP64, so greedy selections are re-scored exactly. ebc_eval_sets
- * always uses FP32 direct differences.
+ * uses FP32 dot products of the caller's rows; ebc_eval_sets_in_dtype uses
+ * this dtype.
  *   EBC_DT_F32       float32 (v_mfma_f32_32x32x2_f32)
  *   EBC_DT_F16       IEEE half; |x| > 65504 raises EBC_E_RANGE
  *   EBC_DT_BF16      bfloat16
@@ -123,6 +124,14 @@ EBC_API ebc_status ebc_dataset_destroy(ebc_dataset* ds);
  * l = 0 is a no-op. */
 EBC_API ebc_status ebc_eval_sets(ebc_dataset* ds, const int64_t* offsets, const int32_t* idx, int64_t l,
                          double* f_out, void* stream);
+
+/* The same f(S_j) with the dot products in the dataset's distance dtype (the
+ * paper compares FP16 with FP32 GPU evaluation, Sec. 5): the cast rows and
+ * their FP32 norms, the dtype's matrix instruction (FP8 with the rows' E8M0
+ * scales), FP32 maxima, FP64 sums. Same arguments, errors and scratch as
+ * ebc_eval_sets; identical to it for EBC_DT_F32 datasets. */
+EBC_API ebc_status ebc_eval_sets_in_dtype(ebc_dataset* ds, const int64_t* offsets, const int32_t* idx, int64_t l,
+                                          double* f_out, void* stream);
 
 /* Marginal gains Delta(c|S) = f(S u {c}) - f(S) (Sec. 3, Definition
  * "Discrete derivative") for candidates c, computed in the form

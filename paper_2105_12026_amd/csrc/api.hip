@@ -195,14 +195,24 @@ ebc_status ebc_dataset_get_info(ebc_dataset* ds, ebc_dataset_info* info) {
     return EBC_OK;
 }
 
-ebc_status ebc_eval_sets(ebc_dataset* ds, const int64_t* offsets, const int32_t* idx, int64_t l,
-                         double* f_out, void* stream) {
+static ebc_status eval_sets_impl(ebc_dataset* ds, const int64_t* offsets, const int32_t* idx, int64_t l,
+                                 double* f_out, bool in_dtype, void* stream) {
     if (!ds || l < 0) return EBC_E_INVALID_ARG;
     if (l == 0) return EBC_OK;
     if (!offsets || !f_out) return EBC_E_INVALID_ARG;
     if (!idx) return EBC_E_INVALID_ARG;
     if (l > (int64_t(1) << 31) * 4 - 4) return EBC_E_INVALID_ARG;
-    return from_hip(launch_eval_sets(ds, offsets, idx, l, f_out, as_stream(stream)));
+    return from_hip(launch_eval_sets(ds, offsets, idx, l, f_out, in_dtype, as_stream(stream)));
+}
+
+ebc_status ebc_eval_sets(ebc_dataset* ds, const int64_t* offsets, const int32_t* idx, int64_t l,
+                         double* f_out, void* stream) {
+    return eval_sets_impl(ds, offsets, idx, l, f_out, false, stream);
+}
+
+ebc_status ebc_eval_sets_in_dtype(ebc_dataset* ds, const int64_t* offsets, const int32_t* idx, int64_t l,
+                                  double* f_out, void* stream) {
+    return eval_sets_impl(ds, offsets, idx, l, f_out, true, stream);
 }
 
 ebc_status ebc_marginal_gains(ebc_dataset* ds, const double* m, const int32_t* cand, int64_t n_cand,

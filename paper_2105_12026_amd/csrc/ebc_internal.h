@@ -289,6 +289,6 @@ hipError_t launch_gains_out(const ebc_dataset* ds, int64_t n_cand, double* out, 
 hipError_t launch_greedy_step(const ebc_dataset* ds, int32_t t, int32_t* sel_out, double* f_out,
                               double* gain_out, hipStream_t s, hipEvent_t ev_gains_done);
 hipError_t launch_eval_sets(const ebc_dataset* ds, const int64_t* offsets, const int32_t* idx,
-                            int64_t l, double* f_out, hipStream_t s);
+                            int64_t l, double* f_out, bool in_dtype, hipStream_t s);
 
 }  // namespace ebc

@@ -28,10 +28,9 @@
 #include <math.h>
 
 #include "ebc_internal.h"
+#include "lp_mfma.h"
 
 namespace ebc {
-
-typedef float floatx16 __attribute__((ext_vector_type(16)));
 
 namespace {
 
@@ -142,6 +141,7 @@ __device__ __forceinline__ int64_t owner_of(const int64_t* __restrict__ U, int64
 struct BlockInfo {
     int32_t row_mem[32];             // member row of V, -1 for padding
     float row_c[32];                 // -n_s/2, or -inf for padding
+    int32_t row_sc[32];              // E8M0 row scale (FP8 rows; 127 otherwise)
     int32_t unit_flags[kBlockUnits];  // bit0 first unit of its set, bit1 last, bit2 valid
     int32_t unit_local[kBlockUnits];  // the set's index within the group
 };
@@ -158,9 +158,12 @@ struct SetTable {
 };
 
 // Threads 0..31 fill the rows, threads 32..39 the units of block blk.
+// Norms: n64 (float64 ||s||^2 of the float32 rows) when hn is null, else hn
+// (float32 ||s^||^2 / 2 of the cast rows); sc: FP8 row scales or null.
 __device__ __forceinline__ void block_info(int tid, int64_t blk, int64_t u0, int64_t u1, int64_t j0, int64_t j1,
                                            const SetTable& tb, const int32_t* __restrict__ idx,
-                                           const double* __restrict__ n64, BlockInfo& bi) {
+                                           const double* __restrict__ n64, const float* __restrict__ hn,
+                                           const int* __restrict__ sc, BlockInfo& bi) {
     if (tid < 32) {
         const int64_t u = u0 + blk * kBlockUnits + tid / kUnitRows;
         int32_t mem = -1;
@@ -170,7 +173,8 @@ __device__ __forceinline__ void block_info(int tid, int64_t blk, int64_t u0, int
             if (tb.off[j] + q < tb.off[j + 1]) mem = idx[tb.off[j] + q];
         }
         bi.row_mem[tid] = mem;
-        bi.row_c[tid] = mem >= 0 ? -float(0.5 * n64[mem]) : -INFINITY;
+        bi.row_c[tid] = mem < 0 ? -INFINITY : (hn ? -hn[mem] : -float(0.5 * n64[mem]));
+        bi.row_sc[tid] = (mem >= 0 && sc) ? sc[mem] : 127;
     } else if (tid < 32 + kBlockUnits) {
         const int uu = tid - 32;
         const int64_t u = u0 + blk * kBlockUnits + uu;
@@ -182,6 +186,35 @@ __device__ __forceinline__ void block_info(int tid, int64_t blk, int64_t u0, int
         }
         bi.unit_flags[uu] = flags;
         bi.unit_local[uu] = loc;
+    }
+}
+
+// Units of 4 rows of one member block against this wave's 64 points: unit
+// uu is held by lane half uu%2 in result registers 4*(uu/2) .. +3. Running
+// maximum per (set, point) in cur (per 32-point block); at a set's last unit
+// the two lane halves are joined, clamped at 0 and the 32 columns summed in
+// float64 into the set's per-wave accumulator.
+__device__ __forceinline__ void es_units(const floatx16 (&acc)[2], const BlockInfo& bi, float (&cur)[2], int half,
+                                         int lane, int wave, double (&acc_set)[4][kWindow]) {
+#pragma unroll
+    for (int uu = 0; uu < kBlockUnits; ++uu) {
+        const int flags = bi.unit_flags[uu];
+        if (!(flags & 4)) continue;
+        const int j4 = 4 * (uu >> 1);
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb) {
+            if (flags & 1) cur[cb] = -INFINITY;
+            const float m = fmaxf(fmaxf(acc[cb][j4 + 0], acc[cb][j4 + 1]), fmaxf(acc[cb][j4 + 2], acc[cb][j4 + 3]));
+            if (half == (uu & 1)) cur[cb] = fmaxf(cur[cb], m);
+        }
+        if (flags & 2) {
+            double sv = 0.0;
+#pragma unroll
+            for (int cb = 0; cb < 2; ++cb) sv += double(fmaxf(fmaxf(cur[cb], __shfl_xor(cur[cb], 32, 64)), 0.0f));
+#pragma unroll
+            for (int o = 16; o > 0; o >>= 1) sv += __shfl_xor(sv, o, 64);
+            if (lane == 0) acc_set[wave][bi.unit_local[uu]] += sv;
+        }
     }
 }
 
@@ -262,8 +295,8 @@ k_es_main(const float* __restrict__ x, int64_t n, int32_t d, const double* __res
                 }
                 float cur[2] = {-INFINITY, -INFINITY};
                 // prologue: bookkeeping of blocks 0 and 1, rows of block 0
-                block_info(tid, 0, u0, u1, j0, j1, tb, idx, n64, info[0]);
-                if (nblk > 1) block_info(tid, 1, u0, u1, j0, j1, tb, idx, n64, info[1]);
+                block_info(tid, 0, u0, u1, j0, j1, tb, idx, n64, nullptr, nullptr, info[0]);
+                if (nblk > 1) block_info(tid, 1, u0, u1, j0, j1, tb, idx, n64, nullptr, nullptr, info[1]);
                 __syncthreads();
                 {
                     const int32_t mem = info[0].row_mem[grow];
@@ -290,7 +323,8 @@ k_es_main(const float* __restrict__ x, int64_t n, int32_t d, const double* __res
                         }
                     }
                     // bookkeeping of block blk+2 (its slot was last read in block blk-1)
-                    if (blk + 2 < nblk) block_info(tid, blk + 2, u0, u1, j0, j1, tb, idx, n64, info[(blk + 2) % 3]);
+                    if (blk + 2 < nblk)
+                        block_info(tid, blk + 2, u0, u1, j0, j1, tb, idx, n64, nullptr, nullptr, info[(blk + 2) % 3]);
                     // member rows x this wave's points
                     floatx16 acc[2];
 #pragma unroll
@@ -309,29 +343,7 @@ k_es_main(const float* __restrict__ x, int64_t n, int32_t d, const double* __res
                                 acc[cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[i], b[cb][4 * s4 + i], acc[cb], 0,
                                                                                0, 0);
                     }
-                    // units of 4 rows: unit uu is held by lane half uu%2 in registers 4*(uu/2) .. +3
-#pragma unroll
-                    for (int uu = 0; uu < kBlockUnits; ++uu) {
-                        const int flags = bi.unit_flags[uu];
-                        if (!(flags & 4)) continue;
-                        const int j4 = 4 * (uu >> 1);
-#pragma unroll
-                        for (int cb = 0; cb < 2; ++cb) {
-                            if (flags & 1) cur[cb] = -INFINITY;
-                            const float m = fmaxf(fmaxf(acc[cb][j4 + 0], acc[cb][j4 + 1]),
-                                                  fmaxf(acc[cb][j4 + 2], acc[cb][j4 + 3]));
-                            if (half == (uu & 1)) cur[cb] = fmaxf(cur[cb], m);
-                        }
-                        if (flags & 2) {
-                            // set complete for these 64 points: join the halves, clamp, sum the columns
-                            double sv = 0.0;
-#pragma unroll
-                            for (int cb = 0; cb < 2; ++cb) sv += double(fmaxf(fmaxf(cur[cb], __shfl_xor(cur[cb], 32, 64)), 0.0f));
-#pragma unroll
-                            for (int o = 16; o > 0; o >>= 1) sv += __shfl_xor(sv, o, 64);
-                            if (lane == 0) acc_set[wave][bi.unit_local[uu]] += sv;
-                        }
-                    }
+                    es_units(acc, bi, cur, half, lane, wave, acc_set);
                     if (more) {
                         float* dst = reinterpret_cast<float*>(lds_m4[rb ^ 1]) + grow * S;
 #pragma unroll
@@ -344,6 +356,141 @@ k_es_main(const float* __restrict__ x, int64_t n, int32_t d, const double* __res
         __syncthreads();
         // fixed-order combination over the waves; one write per non-empty set
         // of the group and split (zero when the split has no points)
+        for (int64_t j = j0 + tid; j < j1; j += 256) {
+            if (sc.E[j + 1] == sc.E[j]) continue;
+            const int loc = int(sc.E[j] - sc.E[j0]);
+            sc.part[int64_t(split) * l + j] = ((acc_set[0][loc] + acc_set[1][loc]) + acc_set[2][loc]) + acc_set[3][loc];
+        }
+        __syncthreads();
+    }
+}
+
+// The same evaluation with the dot products in the dataset's reduced
+// precision (the paper's FP16 GPU variant, Sec. 5): member and ground-point
+// rows come from the cast copy (64-row tiles of 16-byte units, unit-major),
+// the norms are those of the cast rows, the matrix instruction is the
+// dtype's 32x32 one (FP8 with the rows' E8M0 scales); maxima, clamps and
+// sums as above.
+template <int DT, int KC>
+__global__ void __launch_bounds__(256)
+k_es_lp(const uint4* __restrict__ xq, const float* __restrict__ hn, const int* __restrict__ scale, int64_t n,
+        const double* __restrict__ n64, const int64_t* __restrict__ off, const int32_t* __restrict__ idx, int64_t l,
+        int32_t splits, EsScratch sc) {
+    using T = Lp<DT>;
+    constexpr int HU = KC * T::kU4;  // 16-byte units per lane half-row
+    constexpr int RU = 2 * HU;       // units per row
+    constexpr int PFU = (32 * RU + 255) / 256;
+    constexpr bool kFp8 = DT == EBC_DT_FP8_E4M3;
+    __shared__ uint4 lds_m[2][RU * 32];  // [unit][row]
+    __shared__ BlockInfo info[3];
+    __shared__ int64_t t_u[kTab + 1], t_off[kTab + 1];
+    __shared__ int32_t t_e[kTab + 1];
+    __shared__ double acc_set[4][kWindow];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int col = lane & 31;
+    const int half = lane >> 5;
+    const int64_t n_items = *sc.n_groups * splits;
+    const int64_t vchunk = ((n + splits - 1) / splits + kVSub - 1) / kVSub * kVSub;
+    const int* sc_rows = kFp8 ? scale : nullptr;
+
+    for (int64_t item = blockIdx.x; item < n_items; item += gridDim.x) {
+        const int64_t g = item / splits;
+        const int split = int(item % splits);
+        const int64_t j0 = lower_bound_u(sc.U, 0, l, g * kWindow);
+        const int64_t j1 = lower_bound_u(sc.U, j0, l, (g + 1) * kWindow);
+        const int64_t u0 = sc.U[j0], u1 = sc.U[j1];
+        const int64_t v_begin = int64_t(split) * vchunk;
+        int64_t v_end = v_begin + vchunk;
+        if (v_end > n) v_end = n;
+        const bool cached = j1 - j0 <= kTab;
+        if (cached)
+            for (int64_t i = tid; i <= j1 - j0; i += 256) {
+                t_u[i] = sc.U[j0 + i];
+                t_e[i] = sc.E[j0 + i];
+                t_off[i] = off[j0 + i];
+            }
+        for (int i = tid; i < 4 * kWindow; i += 256) acc_set[i / kWindow][i % kWindow] = 0.0;
+        __syncthreads();
+        const SetTable tb = cached ? SetTable{t_u, t_e, t_off, j0} : SetTable{sc.U, sc.E, off, 0};
+        if (u1 > u0 && v_end > v_begin) {
+            const int64_t nblk = (u1 - u0 + kBlockUnits - 1) / kBlockUnits;
+            for (int64_t vs = v_begin; vs < v_end; vs += kVSub) {
+                // this wave's 64 ground points (B operand): the lane half's units
+                uint4 b[2][HU];
+                int sb[2];
+#pragma unroll
+                for (int cb = 0; cb < 2; ++cb) {
+                    const int64_t v = vs + wave * 64 + cb * 32 + col;
+                    const bool ok = v < v_end;
+                    const uint4* src = xq + (v / 64) * (RU * 64) + (v % 64);
+#pragma unroll
+                    for (int u = 0; u < HU; ++u) b[cb][u] = ok ? src[(half * HU + u) * 64] : make_uint4(0, 0, 0, 0);
+                    sb[cb] = (kFp8 && ok) ? scale[v] : 127;
+                }
+                float cur[2] = {-INFINITY, -INFINITY};
+                block_info(tid, 0, u0, u1, j0, j1, tb, idx, n64, hn, sc_rows, info[0]);
+                if (nblk > 1) block_info(tid, 1, u0, u1, j0, j1, tb, idx, n64, hn, sc_rows, info[1]);
+                __syncthreads();
+#pragma unroll
+                for (int i = 0; i < PFU; ++i) {
+                    const int e = tid + 256 * i;
+                    if (e < 32 * RU) {
+                        const int r = e % 32, u = e / 32;
+                        const int32_t mem = info[0].row_mem[r];
+                        lds_m[0][u * 32 + r] =
+                            mem >= 0 ? xq[(int64_t(mem) / 64 * RU + u) * 64 + mem % 64] : make_uint4(0, 0, 0, 0);
+                    }
+                }
+                __syncthreads();
+                for (int64_t blk = 0; blk < nblk; ++blk) {
+                    const int rb = int(blk & 1);
+                    const BlockInfo& bi = info[blk % 3];
+                    uint4 pf[PFU];
+                    const bool more = blk + 1 < nblk;
+                    if (more) {
+#pragma unroll
+                        for (int i = 0; i < PFU; ++i) {
+                            const int e = tid + 256 * i;
+                            pf[i] = make_uint4(0, 0, 0, 0);
+                            if (e < 32 * RU) {
+                                const int32_t mem = info[(blk + 1) % 3].row_mem[e % 32];
+                                if (mem >= 0) pf[i] = xq[(int64_t(mem) / 64 * RU + e / 32) * 64 + mem % 64];
+                            }
+                        }
+                    }
+                    if (blk + 2 < nblk)
+                        block_info(tid, blk + 2, u0, u1, j0, j1, tb, idx, n64, hn, sc_rows, info[(blk + 2) % 3]);
+                    // member rows (A, from LDS) x this wave's points (B)
+                    uint4 a[HU];
+#pragma unroll
+                    for (int u = 0; u < HU; ++u) a[u] = lds_m[rb][(half * HU + u) * 32 + col];
+                    const int sa = bi.row_sc[col];
+                    floatx16 acc[2];
+#pragma unroll
+                    for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+                        for (int r = 0; r < 16; ++r) acc[cb][r] = bi.row_c[8 * (r / 4) + 4 * half + (r % 4)];
+#pragma unroll
+                    for (int q = 0; q < KC; ++q)
+#pragma unroll
+                        for (int cb = 0; cb < 2; ++cb)
+                            acc[cb] = mfma_main<DT>(&a[q * T::kU4], &b[cb][q * T::kU4], acc[cb], sa, sb[cb]);
+                    es_units(acc, bi, cur, half, lane, wave, acc_set);
+                    if (more) {
+#pragma unroll
+                        for (int i = 0; i < PFU; ++i) {
+                            const int e = tid + 256 * i;
+                            if (e < 32 * RU) lds_m[rb ^ 1][(e / 32) * 32 + e % 32] = pf[i];
+                        }
+                    }
+                    __syncthreads();
+                }
+            }
+        }
+        __syncthreads();
         for (int64_t j = j0 + tid; j < j1; j += 256) {
             if (sc.E[j + 1] == sc.E[j]) continue;
             const int loc = int(sc.E[j] - sc.E[j0]);
@@ -380,7 +527,7 @@ void launch_es_main(dim3 g, hipStream_t s, const ebc_dataset* ds, const int64_t*
 }  // namespace
 
 hipError_t launch_eval_sets(const ebc_dataset* ds, const int64_t* offsets, const int32_t* idx, int64_t l,
-                            double* f_out, hipStream_t s) {
+                            double* f_out, bool in_dtype, hipStream_t s) {
     // ground-set splits: as many as keep every split at least one pass long
     int32_t splits = int32_t((ds->n + kVSub - 1) / kVSub);
     if (splits > kMaxSplits) splits = kMaxSplits;
@@ -407,14 +554,53 @@ hipError_t launch_eval_sets(const ebc_dataset* ds, const int64_t* offsets, const
     hipLaunchKernelGGL(k_es_scan, dim3(1), dim3(1024), 0, s, l, sc);
     // persistent grid over (group, split) items; the item count is read on the device
     const dim3 g = dim3(2048);
-    const int kp = (ds->d + 7) / 8 * 8;
-    switch (kp) {
+    if (in_dtype && ds->dt != EBC_DT_F32) {
+        const int kc = ds->k_pad / (ds->dt == EBC_DT_FP8_E4M3 ? 64 : 16);
+        const uint4* xq = static_cast<const uint4*>(static_cast<const void*>(ds->b.xq));
+#define EBC_ESL(DTV, K)                                                                                         \
+    case K:                                                                                                     \
+        hipLaunchKernelGGL((k_es_lp<DTV, K>), g, dim3(256), 0, s, xq, ds->b.hn, ds->b.scale, ds->n, ds->b.n64, \
+                           offsets, idx, l, splits, sc);                                                        \
+        break;
+        bool ok = true;
+        switch (ds->dt) {
+            case EBC_DT_BF16:
+                switch (kc) {
+                    EBC_ESL(EBC_DT_BF16, 1) EBC_ESL(EBC_DT_BF16, 2) EBC_ESL(EBC_DT_BF16, 3) EBC_ESL(EBC_DT_BF16, 4)
+                    EBC_ESL(EBC_DT_BF16, 5) EBC_ESL(EBC_DT_BF16, 6) EBC_ESL(EBC_DT_BF16, 7) EBC_ESL(EBC_DT_BF16, 8)
+                    default: ok = false;
+                }
+                break;
+            case EBC_DT_F16:
+                switch (kc) {
+                    EBC_ESL(EBC_DT_F16, 1) EBC_ESL(EBC_DT_F16, 2) EBC_ESL(EBC_DT_F16, 3) EBC_ESL(EBC_DT_F16, 4)
+                    EBC_ESL(EBC_DT_F16, 5) EBC_ESL(EBC_DT_F16, 6) EBC_ESL(EBC_DT_F16, 7) EBC_ESL(EBC_DT_F16, 8)
+                    default: ok = false;
+                }
+                break;
+            case EBC_DT_FP8_E4M3:
+                switch (kc) {
+                    EBC_ESL(EBC_DT_FP8_E4M3, 1) EBC_ESL(EBC_DT_FP8_E4M3, 2)
+                    default: ok = false;
+                }
+                break;
+            default: ok = false;
+        }
+#undef EBC_ESL
+        if (!ok) {
+            (void)hipFreeAsync(base, s);
+            return hipErrorInvalidValue;
+        }
+    } else {
+        const int kp = (ds->d + 7) / 8 * 8;
+        switch (kp) {
 #define EBC_ES(K) \
     case K: launch_es_main<K>(g, s, ds, offsets, idx, l, splits, sc); break;
-        EBC_ES(8) EBC_ES(16) EBC_ES(24) EBC_ES(32) EBC_ES(40) EBC_ES(48) EBC_ES(56) EBC_ES(64)
-        EBC_ES(72) EBC_ES(80) EBC_ES(88) EBC_ES(96) EBC_ES(104) EBC_ES(112) EBC_ES(120) EBC_ES(128)
+            EBC_ES(8) EBC_ES(16) EBC_ES(24) EBC_ES(32) EBC_ES(40) EBC_ES(48) EBC_ES(56) EBC_ES(64)
+            EBC_ES(72) EBC_ES(80) EBC_ES(88) EBC_ES(96) EBC_ES(104) EBC_ES(112) EBC_ES(120) EBC_ES(128)
 #undef EBC_ES
-        default: (void)hipFreeAsync(base, s); return hipErrorInvalidValue;
+            default: (void)hipFreeAsync(base, s); return hipErrorInvalidValue;
+        }
     }
     hipLaunchKernelGGL(k_es_final, dim3(nb), dim3(256), 0, s, l, ds->n, splits, sc, f_out);
     e = hipGetLastError();

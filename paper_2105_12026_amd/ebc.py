@@ -21,7 +21,7 @@ __all__ = ["EBCError", "Dataset", "Batch", "Server", "Arena", "request_bytes", "
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libebc.so")
 DTYPES = {"f32": 0, "f16": 1, "bf16": 2, "fp8": 3}
 ABI_FUNCTIONS = (
-    "ebc_dataset_bytes", "ebc_dataset_create", "ebc_dataset_destroy", "ebc_eval_sets",
+    "ebc_dataset_bytes", "ebc_dataset_create", "ebc_dataset_destroy", "ebc_eval_sets", "ebc_eval_sets_in_dtype",
     "ebc_marginal_gains", "ebc_greedy", "ebc_sync_status", "ebc_status_string",
     "ebc_dataset_get_info", "ebc_profile_enable", "ebc_profile_read", "ebc_set_gains_variant",
     "ebc_gains_variant_count", "ebc_set_greedy_graph", "ebc_batch_bytes", "ebc_batch_create",
@@ -73,6 +73,7 @@ def lib() -> ctypes.CDLL:
                                          ctypes.POINTER(P)]
         L.ebc_dataset_destroy.argtypes = [P]
         L.ebc_eval_sets.argtypes = [P, P, P, i64, P, P]
+        L.ebc_eval_sets_in_dtype.argtypes = [P, P, P, i64, P, P]
         L.ebc_marginal_gains.argtypes = [P, P, P, i64, P, P]
         L.ebc_greedy.argtypes = [P, i32, P, P, P, P]
         L.ebc_sync_status.argtypes = [P, P, ctypes.POINTER(_Stats)]
@@ -226,16 +227,17 @@ class Dataset:
         return {f: getattr(pr, f) for f, _ in _Profile._fields_}
 
     def eval_sets(self, offsets: torch.Tensor, idx: torch.Tensor, out: torch.Tensor | None = None,
-                  stream=None) -> torch.Tensor:
-        """f(S_j) for CSR sets (offsets int64 [l+1], idx int32 [nnz]); float64 [l]."""
+                  stream=None, in_dtype: bool = False) -> torch.Tensor:
+        """f(S_j) for CSR sets (offsets int64 [l+1], idx int32 [nnz]); float64 [l].
+        in_dtype: dot products in the dataset's distance dtype instead of float32."""
         offsets = offsets.to(device=self.x.device, dtype=torch.int64).contiguous()
         idx = idx.to(device=self.x.device, dtype=torch.int32).contiguous()
         l = offsets.numel() - 1
         if out is None:
             out = torch.empty(max(l, 0), dtype=torch.float64, device=self.x.device)
         idx_arg = idx if idx.numel() > 0 else offsets  # any valid pointer when there are no members
-        _check(lib().ebc_eval_sets(self._h, _ptr(offsets), _ptr(idx_arg), l, _ptr(out), _stream(stream)),
-               "ebc_eval_sets")
+        fn = lib().ebc_eval_sets_in_dtype if in_dtype else lib().ebc_eval_sets
+        _check(fn(self._h, _ptr(offsets), _ptr(idx_arg), l, _ptr(out), _stream(stream)), "ebc_eval_sets")
         return out
 
     def marginal_gains(self, m: torch.Tensor | None = None, cand: torch.Tensor | None = None,

@@ -185,3 +185,39 @@ def test_every_variant_matches_oracle_and_variant0(env, ref, dt, n, d, seed):
             base = g_all
         else:
             np.testing.assert_array_equal(g_all, base, err_msg=f"variant {v}")
+
+
+ES_TOL = {"bf16": 2e-2, "f16": 5e-3, "fp8": 1.5e-1}
+
+
+@pytest.mark.parametrize("dt", ["bf16", "f16", "fp8"])
+@pytest.mark.parametrize("n,d,seed", [(3000, 100, 81), (777, 16, 82), (2049, 64, 83), (300, 128, 84)])
+def test_eval_sets_in_dtype(env, ref, dt, n, d, seed):
+    """Multi-set evaluation with the dot products in the dataset's dtype:
+    sets of many sizes (across unit, block and window boundaries, empty sets
+    between), against the float64 oracle at the dtype's bar (relative to f,
+    with a floor of 1e-3 L({e0})); deterministic; the float32 entry point on
+    the same dataset is unaffected."""
+    torch, ebc = env
+    rng = np.random.default_rng(seed)
+    x = W.gaussian_mixture(rng, n, d, 5).astype(np.float32)
+    sizes = [0, 1, 7, 8, 9, 0, 31, 32, 33, 64, 100, 255, 257, 3, 10, 10] + list(rng.integers(1, 40, 200))
+    sets = [rng.integers(0, n, sz) for sz in sizes]
+    off = np.cumsum([0] + [len(q) for q in sets]).astype(np.int64)
+    idx = np.concatenate(sets).astype(np.int32)
+    print(f"[gpu-case] eval_sets in {dt} n={n} d={d} l={len(sets)}", flush=True)
+    ds = _ds(env, x, dt)
+    to = torch.from_numpy(off)
+    ti = torch.from_numpy(idx)
+    f1 = ds.eval_sets(to, ti, in_dtype=True).cpu().numpy()
+    f2 = ds.eval_sets(to, ti, in_dtype=True).cpu().numpy()
+    f32 = ds.eval_sets(to, ti).cpu().numpy()
+    ds.sync()
+    assert np.array_equal(f1, f2)
+    rf = ref.eval_sets(x, off, idx)
+    l0 = float(np.mean(np.sum(x.astype(np.float64) ** 2, axis=1)))
+    assert np.all(f1[np.array(sizes) == 0] == 0.0)
+    rel = np.abs(f1 - rf) / (np.abs(rf) + 1e-3 * l0)
+    print(f"[gpu-result] eval_sets in {dt} n={n} d={d}: max rel err {rel.max():.3e}", flush=True)
+    assert rel.max() <= ES_TOL[dt]
+    assert np.all(np.abs(f32 - rf) <= 1e-5 * np.abs(rf) + 1e-6 * l0)
