@@ -36,7 +36,10 @@ namespace {
 
 constexpr int kUnitRows = 4;    // rows per unit
 constexpr int kBlockUnits = 8;  // units per 32-row member block
-constexpr int kWindow = 128;    // units per group window
+constexpr int kWindow = 128;    // units per group window (float32 kernel)
+// units per group window of the reduced-precision kernel: its resident
+// member rows and per-set column sums stay within about 64 KB of LDS
+constexpr int lp_window(int dt, int kc) { return 2 * kc * (dt == EBC_DT_FP8_E4M3 ? 2 : 1) <= 8 ? 64 : 32; }
 constexpr int kVSub = 256;      // ground points per workgroup pass (4 waves x 64)
 constexpr int kMaxSplits = 16;
 
@@ -72,7 +75,7 @@ __global__ void __launch_bounds__(256) k_es_units(const int64_t* __restrict__ of
 
 // Single workgroup: inclusive scans of the unit and non-empty counts (in
 // place, U[0] = E[0] = 0), and the number of group windows.
-__global__ void __launch_bounds__(1024) k_es_scan(int64_t l, EsScratch sc) {
+__global__ void __launch_bounds__(1024) k_es_scan(int64_t l, int32_t window, EsScratch sc) {
     __shared__ int64_t su[1024];
     __shared__ int32_t se[1024];
     __shared__ int64_t carry_u;
@@ -109,7 +112,7 @@ __global__ void __launch_bounds__(1024) k_es_scan(int64_t l, EsScratch sc) {
         }
         __syncthreads();
     }
-    if (t == 0) *sc.n_groups = (carry_u + kWindow - 1) / kWindow;
+    if (t == 0) *sc.n_groups = (carry_u + window - 1) / window;
 }
 
 // first j in [lo, hi) with U[j] >= key (hi if none)
@@ -194,8 +197,9 @@ __device__ __forceinline__ void block_info(int tid, int64_t blk, int64_t u0, int
 // maximum per (set, point) in cur (per 32-point block); at a set's last unit
 // the two lane halves are joined, clamped at 0 and the 32 columns summed in
 // float64 into the set's per-wave accumulator.
+template <int WIN>
 __device__ __forceinline__ void es_units(const floatx16 (&acc)[2], const BlockInfo& bi, float (&cur)[2], int half,
-                                         int lane, int wave, double (&acc_set)[4][kWindow]) {
+                                         int lane, int wave, double (&acc_set)[4][WIN]) {
 #pragma unroll
     for (int uu = 0; uu < kBlockUnits; ++uu) {
         const int flags = bi.unit_flags[uu];
@@ -371,7 +375,7 @@ k_es_main(const float* __restrict__ x, int64_t n, int32_t d, const double* __res
 // the norms are those of the cast rows, the matrix instruction is the
 // dtype's 32x32 one (FP8 with the rows' E8M0 scales); maxima, clamps and
 // sums as above.
-template <int DT, int KC>
+template <int DT, int KC, int W>
 __global__ void __launch_bounds__(256)
 k_es_lp(const uint4* __restrict__ xq, const float* __restrict__ hn, const int* __restrict__ scale, int64_t n,
         const double* __restrict__ n64, const int64_t* __restrict__ off, const int32_t* __restrict__ idx, int64_t l,
@@ -381,11 +385,20 @@ k_es_lp(const uint4* __restrict__ xq, const float* __restrict__ hn, const int* _
     constexpr int RU = 2 * HU;       // units per row
     constexpr int PFU = (32 * RU + 255) / 256;
     constexpr bool kFp8 = DT == EBC_DT_FP8_E4M3;
-    __shared__ uint4 lds_m[2][RU * 32];  // [unit][row]
+    constexpr int RB = W / kBlockUnits;  // member blocks a resident group can hold
+    // resident groups (at most W units): all member rows and bookkeeping in LDS
+    __shared__ uint4 res_rows[RB][RU * 32];  // [block][unit][row]
+    __shared__ int32_t res_mem[RB * 32];
+    __shared__ float res_c[RB * 32];
+    __shared__ int32_t res_sc[RB * 32];
+    __shared__ int32_t res_flags[W], res_local[W];
+    __shared__ float lacc[4][W][32];  // per wave, set and column: float sums over points
+    // larger groups (a set longer than the window): stream blocks as in the float32 kernel
+    __shared__ uint4 lds_m[2][RU * 32];
     __shared__ BlockInfo info[3];
     __shared__ int64_t t_u[kTab + 1], t_off[kTab + 1];
     __shared__ int32_t t_e[kTab + 1];
-    __shared__ double acc_set[4][kWindow];
+    __shared__ double acc_set[4][W];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -399,8 +412,8 @@ k_es_lp(const uint4* __restrict__ xq, const float* __restrict__ hn, const int* _
     for (int64_t item = blockIdx.x; item < n_items; item += gridDim.x) {
         const int64_t g = item / splits;
         const int split = int(item % splits);
-        const int64_t j0 = lower_bound_u(sc.U, 0, l, g * kWindow);
-        const int64_t j1 = lower_bound_u(sc.U, j0, l, (g + 1) * kWindow);
+        const int64_t j0 = lower_bound_u(sc.U, 0, l, g * W);
+        const int64_t j1 = lower_bound_u(sc.U, j0, l, (g + 1) * W);
         const int64_t u0 = sc.U[j0], u1 = sc.U[j1];
         const int64_t v_begin = int64_t(split) * vchunk;
         int64_t v_end = v_begin + vchunk;
@@ -412,13 +425,112 @@ k_es_lp(const uint4* __restrict__ xq, const float* __restrict__ hn, const int* _
                 t_e[i] = sc.E[j0 + i];
                 t_off[i] = off[j0 + i];
             }
-        for (int i = tid; i < 4 * kWindow; i += 256) acc_set[i / kWindow][i % kWindow] = 0.0;
+        for (int i = tid; i < 4 * W; i += 256) acc_set[i / W][i % W] = 0.0;
+        for (int i = tid; i < 4 * W * 32; i += 256) (&lacc[0][0][0])[i] = 0.0f;
         __syncthreads();
         const SetTable tb = cached ? SetTable{t_u, t_e, t_off, j0} : SetTable{sc.U, sc.E, off, 0};
-        if (u1 > u0 && v_end > v_begin) {
-            const int64_t nblk = (u1 - u0 + kBlockUnits - 1) / kBlockUnits;
+        const int64_t nunits = u1 - u0;
+        const bool resident = nunits <= W;
+        if (nunits > 0 && v_end > v_begin && resident) {
+            const int nblk = int((nunits + kBlockUnits - 1) / kBlockUnits);
+            // bookkeeping of every row and unit of the group, once per item
+            for (int r = tid; r < nblk * 32; r += 256) {
+                const int64_t u = u0 + r / kUnitRows;
+                int32_t mem = -1;
+                if (u < u1) {
+                    const int64_t jj = owner_of(tb.U, j0 - tb.base, j1 - tb.base, u);
+                    const int64_t q = (u - tb.U[jj]) * kUnitRows + r % kUnitRows;
+                    if (tb.off[jj] + q < tb.off[jj + 1]) mem = idx[tb.off[jj] + q];
+                }
+                res_mem[r] = mem;
+                res_c[r] = mem < 0 ? -INFINITY : -hn[mem];
+                res_sc[r] = (mem >= 0 && kFp8) ? scale[mem] : 127;
+            }
+            for (int uu = tid; uu < nblk * kBlockUnits; uu += 256) {
+                const int64_t u = u0 + uu;
+                int flags = 0, loc = 0;
+                if (u < u1) {
+                    const int64_t jj = owner_of(tb.U, j0 - tb.base, j1 - tb.base, u);
+                    flags = 4 | (u == tb.U[jj] ? 1 : 0) | (u == tb.U[jj + 1] - 1 ? 2 : 0);
+                    loc = tb.E[jj] - tb.E[j0 - tb.base];
+                }
+                res_flags[uu] = flags;
+                res_local[uu] = loc;
+            }
+            __syncthreads();
+            // member rows of the group into LDS
+            for (int e = tid; e < nblk * 32 * RU; e += 256) {
+                const int blk = e / (32 * RU), rem = e % (32 * RU), u = rem / 32, r = rem % 32;
+                const int32_t mem = res_mem[blk * 32 + r];
+                res_rows[blk][u * 32 + r] =
+                    mem >= 0 ? xq[(int64_t(mem) / 64 * RU + u) * 64 + mem % 64] : make_uint4(0, 0, 0, 0);
+            }
+            __syncthreads();
+            // every pass over 64 points per wave reads the resident rows only: no barriers
             for (int64_t vs = v_begin; vs < v_end; vs += kVSub) {
-                // this wave's 64 ground points (B operand): the lane half's units
+                uint4 b[2][HU];
+                int sb[2];
+#pragma unroll
+                for (int cb = 0; cb < 2; ++cb) {
+                    const int64_t v = vs + wave * 64 + cb * 32 + col;
+                    const bool ok = v < v_end;
+                    const uint4* src = xq + (v / 64) * (RU * 64) + (v % 64);
+#pragma unroll
+                    for (int u = 0; u < HU; ++u) b[cb][u] = ok ? src[(half * HU + u) * 64] : make_uint4(0, 0, 0, 0);
+                    sb[cb] = (kFp8 && ok) ? scale[v] : 127;
+                }
+                float cur[2] = {-INFINITY, -INFINITY};
+                for (int blk = 0; blk < nblk; ++blk) {
+                    uint4 a[HU];
+#pragma unroll
+                    for (int u = 0; u < HU; ++u) a[u] = res_rows[blk][(half * HU + u) * 32 + col];
+                    const int sa = res_sc[blk * 32 + col];
+                    floatx16 acc[2];
+#pragma unroll
+                    for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+                        for (int r = 0; r < 16; ++r) acc[cb][r] = res_c[blk * 32 + 8 * (r / 4) + 4 * half + (r % 4)];
+#pragma unroll
+                    for (int q = 0; q < KC; ++q)
+#pragma unroll
+                        for (int cb = 0; cb < 2; ++cb)
+                            acc[cb] = mfma_main<DT>(&a[q * T::kU4], &b[cb][q * T::kU4], acc[cb], sa, sb[cb]);
+                    // units of this block (see es_units); at a set's last unit each
+                    // column's clamped maximum goes to the lane's own accumulator
+#pragma unroll
+                    for (int uu = 0; uu < kBlockUnits; ++uu) {
+                        const int flags = res_flags[blk * kBlockUnits + uu];
+                        if (!(flags & 4)) continue;
+                        const int j4 = 4 * (uu >> 1);
+#pragma unroll
+                        for (int cb = 0; cb < 2; ++cb) {
+                            if (flags & 1) cur[cb] = -INFINITY;
+                            const float m = fmaxf(fmaxf(acc[cb][j4 + 0], acc[cb][j4 + 1]),
+                                                  fmaxf(acc[cb][j4 + 2], acc[cb][j4 + 3]));
+                            if (half == (uu & 1)) cur[cb] = fmaxf(cur[cb], m);
+                        }
+                        if (flags & 2) {
+                            float sv = 0.0f;
+#pragma unroll
+                            for (int cb = 0; cb < 2; ++cb)
+                                sv += fmaxf(fmaxf(cur[cb], __shfl_xor(cur[cb], 32, 64)), 0.0f);
+                            if (half == 0) lacc[wave][res_local[blk * kBlockUnits + uu]][col] += sv;
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+            // per set: float64 sum over the waves and columns, fixed order
+            const int nsets = int(tb.E[j1 - tb.base] - tb.E[j0 - tb.base]);
+            for (int i = tid; i < nsets; i += 256) {
+                double t = 0.0;
+                for (int w = 0; w < 4; ++w)
+                    for (int c = 0; c < 32; ++c) t += double(lacc[w][i][c]);
+                acc_set[0][i] = t;
+            }
+        } else if (nunits > 0 && v_end > v_begin) {
+            const int64_t nblk = (nunits + kBlockUnits - 1) / kBlockUnits;
+            for (int64_t vs = v_begin; vs < v_end; vs += kVSub) {
                 uint4 b[2][HU];
                 int sb[2];
 #pragma unroll
@@ -463,7 +575,6 @@ k_es_lp(const uint4* __restrict__ xq, const float* __restrict__ hn, const int* _
                     }
                     if (blk + 2 < nblk)
                         block_info(tid, blk + 2, u0, u1, j0, j1, tb, idx, n64, hn, sc_rows, info[(blk + 2) % 3]);
-                    // member rows (A, from LDS) x this wave's points (B)
                     uint4 a[HU];
 #pragma unroll
                     for (int u = 0; u < HU; ++u) a[u] = lds_m[rb][(half * HU + u) * 32 + col];
@@ -478,7 +589,7 @@ k_es_lp(const uint4* __restrict__ xq, const float* __restrict__ hn, const int* _
 #pragma unroll
                         for (int cb = 0; cb < 2; ++cb)
                             acc[cb] = mfma_main<DT>(&a[q * T::kU4], &b[cb][q * T::kU4], acc[cb], sa, sb[cb]);
-                    es_units(acc, bi, cur, half, lane, wave, acc_set);
+                    es_units<W>(acc, bi, cur, half, lane, wave, acc_set);
                     if (more) {
 #pragma unroll
                         for (int i = 0; i < PFU; ++i) {
@@ -551,15 +662,18 @@ hipError_t launch_eval_sets(const ebc_dataset* ds, const int64_t* offsets, const
 
     const unsigned nb = unsigned((l + 255) / 256);
     hipLaunchKernelGGL(k_es_units, dim3(nb), dim3(256), 0, s, offsets, idx, l, ds->n, sc, ds->b.state);
-    hipLaunchKernelGGL(k_es_scan, dim3(1), dim3(1024), 0, s, l, sc);
+    const bool lowp = in_dtype && ds->dt != EBC_DT_F32;
+    const int lp_kc = ds->k_pad / (ds->dt == EBC_DT_FP8_E4M3 ? 64 : 16);
+    hipLaunchKernelGGL(k_es_scan, dim3(1), dim3(1024), 0, s, l, lowp ? lp_window(ds->dt, lp_kc) : kWindow, sc);
     // persistent grid over (group, split) items; the item count is read on the device
     const dim3 g = dim3(2048);
-    if (in_dtype && ds->dt != EBC_DT_F32) {
+    if (lowp) {
         const int kc = ds->k_pad / (ds->dt == EBC_DT_FP8_E4M3 ? 64 : 16);
         const uint4* xq = static_cast<const uint4*>(static_cast<const void*>(ds->b.xq));
 #define EBC_ESL(DTV, K)                                                                                         \
     case K:                                                                                                     \
-        hipLaunchKernelGGL((k_es_lp<DTV, K>), g, dim3(256), 0, s, xq, ds->b.hn, ds->b.scale, ds->n, ds->b.n64, \
+        hipLaunchKernelGGL((k_es_lp<DTV, K, lp_window(DTV, K)>), g, dim3(256), 0, s, xq, ds->b.hn, ds->b.scale,   \
+                           ds->n, ds->b.n64,                                                              \
                            offsets, idx, l, splits, sc);                                                        \
         break;
         bool ok = true;
