@@ -15,16 +15,16 @@
 // (ceil(|S_j|/4) units, padding rows contribute -inf); units of consecutive
 // sets follow each other, 8 units form a 32-row member block (in the MFMA
 // result a unit is the 4 rows one lane half holds), and a group is every set
-// whose first unit lies in one window of 128 units. A work item is (group,
+// whose first unit lies in one window of 64 units. A work item is (group,
 // ground-set split); a workgroup (4 waves) walks the group's member blocks
 // through a double-buffered LDS stage (the next block's rows are gathered
 // into registers while the current one is multiplied) while each wave holds
 // 64 ground points in registers, and keeps a running maximum per (set,
 // point) across the set's units (also across blocks, so sets of any size
-// work). At each set's last unit the two lane halves are joined and the
-// clamped maxima of the 32 columns are summed in float64 into a per-wave,
-// per-set accumulator; a final pass adds the splits in a fixed order, so the
-// result does not depend on the schedule.
+// work). At each set's last unit the two lane halves are joined, clamped at
+// 0 and added to the lane's float accumulator of that set; float64 sums over
+// the lanes and waves, and a final pass over the splits, run in a fixed
+// order, so the result does not depend on the schedule.
 #include <math.h>
 
 #include "ebc_internal.h"
@@ -36,7 +36,7 @@ namespace {
 
 constexpr int kUnitRows = 4;    // rows per unit
 constexpr int kBlockUnits = 8;  // units per 32-row member block
-constexpr int kWindow = 128;    // units per group window (float32 kernel)
+constexpr int kWindow = 64;     // units per group window (float32 kernel)
 // units per group window of the reduced-precision kernel: its resident
 // member rows and per-set column sums stay within about 64 KB of LDS
 constexpr int lp_window(int dt, int kc) { return 2 * kc * (dt == EBC_DT_FP8_E4M3 ? 2 : 1) <= 8 ? 64 : 32; }
@@ -195,14 +195,15 @@ __device__ __forceinline__ void block_info(int tid, int64_t blk, int64_t u0, int
 // Units of 4 rows of one member block against this wave's 64 points: unit
 // uu is held by lane half uu%2 in result registers 4*(uu/2) .. +3. Running
 // maximum per (set, point) in cur (per 32-point block); at a set's last unit
-// the two lane halves are joined, clamped at 0 and the 32 columns summed in
-// float64 into the set's per-wave accumulator.
+// the two lane halves are joined, clamped at 0, and each column's value is
+// added to the lane's own float accumulator of that set (lacc[wave][set][col];
+// the final pass sums them in float64 in a fixed order).
 template <int WIN>
-__device__ __forceinline__ void es_units(const floatx16 (&acc)[2], const BlockInfo& bi, float (&cur)[2], int half,
-                                         int lane, int wave, double (&acc_set)[4][WIN]) {
+__device__ __forceinline__ void es_units(const floatx16 (&acc)[2], const int32_t* unit_flags, const int32_t* unit_local,
+                                         float (&cur)[2], int half, int col, float (&lacc)[WIN][32]) {
 #pragma unroll
     for (int uu = 0; uu < kBlockUnits; ++uu) {
-        const int flags = bi.unit_flags[uu];
+        const int flags = unit_flags[uu];
         if (!(flags & 4)) continue;
         const int j4 = 4 * (uu >> 1);
 #pragma unroll
@@ -212,13 +213,26 @@ __device__ __forceinline__ void es_units(const floatx16 (&acc)[2], const BlockIn
             if (half == (uu & 1)) cur[cb] = fmaxf(cur[cb], m);
         }
         if (flags & 2) {
-            double sv = 0.0;
+            float sv = 0.0f;
 #pragma unroll
-            for (int cb = 0; cb < 2; ++cb) sv += double(fmaxf(fmaxf(cur[cb], __shfl_xor(cur[cb], 32, 64)), 0.0f));
-#pragma unroll
-            for (int o = 16; o > 0; o >>= 1) sv += __shfl_xor(sv, o, 64);
-            if (lane == 0) acc_set[wave][bi.unit_local[uu]] += sv;
+            for (int cb = 0; cb < 2; ++cb) sv += fmaxf(fmaxf(cur[cb], __shfl_xor(cur[cb], 32, 64)), 0.0f);
+            if (half == 0) lacc[unit_local[uu]][col] += sv;
         }
+    }
+}
+
+// Per non-empty set of the group: float64 sum of the per-lane accumulators
+// over the waves and columns (fixed order), one write per set and split.
+template <int WIN>
+__device__ __forceinline__ void es_finish(int tid, int64_t j0, int64_t j1, int split, int64_t l, const EsScratch& sc,
+                                          const float (&lacc)[4][WIN][32]) {
+    for (int64_t j = j0 + tid; j < j1; j += 256) {
+        if (sc.E[j + 1] == sc.E[j]) continue;
+        const int loc = int(sc.E[j] - sc.E[j0]);
+        double t = 0.0;
+        for (int w = 0; w < 4; ++w)
+            for (int c = 0; c < 32; ++c) t += double(lacc[w][loc][c]);
+        sc.part[int64_t(split) * l + j] = t;
     }
 }
 
@@ -235,7 +249,7 @@ k_es_main(const float* __restrict__ x, int64_t n, int32_t d, const double* __res
     __shared__ BlockInfo info[3];
     __shared__ int64_t t_u[kTab + 1], t_off[kTab + 1];
     __shared__ int32_t t_e[kTab + 1];
-    __shared__ double acc_set[4][kWindow];
+    __shared__ float lacc[4][kWindow][32];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -264,7 +278,7 @@ k_es_main(const float* __restrict__ x, int64_t n, int32_t d, const double* __res
                 t_e[i] = sc.E[j0 + i];
                 t_off[i] = off[j0 + i];
             }
-        for (int i = tid; i < 4 * kWindow; i += 256) acc_set[i / kWindow][i % kWindow] = 0.0;
+        for (int i = tid; i < 4 * kWindow * 32; i += 256) (&lacc[0][0][0])[i] = 0.0f;
         __syncthreads();
         const SetTable tb = cached ? SetTable{t_u, t_e, t_off, j0} : SetTable{sc.U, sc.E, off, 0};
         if (u1 > u0 && v_end > v_begin) {
@@ -347,7 +361,7 @@ k_es_main(const float* __restrict__ x, int64_t n, int32_t d, const double* __res
                                 acc[cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[i], b[cb][4 * s4 + i], acc[cb], 0,
                                                                                0, 0);
                     }
-                    es_units(acc, bi, cur, half, lane, wave, acc_set);
+                    es_units<kWindow>(acc, bi.unit_flags, bi.unit_local, cur, half, col, lacc[wave]);
                     if (more) {
                         float* dst = reinterpret_cast<float*>(lds_m4[rb ^ 1]) + grow * S;
 #pragma unroll
@@ -358,13 +372,7 @@ k_es_main(const float* __restrict__ x, int64_t n, int32_t d, const double* __res
             }
         }
         __syncthreads();
-        // fixed-order combination over the waves; one write per non-empty set
-        // of the group and split (zero when the split has no points)
-        for (int64_t j = j0 + tid; j < j1; j += 256) {
-            if (sc.E[j + 1] == sc.E[j]) continue;
-            const int loc = int(sc.E[j] - sc.E[j0]);
-            sc.part[int64_t(split) * l + j] = ((acc_set[0][loc] + acc_set[1][loc]) + acc_set[2][loc]) + acc_set[3][loc];
-        }
+        es_finish<kWindow>(tid, j0, j1, split, l, sc, lacc);
         __syncthreads();
     }
 }
@@ -398,7 +406,6 @@ k_es_lp(const uint4* __restrict__ xq, const float* __restrict__ hn, const int* _
     __shared__ BlockInfo info[3];
     __shared__ int64_t t_u[kTab + 1], t_off[kTab + 1];
     __shared__ int32_t t_e[kTab + 1];
-    __shared__ double acc_set[4][W];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -425,7 +432,6 @@ k_es_lp(const uint4* __restrict__ xq, const float* __restrict__ hn, const int* _
                 t_e[i] = sc.E[j0 + i];
                 t_off[i] = off[j0 + i];
             }
-        for (int i = tid; i < 4 * W; i += 256) acc_set[i / W][i % W] = 0.0;
         for (int i = tid; i < 4 * W * 32; i += 256) (&lacc[0][0][0])[i] = 0.0f;
         __syncthreads();
         const SetTable tb = cached ? SetTable{t_u, t_e, t_off, j0} : SetTable{sc.U, sc.E, off, 0};
@@ -495,38 +501,9 @@ k_es_lp(const uint4* __restrict__ xq, const float* __restrict__ hn, const int* _
 #pragma unroll
                         for (int cb = 0; cb < 2; ++cb)
                             acc[cb] = mfma_main<DT>(&a[q * T::kU4], &b[cb][q * T::kU4], acc[cb], sa, sb[cb]);
-                    // units of this block (see es_units); at a set's last unit each
-                    // column's clamped maximum goes to the lane's own accumulator
-#pragma unroll
-                    for (int uu = 0; uu < kBlockUnits; ++uu) {
-                        const int flags = res_flags[blk * kBlockUnits + uu];
-                        if (!(flags & 4)) continue;
-                        const int j4 = 4 * (uu >> 1);
-#pragma unroll
-                        for (int cb = 0; cb < 2; ++cb) {
-                            if (flags & 1) cur[cb] = -INFINITY;
-                            const float m = fmaxf(fmaxf(acc[cb][j4 + 0], acc[cb][j4 + 1]),
-                                                  fmaxf(acc[cb][j4 + 2], acc[cb][j4 + 3]));
-                            if (half == (uu & 1)) cur[cb] = fmaxf(cur[cb], m);
-                        }
-                        if (flags & 2) {
-                            float sv = 0.0f;
-#pragma unroll
-                            for (int cb = 0; cb < 2; ++cb)
-                                sv += fmaxf(fmaxf(cur[cb], __shfl_xor(cur[cb], 32, 64)), 0.0f);
-                            if (half == 0) lacc[wave][res_local[blk * kBlockUnits + uu]][col] += sv;
-                        }
-                    }
+                    es_units<W>(acc, res_flags + blk * kBlockUnits, res_local + blk * kBlockUnits, cur, half, col,
+                                lacc[wave]);
                 }
-            }
-            __syncthreads();
-            // per set: float64 sum over the waves and columns, fixed order
-            const int nsets = int(tb.E[j1 - tb.base] - tb.E[j0 - tb.base]);
-            for (int i = tid; i < nsets; i += 256) {
-                double t = 0.0;
-                for (int w = 0; w < 4; ++w)
-                    for (int c = 0; c < 32; ++c) t += double(lacc[w][i][c]);
-                acc_set[0][i] = t;
             }
         } else if (nunits > 0 && v_end > v_begin) {
             const int64_t nblk = (nunits + kBlockUnits - 1) / kBlockUnits;
@@ -589,7 +566,7 @@ k_es_lp(const uint4* __restrict__ xq, const float* __restrict__ hn, const int* _
 #pragma unroll
                         for (int cb = 0; cb < 2; ++cb)
                             acc[cb] = mfma_main<DT>(&a[q * T::kU4], &b[cb][q * T::kU4], acc[cb], sa, sb[cb]);
-                    es_units<W>(acc, bi, cur, half, lane, wave, acc_set);
+                    es_units<W>(acc, bi.unit_flags, bi.unit_local, cur, half, col, lacc[wave]);
                     if (more) {
 #pragma unroll
                         for (int i = 0; i < PFU; ++i) {
@@ -602,11 +579,7 @@ k_es_lp(const uint4* __restrict__ xq, const float* __restrict__ hn, const int* _
             }
         }
         __syncthreads();
-        for (int64_t j = j0 + tid; j < j1; j += 256) {
-            if (sc.E[j + 1] == sc.E[j]) continue;
-            const int loc = int(sc.E[j] - sc.E[j0]);
-            sc.part[int64_t(split) * l + j] = ((acc_set[0][loc] + acc_set[1][loc]) + acc_set[2][loc]) + acc_set[3][loc];
-        }
+        es_finish<W>(tid, j0, j1, split, l, sc, lacc);
         __syncthreads();
     }
 }
