@@ -36,6 +36,7 @@ WORKLOADS = {
     "serving_curves_d64_bf16": ("serving_requests", {"seed": 5}),
     "paper_sets_n50000_l5000_k10_d100": ("paper_sets", {"seed": 6}),
     "paper_sets_sweep_d100": ("paper_sets", {"seed": 6}),
+    "curves_n1000_d3524_k50": ("case_study_curves", {"seed": 8}),
 }
 
 
@@ -402,7 +403,7 @@ def main():
     variant_used = 0
     if args.variant is not None:
         variant_used = args.variant
-    elif args.dtype != "f32":
+    elif args.dtype != "f32" and d <= 128:  # long rows have a single kernel shape
         tds = ebc.Dataset(x, dtype=args.dtype, stream=stream)
         variant_used = tds.autotune(reps=3, stream=stream)["variant"]
         tds.sync(stream)
@@ -459,7 +460,10 @@ def main():
     flops_per_launch = 2.0 * d * pairs / k
     achieved = flops_per_launch / (gains_avg_ms * 1e-3) / 1e12
     peak = PEAK_TFLOPS[args.dtype]
-    kname = "k_gains_f32" if args.dtype == "f32" else ("k_gains_lp_pp" if variant_used == 3 else "k_gains_lp")
+    if d > 128:
+        kname = "k_gains_wide"
+    else:
+        kname = "k_gains_f32" if args.dtype == "f32" else ("k_gains_lp_pp" if variant_used == 3 else "k_gains_lp")
     roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak,
                 "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
                 "traffic": counters_traffic(kname, args.workload, args.dtype, variant_used),

@@ -55,7 +55,7 @@ typedef enum {
     EBC_E_RANGE = 4,        /* device: a value does not fit the distance dtype (FP16: |x| > 65504) */
     EBC_E_NOMEM = 5,        /* host allocation failed, or an arena block / request does not fit */
     EBC_E_DEVICE = 6,       /* a HIP runtime call failed */
-    EBC_E_UNSUPPORTED = 7   /* valid request this build does not implement (e.g. d > 128) */
+    EBC_E_UNSUPPORTED = 7   /* valid request this build does not implement (e.g. d > EBC_MAX_DIM) */
 } ebc_status;
 
 /* Precision in which the candidate-point distances of the marginal gains are
@@ -78,8 +78,11 @@ typedef enum {
     EBC_DT_FP8_E4M3 = 3
 } ebc_dtype;
 
-/* Largest dimension this build accepts. */
-#define EBC_MAX_DIM 128
+/* Largest dimension this build accepts. Rows padded to at most 128 values
+ * are held whole in registers by the distance kernels; longer rows (the
+ * paper's case-study series have d = 3524, Sec. 6) take kernels that loop
+ * over the dimension in chunks. */
+#define EBC_MAX_DIM 4096
 
 /* Exact device workspace that ebc_dataset_create needs for (n, d, dt), in
  * bytes; 0 if the arguments are invalid. The library allocates no device

@@ -105,12 +105,13 @@ ebc_status ebc_dataset_create(const float* x, int64_t n, int32_t d, ebc_dtype dt
     ds->n_pad = pad_rows(n);
     ds->d = d;
     ds->k_pad = k_pad_for(d, dt);
-    ds->v_splits = v_splits_for(ds->n_pad);
+    ds->v_splits = v_splits_for(ds->n_pad, ds->k_pad);
     ds->dt = dt;
     char* w = static_cast<char*>(workspace);
     Buffers& b = ds->b;
     b.xq = reinterpret_cast<float*>(w + L.off_xq);
     b.scale = dt == EBC_DT_FP8_E4M3 ? reinterpret_cast<int*>(w + L.off_scale) : nullptr;
+    b.mu = wide_rows(ds->k_pad) ? reinterpret_cast<double*>(w + L.off_mu) : nullptr;
     b.n64 = reinterpret_cast<double*>(w + L.off_n64);
     b.m64 = reinterpret_cast<double*>(w + L.off_m64);
     b.hn = reinterpret_cast<float*>(w + L.off_hn);

@@ -36,6 +36,7 @@ struct ebc_batch {
     int32_t* d_slot_inst;
     int64_t* d_wg_pre;
     int64_t total_rows;
+    bool long_rows;  // some instance has rows longer than kNarrowMaxK
     std::vector<Bucket> buckets;
     std::vector<int64_t> h_row_pre, h_wg_pre;
     std::vector<int32_t> h_slot_inst;
@@ -57,7 +58,7 @@ hipError_t enqueue_ticks(ebc_batch* bt, int32_t ticks, hipStream_t s) {
                                      b.slots, b.total_wgs, t, s);
             if (e != hipSuccess) return e;
         }
-        e = launch_step_batched(bt->d_desc, bt->d_row_pre, bt->count, bt->total_rows, t, s);
+        e = launch_step_batched(bt->d_desc, bt->d_row_pre, bt->count, bt->total_rows, t, bt->long_rows, s);
     }
     return e;
 }
@@ -104,6 +105,8 @@ ebc_status ebc_batch_create(ebc_dataset* const* ds, int32_t count, void* workspa
     bt->h_row_pre[0] = 0;
     for (int32_t i = 0; i < count; ++i) bt->h_row_pre[i + 1] = bt->h_row_pre[i] + ds[i]->n_pad / kBlock;
     bt->total_rows = bt->h_row_pre[count];
+    bt->long_rows = false;
+    for (int32_t i = 0; i < count; ++i) bt->long_rows |= wide_rows(ds[i]->k_pad);
 
     // gains buckets: instances grouped by kernel, in first-seen order
     std::vector<int32_t> keys;

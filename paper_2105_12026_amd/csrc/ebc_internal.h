@@ -14,6 +14,14 @@ constexpr int kRowAlign = 256;     // rows of every per-point array are padded t
 constexpr int kBlock = 256;        // threads of the per-point kernels
 constexpr int kGainsCandTile = 128;  // candidates per gains workgroup (4 waves x 32)
 constexpr int kGainsVTile = 64;      // ground points per LDS stage of the gains kernel
+// Rows longer than this (padded length) take the long-row kernels, which
+// loop over the dimension instead of holding whole rows in registers.
+constexpr int kNarrowMaxK = 128;
+__host__ __device__ inline bool wide_rows(int32_t k_pad) { return k_pad > kNarrowMaxK; }
+// Long-row gains: waves of a workgroup that split one candidate block's dot
+// products over K (1: four candidate blocks, no split; 4: one block, K in
+// quarters). Small ground sets split K to give the chip enough workgroups.
+inline int32_t wide_ksplit(int64_t n_pad) { return n_pad >= 16384 ? 1 : 4; }
 
 // Error codes the device writes into DevState::error (first one wins).
 constexpr int kDevErrIndex = EBC_E_INDEX;
@@ -46,6 +54,8 @@ struct Buffers {
                         // reduced precision: 64-row tiles, 16-byte units unit-major inside a tile
     int* scale;         // [n_pad] E8M0 row scales (FP8 only, else null)
     double* n64;        // [n_pad] ||v||^2 in float64 (0 for pad rows)
+    double* mu;         // [k_pad] column means; long rows only (the distance-dtype copy then
+                        // holds x - mu, and hn is the norm of that centred copy), else null
     double* m64;        // [n_pad] running minima m_v (float64 master copy)
     float* hn;          // [n_pad] ||v||^2 / 2 rounded to float32
     float* ha;          // [n_pad] (m_v - ||v||^2) / 2 in float32
@@ -112,13 +122,13 @@ __device__ inline int find_slot(const int64_t* __restrict__ pre, int count, int6
 }
 
 struct Layout {
-    size_t off_xq, off_scale, off_n64, off_m64, off_hn, off_ha, off_hm, off_sel, off_part, off_gsum, off_bmax,
+    size_t off_xq, off_scale, off_mu, off_n64, off_m64, off_hn, off_ha, off_hm, off_sel, off_part, off_gsum, off_bmax,
         off_barg, off_bcnt, off_wstage, off_wfinal, off_rpart, off_fpart, off_state, total;
 };
 
 int64_t pad_rows(int64_t n);
 int32_t k_pad_for(int32_t d, ebc_dtype dt);
-int32_t v_splits_for(int64_t n_pad);
+int32_t v_splits_for(int64_t n_pad, int32_t k_pad);
 Layout layout(int64_t n, int32_t d, ebc_dtype dt);
 
 }  // namespace ebc
@@ -243,6 +253,9 @@ hipError_t launch_gains_f32_batched(int32_t k_pad, const InstDesc* descs, const 
 hipError_t launch_gains_lp_batched(int32_t dt, int32_t kc, int32_t variant, const InstDesc* descs,
                                    const int32_t* slot_inst, const int64_t* wg_pre, int32_t slots, int64_t total_wgs,
                                    int32_t t, hipStream_t s);
+hipError_t launch_gains_wide_batched(int32_t dt, int32_t ksplit, const InstDesc* descs, const int32_t* slot_inst,
+                                     const int64_t* wg_pre, int32_t slots, int64_t total_wgs, int32_t t,
+                                     hipStream_t s);
 hipError_t launch_gains_batched(int32_t bucket, const InstDesc* descs, const int32_t* slot_inst,
                                 const int64_t* wg_pre, int32_t slots, int64_t total_wgs, int32_t t, hipStream_t s);
 // 32-row candidate blocks per wave in the ping-pong gains variant (3):
@@ -252,8 +265,10 @@ constexpr int pp_blocks(int dt, int kc) {
 }
 // Tile variant recorded by the autotuner for this dataset's key, or -1.
 int32_t tuned_variant(const ebc_dataset* ds);
+// long_rows: some instance has rows longer than kNarrowMaxK (their re-score
+// and update run in the long-row kernels)
 hipError_t launch_step_batched(const InstDesc* descs, const int64_t* row_pre, int32_t count, int64_t total_rows,
-                               int32_t t, hipStream_t s);
+                               int32_t t, bool long_rows, hipStream_t s);
 hipError_t launch_reset_batched(const InstDesc* descs, const int64_t* row_pre, int32_t count, int64_t total_rows,
                                 hipStream_t s);
 
@@ -263,6 +278,7 @@ hipError_t launch_reset_state(const ebc_dataset* ds, hipStream_t s);
 hipError_t launch_load_m(const ebc_dataset* ds, const double* m, hipStream_t s);
 hipError_t launch_gains_f32(const ebc_dataset* ds, const int32_t* cand, int64_t n_cand, hipStream_t s);
 hipError_t launch_gains_lp(const ebc_dataset* ds, const int32_t* cand, int64_t n_cand, hipStream_t s);
+hipError_t launch_gains_wide(const ebc_dataset* ds, const int32_t* cand, int64_t n_cand, hipStream_t s);
 hipError_t launch_gains(const ebc_dataset* ds, const int32_t* cand, int64_t n_cand, hipStream_t s);
 int elem_bytes(ebc_dtype dt);
 

@@ -29,6 +29,7 @@
 
 #include "ebc_internal.h"
 #include "lp_mfma.h"
+#include "wide_row.h"
 
 namespace ebc {
 
@@ -584,6 +585,170 @@ k_es_lp(const uint4* __restrict__ xq, const float* __restrict__ hn, const int* _
     }
 }
 
+// Long rows (padded length above 128): the same work items, windows and
+// per-set sums as above, but no row is held whole. For every member block
+// each wave walks the dimension (row pieces straight from global memory,
+// the next batch in flight while the current one is multiplied), and it
+// computes the block's bookkeeping in its own lanes (lane r < 32: row r;
+// lanes 32..39: the units), so the waves meet at a barrier only for the
+// item's final sums. DT = F32 reads the caller's float32 rows [n, d] with the
+// float64 norms; otherwise the cast rows, their norms and (FP8) scales. The
+// cast copy of long rows is centred at the column means mu, so with
+// x' = x - mu the per-pair term becomes
+//     v.s - n_s/2 = x'_v.x'_s - ||x'_s||^2/2 + (n_v - ||x'_v||^2)/2,
+// the last part a per-point shift added to the accumulator's start.
+template <int DT>
+__global__ void __launch_bounds__(256)
+k_es_wide(const void* src, int32_t len, const float* __restrict__ hn, const int* __restrict__ scale, int64_t n,
+          const double* __restrict__ n64, const int64_t* __restrict__ off, const int32_t* __restrict__ idx,
+          int64_t l, int32_t splits, EsScratch sc) {
+    using R = WideRow<DT>;
+    using Piece = typename R::Piece;
+    constexpr int B = R::kBatch;
+    constexpr bool kF32 = DT == EBC_DT_F32;
+    constexpr bool kFp8 = DT == EBC_DT_FP8_E4M3;
+    __shared__ int64_t t_u[kTab + 1], t_off[kTab + 1];
+    __shared__ int32_t t_e[kTab + 1];
+    __shared__ float lacc[4][kWindow][32];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int col = lane & 31;
+    const int half = lane >> 5;
+    const int64_t n_items = *sc.n_groups * splits;
+    const int64_t vchunk = ((n + splits - 1) / splits + kVSub - 1) / kVSub * kVSub;
+    // float32: pieces of 8 values over d (the tail reads as 0); else the padded cast rows
+    const int np = kF32 ? (len + 7) / 8 : R::pieces(len);
+    auto piece = [&](int64_t row, int p) -> Piece {
+        if constexpr (kF32)
+            return R::load_x(static_cast<const float*>(src), row, len, p, half);
+        else
+            return R::load(src, row, len, p, half);
+    };
+
+    for (int64_t item = blockIdx.x; item < n_items; item += gridDim.x) {
+        const int64_t g = item / splits;
+        const int split = int(item % splits);
+        const int64_t j0 = lower_bound_u(sc.U, 0, l, g * kWindow);
+        const int64_t j1 = lower_bound_u(sc.U, j0, l, (g + 1) * kWindow);
+        const int64_t u0 = sc.U[j0], u1 = sc.U[j1];
+        const int64_t v_begin = int64_t(split) * vchunk;
+        int64_t v_end = v_begin + vchunk;
+        if (v_end > n) v_end = n;
+        const bool cached = j1 - j0 <= kTab;
+        if (cached)
+            for (int64_t i = tid; i <= j1 - j0; i += 256) {
+                t_u[i] = sc.U[j0 + i];
+                t_e[i] = sc.E[j0 + i];
+                t_off[i] = off[j0 + i];
+            }
+        for (int i = tid; i < 4 * kWindow * 32; i += 256) (&lacc[0][0][0])[i] = 0.0f;
+        __syncthreads();
+        const SetTable tb = cached ? SetTable{t_u, t_e, t_off, j0} : SetTable{sc.U, sc.E, off, 0};
+        if (u1 > u0 && v_end > v_begin) {
+            const int64_t nblk = (u1 - u0 + kBlockUnits - 1) / kBlockUnits;
+            for (int64_t vs = v_begin; vs < v_end; vs += kVSub) {
+                // this wave's 64 ground points (B operand); points past the
+                // split compute as zero rows, whose clamped terms are 0
+                int64_t prow[2];
+                bool pok[2];
+                int sb[2];
+                float wsh[2];  // per-point shift of the centred cast rows (0 for float32)
+#pragma unroll
+                for (int cb = 0; cb < 2; ++cb) {
+                    const int64_t v = vs + wave * 64 + cb * 32 + col;
+                    pok[cb] = v < v_end;
+                    prow[cb] = pok[cb] ? v : 0;
+                    sb[cb] = (kFp8 && pok[cb]) ? scale[v] : 127;
+                    wsh[cb] = (!kF32 && pok[cb]) ? float(0.5 * n64[v] - double(hn[v])) : 0.0f;
+                }
+                float cur[2] = {-INFINITY, -INFINITY};
+                for (int64_t blk = 0; blk < nblk; ++blk) {
+                    // bookkeeping of block blk in this wave's lanes
+                    int32_t my_mem = -1, my_sc = 127, my_flags = 0, my_loc = 0;
+                    float my_c = -INFINITY;
+                    if (lane < 32) {
+                        const int64_t u = u0 + blk * kBlockUnits + lane / kUnitRows;
+                        if (u < u1) {
+                            const int64_t j = owner_of(tb.U, j0 - tb.base, j1 - tb.base, u);
+                            const int64_t q = (u - tb.U[j]) * kUnitRows + lane % kUnitRows;
+                            if (tb.off[j] + q < tb.off[j + 1]) my_mem = idx[tb.off[j] + q];
+                        }
+                        if (my_mem >= 0) {
+                            my_c = kF32 ? -float(0.5 * n64[my_mem]) : -hn[my_mem];
+                            if (kFp8) my_sc = scale[my_mem];
+                        }
+                    } else if (lane < 32 + kBlockUnits) {
+                        const int64_t u = u0 + blk * kBlockUnits + (lane - 32);
+                        if (u < u1) {
+                            const int64_t j = owner_of(tb.U, j0 - tb.base, j1 - tb.base, u);
+                            my_flags = 4 | (u == tb.U[j] ? 1 : 0) | (u == tb.U[j + 1] - 1 ? 2 : 0);
+                            my_loc = tb.E[j] - tb.E[j0 - tb.base];
+                        }
+                    }
+                    const int32_t amem = __shfl(my_mem, col, 64);  // A operand: member row `col`
+                    const bool alive = amem >= 0;
+                    const int64_t arow = alive ? amem : 0;
+                    const int sa = __shfl(my_sc, col, 64);
+                    int32_t uflags[kBlockUnits], ulocal[kBlockUnits];
+#pragma unroll
+                    for (int uu = 0; uu < kBlockUnits; ++uu) {
+                        uflags[uu] = __shfl(my_flags, 32 + uu, 64);
+                        ulocal[uu] = __shfl(my_loc, 32 + uu, 64);
+                    }
+                    floatx16 acc[2];
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) {
+                        const float c = __shfl(my_c, 8 * (r / 4) + 4 * half + (r % 4), 64);
+                        acc[0][r] = c + wsh[0];
+                        acc[1][r] = c + wsh[1];
+                    }
+                    // member rows x this wave's points over the whole dimension
+                    Piece a[B], b[2][B];
+#pragma unroll
+                    for (int i = 0; i < B; ++i) {
+                        const bool in = i < np;
+                        a[i] = (in && alive) ? piece(arow, i) : Piece{};
+#pragma unroll
+                        for (int cb = 0; cb < 2; ++cb) b[cb][i] = (in && pok[cb]) ? piece(prow[cb], i) : Piece{};
+                    }
+                    for (int p = 0; p < np; p += B) {
+                        const bool more = p + B < np;
+                        Piece an[B], bn[2][B];
+                        if (more) {
+#pragma unroll
+                            for (int i = 0; i < B; ++i) {
+                                const bool in = p + B + i < np;
+                                an[i] = (in && alive) ? piece(arow, p + B + i) : Piece{};
+#pragma unroll
+                                for (int cb = 0; cb < 2; ++cb)
+                                    bn[cb][i] = (in && pok[cb]) ? piece(prow[cb], p + B + i) : Piece{};
+                            }
+                        }
+#pragma unroll
+                        for (int i = 0; i < B; ++i)
+#pragma unroll
+                            for (int cb = 0; cb < 2; ++cb) acc[cb] = R::mma(a[i], b[cb][i], acc[cb], sa, sb[cb]);
+                        if (more) {
+#pragma unroll
+                            for (int i = 0; i < B; ++i) {
+                                a[i] = an[i];
+                                b[0][i] = bn[0][i];
+                                b[1][i] = bn[1][i];
+                            }
+                        }
+                    }
+                    es_units<kWindow>(acc, uflags, ulocal, cur, half, col, lacc[wave]);
+                }
+            }
+        }
+        __syncthreads();
+        es_finish<kWindow>(tid, j0, j1, split, l, sc, lacc);
+        __syncthreads();
+    }
+}
+
 // f_j = (2/|V|) sum over splits (fixed order); empty sets 0; bad sets NaN.
 __global__ void __launch_bounds__(256) k_es_final(int64_t l, int64_t n, int32_t splits, EsScratch sc,
                                                   double* __restrict__ f_out) {
@@ -637,10 +802,27 @@ hipError_t launch_eval_sets(const ebc_dataset* ds, const int64_t* offsets, const
     hipLaunchKernelGGL(k_es_units, dim3(nb), dim3(256), 0, s, offsets, idx, l, ds->n, sc, ds->b.state);
     const bool lowp = in_dtype && ds->dt != EBC_DT_F32;
     const int lp_kc = ds->k_pad / (ds->dt == EBC_DT_FP8_E4M3 ? 64 : 16);
-    hipLaunchKernelGGL(k_es_scan, dim3(1), dim3(1024), 0, s, l, lowp ? lp_window(ds->dt, lp_kc) : kWindow, sc);
+    // long rows (float32 rows padded to 8, or the cast rows): the long-row kernel
+    const bool wide = wide_rows(lowp ? ds->k_pad : (ds->d + 7) / 8 * 8);
+    hipLaunchKernelGGL(k_es_scan, dim3(1), dim3(1024), 0, s, l,
+                       (lowp && !wide) ? lp_window(ds->dt, lp_kc) : kWindow, sc);
     // persistent grid over (group, split) items; the item count is read on the device
     const dim3 g = dim3(2048);
-    if (lowp) {
+    if (wide) {
+        const ebc_dtype dt = lowp ? ds->dt : EBC_DT_F32;
+        const void* src = lowp ? static_cast<const void*>(ds->b.xq) : static_cast<const void*>(ds->x);
+        const int32_t len = lowp ? ds->k_pad : ds->d;
+        switch (dt) {
+#define EBC_ESW(DTV)                                                                                              \
+    case DTV:                                                                                                     \
+        hipLaunchKernelGGL((k_es_wide<DTV>), g, dim3(256), 0, s, src, len, ds->b.hn, ds->b.scale, ds->n, ds->b.n64, \
+                           offsets, idx, l, splits, sc);                                                          \
+        break;
+            EBC_ESW(EBC_DT_F32) EBC_ESW(EBC_DT_F16) EBC_ESW(EBC_DT_BF16) EBC_ESW(EBC_DT_FP8_E4M3)
+#undef EBC_ESW
+            default: (void)hipFreeAsync(base, s); return hipErrorInvalidValue;
+        }
+    } else if (lowp) {
         const int kc = ds->k_pad / (ds->dt == EBC_DT_FP8_E4M3 ? 64 : 16);
         const uint4* xq = static_cast<const uint4*>(static_cast<const void*>(ds->b.xq));
 #define EBC_ESL(DTV, K)                                                                                         \

@@ -25,12 +25,14 @@ int elem_bytes(ebc_dtype dt) { return dt == EBC_DT_F32 ? 4 : (dt == EBC_DT_FP8_E
 int64_t gains_chunk(const ebc_dataset* ds) {
     // ground-set chunk per workgroup: a multiple of the kernel's LDS tile
     // (float32: 64 rows; reduced precision: 256, the same for every variant)
-    const int64_t g = ds->dt == EBC_DT_F32 ? kGainsVTile : 256;
+    // (long rows: 64 for every dtype)
+    const int64_t g = (ds->dt == EBC_DT_F32 || wide_rows(ds->k_pad)) ? kGainsVTile : 256;
     const int64_t c = (ds->n_pad + ds->v_splits - 1) / ds->v_splits;
     return (c + g - 1) / g * g;
 }
 
 int64_t gains_cand_tile(const ebc_dataset* ds) {
+    if (wide_rows(ds->k_pad)) return 32 * 4 / wide_ksplit(ds->n_pad);
     if (ds->dt == EBC_DT_F32) return kGainsCandTile;
     // variant 1: 4 waves x 32 rows x 4 blocks; 3: 8 waves x 32 x pp_blocks; else 4 x 32 x 2
     if (ds->variant == 3) {
@@ -41,6 +43,8 @@ int64_t gains_cand_tile(const ebc_dataset* ds) {
 }
 
 int32_t gains_bucket(const ebc_dataset* ds) {
+    // last digit: the tile variant (reduced precision) or, for long rows, the K split
+    if (wide_rows(ds->k_pad)) return int32_t(ds->dt) * 100000 + ds->k_pad * 10 + wide_ksplit(ds->n_pad);
     return int32_t(ds->dt) * 100000 + ds->k_pad * 10 + (ds->dt == EBC_DT_F32 ? 0 : ds->variant);
 }
 
@@ -67,13 +71,24 @@ void fill_desc(const ebc_dataset* ds, int32_t k, int32_t* sel, double* f, double
 hipError_t launch_gains_batched(int32_t bucket, const InstDesc* descs, const int32_t* slot_inst,
                                 const int64_t* wg_pre, int32_t slots, int64_t total_wgs, int32_t t, hipStream_t s) {
     const int32_t dt = bucket / 100000, k_pad = (bucket % 100000) / 10, variant = bucket % 10;
+    if (wide_rows(k_pad))
+        return launch_gains_wide_batched(dt, variant, descs, slot_inst, wg_pre, slots, total_wgs, t, s);
     if (dt == EBC_DT_F32)
         return launch_gains_f32_batched(k_pad, descs, slot_inst, wg_pre, slots, total_wgs, t, s);
     const int32_t kc = k_pad / (dt == EBC_DT_FP8_E4M3 ? 64 : 16);
     return launch_gains_lp_batched(dt, kc, variant, descs, slot_inst, wg_pre, slots, total_wgs, t, s);
 }
 
-int32_t v_splits_for(int64_t n_pad) {
+int32_t v_splits_for(int64_t n_pad, int32_t k_pad) {
+    if (wide_rows(k_pad)) {
+        // long rows: enough (candidate block, chunk) workgroups for about
+        // eight waves per compute unit, chunks of at least 64 points
+        const int64_t tiles = n_pad / (32 * 4 / wide_ksplit(n_pad));
+        int64_t v = (2048 + tiles - 1) / tiles;
+        if (v > 16) v = 16;
+        if (v > n_pad / 64) v = n_pad / 64;
+        return int32_t(v < 1 ? 1 : v);
+    }
     // The ground set is cut into one chunk per XCD (8 on MI355X) once there
     // are enough candidate tiles; a workgroup then owns (candidate tile,
     // chunk) and consecutive workgroup ids, which the dispatcher deals round
@@ -93,13 +108,14 @@ Layout layout(int64_t n, int32_t d, ebc_dtype dt) {
     auto take = [&](size_t bytes) { size_t at = o; o = align256(o + bytes); return at; };
     L.off_xq = take(size_t(np) * kp * elem_bytes(dt));
     L.off_scale = dt == EBC_DT_FP8_E4M3 ? take(size_t(np) * sizeof(int)) : 0;
+    L.off_mu = wide_rows(kp) ? take(size_t(kp) * sizeof(double)) : 0;
     L.off_n64 = take(size_t(np) * sizeof(double));
     L.off_m64 = take(size_t(np) * sizeof(double));
     L.off_hn = take(size_t(np) * sizeof(float));
     L.off_ha = take(size_t(np) * sizeof(float));
     L.off_hm = take(size_t(np) * sizeof(float));
     L.off_sel = take(size_t(np));
-    L.off_part = take(size_t(v_splits_for(np)) * np * sizeof(double));
+    L.off_part = take(size_t(v_splits_for(np, kp)) * np * sizeof(double));
     L.off_gsum = take(size_t(np) * sizeof(double));
     L.off_bmax = take(size_t(nb) * sizeof(double));
     L.off_barg = take(size_t(nb) * sizeof(int32_t));
@@ -113,8 +129,30 @@ Layout layout(int64_t n, int32_t d, ebc_dtype dt) {
     return L;
 }
 
+// Column means of V in float64 for long rows, in a fixed order: a block
+// takes 64 columns, thread (column, phase) sums rows phase, phase + 16, ...,
+// and the 16 phase sums are added in phase order.
+__global__ void __launch_bounds__(1024) k_colmean(const float* __restrict__ x, int64_t n, int32_t d, int32_t kp,
+                                                  double* __restrict__ mu) {
+    __shared__ double part[16][64];
+    const int c = threadIdx.x & 63, ph = threadIdx.x >> 6;
+    const int k = blockIdx.x * 64 + c;
+    double s = 0.0;
+    if (k < d)
+        for (int64_t r = ph; r < n; r += 16) s += double(x[r * d + k]);
+    part[ph][c] = s;
+    __syncthreads();
+    if (ph == 0 && k < kp) {
+        double t = 0.0;
+        for (int i = 0; i < 16; ++i) t += part[i][c];
+        mu[k] = k < d ? t / double(n) : 0.0;
+    }
+}
+
 // One thread per padded row: float64 norm, finiteness check, the padded
-// float32 copy (columns d.. hold 0), and the initial state
+// float32 copy (columns d.. hold 0; long rows: centred at the column means,
+// which leaves every distance unchanged and shrinks the dot products whose
+// cancellation limits the float32 gains), and the initial state
 // m_v = ||v||^2 (S = {}). Per-block norm sums go to fpart for L({e0}).
 __global__ void __launch_bounds__(kBlock) k_prep(const float* __restrict__ x, int64_t n, int32_t d,
                                                  int32_t kp, Buffers b) {
@@ -126,14 +164,17 @@ __global__ void __launch_bounds__(kBlock) k_prep(const float* __restrict__ x, in
     if (r < n) {
         const float* xr = x + r * d;
         float* q = b.xq + r * kp;
+        double nc = 0.0;  // norm of the stored (centred) copy
         for (int k = 0; k < d; ++k) {
             const float v = xr[k];
             bad |= !isfinite(v);
             nv += double(v) * double(v);
-            q[k] = v;
+            const float c = b.mu ? float(double(v) - b.mu[k]) : v;
+            nc += double(c) * double(c);
+            q[k] = c;
         }
         for (int k = d; k < kp; ++k) q[k] = 0.0f;
-        const float hn = float(0.5 * nv);
+        const float hn = float(0.5 * nc);
         b.n64[r] = nv;
         b.m64[r] = nv;
         b.hn[r] = hn;
@@ -168,7 +209,8 @@ __global__ void __launch_bounds__(kBlock) k_prep(const float* __restrict__ x, in
 }
 
 // Reduced-precision copy: one thread per padded row. Exact float64 norm and
-// initial state as in k_prep, then the row cast with round-to-nearest-even
+// initial state as in k_prep, then the row (long rows: centred at the column
+// means) cast with round-to-nearest-even
 // (FP8: after a power-of-two row scale) into the tiled layout, and the
 // float32 norm of the cast row. FP16 values beyond its range raise
 // EBC_E_RANGE.
@@ -180,13 +222,15 @@ __global__ void __launch_bounds__(kBlock) k_prep_lp(const float* __restrict__ x,
     double nv = 0.0;
     if (r < n) {
         const float* xr = x + r * d;
+        // value cast at column k (long rows: centred at the column mean)
+        auto cv = [&](int k) -> float { return b.mu ? float(double(xr[k]) - b.mu[k]) : xr[k]; };
         bool bad = false, range = false;
         float amax = 0.0f;
         for (int k = 0; k < d; ++k) {
             const float v = xr[k];
             bad |= !isfinite(v);
             nv += double(v) * double(v);
-            amax = fmaxf(amax, fabsf(v));
+            amax = fmaxf(amax, fabsf(cv(k)));
         }
         double nq = 0.0;  // norm of the cast row
         const int eb = dt == EBC_DT_FP8_E4M3 ? 1 : 2;
@@ -204,7 +248,7 @@ __global__ void __launch_bounds__(kBlock) k_prep_lp(const float* __restrict__ x,
             for (int k = 0; k < kp; ++k) {
                 uint8_t c = 0;
                 if (k < d) {
-                    c = f32_to_e4m3_rne(ldexpf(xr[k], -se));
+                    c = f32_to_e4m3_rne(ldexpf(cv(k), -se));
                     const double xv = ldexp(double(e4m3_to_f32(c)), se);
                     nq += xv * xv;
                 }
@@ -216,11 +260,11 @@ __global__ void __launch_bounds__(kBlock) k_prep_lp(const float* __restrict__ x,
                 if (k < d) {
                     float back;
                     if (dt == EBC_DT_BF16) {
-                        c = f32_to_bf16_rne(xr[k]);
+                        c = f32_to_bf16_rne(cv(k));
                         back = bf16_to_f32(c);
                     } else {
-                        range |= fabsf(xr[k]) > 65504.0f;
-                        const _Float16 h = _Float16(xr[k]);
+                        range |= fabsf(cv(k)) > 65504.0f;
+                        const _Float16 h = _Float16(cv(k));
                         c = __builtin_bit_cast(uint16_t, h);
                         back = float(h);
                     }
@@ -310,6 +354,9 @@ __global__ void k_state_init(DevState* st) {
 hipError_t launch_prep(const ebc_dataset* ds, hipStream_t s) {
     const int nb = int(ds->n_pad / kBlock);
     hipLaunchKernelGGL(k_state_init, dim3(1), dim3(64), 0, s, ds->b.state);
+    if (ds->b.mu)
+        hipLaunchKernelGGL(k_colmean, dim3(unsigned((ds->k_pad + 63) / 64)), dim3(1024), 0, s, ds->x, ds->n, ds->d,
+                           ds->k_pad, ds->b.mu);
     if (ds->dt == EBC_DT_F32)
         hipLaunchKernelGGL(k_prep, dim3(nb), dim3(kBlock), 0, s, ds->x, ds->n, ds->d, ds->k_pad, ds->b);
     else

@@ -166,10 +166,13 @@ __device__ void wselect_body(const InstDesc& c) {
 
 // ---- rescore: float64 direct-difference gains of the window candidates ----
 // One thread per ground point, from the caller's float32 points; candidates
-// in groups of 8 staged in LDS; per-block sums in a fixed order.
+// in groups of 8 staged in LDS, up to 512 dimensions at a time (long rows
+// take several passes, summed in dimension order); per-block sums in a
+// fixed order.
 constexpr int kRescoreGroup = 8;
+constexpr int kRescoreChunk = 512;
 __device__ void rescore_body(const InstDesc& c, int64_t blk) {
-    __shared__ float cx[kRescoreGroup * EBC_MAX_DIM];
+    __shared__ float cx[kRescoreGroup * kRescoreChunk];
     __shared__ double red[kRescoreGroup][kBlock];
     const Buffers& b = c.b;
     const float* __restrict__ x = c.x;
@@ -181,22 +184,25 @@ __device__ void rescore_body(const InstDesc& c, int64_t blk) {
     const float* xv = x + (live ? v : 0) * d;
     for (int g0 = 0; g0 < W; g0 += kRescoreGroup) {
         const int gn = (W - g0) < kRescoreGroup ? (W - g0) : kRescoreGroup;
-        __syncthreads();
-        for (int e = threadIdx.x; e < gn * d; e += kBlock) {
-            const int j = e / d, k = e % d;
-            cx[j * EBC_MAX_DIM + k] = x[int64_t(b.wfinal[g0 + j].idx) * d + k];
-        }
-        __syncthreads();
         double acc[kRescoreGroup];
 #pragma unroll
         for (int j = 0; j < kRescoreGroup; ++j) acc[j] = 0.0;
-        if (live) {
-            for (int k = 0; k < d; ++k) {
-                const double xk = double(xv[k]);
+        for (int k0 = 0; k0 < d; k0 += kRescoreChunk) {
+            const int kn = (d - k0) < kRescoreChunk ? (d - k0) : kRescoreChunk;
+            __syncthreads();
+            for (int e = threadIdx.x; e < gn * kn; e += kBlock) {
+                const int j = e / kn, k = e % kn;
+                cx[j * kRescoreChunk + k] = x[int64_t(b.wfinal[g0 + j].idx) * d + k0 + k];
+            }
+            __syncthreads();
+            if (live) {
+                for (int k = 0; k < kn; ++k) {
+                    const double xk = double(xv[k0 + k]);
 #pragma unroll
-                for (int j = 0; j < kRescoreGroup; ++j) {
-                    const double t = xk - double(cx[j * EBC_MAX_DIM + k]);
-                    acc[j] = fma(t, t, acc[j]);
+                    for (int j = 0; j < kRescoreGroup; ++j) {
+                        const double t = xk - double(cx[j * kRescoreChunk + k]);
+                        acc[j] = fma(t, t, acc[j]);
+                    }
                 }
             }
         }
@@ -275,7 +281,7 @@ __device__ void pick_body(const InstDesc& c, int32_t t) {
 
 // ---- update: m_v <- min(m_v, d(v, c*)) in float64, per-block sums of m_v ----
 __device__ void update_body(const InstDesc& c, int64_t blk) {
-    __shared__ float cx[EBC_MAX_DIM];
+    __shared__ float cx[kNarrowMaxK];
     __shared__ double red[kBlock];
     const Buffers& b = c.b;
     const float* __restrict__ x = c.x;
@@ -311,6 +317,147 @@ __device__ void update_body(const InstDesc& c, int64_t blk) {
     if (threadIdx.x == 0) b.fpart[blk] = red[0];
 }
 
+// ---- long rows (padded length above 128): re-score and update ----
+// The block's 256 ground-point rows pass through LDS in chunks of 64
+// dimensions: each thread loads 64 values of the next chunk into registers
+// (a wave reads 64 consecutive values of one row) while the current chunk is
+// used, then stores them transposed, and each thread reads its own row from
+// LDS. The re-score window is split over blockIdx.y in groups of 8
+// candidates, so small ground sets still spread over the chip. Every
+// per-thread float64 sum runs in dimension order, as for short rows.
+constexpr int kLongChunk = 64;
+
+struct LongStage {
+    float v[kLongChunk];  // values (point tid/64 + 4i, dimension tid%64) of the chunk
+    float c[2];           // candidate values (re-score: candidate tid/64 + 4i, dimension tid%64)
+};
+
+// Load chunk [k0, k0 + 64) of points [v0, v0 + 256) and of up to 8
+// candidates (cand[q] < 0: none) into registers; values past d or n read 0.
+__device__ __forceinline__ void long_load(const float* __restrict__ x, int64_t n, int d, int64_t v0, int k0,
+                                          const int64_t (&cand)[2], LongStage& st) {
+    const int k = threadIdx.x % kLongChunk, p0 = threadIdx.x / kLongChunk;
+    const bool kin = k0 + k < d;
+#pragma unroll
+    for (int i = 0; i < kLongChunk; ++i) {
+        const int64_t v = v0 + p0 + 4 * i;
+        st.v[i] = (kin && v < n) ? x[v * d + k0 + k] : 0.0f;
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i) st.c[i] = (kin && cand[i] >= 0) ? x[cand[i] * d + k0 + k] : 0.0f;
+}
+
+__device__ __forceinline__ void long_store(const LongStage& st, float (&xt)[kLongChunk][kBlock + 1],
+                                           float (&cx)[kRescoreGroup][kLongChunk]) {
+    const int k = threadIdx.x % kLongChunk, p0 = threadIdx.x / kLongChunk;
+#pragma unroll
+    for (int i = 0; i < kLongChunk; ++i) xt[k][p0 + 4 * i] = st.v[i];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) cx[p0 + 4 * i][k] = st.c[i];
+}
+
+// Squared distances of this thread's point to the first NJ staged candidates
+// over the whole row, chunk by chunk (cand: the candidates this thread loads).
+template <int NJ>
+__device__ __forceinline__ void long_sums(const InstDesc& c, int64_t v0, const int64_t (&cand)[2], bool live,
+                                          float (&xt)[kLongChunk][kBlock + 1],
+                                          float (&cx)[kRescoreGroup][kLongChunk], double (&acc)[NJ]) {
+    const int d = c.d;
+    LongStage st;
+    long_load(c.x, c.n, d, v0, 0, cand, st);
+    for (int k0 = 0; k0 < d; k0 += kLongChunk) {
+        const int kn = (d - k0) < kLongChunk ? (d - k0) : kLongChunk;
+        __syncthreads();  // the previous chunk is no longer read
+        long_store(st, xt, cx);
+        __syncthreads();
+        if (k0 + kLongChunk < d) long_load(c.x, c.n, d, v0, k0 + kLongChunk, cand, st);  // in flight meanwhile
+        if (live) {
+            for (int k = 0; k < kn; ++k) {
+                const double xk = double(xt[k][threadIdx.x]);
+#pragma unroll
+                for (int q = 0; q < NJ; ++q) {
+                    const double t = xk - double(cx[q][k]);
+                    acc[q] = fma(t, t, acc[q]);
+                }
+            }
+        }
+    }
+}
+
+__device__ void rescore_long_body(const InstDesc& c, int64_t blk, int g) {
+    __shared__ float xt[kLongChunk][kBlock + 1];
+    __shared__ float cx[kRescoreGroup][kLongChunk];
+    __shared__ double red[kRescoreGroup][kBlock];
+    const Buffers& b = c.b;
+    const int W = b.state->window_count;
+    const int g0 = g * kRescoreGroup;
+    if (g0 >= W) return;  // the same for the whole block
+    const int gn = (W - g0) < kRescoreGroup ? (W - g0) : kRescoreGroup;
+    const int64_t v0 = blk * kBlock;
+    const int64_t v = v0 + threadIdx.x;
+    const bool live = v < c.n;
+    const double mv = live ? b.m64[v] : 0.0;
+    int64_t cand[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const int q = threadIdx.x / kLongChunk + 4 * i;
+        cand[i] = q < gn ? int64_t(b.wfinal[g0 + q].idx) : -1;
+    }
+    double acc[kRescoreGroup];
+#pragma unroll
+    for (int q = 0; q < kRescoreGroup; ++q) acc[q] = 0.0;
+    if (gn <= 2) {
+        double a2[2] = {0.0, 0.0};
+        long_sums<2>(c, v0, cand, live, xt, cx, a2);
+        acc[0] = a2[0];
+        acc[1] = a2[1];
+    } else {
+        long_sums<kRescoreGroup>(c, v0, cand, live, xt, cx, acc);
+    }
+#pragma unroll
+    for (int q = 0; q < kRescoreGroup; ++q) red[q][threadIdx.x] = (live && q < gn) ? fmax(0.0, mv - acc[q]) : 0.0;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) {
+#pragma unroll
+            for (int q = 0; q < kRescoreGroup; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < gn) b.rpart[blk * kWindowMax + g0 + threadIdx.x] = red[threadIdx.x][0];
+}
+
+__device__ void update_long_body(const InstDesc& c, int64_t blk) {
+    __shared__ float xt[kLongChunk][kBlock + 1];
+    __shared__ float cx[kRescoreGroup][kLongChunk];
+    __shared__ double red[kBlock];
+    const Buffers& b = c.b;
+    const int cs = b.state->cstar;
+    const int64_t v0 = blk * kBlock;
+    const int64_t v = v0 + threadIdx.x;
+    double acc[1] = {0.0};
+    if (cs >= 0) {
+        const int64_t cand[2] = {threadIdx.x < kLongChunk ? int64_t(cs) : -1, -1};
+        long_sums<1>(c, v0, cand, v < c.n, xt, cx, acc);
+    }
+    double mv = 0.0;
+    if (v < c.n) {
+        mv = b.m64[v];
+        if (cs >= 0 && acc[0] < mv) {
+            mv = acc[0];
+            b.m64[v] = mv;
+            set_point_terms(b, v, mv);
+        }
+    }
+    red[threadIdx.x] = mv;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) b.fpart[blk] = red[0];
+}
+
 // ---- fsum (one block per instance): f(S_t) = L({e0}) - |V|^-1 sum m_v ----
 __device__ void fsum_body(const InstDesc& c, int32_t t) {
     __shared__ double red[kBlock];
@@ -332,6 +479,8 @@ __global__ void __launch_bounds__(kSelThreads) k_wselect(InstDesc c) { wselect_b
 __global__ void __launch_bounds__(kBlock) k_rescore(InstDesc c) { rescore_body(c, blockIdx.x); }
 __global__ void __launch_bounds__(kBlock) k_pick(InstDesc c, int32_t t) { pick_body(c, t); }
 __global__ void __launch_bounds__(kBlock) k_update(InstDesc c) { update_body(c, blockIdx.x); }
+__global__ void __launch_bounds__(kBlock) k_rescore_long(InstDesc c) { rescore_long_body(c, blockIdx.x, blockIdx.y); }
+__global__ void __launch_bounds__(kBlock) k_update_long(InstDesc c) { update_long_body(c, blockIdx.x); }
 __global__ void __launch_bounds__(kBlock) k_fsum(InstDesc c, int32_t t) { fsum_body(c, t); }
 
 // ---- batched kernels: blocks of row_pre[i] .. row_pre[i+1] belong to instance i;
@@ -347,8 +496,23 @@ __global__ void __launch_bounds__(kBlock) k_fsum(InstDesc c, int32_t t) { fsum_b
     }
 EBC_ROW_KERNEL(kb_gsum, gsum_body)
 EBC_ROW_KERNEL(kb_wcount, wcount_body)
-EBC_ROW_KERNEL(kb_rescore, rescore_body)
-EBC_ROW_KERNEL(kb_update, update_body)
+// mixed batches: each re-score / update body runs only for its own row length
+__device__ __forceinline__ void rescore_short(const InstDesc& c, int64_t blk) {
+    if (!wide_rows(c.k_pad)) rescore_body(c, blk);
+}
+__device__ __forceinline__ void update_short(const InstDesc& c, int64_t blk) {
+    if (!wide_rows(c.k_pad)) update_body(c, blk);
+}
+__device__ __forceinline__ void rescore_long(const InstDesc& c, int64_t blk) {
+    if (wide_rows(c.k_pad)) rescore_long_body(c, blk, blockIdx.y);
+}
+__device__ __forceinline__ void update_long(const InstDesc& c, int64_t blk) {
+    if (wide_rows(c.k_pad)) update_long_body(c, blk);
+}
+EBC_ROW_KERNEL(kb_rescore, rescore_short)
+EBC_ROW_KERNEL(kb_update, update_short)
+EBC_ROW_KERNEL(kb_rescore_long, rescore_long)
+EBC_ROW_KERNEL(kb_update_long, update_long)
 #undef EBC_ROW_KERNEL
 
 __global__ void __launch_bounds__(kSelThreads) kb_wselect(const InstDesc* __restrict__ descs, int32_t t) {
@@ -375,27 +539,38 @@ hipError_t launch_greedy_step(const ebc_dataset* ds, int32_t t, int32_t* sel_out
     hipLaunchKernelGGL(k_gsum, dim3(nb), dim3(kBlock), 0, s, c);
     hipLaunchKernelGGL(k_wcount, dim3(nb), dim3(kBlock), 0, s, c);
     hipLaunchKernelGGL(k_wselect, dim3(1), dim3(kSelThreads), 0, s, c);
-    hipLaunchKernelGGL(k_rescore, dim3(nb), dim3(kBlock), 0, s, c);
-    hipLaunchKernelGGL(k_pick, dim3(1), dim3(kBlock), 0, s, c, t);
-    hipLaunchKernelGGL(k_update, dim3(nb), dim3(kBlock), 0, s, c);
+    if (wide_rows(c.k_pad)) {
+        hipLaunchKernelGGL(k_rescore_long, dim3(nb, kWindowMax / kRescoreGroup), dim3(kBlock), 0, s, c);
+        hipLaunchKernelGGL(k_pick, dim3(1), dim3(kBlock), 0, s, c, t);
+        hipLaunchKernelGGL(k_update_long, dim3(nb), dim3(kBlock), 0, s, c);
+    } else {
+        hipLaunchKernelGGL(k_rescore, dim3(nb), dim3(kBlock), 0, s, c);
+        hipLaunchKernelGGL(k_pick, dim3(1), dim3(kBlock), 0, s, c, t);
+        hipLaunchKernelGGL(k_update, dim3(nb), dim3(kBlock), 0, s, c);
+    }
     hipLaunchKernelGGL(k_fsum, dim3(1), dim3(kBlock), 0, s, c, t);
     return hipGetLastError();
 }
 
 hipError_t launch_step_batched(const InstDesc* descs, const int64_t* row_pre, int32_t count, int64_t total_rows,
-                               int32_t t, hipStream_t s) {
+                               int32_t t, bool long_rows, hipStream_t s) {
     const dim3 rows = dim3(unsigned(total_rows)), one = dim3(unsigned(count));
     hipLaunchKernelGGL(kb_gsum, rows, dim3(kBlock), 0, s, descs, row_pre, count, t);
     hipLaunchKernelGGL(kb_wcount, rows, dim3(kBlock), 0, s, descs, row_pre, count, t);
     hipLaunchKernelGGL(kb_wselect, one, dim3(kSelThreads), 0, s, descs, t);
     hipLaunchKernelGGL(kb_rescore, rows, dim3(kBlock), 0, s, descs, row_pre, count, t);
+    if (long_rows)
+        hipLaunchKernelGGL(kb_rescore_long, dim3(unsigned(total_rows), kWindowMax / kRescoreGroup), dim3(kBlock), 0, s,
+                           descs, row_pre, count, t);
     hipLaunchKernelGGL(kb_pick, one, dim3(kBlock), 0, s, descs, t);
     hipLaunchKernelGGL(kb_update, rows, dim3(kBlock), 0, s, descs, row_pre, count, t);
+    if (long_rows) hipLaunchKernelGGL(kb_update_long, rows, dim3(kBlock), 0, s, descs, row_pre, count, t);
     hipLaunchKernelGGL(kb_fsum, one, dim3(kBlock), 0, s, descs, t);
     return hipGetLastError();
 }
 
 hipError_t launch_gains(const ebc_dataset* ds, const int32_t* cand, int64_t n_cand, hipStream_t s) {
+    if (wide_rows(ds->k_pad)) return launch_gains_wide(ds, cand, n_cand, s);
     return ds->dt == EBC_DT_F32 ? launch_gains_f32(ds, cand, n_cand, s) : launch_gains_lp(ds, cand, n_cand, s);
 }
 

@@ -372,7 +372,10 @@ ebc_status ebc_server_step(ebc_server* sv, int32_t* completed) {
         e = launch_gains_batched(b.key, sv->d_desc, sv->d_slot + b.slot_begin, sv->d_wg_pre + b.pre_off, b.slots,
                                  b.total_wgs, 0, sv->stream);
     }
-    if (e == hipSuccess) e = launch_step_batched(sv->d_desc, sv->d_row_pre, count, sv->total_rows, 0, sv->stream);
+    bool long_rows = false;
+    for (const Request* r : sv->active) long_rows |= wide_rows(r->ds->k_pad);
+    if (e == hipSuccess)
+        e = launch_step_batched(sv->d_desc, sv->d_row_pre, count, sv->total_rows, 0, long_rows, sv->stream);
     if (e != hipSuccess) return EBC_E_DEVICE;
     ++sv->ticks;
     // finished requests: copy out at the end of this tick

@@ -20,6 +20,7 @@ __all__ = ["EBCError", "Dataset", "Batch", "Server", "Arena", "request_bytes", "
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libebc.so")
 DTYPES = {"f32": 0, "f16": 1, "bf16": 2, "fp8": 3}
+MAX_DIM = 4096  # EBC_MAX_DIM of include/ebc.h
 ABI_FUNCTIONS = (
     "ebc_dataset_bytes", "ebc_dataset_create", "ebc_dataset_destroy", "ebc_eval_sets", "ebc_eval_sets_in_dtype",
     "ebc_marginal_gains", "ebc_greedy", "ebc_sync_status", "ebc_status_string",
@@ -159,7 +160,7 @@ class Dataset:
             raise ValueError(f"dtype must be one of {sorted(DTYPES)}")
         nbytes = L.ebc_dataset_bytes(self.n, self.d, DTYPES[dtype])
         if nbytes == 0:
-            raise EBCError(1 if self.d <= 128 else 7, f"ebc_dataset_bytes(n={self.n}, d={self.d})")
+            raise EBCError(1 if self.d <= MAX_DIM else 7, f"ebc_dataset_bytes(n={self.n}, d={self.d})")
         self.workspace_bytes = int(nbytes)
         self.workspace = torch.empty(self.workspace_bytes, dtype=torch.uint8, device=self.x.device)
         h = ctypes.c_void_p()

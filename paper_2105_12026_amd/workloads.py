@@ -191,3 +191,14 @@ def paper_sets(seed: int = 6, n: int = 50_000, l: int = 5000, set_size: int = 10
     offsets = np.arange(l + 1, dtype=np.int64) * set_size
     return Problem(x=x, k=0, name=f"paper_sets_n{n}_l{l}_k{set_size}_d{d}", offsets=offsets, idx=idx,
                    meta={"seed": seed, "sets": l, "set_size": set_size})
+
+
+def case_study_curves(seed: int = 8, n: int = 1000, d: int = 3524, k: int = 50) -> Problem:
+    """Long-row workload in the shape of the paper's case study (Sec. 6:
+    summaries of size k from N = 1000 process series of d = 3524 samples;
+    the injection-moulding data is not available): one machine's curves from
+    ``process_curves`` (shared bumps, per-curve jitter, noise, 5% drifted
+    anomalies) at length d."""
+    rng = np.random.default_rng(seed)
+    x = process_curves(rng, n, d).astype(np.float32)
+    return Problem(x=x, k=k, name=f"curves_n{n}_d{d}_k{k}", meta={"seed": seed})

@@ -53,7 +53,9 @@ def test_workspace_size_is_exact_and_monotone(L):
     assert b >= 100096 * 104 * 4
     assert L.ebc_dataset_bytes(0, 16, 0) == 0
     assert L.ebc_dataset_bytes(10, 0, 0) == 0
-    assert L.ebc_dataset_bytes(10, 129, 0) == 0
+    assert L.ebc_dataset_bytes(10, 129, 0) > 0      # long rows are supported ...
+    assert L.ebc_dataset_bytes(10, 4096, 3) > 0
+    assert L.ebc_dataset_bytes(10, 4097, 0) == 0     # ... up to EBC_MAX_DIM
     assert L.ebc_dataset_bytes(10, 16, 9) == 0
 
 
@@ -65,7 +67,7 @@ def test_host_validation_without_device(L):
     assert L.ebc_dataset_create(P(256), 10, 4, 0, 0, None, 1 << 20, None, ctypes.byref(h)) == 1
     assert L.ebc_dataset_create(P(256), 10, 4, 0, 1, P(256), 1 << 20, None, ctypes.byref(h)) == 1
     assert L.ebc_dataset_create(P(256), 10, 4, 5, 0, P(256), 1 << 20, None, ctypes.byref(h)) == 1
-    assert L.ebc_dataset_create(P(256), 10, 200, 0, 0, P(256), 1 << 30, None, ctypes.byref(h)) == 7
+    assert L.ebc_dataset_create(P(256), 10, 5000, 0, 0, P(256), 1 << 30, None, ctypes.byref(h)) == 7
     assert L.ebc_dataset_create(P(256), 10, 4, 0, 0, P(128), 1 << 20, None, ctypes.byref(h)) == 1  # misaligned
     assert L.ebc_dataset_create(P(256), 10, 4, 0, 0, P(256), 16, None, ctypes.byref(h)) == 1  # too small
     assert L.ebc_dataset_create(P(256), 10, 4, 0, 0, P(256), 1 << 20, None, None) == 1

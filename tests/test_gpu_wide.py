@@ -1,0 +1,142 @@
+"""Long rows (padded length above 128 values; the paper's case study has
+N = 1000 series of d = 3524 samples, Sec. 6) against the FP64 oracle, through
+the C ABI: marginal gains with the dimension split over the waves of a
+workgroup (small ground sets) or not (large ones), greedy selections, and
+multi-set evaluation, in every distance dtype.
+
+Bars as for short rows: float32 gains max_c |G - G_ref| <= 1e-5 max_c |G_ref|,
+identical greedy selections, f within 1e-5 relative; reduced precision at the
+per-dtype gain and multi-set bars of the short-row tests."""
+import numpy as np
+import pytest
+
+from paper_2105_12026_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+G_RTOL = 1e-5
+GAIN_TOL = {"bf16": 1e-2, "f16": 2e-3, "fp8": 8e-2}
+ES_TOL = {"bf16": 2e-2, "f16": 5e-3, "fp8": 1.5e-1}
+_REF_CACHE = {}
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    from paper_2105_12026_amd import ebc
+    assert torch.cuda.is_available()
+    return torch, ebc
+
+
+def _x(kind, n, d, seed):
+    if kind == "curves":
+        return W.process_curves(np.random.default_rng(seed), n, d).astype(np.float32)
+    return W.gaussian_mixture(np.random.default_rng(seed), n, d, 6).astype(np.float32)
+
+
+def _ds(env, x, dt):
+    torch, ebc = env
+    return ebc.Dataset(torch.from_numpy(np.ascontiguousarray(x, np.float32)).cuda(), dtype=dt)
+
+
+def _ref_gains(ref, key, x, m):
+    if key not in _REF_CACHE:
+        _REF_CACHE[key] = ref.gains(x, m)
+    return _REF_CACHE[key]
+
+
+# (kind, n, d, seed): 1000 x 3524 and the smallest long row (d = 129) split K
+# over four waves; 16500 x 130 (16640 padded rows) keeps one block per wave.
+GAIN_CASES = [("curves", 1000, 3524, 1), ("gmm", 300, 129, 2), ("gmm", 2113, 200, 3), ("gmm", 16500, 130, 4),
+              ("gmm", 70, 520, 5)]
+
+
+@pytest.mark.parametrize("dt", ["f32", "bf16", "f16", "fp8"])
+@pytest.mark.parametrize("kind,n,d,seed", GAIN_CASES)
+def test_wide_gains(env, ref, dt, kind, n, d, seed):
+    torch, _ = env
+    x = _x(kind, n, d, seed)
+    rng = np.random.default_rng(seed + 100)
+    s = rng.choice(n, min(n, 5), replace=False)
+    print(f"[gpu-case] long-row gains {dt} {kind} n={n} d={d}", flush=True)
+    ds = _ds(env, x, dt)
+    errs = []
+    for tag, sel in (("empty", []), ("later", s)):
+        m = ref.min_dist(x, sel)
+        g = ds.marginal_gains(m=torch.from_numpy(m)).cpu().numpy()
+        ds.sync()
+        rg = _ref_gains(ref, (kind, n, d, seed, tag), x, m)
+        errs.append(float(np.max(np.abs(g - rg)) / np.max(np.abs(rg))))
+    # an unordered candidate list with repeats gives the same values
+    cand = np.concatenate([np.arange(n)[::-1], rng.integers(0, n, 7)]).astype(np.int32)
+    gc = ds.marginal_gains(m=torch.from_numpy(m), cand=torch.from_numpy(cand)).cpu().numpy()
+    ds.sync()
+    np.testing.assert_array_equal(gc, g[cand])
+    print(f"[gpu-result] long-row gains {dt} n={n} d={d}: rel err {max(errs):.3e}", flush=True)
+    assert max(errs) <= (G_RTOL if dt == "f32" else GAIN_TOL[dt])
+
+
+@pytest.mark.parametrize("kind,n,d,k,seed", [("curves", 1000, 3524, 12, 11), ("gmm", 600, 300, 20, 12),
+                                             ("gmm", 16200, 129, 3, 13)])
+def test_wide_greedy_f32(env, ref, kind, n, d, k, seed):
+    x = _x(kind, n, d, seed)
+    print(f"[gpu-case] long-row greedy f32 {kind} n={n} d={d} k={k}", flush=True)
+    ds = _ds(env, x, "f32")
+    sel, f, g = ds.greedy(k)
+    stats = ds.sync()
+    rsel, rf, rg = ref.greedy(x, k)
+    assert sel.cpu().numpy().tolist() == rsel.tolist()
+    np.testing.assert_allclose(f.cpu().numpy(), rf, rtol=1e-5)
+    np.testing.assert_allclose(g.cpu().numpy(), rg, rtol=1e-5, atol=1e-12 * rf[-1])
+    assert stats["window_overflow"] == 0
+
+
+@pytest.mark.parametrize("dt", ["bf16", "f16", "fp8"])
+def test_wide_greedy_lowprec_quality(env, ref, dt):
+    x = _x("curves", 1000, 3524, 11)
+    k = 12
+    print(f"[gpu-case] long-row greedy {dt} curves n=1000 d=3524 k={k}", flush=True)
+    ds = _ds(env, x, dt)
+    sel, f, _ = ds.greedy(k)
+    ds.sync()
+    sel = sel.cpu().numpy()
+    f = f.cpu().numpy()
+    rsel, rf, _ = ref.greedy(x, k)
+    l0 = float(np.mean(np.sum(x.astype(np.float64) ** 2, axis=1)))
+    for t in (0, k - 1):
+        m = ref.min_dist(x, sel[:t + 1])
+        assert f[t] == pytest.approx(l0 - float(np.mean(m)), rel=1e-9)
+    gap = (rf[-1] - f[-1]) / rf[-1]
+    print(f"[gpu-result] long-row greedy {dt}: quality gap {gap:.2e}", flush=True)
+    assert gap <= {"bf16": 1e-3, "f16": 1e-3, "fp8": 2e-2}[dt]
+
+
+@pytest.mark.parametrize("kind,n,d,seed", [("curves", 1000, 3524, 21), ("gmm", 700, 200, 22), ("gmm", 300, 131, 23)])
+def test_wide_eval_sets(env, ref, kind, n, d, seed):
+    """Sets of many sizes (across unit, block and window boundaries, empty
+    sets between) with float32 dot products, and in each reduced dtype."""
+    torch, _ = env
+    x = _x(kind, n, d, seed)
+    rng = np.random.default_rng(seed)
+    sizes = [0, 1, 7, 8, 9, 0, 31, 32, 33, 64, 100, 257, 3, 10] + list(rng.integers(1, 30, 60))
+    sets = [rng.integers(0, n, sz) for sz in sizes]
+    off = np.cumsum([0] + [len(q) for q in sets]).astype(np.int64)
+    idx = np.concatenate(sets).astype(np.int32)
+    rf = ref.eval_sets(x, off, idx)
+    l0 = float(np.mean(np.sum(x.astype(np.float64) ** 2, axis=1)))
+    to, ti = torch.from_numpy(off), torch.from_numpy(idx)
+    for dt in ("f32", "bf16", "f16", "fp8"):
+        print(f"[gpu-case] long-row eval_sets {dt} {kind} n={n} d={d} l={len(sets)}", flush=True)
+        ds = _ds(env, x, dt)
+        f32 = ds.eval_sets(to, ti).cpu().numpy()
+        ds.sync()
+        assert np.all(f32[np.array(sizes) == 0] == 0.0)
+        assert np.all(np.abs(f32 - rf) <= 1e-5 * np.abs(rf) + 1e-6 * l0), dt
+        if dt != "f32":
+            f1 = ds.eval_sets(to, ti, in_dtype=True).cpu().numpy()
+            f2 = ds.eval_sets(to, ti, in_dtype=True).cpu().numpy()
+            ds.sync()
+            assert np.array_equal(f1, f2)
+            rel = np.abs(f1 - rf) / (np.abs(rf) + 1e-3 * l0)
+            print(f"[gpu-result] long-row eval_sets in {dt}: max rel err {rel.max():.3e}", flush=True)
+            assert rel.max() <= ES_TOL[dt]

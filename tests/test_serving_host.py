@@ -78,7 +78,8 @@ def test_request_bytes(ebc):
     assert ebc.request_bytes(10_000, 64, 50, "bf16") > base
     assert ebc.request_bytes(10_000, 64, 10, "f32") > base  # float32 copy is wider than bf16
     assert ebc.request_bytes(10, 64, 11, "bf16") == 0       # k > n
-    assert ebc.request_bytes(10, 129, 5, "bf16") == 0       # d beyond the supported maximum
+    assert ebc.request_bytes(10, 4097, 5, "bf16") == 0      # d beyond the supported maximum
+    assert ebc.request_bytes(1000, 3524, 5, "bf16") > 1000 * 3524 * 4
     assert base % 256 == 0
 
 
