@@ -11,7 +11,9 @@ against the paper by eye:
 * k-medoids loss, Sec. 4, Definition "k-medoids loss" (Eq. k_medoids_loss):
   L(S) = |V|^-1 sum_{v in V} min_{s in S} d(v, s).
 * Exemplar-based clustering, Sec. 4, Definition "Exemplar-based clustering"
-  (Eq. exemplar_based_clustering): f(S) = L({e0}) - L(S u {e0}), e0 = 0.
+  (Eq. exemplar_based_clustering): f(S) = L({e0}) - L(S u {e0}), with the
+  auxiliary vector e0 the zero vector by default (the paper's example) or
+  any d-vector passed as ``e0``.
 * CPU evaluation, Sec. 4.1, Algorithm 1: per ground point a running minimum
   over the set, a sum over the ground points, division by |V|.
 * Discrete derivative, Sec. 3, Definition "Discrete derivative":
@@ -24,7 +26,7 @@ against the paper by eye:
   setup).
 
 Readings where the paper is silent (each listed in the design notes):
-e0 is the zero vector; ties in the greedy argmax go to the lowest index;
+e0 is the zero vector unless given; ties in the greedy argmax go to the lowest index;
 greedy keeps picking (gain 0) once every point is covered; sets are lists of
 row indices into V, may be empty and may repeat an index.
 
@@ -71,32 +73,37 @@ def loss(x: np.ndarray, s_vectors) -> float:
     return float(np.sum(t) / x.shape[0])
 
 
-def f_value(x: np.ndarray, s_idx) -> float:
-    """f(S) = L({e0}) - L(S u {e0}) with e0 the zero vector (Eq.
-    exemplar_based_clustering; Algorithm 1, return statement). ``s_idx`` lists
-    row indices of x forming S (may be empty)."""
+def _aux(x: np.ndarray, e0) -> np.ndarray:
+    """The auxiliary vector e0 (Sec. 4): the zero vector unless given."""
+    return np.zeros(x.shape[1]) if e0 is None else np.asarray(e0, dtype=np.float64).reshape(x.shape[1])
+
+
+def f_value(x: np.ndarray, s_idx, e0=None) -> float:
+    """f(S) = L({e0}) - L(S u {e0}) (Eq. exemplar_based_clustering;
+    Algorithm 1, return statement). ``s_idx`` lists row indices of x forming
+    S (may be empty)."""
     x = np.asarray(x, dtype=np.float64)
-    e0 = np.zeros(x.shape[1])
+    e0 = _aux(x, e0)
     members = [x[int(i)] for i in s_idx]
     return loss(x, [e0]) - loss(x, [e0] + members)
 
 
-def eval_sets(x: np.ndarray, offsets: np.ndarray, idx: np.ndarray) -> np.ndarray:
+def eval_sets(x: np.ndarray, offsets: np.ndarray, idx: np.ndarray, e0=None) -> np.ndarray:
     """f(S_j) for every set of a CSR-packed family S_multi = {S_1, .., S_l}
     (Sec. 4.1: optimisers score many sets per step). Set j holds
     idx[offsets[j]:offsets[j+1]]."""
     l = len(offsets) - 1
     out = np.empty(l)
     for j in range(l):
-        out[j] = f_value(x, idx[offsets[j]:offsets[j + 1]])
+        out[j] = f_value(x, idx[offsets[j]:offsets[j + 1]], e0)
     return out
 
 
-def min_dist_to_set(x: np.ndarray, s_idx) -> np.ndarray:
+def min_dist_to_set(x: np.ndarray, s_idx, e0=None) -> np.ndarray:
     """m_v = min(d(v, e0), min_{s in S} d(v, s)) for every v: the per-point
     term inside L(S u {e0}) (Eq. loss_decomposed, times |V|)."""
     x = np.asarray(x, dtype=np.float64)
-    m = sqdist(x, np.zeros(x.shape[1]))
+    m = sqdist(x, _aux(x, e0))
     for i in s_idx:
         m = np.minimum(m, sqdist(x, x[int(i)]))
     return m
@@ -121,7 +128,7 @@ def gains(x: np.ndarray, m: np.ndarray, cand=None) -> np.ndarray:
     return np.array([marginal_gain(x, m, c) for c in cand], dtype=np.float64)
 
 
-def greedy(x: np.ndarray, k: int):
+def greedy(x: np.ndarray, k: int, e0=None):
     """Greedy maximisation of f under |S| <= k (Sec. 3; Sec. 4.1).
 
     Each step scores every not-yet-selected point by its marginal gain,
@@ -129,8 +136,8 @@ def greedy(x: np.ndarray, k: int):
     S. Returns (selected indices [k], f(S_1..S_k) [k], gains [k])."""
     x = np.asarray(x, dtype=np.float64)
     n = x.shape[0]
-    l0 = float(np.sum(sqdist(x, np.zeros(x.shape[1]))) / n)
-    m = min_dist_to_set(x, [])
+    l0 = float(np.sum(sqdist(x, _aux(x, e0))) / n)
+    m = min_dist_to_set(x, [], e0)
     chosen = np.zeros(n, dtype=bool)
     sel, fs, gs = [], [], []
     for _ in range(k):
@@ -145,7 +152,7 @@ def greedy(x: np.ndarray, k: int):
     return np.array(sel, dtype=np.int64), np.array(fs), np.array(gs)
 
 
-def exhaustive(x: np.ndarray, k: int):
+def exhaustive(x: np.ndarray, k: int, e0=None):
     """max_{S subset V, |S| <= k} f(S) by enumerating every subset (Eq.
     submodular_function_optimization_cardinality_constraint). Tiny n only.
     Returns (best value, best subset as a tuple)."""
@@ -153,7 +160,7 @@ def exhaustive(x: np.ndarray, k: int):
     best, arg = 0.0, ()
     for size in range(0, k + 1):
         for s in itertools.combinations(range(n), size):
-            v = f_value(x, s)
+            v = f_value(x, s, e0)
             if v > best:
                 best, arg = v, s
     return best, arg

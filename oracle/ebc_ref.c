@@ -8,7 +8,8 @@
  * These are the same definitions as oracle/ebc_oracle.py, written as loops so
  * that they finish at the benchmark sizes:
  *   - squared Euclidean dissimilarity (Sec. 5), direct differences in double;
- *   - k-medoids loss and f(S) = L({e0}) - L(S u {e0}) with e0 = 0
+ *   - k-medoids loss and f(S) = L({e0}) - L(S u {e0}), the auxiliary
+ *     vector e0 given as a d-vector or, when NULL, the zero vector
  *     (Sec. 4, Eqs. k_medoids_loss and exemplar_based_clustering; Alg. 1);
  *   - marginal gain Delta(c|S) = |V|^-1 sum_v max(0, m_v - d(v,c)), where
  *     m_v = min(d(v,e0), min_{s in S} d(v,s)) (Sec. 3, discrete derivative);
@@ -42,6 +43,12 @@ static double sqn(const float* a, int d)
     return s;
 }
 
+/* d(v, e0): e0 NULL is the zero vector */
+static double d_e0(const float* a, const float* e0, int d)
+{
+    return e0 ? sqd(a, e0, d) : sqn(a, d);
+}
+
 int ebc_ref_threads(void)
 {
 #ifdef _OPENMP
@@ -53,12 +60,12 @@ int ebc_ref_threads(void)
 
 /* m[v] = min(d(v, e0), min_{s in S} d(v, s)) for all v. */
 void ebc_ref_min_dist(const float* x, int64_t n, int32_t d, const int32_t* s, int64_t ns,
-                      double* m)
+                      double* m, const float* e0)
 {
 #pragma omp parallel for schedule(static)
     for (int64_t v = 0; v < n; ++v) {
         const float* xv = x + v * d;
-        double t = sqn(xv, d);
+        double t = d_e0(xv, e0, d);
         for (int64_t j = 0; j < ns; ++j) {
             double dv = sqd(xv, x + (int64_t)s[j] * d, d);
             if (dv < t) t = dv;
@@ -85,17 +92,17 @@ void ebc_ref_gains(const float* x, int64_t n, int32_t d, const double* m, const 
 
 /* f(S_j) = L({e0}) - L(S_j u {e0}) for CSR sets; set j = idx[off[j] .. off[j+1]). */
 void ebc_ref_eval_sets(const float* x, int64_t n, int32_t d, const int64_t* off,
-                       const int32_t* idx, int64_t l, double* out)
+                       const int32_t* idx, int64_t l, double* out, const float* e0)
 {
     double l0 = 0.0;
-    for (int64_t v = 0; v < n; ++v) l0 += sqn(x + v * d, d);
+    for (int64_t v = 0; v < n; ++v) l0 += d_e0(x + v * d, e0, d);
     l0 /= (double)n;
 #pragma omp parallel for schedule(dynamic, 1)
     for (int64_t j = 0; j < l; ++j) {
         double sum = 0.0;
         for (int64_t v = 0; v < n; ++v) {
             const float* xv = x + v * d;
-            double t = sqn(xv, d); /* e0 = 0 is always in the set */
+            double t = d_e0(xv, e0, d); /* e0 is always in the set */
             for (int64_t q = off[j]; q < off[j + 1]; ++q) {
                 double dv = sqd(xv, x + (int64_t)idx[q] * d, d);
                 if (dv < t) t = dv;
@@ -109,7 +116,7 @@ void ebc_ref_eval_sets(const float* x, int64_t n, int32_t d, const int64_t* off,
 /* Greedy to cardinality k. sel[t], f[t] = f(S_{t+1}), g[t] = gain of step t.
  * Returns 0, -1 if memory runs out, -2 if k > n. */
 int ebc_ref_greedy(const float* x, int64_t n, int32_t d, int32_t k, int32_t* sel, double* f,
-                   double* g)
+                   double* g, const float* e0)
 {
     double* m = (double*)malloc(sizeof(double) * (size_t)n);
     double* gv = (double*)malloc(sizeof(double) * (size_t)n);
@@ -120,7 +127,7 @@ int ebc_ref_greedy(const float* x, int64_t n, int32_t d, int32_t k, int32_t* sel
     }
     double l0 = 0.0;
     for (int64_t v = 0; v < n; ++v) {
-        m[v] = sqn(x + v * d, d);
+        m[v] = d_e0(x + v * d, e0, d);
         l0 += m[v];
     }
     l0 /= (double)n;
@@ -211,7 +218,7 @@ static double ref_gain_one(const float* x, int64_t n, int32_t d, const double* m
 }
 
 int ebc_ref_greedy_lazy(const float* x, int64_t n, int32_t d, int32_t k, int32_t* sel, double* f,
-                        double* g, int64_t* evals)
+                        double* g, int64_t* evals, const float* e0)
 {
     if (k > n) return -2;
     double* m = (double*)malloc(sizeof(double) * (size_t)n);
@@ -225,7 +232,7 @@ int ebc_ref_greedy_lazy(const float* x, int64_t n, int32_t d, int32_t k, int32_t
     }
     double l0 = 0.0;
     for (int64_t v = 0; v < n; ++v) {
-        m[v] = sqn(x + v * d, d);
+        m[v] = d_e0(x + v * d, e0, d);
         l0 += m[v];
     }
     l0 /= (double)n;

@@ -24,12 +24,12 @@ def lib():
         P = ctypes.c_void_p
         i64, i32 = ctypes.c_int64, ctypes.c_int32
         L.ebc_ref_threads.restype = ctypes.c_int
-        L.ebc_ref_min_dist.argtypes = [P, i64, i32, P, i64, P]
+        L.ebc_ref_min_dist.argtypes = [P, i64, i32, P, i64, P, P]
         L.ebc_ref_gains.argtypes = [P, i64, i32, P, P, i64, P]
-        L.ebc_ref_eval_sets.argtypes = [P, i64, i32, P, P, i64, P]
-        L.ebc_ref_greedy.argtypes = [P, i64, i32, i32, P, P, P]
+        L.ebc_ref_eval_sets.argtypes = [P, i64, i32, P, P, i64, P, P]
+        L.ebc_ref_greedy.argtypes = [P, i64, i32, i32, P, P, P, P]
         L.ebc_ref_greedy.restype = ctypes.c_int
-        L.ebc_ref_greedy_lazy.argtypes = [P, i64, i32, i32, P, P, P, P]
+        L.ebc_ref_greedy_lazy.argtypes = [P, i64, i32, i32, P, P, P, P, P]
         L.ebc_ref_greedy_lazy.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -43,15 +43,24 @@ def _p(a):
     return a.ctypes.data_as(ctypes.c_void_p)
 
 
+def _e0(x, e0):
+    """(keep-alive array, pointer) of the auxiliary vector; None = zero vector."""
+    if e0 is None:
+        return None, None
+    a = np.ascontiguousarray(np.asarray(e0, dtype=np.float32).reshape(x.shape[1]))
+    return a, _p(a)
+
+
 def threads() -> int:
     return int(lib().ebc_ref_threads())
 
 
-def min_dist(x, s_idx) -> np.ndarray:
+def min_dist(x, s_idx, e0=None) -> np.ndarray:
     x = _f32(x)
     s = np.ascontiguousarray(s_idx, dtype=np.int32)
     m = np.empty(x.shape[0])
-    lib().ebc_ref_min_dist(_p(x), x.shape[0], x.shape[1], _p(s), s.size, _p(m))
+    keep, pe = _e0(x, e0)
+    lib().ebc_ref_min_dist(_p(x), x.shape[0], x.shape[1], _p(s), s.size, _p(m), pe)
     return m
 
 
@@ -64,27 +73,29 @@ def gains(x, m, cand=None) -> np.ndarray:
     return out
 
 
-def eval_sets(x, offsets, idx) -> np.ndarray:
+def eval_sets(x, offsets, idx, e0=None) -> np.ndarray:
     x = _f32(x)
     off = np.ascontiguousarray(offsets, dtype=np.int64)
     idx = np.ascontiguousarray(idx, dtype=np.int32)
     out = np.empty(off.size - 1)
-    lib().ebc_ref_eval_sets(_p(x), x.shape[0], x.shape[1], _p(off), _p(idx), off.size - 1, _p(out))
+    keep, pe = _e0(x, e0)
+    lib().ebc_ref_eval_sets(_p(x), x.shape[0], x.shape[1], _p(off), _p(idx), off.size - 1, _p(out), pe)
     return out
 
 
-def greedy(x, k: int):
+def greedy(x, k: int, e0=None):
     x = _f32(x)
     sel = np.empty(k, dtype=np.int32)
     f = np.empty(k)
     g = np.empty(k)
-    rc = lib().ebc_ref_greedy(_p(x), x.shape[0], x.shape[1], int(k), _p(sel), _p(f), _p(g))
+    keep, pe = _e0(x, e0)
+    rc = lib().ebc_ref_greedy(_p(x), x.shape[0], x.shape[1], int(k), _p(sel), _p(f), _p(g), pe)
     if rc != 0:
         raise ValueError(f"ebc_ref_greedy failed ({rc})")
     return sel.astype(np.int64), f, g
 
 
-def greedy_lazy(x, k: int):
+def greedy_lazy(x, k: int, e0=None):
     """Same result as greedy(), by lazy re-evaluation of stale upper bounds.
     Returns (sel, f, gain, gain evaluations)."""
     x = _f32(x)
@@ -92,7 +103,9 @@ def greedy_lazy(x, k: int):
     f = np.empty(k)
     g = np.empty(k)
     ev = ctypes.c_int64(0)
-    rc = lib().ebc_ref_greedy_lazy(_p(x), x.shape[0], x.shape[1], int(k), _p(sel), _p(f), _p(g), ctypes.byref(ev))
+    keep, pe = _e0(x, e0)
+    rc = lib().ebc_ref_greedy_lazy(_p(x), x.shape[0], x.shape[1], int(k), _p(sel), _p(f), _p(g), ctypes.byref(ev),
+                                   pe)
     if rc != 0:
         raise ValueError(f"ebc_ref_greedy_lazy failed ({rc})")
     return sel.astype(np.int64), f, g, int(ev.value)

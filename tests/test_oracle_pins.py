@@ -290,3 +290,88 @@ def test_lazy_greedy_equals_plain_greedy(ref, name):
     assert evals <= x.shape[0] * k
     with pytest.raises(ValueError):
         ref.greedy_lazy(x, x.shape[0] + 1)
+
+
+# --------------------------------------------------------------------------
+# A non-zero auxiliary vector e0 (Sec. 4 leaves e0 open, the zero vector
+# being its example)
+# --------------------------------------------------------------------------
+def test_e0_hand_values():
+    # V = {0, 2, 5} on a line, e0 = 4: d(., e0) = {16, 4, 1}, L({e0}) = 7.
+    # S = {2}: m = min({16,4,1}, {4,0,9}) = {4, 0, 1}, f = 7 - 5/3 = 16/3.
+    # S = {0}: m = min({16,4,1}, {0,4,25}) = {0, 4, 1}, f = 7 - 5/3 = 16/3.
+    # S = {5}: m = {16,4,1} vs {25,9,0} -> {16,4,0}, f = 7 - 20/3 = 1/3.
+    x = _x([[0.0], [2.0], [5.0]])
+    e0 = np.array([4.0])
+    assert O.f_value(x, [], e0) == 0.0
+    assert O.f_value(x, [1], e0) == pytest.approx(16 / 3, rel=1e-15)
+    assert O.f_value(x, [0], e0) == pytest.approx(16 / 3, rel=1e-15)
+    assert O.f_value(x, [2], e0) == pytest.approx(1 / 3, rel=1e-15)
+    assert O.f_value(x, [0, 1, 2], e0) == pytest.approx(7.0, rel=1e-15)
+    # greedy: gains {16/3, 16/3, 1/3}, tie -> index 0 first; then from
+    # m = {0, 4, 1}: index 1 gains (4)/3, index 2 gains (1)/3
+    sel, f, g = O.greedy(x, 2, e0)
+    assert list(sel) == [0, 1]
+    np.testing.assert_allclose(g, [16 / 3, 4 / 3], rtol=1e-15)
+
+
+def test_e0_translation_identity():
+    # d is translation invariant while e0 moves with the data: f on (X, e0)
+    # equals f on (X - e0, 0), for every set (float32 inputs, differences
+    # exact in float64, so the values agree to the last bit)
+    x = _rand(50, 6, 31)
+    e0 = np.random.default_rng(32).standard_normal(6).astype(np.float32)
+    xs = x.astype(np.float64) - e0.astype(np.float64)
+    for s in ([], [3], [0, 7, 19], list(range(0, 50, 5))):
+        assert O.f_value(x, s, e0) == O.f_value(xs, s)
+    m = O.min_dist_to_set(x, [4, 9], e0)
+    np.testing.assert_array_equal(m, O.min_dist_to_set(xs, [4, 9]))
+
+
+def test_e0_at_a_data_point():
+    # e0 equal to a point p: d(p, e0) = 0, so adding p gains nothing, and a
+    # far e0 makes L({e0}) the mean squared distance to it
+    x = _rand(30, 4, 33)
+    p = 11
+    e0 = x[p].astype(np.float64)
+    assert O.f_value(x, [p], e0) == 0.0
+    assert O.marginal_gain(x, O.min_dist_to_set(x, [3], e0), p) == 0.0
+    far = np.full(4, 100.0)
+    l0 = float(np.mean(np.sum((x.astype(np.float64) - far) ** 2, axis=1)))
+    assert O.f_value(x, range(30), far) == pytest.approx(l0, rel=1e-14)
+
+
+@pytest.mark.parametrize("seed", [41, 42])
+def test_e0_greedy_bound_and_invariants(seed):
+    rng = np.random.default_rng(seed)
+    x = rng.standard_normal((11, 3)).astype(np.float32)
+    e0 = rng.standard_normal(3)
+    k = 3
+    best, _ = O.exhaustive(x, k, e0)
+    sel, f, g = O.greedy(x, k, e0)
+    assert f[-1] >= (1 - 1 / math.e) * best - 1e-12
+    assert np.all(np.diff(g) <= 1e-12) and np.all(g >= 0)
+    np.testing.assert_allclose(np.cumsum(g), f, rtol=1e-12, atol=1e-14)
+    # monotone and submodular with this e0
+    a, b = [1], [1, 4, 7]
+    for e in (0, 2, 9):
+        da = O.f_value(x, a + [e], e0) - O.f_value(x, a, e0)
+        db = O.f_value(x, b + [e], e0) - O.f_value(x, b, e0)
+        assert da >= db - 1e-12 and db >= -1e-12
+
+
+def test_c_oracle_e0_matches_numpy_oracle(ref):
+    x = _rand(200, 7, 43)
+    e0 = np.random.default_rng(44).standard_normal(7).astype(np.float32)
+    sel_np, f_np, g_np = O.greedy(x, 5, e0)
+    sel_c, f_c, g_c = ref.greedy(x, 5, e0)
+    assert list(sel_c) == list(sel_np)
+    np.testing.assert_allclose(f_c, f_np, rtol=1e-12)
+    sel_l, f_l, g_l, _ = ref.greedy_lazy(x, 5, e0)
+    assert list(sel_l) == list(sel_c)
+    np.testing.assert_array_equal(f_l, f_c)
+    np.testing.assert_allclose(ref.min_dist(x, sel_np[:2], e0), O.min_dist_to_set(x, sel_np[:2], e0), rtol=1e-13)
+    off = np.array([0, 0, 3, 8, 9], dtype=np.int64)
+    idx = np.random.default_rng(45).integers(0, 200, 9).astype(np.int32)
+    np.testing.assert_allclose(ref.eval_sets(x, off, idx, e0), O.eval_sets(x, off, idx, e0), rtol=1e-12,
+                               atol=1e-15)
