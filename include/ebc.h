@@ -111,6 +111,19 @@ EBC_API ebc_status ebc_dataset_create(const float* x, int64_t n, int32_t d, ebc_
  * caller must not free those before enqueued work has finished. */
 EBC_API ebc_status ebc_dataset_destroy(ebc_dataset* ds);
 
+/* Set the auxiliary vector e0 of f(S) = L({e0}) - L(S u {e0}) (Sec. 4, Eq.
+ * exemplar_based_clustering: e0 is any fixed vector, the zero vector being
+ * the paper's example and the default after ebc_dataset_create).
+ *   e0  [device] float32 [d], read during the call's stream work only (it may
+ *       be freed once that work has finished); NULL restores the origin.
+ * Stream-ordered on `stream`: recomputes d(v, e0) in float64 (direct
+ * differences) and L({e0}), and resets the greedy state to S = {}. Every
+ * later f, gain and greedy result of this dataset uses e0. A non-finite e0
+ * is reported by ebc_sync_status as EBC_E_NONFINITE.
+ * Errors: EBC_E_INVALID_ARG for a null dataset; EBC_E_DEVICE if a launch
+ * fails. */
+EBC_API ebc_status ebc_dataset_set_e0(ebc_dataset* ds, const float* e0, void* stream);
+
 /* f(S_j) for l sets packed as CSR (Sec. 4.1, S_multi = {S_1..S_l}; Alg. 1
  * per set; Alg. 2 computes the same per-(set, point) minima).
  *   offsets [device] int64 [l+1], offsets[0] = 0, non-decreasing.

@@ -113,6 +113,7 @@ ebc_status ebc_dataset_create(const float* x, int64_t n, int32_t d, ebc_dtype dt
     b.scale = dt == EBC_DT_FP8_E4M3 ? reinterpret_cast<int*>(w + L.off_scale) : nullptr;
     b.mu = wide_rows(ds->k_pad) ? reinterpret_cast<double*>(w + L.off_mu) : nullptr;
     b.n64 = reinterpret_cast<double*>(w + L.off_n64);
+    b.m0 = reinterpret_cast<double*>(w + L.off_m0);
     b.m64 = reinterpret_cast<double*>(w + L.off_m64);
     b.hn = reinterpret_cast<float*>(w + L.off_hn);
     b.ha = reinterpret_cast<float*>(w + L.off_ha);
@@ -145,6 +146,11 @@ ebc_status ebc_dataset_destroy(ebc_dataset* ds) {
     delete ds->prof;
     delete ds;
     return EBC_OK;
+}
+
+ebc_status ebc_dataset_set_e0(ebc_dataset* ds, const float* e0, void* stream) {
+    if (!ds) return EBC_E_INVALID_ARG;
+    return from_hip(launch_set_e0(ds, e0, as_stream(stream)));
 }
 
 ebc_status ebc_set_gains_variant(ebc_dataset* ds, int32_t variant) {
@@ -189,7 +195,7 @@ ebc_status ebc_dataset_get_info(ebc_dataset* ds, ebc_dataset_info* info) {
     info->d = ds->d;
     info->k_pad = ds->k_pad;
     info->v_splits = ds->v_splits;
-    info->cand_tile = ds->dt == EBC_DT_F32 ? kGainsCandTile : 256;
+    info->cand_tile = int32_t(gains_cand_tile(ds));
     info->window_cap = kWindowMax;
     info->dtype = int32_t(ds->dt);
     info->l0 = ds->l0_host;

@@ -54,6 +54,7 @@ struct Buffers {
                         // reduced precision: 64-row tiles, 16-byte units unit-major inside a tile
     int* scale;         // [n_pad] E8M0 row scales (FP8 only, else null)
     double* n64;        // [n_pad] ||v||^2 in float64 (0 for pad rows)
+    double* m0;         // [n_pad] d(v, e0) in float64, the minima of S = {} (= n64 for e0 = 0)
     double* mu;         // [k_pad] column means; long rows only (the distance-dtype copy then
                         // holds x - mu, and hn is the norm of that centred copy), else null
     double* m64;        // [n_pad] running minima m_v (float64 master copy)
@@ -122,7 +123,7 @@ __device__ inline int find_slot(const int64_t* __restrict__ pre, int count, int6
 }
 
 struct Layout {
-    size_t off_xq, off_scale, off_mu, off_n64, off_m64, off_hn, off_ha, off_hm, off_sel, off_part, off_gsum, off_bmax,
+    size_t off_xq, off_scale, off_mu, off_n64, off_m0, off_m64, off_hn, off_ha, off_hm, off_sel, off_part, off_gsum, off_bmax,
         off_barg, off_bcnt, off_wstage, off_wfinal, off_rpart, off_fpart, off_state, total;
 };
 
@@ -275,6 +276,7 @@ hipError_t launch_reset_batched(const InstDesc* descs, const int64_t* row_pre, i
 // Launchers (each defined next to its kernels). All return hipGetLastError().
 hipError_t launch_prep(const ebc_dataset* ds, hipStream_t s);
 hipError_t launch_reset_state(const ebc_dataset* ds, hipStream_t s);
+hipError_t launch_set_e0(const ebc_dataset* ds, const float* e0, hipStream_t s);
 hipError_t launch_load_m(const ebc_dataset* ds, const double* m, hipStream_t s);
 hipError_t launch_gains_f32(const ebc_dataset* ds, const int32_t* cand, int64_t n_cand, hipStream_t s);
 hipError_t launch_gains_lp(const ebc_dataset* ds, const int32_t* cand, int64_t n_cand, hipStream_t s);

@@ -196,12 +196,20 @@ __device__ __forceinline__ void block_info(int tid, int64_t blk, int64_t u0, int
 // Units of 4 rows of one member block against this wave's 64 points: unit
 // uu is held by lane half uu%2 in result registers 4*(uu/2) .. +3. Running
 // maximum per (set, point) in cur (per 32-point block); at a set's last unit
-// the two lane halves are joined, clamped at 0, and each column's value is
-// added to the lane's own float accumulator of that set (lacc[wave][set][col];
-// the final pass sums them in float64 in a fixed order).
+// the two lane halves are joined, shifted by the point's wsh (below), clamped
+// at 0, and each column's value is added to the lane's own float accumulator
+// of that set (lacc[wave][set][col]; the final pass sums them in float64 in
+// a fixed order).
+//
+// wsh: with a general auxiliary vector e0 (and, for the cast rows, norms
+// that are not those of the exact rows) the per-point term is
+//     n_v - min(n_v, d(v,s)) = 2 max(0, v.s - ||s||^2/2 + (n_v - ||v||^2)/2)
+// with n_v = d(v, e0); the last part is the per-point shift wsh (0 for the
+// float32 rows when e0 = 0).
 template <int WIN>
 __device__ __forceinline__ void es_units(const floatx16 (&acc)[2], const int32_t* unit_flags, const int32_t* unit_local,
-                                         float (&cur)[2], int half, int col, float (&lacc)[WIN][32]) {
+                                         const float (&wsh)[2], float (&cur)[2], int half, int col,
+                                         float (&lacc)[WIN][32]) {
 #pragma unroll
     for (int uu = 0; uu < kBlockUnits; ++uu) {
         const int flags = unit_flags[uu];
@@ -216,7 +224,7 @@ __device__ __forceinline__ void es_units(const floatx16 (&acc)[2], const int32_t
         if (flags & 2) {
             float sv = 0.0f;
 #pragma unroll
-            for (int cb = 0; cb < 2; ++cb) sv += fmaxf(fmaxf(cur[cb], __shfl_xor(cur[cb], 32, 64)), 0.0f);
+            for (int cb = 0; cb < 2; ++cb) sv += fmaxf(fmaxf(cur[cb], __shfl_xor(cur[cb], 32, 64)) + wsh[cb], 0.0f);
             if (half == 0) lacc[unit_local[uu]][col] += sv;
         }
     }
@@ -240,7 +248,7 @@ __device__ __forceinline__ void es_finish(int tid, int64_t j0, int64_t j1, int s
 template <int KP>
 __global__ void __launch_bounds__(256)
 k_es_main(const float* __restrict__ x, int64_t n, int32_t d, const double* __restrict__ n64,
-          const int64_t* __restrict__ off, const int32_t* __restrict__ idx, int64_t l, int32_t splits,
+          const double* __restrict__ m0, const int64_t* __restrict__ off, const int32_t* __restrict__ idx, int64_t l, int32_t splits,
           EsScratch sc) {
     constexpr int KH = KP / 2;  // K values per lane half
     constexpr int S = KP + 4;   // LDS row stride (S/4 odd: conflict-free 16-byte reads)
@@ -287,10 +295,12 @@ k_es_main(const float* __restrict__ x, int64_t n, int32_t d, const double* __res
             for (int64_t vs = v_begin; vs < v_end; vs += kVSub) {
                 // this wave's 64 ground points (B operand), K split in lane halves
                 float b[2][KH];
+                float wsh[2];
 #pragma unroll
                 for (int cb = 0; cb < 2; ++cb) {
                     const int64_t v = vs + wave * 64 + cb * 32 + col;
                     const bool ok = v < v_end;
+                    wsh[cb] = ok ? float(0.5 * (m0[v] - n64[v])) : 0.0f;
                     if (d % 4 == 0) {
                         // rows 16-byte aligned: 4 values per load; a 4-group is
                         // either wholly inside the row or wholly padding
@@ -362,7 +372,7 @@ k_es_main(const float* __restrict__ x, int64_t n, int32_t d, const double* __res
                                 acc[cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[i], b[cb][4 * s4 + i], acc[cb], 0,
                                                                                0, 0);
                     }
-                    es_units<kWindow>(acc, bi.unit_flags, bi.unit_local, cur, half, col, lacc[wave]);
+                    es_units<kWindow>(acc, bi.unit_flags, bi.unit_local, wsh, cur, half, col, lacc[wave]);
                     if (more) {
                         float* dst = reinterpret_cast<float*>(lds_m4[rb ^ 1]) + grow * S;
 #pragma unroll
@@ -387,8 +397,8 @@ k_es_main(const float* __restrict__ x, int64_t n, int32_t d, const double* __res
 template <int DT, int KC, int W>
 __global__ void __launch_bounds__(256)
 k_es_lp(const uint4* __restrict__ xq, const float* __restrict__ hn, const int* __restrict__ scale, int64_t n,
-        const double* __restrict__ n64, const int64_t* __restrict__ off, const int32_t* __restrict__ idx, int64_t l,
-        int32_t splits, EsScratch sc) {
+        const double* __restrict__ n64, const double* __restrict__ m0, const int64_t* __restrict__ off,
+        const int32_t* __restrict__ idx, int64_t l, int32_t splits, EsScratch sc) {
     using T = Lp<DT>;
     constexpr int HU = KC * T::kU4;  // 16-byte units per lane half-row
     constexpr int RU = 2 * HU;       // units per row
@@ -477,10 +487,12 @@ k_es_lp(const uint4* __restrict__ xq, const float* __restrict__ hn, const int* _
             for (int64_t vs = v_begin; vs < v_end; vs += kVSub) {
                 uint4 b[2][HU];
                 int sb[2];
+                float wsh[2];
 #pragma unroll
                 for (int cb = 0; cb < 2; ++cb) {
                     const int64_t v = vs + wave * 64 + cb * 32 + col;
                     const bool ok = v < v_end;
+                    wsh[cb] = ok ? float(0.5 * m0[v] - double(hn[v])) : 0.0f;
                     const uint4* src = xq + (v / 64) * (RU * 64) + (v % 64);
 #pragma unroll
                     for (int u = 0; u < HU; ++u) b[cb][u] = ok ? src[(half * HU + u) * 64] : make_uint4(0, 0, 0, 0);
@@ -502,8 +514,8 @@ k_es_lp(const uint4* __restrict__ xq, const float* __restrict__ hn, const int* _
 #pragma unroll
                         for (int cb = 0; cb < 2; ++cb)
                             acc[cb] = mfma_main<DT>(&a[q * T::kU4], &b[cb][q * T::kU4], acc[cb], sa, sb[cb]);
-                    es_units<W>(acc, res_flags + blk * kBlockUnits, res_local + blk * kBlockUnits, cur, half, col,
-                                lacc[wave]);
+                    es_units<W>(acc, res_flags + blk * kBlockUnits, res_local + blk * kBlockUnits, wsh, cur, half,
+                                col, lacc[wave]);
                 }
             }
         } else if (nunits > 0 && v_end > v_begin) {
@@ -511,10 +523,12 @@ k_es_lp(const uint4* __restrict__ xq, const float* __restrict__ hn, const int* _
             for (int64_t vs = v_begin; vs < v_end; vs += kVSub) {
                 uint4 b[2][HU];
                 int sb[2];
+                float wsh[2];
 #pragma unroll
                 for (int cb = 0; cb < 2; ++cb) {
                     const int64_t v = vs + wave * 64 + cb * 32 + col;
                     const bool ok = v < v_end;
+                    wsh[cb] = ok ? float(0.5 * m0[v] - double(hn[v])) : 0.0f;
                     const uint4* src = xq + (v / 64) * (RU * 64) + (v % 64);
 #pragma unroll
                     for (int u = 0; u < HU; ++u) b[cb][u] = ok ? src[(half * HU + u) * 64] : make_uint4(0, 0, 0, 0);
@@ -567,7 +581,7 @@ k_es_lp(const uint4* __restrict__ xq, const float* __restrict__ hn, const int* _
 #pragma unroll
                         for (int cb = 0; cb < 2; ++cb)
                             acc[cb] = mfma_main<DT>(&a[q * T::kU4], &b[cb][q * T::kU4], acc[cb], sa, sb[cb]);
-                    es_units<W>(acc, bi.unit_flags, bi.unit_local, cur, half, col, lacc[wave]);
+                    es_units<W>(acc, bi.unit_flags, bi.unit_local, wsh, cur, half, col, lacc[wave]);
                     if (more) {
 #pragma unroll
                         for (int i = 0; i < PFU; ++i) {
@@ -593,15 +607,14 @@ k_es_lp(const uint4* __restrict__ xq, const float* __restrict__ hn, const int* _
 // lanes 32..39: the units), so the waves meet at a barrier only for the
 // item's final sums. DT = F32 reads the caller's float32 rows [n, d] with the
 // float64 norms; otherwise the cast rows, their norms and (FP8) scales. The
-// cast copy of long rows is centred at the column means mu, so with
-// x' = x - mu the per-pair term becomes
-//     v.s - n_s/2 = x'_v.x'_s - ||x'_s||^2/2 + (n_v - ||x'_v||^2)/2,
-// the last part a per-point shift added to the accumulator's start.
+// cast copy of long rows is centred at the column means mu: with x' = x - mu,
+// v.s - ||s||^2/2 = x'_v.x'_s - ||x'_s||^2/2 + (||v||^2 - ||x'_v||^2)/2, so
+// the per-point shift of es_units is taken against the centred norms.
 template <int DT>
 __global__ void __launch_bounds__(256)
 k_es_wide(const void* src, int32_t len, const float* __restrict__ hn, const int* __restrict__ scale, int64_t n,
-          const double* __restrict__ n64, const int64_t* __restrict__ off, const int32_t* __restrict__ idx,
-          int64_t l, int32_t splits, EsScratch sc) {
+          const double* __restrict__ n64, const double* __restrict__ m0, const int64_t* __restrict__ off,
+          const int32_t* __restrict__ idx, int64_t l, int32_t splits, EsScratch sc) {
     using R = WideRow<DT>;
     using Piece = typename R::Piece;
     constexpr int B = R::kBatch;
@@ -654,14 +667,15 @@ k_es_wide(const void* src, int32_t len, const float* __restrict__ hn, const int*
                 int64_t prow[2];
                 bool pok[2];
                 int sb[2];
-                float wsh[2];  // per-point shift of the centred cast rows (0 for float32)
+                float wsh[2];  // per-point shift (see es_units)
 #pragma unroll
                 for (int cb = 0; cb < 2; ++cb) {
                     const int64_t v = vs + wave * 64 + cb * 32 + col;
                     pok[cb] = v < v_end;
                     prow[cb] = pok[cb] ? v : 0;
                     sb[cb] = (kFp8 && pok[cb]) ? scale[v] : 127;
-                    wsh[cb] = (!kF32 && pok[cb]) ? float(0.5 * n64[v] - double(hn[v])) : 0.0f;
+                    wsh[cb] = !pok[cb] ? 0.0f
+                                       : (kF32 ? float(0.5 * (m0[v] - n64[v])) : float(0.5 * m0[v] - double(hn[v])));
                 }
                 float cur[2] = {-INFINITY, -INFINITY};
                 for (int64_t blk = 0; blk < nblk; ++blk) {
@@ -701,8 +715,8 @@ k_es_wide(const void* src, int32_t len, const float* __restrict__ hn, const int*
 #pragma unroll
                     for (int r = 0; r < 16; ++r) {
                         const float c = __shfl(my_c, 8 * (r / 4) + 4 * half + (r % 4), 64);
-                        acc[0][r] = c + wsh[0];
-                        acc[1][r] = c + wsh[1];
+                        acc[0][r] = c;
+                        acc[1][r] = c;
                     }
                     // member rows x this wave's points over the whole dimension
                     Piece a[B], b[2][B];
@@ -739,7 +753,7 @@ k_es_wide(const void* src, int32_t len, const float* __restrict__ hn, const int*
                             }
                         }
                     }
-                    es_units<kWindow>(acc, uflags, ulocal, cur, half, col, lacc[wave]);
+                    es_units<kWindow>(acc, uflags, ulocal, wsh, cur, half, col, lacc[wave]);
                 }
             }
         }
@@ -770,7 +784,8 @@ __global__ void __launch_bounds__(256) k_es_final(int64_t l, int64_t n, int32_t 
 template <int KP>
 void launch_es_main(dim3 g, hipStream_t s, const ebc_dataset* ds, const int64_t* off, const int32_t* idx, int64_t l,
                     int32_t splits, const EsScratch& sc) {
-    hipLaunchKernelGGL((k_es_main<KP>), g, dim3(256), 0, s, ds->x, ds->n, ds->d, ds->b.n64, off, idx, l, splits, sc);
+    hipLaunchKernelGGL((k_es_main<KP>), g, dim3(256), 0, s, ds->x, ds->n, ds->d, ds->b.n64, ds->b.m0, off, idx, l,
+                       splits, sc);
 }
 
 }  // namespace
@@ -816,7 +831,7 @@ hipError_t launch_eval_sets(const ebc_dataset* ds, const int64_t* offsets, const
 #define EBC_ESW(DTV)                                                                                              \
     case DTV:                                                                                                     \
         hipLaunchKernelGGL((k_es_wide<DTV>), g, dim3(256), 0, s, src, len, ds->b.hn, ds->b.scale, ds->n, ds->b.n64, \
-                           offsets, idx, l, splits, sc);                                                          \
+                           ds->b.m0, offsets, idx, l, splits, sc);                                                \
         break;
             EBC_ESW(EBC_DT_F32) EBC_ESW(EBC_DT_F16) EBC_ESW(EBC_DT_BF16) EBC_ESW(EBC_DT_FP8_E4M3)
 #undef EBC_ESW
@@ -828,8 +843,7 @@ hipError_t launch_eval_sets(const ebc_dataset* ds, const int64_t* offsets, const
 #define EBC_ESL(DTV, K)                                                                                         \
     case K:                                                                                                     \
         hipLaunchKernelGGL((k_es_lp<DTV, K, lp_window(DTV, K)>), g, dim3(256), 0, s, xq, ds->b.hn, ds->b.scale,   \
-                           ds->n, ds->b.n64,                                                              \
-                           offsets, idx, l, splits, sc);                                                        \
+                           ds->n, ds->b.n64, ds->b.m0, offsets, idx, l, splits, sc);                     \
         break;
         bool ok = true;
         switch (ds->dt) {

@@ -110,6 +110,7 @@ Layout layout(int64_t n, int32_t d, ebc_dtype dt) {
     L.off_scale = dt == EBC_DT_FP8_E4M3 ? take(size_t(np) * sizeof(int)) : 0;
     L.off_mu = wide_rows(kp) ? take(size_t(kp) * sizeof(double)) : 0;
     L.off_n64 = take(size_t(np) * sizeof(double));
+    L.off_m0 = take(size_t(np) * sizeof(double));
     L.off_m64 = take(size_t(np) * sizeof(double));
     L.off_hn = take(size_t(np) * sizeof(float));
     L.off_ha = take(size_t(np) * sizeof(float));
@@ -176,6 +177,7 @@ __global__ void __launch_bounds__(kBlock) k_prep(const float* __restrict__ x, in
         for (int k = d; k < kp; ++k) q[k] = 0.0f;
         const float hn = float(0.5 * nc);
         b.n64[r] = nv;
+        b.m0[r] = nv;
         b.m64[r] = nv;
         b.hn[r] = hn;
         b.ha[r] = float(0.5 * nv - double(hn));
@@ -185,6 +187,7 @@ __global__ void __launch_bounds__(kBlock) k_prep(const float* __restrict__ x, in
         float* q = b.xq + r * kp;
         for (int k = 0; k < kp; ++k) q[k] = 0.0f;
         b.n64[r] = 0.0;
+        b.m0[r] = 0.0;
         b.m64[r] = 0.0;
         b.hn[r] = 0.0f;
         b.ha[r] = 0.0f;
@@ -277,6 +280,7 @@ __global__ void __launch_bounds__(kBlock) k_prep_lp(const float* __restrict__ x,
         if (range) atomicCAS(&b.state->error, 0, int(EBC_E_RANGE));
         b.hn[r] = float(0.5 * nq);
         b.n64[r] = nv;
+        b.m0[r] = nv;
         b.m64[r] = nv;
         b.selected[r] = 0;
         set_point_terms(b, r, nv);
@@ -287,6 +291,7 @@ __global__ void __launch_bounds__(kBlock) k_prep_lp(const float* __restrict__ x,
         for (int k = 0; k < kp * eb; ++k) base[tiled_offset(r, k, ru)] = 0;
         if (b.scale) b.scale[r] = 127;
         b.n64[r] = 0.0;
+        b.m0[r] = 0.0;
         b.m64[r] = 0.0;
         b.hn[r] = 0.0f;
         b.ha[r] = 0.0f;
@@ -366,12 +371,12 @@ hipError_t launch_prep(const ebc_dataset* ds, hipStream_t s) {
     return hipGetLastError();
 }
 
-// Greedy restart: m_v = ||v||^2, nothing selected, window counters cleared.
+// Greedy restart: m_v = d(v, e0), nothing selected, window counters cleared.
 __device__ void reset_body(const InstDesc& c, int64_t blk) {
     const Buffers& b = c.b;
     const int64_t r = blk * kBlock + threadIdx.x;
     if (r < c.n) {
-        const double nv = b.n64[r];
+        const double nv = b.m0[r];
         b.m64[r] = nv;
         set_point_terms(b, r, nv);
         b.selected[r] = 0;
@@ -407,6 +412,62 @@ hipError_t launch_reset_batched(const InstDesc* descs, const int64_t* row_pre, i
                                 hipStream_t s) {
     hipLaunchKernelGGL(kb_reset, dim3(unsigned(total_rows)), dim3(kBlock), 0, s, descs, row_pre, count);
     return hipGetLastError();
+}
+
+// The auxiliary vector e0 (Sec. 4: any fixed vector, the zero vector being
+// the paper's example): d(v, e0) in float64 by direct differences (e0 null:
+// ||v||^2), with per-block sums and maxima for L({e0}); a non-finite e0
+// raises EBC_E_NONFINITE.
+__global__ void __launch_bounds__(kBlock) k_set_e0(const float* __restrict__ x, int64_t n, int32_t d,
+                                                   const float* __restrict__ e0, Buffers b) {
+    __shared__ float ce[EBC_MAX_DIM];
+    __shared__ double red[kBlock];
+    __shared__ double rmax[kBlock];
+    __shared__ int bad;
+    if (threadIdx.x == 0) bad = 0;
+    __syncthreads();
+    if (e0)
+        for (int k = threadIdx.x; k < d; k += kBlock) {
+            ce[k] = e0[k];
+            if (!isfinite(ce[k])) bad = 1;
+        }
+    __syncthreads();
+    const int64_t r = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+    double mv = 0.0;
+    if (r < n) {
+        if (e0) {
+            const float* xr = x + r * d;
+            for (int k = 0; k < d; ++k) {
+                const double t = double(xr[k]) - double(ce[k]);
+                mv += t * t;
+            }
+        } else {
+            mv = b.n64[r];
+        }
+        b.m0[r] = mv;
+    }
+    if (threadIdx.x == 0 && blockIdx.x == 0 && bad) atomicCAS(&b.state->error, 0, kDevErrNonFinite);
+    red[threadIdx.x] = mv;
+    rmax[threadIdx.x] = mv;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) {
+            red[threadIdx.x] += red[threadIdx.x + w];
+            rmax[threadIdx.x] = fmax(rmax[threadIdx.x], rmax[threadIdx.x + w]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        b.fpart[blockIdx.x] = red[0];
+        b.bmax[blockIdx.x] = rmax[0];
+    }
+}
+
+hipError_t launch_set_e0(const ebc_dataset* ds, const float* e0, hipStream_t s) {
+    const int nb = int(ds->n_pad / kBlock);
+    hipLaunchKernelGGL(k_set_e0, dim3(nb), dim3(kBlock), 0, s, ds->x, ds->n, ds->d, e0, ds->b);
+    hipLaunchKernelGGL(k_l0, dim3(1), dim3(kBlock), 0, s, ds->n, nb, ds->b);
+    return launch_reset_state(ds, s);
 }
 
 // Replace the running minima by a caller-supplied m (float64, [n]).

@@ -24,7 +24,7 @@ MAX_DIM = 4096  # EBC_MAX_DIM of include/ebc.h
 ABI_FUNCTIONS = (
     "ebc_dataset_bytes", "ebc_dataset_create", "ebc_dataset_destroy", "ebc_eval_sets", "ebc_eval_sets_in_dtype",
     "ebc_marginal_gains", "ebc_greedy", "ebc_sync_status", "ebc_status_string",
-    "ebc_dataset_get_info", "ebc_profile_enable", "ebc_profile_read", "ebc_set_gains_variant",
+    "ebc_dataset_get_info", "ebc_dataset_set_e0", "ebc_profile_enable", "ebc_profile_read", "ebc_set_gains_variant",
     "ebc_gains_variant_count", "ebc_set_greedy_graph", "ebc_batch_bytes", "ebc_batch_create",
     "ebc_batch_destroy", "ebc_batch_set_graph", "ebc_greedy_batched", "ebc_batch_info", "ebc_autotune",
     "ebc_tune_cache_load", "ebc_tune_cache_save", "ebc_tune_cache_size", "ebc_request_bytes",
@@ -83,6 +83,7 @@ def lib() -> ctypes.CDLL:
         L.ebc_dataset_get_info.argtypes = [P, ctypes.POINTER(_Info)]
         L.ebc_profile_enable.argtypes = [P, i32]
         L.ebc_set_gains_variant.argtypes = [P, i32]
+        L.ebc_dataset_set_e0.argtypes = [P, P, P]
         L.ebc_set_greedy_graph.argtypes = [P, i32]
         L.ebc_gains_variant_count.argtypes = [ctypes.c_int]
         L.ebc_profile_read.argtypes = [P, ctypes.POINTER(_Profile), i32]
@@ -195,6 +196,18 @@ class Dataset:
         inf = _Info()
         _check(lib().ebc_dataset_get_info(self._h, ctypes.byref(inf)), "ebc_dataset_get_info")
         return {f: getattr(inf, f) for f, _ in _Info._fields_}
+
+    def set_e0(self, e0=None, stream=None):
+        """Auxiliary vector e0 of f (ebc_dataset_set_e0): a float32 CUDA
+        tensor [d], or None for the origin. Resets the greedy state."""
+        if e0 is not None:
+            if not (isinstance(e0, torch.Tensor) and e0.is_cuda and e0.dtype == torch.float32
+                    and e0.numel() == self.d):
+                raise TypeError("e0 must be a float32 CUDA tensor with d elements")
+            e0 = e0.contiguous()
+        self._e0 = e0  # kept alive until the stream work has read it
+        _check(lib().ebc_dataset_set_e0(self._h, None if e0 is None else _ptr(e0), _stream(stream)),
+               "ebc_dataset_set_e0")
 
     def set_variant(self, variant: int):
         """Tile shape of the gains kernel (results are identical across variants)."""
