@@ -37,6 +37,7 @@ routine and the submodularity/monotonicity invariants.
 from __future__ import annotations
 
 import itertools
+import math
 
 import numpy as np
 
@@ -50,6 +51,8 @@ __all__ = [
     "greedy",
     "exhaustive",
     "min_dist_to_set",
+    "sieve_thresholds",
+    "three_sieves",
 ]
 
 
@@ -164,3 +167,62 @@ def exhaustive(x: np.ndarray, k: int, e0=None):
             if v > best:
                 best, arg = v, s
     return best, arg
+
+
+def sieve_thresholds(m: float, k: int, eps: float) -> list:
+    """Guesses of the optimum for a threshold rule (the sieve grid of the
+    streaming optimisers the paper cites in Sec. 2 and runs in Sec. 6): every
+    power (1+eps)^i with m <= (1+eps)^i <= k*m, where m is the largest
+    singleton value max_e f({e}); largest first. Empty when m <= 0."""
+    if m <= 0.0:
+        return []
+    base = math.log1p(eps)
+    lo = math.ceil(math.log(m) / base)
+    hi = math.floor(math.log(k * m) / base)
+    return [(1.0 + eps) ** i for i in range(hi, lo - 1, -1)]
+
+
+def three_sieves(x: np.ndarray, k: int, eps: float, T: int, m=None, order=None, e0=None):
+    """Three Sieves: one summary S built from a stream of the points of V.
+
+    The threshold v starts at the largest guess of sieve_thresholds. An
+    arriving point e joins S when |S| < k and
+        Delta(e | S) >= (v/2 - f(S)) / (k - |S|);
+    otherwise a counter of consecutive rejections grows, and after T of them
+    v moves to the next smaller guess (the counter restarts; it also restarts
+    on every acceptance; at the smallest guess v stays). The stream ends
+    early once |S| = k. ``m`` is the largest singleton value (computed when
+    None); ``order`` the stream as indices into x (default 0..n-1).
+    Returns (accepted indices, f(S) after each acceptance, v at each
+    acceptance, number of points examined)."""
+    x = np.asarray(x, dtype=np.float64)
+    n = x.shape[0]
+    order = range(n) if order is None else [int(i) for i in order]
+    mv = min_dist_to_set(x, [], e0)
+    l0 = float(np.sum(mv) / n)
+    if m is None:
+        m = max(marginal_gain(x, mv, c) for c in range(n))
+    grid = sieve_thresholds(m, k, eps)
+    sel, fs, vs = [], [], []
+    if not grid or k <= 0:
+        return sel, fs, vs, 0
+    j, t, fS, seen = 0, 0, 0.0, 0
+    for e in order:
+        if len(sel) == k:
+            break
+        seen += 1
+        v = grid[j]
+        g = marginal_gain(x, mv, e)
+        if g >= (v / 2.0 - fS) / (k - len(sel)):
+            sel.append(e)
+            mv = np.minimum(mv, sqdist(x, x[e]))
+            fS = l0 - float(np.sum(mv) / n)
+            fs.append(fS)
+            vs.append(v)
+            t = 0
+        else:
+            t += 1
+            if t >= T and j + 1 < len(grid):
+                j += 1
+                t = 0
+    return sel, fs, vs, seen

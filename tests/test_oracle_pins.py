@@ -375,3 +375,64 @@ def test_c_oracle_e0_matches_numpy_oracle(ref):
     idx = np.random.default_rng(45).integers(0, 200, 9).astype(np.int32)
     np.testing.assert_allclose(ref.eval_sets(x, off, idx, e0), O.eval_sets(x, off, idx, e0), rtol=1e-12,
                                atol=1e-15)
+
+
+# --------------------------------------------------------------------------
+# Three Sieves (the streaming optimiser the paper cites in Sec. 2 and runs in
+# its case study, Sec. 6)
+# --------------------------------------------------------------------------
+def test_sieve_thresholds_grid():
+    for m, k, eps in [(33.0, 2, 0.25), (1.0, 10, 0.1), (0.37, 5, 0.5)]:
+        g = O.sieve_thresholds(m, k, eps)
+        assert g and all(m <= v <= k * m for v in g)
+        assert all(a > b for a, b in zip(g, g[1:]))
+        np.testing.assert_allclose([a / b for a, b in zip(g, g[1:])], 1 + eps, rtol=1e-12)
+        assert g[0] * (1 + eps) > k * m and g[-1] / (1 + eps) < m  # no power of (1+eps) left out
+    assert O.sieve_thresholds(0.0, 3, 0.1) == []
+
+
+def test_three_sieves_hand_cases():
+    # V = {0, 4, 6, 10} on a line, e0 = 0: n_v = {0, 16, 36, 100}, L({e0}) = 38;
+    # singletons f({4}) = 112/4 = 28, f({6}) = 132/4 = 33, f({10}) = 120/4 = 30,
+    # f({0}) = 0, so m = 33. k = 2, eps = 1/4: the powers 1.25^i in [33, 66] are
+    # 1.25^18 = 55.51, 1.25^17 = 44.41, 1.25^16 = 35.53.
+    # Stream 0, 4, 10, 6 with T = 1: x=0 gains 0 < 55.51/4 -> rejected, v drops
+    # to 44.41; x=4 gains 28 >= 44.41/4 -> S = {4}, m = {0,0,4,36}, f = 28;
+    # x=10 gains 36/4 = 9 >= (22.2 - 28)/1 -> S = {4, 10}, m = {0,0,4,0}, f = 37.
+    x = _x([[0.0], [4.0], [6.0], [10.0]])
+    sel, f, v, seen = O.three_sieves(x, 2, 0.25, 1, order=[0, 1, 3, 2])
+    assert sel == [1, 3] and seen == 3
+    np.testing.assert_allclose(f, [28.0, 37.0], rtol=1e-15)
+    np.testing.assert_allclose(v, [1.25 ** 17] * 2, rtol=1e-15)
+    # V = {0, 1, 10, 11}: L({e0}) = 55.5, singletons 0, 10.25, 55, 55; k = 2,
+    # eps = 1: the grid in [55, 110] is {64}. x=0 (0) and x=1 (10.25) fall
+    # short of 64/4 = 16; x=10 joins (f = 55.5 - 2/4 = 55); then the bound
+    # (32 - 55)/1 is negative and x=11 joins with gain 1/4 (f = 55.25).
+    x = _x([[0.0], [1.0], [10.0], [11.0]])
+    sel, f, v, seen = O.three_sieves(x, 2, 1.0, 1)
+    assert sel == [2, 3] and seen == 4
+    np.testing.assert_allclose(f, [55.0, 55.25], rtol=1e-15)
+    assert v == [64.0, 64.0]
+
+
+@pytest.mark.parametrize("seed,k,eps,T", [(51, 4, 0.1, 3), (52, 6, 0.5, 1), (53, 3, 0.2, 50), (54, 8, 0.05, 10)])
+def test_three_sieves_invariants(seed, k, eps, T):
+    # Each acceptance at threshold v closes at least the fraction 1/(k - |S|)
+    # of the gap v/2 - f(S), and v never grows, so a full summary satisfies
+    # f(S) >= v_last / 2; f after each acceptance is f of that prefix (Eq.
+    # exemplar_based_clustering), the summary keeps stream order and size <= k.
+    rng = np.random.default_rng(seed)
+    x = rng.standard_normal((60, 4)).astype(np.float32)
+    order = rng.permutation(60)
+    sel, f, v, seen = O.three_sieves(x, k, eps, T, order=order)
+    assert len(sel) <= k and len(set(sel)) == len(sel)
+    pos = {int(e): i for i, e in enumerate(order)}
+    assert all(pos[a] < pos[b] for a, b in zip(sel, sel[1:]))
+    assert all(a >= b for a, b in zip(v, v[1:]))
+    for i in range(len(sel)):
+        assert f[i] == pytest.approx(O.f_value(x, sel[:i + 1]), rel=1e-12)
+    if len(sel) == k:
+        assert f[-1] >= v[-1] / 2 - 1e-12
+    mx = max(O.f_value(x, [c]) for c in range(60))
+    g = O.sieve_thresholds(mx, k, eps)
+    assert set(v) <= set(g)
