@@ -177,6 +177,36 @@ EBC_API ebc_status ebc_marginal_gains(ebc_dataset* ds, const double* m, const in
 EBC_API ebc_status ebc_greedy(ebc_dataset* ds, int32_t k, int32_t* sel_out, double* f_out, double* gain_out,
                       void* stream);
 
+/* Three Sieves, a streaming optimiser for f under |S| <= k (the optimiser
+ * the paper cites in Sec. 2 and runs beside greedy in its Sec. 6 case
+ * study). Points arrive in `order`; one summary S; the threshold v walks
+ * down the guesses (1+eps)^i in [m, k m], m = max_e f({e}), largest first,
+ * after T consecutive rejections (at the smallest guess it stays); a point
+ * joins while |S| < k and Delta(e|S) >= (v/2 - f(S)) / (k - |S|); the
+ * stream ends early once |S| = k. Gains of stretches of `batch` points run
+ * on the matrix cores in the dataset dtype; every point not clearly below
+ * its bound is re-scored in float64 (direct differences) and decided on
+ * that value, so the decisions are float64 ones in every dtype.
+ * Blocking: the host decides between launches and the call returns when
+ * the stream is done (work is ordered on `stream`).
+ *   k            1 <= k <= n.
+ *   eps          > 0, ratio of consecutive guesses minus 1.
+ *   T            >= 1.
+ *   m_max        m in f units; <= 0: computed (float64 best singleton).
+ *   order        [device] int32 [n_order] indices into V (repeats allowed), or
+ *                NULL for 0 .. n_order-1 (then n_order <= n).
+ *   batch        points scored per gains launch; 0 = 1024; capped at n_pad.
+ *   sel_out      [device] int32 [k]: accepted points in arrival order.
+ *   f_out        [device] float64 [k]: f(S) after each acceptance.
+ *   count_out    [host] number of accepted points.
+ *   examined_out [host] or NULL: points examined before the stream ended.
+ * Errors: EBC_E_INVALID_ARG (arguments), EBC_E_INDEX (an order entry outside
+ * [0, n), detected on the host before any work), EBC_E_DEVICE. The dataset
+ * state afterwards holds the summary (usable by ebc_marginal_gains). */
+EBC_API ebc_status ebc_three_sieves(ebc_dataset* ds, int32_t k, double eps, int64_t T, double m_max,
+                                    const int32_t* order, int64_t n_order, int32_t batch, int32_t* sel_out,
+                                    double* f_out, int32_t* count_out, int64_t* examined_out, void* stream);
+
 /* Graph mode for ebc_greedy (default off): the reset and all k steps are
  * recorded once into a HIP graph (on a private stream; recording runs
  * nothing) and the graph is replayed on `stream` by every later call with

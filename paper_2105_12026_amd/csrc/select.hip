@@ -584,6 +584,64 @@ k_gains_out(int64_t n, int64_t n_cand, int64_t stride, int32_t v_splits, const d
     out[p] = g / double(n);
 }
 
+// ---- one candidate at a time (streaming optimisers): float64 gain, acceptance ----
+__global__ void k_one_stage(InstDesc c, int32_t item) {
+    if (threadIdx.x == 0) {
+        c.b.wfinal[0].g = 0.0;
+        c.b.wfinal[0].idx = item;
+        c.b.wfinal[0].pad = 0;
+        c.b.state->window_count = 1;
+    }
+}
+
+// float64 gain sum of the staged candidate: the re-score's block sums, in block order
+__global__ void __launch_bounds__(kBlock) k_one_sum(InstDesc c) {
+    __shared__ double red[kBlock];
+    double s = 0.0;
+    for (int blk = threadIdx.x; blk < c.nb; blk += kBlock) s += c.b.rpart[int64_t(blk) * kWindowMax];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) c.b.state->gstar = red[0];
+}
+
+__global__ void k_one_accept(InstDesc c, int32_t item, int32_t t) {
+    if (threadIdx.x == 0) {
+        c.b.state->cstar = item;
+        c.b.selected[item] = 1;
+        c.sel[t] = item;
+        if (c.gain) c.gain[t] = c.b.state->gstar / double(c.n);
+    }
+}
+
+hipError_t launch_gain64_one(const ebc_dataset* ds, int32_t item, hipStream_t s) {
+    InstDesc c;
+    fill_desc(ds, 0, nullptr, nullptr, nullptr, &c);
+    hipLaunchKernelGGL(k_one_stage, dim3(1), dim3(64), 0, s, c, item);
+    if (wide_rows(c.k_pad))
+        hipLaunchKernelGGL(k_rescore_long, dim3(c.nb, 1), dim3(kBlock), 0, s, c);
+    else
+        hipLaunchKernelGGL(k_rescore, dim3(c.nb), dim3(kBlock), 0, s, c);
+    hipLaunchKernelGGL(k_one_sum, dim3(1), dim3(kBlock), 0, s, c);
+    return hipGetLastError();
+}
+
+hipError_t launch_accept_one(const ebc_dataset* ds, int32_t item, int32_t t, int32_t* sel, double* f, double* gain,
+                             hipStream_t s) {
+    InstDesc c;
+    fill_desc(ds, t + 1, sel, f, gain, &c);
+    hipLaunchKernelGGL(k_one_accept, dim3(1), dim3(64), 0, s, c, item, t);
+    if (wide_rows(c.k_pad))
+        hipLaunchKernelGGL(k_update_long, dim3(c.nb), dim3(kBlock), 0, s, c);
+    else
+        hipLaunchKernelGGL(k_update, dim3(c.nb), dim3(kBlock), 0, s, c);
+    hipLaunchKernelGGL(k_fsum, dim3(1), dim3(kBlock), 0, s, c, t);
+    return hipGetLastError();
+}
+
 hipError_t launch_gains_out(const ebc_dataset* ds, int64_t n_cand, double* out, hipStream_t s) {
     const unsigned nb = unsigned((n_cand + kBlock - 1) / kBlock);
     hipLaunchKernelGGL(k_gains_out, dim3(nb), dim3(kBlock), 0, s, ds->n, n_cand, ds->n_pad, ds->v_splits,
