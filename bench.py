@@ -37,6 +37,7 @@ WORKLOADS = {
     "paper_sets_n50000_l5000_k10_d100": ("paper_sets", {"seed": 6}),
     "paper_sets_sweep_d100": ("paper_sets", {"seed": 6}),
     "curves_n1000_d3524_k50": ("case_study_curves", {"seed": 8}),
+    "sieves_curves_n1000_d3524_k50": ("case_study_curves", {"seed": 8}),
 }
 
 
@@ -289,6 +290,53 @@ def bench_sets(args):
     print(json.dumps(res), flush=True)
 
 
+def bench_sieves(args):
+    """Three Sieves (ebc_three_sieves) over the case-study shape: 1000 process
+    curves of length 3524 streamed in index order into a summary of k = 50
+    (grid ratio eps = 0.1, T = 5 rejections per threshold step; the paper's
+    case study, Sec. 6, runs Three Sieves on N = 1000, d = 3524 series). One
+    step = one call from S = {} (inputs resident). Metric: (examined point,
+    ground point) pairs per second, i.e. points examined * n per call."""
+    import numpy as np
+    import torch
+
+    from paper_2105_12026_amd import ebc, workloads
+
+    p = workloads.case_study_curves(seed=8)
+    n, d, k = p.n, p.d, p.k
+    eps, T = 0.1, 5
+    dev = torch.device("cuda:0")
+    ds = ebc.Dataset(torch.from_numpy(p.x).to(dev), dtype=args.dtype)
+    for _ in range(args.warmup):
+        ds.three_sieves(k, eps, T)
+    torch.cuda.synchronize()
+    times, seen, acc = [], 0, 0
+    for _ in range(args.steps):
+        t0 = time.perf_counter()
+        sel, f, seen = ds.three_sieves(k, eps, T)
+        torch.cuda.synchronize()
+        times.append((time.perf_counter() - t0) * 1e3)
+        acc = int(sel.numel())
+    ds.sync()
+    ms = float(np.median(times))
+    pairs = float(seen) * n
+    achieved = 2.0 * d * pairs / (ms * 1e-3) / 1e12
+    res = {
+        "metric": "examined-point x point distance evals/s (three sieves, one summary)",
+        "value": pairs / (ms * 1e-3), "unit": "pair-evals/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": args.dtype, "data": "synthetic",
+        "config": {"workload": args.workload, "n": n, "d": d, "k": k, "eps": eps, "T": T,
+                   "accepted": acc, "examined": seen, "f_last": float(f[-1]) if acc else 0.0,
+                   "ms_min": float(np.min(times)), "ms_max": float(np.max(times)),
+                   "step": "one ebc_three_sieves call, stream in index order"},
+        "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_TFLOPS[args.dtype],
+                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_TFLOPS[args.dtype], 4), "traffic": None,
+                     "kernel": "whole call (host decisions included), algorithmic 2*d flops per examined pair"},
+    }
+    print(json.dumps(res), flush=True)
+
+
 def bench_sets_sweep(args):
     """The paper's runtime sweep (Sec. 5.1) on ebc_eval_sets: from the defaults
     |V| = 50000, l = 5000, k = 10 (d = 100, N(0,1) data, random sets), vary
@@ -375,6 +423,9 @@ def main():
         return
     if args.workload.startswith("serving"):
         bench_serving(args)
+        return
+    if args.workload.startswith("sieves"):
+        bench_sieves(args)
         return
     if args.workload == "paper_sets_sweep_d100":
         bench_sets_sweep(args)

@@ -7,9 +7,10 @@
 // The stream is consumed in stretches. One marginal-gains launch scores the
 // next `batch` points against the current S (the same matrix-core kernels as
 // greedy, with a candidate list). The host then walks the stretch in order,
-// applying the rule. A point whose gain is not clearly below its bound (by
-// twice the dtype's re-score half-width, relative to m) is re-scored in
-// float64 by direct differences, and the decision uses that value. At an acceptance the summary
+// applying the rule. A point whose gain is within twice the dtype's
+// re-score half-width (relative to m) of its bound is re-scored in float64
+// by direct differences, and the decision uses that value; points clearly
+// above or below need no re-score. At an acceptance the summary
 // grows (m_v update and f(S) in float64) and the next stretch starts right
 // after the accepted point, because every later gain changed. Rejections do
 // not change S, so the gains of a stretch stay valid until its first
@@ -111,17 +112,21 @@ ebc_status ebc_three_sieves(ebc_dataset* ds, int32_t k, double eps, int64_t T, d
     if (grid.empty()) return done(EBC_OK);
     // Every gain is at most m (submodularity: Delta(e|S) <= f({e}) <= m), and
     // the dtype's gains are within window_tau * (largest gain) of float64, so
-    // a point whose gain is below its bound by more than 2 window_tau m is
-    // rejected without a float64 re-score: every decision is the float64 one.
+    // a point whose gain is more than 2 window_tau m away from its bound is
+    // decided without a float64 re-score: every decision is the float64 one.
     const double tol = 2.0 * window_tau(ds->dt) * m_max;
 
     std::vector<double> h_gain(static_cast<size_t>(batch));
     size_t j = 0;
-    int64_t t = 0, pos = 0, examined = 0;
+    int64_t t = 0, pos = 0, examined = 0, last = 0;
     int32_t nsel = 0;
     double fS = 0.0;
+    // stretch length: twice the last gap between acceptances (at least 64),
+    // doubled after every stretch without one, at most `batch`; only the
+    // amount of discarded work depends on it, never a decision
+    int64_t stretch = std::min<int64_t>(batch, 256);
     while (pos < n_order && nsel < k) {
-        const int64_t cnt = std::min<int64_t>(batch, n_order - pos);
+        const int64_t cnt = std::min<int64_t>(stretch, n_order - pos);
         if (launch_gains(ds, d_order + pos, cnt, s) != hipSuccess || launch_gains_out(ds, cnt, d_gain, s) != hipSuccess ||
             hipMemcpyAsync(h_gain.data(), d_gain, size_t(cnt) * sizeof(double), hipMemcpyDeviceToHost, s) !=
                 hipSuccess ||
@@ -134,8 +139,8 @@ ebc_status ebc_three_sieves(ebc_dataset* ds, int32_t k, double eps, int64_t T, d
             const double v = grid[j];
             const double bound = (0.5 * v - fS) / double(k - nsel);
             const double g = h_gain[size_t(i)];
-            bool take = false;
-            if (g >= bound - tol) {
+            bool take = g >= bound + tol;  // clearly above: the float64 gain is too
+            if (!take && g >= bound - tol) {
                 double g64 = 0.0;
                 if (gain64(ds, item, s, &g64) != hipSuccess) return done(EBC_E_DEVICE);
                 take = g64 >= bound;
@@ -148,6 +153,8 @@ ebc_status ebc_three_sieves(ebc_dataset* ds, int32_t k, double eps, int64_t T, d
                 ++nsel;
                 t = 0;
                 next = pos + i + 1;  // later gains are stale: rescore from the next point
+                stretch = std::min<int64_t>(batch, std::max<int64_t>(64, 2 * (next - last)));
+                last = next;
                 break;
             }
             if (++t >= T && j + 1 < grid.size()) {
@@ -155,6 +162,7 @@ ebc_status ebc_three_sieves(ebc_dataset* ds, int32_t k, double eps, int64_t T, d
                 t = 0;
             }
         }
+        if (next == pos + cnt) stretch = std::min<int64_t>(batch, 2 * stretch);
         pos = next;
     }
     *count_out = nsel;
