@@ -318,62 +318,52 @@ __device__ void update_body(const InstDesc& c, int64_t blk) {
 }
 
 // ---- long rows (padded length above 128): re-score and update ----
-// The block's 256 ground-point rows pass through LDS in chunks of 64
-// dimensions: each thread loads 64 values of the next chunk into registers
-// (a wave reads 64 consecutive values of one row) while the current chunk is
-// used, then stores them transposed, and each thread reads its own row from
-// LDS. The re-score window is split over blockIdx.y in groups of 8
-// candidates, so small ground sets still spread over the chip. Every
-// per-thread float64 sum runs in dimension order, as for short rows.
-constexpr int kLongChunk = 64;
+// One thread per ground point, as for short rows, reading its own row in
+// 16-byte pieces when the rows are 16-byte aligned (the other lanes' pieces of the
+// same cache lines follow in the next iterations); the candidates' values
+// are staged in LDS 512 dimensions at a time. The re-score window is split
+// over blockIdx.y in groups of 8 candidates, so small ground sets still
+// spread over the chip. Every per-thread float64 sum runs in dimension
+// order, as for short rows.
+constexpr int kLongChunk = 512;
 
-struct LongStage {
-    float v[kLongChunk];  // values (point tid/64 + 4i, dimension tid%64) of the chunk
-    float c[2];           // candidate values (re-score: candidate tid/64 + 4i, dimension tid%64)
-};
-
-// Load chunk [k0, k0 + 64) of points [v0, v0 + 256) and of up to 8
-// candidates (cand[q] < 0: none) into registers; values past d or n read 0.
-__device__ __forceinline__ void long_load(const float* __restrict__ x, int64_t n, int d, int64_t v0, int k0,
-                                          const int64_t (&cand)[2], LongStage& st) {
-    const int k = threadIdx.x % kLongChunk, p0 = threadIdx.x / kLongChunk;
-    const bool kin = k0 + k < d;
-#pragma unroll
-    for (int i = 0; i < kLongChunk; ++i) {
-        const int64_t v = v0 + p0 + 4 * i;
-        st.v[i] = (kin && v < n) ? x[v * d + k0 + k] : 0.0f;
-    }
-#pragma unroll
-    for (int i = 0; i < 2; ++i) st.c[i] = (kin && cand[i] >= 0) ? x[cand[i] * d + k0 + k] : 0.0f;
-}
-
-__device__ __forceinline__ void long_store(const LongStage& st, float (&xt)[kLongChunk][kBlock + 1],
-                                           float (&cx)[kRescoreGroup][kLongChunk]) {
-    const int k = threadIdx.x % kLongChunk, p0 = threadIdx.x / kLongChunk;
-#pragma unroll
-    for (int i = 0; i < kLongChunk; ++i) xt[k][p0 + 4 * i] = st.v[i];
-#pragma unroll
-    for (int i = 0; i < 2; ++i) cx[p0 + 4 * i][k] = st.c[i];
-}
-
-// Squared distances of this thread's point to the first NJ staged candidates
-// over the whole row, chunk by chunk (cand: the candidates this thread loads).
 template <int NJ>
-__device__ __forceinline__ void long_sums(const InstDesc& c, int64_t v0, const int64_t (&cand)[2], bool live,
-                                          float (&xt)[kLongChunk][kBlock + 1],
-                                          float (&cx)[kRescoreGroup][kLongChunk], double (&acc)[NJ]) {
+__device__ __forceinline__ void long_sums(const InstDesc& c, int64_t v, bool live, const int64_t (&cand)[kRescoreGroup],
+                                          int nc, float (&cx)[kRescoreGroup][kLongChunk], double (&acc)[NJ]) {
+    const float* __restrict__ x = c.x;
     const int d = c.d;
-    LongStage st;
-    long_load(c.x, c.n, d, v0, 0, cand, st);
+    const float* __restrict__ xv = x + (live ? v : 0) * d;
+    const bool vec = (d & 3) == 0 && (reinterpret_cast<uintptr_t>(x) & 15) == 0;
+#pragma unroll
+    for (int q = 0; q < NJ; ++q) acc[q] = 0.0;
     for (int k0 = 0; k0 < d; k0 += kLongChunk) {
         const int kn = (d - k0) < kLongChunk ? (d - k0) : kLongChunk;
-        __syncthreads();  // the previous chunk is no longer read
-        long_store(st, xt, cx);
+        __syncthreads();  // the previous piece of cx is no longer read
+        for (int e = threadIdx.x; e < nc * kLongChunk; e += kBlock) {
+            const int q = e / kLongChunk, k = e % kLongChunk;
+            cx[q][k] = k < kn ? x[cand[q] * d + k0 + k] : 0.0f;
+        }
         __syncthreads();
-        if (k0 + kLongChunk < d) long_load(c.x, c.n, d, v0, k0 + kLongChunk, cand, st);  // in flight meanwhile
-        if (live) {
+        if (!live) continue;
+        if (vec) {
+            const float4* __restrict__ x4 = reinterpret_cast<const float4*>(xv + k0);
+#pragma unroll 4
+            for (int k4 = 0; k4 < kn / 4; ++k4) {
+                const float4 a = x4[k4];
+                const float av[4] = {a.x, a.y, a.z, a.w};
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const double xk = double(av[i]);
+#pragma unroll
+                    for (int q = 0; q < NJ; ++q) {
+                        const double t = xk - double(cx[q][4 * k4 + i]);
+                        acc[q] = fma(t, t, acc[q]);
+                    }
+                }
+            }
+        } else {
             for (int k = 0; k < kn; ++k) {
-                const double xk = double(xt[k][threadIdx.x]);
+                const double xk = double(xv[k0 + k]);
 #pragma unroll
                 for (int q = 0; q < NJ; ++q) {
                     const double t = xk - double(cx[q][k]);
@@ -385,7 +375,6 @@ __device__ __forceinline__ void long_sums(const InstDesc& c, int64_t v0, const i
 }
 
 __device__ void rescore_long_body(const InstDesc& c, int64_t blk, int g) {
-    __shared__ float xt[kLongChunk][kBlock + 1];
     __shared__ float cx[kRescoreGroup][kLongChunk];
     __shared__ double red[kRescoreGroup][kBlock];
     const Buffers& b = c.b;
@@ -393,29 +382,25 @@ __device__ void rescore_long_body(const InstDesc& c, int64_t blk, int g) {
     const int g0 = g * kRescoreGroup;
     if (g0 >= W) return;  // the same for the whole block
     const int gn = (W - g0) < kRescoreGroup ? (W - g0) : kRescoreGroup;
-    const int64_t v0 = blk * kBlock;
-    const int64_t v = v0 + threadIdx.x;
+    const int64_t v = blk * kBlock + threadIdx.x;
     const bool live = v < c.n;
     const double mv = live ? b.m64[v] : 0.0;
-    int64_t cand[2];
+    int64_t cand[kRescoreGroup];
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
-        const int q = threadIdx.x / kLongChunk + 4 * i;
-        cand[i] = q < gn ? int64_t(b.wfinal[g0 + q].idx) : -1;
-    }
-    double acc[kRescoreGroup];
+    for (int q = 0; q < kRescoreGroup; ++q) cand[q] = q < gn ? int64_t(b.wfinal[g0 + q].idx) : 0;
+    double dist[kRescoreGroup];
 #pragma unroll
-    for (int q = 0; q < kRescoreGroup; ++q) acc[q] = 0.0;
+    for (int q = 0; q < kRescoreGroup; ++q) dist[q] = 0.0;
     if (gn <= 2) {
-        double a2[2] = {0.0, 0.0};
-        long_sums<2>(c, v0, cand, live, xt, cx, a2);
-        acc[0] = a2[0];
-        acc[1] = a2[1];
+        double d2[2];
+        long_sums<2>(c, v, live, cand, gn, cx, d2);
+        dist[0] = d2[0];
+        dist[1] = d2[1];
     } else {
-        long_sums<kRescoreGroup>(c, v0, cand, live, xt, cx, acc);
+        long_sums<kRescoreGroup>(c, v, live, cand, gn, cx, dist);
     }
 #pragma unroll
-    for (int q = 0; q < kRescoreGroup; ++q) red[q][threadIdx.x] = (live && q < gn) ? fmax(0.0, mv - acc[q]) : 0.0;
+    for (int q = 0; q < kRescoreGroup; ++q) red[q][threadIdx.x] = (live && q < gn) ? fmax(0.0, mv - dist[q]) : 0.0;
     __syncthreads();
     for (int w = kBlock / 2; w > 0; w >>= 1) {
         if (threadIdx.x < w) {
@@ -428,23 +413,23 @@ __device__ void rescore_long_body(const InstDesc& c, int64_t blk, int g) {
 }
 
 __device__ void update_long_body(const InstDesc& c, int64_t blk) {
-    __shared__ float xt[kLongChunk][kBlock + 1];
     __shared__ float cx[kRescoreGroup][kLongChunk];
     __shared__ double red[kBlock];
     const Buffers& b = c.b;
     const int cs = b.state->cstar;
-    const int64_t v0 = blk * kBlock;
-    const int64_t v = v0 + threadIdx.x;
-    double acc[1] = {0.0};
+    const int64_t v = blk * kBlock + threadIdx.x;
+    double dist[1] = {0.0};
     if (cs >= 0) {
-        const int64_t cand[2] = {threadIdx.x < kLongChunk ? int64_t(cs) : -1, -1};
-        long_sums<1>(c, v0, cand, v < c.n, xt, cx, acc);
+        int64_t cand[kRescoreGroup];
+#pragma unroll
+        for (int q = 0; q < kRescoreGroup; ++q) cand[q] = cs;
+        long_sums<1>(c, v, v < c.n, cand, 1, cx, dist);
     }
     double mv = 0.0;
     if (v < c.n) {
         mv = b.m64[v];
-        if (cs >= 0 && acc[0] < mv) {
-            mv = acc[0];
+        if (cs >= 0 && dist[0] < mv) {
+            mv = dist[0];
             b.m64[v] = mv;
             set_point_terms(b, v, mv);
         }
