@@ -53,6 +53,7 @@ __all__ = [
     "min_dist_to_set",
     "sieve_thresholds",
     "three_sieves",
+    "sieve_streaming",
 ]
 
 
@@ -226,3 +227,47 @@ def three_sieves(x: np.ndarray, k: int, eps: float, T: int, m=None, order=None, 
                 j += 1
                 t = 0
     return sel, fs, vs, seen
+
+
+def sieve_streaming(x: np.ndarray, k: int, eps: float, m=None, order=None, e0=None):
+    """Sieve Streaming (the paper names it, Sec. 2 and Sec. 4.1, as an
+    optimiser that scores many sets per step): one summary S_v per guess v of
+    sieve_thresholds. Every arriving point is offered to every summary,
+    and joins S_v when |S_v| < k and Delta(e | S_v) >= (v/2 - f(S_v)) /
+    (k - |S_v|). The stream ends early once every summary is full. Returns
+    (indices of the best summary, f after each of its acceptances, its v,
+    number of points examined); the best summary is the first, in grid
+    order (largest v first), with the largest f."""
+    x = np.asarray(x, dtype=np.float64)
+    n = x.shape[0]
+    order = range(n) if order is None else [int(i) for i in order]
+    m0 = min_dist_to_set(x, [], e0)
+    l0 = float(np.sum(m0) / n)
+    if m is None:
+        m = max(marginal_gain(x, m0, c) for c in range(n))
+    grid = sieve_thresholds(m, k, eps)
+    if not grid or k <= 0:
+        return [], [], 0.0, 0
+    mv = [m0.copy() for _ in grid]
+    sel = [[] for _ in grid]
+    fs = [[] for _ in grid]
+    fS = [0.0] * len(grid)
+    seen = 0
+    for e in order:
+        if all(len(s) == k for s in sel):
+            break
+        seen += 1
+        for j, v in enumerate(grid):
+            if len(sel[j]) == k:
+                continue
+            g = marginal_gain(x, mv[j], e)
+            if g >= (v / 2.0 - fS[j]) / (k - len(sel[j])):
+                sel[j].append(e)
+                mv[j] = np.minimum(mv[j], sqdist(x, x[e]))
+                fS[j] = l0 - float(np.sum(mv[j]) / n)
+                fs[j].append(fS[j])
+    best = 0
+    for j in range(len(grid)):
+        if fS[j] > fS[best]:
+            best = j
+    return sel[best], fs[best], grid[best], seen

@@ -436,3 +436,36 @@ def test_three_sieves_invariants(seed, k, eps, T):
     mx = max(O.f_value(x, [c]) for c in range(60))
     g = O.sieve_thresholds(mx, k, eps)
     assert set(v) <= set(g)
+
+
+# --------------------------------------------------------------------------
+# Sieve Streaming (Sec. 2 and Sec. 4.1 name it as an optimiser that scores
+# many sets per step)
+# --------------------------------------------------------------------------
+def test_sieve_streaming_hand_case():
+    # V = {0, 4, 6, 10}, k = 2, eps = 1/4: guesses 55.51, 44.41, 35.53 (see the
+    # Three Sieves case). Stream 0, 4, 10, 6: in every summary x=0 (gain 0)
+    # falls short of v/4 > 8.8, x=4 joins (gain 28 >= v/4), then the bound
+    # (v/2 - 28)/1 is negative and x=10 joins (gain 9, f = 37); all summaries
+    # are full after 3 points, equal, and the first (largest v) is returned.
+    x = _x([[0.0], [4.0], [6.0], [10.0]])
+    sel, f, v, seen = O.sieve_streaming(x, 2, 0.25, order=[0, 1, 3, 2])
+    assert sel == [1, 3] and seen == 3 and v == 1.25 ** 18
+    np.testing.assert_allclose(f, [28.0, 37.0], rtol=1e-15)
+
+
+@pytest.mark.parametrize("seed,n,k,eps", [(61, 10, 2, 0.1), (62, 11, 3, 0.2), (63, 9, 3, 0.5), (64, 12, 2, 0.05)])
+def test_sieve_streaming_half_approximation(seed, n, k, eps):
+    # Sieve Streaming's published guarantee for a stream holding all of V:
+    # with m = max_e f({e}) <= OPT <= k m (monotone, submodular) the grid holds
+    # a guess within a factor 1+eps below OPT, whose summary reaches half of
+    # it, so f(best) >= (1/2 - eps) OPT; checked against exhaustive search.
+    rng = np.random.default_rng(seed)
+    x = rng.standard_normal((n, 3)).astype(np.float32)
+    order = rng.permutation(n)
+    best, _ = O.exhaustive(x, k)
+    sel, f, v, seen = O.sieve_streaming(x, k, eps, order=order)
+    assert len(sel) <= k and f
+    assert f[-1] >= (0.5 - eps) * best - 1e-12
+    for i in range(len(sel)):
+        assert f[i] == pytest.approx(O.f_value(x, sel[:i + 1]), rel=1e-12)
