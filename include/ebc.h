@@ -207,6 +207,25 @@ EBC_API ebc_status ebc_three_sieves(ebc_dataset* ds, int32_t k, double eps, int6
                                     const int32_t* order, int64_t n_order, int32_t batch, int32_t* sel_out,
                                     double* f_out, int32_t* count_out, int64_t* examined_out, void* stream);
 
+/* Sieve Streaming, the other optimiser the paper names (Sec. 2; Sec. 4.1:
+ * optimisers such as greedy or Sieve Streaming score many sets per step):
+ * one summary per guess v of the same grid as ebc_three_sieves, every
+ * arriving point offered to each summary under the same rule, the stream
+ * ending early once every summary is full; the best summary (largest f,
+ * the largest v among equal f) is returned. Each summary keeps its own
+ * float64 running minima on the device; decisions are float64 ones as in
+ * ebc_three_sieves. Blocking, like ebc_three_sieves; arguments as there,
+ * and:
+ *   sel_out, f_out  [device] the best summary's points and f after each of
+ *                   its acceptances;
+ *   v_out           [host] or NULL: the best summary's guess v.
+ * Device scratch: (8 n_pad + 8 batch + 12 k) bytes per guess, plus the
+ * stream, allocated stream-ordered for the call. The dataset state
+ * afterwards holds the best summary's minima. */
+EBC_API ebc_status ebc_sieve_streaming(ebc_dataset* ds, int32_t k, double eps, double m_max, const int32_t* order,
+                                       int64_t n_order, int32_t batch, int32_t* sel_out, double* f_out,
+                                       int32_t* count_out, double* v_out, int64_t* examined_out, void* stream);
+
 /* Graph mode for ebc_greedy (default off): the reset and all k steps are
  * recorded once into a HIP graph (on a private stream; recording runs
  * nothing) and the graph is replayed on `stream` by every later call with

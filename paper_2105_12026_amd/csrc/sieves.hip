@@ -15,6 +15,14 @@
 // after the accepted point, because every later gain changed. Rejections do
 // not change S, so the gains of a stretch stay valid until its first
 // acceptance.
+//
+// Sieve Streaming (named with greedy in Sec. 2 and Sec. 4.1 as an optimiser
+// that scores many sets per step) keeps one summary per guess v and offers
+// every point to each of them under the same rule. Each summary has its own
+// running minima m^v (float64, on the device); scoring or growing summary v
+// loads m^v into the dataset state first. Each summary has its own stretch
+// of gains, re-scored only after that summary changes. The best summary
+// (first in grid order among equal f) is returned.
 #include <math.h>
 #include <string.h>
 
@@ -53,6 +61,46 @@ hipError_t gain64(const ebc_dataset* ds, int32_t item, hipStream_t s, double* g)
     return e;
 }
 
+// The stream's indices on the host (validated) and on the device, in
+// `scratch` (device, stream-ordered) followed by `extra` bytes.
+ebc_status prepare_stream(const ebc_dataset* ds, const int32_t* order, int64_t n_order, size_t extra, hipStream_t s,
+                          std::vector<int32_t>& h_order, char** scratch, int32_t** d_order, char** d_extra) {
+    h_order.assign(static_cast<size_t>(n_order), 0);
+    if (order && n_order > 0) {
+        if (hipMemcpyAsync(h_order.data(), order, size_t(n_order) * sizeof(int32_t), hipMemcpyDeviceToHost, s) !=
+                hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            return EBC_E_DEVICE;
+        for (int32_t v : h_order)
+            if (v < 0 || int64_t(v) >= ds->n) return EBC_E_INDEX;
+    } else {
+        for (int64_t i = 0; i < n_order; ++i) h_order[size_t(i)] = int32_t(i);
+    }
+    const size_t ord_bytes = (size_t(n_order) * sizeof(int32_t) + 255) & ~size_t(255);
+    if (hipMallocAsync(reinterpret_cast<void**>(scratch), ord_bytes + extra, s) != hipSuccess) return EBC_E_DEVICE;
+    *d_order = reinterpret_cast<int32_t*>(*scratch);
+    *d_extra = *scratch + ord_bytes;
+    if (n_order > 0 && hipMemcpyAsync(*d_order, h_order.data(), size_t(n_order) * sizeof(int32_t),
+                                      hipMemcpyHostToDevice, s) != hipSuccess)
+        return EBC_E_DEVICE;
+    return EBC_OK;
+}
+
+// S = {} in the dataset state; m = max_e f({e}) unless given (> 0): one
+// greedy step (the float64 re-scored best singleton), then S = {} again.
+ebc_status start_stream(ebc_dataset* ds, double* m_max, int32_t* sel_tmp, double* f_tmp, hipStream_t s,
+                        DevState* st) {
+    if (launch_reset_state(ds, s) != hipSuccess) return EBC_E_DEVICE;
+    if (!(*m_max > 0.0)) {
+        if (launch_greedy_step(ds, 0, sel_tmp, f_tmp, nullptr, s, nullptr) != hipSuccess ||
+            read_state(ds, st, s) != hipSuccess)
+            return EBC_E_DEVICE;
+        *m_max = st->gstar / double(ds->n);
+        if (launch_reset_state(ds, s) != hipSuccess) return EBC_E_DEVICE;
+    }
+    return read_state(ds, st, s) == hipSuccess ? EBC_OK : EBC_E_DEVICE;
+}
+
 }  // namespace
 
 extern "C" {
@@ -65,48 +113,23 @@ ebc_status ebc_three_sieves(ebc_dataset* ds, int32_t k, double eps, int64_t T, d
     *count_out = 0;
     if (examined_out) *examined_out = 0;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    const int64_t n = ds->n;
     if (batch == 0) batch = 1024;
     if (batch > ds->n_pad) batch = int32_t(ds->n_pad);
 
-    // the stream's indices, on the host (validated) and on the device
-    std::vector<int32_t> h_order(static_cast<size_t>(n_order));
-    if (order && n_order > 0) {
-        if (hipMemcpyAsync(h_order.data(), order, size_t(n_order) * sizeof(int32_t), hipMemcpyDeviceToHost, s) !=
-                hipSuccess ||
-            hipStreamSynchronize(s) != hipSuccess)
-            return EBC_E_DEVICE;
-        for (int32_t v : h_order)
-            if (v < 0 || int64_t(v) >= n) return EBC_E_INDEX;
-    } else {
-        for (int64_t i = 0; i < n_order; ++i) h_order[size_t(i)] = int32_t(i);
-    }
+    std::vector<int32_t> h_order;
     char* scratch = nullptr;
-    const size_t ord_bytes = (size_t(n_order) * sizeof(int32_t) + 255) & ~size_t(255);
-    if (hipMallocAsync(reinterpret_cast<void**>(&scratch), ord_bytes + size_t(batch) * sizeof(double), s) != hipSuccess)
-        return EBC_E_DEVICE;
-    int32_t* d_order = reinterpret_cast<int32_t*>(scratch);
-    double* d_gain = reinterpret_cast<double*>(scratch + ord_bytes);
+    int32_t* d_order = nullptr;
+    char* d_extra = nullptr;
+    ebc_status pst = prepare_stream(ds, order, n_order, size_t(batch) * sizeof(double), s, h_order, &scratch, &d_order,
+                                    &d_extra);
     auto done = [&](ebc_status st) {
-        (void)hipFreeAsync(scratch, s);
+        if (scratch) (void)hipFreeAsync(scratch, s);
         return st;
     };
-    if (n_order > 0 && hipMemcpyAsync(d_order, h_order.data(), size_t(n_order) * sizeof(int32_t),
-                                      hipMemcpyHostToDevice, s) != hipSuccess)
-        return done(EBC_E_DEVICE);
-
-    // S = {}; m = max_e f({e}) unless given: one greedy step (float64 re-scored
-    // best singleton), then S = {} again
-    if (launch_reset_state(ds, s) != hipSuccess) return done(EBC_E_DEVICE);
+    if (pst != EBC_OK) return done(pst);
+    double* d_gain = reinterpret_cast<double*>(d_extra);
     DevState st;
-    if (!(m_max > 0.0)) {
-        if (launch_greedy_step(ds, 0, sel_out, f_out, nullptr, s, nullptr) != hipSuccess ||
-            read_state(ds, &st, s) != hipSuccess)
-            return done(EBC_E_DEVICE);
-        m_max = st.gstar / double(n);
-        if (launch_reset_state(ds, s) != hipSuccess) return done(EBC_E_DEVICE);
-    }
-    if (read_state(ds, &st, s) != hipSuccess) return done(EBC_E_DEVICE);
+    if ((pst = start_stream(ds, &m_max, sel_out, f_out, s, &st)) != EBC_OK) return done(pst);
     if (st.error != 0) return done(EBC_OK);  // reported by ebc_sync_status
     const std::vector<double> grid = sieve_grid(m_max, k, eps);
     if (grid.empty()) return done(EBC_OK);
@@ -168,6 +191,120 @@ ebc_status ebc_three_sieves(ebc_dataset* ds, int32_t k, double eps, int64_t T, d
     *count_out = nsel;
     if (examined_out) *examined_out = examined;
     ds->stats.steps = nsel;
+    return done(EBC_OK);
+}
+
+ebc_status ebc_sieve_streaming(ebc_dataset* ds, int32_t k, double eps, double m_max, const int32_t* order,
+                               int64_t n_order, int32_t batch, int32_t* sel_out, double* f_out, int32_t* count_out,
+                               double* v_out, int64_t* examined_out, void* stream) {
+    if (!ds || !count_out || k < 1 || int64_t(k) > ds->n || !(eps > 0.0) || batch < 0) return EBC_E_INVALID_ARG;
+    if (!sel_out || !f_out || n_order < 0 || (!order && n_order > ds->n)) return EBC_E_INVALID_ARG;
+    *count_out = 0;
+    if (v_out) *v_out = 0.0;
+    if (examined_out) *examined_out = 0;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    if (batch == 0) batch = 1024;
+    if (batch > ds->n_pad) batch = int32_t(ds->n_pad);
+
+    // the grid needs m before the per-summary buffers can be sized
+    DevState st;
+    ebc_status pst = start_stream(ds, &m_max, sel_out, f_out, s, &st);
+    if (pst != EBC_OK) return pst;
+    if (st.error != 0) return EBC_OK;  // reported by ebc_sync_status
+    const std::vector<double> grid = sieve_grid(m_max, k, eps);
+    const int64_t J = int64_t(grid.size());
+    if (J == 0) return EBC_OK;
+
+    // per summary: m^v [n_pad] f64, gains of its stretch [batch] f64, f [k] f64, members [k] i32
+    auto al = [](size_t v) { return (v + 255) & ~size_t(255); };
+    const size_t m_bytes = al(size_t(ds->n_pad) * sizeof(double)), g_bytes = al(size_t(batch) * sizeof(double));
+    const size_t f_bytes = al(size_t(k) * sizeof(double)), s_bytes = al(size_t(k) * sizeof(int32_t));
+    const size_t per = m_bytes + g_bytes + f_bytes + s_bytes;
+    std::vector<int32_t> h_order;
+    char* scratch = nullptr;
+    int32_t* d_order = nullptr;
+    char* d_extra = nullptr;
+    pst = prepare_stream(ds, order, n_order, size_t(J) * per, s, h_order, &scratch, &d_order, &d_extra);
+    auto done = [&](ebc_status r) {
+        if (scratch) (void)hipFreeAsync(scratch, s);
+        return r;
+    };
+    if (pst != EBC_OK) return done(pst);
+    auto m_of = [&](int64_t j) { return reinterpret_cast<double*>(d_extra + j * per); };
+    auto g_of = [&](int64_t j) { return reinterpret_cast<double*>(d_extra + j * per + m_bytes); };
+    auto f_of = [&](int64_t j) { return reinterpret_cast<double*>(d_extra + j * per + m_bytes + g_bytes); };
+    auto s_of = [&](int64_t j) { return reinterpret_cast<int32_t*>(d_extra + j * per + m_bytes + g_bytes + f_bytes); };
+    const size_t n_bytes = size_t(ds->n) * sizeof(double);
+    for (int64_t j = 0; j < J; ++j)  // every summary starts at S = {}: m^v = the current minima
+        if (hipMemcpyAsync(m_of(j), ds->b.m64, n_bytes, hipMemcpyDeviceToDevice, s) != hipSuccess)
+            return done(EBC_E_DEVICE);
+
+    const double tol = 2.0 * window_tau(ds->dt) * m_max;  // as in ebc_three_sieves
+    std::vector<std::vector<double>> h_gain(size_t(J), std::vector<double>(static_cast<size_t>(batch)));
+    std::vector<int64_t> base(size_t(J), 0), len(size_t(J), 0), stretch(size_t(J), std::min<int64_t>(batch, 256));
+    std::vector<int64_t> last(size_t(J), 0);
+    std::vector<int32_t> cnt(size_t(J), 0);
+    std::vector<double> fS(size_t(J), 0.0);
+    int64_t loaded = -1, full = 0, examined = 0;
+    auto load = [&](int64_t j) -> hipError_t {  // summary j's minima into the dataset state
+        if (loaded == j) return hipSuccess;
+        loaded = j;
+        return launch_load_m(ds, m_of(j), s);
+    };
+    for (int64_t i = 0; i < n_order && full < J; ++i) {
+        ++examined;
+        const int32_t item = h_order[size_t(i)];
+        for (int64_t j = 0; j < J; ++j) {
+            if (cnt[size_t(j)] == k) continue;
+            if (!(i >= base[size_t(j)] && i < base[size_t(j)] + len[size_t(j)])) {
+                // gains of summary j for the next stretch of the stream
+                if (len[size_t(j)] > 0 && i == base[size_t(j)] + len[size_t(j)])
+                    stretch[size_t(j)] = std::min<int64_t>(batch, 2 * stretch[size_t(j)]);
+                const int64_t L = std::min<int64_t>(stretch[size_t(j)], n_order - i);
+                if (load(j) != hipSuccess || launch_gains(ds, d_order + i, L, s) != hipSuccess ||
+                    launch_gains_out(ds, L, g_of(j), s) != hipSuccess ||
+                    hipMemcpyAsync(h_gain[size_t(j)].data(), g_of(j), size_t(L) * sizeof(double),
+                                   hipMemcpyDeviceToHost, s) != hipSuccess ||
+                    hipStreamSynchronize(s) != hipSuccess)
+                    return done(EBC_E_DEVICE);
+                base[size_t(j)] = i;
+                len[size_t(j)] = L;
+            }
+            const double bound = (0.5 * grid[size_t(j)] - fS[size_t(j)]) / double(k - cnt[size_t(j)]);
+            const double g = h_gain[size_t(j)][size_t(i - base[size_t(j)])];
+            bool take = g >= bound + tol;
+            if (!take && g >= bound - tol) {
+                double g64 = 0.0;
+                if (load(j) != hipSuccess || gain64(ds, item, s, &g64) != hipSuccess) return done(EBC_E_DEVICE);
+                take = g64 >= bound;
+            }
+            if (!take) continue;
+            const int32_t t = cnt[size_t(j)];
+            if (load(j) != hipSuccess || launch_accept_one(ds, item, t, s_of(j), f_of(j), nullptr, s) != hipSuccess ||
+                hipMemcpyAsync(m_of(j), ds->b.m64, n_bytes, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+                hipMemcpyAsync(&fS[size_t(j)], f_of(j) + t, sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
+                hipStreamSynchronize(s) != hipSuccess)
+                return done(EBC_E_DEVICE);
+            if (++cnt[size_t(j)] == k) ++full;
+            len[size_t(j)] = 0;  // its later gains are stale
+            stretch[size_t(j)] = std::min<int64_t>(batch, std::max<int64_t>(64, 2 * (i + 1 - last[size_t(j)])));
+            last[size_t(j)] = i + 1;
+        }
+    }
+    int64_t best = 0;
+    for (int64_t j = 1; j < J; ++j)
+        if (fS[size_t(j)] > fS[size_t(best)]) best = j;
+    const int32_t nb = cnt[size_t(best)];
+    if ((nb > 0 && (hipMemcpyAsync(sel_out, s_of(best), size_t(nb) * sizeof(int32_t), hipMemcpyDeviceToDevice, s) !=
+                        hipSuccess ||
+                    hipMemcpyAsync(f_out, f_of(best), size_t(nb) * sizeof(double), hipMemcpyDeviceToDevice, s) !=
+                        hipSuccess)) ||
+        load(best) != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
+        return done(EBC_E_DEVICE);
+    *count_out = nb;
+    if (v_out) *v_out = grid[size_t(best)];
+    if (examined_out) *examined_out = examined;
+    ds->stats.steps = nb;
     return done(EBC_OK);
 }
 

@@ -23,7 +23,8 @@ DTYPES = {"f32": 0, "f16": 1, "bf16": 2, "fp8": 3}
 MAX_DIM = 4096  # EBC_MAX_DIM of include/ebc.h
 ABI_FUNCTIONS = (
     "ebc_dataset_bytes", "ebc_dataset_create", "ebc_dataset_destroy", "ebc_eval_sets", "ebc_eval_sets_in_dtype",
-    "ebc_marginal_gains", "ebc_greedy", "ebc_three_sieves", "ebc_sync_status", "ebc_status_string",
+    "ebc_marginal_gains", "ebc_greedy", "ebc_three_sieves", "ebc_sieve_streaming", "ebc_sync_status",
+    "ebc_status_string",
     "ebc_dataset_get_info", "ebc_dataset_set_e0", "ebc_profile_enable", "ebc_profile_read", "ebc_set_gains_variant",
     "ebc_gains_variant_count", "ebc_set_greedy_graph", "ebc_batch_bytes", "ebc_batch_create",
     "ebc_batch_destroy", "ebc_batch_set_graph", "ebc_greedy_batched", "ebc_batch_info", "ebc_autotune",
@@ -79,6 +80,9 @@ def lib() -> ctypes.CDLL:
         L.ebc_greedy.argtypes = [P, i32, P, P, P, P]
         L.ebc_three_sieves.argtypes = [P, i32, ctypes.c_double, i64, ctypes.c_double, P, i64, i32, P, P,
                                        ctypes.POINTER(i32), ctypes.POINTER(i64), P]
+        L.ebc_sieve_streaming.argtypes = [P, i32, ctypes.c_double, ctypes.c_double, P, i64, i32, P, P,
+                                          ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double),
+                                          ctypes.POINTER(i64), P]
         L.ebc_sync_status.argtypes = [P, P, ctypes.POINTER(_Stats)]
         L.ebc_status_string.argtypes = [ctypes.c_int]
         L.ebc_status_string.restype = ctypes.c_char_p
@@ -286,6 +290,24 @@ class Dataset:
                                       int(batch), _ptr(sel), _ptr(f), ctypes.byref(cnt), ctypes.byref(seen),
                                       _stream(stream)), "ebc_three_sieves")
         return sel[:cnt.value], f[:cnt.value], int(seen.value)
+
+    def sieve_streaming(self, k: int, eps: float, m_max: float = 0.0, order=None, batch: int = 0, stream=None):
+        """Sieve Streaming over a stream of points (ebc_sieve_streaming). Returns
+        (best summary int32, f after each of its acceptances float64, its guess v,
+        points examined)."""
+        dev = self.x.device
+        if order is not None:
+            order = order.to(device=dev, dtype=torch.int32).contiguous()
+        n_order = self.n if order is None else order.numel()
+        sel = torch.empty(k, dtype=torch.int32, device=dev)
+        f = torch.empty(k, dtype=torch.float64, device=dev)
+        cnt = ctypes.c_int32(0)
+        v = ctypes.c_double(0.0)
+        seen = ctypes.c_int64(0)
+        _check(lib().ebc_sieve_streaming(self._h, int(k), float(eps), float(m_max), _ptr(order), n_order,
+                                         int(batch), _ptr(sel), _ptr(f), ctypes.byref(cnt), ctypes.byref(v),
+                                         ctypes.byref(seen), _stream(stream)), "ebc_sieve_streaming")
+        return sel[:cnt.value], f[:cnt.value], float(v.value), int(seen.value)
 
     def greedy(self, k: int, stream=None, sel=None, f=None, gain=None):
         """Greedy to cardinality k on the device; returns (sel int32 [k], f float64 [k], gain float64 [k])."""

@@ -97,3 +97,37 @@ def test_three_sieves_bad_order_is_rejected(env):
         ds.three_sieves(3, 0.1, 5, order=torch.tensor([1, 2, 50], dtype=torch.int32))
     assert ei.value.code == 2
     ds.sync()
+
+
+SS_CASES = [  # (kind, n, d, k, eps, stream, seed)
+    ("gmm", 800, 32, 6, 0.3, "perm", 11),
+    ("gmm", 500, 100, 4, 0.5, "index", 12),
+    ("curves", 300, 260, 5, 0.5, "repeats", 13),
+]
+
+
+@pytest.mark.parametrize("dt", ["f32", "bf16", "fp8"])
+@pytest.mark.parametrize("kind,n,d,k,eps,stream,seed", SS_CASES)
+def test_sieve_streaming_matches_oracle(env, dt, kind, n, d, k, eps, stream, seed):
+    torch, _ = env
+    rng = np.random.default_rng(seed)
+    if kind == "curves":
+        x = W.process_curves(rng, n, d).astype(np.float32)
+    else:
+        x = W.gaussian_mixture(rng, n, d, 6).astype(np.float32)
+    order = _stream(stream, n, rng)
+    rsel, rf, rv, rseen = O.sieve_streaming(x, k, eps, order=order)
+    print(f"[gpu-case] sieve streaming {dt} {kind} n={n} d={d} k={k} eps={eps} stream={stream}", flush=True)
+    ds = _ds(env, x, dt)
+    to = None if order is None else torch.from_numpy(order)
+    sel, f, v, seen = ds.sieve_streaming(k, eps, order=to, batch=128)
+    ds.sync()
+    assert sel.cpu().numpy().tolist() == rsel
+    np.testing.assert_allclose(f.cpu().numpy(), rf, rtol=1e-12)
+    assert v == pytest.approx(rv, rel=1e-15) and seen == rseen
+    # the dataset state holds the best summary's minima
+    g = ds.marginal_gains(cand=torch.arange(min(n, 64), dtype=torch.int32)).cpu().numpy()
+    ds.sync()
+    m = O.min_dist_to_set(x, rsel)
+    rg = O.gains(x, m, range(min(n, 64)))
+    assert np.max(np.abs(g - rg)) <= {"f32": 1e-5, "bf16": 1e-2, "fp8": 8e-2}[dt] * max(np.max(np.abs(rg)), 1e-300)
