@@ -1,7 +1,7 @@
 """Serving core (continuous batching at greedy-step granularity, admission
 by device footprint): every request's result equals its solo ebc_greedy run
-bitwise, whatever the mix, the arrival pattern, the slot count or the arena
-budget; the arena is never oversubscribed; the float32 requests also match
+bitwise, whatever the mix (short and long rows), the arrival pattern, the slot
+count or the arena budget; the arena is never oversubscribed; the float32 requests also match
 the oracle."""
 import numpy as np
 import pytest
@@ -12,7 +12,8 @@ pytestmark = pytest.mark.gpu
 
 # (n, d, dtype, k)
 REQS = [(3000, 64, "bf16", 7), (700, 64, "f32", 4), (5000, 64, "bf16", 12), (1200, 16, "fp8", 3),
-        (2600, 64, "f16", 9), (4100, 100, "f32", 6), (257, 64, "bf16", 1), (1800, 64, "bf16", 10)]
+        (2600, 64, "f16", 9), (4100, 100, "f32", 6), (257, 64, "bf16", 1), (1800, 64, "bf16", 10),
+        (900, 300, "f32", 5), (600, 520, "bf16", 4)]  # the last two: long rows
 
 
 @pytest.fixture(scope="module")
@@ -84,7 +85,7 @@ def test_staggered_arrivals_equal_solo(env, solos):
     print("[gpu-case] serving: staggered arrivals", flush=True)
     sv = ebc.Server(256 << 20, max_slots=8)
     ids = {}
-    order = [2, 0, 5, 7, 1, 4, 3, 6]
+    order = [2, 0, 8, 5, 7, 1, 9, 4, 3, 6]
     for tick in range(40):
         if tick < len(order):
             i = order[tick]
