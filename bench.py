@@ -288,6 +288,22 @@ def bench_sets(args):
         res["cpu_baseline"] = {"value": float(p.offsets[ns]) * n / dt, "unit": "pair-evals/s",
                                "cores": ref.threads(), "kind": "oracle",
                                "sample": f"float64 f of the first {ns} sets ({dt:.1f} s)"}
+        # The paper's own comparison (Table 1): single- and multi-threaded CPU
+        # runs of Alg. 1 in single precision; speedups of this GPU line over both.
+        paper_cpu = {}
+        for label, threads in (("st", 1), ("mt", ref.threads())):
+            ns = 4
+            while True:
+                t0 = time.perf_counter()
+                ref.eval_sets_f32(p.x, p.offsets[:ns + 1], p.idx[:int(p.offsets[ns])], threads)
+                el = time.perf_counter() - t0
+                if el >= 2.0 or ns >= l:
+                    break
+                ns = min(l, max(ns * 2, int(ns * 3.0 / max(el, 1e-3))))
+            rate = float(p.offsets[ns]) * n / el
+            paper_cpu[label] = {"pair_evals_per_s": rate, "threads": threads, "sets": ns,
+                                "speedup": res["value"] / rate}
+        res["paper_style_cpu"] = paper_cpu
     print(json.dumps(res), flush=True)
 
 

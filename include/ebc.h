@@ -339,7 +339,7 @@ typedef struct {
     int32_t cand_tile;      /* candidates per gains workgroup */
     int32_t window_cap;     /* most candidates re-scored in float64 per step */
     int32_t dtype;
-    double l0;              /* L({e0}); valid after the stream passed create */
+    double l0;              /* L({e0}) as of the last ebc_sync_status (follows ebc_dataset_set_e0) */
 } ebc_dataset_info;
 
 EBC_API ebc_status ebc_dataset_get_info(ebc_dataset* ds, ebc_dataset_info* info);
@@ -347,7 +347,9 @@ EBC_API ebc_status ebc_dataset_get_info(ebc_dataset* ds, ebc_dataset_info* info)
 /* Tile shape of the marginal-gains kernel for this dataset. Every variant
  * computes the same sums in the same order per (candidate, ground chunk), so
  * results do not depend on it; an autotuner picks the fastest per dtype and
- * size. Variants 0..ebc_gains_variant_count(dt)-1; 0 is the default. */
+ * size. Variants 0..ebc_gains_variant_count(dt)-1; 0 is the default. Rows
+ * padded past 128 values have a single long-row kernel, which every
+ * variant selects. */
 EBC_API ebc_status ebc_set_gains_variant(ebc_dataset* ds, int32_t variant);
 EBC_API int32_t ebc_gains_variant_count(ebc_dtype dt);
 

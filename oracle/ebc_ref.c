@@ -113,6 +113,43 @@ void ebc_ref_eval_sets(const float* x, int64_t n, int32_t d, const int64_t* off,
     }
 }
 
+/* Paper-style CPU baseline of the multi-set evaluation (Sec. 5 times
+ * single- and multi-threaded CPU runs of Alg. 1 in single precision): float32
+ * direct differences vectorised over the dimension, a float32 running
+ * minimum per ground point starting at ||v||^2 (e0 = 0), float64 sums over
+ * the points, sets spread over `threads` OpenMP threads. A timed baseline
+ * for speed comparisons only; the float64 functions above are the
+ * reference of record. */
+void ebc_ref_eval_sets_f32(const float* x, int64_t n, int32_t d, const int64_t* off,
+                           const int32_t* idx, int64_t l, double* out, int threads)
+{
+    double l0 = 0.0;
+    for (int64_t v = 0; v < n; ++v) l0 += sqn(x + v * d, d);
+    l0 /= (double)n;
+#pragma omp parallel for schedule(dynamic, 1) num_threads(threads)
+    for (int64_t j = 0; j < l; ++j) {
+        double sum = 0.0;
+        for (int64_t v = 0; v < n; ++v) {
+            const float* xv = x + v * d;
+            float t = 0.0f;
+#pragma omp simd reduction(+ : t)
+            for (int k = 0; k < d; ++k) t += xv[k] * xv[k];
+            for (int64_t q = off[j]; q < off[j + 1]; ++q) {
+                const float* xs = x + (int64_t)idx[q] * d;
+                float dv = 0.0f;
+#pragma omp simd reduction(+ : dv)
+                for (int k = 0; k < d; ++k) {
+                    const float u = xv[k] - xs[k];
+                    dv += u * u;
+                }
+                if (dv < t) t = dv;
+            }
+            sum += (double)t;
+        }
+        out[j] = l0 - sum / (double)n;
+    }
+}
+
 /* Greedy to cardinality k. sel[t], f[t] = f(S_{t+1}), g[t] = gain of step t.
  * Returns 0, -1 if memory runs out, -2 if k > n. */
 int ebc_ref_greedy(const float* x, int64_t n, int32_t d, int32_t k, int32_t* sel, double* f,

@@ -27,6 +27,7 @@ def lib():
         L.ebc_ref_min_dist.argtypes = [P, i64, i32, P, i64, P, P]
         L.ebc_ref_gains.argtypes = [P, i64, i32, P, P, i64, P]
         L.ebc_ref_eval_sets.argtypes = [P, i64, i32, P, P, i64, P, P]
+        L.ebc_ref_eval_sets_f32.argtypes = [P, i64, i32, P, P, i64, P, ctypes.c_int]
         L.ebc_ref_greedy.argtypes = [P, i64, i32, i32, P, P, P, P]
         L.ebc_ref_greedy.restype = ctypes.c_int
         L.ebc_ref_greedy_lazy.argtypes = [P, i64, i32, i32, P, P, P, P, P]
@@ -80,6 +81,16 @@ def eval_sets(x, offsets, idx, e0=None) -> np.ndarray:
     out = np.empty(off.size - 1)
     keep, pe = _e0(x, e0)
     lib().ebc_ref_eval_sets(_p(x), x.shape[0], x.shape[1], _p(off), _p(idx), off.size - 1, _p(out), pe)
+    return out
+
+
+def eval_sets_f32(x, offsets, idx, threads: int) -> np.ndarray:
+    """Paper-style single-precision CPU baseline of eval_sets (timing only)."""
+    x = _f32(x)
+    off = np.ascontiguousarray(offsets, dtype=np.int64)
+    idx = np.ascontiguousarray(idx, dtype=np.int32)
+    out = np.empty(off.size - 1)
+    lib().ebc_ref_eval_sets_f32(_p(x), x.shape[0], x.shape[1], _p(off), _p(idx), off.size - 1, _p(out), int(threads))
     return out
 
 
