@@ -69,6 +69,31 @@ def cpu_baseline(x, n: int, target_s: float = 12.0) -> dict:
                       f"(one greedy step's work for {nc} candidates; {dt:.1f} s)"}
 
 
+def paper_style_cpu(x, n: int, value: float) -> dict:
+    """The paper's comparison (Table 1): single- and multi-threaded CPU runs in
+    single precision; here the gains loop (oracle/ebc_ref.c, ebc_ref_gains_f32)
+    on a bounded prefix of the candidates (about 2 s each), with the speedup
+    of `value` (pair-evals/s) over each."""
+    import numpy as np
+
+    from oracle import ref
+    m = ref.min_dist(x, [])
+    out = {}
+    for label, threads in (("st", 1), ("mt", ref.threads())):
+        nc = 16
+        while True:
+            cand = np.arange(nc, dtype=np.int32)
+            t0 = time.perf_counter()
+            ref.gains_f32(x, m, cand, threads)
+            el = time.perf_counter() - t0
+            if el >= 2.0 or nc >= n:
+                break
+            nc = min(n, max(nc * 2, int(nc * 3.0 / max(el, 1e-3))))
+        rate = nc * n / el
+        out[label] = {"pair_evals_per_s": rate, "threads": threads, "candidates": nc, "speedup": value / rate}
+    return out
+
+
 def counters_traffic(kernel: str, workload: str, dtype: str, variant: int):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 --pmc
     summary (FETCH_SIZE, WRITE_SIZE scaled by a plain-copy calibration), or
@@ -565,6 +590,7 @@ def main():
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p.x, n)
+        out["paper_style_cpu"] = paper_style_cpu(p.x, n, value)
     print(json.dumps(out), flush=True)
 
 

@@ -150,6 +150,32 @@ void ebc_ref_eval_sets_f32(const float* x, int64_t n, int32_t d, const int64_t* 
     }
 }
 
+/* Paper-style CPU baseline of the marginal gains (timing only, like
+ * ebc_ref_eval_sets_f32): float32 direct differences vectorised over the
+ * dimension, float64 sums over the points, candidates over `threads`
+ * OpenMP threads; out[i] = |V|^-1 sum_v max(0, m[v] - d(v, cand[i])). */
+void ebc_ref_gains_f32(const float* x, int64_t n, int32_t d, const double* m, const int32_t* cand,
+                       int64_t nc, double* out, int threads)
+{
+#pragma omp parallel for schedule(dynamic, 4) num_threads(threads)
+    for (int64_t i = 0; i < nc; ++i) {
+        const float* xc = x + (int64_t)cand[i] * d;
+        double acc = 0.0;
+        for (int64_t v = 0; v < n; ++v) {
+            const float* xv = x + v * d;
+            float dv = 0.0f;
+#pragma omp simd reduction(+ : dv)
+            for (int k = 0; k < d; ++k) {
+                const float u = xv[k] - xc[k];
+                dv += u * u;
+            }
+            const double g = m[v] - (double)dv;
+            if (g > 0.0) acc += g;
+        }
+        out[i] = acc / (double)n;
+    }
+}
+
 /* Greedy to cardinality k. sel[t], f[t] = f(S_{t+1}), g[t] = gain of step t.
  * Returns 0, -1 if memory runs out, -2 if k > n. */
 int ebc_ref_greedy(const float* x, int64_t n, int32_t d, int32_t k, int32_t* sel, double* f,

@@ -28,6 +28,7 @@ def lib():
         L.ebc_ref_gains.argtypes = [P, i64, i32, P, P, i64, P]
         L.ebc_ref_eval_sets.argtypes = [P, i64, i32, P, P, i64, P, P]
         L.ebc_ref_eval_sets_f32.argtypes = [P, i64, i32, P, P, i64, P, ctypes.c_int]
+        L.ebc_ref_gains_f32.argtypes = [P, i64, i32, P, P, i64, P, ctypes.c_int]
         L.ebc_ref_greedy.argtypes = [P, i64, i32, i32, P, P, P, P]
         L.ebc_ref_greedy.restype = ctypes.c_int
         L.ebc_ref_greedy_lazy.argtypes = [P, i64, i32, i32, P, P, P, P, P]
@@ -91,6 +92,16 @@ def eval_sets_f32(x, offsets, idx, threads: int) -> np.ndarray:
     idx = np.ascontiguousarray(idx, dtype=np.int32)
     out = np.empty(off.size - 1)
     lib().ebc_ref_eval_sets_f32(_p(x), x.shape[0], x.shape[1], _p(off), _p(idx), off.size - 1, _p(out), int(threads))
+    return out
+
+
+def gains_f32(x, m, cand, threads: int) -> np.ndarray:
+    """Paper-style single-precision CPU baseline of gains (timing only)."""
+    x = _f32(x)
+    m = np.ascontiguousarray(m, dtype=np.float64)
+    cand = np.ascontiguousarray(cand, dtype=np.int32)
+    out = np.empty(cand.size)
+    lib().ebc_ref_gains_f32(_p(x), x.shape[0], x.shape[1], _p(m), _p(cand), cand.size, _p(out), int(threads))
     return out
 
 
