@@ -140,3 +140,20 @@ def test_wide_eval_sets(env, ref, kind, n, d, seed):
             rel = np.abs(f1 - rf) / (np.abs(rf) + 1e-3 * l0)
             print(f"[gpu-result] long-row eval_sets in {dt}: max rel err {rel.max():.3e}", flush=True)
             assert rel.max() <= ES_TOL[dt]
+
+
+@pytest.mark.parametrize("dt", ["f32", "bf16"])
+def test_wide_greedy_graph_mode_equals_eager(env, dt):
+    """Greedy recorded into a HIP graph (two-dimensional re-score grid of the
+    long-row path included) replays to the eager results bitwise."""
+    x = _x("curves", 700, 600, 31)
+    print(f"[gpu-case] long-row greedy graph mode {dt} n=700 d=600", flush=True)
+    ds = _ds(env, x, dt)
+    eager = [t.cpu().numpy() for t in ds.greedy(6)]
+    ds.sync()
+    ds.set_graph(True)
+    for _ in range(2):
+        rep = [t.cpu().numpy() for t in ds.greedy(6)]
+        ds.sync()
+        for a, b in zip(eager, rep):
+            np.testing.assert_array_equal(a, b)
