@@ -387,6 +387,22 @@ def bench_sieves(args):
                      "unit": "TFLOP/s", "frac": round(achieved / PEAK_TFLOPS[args.dtype], 4), "traffic": None,
                      "kernel": "whole call (host decisions included), algorithmic 2*d flops per examined pair"},
     }
+    if not args.no_cpu_baseline:
+        # the float64 oracle (NumPy, as it stands) on a bounded prefix of the stream
+        from oracle import build_ref, ebc_oracle, ref
+        if not os.path.exists(build_ref.LIB):
+            build_ref.build()
+        mx = float(np.max(ref.gains(p.x, ref.min_dist(p.x, []))))  # largest singleton value (C oracle)
+        limit = 8 if stream_all else 120
+        t0 = time.perf_counter()
+        if stream_all:
+            _, _, _, o_seen = ebc_oracle.sieve_streaming(p.x, k, eps, m=mx, order=range(limit))
+        else:
+            _, _, _, o_seen = ebc_oracle.three_sieves(p.x, k, eps, T, m=mx, order=range(limit))
+        el = time.perf_counter() - t0
+        res["cpu_baseline"] = {"value": o_seen * n / el, "unit": "pair-evals/s", "cores": 1, "kind": "oracle",
+                               "sample": f"float64 NumPy oracle on the first {limit} points of the stream "
+                                         f"({o_seen} examined, {el:.1f} s; the largest singleton value given)"}
     print(json.dumps(res), flush=True)
 
 
