@@ -374,6 +374,8 @@ __device__ __forceinline__ void long_sums(const InstDesc& c, int64_t v, bool liv
     }
 }
 
+__host__ __device__ inline int split_window(const InstDesc& c);
+
 __device__ void rescore_long_body(const InstDesc& c, int64_t blk, int g) {
     __shared__ float cx[kRescoreGroup][kLongChunk];
     __shared__ double red[kRescoreGroup][kBlock];
@@ -381,6 +383,7 @@ __device__ void rescore_long_body(const InstDesc& c, int64_t blk, int g) {
     const int W = b.state->window_count;
     const int g0 = g * kRescoreGroup;
     if (g0 >= W) return;  // the same for the whole block
+    if (W <= split_window(c)) return;  // the two-pass re-score takes small windows
     const int gn = (W - g0) < kRescoreGroup ? (W - g0) : kRescoreGroup;
     const int64_t v = blk * kBlock + threadIdx.x;
     const bool live = v < c.n;
@@ -443,6 +446,139 @@ __device__ void update_long_body(const InstDesc& c, int64_t blk) {
     if (threadIdx.x == 0) b.fpart[blk] = red[0];
 }
 
+// Long rows with at least 4 ground-set chunks (small ground sets): the
+// float64 squared distance of every point to one row in two passes, so the
+// update and a single-candidate re-score use 4x more workgroups. Pass 1
+// (blockIdx.y = quarter q of the dimension, 16-byte reads as above) writes
+// each point's partial sum to the per-chunk gains buffer, free at that point
+// of a step, at part[q * n_pad + v]. Pass 2 adds the four in quarter order.
+__host__ __device__ inline bool long_split(const InstDesc& c) { return wide_rows(c.k_pad) && c.v_splits >= 4; }
+__device__ __forceinline__ int long_quarter(int d) { return ((d + 3) / 4 + 3) / 4 * 4; }
+
+__device__ void dist_quarter_body(const InstDesc& c, int64_t blk, int q, int64_t row) {
+    if (row < 0) return;
+    const float* __restrict__ x = c.x;
+    const int d = c.d;
+    const int Q = long_quarter(d);
+    const int k0 = q * Q;
+    const int k1 = (k0 + Q) < d ? (k0 + Q) : d;
+    const int64_t v = blk * kBlock + threadIdx.x;
+    if (v >= c.n) return;
+    const float* __restrict__ xv = x + v * d;
+    const float* __restrict__ xc = x + row * d;
+    double acc = 0.0;
+    if ((d & 3) == 0 && (reinterpret_cast<uintptr_t>(x) & 15) == 0) {
+        const float4* __restrict__ a4 = reinterpret_cast<const float4*>(xv);
+        const float4* __restrict__ c4 = reinterpret_cast<const float4*>(xc);
+#pragma unroll 4
+        for (int k4 = k0 / 4; k4 < k1 / 4; ++k4) {
+            const float4 a = a4[k4], b = c4[k4];
+            const float av[4] = {a.x, a.y, a.z, a.w}, bv[4] = {b.x, b.y, b.z, b.w};
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const double t = double(av[i]) - double(bv[i]);
+                acc = fma(t, t, acc);
+            }
+        }
+    } else {
+        for (int k = k0; k < k1; ++k) {
+            const double t = double(xv[k]) - double(xc[k]);
+            acc = fma(t, t, acc);
+        }
+    }
+    c.b.part[int64_t(q) * c.n_pad + v] = acc;
+}
+
+__device__ __forceinline__ double quarters_sum(const InstDesc& c, int64_t v) {
+    const double* __restrict__ p = c.b.part;
+    return ((p[v] + p[c.n_pad + v]) + p[2 * c.n_pad + v]) + p[3 * c.n_pad + v];
+}
+
+// m_v update from the four quarter sums (pass 2), per-block sums of m_v
+__device__ void update_split_body(const InstDesc& c, int64_t blk) {
+    __shared__ double red[kBlock];
+    const Buffers& b = c.b;
+    const int cs = b.state->cstar;
+    const int64_t v = blk * kBlock + threadIdx.x;
+    double mv = 0.0;
+    if (v < c.n) {
+        mv = b.m64[v];
+        if (cs >= 0) {
+            const double dist = quarters_sum(c, v);
+            if (dist < mv) {
+                mv = dist;
+                b.m64[v] = mv;
+                set_point_terms(b, v, mv);
+            }
+        }
+    }
+    red[threadIdx.x] = mv;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) b.fpart[blk] = red[0];
+}
+
+// float64 gain sum of window entry 0 from the four quarter sums (pass 2)
+__device__ void rescore_one_split_body(const InstDesc& c, int64_t blk) {
+    __shared__ double red[kBlock];
+    const int64_t v = blk * kBlock + threadIdx.x;
+    red[threadIdx.x] = v < c.n ? fmax(0.0, c.b.m64[v] - quarters_sum(c, v)) : 0.0;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) c.b.rpart[blk * kWindowMax] = red[0];
+}
+
+// Small re-score windows of long rows (at most v_splits/4, and 4,
+// candidates): the same two passes per candidate, pass 1 over (quarter,
+// candidate) on blockIdx.y writing part[(4 j + q) * n_pad + v].
+__host__ __device__ inline int split_window(const InstDesc& c) {
+    return long_split(c) ? (c.v_splits / 4 < 4 ? c.v_splits / 4 : 4) : 0;
+}
+
+__device__ void dist_window_body(const InstDesc& c, int64_t blk, int y) {
+    const int W = c.b.state->window_count;
+    if (W > split_window(c)) return;  // the one-pass re-score takes it
+    const int j = y / 4, q = y % 4;
+    if (j >= W) return;
+    // quarter q of candidate j into the slot block 4 j + q
+    InstDesc cj = c;
+    cj.b.part = c.b.part + int64_t(4 * j) * c.n_pad;
+    dist_quarter_body(cj, blk, q, int64_t(c.b.wfinal[j].idx));
+}
+
+__device__ void rescore_split_body(const InstDesc& c, int64_t blk) {
+    __shared__ double red[4][kBlock];
+    const int W = c.b.state->window_count;
+    if (W > split_window(c) || W == 0) return;  // the same for the whole block
+    const int64_t v = blk * kBlock + threadIdx.x;
+    const double mv = v < c.n ? c.b.m64[v] : 0.0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        double val = 0.0;
+        if (j < W && v < c.n) {
+            InstDesc cj = c;
+            cj.b.part = c.b.part + int64_t(4 * j) * c.n_pad;
+            val = fmax(0.0, mv - quarters_sum(cj, v));
+        }
+        red[j][threadIdx.x] = val;
+    }
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) red[j][threadIdx.x] += red[j][threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < W) c.b.rpart[blk * kWindowMax + threadIdx.x] = red[threadIdx.x][0];
+}
+
 // ---- fsum (one block per instance): f(S_t) = L({e0}) - |V|^-1 sum m_v ----
 __device__ void fsum_body(const InstDesc& c, int32_t t) {
     __shared__ double red[kBlock];
@@ -466,6 +602,14 @@ __global__ void __launch_bounds__(kBlock) k_pick(InstDesc c, int32_t t) { pick_b
 __global__ void __launch_bounds__(kBlock) k_update(InstDesc c) { update_body(c, blockIdx.x); }
 __global__ void __launch_bounds__(kBlock) k_rescore_long(InstDesc c) { rescore_long_body(c, blockIdx.x, blockIdx.y); }
 __global__ void __launch_bounds__(kBlock) k_update_long(InstDesc c) { update_long_body(c, blockIdx.x); }
+__global__ void __launch_bounds__(kBlock) k_dist_quarter(InstDesc c, int32_t from_window) {
+    const int64_t row = from_window ? int64_t(c.b.wfinal[0].idx) : int64_t(c.b.state->cstar);
+    dist_quarter_body(c, blockIdx.x, blockIdx.y, row);
+}
+__global__ void __launch_bounds__(kBlock) k_update_split(InstDesc c) { update_split_body(c, blockIdx.x); }
+__global__ void __launch_bounds__(kBlock) k_dist_window(InstDesc c) { dist_window_body(c, blockIdx.x, blockIdx.y); }
+__global__ void __launch_bounds__(kBlock) k_rescore_split(InstDesc c) { rescore_split_body(c, blockIdx.x); }
+__global__ void __launch_bounds__(kBlock) k_rescore_one_split(InstDesc c) { rescore_one_split_body(c, blockIdx.x); }
 __global__ void __launch_bounds__(kBlock) k_fsum(InstDesc c, int32_t t) { fsum_body(c, t); }
 
 // ---- batched kernels: blocks of row_pre[i] .. row_pre[i+1] belong to instance i;
@@ -492,12 +636,28 @@ __device__ __forceinline__ void rescore_long(const InstDesc& c, int64_t blk) {
     if (wide_rows(c.k_pad)) rescore_long_body(c, blk, blockIdx.y);
 }
 __device__ __forceinline__ void update_long(const InstDesc& c, int64_t blk) {
-    if (wide_rows(c.k_pad)) update_long_body(c, blk);
+    if (!wide_rows(c.k_pad)) return;
+    if (long_split(c))
+        update_split_body(c, blk);
+    else
+        update_long_body(c, blk);
+}
+__device__ __forceinline__ void dist_quarter(const InstDesc& c, int64_t blk) {
+    if (long_split(c)) dist_quarter_body(c, blk, blockIdx.y, c.b.state->cstar);
+}
+__device__ __forceinline__ void dist_window(const InstDesc& c, int64_t blk) {
+    if (long_split(c)) dist_window_body(c, blk, blockIdx.y);
+}
+__device__ __forceinline__ void rescore_split(const InstDesc& c, int64_t blk) {
+    if (long_split(c)) rescore_split_body(c, blk);
 }
 EBC_ROW_KERNEL(kb_rescore, rescore_short)
 EBC_ROW_KERNEL(kb_update, update_short)
 EBC_ROW_KERNEL(kb_rescore_long, rescore_long)
 EBC_ROW_KERNEL(kb_update_long, update_long)
+EBC_ROW_KERNEL(kb_dist_quarter, dist_quarter)
+EBC_ROW_KERNEL(kb_dist_window, dist_window)
+EBC_ROW_KERNEL(kb_rescore_split, rescore_split)
 #undef EBC_ROW_KERNEL
 
 __global__ void __launch_bounds__(kSelThreads) kb_wselect(const InstDesc* __restrict__ descs, int32_t t) {
@@ -525,9 +685,18 @@ hipError_t launch_greedy_step(const ebc_dataset* ds, int32_t t, int32_t* sel_out
     hipLaunchKernelGGL(k_wcount, dim3(nb), dim3(kBlock), 0, s, c);
     hipLaunchKernelGGL(k_wselect, dim3(1), dim3(kSelThreads), 0, s, c);
     if (wide_rows(c.k_pad)) {
+        if (long_split(c)) {  // small windows: two passes over quarters of the dimension
+            hipLaunchKernelGGL(k_dist_window, dim3(nb, 16), dim3(kBlock), 0, s, c);
+            hipLaunchKernelGGL(k_rescore_split, dim3(nb), dim3(kBlock), 0, s, c);
+        }
         hipLaunchKernelGGL(k_rescore_long, dim3(nb, kWindowMax / kRescoreGroup), dim3(kBlock), 0, s, c);
         hipLaunchKernelGGL(k_pick, dim3(1), dim3(kBlock), 0, s, c, t);
-        hipLaunchKernelGGL(k_update_long, dim3(nb), dim3(kBlock), 0, s, c);
+        if (long_split(c)) {
+            hipLaunchKernelGGL(k_dist_quarter, dim3(nb, 4), dim3(kBlock), 0, s, c, 0);
+            hipLaunchKernelGGL(k_update_split, dim3(nb), dim3(kBlock), 0, s, c);
+        } else {
+            hipLaunchKernelGGL(k_update_long, dim3(nb), dim3(kBlock), 0, s, c);
+        }
     } else {
         hipLaunchKernelGGL(k_rescore, dim3(nb), dim3(kBlock), 0, s, c);
         hipLaunchKernelGGL(k_pick, dim3(1), dim3(kBlock), 0, s, c, t);
@@ -544,12 +713,20 @@ hipError_t launch_step_batched(const InstDesc* descs, const int64_t* row_pre, in
     hipLaunchKernelGGL(kb_wcount, rows, dim3(kBlock), 0, s, descs, row_pre, count, t);
     hipLaunchKernelGGL(kb_wselect, one, dim3(kSelThreads), 0, s, descs, t);
     hipLaunchKernelGGL(kb_rescore, rows, dim3(kBlock), 0, s, descs, row_pre, count, t);
-    if (long_rows)
+    if (long_rows) {
+        hipLaunchKernelGGL(kb_dist_window, dim3(unsigned(total_rows), 16), dim3(kBlock), 0, s, descs, row_pre, count,
+                           t);
+        hipLaunchKernelGGL(kb_rescore_split, rows, dim3(kBlock), 0, s, descs, row_pre, count, t);
         hipLaunchKernelGGL(kb_rescore_long, dim3(unsigned(total_rows), kWindowMax / kRescoreGroup), dim3(kBlock), 0, s,
                            descs, row_pre, count, t);
+    }
     hipLaunchKernelGGL(kb_pick, one, dim3(kBlock), 0, s, descs, t);
     hipLaunchKernelGGL(kb_update, rows, dim3(kBlock), 0, s, descs, row_pre, count, t);
-    if (long_rows) hipLaunchKernelGGL(kb_update_long, rows, dim3(kBlock), 0, s, descs, row_pre, count, t);
+    if (long_rows) {
+        hipLaunchKernelGGL(kb_dist_quarter, dim3(unsigned(total_rows), 4), dim3(kBlock), 0, s, descs, row_pre, count,
+                           t);
+        hipLaunchKernelGGL(kb_update_long, rows, dim3(kBlock), 0, s, descs, row_pre, count, t);
+    }
     hipLaunchKernelGGL(kb_fsum, one, dim3(kBlock), 0, s, descs, t);
     return hipGetLastError();
 }
@@ -606,7 +783,10 @@ hipError_t launch_gain64_one(const ebc_dataset* ds, int32_t item, hipStream_t s)
     InstDesc c;
     fill_desc(ds, 0, nullptr, nullptr, nullptr, &c);
     hipLaunchKernelGGL(k_one_stage, dim3(1), dim3(64), 0, s, c, item);
-    if (wide_rows(c.k_pad))
+    if (long_split(c)) {
+        hipLaunchKernelGGL(k_dist_quarter, dim3(c.nb, 4), dim3(kBlock), 0, s, c, 1);
+        hipLaunchKernelGGL(k_rescore_one_split, dim3(c.nb), dim3(kBlock), 0, s, c);
+    } else if (wide_rows(c.k_pad))
         hipLaunchKernelGGL(k_rescore_long, dim3(c.nb, 1), dim3(kBlock), 0, s, c);
     else
         hipLaunchKernelGGL(k_rescore, dim3(c.nb), dim3(kBlock), 0, s, c);
@@ -619,7 +799,10 @@ hipError_t launch_accept_one(const ebc_dataset* ds, int32_t item, int32_t t, int
     InstDesc c;
     fill_desc(ds, t + 1, sel, f, gain, &c);
     hipLaunchKernelGGL(k_one_accept, dim3(1), dim3(64), 0, s, c, item, t);
-    if (wide_rows(c.k_pad))
+    if (long_split(c)) {
+        hipLaunchKernelGGL(k_dist_quarter, dim3(c.nb, 4), dim3(kBlock), 0, s, c, 0);
+        hipLaunchKernelGGL(k_update_split, dim3(c.nb), dim3(kBlock), 0, s, c);
+    } else if (wide_rows(c.k_pad))
         hipLaunchKernelGGL(k_update_long, dim3(c.nb), dim3(kBlock), 0, s, c);
     else
         hipLaunchKernelGGL(k_update, dim3(c.nb), dim3(kBlock), 0, s, c);
