@@ -166,13 +166,28 @@ __global__ void __launch_bounds__(kBlock) k_prep(const float* __restrict__ x, in
         const float* xr = x + r * d;
         float* q = b.xq + r * kp;
         double nc = 0.0;  // norm of the stored (centred) copy
-        for (int k = 0; k < d; ++k) {
-            const float v = xr[k];
+        auto one = [&](float v, int k) -> float {
             bad |= !isfinite(v);
             nv += double(v) * double(v);
             const float c = b.mu ? float(double(v) - b.mu[k]) : v;
             nc += double(c) * double(c);
-            q[k] = c;
+            return c;
+        };
+        if ((d & 3) == 0 && (reinterpret_cast<uintptr_t>(x) & 15) == 0) {
+            // 16-byte pieces (same values and summation order as below)
+            const float4* __restrict__ x4 = reinterpret_cast<const float4*>(xr);
+            float4* q4 = reinterpret_cast<float4*>(q);
+            for (int k4 = 0; k4 < d / 4; ++k4) {
+                const float4 v = x4[k4];
+                float4 c;
+                c.x = one(v.x, 4 * k4);
+                c.y = one(v.y, 4 * k4 + 1);
+                c.z = one(v.z, 4 * k4 + 2);
+                c.w = one(v.w, 4 * k4 + 3);
+                q4[k4] = c;
+            }
+        } else {
+            for (int k = 0; k < d; ++k) q[k] = one(xr[k], k);
         }
         for (int k = d; k < kp; ++k) q[k] = 0.0f;
         const float hn = float(0.5 * nc);
