@@ -77,3 +77,9 @@ def test_host_validation_without_device(L):
     assert L.ebc_eval_sets(None, None, None, 1, None, None) == 1
     assert L.ebc_marginal_gains(None, None, None, 1, None, None) == 1
     assert L.ebc_sync_status(None, None, None) == 1
+    assert L.ebc_dataset_set_e0(None, None, None) == 1
+    cnt, seen, v = ctypes.c_int32(7), ctypes.c_int64(7), ctypes.c_double(7.0)
+    assert L.ebc_three_sieves(None, 3, 0.1, 5, 0.0, None, 10, 0, P(256), P(256), ctypes.byref(cnt),
+                              ctypes.byref(seen), None) == 1
+    assert L.ebc_sieve_streaming(None, 3, 0.1, 0.0, None, 10, 0, P(256), P(256), ctypes.byref(cnt),
+                                 ctypes.byref(v), ctypes.byref(seen), None) == 1
