@@ -210,22 +210,36 @@ template <int WIN>
 __device__ __forceinline__ void es_units(const floatx16 (&acc)[2], const int32_t* unit_flags, const int32_t* unit_local,
                                          const float (&wsh)[2], float (&cur)[2], int half, int col,
                                          float (&lacc)[WIN][32]) {
+    // the block's unit bookkeeping (the same for every lane) read up front
+    int fl[kBlockUnits], lo[kBlockUnits];
 #pragma unroll
     for (int uu = 0; uu < kBlockUnits; ++uu) {
-        const int flags = unit_flags[uu];
-        if (!(flags & 4)) continue;
-        const int j4 = 4 * (uu >> 1);
+        fl[uu] = unit_flags[uu];
+        lo[uu] = unit_local[uu];
+    }
+    // each lane's maximum over the 4 rows of each register group: in group g,
+    // half 0 holds unit 2g and half 1 unit 2g+1; the other half's lanes see -inf
+    float mg[2][kBlockUnits];
 #pragma unroll
-        for (int cb = 0; cb < 2; ++cb) {
-            if (flags & 1) cur[cb] = -INFINITY;
-            const float m = fmaxf(fmaxf(acc[cb][j4 + 0], acc[cb][j4 + 1]), fmaxf(acc[cb][j4 + 2], acc[cb][j4 + 3]));
-            if (half == (uu & 1)) cur[cb] = fmaxf(cur[cb], m);
+    for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+        for (int g = 0; g < kBlockUnits / 2; ++g) {
+            const float m = fmaxf(fmaxf(acc[cb][4 * g + 0], acc[cb][4 * g + 1]),
+                                  fmaxf(acc[cb][4 * g + 2], acc[cb][4 * g + 3]));
+            mg[cb][2 * g] = half == 0 ? m : -INFINITY;
+            mg[cb][2 * g + 1] = half == 1 ? m : -INFINITY;
         }
-        if (flags & 2) {
+#pragma unroll
+    for (int uu = 0; uu < kBlockUnits; ++uu) {
+        const int flags = __builtin_amdgcn_readfirstlane(fl[uu]);
+        if (!(flags & 4)) continue;
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb) cur[cb] = fmaxf((flags & 1) ? -INFINITY : cur[cb], mg[cb][uu]);
+        if (__builtin_expect((flags & 2) != 0, 0)) {  // a set's last unit (about one in three)
             float sv = 0.0f;
 #pragma unroll
             for (int cb = 0; cb < 2; ++cb) sv += fmaxf(fmaxf(cur[cb], __shfl_xor(cur[cb], 32, 64)) + wsh[cb], 0.0f);
-            if (half == 0) lacc[unit_local[uu]][col] += sv;
+            if (half == 0) lacc[__builtin_amdgcn_readfirstlane(lo[uu])][col] += sv;
         }
     }
 }
