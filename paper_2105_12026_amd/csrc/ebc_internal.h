@@ -69,7 +69,7 @@ struct Buffers {
     int32_t* bcnt;      // [nb] window entries found in each block
     WindowEntry* wstage;// [n_pad] window entries, block b's at [b*kBlock ..)
     WindowEntry* wfinal;// [kWindowMax] candidates re-scored in float64 this step
-    double* rpart;      // [nb, kWindowMax] float64 re-score partial sums
+    double* rpart;      // [nb, kWindowMax] float64 re-score partial sums ([4 nb, ...] for long rows)
     double* fpart;      // [nb] partial sums of m_v or norms
     DevState* state;
 };

@@ -123,7 +123,7 @@ Layout layout(int64_t n, int32_t d, ebc_dtype dt) {
     L.off_bcnt = take(size_t(nb) * sizeof(int32_t));
     L.off_wstage = take(size_t(np) * sizeof(WindowEntry));
     L.off_wfinal = take(size_t(kWindowMax) * sizeof(WindowEntry));
-    L.off_rpart = take(size_t(nb) * kWindowMax * sizeof(double));
+    L.off_rpart = take(size_t(wide_rows(kp) ? 4 * nb : nb) * kWindowMax * sizeof(double));
     L.off_fpart = take(size_t(nb) * sizeof(double));
     L.off_state = take(sizeof(DevState));
     L.total = o;

@@ -220,6 +220,8 @@ __device__ void rescore_body(const InstDesc& c, int64_t blk) {
     }
 }
 
+__device__ __forceinline__ int rescore_rows(const InstDesc& c, int W);
+
 // ---- pick (one block per instance) ----
 // float64 gain of each window candidate = sum of the per-block sums (thread
 // i takes blocks i, i+256, ..., then a fixed tree); best gain wins, ties to
@@ -230,8 +232,8 @@ __device__ void pick_body(const InstDesc& c, int32_t t) {
     __shared__ double sg[kWindowMax];
     __shared__ int si[kWindowMax];
     const Buffers& b = c.b;
-    const int nbv = c.nb;
     const int W = b.state->window_count;
+    const int nbv = rescore_rows(c, W);
     for (int j = 0; j < kWindowMax; ++j) {
         double s = 0.0;
         if (j < W)
@@ -321,10 +323,8 @@ __device__ void update_body(const InstDesc& c, int64_t blk) {
 // One thread per ground point, as for short rows, reading its own row in
 // 16-byte pieces when the rows are 16-byte aligned (the other lanes' pieces of the
 // same cache lines follow in the next iterations); the candidates' values
-// are staged in LDS 512 dimensions at a time. The re-score window is split
-// over blockIdx.y in groups of 8 candidates, so small ground sets still
-// spread over the chip. Every per-thread float64 sum runs in dimension
-// order, as for short rows.
+// are staged in LDS 512 dimensions at a time. Every per-thread float64 sum
+// runs in dimension order, as for short rows.
 constexpr int kLongChunk = 512;
 
 template <int NJ>
@@ -375,44 +375,108 @@ __device__ __forceinline__ void long_sums(const InstDesc& c, int64_t v, bool liv
 }
 
 __host__ __device__ inline int split_window(const InstDesc& c);
+__device__ __forceinline__ int long_quarter(int d);
 
-__device__ void rescore_long_body(const InstDesc& c, int64_t blk, int g) {
-    __shared__ float cx[kRescoreGroup][kLongChunk];
-    __shared__ double red[kRescoreGroup][kBlock];
+// One-pass re-score of long rows (windows above the two-pass size). A
+// workgroup takes 64 ground points (sub-block s of row block blk) and a group
+// g of up to 8 window candidates, blockIdx.y = 4 g + s. Wave w sums
+// dimension quarter w, the quarters of the two-pass path, so both paths give
+// the same float64 distances; the candidates' values are staged in LDS as
+// float64, 128 dimensions of every quarter at a time. The four partial sums
+// are added in quarter order and the clamped terms of the 64 points summed in
+// a fixed tree into rpart row 4 blk + s.
+constexpr int kLongQChunk = 128;
+
+template <int NJ>
+__device__ __forceinline__ void quarter_chunk(const float* __restrict__ xv, bool vec, int k0, int kn,
+                                              const double (&cq)[kRescoreGroup][kLongQChunk],
+                                              double (&acc)[kRescoreGroup]) {
+    if (vec) {
+        const float4* __restrict__ x4 = reinterpret_cast<const float4*>(xv + k0);
+#pragma unroll 2
+        for (int k4 = 0; k4 < kn / 4; ++k4) {
+            const float4 a = x4[k4];
+            const float av[4] = {a.x, a.y, a.z, a.w};
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const double xk = double(av[i]);
+#pragma unroll
+                for (int q = 0; q < NJ; ++q) {
+                    const double t = xk - cq[q][4 * k4 + i];
+                    acc[q] = fma(t, t, acc[q]);
+                }
+            }
+        }
+    } else {
+        for (int k = 0; k < kn; ++k) {
+            const double xk = double(xv[k0 + k]);
+#pragma unroll
+            for (int q = 0; q < NJ; ++q) {
+                const double t = xk - cq[q][k];
+                acc[q] = fma(t, t, acc[q]);
+            }
+        }
+    }
+}
+
+__device__ void rescore_long_body(const InstDesc& c, int64_t blk, int y) {
+    __shared__ double cq[4][kRescoreGroup][kLongQChunk];
+    __shared__ double red[4][kRescoreGroup][64];
+    __shared__ int64_t scand[kRescoreGroup];
     const Buffers& b = c.b;
     const int W = b.state->window_count;
-    const int g0 = g * kRescoreGroup;
-    if (g0 >= W) return;  // the same for the whole block
+    const int g0 = (y / 4) * kRescoreGroup, sub = y % 4;
+    if (g0 >= W) return;               // the same for the whole block
     if (W <= split_window(c)) return;  // the two-pass re-score takes small windows
     const int gn = (W - g0) < kRescoreGroup ? (W - g0) : kRescoreGroup;
-    const int64_t v = blk * kBlock + threadIdx.x;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t v = blk * kBlock + sub * 64 + lane;
     const bool live = v < c.n;
-    const double mv = live ? b.m64[v] : 0.0;
-    int64_t cand[kRescoreGroup];
+    const float* __restrict__ x = c.x;
+    const int d = c.d;
+    const int Q = long_quarter(d);
+    const int qb = w * Q;
+    const int qe = (qb + Q) < d ? (qb + Q) : d;
+    const float* __restrict__ xv = x + (live ? v : 0) * d;
+    const bool vec = (d & 3) == 0 && (reinterpret_cast<uintptr_t>(x) & 15) == 0;
+    if (threadIdx.x < kRescoreGroup) scand[threadIdx.x] = threadIdx.x < gn ? int64_t(b.wfinal[g0 + threadIdx.x].idx) : 0;
+    double acc[kRescoreGroup];
 #pragma unroll
-    for (int q = 0; q < kRescoreGroup; ++q) cand[q] = q < gn ? int64_t(b.wfinal[g0 + q].idx) : 0;
-    double dist[kRescoreGroup];
-#pragma unroll
-    for (int q = 0; q < kRescoreGroup; ++q) dist[q] = 0.0;
-    if (gn <= 2) {
-        double d2[2];
-        long_sums<2>(c, v, live, cand, gn, cx, d2);
-        dist[0] = d2[0];
-        dist[1] = d2[1];
-    } else {
-        long_sums<kRescoreGroup>(c, v, live, cand, gn, cx, dist);
-    }
-#pragma unroll
-    for (int q = 0; q < kRescoreGroup; ++q) red[q][threadIdx.x] = (live && q < gn) ? fmax(0.0, mv - dist[q]) : 0.0;
-    __syncthreads();
-    for (int w = kBlock / 2; w > 0; w >>= 1) {
-        if (threadIdx.x < w) {
-#pragma unroll
-            for (int q = 0; q < kRescoreGroup; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + w];
+    for (int q = 0; q < kRescoreGroup; ++q) acc[q] = 0.0;
+    for (int t0 = 0; t0 < Q; t0 += kLongQChunk) {
+        __syncthreads();  // scand is written; the previous piece of cq is no longer read
+        for (int e = threadIdx.x; e < 4 * kRescoreGroup * kLongQChunk; e += kBlock) {
+            const int qq = e / (kRescoreGroup * kLongQChunk);
+            const int q = (e / kLongQChunk) % kRescoreGroup, k = e % kLongQChunk;
+            const int kk = qq * Q + t0 + k;
+            const int ke = (qq * Q + Q) < d ? (qq * Q + Q) : d;
+            cq[qq][q][k] = (q < gn && kk < ke) ? double(x[scand[q] * d + kk]) : 0.0;
         }
         __syncthreads();
+        const int rest = qe - (qb + t0);
+        const int kn = rest < kLongQChunk ? rest : kLongQChunk;
+        if (!live || kn <= 0) continue;
+        if (gn <= 2)
+            quarter_chunk<2>(xv, vec, qb + t0, kn, cq[w], acc);
+        else
+            quarter_chunk<kRescoreGroup>(xv, vec, qb + t0, kn, cq[w], acc);
     }
-    if (threadIdx.x < gn) b.rpart[blk * kWindowMax + g0 + threadIdx.x] = red[threadIdx.x][0];
+#pragma unroll
+    for (int q = 0; q < kRescoreGroup; ++q) red[w][q][lane] = acc[q];
+    __syncthreads();
+    const double mv = live ? b.m64[v] : 0.0;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int q = w + 4 * h;
+        double val = 0.0;
+        if (live && q < gn) {
+            const double dist = ((red[0][q][lane] + red[1][q][lane]) + red[2][q][lane]) + red[3][q][lane];
+            val = fmax(0.0, mv - dist);
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) val += __shfl_xor(val, off, 64);
+        if (lane == 0 && q < gn) b.rpart[(4 * blk + sub) * kWindowMax + g0 + q] = val;
+    }
 }
 
 __device__ void update_long_body(const InstDesc& c, int64_t blk) {
@@ -539,6 +603,12 @@ __device__ void rescore_one_split_body(const InstDesc& c, int64_t blk) {
 // candidate) on blockIdx.y writing part[(4 j + q) * n_pad + v].
 __host__ __device__ inline int split_window(const InstDesc& c) {
     return long_split(c) ? (c.v_splits / 4 < 4 ? c.v_splits / 4 : 4) : 0;
+}
+
+// rpart rows a re-score of W candidates fills: one per 64-point sub-block
+// for the one-pass long-row re-score, one per row block otherwise
+__device__ __forceinline__ int rescore_rows(const InstDesc& c, int W) {
+    return (wide_rows(c.k_pad) && W > split_window(c)) ? 4 * c.nb : c.nb;
 }
 
 __device__ void dist_window_body(const InstDesc& c, int64_t blk, int y) {
@@ -689,7 +759,7 @@ hipError_t launch_greedy_step(const ebc_dataset* ds, int32_t t, int32_t* sel_out
             hipLaunchKernelGGL(k_dist_window, dim3(nb, 16), dim3(kBlock), 0, s, c);
             hipLaunchKernelGGL(k_rescore_split, dim3(nb), dim3(kBlock), 0, s, c);
         }
-        hipLaunchKernelGGL(k_rescore_long, dim3(nb, kWindowMax / kRescoreGroup), dim3(kBlock), 0, s, c);
+        hipLaunchKernelGGL(k_rescore_long, dim3(nb, 4 * kWindowMax / kRescoreGroup), dim3(kBlock), 0, s, c);
         hipLaunchKernelGGL(k_pick, dim3(1), dim3(kBlock), 0, s, c, t);
         if (long_split(c)) {
             hipLaunchKernelGGL(k_dist_quarter, dim3(nb, 4), dim3(kBlock), 0, s, c, 0);
@@ -717,7 +787,7 @@ hipError_t launch_step_batched(const InstDesc* descs, const int64_t* row_pre, in
         hipLaunchKernelGGL(kb_dist_window, dim3(unsigned(total_rows), 16), dim3(kBlock), 0, s, descs, row_pre, count,
                            t);
         hipLaunchKernelGGL(kb_rescore_split, rows, dim3(kBlock), 0, s, descs, row_pre, count, t);
-        hipLaunchKernelGGL(kb_rescore_long, dim3(unsigned(total_rows), kWindowMax / kRescoreGroup), dim3(kBlock), 0, s,
+        hipLaunchKernelGGL(kb_rescore_long, dim3(unsigned(total_rows), 4 * kWindowMax / kRescoreGroup), dim3(kBlock), 0, s,
                            descs, row_pre, count, t);
     }
     hipLaunchKernelGGL(kb_pick, one, dim3(kBlock), 0, s, descs, t);
@@ -759,8 +829,9 @@ __global__ void k_one_stage(InstDesc c, int32_t item) {
 // float64 gain sum of the staged candidate: the re-score's block sums, in block order
 __global__ void __launch_bounds__(kBlock) k_one_sum(InstDesc c) {
     __shared__ double red[kBlock];
+    const int rows = rescore_rows(c, 1);
     double s = 0.0;
-    for (int blk = threadIdx.x; blk < c.nb; blk += kBlock) s += c.b.rpart[int64_t(blk) * kWindowMax];
+    for (int blk = threadIdx.x; blk < rows; blk += kBlock) s += c.b.rpart[int64_t(blk) * kWindowMax];
     red[threadIdx.x] = s;
     __syncthreads();
     for (int w = kBlock / 2; w > 0; w >>= 1) {
@@ -787,7 +858,7 @@ hipError_t launch_gain64_one(const ebc_dataset* ds, int32_t item, hipStream_t s)
         hipLaunchKernelGGL(k_dist_quarter, dim3(c.nb, 4), dim3(kBlock), 0, s, c, 1);
         hipLaunchKernelGGL(k_rescore_one_split, dim3(c.nb), dim3(kBlock), 0, s, c);
     } else if (wide_rows(c.k_pad))
-        hipLaunchKernelGGL(k_rescore_long, dim3(c.nb, 1), dim3(kBlock), 0, s, c);
+        hipLaunchKernelGGL(k_rescore_long, dim3(c.nb, 4), dim3(kBlock), 0, s, c);
     else
         hipLaunchKernelGGL(k_rescore, dim3(c.nb), dim3(kBlock), 0, s, c);
     hipLaunchKernelGGL(k_one_sum, dim3(1), dim3(kBlock), 0, s, c);
