@@ -329,6 +329,198 @@ __global__ void __launch_bounds__(kBlock) k_prep_lp(const float* __restrict__ x,
     }
 }
 
+// Long rows: one workgroup of 16 waves per 64-row tile. Lane = row of the
+// tile (the tiled stores of a wave cover whole 1 KB runs), wave = one of 16
+// column slices (multiples of 16 columns); the per-slice float64 sums and
+// maxima are combined through LDS in slice order. Pass 1: norm, finiteness
+// and the largest centred magnitude (FP8 row scale); pass 2: the stored copy
+// (float32 rows or the tiled cast, centred at the column means) and its norm.
+// Per-block norm sums follow in k_norm_blocks. Same values as the one-thread-
+// per-row kernels up to the order of the float64 norm sums.
+constexpr int kPrepSlices = 16;
+
+__device__ __forceinline__ float4 row4(const float* __restrict__ xr, int k, int d, bool vec) {
+    if (vec && k < d) return *reinterpret_cast<const float4*>(xr + k);
+    float4 v;
+    v.x = k < d ? xr[k] : 0.0f;
+    v.y = k + 1 < d ? xr[k + 1] : 0.0f;
+    v.z = k + 2 < d ? xr[k + 2] : 0.0f;
+    v.w = k + 3 < d ? xr[k + 3] : 0.0f;
+    return v;
+}
+
+template <int DT>
+__global__ void __launch_bounds__(1024) k_prep_wide(const float* __restrict__ x, int64_t n, int32_t d, int32_t kp,
+                                                    Buffers b) {
+    __shared__ double pn[kPrepSlices][64];
+    __shared__ float pa[kPrepSlices][64];
+    __shared__ int pf[kPrepSlices][64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t r = int64_t(blockIdx.x) * 64 + lane;
+    const bool live = r < n;
+    const int sw = ((kp + kPrepSlices - 1) / kPrepSlices + 15) / 16 * 16;  // columns per slice
+    const int k0 = w * sw;
+    const int k1 = (k0 + sw) < kp ? (k0 + sw) : kp;
+    const float* __restrict__ xr = x + (live ? r : 0) * d;
+    const double* __restrict__ mu = b.mu;
+    const bool vec = (d & 3) == 0 && (reinterpret_cast<uintptr_t>(x) & 15) == 0;
+    auto cv = [&](float v, int k) -> float { return k < d ? float(double(v) - mu[k]) : 0.0f; };
+
+    // pass 1: float64 norm, finiteness, largest centred magnitude
+    double nv = 0.0;
+    float amax = 0.0f;
+    int bad = 0;
+    if (live) {
+        for (int k = k0; k < k1 && k < d; k += 4) {
+            const float4 v4 = row4(xr, k, d, vec);
+            const float v[4] = {v4.x, v4.y, v4.z, v4.w};
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                if (k + i >= d) break;
+                bad |= !isfinite(v[i]);
+                nv += double(v[i]) * double(v[i]);
+                if (DT == EBC_DT_FP8_E4M3) amax = fmaxf(amax, fabsf(cv(v[i], k + i)));
+            }
+        }
+    }
+    pn[w][lane] = nv;
+    pa[w][lane] = amax;
+    pf[w][lane] = bad;
+    __syncthreads();
+    double nvt = 0.0;
+    float amt = 0.0f;
+    int badt = 0;
+#pragma unroll
+    for (int q = 0; q < kPrepSlices; ++q) {
+        nvt += pn[q][lane];
+        amt = fmaxf(amt, pa[q][lane]);
+        badt |= pf[q][lane];
+    }
+    __syncthreads();  // pn and pf are rewritten below
+
+    // pass 2: the stored copy and its norm
+    int se = 0;  // FP8 scale exponent: ceil(log2(amax / 448))
+    if (DT == EBC_DT_FP8_E4M3 && amt > 0.0f) {
+        int e;
+        const float m = frexpf(amt / 448.0f, &e);
+        se = (m == 0.5f) ? e - 1 : e;
+        se = se < -126 ? -126 : (se > 126 ? 126 : se);
+    }
+    double nq = 0.0;
+    int range = 0;
+    if (DT == EBC_DT_F32) {
+        float4* __restrict__ q4 = reinterpret_cast<float4*>(b.xq + r * kp);
+        for (int k = k0; k < k1; k += 4) {
+            float4 c = {0.0f, 0.0f, 0.0f, 0.0f};
+            if (live) {
+                const float4 v = row4(xr, k, d, vec);
+                c.x = cv(v.x, k);
+                c.y = cv(v.y, k + 1);
+                c.z = cv(v.z, k + 2);
+                c.w = cv(v.w, k + 3);
+                nq += double(c.x) * double(c.x);
+                nq += double(c.y) * double(c.y);
+                nq += double(c.z) * double(c.z);
+                nq += double(c.w) * double(c.w);
+            }
+            q4[k / 4] = c;
+        }
+    } else {
+        constexpr int eb = DT == EBC_DT_FP8_E4M3 ? 1 : 2;
+        constexpr int per_unit = 16 / eb;  // columns per 16-byte unit
+        const int ru = kp * eb / 16;
+        uint8_t* base = reinterpret_cast<uint8_t*>(b.xq);
+        for (int k = k0; k < k1; k += per_unit) {
+            uint32_t wv[4] = {0u, 0u, 0u, 0u};
+            if (live) {
+#pragma unroll
+                for (int j = 0; j < per_unit; j += 4) {
+                    const float4 v4 = row4(xr, k + j, d, vec);
+                    const float v[4] = {v4.x, v4.y, v4.z, v4.w};
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const int kk = k + j + i;
+                        if (kk >= d) continue;
+                        const float c = cv(v[i], kk);
+                        uint32_t code;
+                        double back;
+                        if (DT == EBC_DT_FP8_E4M3) {
+                            const uint8_t e8 = f32_to_e4m3_rne(ldexpf(c, -se));
+                            back = ldexp(double(e4m3_to_f32(e8)), se);
+                            code = e8;
+                        } else if (DT == EBC_DT_BF16) {
+                            const uint16_t h = f32_to_bf16_rne(c);
+                            back = double(bf16_to_f32(h));
+                            code = h;
+                        } else {
+                            range |= fabsf(c) > 65504.0f;
+                            const _Float16 h = _Float16(c);
+                            back = double(float(h));
+                            code = __builtin_bit_cast(uint16_t, h);
+                        }
+                        nq += back * back;
+                        const int bit = (j + i) * eb * 8;  // bit offset of column kk in the unit
+                        wv[bit / 32] |= code << (bit % 32);
+                    }
+                }
+            }
+            *reinterpret_cast<uint4*>(base + tiled_offset(r, k * eb, ru)) = make_uint4(wv[0], wv[1], wv[2], wv[3]);
+        }
+    }
+    pn[w][lane] = nq;
+    pf[w][lane] = range;
+    __syncthreads();
+    if (w != 0) return;
+    double nqt = 0.0;
+    int ranget = 0;
+#pragma unroll
+    for (int q = 0; q < kPrepSlices; ++q) {
+        nqt += pn[q][lane];
+        ranget |= pf[q][lane];
+    }
+    if (live) {
+        if (badt) atomicCAS(&b.state->error, 0, kDevErrNonFinite);
+        if (ranget) atomicCAS(&b.state->error, 0, int(EBC_E_RANGE));
+        if (DT == EBC_DT_FP8_E4M3) b.scale[r] = 127 + se;
+        b.hn[r] = float(0.5 * nqt);
+        b.n64[r] = nvt;
+        b.m0[r] = nvt;
+        b.m64[r] = nvt;
+        b.selected[r] = 0;
+        set_point_terms(b, r, nvt);
+    } else {
+        if (DT == EBC_DT_FP8_E4M3) b.scale[r] = 127;
+        b.n64[r] = 0.0;
+        b.m0[r] = 0.0;
+        b.m64[r] = 0.0;
+        b.hn[r] = 0.0f;
+        b.ha[r] = 0.0f;
+        b.hm[r] = 0.0f;
+        b.selected[r] = 1;  // padding is never a candidate
+    }
+}
+
+// Per-block sum and maximum of the float64 norms (the epilogue of k_prep).
+__global__ void __launch_bounds__(kBlock) k_norm_blocks(Buffers b) {
+    __shared__ double red[kBlock];
+    __shared__ double rmax[kBlock];
+    const double nv = b.n64[int64_t(blockIdx.x) * kBlock + threadIdx.x];
+    red[threadIdx.x] = nv;
+    rmax[threadIdx.x] = nv;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) {
+            red[threadIdx.x] += red[threadIdx.x + w];
+            rmax[threadIdx.x] = fmax(rmax[threadIdx.x], rmax[threadIdx.x + w]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        b.fpart[blockIdx.x] = red[0];
+        b.bmax[blockIdx.x] = rmax[0];
+    }
+}
+
 // One block: L({e0}) = |V|^-1 sum of the per-block norm sums (fixed order),
 // and the largest norm.
 __global__ void __launch_bounds__(kBlock) k_l0(int64_t n, int32_t nblocks, Buffers b) {
@@ -377,7 +569,25 @@ hipError_t launch_prep(const ebc_dataset* ds, hipStream_t s) {
     if (ds->b.mu)
         hipLaunchKernelGGL(k_colmean, dim3(unsigned((ds->k_pad + 63) / 64)), dim3(1024), 0, s, ds->x, ds->n, ds->d,
                            ds->k_pad, ds->b.mu);
-    if (ds->dt == EBC_DT_F32)
+    if (wide_rows(ds->k_pad)) {
+        const dim3 g = dim3(unsigned(ds->n_pad / 64)), blk = dim3(64 * kPrepSlices);
+        switch (ds->dt) {
+            case EBC_DT_F32:
+                hipLaunchKernelGGL(k_prep_wide<EBC_DT_F32>, g, blk, 0, s, ds->x, ds->n, ds->d, ds->k_pad, ds->b);
+                break;
+            case EBC_DT_BF16:
+                hipLaunchKernelGGL(k_prep_wide<EBC_DT_BF16>, g, blk, 0, s, ds->x, ds->n, ds->d, ds->k_pad, ds->b);
+                break;
+            case EBC_DT_F16:
+                hipLaunchKernelGGL(k_prep_wide<EBC_DT_F16>, g, blk, 0, s, ds->x, ds->n, ds->d, ds->k_pad, ds->b);
+                break;
+            default:
+                hipLaunchKernelGGL(k_prep_wide<EBC_DT_FP8_E4M3>, g, blk, 0, s, ds->x, ds->n, ds->d, ds->k_pad,
+                                   ds->b);
+                break;
+        }
+        hipLaunchKernelGGL(k_norm_blocks, dim3(nb), dim3(kBlock), 0, s, ds->b);
+    } else if (ds->dt == EBC_DT_F32)
         hipLaunchKernelGGL(k_prep, dim3(nb), dim3(kBlock), 0, s, ds->x, ds->n, ds->d, ds->k_pad, ds->b);
     else
         hipLaunchKernelGGL(k_prep_lp, dim3(nb), dim3(kBlock), 0, s, ds->x, ds->n, ds->d, ds->k_pad, int(ds->dt),

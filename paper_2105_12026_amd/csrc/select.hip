@@ -223,10 +223,14 @@ __device__ void rescore_body(const InstDesc& c, int64_t blk) {
 __device__ __forceinline__ int rescore_rows(const InstDesc& c, int W);
 
 // ---- pick (one block per instance) ----
-// float64 gain of each window candidate = sum of the per-block sums (thread
-// i takes blocks i, i+256, ..., then a fixed tree); best gain wins, ties to
-// the lowest index. Records the pick. A step with no valid candidate (only
-// possible with non-finite input) records -1 and flags it.
+// float64 gain of each window candidate = sum of the per-block sums: up to
+// kPickColumnRows of them, thread j adds candidate j's in block order;
+// otherwise, candidate by candidate, thread i takes blocks i, i+256, ...,
+// then a fixed tree. Best gain wins, ties to the lowest index. Records the
+// pick. A step with no valid candidate (only possible with non-finite input)
+// records -1 and flags it.
+constexpr int kPickColumnRows = 64;
+
 __device__ void pick_body(const InstDesc& c, int32_t t) {
     __shared__ double red[kBlock];
     __shared__ double sg[kWindowMax];
@@ -234,7 +238,16 @@ __device__ void pick_body(const InstDesc& c, int32_t t) {
     const Buffers& b = c.b;
     const int W = b.state->window_count;
     const int nbv = rescore_rows(c, W);
-    for (int j = 0; j < kWindowMax; ++j) {
+    if (nbv <= kPickColumnRows) {
+        for (int j = threadIdx.x; j < kWindowMax; j += kBlock) {
+            double s = 0.0;
+            if (j < W)
+                for (int blk = 0; blk < nbv; ++blk) s += b.rpart[int64_t(blk) * kWindowMax + j];
+            sg[j] = j < W ? s : -INFINITY;
+            si[j] = j < W ? b.wfinal[j].idx : 0x7fffffff;
+        }
+    }
+    for (int j = 0; j < kWindowMax && nbv > kPickColumnRows; ++j) {
         double s = 0.0;
         if (j < W)
             for (int blk = threadIdx.x; blk < nbv; blk += kBlock) s += b.rpart[int64_t(blk) * kWindowMax + j];
@@ -251,9 +264,11 @@ __device__ void pick_body(const InstDesc& c, int32_t t) {
         __syncthreads();
         if (j + 1 >= W) break;
     }
-    for (int j = W + threadIdx.x; j < kWindowMax; j += kBlock) {
-        sg[j] = -INFINITY;
-        si[j] = 0x7fffffff;
+    if (nbv > kPickColumnRows) {
+        for (int j = W + threadIdx.x; j < kWindowMax; j += kBlock) {
+            sg[j] = -INFINITY;
+            si[j] = 0x7fffffff;
+        }
     }
     __syncthreads();
     const int j = threadIdx.x;
