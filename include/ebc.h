@@ -184,9 +184,11 @@ EBC_API ebc_status ebc_greedy(ebc_dataset* ds, int32_t k, int32_t* sel_out, doub
  * after T consecutive rejections (at the smallest guess it stays); a point
  * joins while |S| < k and Delta(e|S) >= (v/2 - f(S)) / (k - |S|); the
  * stream ends early once |S| = k. Gains of stretches of `batch` points run
- * on the matrix cores in the dataset dtype; every point not clearly below
- * its bound is re-scored in float64 (direct differences) and decided on
- * that value, so the decisions are float64 ones in every dtype.
+ * on the matrix cores in the dataset dtype; a point whose gain lies within
+ * the dtype's error band of its bound is re-scored in float64 (direct
+ * differences; the later points of the stretch that may need it join the
+ * same list, up to 256) and decided on that value, so the decisions are
+ * float64 ones in every dtype.
  * Blocking: the host decides between launches and the call returns when
  * the stream is done (work is ordered on `stream`).
  *   k            1 <= k <= n.

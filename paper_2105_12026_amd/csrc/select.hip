@@ -393,8 +393,10 @@ __host__ __device__ inline int split_window(const InstDesc& c);
 __device__ __forceinline__ int long_quarter(int d);
 
 // One-pass re-score of long rows (windows above the two-pass size). A
-// workgroup takes 64 ground points (sub-block s of row block blk) and a group
-// g of up to 8 window candidates, blockIdx.y = 4 g + s. Wave w sums
+// workgroup takes 64 ground points (sub-block s of row block blk) and group
+// g of the window, blockIdx.y = 4 g + s; the window is cut into at most 32
+// groups of 1, 2, 4 or 8 candidates (the smallest size that fits), so
+// small windows still spread over the chip. Wave w sums
 // dimension quarter w, the quarters of the two-pass path, so both paths give
 // the same float64 distances; the candidates' values are staged in LDS as
 // float64, 128 dimensions of every quarter at a time. The four partial sums
@@ -406,9 +408,10 @@ template <int NJ>
 __device__ __forceinline__ void quarter_chunk(const float* __restrict__ xv, bool vec, int k0, int kn,
                                               const double (&cq)[kRescoreGroup][kLongQChunk],
                                               double (&acc)[kRescoreGroup]) {
+    constexpr int kUnroll = NJ <= 2 ? 8 : 2;  // 16-byte loads in flight per lane
     if (vec) {
         const float4* __restrict__ x4 = reinterpret_cast<const float4*>(xv + k0);
-#pragma unroll 2
+#pragma unroll kUnroll
         for (int k4 = 0; k4 < kn / 4; ++k4) {
             const float4 a = x4[k4];
             const float av[4] = {a.x, a.y, a.z, a.w};
@@ -440,10 +443,11 @@ __device__ void rescore_long_body(const InstDesc& c, int64_t blk, int y) {
     __shared__ int64_t scand[kRescoreGroup];
     const Buffers& b = c.b;
     const int W = b.state->window_count;
-    const int g0 = (y / 4) * kRescoreGroup, sub = y % 4;
+    const int gsz = W <= 32 ? 1 : (W <= 64 ? 2 : (W <= 128 ? 4 : kRescoreGroup));
+    const int g0 = (y / 4) * gsz, sub = y % 4;
     if (g0 >= W) return;               // the same for the whole block
     if (W <= split_window(c)) return;  // the two-pass re-score takes small windows
-    const int gn = (W - g0) < kRescoreGroup ? (W - g0) : kRescoreGroup;
+    const int gn = (W - g0) < gsz ? (W - g0) : gsz;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int64_t v = blk * kBlock + sub * 64 + lane;
     const bool live = v < c.n;
@@ -460,19 +464,23 @@ __device__ void rescore_long_body(const InstDesc& c, int64_t blk, int y) {
     for (int q = 0; q < kRescoreGroup; ++q) acc[q] = 0.0;
     for (int t0 = 0; t0 < Q; t0 += kLongQChunk) {
         __syncthreads();  // scand is written; the previous piece of cq is no longer read
-        for (int e = threadIdx.x; e < 4 * kRescoreGroup * kLongQChunk; e += kBlock) {
-            const int qq = e / (kRescoreGroup * kLongQChunk);
-            const int q = (e / kLongQChunk) % kRescoreGroup, k = e % kLongQChunk;
+        for (int e = threadIdx.x; e < 4 * gn * kLongQChunk; e += kBlock) {
+            const int qq = e / (gn * kLongQChunk);
+            const int q = (e / kLongQChunk) % gn, k = e % kLongQChunk;
             const int kk = qq * Q + t0 + k;
             const int ke = (qq * Q + Q) < d ? (qq * Q + Q) : d;
-            cq[qq][q][k] = (q < gn && kk < ke) ? double(x[scand[q] * d + kk]) : 0.0;
+            cq[qq][q][k] = kk < ke ? double(x[scand[q] * d + kk]) : 0.0;
         }
         __syncthreads();
         const int rest = qe - (qb + t0);
         const int kn = rest < kLongQChunk ? rest : kLongQChunk;
         if (!live || kn <= 0) continue;
-        if (gn <= 2)
+        if (gn == 1)
+            quarter_chunk<1>(xv, vec, qb + t0, kn, cq[w], acc);
+        else if (gn == 2)
             quarter_chunk<2>(xv, vec, qb + t0, kn, cq[w], acc);
+        else if (gn <= 4)
+            quarter_chunk<4>(xv, vec, qb + t0, kn, cq[w], acc);
         else
             quarter_chunk<kRescoreGroup>(xv, vec, qb + t0, kn, cq[w], acc);
     }
@@ -600,19 +608,6 @@ __device__ void update_split_body(const InstDesc& c, int64_t blk) {
     if (threadIdx.x == 0) b.fpart[blk] = red[0];
 }
 
-// float64 gain sum of window entry 0 from the four quarter sums (pass 2)
-__device__ void rescore_one_split_body(const InstDesc& c, int64_t blk) {
-    __shared__ double red[kBlock];
-    const int64_t v = blk * kBlock + threadIdx.x;
-    red[threadIdx.x] = v < c.n ? fmax(0.0, c.b.m64[v] - quarters_sum(c, v)) : 0.0;
-    __syncthreads();
-    for (int w = kBlock / 2; w > 0; w >>= 1) {
-        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) c.b.rpart[blk * kWindowMax] = red[0];
-}
-
 // Small re-score windows of long rows (at most v_splits/4, and 4,
 // candidates): the same two passes per candidate, pass 1 over (quarter,
 // candidate) on blockIdx.y writing part[(4 j + q) * n_pad + v].
@@ -687,14 +682,13 @@ __global__ void __launch_bounds__(kBlock) k_pick(InstDesc c, int32_t t) { pick_b
 __global__ void __launch_bounds__(kBlock) k_update(InstDesc c) { update_body(c, blockIdx.x); }
 __global__ void __launch_bounds__(kBlock) k_rescore_long(InstDesc c) { rescore_long_body(c, blockIdx.x, blockIdx.y); }
 __global__ void __launch_bounds__(kBlock) k_update_long(InstDesc c) { update_long_body(c, blockIdx.x); }
-__global__ void __launch_bounds__(kBlock) k_dist_quarter(InstDesc c, int32_t from_window) {
-    const int64_t row = from_window ? int64_t(c.b.wfinal[0].idx) : int64_t(c.b.state->cstar);
+__global__ void __launch_bounds__(kBlock) k_dist_quarter(InstDesc c) {
+    const int64_t row = int64_t(c.b.state->cstar);
     dist_quarter_body(c, blockIdx.x, blockIdx.y, row);
 }
 __global__ void __launch_bounds__(kBlock) k_update_split(InstDesc c) { update_split_body(c, blockIdx.x); }
 __global__ void __launch_bounds__(kBlock) k_dist_window(InstDesc c) { dist_window_body(c, blockIdx.x, blockIdx.y); }
 __global__ void __launch_bounds__(kBlock) k_rescore_split(InstDesc c) { rescore_split_body(c, blockIdx.x); }
-__global__ void __launch_bounds__(kBlock) k_rescore_one_split(InstDesc c) { rescore_one_split_body(c, blockIdx.x); }
 __global__ void __launch_bounds__(kBlock) k_fsum(InstDesc c, int32_t t) { fsum_body(c, t); }
 
 // ---- batched kernels: blocks of row_pre[i] .. row_pre[i+1] belong to instance i;
@@ -777,7 +771,7 @@ hipError_t launch_greedy_step(const ebc_dataset* ds, int32_t t, int32_t* sel_out
         hipLaunchKernelGGL(k_rescore_long, dim3(nb, 4 * kWindowMax / kRescoreGroup), dim3(kBlock), 0, s, c);
         hipLaunchKernelGGL(k_pick, dim3(1), dim3(kBlock), 0, s, c, t);
         if (long_split(c)) {
-            hipLaunchKernelGGL(k_dist_quarter, dim3(nb, 4), dim3(kBlock), 0, s, c, 0);
+            hipLaunchKernelGGL(k_dist_quarter, dim3(nb, 4), dim3(kBlock), 0, s, c);
             hipLaunchKernelGGL(k_update_split, dim3(nb), dim3(kBlock), 0, s, c);
         } else {
             hipLaunchKernelGGL(k_update_long, dim3(nb), dim3(kBlock), 0, s, c);
@@ -831,29 +825,26 @@ k_gains_out(int64_t n, int64_t n_cand, int64_t stride, int32_t v_splits, const d
     out[p] = g / double(n);
 }
 
-// ---- one candidate at a time (streaming optimisers): float64 gain, acceptance ----
-__global__ void k_one_stage(InstDesc c, int32_t item) {
-    if (threadIdx.x == 0) {
-        c.b.wfinal[0].g = 0.0;
-        c.b.wfinal[0].idx = item;
-        c.b.wfinal[0].pad = 0;
-        c.b.state->window_count = 1;
+// ---- streaming optimisers: float64 gains of a list of points, acceptance ----
+// The list is staged as a re-score window, re-scored by the same kernels as
+// a greedy step's window, and each point's row sums added in row order.
+__global__ void __launch_bounds__(kWindowMax) k_many_stage(InstDesc c, const int32_t* __restrict__ items, int32_t W) {
+    const int j = threadIdx.x;
+    if (j < W) {
+        c.b.wfinal[j].g = 0.0;
+        c.b.wfinal[j].idx = items[j];
+        c.b.wfinal[j].pad = 0;
     }
+    if (j == 0) c.b.state->window_count = W;
 }
 
-// float64 gain sum of the staged candidate: the re-score's block sums, in block order
-__global__ void __launch_bounds__(kBlock) k_one_sum(InstDesc c) {
-    __shared__ double red[kBlock];
-    const int rows = rescore_rows(c, 1);
+__global__ void __launch_bounds__(kWindowMax) k_many_sum(InstDesc c, int32_t W, double* __restrict__ out) {
+    const int j = threadIdx.x;
+    if (j >= W) return;
+    const int rows = rescore_rows(c, W);
     double s = 0.0;
-    for (int blk = threadIdx.x; blk < rows; blk += kBlock) s += c.b.rpart[int64_t(blk) * kWindowMax];
-    red[threadIdx.x] = s;
-    __syncthreads();
-    for (int w = kBlock / 2; w > 0; w >>= 1) {
-        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) c.b.state->gstar = red[0];
+    for (int blk = 0; blk < rows; ++blk) s += c.b.rpart[int64_t(blk) * kWindowMax + j];
+    out[j] = s;
 }
 
 __global__ void k_one_accept(InstDesc c, int32_t item, int32_t t) {
@@ -865,18 +856,20 @@ __global__ void k_one_accept(InstDesc c, int32_t item, int32_t t) {
     }
 }
 
-hipError_t launch_gain64_one(const ebc_dataset* ds, int32_t item, hipStream_t s) {
+hipError_t launch_gain64_many(const ebc_dataset* ds, const int32_t* items, int32_t W, double* out, hipStream_t s) {
     InstDesc c;
     fill_desc(ds, 0, nullptr, nullptr, nullptr, &c);
-    hipLaunchKernelGGL(k_one_stage, dim3(1), dim3(64), 0, s, c, item);
-    if (long_split(c)) {
-        hipLaunchKernelGGL(k_dist_quarter, dim3(c.nb, 4), dim3(kBlock), 0, s, c, 1);
-        hipLaunchKernelGGL(k_rescore_one_split, dim3(c.nb), dim3(kBlock), 0, s, c);
-    } else if (wide_rows(c.k_pad))
-        hipLaunchKernelGGL(k_rescore_long, dim3(c.nb, 4), dim3(kBlock), 0, s, c);
-    else
+    hipLaunchKernelGGL(k_many_stage, dim3(1), dim3(kWindowMax), 0, s, c, items, W);
+    if (wide_rows(c.k_pad)) {
+        if (long_split(c)) {  // small lists: two passes over quarters of the dimension
+            hipLaunchKernelGGL(k_dist_window, dim3(c.nb, 16), dim3(kBlock), 0, s, c);
+            hipLaunchKernelGGL(k_rescore_split, dim3(c.nb), dim3(kBlock), 0, s, c);
+        }
+        hipLaunchKernelGGL(k_rescore_long, dim3(c.nb, 4 * kWindowMax / kRescoreGroup), dim3(kBlock), 0, s, c);
+    } else {
         hipLaunchKernelGGL(k_rescore, dim3(c.nb), dim3(kBlock), 0, s, c);
-    hipLaunchKernelGGL(k_one_sum, dim3(1), dim3(kBlock), 0, s, c);
+    }
+    hipLaunchKernelGGL(k_many_sum, dim3(1), dim3(kWindowMax), 0, s, c, W, out);
     return hipGetLastError();
 }
 
@@ -886,7 +879,7 @@ hipError_t launch_accept_one(const ebc_dataset* ds, int32_t item, int32_t t, int
     fill_desc(ds, t + 1, sel, f, gain, &c);
     hipLaunchKernelGGL(k_one_accept, dim3(1), dim3(64), 0, s, c, item, t);
     if (long_split(c)) {
-        hipLaunchKernelGGL(k_dist_quarter, dim3(c.nb, 4), dim3(kBlock), 0, s, c, 0);
+        hipLaunchKernelGGL(k_dist_quarter, dim3(c.nb, 4), dim3(kBlock), 0, s, c);
         hipLaunchKernelGGL(k_update_split, dim3(c.nb), dim3(kBlock), 0, s, c);
     } else if (wide_rows(c.k_pad))
         hipLaunchKernelGGL(k_update_long, dim3(c.nb), dim3(kBlock), 0, s, c);

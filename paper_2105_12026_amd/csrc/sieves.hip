@@ -10,7 +10,9 @@
 // applying the rule. A point whose gain is within twice the dtype's
 // re-score half-width (relative to m) of its bound is re-scored in float64
 // by direct differences, and the decision uses that value; points clearly
-// above or below need no re-score. At an acceptance the summary
+// above or below need no re-score. The first such point of a stretch takes
+// the later points of the stretch that may need it into the same re-score
+// list (the window re-score of a greedy step). At an acceptance the summary
 // grows (m_v update and f(S) in float64) and the next stretch starts right
 // after the accepted point, because every later gain changed. Rejections do
 // not change S, so the gains of a stretch stay valid until its first
@@ -52,14 +54,61 @@ hipError_t read_state(const ebc_dataset* ds, DevState* st, hipStream_t s) {
     return e;
 }
 
-// float64 gain of one point in f units (stream-synchronous)
-hipError_t gain64(const ebc_dataset* ds, int32_t item, hipStream_t s, double* g) {
-    hipError_t e = launch_gain64_one(ds, item, s);
-    DevState st;
-    if (e == hipSuccess) e = read_state(ds, &st, s);
-    *g = st.gstar / double(ds->n);
+// Device room for a float64 re-score list: indices and gain sums.
+constexpr size_t kListBytes = size_t(kWindowMax) * (sizeof(int32_t) + sizeof(double));
+
+// float64 gains in f units of points items[0..W), 1 <= W <= kWindowMax
+// (stream-synchronous); `list` is kListBytes of device scratch.
+hipError_t gain64_list(const ebc_dataset* ds, const int32_t* items, int32_t W, char* list, double* out,
+                       hipStream_t s) {
+    int32_t* d_items = reinterpret_cast<int32_t*>(list);
+    double* d_out = reinterpret_cast<double*>(list + size_t(kWindowMax) * sizeof(int32_t));
+    hipError_t e = hipMemcpyAsync(d_items, items, size_t(W) * sizeof(int32_t), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = launch_gain64_many(ds, d_items, W, d_out, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(out, d_out, size_t(W) * sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    for (int32_t j = 0; j < W; ++j) out[j] /= double(ds->n);
     return e;
 }
+
+// The float64 gains a stretch needs, computed in lists. When point p of the
+// stretch falls inside its band, p and the later points of the stretch whose
+// gains lie in [lo, hi) (every bound the rule can still reach, widened by the
+// band) are re-scored together; their values hold until the summary changes,
+// which ends the stretch. A list holds at most twice the points examined
+// since the summary last changed (at least 8, at most kWindowMax), so short
+// gaps between acceptances re-score little that goes unused.
+struct Gain64Cache {
+    std::vector<double> g64;
+    std::vector<char> have;
+    std::vector<int32_t> items;
+    std::vector<int64_t> at;
+    std::vector<double> out;
+    explicit Gain64Cache(size_t n) : g64(n), have(n, 0) {}
+    void clear() { std::fill(have.begin(), have.end(), 0); }
+    hipError_t get(const ebc_dataset* ds, const double* gain, const int32_t* stream_items, int64_t p, int64_t len,
+                   double lo, double hi, int64_t since, char* list, hipStream_t s, double* g) {
+        if (!have[size_t(p)]) {
+            const int64_t cap = std::min<int64_t>(kWindowMax, std::max<int64_t>(8, 2 * since));
+            items.clear();
+            at.clear();
+            for (int64_t q = p; q < len && int64_t(at.size()) < cap; ++q)
+                if (!have[size_t(q)] && (q == p || (gain[q] >= lo && gain[q] < hi))) {
+                    items.push_back(stream_items[q]);
+                    at.push_back(q);
+                }
+            out.resize(at.size());
+            const hipError_t e = gain64_list(ds, items.data(), int32_t(at.size()), list, out.data(), s);
+            if (e != hipSuccess) return e;
+            for (size_t j = 0; j < at.size(); ++j) {
+                g64[size_t(at[j])] = out[j];
+                have[size_t(at[j])] = 1;
+            }
+        }
+        *g = g64[size_t(p)];
+        return hipSuccess;
+    }
+};
 
 // The stream's indices on the host (validated) and on the device, in
 // `scratch` (device, stream-ordered) followed by `extra` bytes.
@@ -120,7 +169,8 @@ ebc_status ebc_three_sieves(ebc_dataset* ds, int32_t k, double eps, int64_t T, d
     char* scratch = nullptr;
     int32_t* d_order = nullptr;
     char* d_extra = nullptr;
-    ebc_status pst = prepare_stream(ds, order, n_order, size_t(batch) * sizeof(double), s, h_order, &scratch, &d_order,
+    const size_t gain_bytes = (size_t(batch) * sizeof(double) + 255) & ~size_t(255);
+    ebc_status pst = prepare_stream(ds, order, n_order, gain_bytes + kListBytes, s, h_order, &scratch, &d_order,
                                     &d_extra);
     auto done = [&](ebc_status st) {
         if (scratch) (void)hipFreeAsync(scratch, s);
@@ -128,6 +178,7 @@ ebc_status ebc_three_sieves(ebc_dataset* ds, int32_t k, double eps, int64_t T, d
     };
     if (pst != EBC_OK) return done(pst);
     double* d_gain = reinterpret_cast<double*>(d_extra);
+    char* d_list = d_extra + gain_bytes;
     DevState st;
     if ((pst = start_stream(ds, &m_max, sel_out, f_out, s, &st)) != EBC_OK) return done(pst);
     if (st.error != 0) return done(EBC_OK);  // reported by ebc_sync_status
@@ -140,6 +191,7 @@ ebc_status ebc_three_sieves(ebc_dataset* ds, int32_t k, double eps, int64_t T, d
     const double tol = 2.0 * window_tau(ds->dt) * m_max;
 
     std::vector<double> h_gain(static_cast<size_t>(batch));
+    Gain64Cache c64(static_cast<size_t>(batch));
     size_t j = 0;
     int64_t t = 0, pos = 0, examined = 0, last = 0;
     int32_t nsel = 0;
@@ -155,6 +207,7 @@ ebc_status ebc_three_sieves(ebc_dataset* ds, int32_t k, double eps, int64_t T, d
                 hipSuccess ||
             hipStreamSynchronize(s) != hipSuccess)
             return done(EBC_E_DEVICE);
+        c64.clear();
         int64_t next = pos + cnt;
         for (int64_t i = 0; i < cnt && nsel < k; ++i) {
             ++examined;
@@ -164,8 +217,12 @@ ebc_status ebc_three_sieves(ebc_dataset* ds, int32_t k, double eps, int64_t T, d
             const double g = h_gain[size_t(i)];
             bool take = g >= bound + tol;  // clearly above: the float64 gain is too
             if (!take && g >= bound - tol) {
+                // until the next acceptance the bound can only fall, to that of the last guess
+                const double lowest = (0.5 * grid.back() - fS) / double(k - nsel);
                 double g64 = 0.0;
-                if (gain64(ds, item, s, &g64) != hipSuccess) return done(EBC_E_DEVICE);
+                if (c64.get(ds, h_gain.data(), h_order.data() + pos, i, cnt, lowest - tol, bound + tol,
+                            pos + i + 1 - last, d_list, s, &g64) != hipSuccess)
+                    return done(EBC_E_DEVICE);
                 take = g64 >= bound;
             }
             if (take) {
@@ -224,7 +281,7 @@ ebc_status ebc_sieve_streaming(ebc_dataset* ds, int32_t k, double eps, double m_
     char* scratch = nullptr;
     int32_t* d_order = nullptr;
     char* d_extra = nullptr;
-    pst = prepare_stream(ds, order, n_order, size_t(J) * per, s, h_order, &scratch, &d_order, &d_extra);
+    pst = prepare_stream(ds, order, n_order, size_t(J) * per + kListBytes, s, h_order, &scratch, &d_order, &d_extra);
     auto done = [&](ebc_status r) {
         if (scratch) (void)hipFreeAsync(scratch, s);
         return r;
@@ -234,6 +291,7 @@ ebc_status ebc_sieve_streaming(ebc_dataset* ds, int32_t k, double eps, double m_
     auto g_of = [&](int64_t j) { return reinterpret_cast<double*>(d_extra + j * per + m_bytes); };
     auto f_of = [&](int64_t j) { return reinterpret_cast<double*>(d_extra + j * per + m_bytes + g_bytes); };
     auto s_of = [&](int64_t j) { return reinterpret_cast<int32_t*>(d_extra + j * per + m_bytes + g_bytes + f_bytes); };
+    char* d_list = d_extra + size_t(J) * per;
     const size_t n_bytes = size_t(ds->n) * sizeof(double);
     for (int64_t j = 0; j < J; ++j)  // every summary starts at S = {}: m^v = the current minima
         if (hipMemcpyAsync(m_of(j), ds->b.m64, n_bytes, hipMemcpyDeviceToDevice, s) != hipSuccess)
@@ -241,6 +299,7 @@ ebc_status ebc_sieve_streaming(ebc_dataset* ds, int32_t k, double eps, double m_
 
     const double tol = 2.0 * window_tau(ds->dt) * m_max;  // as in ebc_three_sieves
     std::vector<std::vector<double>> h_gain(size_t(J), std::vector<double>(static_cast<size_t>(batch)));
+    std::vector<Gain64Cache> c64(size_t(J), Gain64Cache(static_cast<size_t>(batch)));
     std::vector<int64_t> base(size_t(J), 0), len(size_t(J), 0), stretch(size_t(J), std::min<int64_t>(batch, 256));
     std::vector<int64_t> last(size_t(J), 0);
     std::vector<int32_t> cnt(size_t(J), 0);
@@ -269,13 +328,20 @@ ebc_status ebc_sieve_streaming(ebc_dataset* ds, int32_t k, double eps, double m_
                     return done(EBC_E_DEVICE);
                 base[size_t(j)] = i;
                 len[size_t(j)] = L;
+                c64[size_t(j)].clear();
             }
             const double bound = (0.5 * grid[size_t(j)] - fS[size_t(j)]) / double(k - cnt[size_t(j)]);
             const double g = h_gain[size_t(j)][size_t(i - base[size_t(j)])];
             bool take = g >= bound + tol;
             if (!take && g >= bound - tol) {
+                // summary j's bound holds until it changes
+                const int64_t b0 = base[size_t(j)];
                 double g64 = 0.0;
-                if (load(j) != hipSuccess || gain64(ds, item, s, &g64) != hipSuccess) return done(EBC_E_DEVICE);
+                if ((!c64[size_t(j)].have[size_t(i - b0)] && load(j) != hipSuccess) ||
+                    c64[size_t(j)].get(ds, h_gain[size_t(j)].data(), h_order.data() + b0, i - b0, len[size_t(j)],
+                                       bound - tol, bound + tol, i + 1 - last[size_t(j)], d_list, s,
+                                       &g64) != hipSuccess)
+                    return done(EBC_E_DEVICE);
                 take = g64 >= bound;
             }
             if (!take) continue;
