@@ -535,18 +535,22 @@ __device__ void update_long_body(const InstDesc& c, int64_t blk) {
 
 // Long rows with at least 4 ground-set chunks (small ground sets): the
 // float64 squared distance of every point to one row in two passes, so the
-// update and a single-candidate re-score use 4x more workgroups. Pass 1
-// (blockIdx.y = quarter q of the dimension, 16-byte reads as above) writes
+// update and small re-score windows use more workgroups. Pass 1
+// (blockIdx.y = slice q of the dimension, 16-byte reads as above) writes
 // each point's partial sum to the per-chunk gains buffer, free at that point
-// of a step, at part[q * n_pad + v]. Pass 2 adds the four in quarter order.
+// of a step, at part[q * n_pad + v]. Pass 2 adds the slices in order. The
+// update takes one slice per chunk (up to 16); re-score windows take
+// quarters, the slices of the one-pass re-score.
 __host__ __device__ inline bool long_split(const InstDesc& c) { return wide_rows(c.k_pad) && c.v_splits >= 4; }
-__device__ __forceinline__ int long_quarter(int d) { return ((d + 3) / 4 + 3) / 4 * 4; }
+__host__ __device__ inline int update_slices(const InstDesc& c) { return c.v_splits < 16 ? c.v_splits : 16; }
+__device__ __forceinline__ int long_slice(int d, int S) { return ((d + S - 1) / S + 3) / 4 * 4; }
+__device__ __forceinline__ int long_quarter(int d) { return long_slice(d, 4); }
 
-__device__ void dist_quarter_body(const InstDesc& c, int64_t blk, int q, int64_t row) {
-    if (row < 0) return;
+__device__ void dist_slice_body(const InstDesc& c, int64_t blk, int q, int S, int64_t row) {
+    if (row < 0 || q >= S) return;
     const float* __restrict__ x = c.x;
     const int d = c.d;
-    const int Q = long_quarter(d);
+    const int Q = long_slice(d, S);
     const int k0 = q * Q;
     const int k1 = (k0 + Q) < d ? (k0 + Q) : d;
     const int64_t v = blk * kBlock + threadIdx.x;
@@ -581,7 +585,14 @@ __device__ __forceinline__ double quarters_sum(const InstDesc& c, int64_t v) {
     return ((p[v] + p[c.n_pad + v]) + p[2 * c.n_pad + v]) + p[3 * c.n_pad + v];
 }
 
-// m_v update from the four quarter sums (pass 2), per-block sums of m_v
+__device__ __forceinline__ double slices_sum(const InstDesc& c, int64_t v, int S) {
+    const double* __restrict__ p = c.b.part;
+    double s = p[v];
+    for (int q = 1; q < S; ++q) s += p[int64_t(q) * c.n_pad + v];
+    return s;
+}
+
+// m_v update from the slice sums (pass 2), per-block sums of m_v
 __device__ void update_split_body(const InstDesc& c, int64_t blk) {
     __shared__ double red[kBlock];
     const Buffers& b = c.b;
@@ -591,7 +602,7 @@ __device__ void update_split_body(const InstDesc& c, int64_t blk) {
     if (v < c.n) {
         mv = b.m64[v];
         if (cs >= 0) {
-            const double dist = quarters_sum(c, v);
+            const double dist = slices_sum(c, v, update_slices(c));
             if (dist < mv) {
                 mv = dist;
                 b.m64[v] = mv;
@@ -629,7 +640,7 @@ __device__ void dist_window_body(const InstDesc& c, int64_t blk, int y) {
     // quarter q of candidate j into the slot block 4 j + q
     InstDesc cj = c;
     cj.b.part = c.b.part + int64_t(4 * j) * c.n_pad;
-    dist_quarter_body(cj, blk, q, int64_t(c.b.wfinal[j].idx));
+    dist_slice_body(cj, blk, q, 4, int64_t(c.b.wfinal[j].idx));
 }
 
 __device__ void rescore_split_body(const InstDesc& c, int64_t blk) {
@@ -682,9 +693,8 @@ __global__ void __launch_bounds__(kBlock) k_pick(InstDesc c, int32_t t) { pick_b
 __global__ void __launch_bounds__(kBlock) k_update(InstDesc c) { update_body(c, blockIdx.x); }
 __global__ void __launch_bounds__(kBlock) k_rescore_long(InstDesc c) { rescore_long_body(c, blockIdx.x, blockIdx.y); }
 __global__ void __launch_bounds__(kBlock) k_update_long(InstDesc c) { update_long_body(c, blockIdx.x); }
-__global__ void __launch_bounds__(kBlock) k_dist_quarter(InstDesc c) {
-    const int64_t row = int64_t(c.b.state->cstar);
-    dist_quarter_body(c, blockIdx.x, blockIdx.y, row);
+__global__ void __launch_bounds__(kBlock) k_dist_slices(InstDesc c) {
+    dist_slice_body(c, blockIdx.x, blockIdx.y, update_slices(c), int64_t(c.b.state->cstar));
 }
 __global__ void __launch_bounds__(kBlock) k_update_split(InstDesc c) { update_split_body(c, blockIdx.x); }
 __global__ void __launch_bounds__(kBlock) k_dist_window(InstDesc c) { dist_window_body(c, blockIdx.x, blockIdx.y); }
@@ -721,8 +731,8 @@ __device__ __forceinline__ void update_long(const InstDesc& c, int64_t blk) {
     else
         update_long_body(c, blk);
 }
-__device__ __forceinline__ void dist_quarter(const InstDesc& c, int64_t blk) {
-    if (long_split(c)) dist_quarter_body(c, blk, blockIdx.y, c.b.state->cstar);
+__device__ __forceinline__ void dist_slices(const InstDesc& c, int64_t blk) {
+    if (long_split(c)) dist_slice_body(c, blk, blockIdx.y, update_slices(c), c.b.state->cstar);
 }
 __device__ __forceinline__ void dist_window(const InstDesc& c, int64_t blk) {
     if (long_split(c)) dist_window_body(c, blk, blockIdx.y);
@@ -734,7 +744,7 @@ EBC_ROW_KERNEL(kb_rescore, rescore_short)
 EBC_ROW_KERNEL(kb_update, update_short)
 EBC_ROW_KERNEL(kb_rescore_long, rescore_long)
 EBC_ROW_KERNEL(kb_update_long, update_long)
-EBC_ROW_KERNEL(kb_dist_quarter, dist_quarter)
+EBC_ROW_KERNEL(kb_dist_slices, dist_slices)
 EBC_ROW_KERNEL(kb_dist_window, dist_window)
 EBC_ROW_KERNEL(kb_rescore_split, rescore_split)
 #undef EBC_ROW_KERNEL
@@ -771,7 +781,7 @@ hipError_t launch_greedy_step(const ebc_dataset* ds, int32_t t, int32_t* sel_out
         hipLaunchKernelGGL(k_rescore_long, dim3(nb, 4 * kWindowMax / kRescoreGroup), dim3(kBlock), 0, s, c);
         hipLaunchKernelGGL(k_pick, dim3(1), dim3(kBlock), 0, s, c, t);
         if (long_split(c)) {
-            hipLaunchKernelGGL(k_dist_quarter, dim3(nb, 4), dim3(kBlock), 0, s, c);
+            hipLaunchKernelGGL(k_dist_slices, dim3(nb, update_slices(c)), dim3(kBlock), 0, s, c);
             hipLaunchKernelGGL(k_update_split, dim3(nb), dim3(kBlock), 0, s, c);
         } else {
             hipLaunchKernelGGL(k_update_long, dim3(nb), dim3(kBlock), 0, s, c);
@@ -802,7 +812,7 @@ hipError_t launch_step_batched(const InstDesc* descs, const int64_t* row_pre, in
     hipLaunchKernelGGL(kb_pick, one, dim3(kBlock), 0, s, descs, t);
     hipLaunchKernelGGL(kb_update, rows, dim3(kBlock), 0, s, descs, row_pre, count, t);
     if (long_rows) {
-        hipLaunchKernelGGL(kb_dist_quarter, dim3(unsigned(total_rows), 4), dim3(kBlock), 0, s, descs, row_pre, count,
+        hipLaunchKernelGGL(kb_dist_slices, dim3(unsigned(total_rows), 16), dim3(kBlock), 0, s, descs, row_pre, count,
                            t);
         hipLaunchKernelGGL(kb_update_long, rows, dim3(kBlock), 0, s, descs, row_pre, count, t);
     }
@@ -879,7 +889,7 @@ hipError_t launch_accept_one(const ebc_dataset* ds, int32_t item, int32_t t, int
     fill_desc(ds, t + 1, sel, f, gain, &c);
     hipLaunchKernelGGL(k_one_accept, dim3(1), dim3(64), 0, s, c, item, t);
     if (long_split(c)) {
-        hipLaunchKernelGGL(k_dist_quarter, dim3(c.nb, 4), dim3(kBlock), 0, s, c);
+        hipLaunchKernelGGL(k_dist_slices, dim3(c.nb, update_slices(c)), dim3(kBlock), 0, s, c);
         hipLaunchKernelGGL(k_update_split, dim3(c.nb), dim3(kBlock), 0, s, c);
     } else if (wide_rows(c.k_pad))
         hipLaunchKernelGGL(k_update_long, dim3(c.nb), dim3(kBlock), 0, s, c);
