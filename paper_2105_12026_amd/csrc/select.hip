@@ -397,8 +397,7 @@ __device__ __forceinline__ int long_quarter(int d);
 // g of the window, blockIdx.y = 4 g + s; the window is cut into at most 32
 // groups of 1, 2, 4 or 8 candidates (the smallest size that fits), so
 // small windows still spread over the chip. Wave w sums
-// dimension quarter w, the quarters of the two-pass path, so both paths give
-// the same float64 distances; the candidates' values are staged in LDS as
+// dimension quarter w; the candidates' values are staged in LDS as
 // float64, 128 dimensions of every quarter at a time. The four partial sums
 // are added in quarter order and the clamped terms of the 64 points summed in
 // a fixed tree into rpart row 4 blk + s.
@@ -539,8 +538,8 @@ __device__ void update_long_body(const InstDesc& c, int64_t blk) {
 // (blockIdx.y = slice q of the dimension, 16-byte reads as above) writes
 // each point's partial sum to the per-chunk gains buffer, free at that point
 // of a step, at part[q * n_pad + v]. Pass 2 adds the slices in order. The
-// update takes one slice per chunk (up to 16); re-score windows take
-// quarters, the slices of the one-pass re-score.
+// update takes one slice per chunk (up to 16); small re-score windows share
+// the chunks among their candidates.
 __host__ __device__ inline bool long_split(const InstDesc& c) { return wide_rows(c.k_pad) && c.v_splits >= 4; }
 __host__ __device__ inline int update_slices(const InstDesc& c) { return c.v_splits < 16 ? c.v_splits : 16; }
 __device__ __forceinline__ int long_slice(int d, int S) { return ((d + S - 1) / S + 3) / 4 * 4; }
@@ -580,11 +579,6 @@ __device__ void dist_slice_body(const InstDesc& c, int64_t blk, int q, int S, in
     c.b.part[int64_t(q) * c.n_pad + v] = acc;
 }
 
-__device__ __forceinline__ double quarters_sum(const InstDesc& c, int64_t v) {
-    const double* __restrict__ p = c.b.part;
-    return ((p[v] + p[c.n_pad + v]) + p[2 * c.n_pad + v]) + p[3 * c.n_pad + v];
-}
-
 __device__ __forceinline__ double slices_sum(const InstDesc& c, int64_t v, int S) {
     const double* __restrict__ p = c.b.part;
     double s = p[v];
@@ -620,10 +614,15 @@ __device__ void update_split_body(const InstDesc& c, int64_t blk) {
 }
 
 // Small re-score windows of long rows (at most v_splits/4, and 4,
-// candidates): the same two passes per candidate, pass 1 over (quarter,
-// candidate) on blockIdx.y writing part[(4 j + q) * n_pad + v].
+// candidates): the same two passes per candidate, each candidate's distances
+// over S = min(16, v_splits / W) slices; pass 1 over (candidate, slice) on
+// blockIdx.y writing part[(S j + q) * n_pad + v].
 __host__ __device__ inline int split_window(const InstDesc& c) {
     return long_split(c) ? (c.v_splits / 4 < 4 ? c.v_splits / 4 : 4) : 0;
+}
+__device__ __forceinline__ int window_slices(const InstDesc& c, int W) {
+    const int s = c.v_splits / W;
+    return s < 16 ? s : 16;
 }
 
 // rpart rows a re-score of W candidates fills: one per 64-point sub-block
@@ -635,12 +634,14 @@ __device__ __forceinline__ int rescore_rows(const InstDesc& c, int W) {
 __device__ void dist_window_body(const InstDesc& c, int64_t blk, int y) {
     const int W = c.b.state->window_count;
     if (W > split_window(c)) return;  // the one-pass re-score takes it
-    const int j = y / 4, q = y % 4;
+    if (W == 0) return;
+    const int S = window_slices(c, W);
+    const int j = y / S, q = y % S;
     if (j >= W) return;
-    // quarter q of candidate j into the slot block 4 j + q
+    // slice q of candidate j into the slot block S j + q
     InstDesc cj = c;
-    cj.b.part = c.b.part + int64_t(4 * j) * c.n_pad;
-    dist_slice_body(cj, blk, q, 4, int64_t(c.b.wfinal[j].idx));
+    cj.b.part = c.b.part + int64_t(S * j) * c.n_pad;
+    dist_slice_body(cj, blk, q, S, int64_t(c.b.wfinal[j].idx));
 }
 
 __device__ void rescore_split_body(const InstDesc& c, int64_t blk) {
@@ -649,13 +650,14 @@ __device__ void rescore_split_body(const InstDesc& c, int64_t blk) {
     if (W > split_window(c) || W == 0) return;  // the same for the whole block
     const int64_t v = blk * kBlock + threadIdx.x;
     const double mv = v < c.n ? c.b.m64[v] : 0.0;
+    const int S = window_slices(c, W);
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         double val = 0.0;
         if (j < W && v < c.n) {
             InstDesc cj = c;
-            cj.b.part = c.b.part + int64_t(4 * j) * c.n_pad;
-            val = fmax(0.0, mv - quarters_sum(cj, v));
+            cj.b.part = c.b.part + int64_t(S * j) * c.n_pad;
+            val = fmax(0.0, mv - slices_sum(cj, v, S));
         }
         red[j][threadIdx.x] = val;
     }
@@ -774,7 +776,7 @@ hipError_t launch_greedy_step(const ebc_dataset* ds, int32_t t, int32_t* sel_out
     hipLaunchKernelGGL(k_wcount, dim3(nb), dim3(kBlock), 0, s, c);
     hipLaunchKernelGGL(k_wselect, dim3(1), dim3(kSelThreads), 0, s, c);
     if (wide_rows(c.k_pad)) {
-        if (long_split(c)) {  // small windows: two passes over quarters of the dimension
+        if (long_split(c)) {  // small windows: two passes over slices of the dimension
             hipLaunchKernelGGL(k_dist_window, dim3(nb, 16), dim3(kBlock), 0, s, c);
             hipLaunchKernelGGL(k_rescore_split, dim3(nb), dim3(kBlock), 0, s, c);
         }
@@ -871,7 +873,7 @@ hipError_t launch_gain64_many(const ebc_dataset* ds, const int32_t* items, int32
     fill_desc(ds, 0, nullptr, nullptr, nullptr, &c);
     hipLaunchKernelGGL(k_many_stage, dim3(1), dim3(kWindowMax), 0, s, c, items, W);
     if (wide_rows(c.k_pad)) {
-        if (long_split(c)) {  // small lists: two passes over quarters of the dimension
+        if (long_split(c)) {  // small lists: two passes over slices of the dimension
             hipLaunchKernelGGL(k_dist_window, dim3(c.nb, 16), dim3(kBlock), 0, s, c);
             hipLaunchKernelGGL(k_rescore_split, dim3(c.nb), dim3(kBlock), 0, s, c);
         }
