@@ -50,8 +50,9 @@ struct WindowEntry {
 
 // Pointers into the caller's workspace (see layout()).
 struct Buffers {
-    float* xq;          // distance-dtype copy of x, columns d.. are 0: float32 row-major [n_pad, k_pad];
-                        // reduced precision: 64-row tiles, 16-byte units unit-major inside a tile
+    float* xq;          // distance-dtype copy of x, columns d.. are 0: float32 rows up to 128 row-major
+                        // [n_pad, k_pad]; longer float32 rows and reduced precision: 64-row tiles,
+                        // 16-byte units unit-major inside a tile
     int* scale;         // [n_pad] E8M0 row scales (FP8 only, else null)
     double* n64;        // [n_pad] ||v||^2 in float64 (0 for pad rows)
     double* m0;         // [n_pad] d(v, e0) in float64, the minima of S = {} (= n64 for e0 = 0)

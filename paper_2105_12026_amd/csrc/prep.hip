@@ -334,7 +334,8 @@ __global__ void __launch_bounds__(kBlock) k_prep_lp(const float* __restrict__ x,
 // column slices (multiples of 16 columns); the per-slice float64 sums and
 // maxima are combined through LDS in slice order. Pass 1: norm, finiteness
 // and the largest centred magnitude (FP8 row scale); pass 2: the stored copy
-// (float32 rows or the tiled cast, centred at the column means) and its norm.
+// (centred at the column means, tiled in 16-byte units like the cast rows
+// of every dtype, float32 included) and its norm.
 // Per-block norm sums follow in k_norm_blocks. Same values as the one-thread-
 // per-row kernels up to the order of the float64 norm sums.
 constexpr int kPrepSlices = 16;
@@ -409,7 +410,9 @@ __global__ void __launch_bounds__(1024) k_prep_wide(const float* __restrict__ x,
     double nq = 0.0;
     int range = 0;
     if (DT == EBC_DT_F32) {
-        float4* __restrict__ q4 = reinterpret_cast<float4*>(b.xq + r * kp);
+        // tiled like the cast rows: unit k/4 of row r (kp/4 units a row)
+        float4* __restrict__ q4 = reinterpret_cast<float4*>(b.xq);
+        const int64_t row_at = (r >> 6) * (kp / 4) * 64 + (r & 63);
         for (int k = k0; k < k1; k += 4) {
             float4 c = {0.0f, 0.0f, 0.0f, 0.0f};
             if (live) {
@@ -423,7 +426,7 @@ __global__ void __launch_bounds__(1024) k_prep_wide(const float* __restrict__ x,
                 nq += double(c.z) * double(c.z);
                 nq += double(c.w) * double(c.w);
             }
-            q4[k / 4] = c;
+            q4[row_at + int64_t(k / 4) * 64] = c;
         }
     } else {
         constexpr int eb = DT == EBC_DT_FP8_E4M3 ? 1 : 2;

@@ -14,8 +14,15 @@ namespace ebc {
 template <int DT>
 struct WideRow;
 
-// float32 row-major [n_pad, k_pad]: piece p = values 8p .. 8p+7, half h
-// holds 8p+4h .. 8p+4h+3 (four 32x32x2 steps).
+// Tiled rows (64-row tiles, 16-byte units unit-major): unit u of row r at
+// 16-byte index ((r/64)*RU + u)*64 + r%64, so the 32 rows of an operand
+// block read one unit as 512 contiguous bytes.
+__device__ __forceinline__ uint4 tiled_unit(const void* xq, int64_t row, int ru, int u) {
+    return static_cast<const uint4*>(xq)[((row >> 6) * ru + u) * 64 + (row & 63)];
+}
+
+// float32 long rows, tiled (k_pad/4 units a row): piece p = values
+// 8p .. 8p+7, half h holds unit 2p+h = 8p+4h .. 8p+4h+3 (four 32x32x2 steps).
 template <>
 struct WideRow<EBC_DT_F32> {
     struct Piece {
@@ -24,7 +31,7 @@ struct WideRow<EBC_DT_F32> {
     static constexpr int kBatch = 4;  // pieces per load batch
     __device__ static int pieces(int k_pad) { return k_pad / 8; }
     __device__ static Piece load(const void* xq, int64_t row, int k_pad, int p, int half) {
-        return {*reinterpret_cast<const float4*>(static_cast<const float*>(xq) + row * k_pad + 8 * p + 4 * half)};
+        return {static_cast<const float4*>(xq)[((row >> 6) * (k_pad / 4) + 2 * p + half) * 64 + (row & 63)]};
     }
     // the caller's unpadded rows [n, d]: values past d read as 0
     __device__ static Piece load_x(const float* x, int64_t row, int d, int p, int half) {
@@ -41,12 +48,6 @@ struct WideRow<EBC_DT_F32> {
         return __builtin_amdgcn_mfma_f32_32x32x2f32(a.v.w, b.v.w, c, 0, 0, 0);
     }
 };
-
-// Tiled reduced-precision rows (64-row tiles, 16-byte units unit-major):
-// unit u of row r at uint4 index ((r/64)*RU + u)*64 + r%64.
-__device__ __forceinline__ uint4 tiled_unit(const void* xq, int64_t row, int ru, int u) {
-    return static_cast<const uint4*>(xq)[((row >> 6) * ru + u) * 64 + (row & 63)];
-}
 
 // BF16 / FP16: piece p = units 2p, 2p+1; half h holds unit 2p+h (one
 // 32x32x16 step).
