@@ -63,8 +63,8 @@ typedef enum {
  * round-to-nearest-even; products accumulate in FP32; the norms are FP32 of
  * the cast rows; m_v, L({e0}), f, the window re-score and every cross-block
  * sum stay FP64, so greedy selections are re-scored exactly. ebc_eval_sets
- * uses FP32 dot products of the caller's rows; ebc_eval_sets_in_dtype uses
- * this dtype.
+ * uses FP32 dot products of the caller's rows (or, for long rows of an FP32
+ * dataset, of its centred FP32 copy); ebc_eval_sets_in_dtype uses this dtype.
  *   EBC_DT_F32       float32 (v_mfma_f32_32x32x2_f32)
  *   EBC_DT_F16       IEEE half; |x| > 65504 raises EBC_E_RANGE
  *   EBC_DT_BF16      bfloat16
@@ -133,8 +133,9 @@ EBC_API ebc_status ebc_dataset_set_e0(ebc_dataset* ds, const float* e0, void* st
  *   f_out   [device] float64 [l].
  * Uses f(S) = (2/|V|) sum_v max(0, max_{s in S} (v.s - ||s||^2/2)) (the e0 = 0
  * term folded in): float32 dot products of the caller's float32 rows on the
- * matrix cores whatever the dataset's distance dtype, float32 maxima, float64
- * sums. A bad index or offsets make that set's f NaN and raise EBC_E_INDEX.
+ * matrix cores whatever the dataset's distance dtype (rows longer than 128
+ * of a float32 dataset: its float32 copy centred at the column means, which
+ * leaves f unchanged), float32 maxima, float64 sums. A bad index or offsets make that set's f NaN and raise EBC_E_INDEX.
  * Scratch of about (9 + 8 * min(16, n/256)) * l bytes is taken from the
  * stream-ordered allocator (hipMallocAsync) and freed on the same stream.
  * l = 0 is a no-op. */

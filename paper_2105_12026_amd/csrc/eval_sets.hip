@@ -619,12 +619,14 @@ k_es_lp(const uint4* __restrict__ xq, const float* __restrict__ hn, const int* _
 // the next batch in flight while the current one is multiplied), and it
 // computes the block's bookkeeping in its own lanes (lane r < 32: row r;
 // lanes 32..39: the units), so the waves meet at a barrier only for the
-// item's final sums. DT = F32 reads the caller's float32 rows [n, d] with the
-// float64 norms; otherwise the cast rows, their norms and (FP8) scales. The
-// cast copy of long rows is centred at the column means mu: with x' = x - mu,
-// v.s - ||s||^2/2 = x'_v.x'_s - ||x'_s||^2/2 + (||v||^2 - ||x'_v||^2)/2, so
-// the per-point shift of es_units is taken against the centred norms.
-template <int DT>
+// item's final sums. kCallerRows (DT = F32 over a reduced-precision
+// dataset) reads the caller's float32 rows [n, d] with the float64 norms;
+// otherwise the dataset's own copy (float32 or cast, tiled), its norms and
+// (FP8) scales. The copy of long rows is centred at the column means mu: with
+// x' = x - mu, v.s - ||s||^2/2 = x'_v.x'_s - ||x'_s||^2/2 + (||v||^2 -
+// ||x'_v||^2)/2, so the per-point shift of es_units is taken against the
+// centred norms.
+template <int DT, bool kCallerRows>
 __global__ void __launch_bounds__(256)
 k_es_wide(const void* src, int32_t len, const float* __restrict__ hn, const int* __restrict__ scale, int64_t n,
           const double* __restrict__ n64, const double* __restrict__ m0, const int64_t* __restrict__ off,
@@ -632,7 +634,8 @@ k_es_wide(const void* src, int32_t len, const float* __restrict__ hn, const int*
     using R = WideRow<DT>;
     using Piece = typename R::Piece;
     constexpr int B = R::kBatch;
-    constexpr bool kF32 = DT == EBC_DT_F32;
+    static_assert(!kCallerRows || DT == EBC_DT_F32, "the caller's rows are float32");
+    constexpr bool kF32 = kCallerRows;
     constexpr bool kFp8 = DT == EBC_DT_FP8_E4M3;
     __shared__ int64_t t_u[kTab + 1], t_off[kTab + 1];
     __shared__ int32_t t_e[kTab + 1];
@@ -645,7 +648,7 @@ k_es_wide(const void* src, int32_t len, const float* __restrict__ hn, const int*
     const int half = lane >> 5;
     const int64_t n_items = *sc.n_groups * splits;
     const int64_t vchunk = ((n + splits - 1) / splits + kVSub - 1) / kVSub * kVSub;
-    // float32: pieces of 8 values over d (the tail reads as 0); else the padded cast rows
+    // the caller's rows: pieces of 8 values over d (the tail reads as 0); else the padded copy
     const int np = kF32 ? (len + 7) / 8 : R::pieces(len);
     auto piece = [&](int64_t row, int p) -> Piece {
         if constexpr (kF32)
@@ -839,15 +842,23 @@ hipError_t launch_eval_sets(const ebc_dataset* ds, const int64_t* offsets, const
     const dim3 g = dim3(2048);
     if (wide) {
         const ebc_dtype dt = lowp ? ds->dt : EBC_DT_F32;
-        const void* src = lowp ? static_cast<const void*>(ds->b.xq) : static_cast<const void*>(ds->x);
-        const int32_t len = lowp ? ds->k_pad : ds->d;
+        // float32 over a float32 dataset: its tiled, centred float32 copy
+        const bool own = lowp || ds->dt == EBC_DT_F32;
+        const void* src = own ? static_cast<const void*>(ds->b.xq) : static_cast<const void*>(ds->x);
+        const int32_t len = own ? ds->k_pad : ds->d;
         switch (dt) {
-#define EBC_ESW(DTV)                                                                                              \
-    case DTV:                                                                                                     \
-        hipLaunchKernelGGL((k_es_wide<DTV>), g, dim3(256), 0, s, src, len, ds->b.hn, ds->b.scale, ds->n, ds->b.n64, \
-                           ds->b.m0, offsets, idx, l, splits, sc);                                                \
-        break;
-            EBC_ESW(EBC_DT_F32) EBC_ESW(EBC_DT_F16) EBC_ESW(EBC_DT_BF16) EBC_ESW(EBC_DT_FP8_E4M3)
+#define EBC_ESW(DTV, CALLER)                                                                                \
+    hipLaunchKernelGGL((k_es_wide<DTV, CALLER>), g, dim3(256), 0, s, src, len, ds->b.hn, ds->b.scale, ds->n,  \
+                       ds->b.n64, ds->b.m0, offsets, idx, l, splits, sc)
+            case EBC_DT_F32:
+                if (own)
+                    EBC_ESW(EBC_DT_F32, false);
+                else
+                    EBC_ESW(EBC_DT_F32, true);
+                break;
+            case EBC_DT_F16: EBC_ESW(EBC_DT_F16, false); break;
+            case EBC_DT_BF16: EBC_ESW(EBC_DT_BF16, false); break;
+            case EBC_DT_FP8_E4M3: EBC_ESW(EBC_DT_FP8_E4M3, false); break;
 #undef EBC_ESW
             default: (void)hipFreeAsync(base, s); return hipErrorInvalidValue;
         }
