@@ -873,11 +873,13 @@ hipError_t launch_gain64_many(const ebc_dataset* ds, const int32_t* items, int32
     fill_desc(ds, 0, nullptr, nullptr, nullptr, &c);
     hipLaunchKernelGGL(k_many_stage, dim3(1), dim3(kWindowMax), 0, s, c, items, W);
     if (wide_rows(c.k_pad)) {
-        if (long_split(c)) {  // small lists: two passes over slices of the dimension
+        // the list length is known here: launch only the re-score that takes it
+        if (W <= split_window(c)) {  // small lists: two passes over slices of the dimension
             hipLaunchKernelGGL(k_dist_window, dim3(c.nb, 16), dim3(kBlock), 0, s, c);
             hipLaunchKernelGGL(k_rescore_split, dim3(c.nb), dim3(kBlock), 0, s, c);
+        } else {
+            hipLaunchKernelGGL(k_rescore_long, dim3(c.nb, 4 * kWindowMax / kRescoreGroup), dim3(kBlock), 0, s, c);
         }
-        hipLaunchKernelGGL(k_rescore_long, dim3(c.nb, 4 * kWindowMax / kRescoreGroup), dim3(kBlock), 0, s, c);
     } else {
         hipLaunchKernelGGL(k_rescore, dim3(c.nb), dim3(kBlock), 0, s, c);
     }
