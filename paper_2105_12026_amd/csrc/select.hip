@@ -391,6 +391,7 @@ __device__ __forceinline__ void long_sums(const InstDesc& c, int64_t v, bool liv
 
 __host__ __device__ inline int split_window(const InstDesc& c);
 __device__ __forceinline__ int long_quarter(int d);
+__device__ void rescore_split_sum(const InstDesc& c, int64_t blk, double (*red)[kBlock]);
 
 // One-pass re-score of long rows (windows above the two-pass size). A
 // workgroup takes 64 ground points (sub-block s of row block blk) and group
@@ -442,10 +443,15 @@ __device__ void rescore_long_body(const InstDesc& c, int64_t blk, int y) {
     __shared__ int64_t scand[kRescoreGroup];
     const Buffers& b = c.b;
     const int W = b.state->window_count;
+    if (W <= split_window(c)) {
+        // small windows: pass 2 of the two-pass re-score, on the blocks of y = 0
+        // (same for the whole block), in the LDS of cq
+        if (y == 0) rescore_split_sum(c, blk, reinterpret_cast<double (*)[kBlock]>(&cq[0][0][0]));
+        return;
+    }
     const int gsz = W <= 32 ? 1 : (W <= 64 ? 2 : (W <= 128 ? 4 : kRescoreGroup));
     const int g0 = (y / 4) * gsz, sub = y % 4;
-    if (g0 >= W) return;               // the same for the whole block
-    if (W <= split_window(c)) return;  // the two-pass re-score takes small windows
+    if (g0 >= W) return;  // the same for the whole block
     const int gn = (W - g0) < gsz ? (W - g0) : gsz;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int64_t v = blk * kBlock + sub * 64 + lane;
@@ -644,8 +650,7 @@ __device__ void dist_window_body(const InstDesc& c, int64_t blk, int y) {
     dist_slice_body(cj, blk, q, S, int64_t(c.b.wfinal[j].idx));
 }
 
-__device__ void rescore_split_body(const InstDesc& c, int64_t blk) {
-    __shared__ double red[4][kBlock];
+__device__ void rescore_split_sum(const InstDesc& c, int64_t blk, double (*red)[kBlock]) {
     const int W = c.b.state->window_count;
     if (W > split_window(c) || W == 0) return;  // the same for the whole block
     const int64_t v = blk * kBlock + threadIdx.x;
@@ -670,6 +675,11 @@ __device__ void rescore_split_body(const InstDesc& c, int64_t blk) {
         __syncthreads();
     }
     if (threadIdx.x < W) c.b.rpart[blk * kWindowMax + threadIdx.x] = red[threadIdx.x][0];
+}
+
+__device__ void rescore_split_body(const InstDesc& c, int64_t blk) {
+    __shared__ double red[4][kBlock];
+    rescore_split_sum(c, blk, red);
 }
 
 // ---- fsum (one block per instance): f(S_t) = L({e0}) - |V|^-1 sum m_v ----
@@ -739,16 +749,12 @@ __device__ __forceinline__ void dist_slices(const InstDesc& c, int64_t blk) {
 __device__ __forceinline__ void dist_window(const InstDesc& c, int64_t blk) {
     if (long_split(c)) dist_window_body(c, blk, blockIdx.y);
 }
-__device__ __forceinline__ void rescore_split(const InstDesc& c, int64_t blk) {
-    if (long_split(c)) rescore_split_body(c, blk);
-}
 EBC_ROW_KERNEL(kb_rescore, rescore_short)
 EBC_ROW_KERNEL(kb_update, update_short)
 EBC_ROW_KERNEL(kb_rescore_long, rescore_long)
 EBC_ROW_KERNEL(kb_update_long, update_long)
 EBC_ROW_KERNEL(kb_dist_slices, dist_slices)
 EBC_ROW_KERNEL(kb_dist_window, dist_window)
-EBC_ROW_KERNEL(kb_rescore_split, rescore_split)
 #undef EBC_ROW_KERNEL
 
 __global__ void __launch_bounds__(kSelThreads) kb_wselect(const InstDesc* __restrict__ descs, int32_t t) {
@@ -776,10 +782,8 @@ hipError_t launch_greedy_step(const ebc_dataset* ds, int32_t t, int32_t* sel_out
     hipLaunchKernelGGL(k_wcount, dim3(nb), dim3(kBlock), 0, s, c);
     hipLaunchKernelGGL(k_wselect, dim3(1), dim3(kSelThreads), 0, s, c);
     if (wide_rows(c.k_pad)) {
-        if (long_split(c)) {  // small windows: two passes over slices of the dimension
-            hipLaunchKernelGGL(k_dist_window, dim3(nb, 16), dim3(kBlock), 0, s, c);
-            hipLaunchKernelGGL(k_rescore_split, dim3(nb), dim3(kBlock), 0, s, c);
-        }
+        // small windows: pass 1 over slices of the dimension here, pass 2 inside k_rescore_long
+        if (long_split(c)) hipLaunchKernelGGL(k_dist_window, dim3(nb, 16), dim3(kBlock), 0, s, c);
         hipLaunchKernelGGL(k_rescore_long, dim3(nb, 4 * kWindowMax / kRescoreGroup), dim3(kBlock), 0, s, c);
         hipLaunchKernelGGL(k_pick, dim3(1), dim3(kBlock), 0, s, c, t);
         if (long_split(c)) {
@@ -807,7 +811,6 @@ hipError_t launch_step_batched(const InstDesc* descs, const int64_t* row_pre, in
     if (long_rows) {
         hipLaunchKernelGGL(kb_dist_window, dim3(unsigned(total_rows), 16), dim3(kBlock), 0, s, descs, row_pre, count,
                            t);
-        hipLaunchKernelGGL(kb_rescore_split, rows, dim3(kBlock), 0, s, descs, row_pre, count, t);
         hipLaunchKernelGGL(kb_rescore_long, dim3(unsigned(total_rows), 4 * kWindowMax / kRescoreGroup), dim3(kBlock), 0, s,
                            descs, row_pre, count, t);
     }
