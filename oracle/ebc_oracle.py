@@ -22,8 +22,12 @@ against the paper by eye:
   submodular_function_optimization_cardinality_constraint and the text after
   it) and Sec. 4.1 (greedy picks the not-yet-selected item of largest
   marginal gain).
-* The dissimilarity is the squared Euclidean distance, Sec. 5 (experimental
-  setup).
+* The dissimilarity d is the squared Euclidean distance of the paper's
+  experiments, Sec. 5 (experimental setup), by default. Sec. 4 defines L and
+  f for any dissimilarity; ``dist="l1"`` selects the L1 (Manhattan)
+  distance sum_k |a_k - b_k| instead. f stays monotone and submodular for
+  any non-negative dissimilarity (it is a facility-location function), so
+  the same pins apply.
 
 Readings where the paper is silent (each listed in the design notes):
 e0 is the zero vector unless given; ties in the greedy argmax go to the lowest index;
@@ -43,6 +47,8 @@ import numpy as np
 
 __all__ = [
     "sqdist",
+    "l1dist",
+    "dissim",
     "loss",
     "f_value",
     "eval_sets",
@@ -64,7 +70,24 @@ def sqdist(a: np.ndarray, b: np.ndarray) -> np.ndarray:
     return np.sum(diff * diff, axis=-1)
 
 
-def loss(x: np.ndarray, s_vectors) -> float:
+def l1dist(a: np.ndarray, b: np.ndarray) -> np.ndarray:
+    """L1 (Manhattan) distance d(a, b) = sum_k |a_k - b_k| in float64 by
+    direct differences. ``a`` is [n, d] or [d]; ``b`` is [d]."""
+    diff = np.asarray(a, dtype=np.float64) - np.asarray(b, dtype=np.float64)
+    return np.sum(np.abs(diff), axis=-1)
+
+
+DISSIMILARITIES = {"sqeuclidean": sqdist, "l1": l1dist}
+
+
+def dissim(a: np.ndarray, b: np.ndarray, dist: str = "sqeuclidean") -> np.ndarray:
+    """The dissimilarity d(a, b) named by ``dist`` ("sqeuclidean" or "l1")."""
+    if dist not in DISSIMILARITIES:
+        raise ValueError(f"dist must be one of {sorted(DISSIMILARITIES)}")
+    return DISSIMILARITIES[dist](a, b)
+
+
+def loss(x: np.ndarray, s_vectors, dist: str = "sqeuclidean") -> float:
     """k-medoids loss L(V, S) as in Algorithm 1 (function L): for every ground
     point v a running minimum t over the vectors of S, then the sum of the t's
     divided by |V|. The running minimum starts at +inf (Algorithm 1 uses the
@@ -73,7 +96,7 @@ def loss(x: np.ndarray, s_vectors) -> float:
     x = np.asarray(x, dtype=np.float64)
     t = np.full(x.shape[0], np.inf)
     for s in s_vectors:
-        t = np.minimum(t, sqdist(x, s))
+        t = np.minimum(t, dissim(x, s, dist))
     return float(np.sum(t) / x.shape[0])
 
 
@@ -82,38 +105,38 @@ def _aux(x: np.ndarray, e0) -> np.ndarray:
     return np.zeros(x.shape[1]) if e0 is None else np.asarray(e0, dtype=np.float64).reshape(x.shape[1])
 
 
-def f_value(x: np.ndarray, s_idx, e0=None) -> float:
+def f_value(x: np.ndarray, s_idx, e0=None, dist: str = "sqeuclidean") -> float:
     """f(S) = L({e0}) - L(S u {e0}) (Eq. exemplar_based_clustering;
     Algorithm 1, return statement). ``s_idx`` lists row indices of x forming
     S (may be empty)."""
     x = np.asarray(x, dtype=np.float64)
     e0 = _aux(x, e0)
     members = [x[int(i)] for i in s_idx]
-    return loss(x, [e0]) - loss(x, [e0] + members)
+    return loss(x, [e0], dist) - loss(x, [e0] + members, dist)
 
 
-def eval_sets(x: np.ndarray, offsets: np.ndarray, idx: np.ndarray, e0=None) -> np.ndarray:
+def eval_sets(x: np.ndarray, offsets: np.ndarray, idx: np.ndarray, e0=None, dist: str = "sqeuclidean") -> np.ndarray:
     """f(S_j) for every set of a CSR-packed family S_multi = {S_1, .., S_l}
     (Sec. 4.1: optimisers score many sets per step). Set j holds
     idx[offsets[j]:offsets[j+1]]."""
     l = len(offsets) - 1
     out = np.empty(l)
     for j in range(l):
-        out[j] = f_value(x, idx[offsets[j]:offsets[j + 1]], e0)
+        out[j] = f_value(x, idx[offsets[j]:offsets[j + 1]], e0, dist)
     return out
 
 
-def min_dist_to_set(x: np.ndarray, s_idx, e0=None) -> np.ndarray:
+def min_dist_to_set(x: np.ndarray, s_idx, e0=None, dist: str = "sqeuclidean") -> np.ndarray:
     """m_v = min(d(v, e0), min_{s in S} d(v, s)) for every v: the per-point
     term inside L(S u {e0}) (Eq. loss_decomposed, times |V|)."""
     x = np.asarray(x, dtype=np.float64)
-    m = sqdist(x, _aux(x, e0))
+    m = dissim(x, _aux(x, e0), dist)
     for i in s_idx:
-        m = np.minimum(m, sqdist(x, x[int(i)]))
+        m = np.minimum(m, dissim(x, x[int(i)], dist))
     return m
 
 
-def marginal_gain(x: np.ndarray, m: np.ndarray, c: int) -> float:
+def marginal_gain(x: np.ndarray, m: np.ndarray, c: int, dist: str = "sqeuclidean") -> float:
     """Delta(c | S) given m = min_dist_to_set(x, S).
 
     From the definitions: f(S u {c}) - f(S) = L(S u {e0}) - L(S u {c} u {e0})
@@ -121,18 +144,18 @@ def marginal_gain(x: np.ndarray, m: np.ndarray, c: int) -> float:
     The tests check this against the literal difference of two f_value calls.
     """
     x = np.asarray(x, dtype=np.float64)
-    dist = sqdist(x, x[int(c)])
-    return float(np.sum(np.maximum(0.0, m - dist)) / x.shape[0])
+    dc = dissim(x, x[int(c)], dist)
+    return float(np.sum(np.maximum(0.0, m - dc)) / x.shape[0])
 
 
-def gains(x: np.ndarray, m: np.ndarray, cand=None) -> np.ndarray:
+def gains(x: np.ndarray, m: np.ndarray, cand=None, dist: str = "sqeuclidean") -> np.ndarray:
     """Delta(c | S) for every candidate c (default: every row of x)."""
     n = x.shape[0]
     cand = range(n) if cand is None else cand
-    return np.array([marginal_gain(x, m, c) for c in cand], dtype=np.float64)
+    return np.array([marginal_gain(x, m, c, dist) for c in cand], dtype=np.float64)
 
 
-def greedy(x: np.ndarray, k: int, e0=None):
+def greedy(x: np.ndarray, k: int, e0=None, dist: str = "sqeuclidean"):
     """Greedy maximisation of f under |S| <= k (Sec. 3; Sec. 4.1).
 
     Each step scores every not-yet-selected point by its marginal gain,
@@ -140,23 +163,23 @@ def greedy(x: np.ndarray, k: int, e0=None):
     S. Returns (selected indices [k], f(S_1..S_k) [k], gains [k])."""
     x = np.asarray(x, dtype=np.float64)
     n = x.shape[0]
-    l0 = float(np.sum(sqdist(x, _aux(x, e0))) / n)
-    m = min_dist_to_set(x, [], e0)
+    l0 = float(np.sum(dissim(x, _aux(x, e0), dist)) / n)
+    m = min_dist_to_set(x, [], e0, dist)
     chosen = np.zeros(n, dtype=bool)
     sel, fs, gs = [], [], []
     for _ in range(k):
-        g = gains(x, m)
+        g = gains(x, m, dist=dist)
         g[chosen] = -np.inf
         c = int(np.argmax(g))  # first maximum = lowest index on ties
         sel.append(c)
         gs.append(float(g[c]))
         chosen[c] = True
-        m = np.minimum(m, sqdist(x, x[c]))
+        m = np.minimum(m, dissim(x, x[c], dist))
         fs.append(l0 - float(np.sum(m) / n))
     return np.array(sel, dtype=np.int64), np.array(fs), np.array(gs)
 
 
-def exhaustive(x: np.ndarray, k: int, e0=None):
+def exhaustive(x: np.ndarray, k: int, e0=None, dist: str = "sqeuclidean"):
     """max_{S subset V, |S| <= k} f(S) by enumerating every subset (Eq.
     submodular_function_optimization_cardinality_constraint). Tiny n only.
     Returns (best value, best subset as a tuple)."""
@@ -164,7 +187,7 @@ def exhaustive(x: np.ndarray, k: int, e0=None):
     best, arg = 0.0, ()
     for size in range(0, k + 1):
         for s in itertools.combinations(range(n), size):
-            v = f_value(x, s, e0)
+            v = f_value(x, s, e0, dist)
             if v > best:
                 best, arg = v, s
     return best, arg
@@ -183,7 +206,7 @@ def sieve_thresholds(m: float, k: int, eps: float) -> list:
     return [(1.0 + eps) ** i for i in range(hi, lo - 1, -1)]
 
 
-def three_sieves(x: np.ndarray, k: int, eps: float, T: int, m=None, order=None, e0=None):
+def three_sieves(x: np.ndarray, k: int, eps: float, T: int, m=None, order=None, e0=None, dist: str = "sqeuclidean"):
     """Three Sieves: one summary S built from a stream of the points of V.
 
     The threshold v starts at the largest guess of sieve_thresholds. An
@@ -199,10 +222,10 @@ def three_sieves(x: np.ndarray, k: int, eps: float, T: int, m=None, order=None, 
     x = np.asarray(x, dtype=np.float64)
     n = x.shape[0]
     order = range(n) if order is None else [int(i) for i in order]
-    mv = min_dist_to_set(x, [], e0)
+    mv = min_dist_to_set(x, [], e0, dist)
     l0 = float(np.sum(mv) / n)
     if m is None:
-        m = max(marginal_gain(x, mv, c) for c in range(n))
+        m = max(marginal_gain(x, mv, c, dist) for c in range(n))
     grid = sieve_thresholds(m, k, eps)
     sel, fs, vs = [], [], []
     if not grid or k <= 0:
@@ -213,10 +236,10 @@ def three_sieves(x: np.ndarray, k: int, eps: float, T: int, m=None, order=None, 
             break
         seen += 1
         v = grid[j]
-        g = marginal_gain(x, mv, e)
+        g = marginal_gain(x, mv, e, dist)
         if g >= (v / 2.0 - fS) / (k - len(sel)):
             sel.append(e)
-            mv = np.minimum(mv, sqdist(x, x[e]))
+            mv = np.minimum(mv, dissim(x, x[e], dist))
             fS = l0 - float(np.sum(mv) / n)
             fs.append(fS)
             vs.append(v)
@@ -229,7 +252,7 @@ def three_sieves(x: np.ndarray, k: int, eps: float, T: int, m=None, order=None, 
     return sel, fs, vs, seen
 
 
-def sieve_streaming(x: np.ndarray, k: int, eps: float, m=None, order=None, e0=None):
+def sieve_streaming(x: np.ndarray, k: int, eps: float, m=None, order=None, e0=None, dist: str = "sqeuclidean"):
     """Sieve Streaming (the paper names it, Sec. 2 and Sec. 4.1, as an
     optimiser that scores many sets per step): one summary S_v per guess v of
     sieve_thresholds. Every arriving point is offered to every summary,
@@ -241,10 +264,10 @@ def sieve_streaming(x: np.ndarray, k: int, eps: float, m=None, order=None, e0=No
     x = np.asarray(x, dtype=np.float64)
     n = x.shape[0]
     order = range(n) if order is None else [int(i) for i in order]
-    m0 = min_dist_to_set(x, [], e0)
+    m0 = min_dist_to_set(x, [], e0, dist)
     l0 = float(np.sum(m0) / n)
     if m is None:
-        m = max(marginal_gain(x, m0, c) for c in range(n))
+        m = max(marginal_gain(x, m0, c, dist) for c in range(n))
     grid = sieve_thresholds(m, k, eps)
     if not grid or k <= 0:
         return [], [], 0.0, 0
@@ -260,10 +283,10 @@ def sieve_streaming(x: np.ndarray, k: int, eps: float, m=None, order=None, e0=No
         for j, v in enumerate(grid):
             if len(sel[j]) == k:
                 continue
-            g = marginal_gain(x, mv[j], e)
+            g = marginal_gain(x, mv[j], e, dist)
             if g >= (v / 2.0 - fS[j]) / (k - len(sel[j])):
                 sel[j].append(e)
-                mv[j] = np.minimum(mv[j], sqdist(x, x[e]))
+                mv[j] = np.minimum(mv[j], dissim(x, x[e], dist))
                 fS[j] = l0 - float(np.sum(mv[j]) / n)
                 fs[j].append(fS[j])
     best = 0

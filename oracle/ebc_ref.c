@@ -7,7 +7,10 @@
  *
  * These are the same definitions as oracle/ebc_oracle.py, written as loops so
  * that they finish at the benchmark sizes:
- *   - squared Euclidean dissimilarity (Sec. 5), direct differences in double;
+ *   - the dissimilarity d: the squared Euclidean distance of the paper's
+ *     experiments (Sec. 5), or, with metric = 1, the L1 (Manhattan) distance
+ *     sum_k |a_k - b_k| (Sec. 4 defines L and f for any dissimilarity);
+ *     direct differences in double either way;
  *   - k-medoids loss and f(S) = L({e0}) - L(S u {e0}), the auxiliary
  *     vector e0 given as a d-vector or, when NULL, the zero vector
  *     (Sec. 4, Eqs. k_medoids_loss and exemplar_based_clustering; Alg. 1);
@@ -43,10 +46,32 @@ static double sqn(const float* a, int d)
     return s;
 }
 
-/* d(v, e0): e0 NULL is the zero vector */
-static double d_e0(const float* a, const float* e0, int d)
+/* L1 (Manhattan) distance sum_k |a_k - b_k| */
+static double l1d(const float* a, const float* b, int d)
 {
-    return e0 ? sqd(a, e0, d) : sqn(a, d);
+    double s = 0.0;
+    for (int k = 0; k < d; ++k) s += fabs((double)a[k] - (double)b[k]);
+    return s;
+}
+
+static double l1n(const float* a, int d)
+{
+    double s = 0.0;
+    for (int k = 0; k < d; ++k) s += fabs((double)a[k]);
+    return s;
+}
+
+/* d(a, b): metric 0 squared Euclidean, 1 L1 */
+static double dis(const float* a, const float* b, int d, int metric)
+{
+    return metric == 1 ? l1d(a, b, d) : sqd(a, b, d);
+}
+
+/* d(v, e0): e0 NULL is the zero vector */
+static double d_e0(const float* a, const float* e0, int d, int metric)
+{
+    if (e0) return dis(a, e0, d, metric);
+    return metric == 1 ? l1n(a, d) : sqn(a, d);
 }
 
 int ebc_ref_threads(void)
@@ -60,14 +85,14 @@ int ebc_ref_threads(void)
 
 /* m[v] = min(d(v, e0), min_{s in S} d(v, s)) for all v. */
 void ebc_ref_min_dist(const float* x, int64_t n, int32_t d, const int32_t* s, int64_t ns,
-                      double* m, const float* e0)
+                      double* m, const float* e0, int metric)
 {
 #pragma omp parallel for schedule(static)
     for (int64_t v = 0; v < n; ++v) {
         const float* xv = x + v * d;
-        double t = d_e0(xv, e0, d);
+        double t = d_e0(xv, e0, d, metric);
         for (int64_t j = 0; j < ns; ++j) {
-            double dv = sqd(xv, x + (int64_t)s[j] * d, d);
+            double dv = dis(xv, x + (int64_t)s[j] * d, d, metric);
             if (dv < t) t = dv;
         }
         m[v] = t;
@@ -76,14 +101,14 @@ void ebc_ref_min_dist(const float* x, int64_t n, int32_t d, const int32_t* s, in
 
 /* out[i] = |V|^-1 sum_v max(0, m[v] - d(v, cand[i])). */
 void ebc_ref_gains(const float* x, int64_t n, int32_t d, const double* m, const int32_t* cand,
-                   int64_t nc, double* out)
+                   int64_t nc, double* out, int metric)
 {
 #pragma omp parallel for schedule(dynamic, 4)
     for (int64_t i = 0; i < nc; ++i) {
         const float* xc = x + (int64_t)cand[i] * d;
         double acc = 0.0;
         for (int64_t v = 0; v < n; ++v) {
-            double g = m[v] - sqd(x + v * d, xc, d);
+            double g = m[v] - dis(x + v * d, xc, d, metric);
             if (g > 0.0) acc += g;
         }
         out[i] = acc / (double)n;
@@ -92,19 +117,19 @@ void ebc_ref_gains(const float* x, int64_t n, int32_t d, const double* m, const 
 
 /* f(S_j) = L({e0}) - L(S_j u {e0}) for CSR sets; set j = idx[off[j] .. off[j+1]). */
 void ebc_ref_eval_sets(const float* x, int64_t n, int32_t d, const int64_t* off,
-                       const int32_t* idx, int64_t l, double* out, const float* e0)
+                       const int32_t* idx, int64_t l, double* out, const float* e0, int metric)
 {
     double l0 = 0.0;
-    for (int64_t v = 0; v < n; ++v) l0 += d_e0(x + v * d, e0, d);
+    for (int64_t v = 0; v < n; ++v) l0 += d_e0(x + v * d, e0, d, metric);
     l0 /= (double)n;
 #pragma omp parallel for schedule(dynamic, 1)
     for (int64_t j = 0; j < l; ++j) {
         double sum = 0.0;
         for (int64_t v = 0; v < n; ++v) {
             const float* xv = x + v * d;
-            double t = d_e0(xv, e0, d); /* e0 is always in the set */
+            double t = d_e0(xv, e0, d, metric); /* e0 is always in the set */
             for (int64_t q = off[j]; q < off[j + 1]; ++q) {
-                double dv = sqd(xv, x + (int64_t)idx[q] * d, d);
+                double dv = dis(xv, x + (int64_t)idx[q] * d, d, metric);
                 if (dv < t) t = dv;
             }
             sum += t;
@@ -179,7 +204,7 @@ void ebc_ref_gains_f32(const float* x, int64_t n, int32_t d, const double* m, co
 /* Greedy to cardinality k. sel[t], f[t] = f(S_{t+1}), g[t] = gain of step t.
  * Returns 0, -1 if memory runs out, -2 if k > n. */
 int ebc_ref_greedy(const float* x, int64_t n, int32_t d, int32_t k, int32_t* sel, double* f,
-                   double* g, const float* e0)
+                   double* g, const float* e0, int metric)
 {
     double* m = (double*)malloc(sizeof(double) * (size_t)n);
     double* gv = (double*)malloc(sizeof(double) * (size_t)n);
@@ -190,7 +215,7 @@ int ebc_ref_greedy(const float* x, int64_t n, int32_t d, int32_t k, int32_t* sel
     }
     double l0 = 0.0;
     for (int64_t v = 0; v < n; ++v) {
-        m[v] = d_e0(x + v * d, e0, d);
+        m[v] = d_e0(x + v * d, e0, d, metric);
         l0 += m[v];
     }
     l0 /= (double)n;
@@ -201,7 +226,7 @@ int ebc_ref_greedy(const float* x, int64_t n, int32_t d, int32_t k, int32_t* sel
             const float* xc = x + c * d;
             double acc = 0.0;
             for (int64_t v = 0; v < n; ++v) {
-                double q = m[v] - sqd(x + v * d, xc, d);
+                double q = m[v] - dis(x + v * d, xc, d, metric);
                 if (q > 0.0) acc += q;
             }
             gv[c] = acc / (double)n;
@@ -215,7 +240,7 @@ int ebc_ref_greedy(const float* x, int64_t n, int32_t d, int32_t k, int32_t* sel
         g[t] = gv[best];
         double sum = 0.0;
         for (int64_t v = 0; v < n; ++v) {
-            double dv = sqd(x + v * d, x + best * d, d);
+            double dv = dis(x + v * d, x + best * d, d, metric);
             if (dv < m[v]) m[v] = dv;
             sum += m[v];
         }
@@ -269,19 +294,19 @@ static void ref_sift_up(ref_entry* h, int64_t i)
     }
 }
 
-static double ref_gain_one(const float* x, int64_t n, int32_t d, const double* m, int64_t c)
+static double ref_gain_one(const float* x, int64_t n, int32_t d, const double* m, int64_t c, int metric)
 {
     const float* xc = x + c * d;
     double acc = 0.0;
     for (int64_t v = 0; v < n; ++v) {
-        double q = m[v] - sqd(x + v * d, xc, d);
+        double q = m[v] - dis(x + v * d, xc, d, metric);
         if (q > 0.0) acc += q;
     }
     return acc / (double)n;
 }
 
 int ebc_ref_greedy_lazy(const float* x, int64_t n, int32_t d, int32_t k, int32_t* sel, double* f,
-                        double* g, int64_t* evals, const float* e0)
+                        double* g, int64_t* evals, const float* e0, int metric)
 {
     if (k > n) return -2;
     double* m = (double*)malloc(sizeof(double) * (size_t)n);
@@ -295,14 +320,14 @@ int ebc_ref_greedy_lazy(const float* x, int64_t n, int32_t d, int32_t k, int32_t
     }
     double l0 = 0.0;
     for (int64_t v = 0; v < n; ++v) {
-        m[v] = d_e0(x + v * d, e0, d);
+        m[v] = d_e0(x + v * d, e0, d, metric);
         l0 += m[v];
     }
     l0 /= (double)n;
     /* step 0: every gain, as the plain loop computes it */
 #pragma omp parallel for schedule(dynamic, 4)
     for (int64_t c = 0; c < n; ++c) {
-        h[c].key = ref_gain_one(x, n, d, m, c);
+        h[c].key = ref_gain_one(x, n, d, m, c, metric);
         h[c].idx = (int32_t)c;
         h[c].stamp = 0;
     }
@@ -321,7 +346,7 @@ int ebc_ref_greedy_lazy(const float* x, int64_t n, int32_t d, int32_t k, int32_t
                 }
 #pragma omp parallel for schedule(dynamic, 1)
                 for (int64_t i = 0; i < nb; ++i) {
-                    batch[i].key = ref_gain_one(x, n, d, m, batch[i].idx);
+                    batch[i].key = ref_gain_one(x, n, d, m, batch[i].idx, metric);
                     batch[i].stamp = t;
                 }
                 count += nb;
@@ -348,7 +373,7 @@ int ebc_ref_greedy_lazy(const float* x, int64_t n, int32_t d, int32_t k, int32_t
             if (ns == 0) break;
 #pragma omp parallel for schedule(dynamic, 1)
             for (int64_t q = 0; q < ns; ++q) {
-                h[stale[q]].key = ref_gain_one(x, n, d, m, h[stale[q]].idx);
+                h[stale[q]].key = ref_gain_one(x, n, d, m, h[stale[q]].idx, metric);
                 h[stale[q]].stamp = t;
             }
             count += ns;
@@ -361,7 +386,7 @@ int ebc_ref_greedy_lazy(const float* x, int64_t n, int32_t d, int32_t k, int32_t
         ref_sift_down(h, len, 0);
         double sum = 0.0;
         for (int64_t v = 0; v < n; ++v) {
-            double dv = sqd(x + v * d, x + best * d, d);
+            double dv = dis(x + v * d, x + best * d, d, metric);
             if (dv < m[v]) m[v] = dv;
             sum += m[v];
         }

@@ -24,17 +24,29 @@ def lib():
         P = ctypes.c_void_p
         i64, i32 = ctypes.c_int64, ctypes.c_int32
         L.ebc_ref_threads.restype = ctypes.c_int
-        L.ebc_ref_min_dist.argtypes = [P, i64, i32, P, i64, P, P]
-        L.ebc_ref_gains.argtypes = [P, i64, i32, P, P, i64, P]
-        L.ebc_ref_eval_sets.argtypes = [P, i64, i32, P, P, i64, P, P]
+        ci = ctypes.c_int
+        L.ebc_ref_min_dist.argtypes = [P, i64, i32, P, i64, P, P, ci]
+        L.ebc_ref_gains.argtypes = [P, i64, i32, P, P, i64, P, ci]
+        L.ebc_ref_eval_sets.argtypes = [P, i64, i32, P, P, i64, P, P, ci]
         L.ebc_ref_eval_sets_f32.argtypes = [P, i64, i32, P, P, i64, P, ctypes.c_int]
         L.ebc_ref_gains_f32.argtypes = [P, i64, i32, P, P, i64, P, ctypes.c_int]
-        L.ebc_ref_greedy.argtypes = [P, i64, i32, i32, P, P, P, P]
+        L.ebc_ref_greedy.argtypes = [P, i64, i32, i32, P, P, P, P, ci]
         L.ebc_ref_greedy.restype = ctypes.c_int
-        L.ebc_ref_greedy_lazy.argtypes = [P, i64, i32, i32, P, P, P, P, P]
+        L.ebc_ref_greedy_lazy.argtypes = [P, i64, i32, i32, P, P, P, P, P, ci]
         L.ebc_ref_greedy_lazy.restype = ctypes.c_int
         _lib = L
     return _lib
+
+
+# dissimilarities: the squared Euclidean distance (the paper's experiments,
+# Sec. 5) and the L1 distance (Sec. 4 defines f for any dissimilarity)
+METRICS = {"sqeuclidean": 0, "l1": 1}
+
+
+def _metric(dist: str) -> int:
+    if dist not in METRICS:
+        raise ValueError(f"dist must be one of {sorted(METRICS)}")
+    return METRICS[dist]
 
 
 def _f32(x):
@@ -57,31 +69,32 @@ def threads() -> int:
     return int(lib().ebc_ref_threads())
 
 
-def min_dist(x, s_idx, e0=None) -> np.ndarray:
+def min_dist(x, s_idx, e0=None, dist: str = "sqeuclidean") -> np.ndarray:
     x = _f32(x)
     s = np.ascontiguousarray(s_idx, dtype=np.int32)
     m = np.empty(x.shape[0])
     keep, pe = _e0(x, e0)
-    lib().ebc_ref_min_dist(_p(x), x.shape[0], x.shape[1], _p(s), s.size, _p(m), pe)
+    lib().ebc_ref_min_dist(_p(x), x.shape[0], x.shape[1], _p(s), s.size, _p(m), pe, _metric(dist))
     return m
 
 
-def gains(x, m, cand=None) -> np.ndarray:
+def gains(x, m, cand=None, dist: str = "sqeuclidean") -> np.ndarray:
     x = _f32(x)
     m = np.ascontiguousarray(m, dtype=np.float64)
     cand = np.arange(x.shape[0], dtype=np.int32) if cand is None else np.ascontiguousarray(cand, dtype=np.int32)
     out = np.empty(cand.size)
-    lib().ebc_ref_gains(_p(x), x.shape[0], x.shape[1], _p(m), _p(cand), cand.size, _p(out))
+    lib().ebc_ref_gains(_p(x), x.shape[0], x.shape[1], _p(m), _p(cand), cand.size, _p(out), _metric(dist))
     return out
 
 
-def eval_sets(x, offsets, idx, e0=None) -> np.ndarray:
+def eval_sets(x, offsets, idx, e0=None, dist: str = "sqeuclidean") -> np.ndarray:
     x = _f32(x)
     off = np.ascontiguousarray(offsets, dtype=np.int64)
     idx = np.ascontiguousarray(idx, dtype=np.int32)
     out = np.empty(off.size - 1)
     keep, pe = _e0(x, e0)
-    lib().ebc_ref_eval_sets(_p(x), x.shape[0], x.shape[1], _p(off), _p(idx), off.size - 1, _p(out), pe)
+    lib().ebc_ref_eval_sets(_p(x), x.shape[0], x.shape[1], _p(off), _p(idx), off.size - 1, _p(out), pe,
+                            _metric(dist))
     return out
 
 
@@ -105,19 +118,19 @@ def gains_f32(x, m, cand, threads: int) -> np.ndarray:
     return out
 
 
-def greedy(x, k: int, e0=None):
+def greedy(x, k: int, e0=None, dist: str = "sqeuclidean"):
     x = _f32(x)
     sel = np.empty(k, dtype=np.int32)
     f = np.empty(k)
     g = np.empty(k)
     keep, pe = _e0(x, e0)
-    rc = lib().ebc_ref_greedy(_p(x), x.shape[0], x.shape[1], int(k), _p(sel), _p(f), _p(g), pe)
+    rc = lib().ebc_ref_greedy(_p(x), x.shape[0], x.shape[1], int(k), _p(sel), _p(f), _p(g), pe, _metric(dist))
     if rc != 0:
         raise ValueError(f"ebc_ref_greedy failed ({rc})")
     return sel.astype(np.int64), f, g
 
 
-def greedy_lazy(x, k: int, e0=None):
+def greedy_lazy(x, k: int, e0=None, dist: str = "sqeuclidean"):
     """Same result as greedy(), by lazy re-evaluation of stale upper bounds.
     Returns (sel, f, gain, gain evaluations)."""
     x = _f32(x)
@@ -127,7 +140,7 @@ def greedy_lazy(x, k: int, e0=None):
     ev = ctypes.c_int64(0)
     keep, pe = _e0(x, e0)
     rc = lib().ebc_ref_greedy_lazy(_p(x), x.shape[0], x.shape[1], int(k), _p(sel), _p(f), _p(g), ctypes.byref(ev),
-                                   pe)
+                                   pe, _metric(dist))
     if rc != 0:
         raise ValueError(f"ebc_ref_greedy_lazy failed ({rc})")
     return sel.astype(np.int64), f, g, int(ev.value)

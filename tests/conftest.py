@@ -21,3 +21,14 @@ def ref():
         build_ref.build()
     from oracle import ref as r
     return r
+
+
+def pytest_collection_modifyitems(config, items):
+    """Tests marked `slow` take minutes of CPU time; they run only when
+    EBC_RUN_SLOW=1 is set."""
+    if os.environ.get("EBC_RUN_SLOW") == "1":
+        return
+    skip = pytest.mark.skip(reason="slow CPU test: set EBC_RUN_SLOW=1 to run it")
+    for item in items:
+        if "slow" in item.keywords:
+            item.add_marker(skip)

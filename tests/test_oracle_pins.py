@@ -259,6 +259,63 @@ def test_c_oracle_hand_cases(ref):
 
 
 # --------------------------------------------------------------------------
+# The single-precision CPU baselines (the paper's Sec. 5 CPU runs of Alg. 1
+# are single precision; these loops time that baseline) agree with the
+# float64 definitions within the forward error bound of float32 arithmetic.
+# A distance sum_k (a_k - b_k)^2 of d terms, each difference and square
+# rounded once, and the d - 1 additions of non-negative terms in any order,
+# carries a relative error of at most gamma_{d+2} = (d+2)u / (1 - (d+2)u),
+# u = 2^-24. A minimum of such values keeps that relative bound, and
+# max(0, m - .) is 1-Lipschitz and only nonzero where the distance is below
+# m / (1 - gamma), so:
+#   |f32(S) - f(S)|   <= gamma_{d+2} L(S u {e0})                (+ float64 rounding)
+#   |g32(c) - g(c)|   <= gamma_{d+2} / (1 - gamma_{d+2}) mean_v m_v
+# --------------------------------------------------------------------------
+def _gamma(d):
+    u = 2.0 ** -24
+    return (d + 2) * u / (1.0 - (d + 2) * u)
+
+
+@pytest.mark.parametrize("threads", [1, 4])
+@pytest.mark.parametrize("n,d,seed", [(300, 9, 71), (517, 100, 72), (64, 1, 73)])
+def test_fp32_baselines_within_rounding_bound(ref, threads, n, d, seed):
+    rng = np.random.default_rng(seed)
+    x = (rng.standard_normal((n, d)) * rng.uniform(0.5, 3.0, (n, 1))).astype(np.float32)
+    gam = _gamma(d)
+    s = rng.choice(n, 5, replace=False)
+    for members in ([], list(s)):
+        m = O.min_dist_to_set(x, members)
+        cand = rng.integers(0, n, 40).astype(np.int32)
+        g64 = O.gains(x, m, cand)
+        g32 = ref.gains_f32(x, m, cand, threads)
+        bound = gam / (1.0 - gam) * float(np.mean(m)) + 1e-13 * float(np.max(m))
+        assert np.max(np.abs(g32 - g64)) <= bound
+    sizes = [0, 1, 2, 5, 9, 17]
+    sets = [rng.integers(0, n, z) for z in sizes]
+    off = np.cumsum([0] + sizes).astype(np.int64)
+    idx = np.concatenate(sets).astype(np.int32)
+    f64 = O.eval_sets(x, off, idx)
+    f32 = ref.eval_sets_f32(x, off, idx, threads)
+    l0 = float(np.mean(np.sum(x.astype(np.float64) ** 2, axis=1)))
+    for j in range(len(sizes)):
+        loss_j = l0 - f64[j]  # L(S_j u {e0})
+        assert abs(f32[j] - f64[j]) <= gam * loss_j + 1e-13 * l0, j
+
+
+def test_fp32_baselines_exact_on_small_integers(ref):
+    """Small integer coordinates make every float32 operation exact, so the
+    baselines must return the hand values of LINE and PLANE (exact
+    fractions) up to the final float64 division."""
+    m = O.min_dist_to_set(LINE, [2])  # {1, 4, 0}
+    g = ref.gains_f32(LINE, m, np.array([0, 1, 2], np.int32), 1)
+    np.testing.assert_allclose(g, [4 / 3, 4 / 3, 0.0], rtol=1e-15, atol=0)
+    off = np.array([0, 1, 2, 3, 5, 5], dtype=np.int64)
+    f = ref.eval_sets_f32(PLANE, off, np.array([0, 1, 2, 0, 1], np.int32), 2)
+    # S = {(1,0),(0,2)}: m = {0, 0, min(5, 4, 1)} = {0, 0, 1} -> f = 10/3 - 1/3 = 3
+    np.testing.assert_allclose(f, [2 / 3, 8 / 3, 8 / 3, 3.0, 0.0], rtol=1e-15, atol=1e-15)
+
+
+# --------------------------------------------------------------------------
 # The lazy evaluation of greedy returns exactly the plain loop's run
 # --------------------------------------------------------------------------
 def _mixture(seed, n, d, comps):
@@ -290,6 +347,26 @@ def test_lazy_greedy_equals_plain_greedy(ref, name):
     assert evals <= x.shape[0] * k
     with pytest.raises(ValueError):
         ref.greedy_lazy(x, x.shape[0] + 1)
+
+
+@pytest.mark.slow
+def test_lazy_greedy_reproduces_stored_full_size_plain_run(ref):
+    """The stored 100000 x 100 reference run (k = 50) was produced by the
+    plain loop (ebc_ref_greedy); the lazy evaluation, which produced the
+    200000 x 64 reference run, must reproduce it bitwise. Minutes of CPU
+    time: runs only with EBC_RUN_SLOW=1."""
+    import json
+    import os
+    from paper_2105_12026_amd import workloads as W
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "gmm20_n100000_d100_k50.json")
+    gold = json.load(open(path))
+    assert "ebc_ref_greedy " in gold["oracle"] + " "  # the plain loop wrote it
+    p = W.greedy_fp32(seed=2)
+    assert W.sha256_of(p.x) == gold["sha256_x"]
+    sel, f, g, evals = ref.greedy_lazy(p.x, p.k)
+    print(f"lazy greedy 100000 x 100 k=50: {evals} gain evaluations", flush=True)
+    assert sel.tolist() == gold["sel"]
+    assert f.tolist() == gold["f"] and g.tolist() == gold["gain"]  # bitwise
 
 
 # --------------------------------------------------------------------------
@@ -469,3 +546,127 @@ def test_sieve_streaming_half_approximation(seed, n, k, eps):
     assert f[-1] >= (0.5 - eps) * best - 1e-12
     for i in range(len(sel)):
         assert f[i] == pytest.approx(O.f_value(x, sel[:i + 1]), rel=1e-12)
+
+
+# --------------------------------------------------------------------------
+# A second dissimilarity: the L1 (Manhattan) distance. Sec. 4 defines the
+# loss and f for any dissimilarity d; f stays monotone submodular for any
+# d >= 0 (a facility-location function), so the pins above carry over.
+# --------------------------------------------------------------------------
+# LINE = {1, 2, 10}: d(v, 0) = {1, 2, 10}, L({e0}) = 13/3.
+#   S={1}:  d = {0, 1, 9}, m = {0, 1, 9} -> L = 10/3, f = 1
+#   S={2}:  d = {1, 0, 8}, m = {1, 0, 8} -> L = 3,    f = 4/3
+#   S={10}: d = {9, 8, 0}, m = {1, 2, 0} -> L = 1,    f = 10/3
+#   S={1,2}: m = {0,0,8} -> f = 5/3;  S={2,10}: m = {1,0,0} -> f = 4;  S={1,10}: m = {0,1,0} -> f = 4
+# Greedy: 10 first; at m = {1,2,0}, gain(1) = (1 + 1)/3 = gain(2) = (0 + 2)/3 = 2/3, an exact tie
+# -> row 0; then gain(2) = 1/3 and f = 13/3.
+LINE_L1_F = {(): Fraction(0), (0,): Fraction(1), (1,): Fraction(4, 3), (2,): Fraction(10, 3),
+             (0, 1): Fraction(5, 3), (1, 2): Fraction(4), (0, 2): Fraction(4), (0, 1, 2): Fraction(13, 3)}
+
+
+@pytest.mark.parametrize("s,expected", sorted(LINE_L1_F.items()))
+def test_l1_line_hand_values(s, expected):
+    assert O.f_value(LINE, s, dist="l1") == pytest.approx(float(expected), rel=1e-15, abs=1e-15)
+
+
+def test_l1_hand_greedy_and_plane():
+    sel, f, g = O.greedy(LINE, 3, dist="l1")
+    assert list(sel) == [2, 0, 1]
+    np.testing.assert_allclose(f, [10 / 3, 4.0, 13 / 3], rtol=1e-15)
+    np.testing.assert_allclose(g, [10 / 3, 2 / 3, 1 / 3], rtol=1e-15)
+    # PLANE = {(1,0), (0,2), (1,2)}: d(v, 0) = {1, 2, 3}, L({e0}) = 2.
+    #   S={(1,0)}: d = {0,3,2} -> m = {0,2,2} -> f = 2/3
+    #   S={(0,2)}: d = {3,0,1} -> m = {1,0,1} -> f = 4/3
+    #   S={(1,2)}: d = {2,1,0} -> m = {1,1,0} -> f = 4/3
+    # (the squared distance gives 2/3, 8/3, 8/3: a squared difference fails here)
+    assert O.f_value(PLANE, [0], dist="l1") == pytest.approx(2 / 3, rel=1e-15)
+    assert O.f_value(PLANE, [1], dist="l1") == pytest.approx(4 / 3, rel=1e-15)
+    assert O.f_value(PLANE, [2], dist="l1") == pytest.approx(4 / 3, rel=1e-15)
+    # greedy: tie 4/3 -> row 1; at m = {1,0,1}: gain(0) = 1/3 = gain(2) -> row 0; then row 2, f = 2
+    sel, f, _ = O.greedy(PLANE, 3, dist="l1")
+    assert list(sel) == [1, 0, 2]
+    np.testing.assert_allclose(f, [4 / 3, 5 / 3, 2.0], rtol=1e-15)
+
+
+def test_l1_against_scipy_cityblock_and_closed_forms():
+    scipy_spatial = pytest.importorskip("scipy.spatial.distance")
+    x = _rand(50, 7, 91)
+    D = scipy_spatial.cdist(x.astype(np.float64), x.astype(np.float64), "cityblock")
+    for c in (0, 17, 49):
+        np.testing.assert_allclose(O.l1dist(x, x[c]), D[:, c], rtol=1e-14, atol=1e-14)
+    n1 = np.sum(np.abs(x.astype(np.float64)), axis=1)
+    assert O.f_value(x, [], dist="l1") == 0.0
+    assert O.f_value(x, range(50), dist="l1") == pytest.approx(float(np.mean(n1)), rel=1e-14)
+    # singleton: f({c}) = |V|^-1 sum_v max(0, |v|_1 - |v - c|_1)
+    for c in (3, 30):
+        want = float(np.mean(np.maximum(0.0, n1 - D[:, c])))
+        assert O.f_value(x, [c], dist="l1") == pytest.approx(want, rel=1e-13)
+
+
+def test_l1_gain_is_discrete_derivative_monotone_submodular():
+    rng = np.random.default_rng(92)
+    x = _rand(30, 4, 93)
+    for _ in range(20):
+        a = list(rng.choice(30, 3, replace=False))
+        b = a + [i for i in rng.choice(30, 4, replace=False) if i not in a]
+        e = int(rng.integers(0, 30))
+        ma = O.min_dist_to_set(x, a, dist="l1")
+        mb = O.min_dist_to_set(x, b, dist="l1")
+        ga = O.marginal_gain(x, ma, e, dist="l1")
+        gb = O.marginal_gain(x, mb, e, dist="l1")
+        assert ga == pytest.approx(O.f_value(x, a + [e], dist="l1") - O.f_value(x, a, dist="l1"), abs=1e-12)
+        assert ga >= gb - 1e-12                                                # submodular
+        assert O.f_value(x, b, dist="l1") >= O.f_value(x, a, dist="l1") - 1e-12  # monotone
+
+
+def test_l1_scaling_is_degree_one():
+    # |2a - 2b|_1 = 2 |a - b|_1 exactly: f doubles (the squared distance would quadruple)
+    x = _rand(40, 5, 94)
+    sel, f, _ = O.greedy(x, 4, dist="l1")
+    sel2, f2, _ = O.greedy(2 * x, 4, dist="l1")
+    assert list(sel2) == list(sel)
+    np.testing.assert_allclose(f2, 2 * f, rtol=1e-14)
+
+
+@pytest.mark.parametrize("seed,n,d,k", [(95, 12, 2, 3), (96, 14, 3, 4)])
+def test_l1_greedy_against_exhaustive(seed, n, d, k):
+    x = _rand(n, d, seed)
+    sel, f, g = O.greedy(x, k, dist="l1")
+    best, arg = O.exhaustive(x, k, dist="l1")
+    assert f[-1] <= best + 1e-12
+    assert f[-1] >= (1.0 - 1.0 / math.e) * best - 1e-12
+    assert np.all(np.diff(g) <= 1e-12)                      # diminishing greedy gains
+    np.testing.assert_allclose(np.cumsum(g), f, rtol=1e-12)  # f(S_t) = sum of gains
+
+
+def test_l1_e0_translation_identity():
+    x = _rand(25, 3, 97)
+    e0 = np.array([0.5, -1.0, 2.0], dtype=np.float32)
+    for s in ([], [3], [1, 7, 20]):
+        assert O.f_value(x, s, e0=e0, dist="l1") == pytest.approx(
+            O.f_value(x.astype(np.float64) - e0.astype(np.float64), s, dist="l1"), rel=1e-13, abs=1e-14)
+
+
+def test_c_oracle_l1_matches_numpy_oracle(ref):
+    x = _rand(200, 6, 98)
+    e0 = np.array([0.3, 0.0, -0.5, 1.0, 0.0, 2.0], dtype=np.float32)
+    for e in (None, e0):
+        sel_np, f_np, g_np = O.greedy(x, 5, e0=e, dist="l1")
+        sel_c, f_c, g_c = ref.greedy(x, 5, e0=e, dist="l1")
+        assert list(sel_c) == list(sel_np)
+        np.testing.assert_allclose(f_c, f_np, rtol=1e-12)
+        np.testing.assert_allclose(g_c, g_np, rtol=1e-12)
+        sel_l, f_l, g_l, _ = ref.greedy_lazy(x, 5, e0=e, dist="l1")
+        assert list(sel_l) == list(sel_c) and np.array_equal(f_l, f_c)
+        m = O.min_dist_to_set(x, sel_np[:2], e0=e, dist="l1")
+        np.testing.assert_allclose(ref.min_dist(x, sel_np[:2], e0=e, dist="l1"), m, rtol=1e-13)
+        np.testing.assert_allclose(ref.gains(x, m, dist="l1"), O.gains(x, m, dist="l1"), rtol=1e-11, atol=1e-14)
+        off = np.array([0, 0, 3, 8, 9], dtype=np.int64)
+        idx = np.random.default_rng(99).integers(0, 200, 9).astype(np.int32)
+        np.testing.assert_allclose(ref.eval_sets(x, off, idx, e0=e, dist="l1"),
+                                   O.eval_sets(x, off, idx, e0=e, dist="l1"), rtol=1e-12, atol=1e-15)
+    sel, f, _ = ref.greedy(LINE, 3, dist="l1")
+    assert list(sel) == [2, 0, 1]
+    np.testing.assert_allclose(f, [10 / 3, 4.0, 13 / 3], rtol=1e-15)
+    with pytest.raises(ValueError):
+        ref.greedy(LINE, 2, dist="l2")
