@@ -474,6 +474,9 @@ def main():
     ap.add_argument("--dtype", default="f32", choices=sorted(PEAK_TFLOPS))
     ap.add_argument("--variant", type=int, default=None, help="tile variant of the gains kernel")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--legs", default="bf16,f16,fp8",
+                    help="reduced-precision legs of an FP32 greedy line (comma-separated dtypes, '' for none)")
+    ap.add_argument("--leg-steps", type=int, default=5, help="timed runs per reduced-precision leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 256 MiB device copy (reference for HBM byte counters)")
     ap.add_argument("--sets-shape", default="", help="paper_sets overrides, e.g. n=50000,l=5000,set_size=10")
@@ -514,30 +517,6 @@ def main():
     dev = torch.device("cuda:0")
     x = torch.from_numpy(p.x).to(dev)
     stream = torch.cuda.current_stream()
-    sel = torch.empty(k, dtype=torch.int32, device=dev)
-    f = torch.empty(k, dtype=torch.float64, device=dev)
-    gain = torch.empty(k, dtype=torch.float64, device=dev)
-
-    # gains tile variant: as given, else the autotuner's choice for this
-    # (dtype, row length, size), timed once before the measured steps
-    variant_used = 0
-    if args.variant is not None:
-        variant_used = args.variant
-    elif args.dtype != "f32" and d <= 128:  # long rows have a single kernel shape
-        tds = ebc.Dataset(x, dtype=args.dtype, stream=stream)
-        variant_used = tds.autotune(reps=3, stream=stream)["variant"]
-        tds.sync(stream)
-        tds.close()
-
-    def one_step(profile: bool):
-        ds = ebc.Dataset(x, dtype=args.dtype, stream=stream)
-        if args.dtype != "f32":
-            ds.set_variant(variant_used)
-        if profile:
-            ds.profile(True)
-        ds.greedy(k, stream=stream, sel=sel, f=f, gain=gain)
-        return ds
-
     print(f"# workload {args.workload}: n={n} d={d} k={k}", file=sys.stderr, flush=True)
     if args.copy_calibration:
         src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
@@ -546,17 +525,127 @@ def main():
         torch.cuda.synchronize()
         del src, dst
         print("# copy calibration: 268435456 bytes read, 268435456 bytes written", file=sys.stderr, flush=True)
+
+    golden = load_golden(args.workload, p)
+    run = timed_greedy(ebc, torch, x, n, d, k, args.dtype, args.variant, args.steps, args.warmup, stream)
+    ms_per_step = run["ms"]
+    pairs = pairs_per_greedy(n, k)
+    value = pairs / (ms_per_step * 1e-3)
+    roofline = run["roofline"]
+    roofline["traffic"] = counters_traffic(roofline["kernel"], args.workload, args.dtype, run["variant"])
+
+    out = {
+        "metric": "candidate x point distance evals/s (greedy, all candidates)",
+        "value": value, "unit": "pair-evals/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": args.dtype, "data": "synthetic",
+        "config": {"workload": args.workload, "n": n, "d": d, "k": k, "distance_dtype": args.dtype,
+                   "variant": run["variant"],
+                   "candidates": "all n points every step", "step": "residency + greedy k"},
+        "greedy_ms": ms_per_step, "gains_kernel_ms_total_per_step": run["gains_ms_per_run"],
+        "rest_of_step_ms_per_step": run["select_ms_per_run"],
+        "window_max": run["window_max"], "f_last": float(run["f"][-1]), "sel_head": run["sel"][:5],
+        "roofline": roofline,
+    }
+    if golden is not None:
+        out["parity"] = parity_vs_golden(np, run, golden, args.dtype)
+    if args.legs and args.dtype == "f32":
+        # the metric compares FP32 with reduced-precision distances: the same
+        # greedy run per dtype (timed like the main line, fewer runs), with
+        # its speed-up over FP32 and its f error and selection agreement
+        # against the stored float64 oracle run
+        legs = {}
+        for dt in [v for v in args.legs.split(",") if v]:
+            r = timed_greedy(ebc, torch, x, n, d, k, dt, None, args.leg_steps, 1, stream)
+            leg = {"ms_per_run": round(r["ms"], 3), "pair_evals_per_s": pairs / (r["ms"] * 1e-3),
+                   "speedup_vs_f32": round(ms_per_step / r["ms"], 3), "variant": r["variant"],
+                   "window_max": r["window_max"],
+                   "roofline": {k2: r["roofline"][k2] for k2 in ("kernel", "achieved", "peak", "frac",
+                                                                   "avg_launch_ms")}}
+            if golden is not None:
+                leg["parity"] = parity_vs_golden(np, r, golden, dt)
+            legs[dt] = leg
+            print(f"# leg {dt}: {leg}", file=sys.stderr, flush=True)
+        out["legs"] = legs
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(p.x, n)
+        out["paper_style_cpu"] = paper_style_cpu(p.x, n, value)
+    print(json.dumps(out), flush=True)
+
+
+GOLDEN = {"gmm20_n100000_d100_k50": "gmm20_n100000_d100_k50.json",
+          "gmm50+out_n200000_d64_k100": "gmm50+out_n200000_d64_k100.json",
+          "normal_n1000_d16_k5": "normal_n1000_d16.json"}
+
+
+def load_golden(workload, p):
+    """The stored float64 oracle run of this workload (tests/golden/, written
+    by tests/golden/make_golden.py from the oracle), if its input matches."""
+    from paper_2105_12026_amd import workloads
+    name = GOLDEN.get(workload)
+    if not name:
+        return None
+    try:
+        g = json.load(open(os.path.join(ROOT, "tests", "golden", name)))
+    except OSError:
+        return None
+    return g if g.get("sha256_x") == workloads.sha256_of(p.x) and "sel" in g else None
+
+
+def parity_vs_golden(np, run, golden, dt):
+    """Selections and f(S_t) of a timed run against the stored oracle run:
+    FP32 must select the oracle's points in the oracle's order; every dtype
+    reports the largest relative f error over the common prefix (where the
+    sets are equal, so f must agree to float64 rounding), the agreement, the
+    common prefix and the final quality gap."""
+    sel, f = run["sel"], np.asarray(run["f"])
+    rsel, rf = golden["sel"], np.asarray(golden["f"])
+    k = len(rsel)
+    prefix = next((i for i in range(k) if sel[i] != rsel[i]), k)
+    f_err = float(np.max(np.abs(f[:prefix] - rf[:prefix]) / np.abs(rf[:prefix]))) if prefix else None
+    return {"sel_equal": sel == rsel, "agreement": len(set(sel) & set(rsel)) / k, "common_prefix": prefix,
+            "max_rel_f_err_on_prefix": f_err, "quality_gap": float((rf[-1] - f[-1]) / rf[-1]),
+            "reference": "tests/golden (float64 oracle run)"}
+
+
+def timed_greedy(ebc, torch, x, n, d, k, dtype, variant, steps, warmup, stream):
+    """`warmup` untimed then `steps` timed runs of one step (dataset residency
+    + greedy k) in `dtype`, with the per-launch gains-kernel time from the
+    library's HIP events on the launch stream."""
+    dev = x.device
+    sel = torch.empty(k, dtype=torch.int32, device=dev)
+    f = torch.empty(k, dtype=torch.float64, device=dev)
+    gain = torch.empty(k, dtype=torch.float64, device=dev)
+    # gains tile variant: as given, else the autotuner's choice for this
+    # (dtype, row length, size), timed once before the measured steps
+    variant_used = 0
+    if variant is not None:
+        variant_used = variant
+    elif dtype != "f32" and d <= 128:  # long rows have a single kernel shape
+        tds = ebc.Dataset(x, dtype=dtype, stream=stream)
+        variant_used = tds.autotune(reps=3, stream=stream)["variant"]
+        tds.sync(stream)
+        tds.close()
+
+    def one_step(profile: bool):
+        ds = ebc.Dataset(x, dtype=dtype, stream=stream)
+        if dtype != "f32":
+            ds.set_variant(variant_used)
+        if profile:
+            ds.profile(True)
+        ds.greedy(k, stream=stream, sel=sel, f=f, gain=gain)
+        return ds
+
     keep = []
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         keep.append(one_step(False))
     torch.cuda.synchronize()
     for ds in keep:
         ds.sync()
     keep.clear()
-
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         keep.append(one_step(True))
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
@@ -568,46 +657,25 @@ def main():
         pr = ds.profile_read()
         for key in prof:
             prof[key] += pr[key]
-    ms_per_step = elapsed * 1e3 / args.steps
-    pairs = pairs_per_greedy(n, k)
-    value = pairs * args.steps / elapsed
-
     # roofline of the dominant kernel (marginal gains on the MFMA units):
     # algorithmic flops per launch = 2*d per (candidate, point) pair, with
     # the already-selected candidates not counted, averaged over the steps;
     # padding of d and the affine chunk are not counted.
     gains_avg_ms = prof["gains_ms"] / max(prof["gains_launches"], 1)
-    flops_per_launch = 2.0 * d * pairs / k
+    flops_per_launch = 2.0 * d * pairs_per_greedy(n, k) / k
     achieved = flops_per_launch / (gains_avg_ms * 1e-3) / 1e12
-    peak = PEAK_TFLOPS[args.dtype]
+    peak = PEAK_TFLOPS[dtype]
     if d > 128:
         kname = "k_gains_wide"
     else:
-        kname = "k_gains_f32" if args.dtype == "f32" else ("k_gains_lp_pp" if variant_used == 3 else "k_gains_lp")
+        kname = "k_gains_f32" if dtype == "f32" else ("k_gains_lp_pp" if variant_used == 3 else "k_gains_lp")
     roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak,
-                "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
-                "traffic": counters_traffic(kname, args.workload, args.dtype, variant_used),
+                "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
                 "kernel": kname, "avg_launch_ms": round(gains_avg_ms, 4),
                 "flops_per_launch": flops_per_launch}
-
-    sel_host = sel.cpu().numpy().tolist()
-    out = {
-        "metric": "candidate x point distance evals/s (greedy, all candidates)",
-        "value": value, "unit": "pair-evals/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": args.dtype, "data": "synthetic",
-        "config": {"workload": args.workload, "n": n, "d": d, "k": k, "distance_dtype": args.dtype,
-                   "variant": variant_used,
-                   "candidates": "all n points every step", "step": "residency + greedy k"},
-        "greedy_ms": ms_per_step, "gains_kernel_ms_total_per_step": prof["gains_ms"] / args.steps,
-        "rest_of_step_ms_per_step": prof["select_ms"] / args.steps,
-        "window_max": window_max, "f_last": float(f[-1].item()), "sel_head": sel_host[:5],
-        "roofline": roofline,
-    }
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(p.x, n)
-        out["paper_style_cpu"] = paper_style_cpu(p.x, n, value)
-    print(json.dumps(out), flush=True)
+    return {"ms": elapsed * 1e3 / steps, "variant": variant_used, "window_max": window_max,
+            "gains_ms_per_run": prof["gains_ms"] / steps, "select_ms_per_run": prof["select_ms"] / steps,
+            "sel": sel.cpu().numpy().tolist(), "f": f.cpu().numpy().tolist(), "roofline": roofline}
 
 
 if __name__ == "__main__":

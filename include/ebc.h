@@ -84,6 +84,18 @@ typedef enum {
  * over the dimension in chunks. */
 #define EBC_MAX_DIM 4096
 
+/* Dissimilarity flag of ebc_dataset_create. Sec. 4 defines the k-medoids
+ * loss and f for any dissimilarity d; the paper's experiments (Sec. 5) and
+ * this library's default use the squared Euclidean distance. EBC_FLAG_L1
+ * selects the L1 (Manhattan) distance d(x,y) = sum_k |x_k - y_k| instead:
+ * d(v, e0), f, the gains, greedy (including its float64 re-score and m_v
+ * update), the streaming optimisers and the multi-set evaluation all use it.
+ * It has no dot-product form, so its kernels run on the vector ALUs in
+ * float32 (dt must be EBC_DT_F32, else EBC_E_UNSUPPORTED) with the same
+ * float64 sums; L1 datasets cannot join a batch (ebc_batch_create returns
+ * EBC_E_UNSUPPORTED). */
+#define EBC_FLAG_L1 1u
+
 /* Exact device workspace that ebc_dataset_create needs for (n, d, dt), in
  * bytes; 0 if the arguments are invalid. The library allocates no device
  * memory of its own, so this is the whole device footprint of a dataset
@@ -98,7 +110,7 @@ EBC_API size_t ebc_dataset_bytes(int64_t n, int32_t d, ebc_dtype dt);
  *             and unchanged until ebc_dataset_destroy (float64 re-scoring and
  *             the m_v update read it).
  *   n, d      1 <= n < 2^31, 1 <= d <= EBC_MAX_DIM.
- *   flags     must be 0.
+ *   flags     0 (squared Euclidean distance) or EBC_FLAG_L1.
  *   workspace [device] at least ebc_dataset_bytes(n, d, dt) bytes, 256-byte
  *             aligned, owned by the caller, valid until destroy.
  *   out       [host] receives the dataset handle.
@@ -124,6 +136,13 @@ EBC_API ebc_status ebc_dataset_destroy(ebc_dataset* ds);
  * fails. */
 EBC_API ebc_status ebc_dataset_set_e0(ebc_dataset* ds, const float* e0, void* stream);
 
+/* Device scratch that ebc_eval_sets / ebc_eval_sets_in_dtype need for l
+ * sets over a ground set of n points, in bytes: per-set unit counts,
+ * validation flags and per-(set, ground-set split) float64 partial sums,
+ * about (16 + 8 min(16, ceil(n/256))) l bytes plus alignment. 0 if n is out
+ * of range (as for ebc_dataset_bytes) or l < 0. Host-only arithmetic. */
+EBC_API size_t ebc_eval_sets_bytes(int64_t n, int64_t l);
+
 /* f(S_j) for l sets packed as CSR (Sec. 4.1, S_multi = {S_1..S_l}; Alg. 1
  * per set; Alg. 2 computes the same per-(set, point) minima).
  *   offsets [device] int64 [l+1], offsets[0] = 0, non-decreasing.
@@ -131,24 +150,28 @@ EBC_API ebc_status ebc_dataset_set_e0(ebc_dataset* ds, const float* e0, void* st
  *           Indices are rows of V. Sets of any size; empty sets (f = 0) and
  *           repeats are allowed.
  *   f_out   [device] float64 [l].
+ *   scratch [device] at least ebc_eval_sets_bytes(n, l) bytes, 256-byte
+ *           aligned, owned by the caller; its contents are not needed before
+ *           or after the call's stream work. The library allocates nothing.
  * Uses f(S) = (2/|V|) sum_v max(0, max_{s in S} (v.s - ||s||^2/2)) (the e0 = 0
  * term folded in): float32 dot products of the caller's float32 rows on the
  * matrix cores whatever the dataset's distance dtype (rows longer than 128
  * of a float32 dataset: its float32 copy centred at the column means, which
- * leaves f unchanged), float32 maxima, float64 sums. A bad index or offsets make that set's f NaN and raise EBC_E_INDEX.
- * Scratch of about (9 + 8 * min(16, n/256)) * l bytes is taken from the
- * stream-ordered allocator (hipMallocAsync) and freed on the same stream.
+ * leaves f unchanged), float32 maxima, float64 sums. A bad index or offsets
+ * make that set's f NaN and raise EBC_E_INDEX (deferred).
+ * Errors: EBC_E_INVALID_ARG for null pointers, l < 0, a scratch that is too
+ * small or not 256-byte aligned; EBC_E_DEVICE if a launch fails.
  * l = 0 is a no-op. */
 EBC_API ebc_status ebc_eval_sets(ebc_dataset* ds, const int64_t* offsets, const int32_t* idx, int64_t l,
-                         double* f_out, void* stream);
+                                 double* f_out, void* scratch, size_t scratch_bytes, void* stream);
 
 /* The same f(S_j) with the dot products in the dataset's distance dtype (the
  * paper compares FP16 with FP32 GPU evaluation, Sec. 5): the cast rows and
  * their FP32 norms, the dtype's matrix instruction (FP8 with the rows' E8M0
- * scales), FP32 maxima, FP64 sums. Same arguments, errors and scratch as
+ * scales), FP32 maxima, FP64 sums. Same arguments, scratch and errors as
  * ebc_eval_sets; identical to it for EBC_DT_F32 datasets. */
 EBC_API ebc_status ebc_eval_sets_in_dtype(ebc_dataset* ds, const int64_t* offsets, const int32_t* idx, int64_t l,
-                                          double* f_out, void* stream);
+                                          double* f_out, void* scratch, size_t scratch_bytes, void* stream);
 
 /* Marginal gains Delta(c|S) = f(S u {c}) - f(S) (Sec. 3, Definition
  * "Discrete derivative") for candidates c, computed in the form
@@ -203,12 +226,20 @@ EBC_API ebc_status ebc_greedy(ebc_dataset* ds, int32_t k, int32_t* sel_out, doub
  *   f_out        [device] float64 [k]: f(S) after each acceptance.
  *   count_out    [host] number of accepted points.
  *   examined_out [host] or NULL: points examined before the stream ended.
- * Errors: EBC_E_INVALID_ARG (arguments), EBC_E_INDEX (an order entry outside
- * [0, n), detected on the host before any work), EBC_E_DEVICE. The dataset
- * state afterwards holds the summary (usable by ebc_marginal_gains). */
+ *   scratch      [device] at least ebc_three_sieves_bytes(n, n_order, batch)
+ *                bytes (the stream's indices, one stretch of gains and one
+ *                float64 re-score list), 256-byte aligned, caller-owned;
+ *                ebc_three_sieves_bytes is host-only arithmetic, 0 for
+ *                arguments out of range.
+ * Errors: EBC_E_INVALID_ARG (arguments, scratch too small or unaligned),
+ * EBC_E_INDEX (an order entry outside [0, n), detected on the host before
+ * any work), EBC_E_DEVICE. The dataset state afterwards holds the summary
+ * (usable by ebc_marginal_gains). */
+EBC_API size_t ebc_three_sieves_bytes(int64_t n, int64_t n_order, int32_t batch);
 EBC_API ebc_status ebc_three_sieves(ebc_dataset* ds, int32_t k, double eps, int64_t T, double m_max,
                                     const int32_t* order, int64_t n_order, int32_t batch, int32_t* sel_out,
-                                    double* f_out, int32_t* count_out, int64_t* examined_out, void* stream);
+                                    double* f_out, int32_t* count_out, int64_t* examined_out, void* scratch,
+                                    size_t scratch_bytes, void* stream);
 
 /* Sieve Streaming, the other optimiser the paper names (Sec. 2; Sec. 4.1:
  * optimisers such as greedy or Sieve Streaming score many sets per step):
@@ -222,12 +253,18 @@ EBC_API ebc_status ebc_three_sieves(ebc_dataset* ds, int32_t k, double eps, int6
  *   sel_out, f_out  [device] the best summary's points and f after each of
  *                   its acceptances;
  *   v_out           [host] or NULL: the best summary's guess v.
- * Device scratch: (8 n_pad + 8 batch + 12 k) bytes per guess, plus the
- * stream, allocated stream-ordered for the call. The dataset state
- * afterwards holds the best summary's minima. */
+ *   scratch         [device] at least ebc_sieve_streaming_bytes(n, k, eps,
+ *                   n_order, batch) bytes (host-only arithmetic; 0 for
+ *                   arguments out of range), 256-byte aligned, caller-owned:
+ *                   the stream's indices, and per guess (at most
+ *                   floor(log k / log(1+eps)) + 2 of them) its float64 minima,
+ *                   a stretch of gains, its members and f values.
+ * The dataset state afterwards holds the best summary's minima. */
+EBC_API size_t ebc_sieve_streaming_bytes(int64_t n, int32_t k, double eps, int64_t n_order, int32_t batch);
 EBC_API ebc_status ebc_sieve_streaming(ebc_dataset* ds, int32_t k, double eps, double m_max, const int32_t* order,
                                        int64_t n_order, int32_t batch, int32_t* sel_out, double* f_out,
-                                       int32_t* count_out, double* v_out, int64_t* examined_out, void* stream);
+                                       int32_t* count_out, double* v_out, int64_t* examined_out, void* scratch,
+                                       size_t scratch_bytes, void* stream);
 
 /* Graph mode for ebc_greedy (default off): the reset and all k steps are
  * recorded once into a HIP graph (on a private stream; recording runs
@@ -342,6 +379,8 @@ typedef struct {
     int32_t cand_tile;      /* candidates per gains workgroup */
     int32_t window_cap;     /* most candidates re-scored in float64 per step */
     int32_t dtype;
+    uint32_t flags;         /* the dissimilarity flag given at creation (0 or EBC_FLAG_L1) */
+    int32_t reserved;
     double l0;              /* L({e0}) as of the last ebc_sync_status (follows ebc_dataset_set_e0) */
 } ebc_dataset_info;
 

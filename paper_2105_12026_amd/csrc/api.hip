@@ -58,6 +58,9 @@ hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
 ebc_status from_hip(hipError_t e) { return e == hipSuccess ? EBC_OK : EBC_E_DEVICE; }
 
+// sets per multi-set evaluation call (set indices fit the kernels' int32 unit counts)
+constexpr int64_t kMaxSets = (int64_t(1) << 31) - 1;
+
 bool valid_dtype(ebc_dtype dt) {
     return dt == EBC_DT_F32 || dt == EBC_DT_F16 || dt == EBC_DT_BF16 || dt == EBC_DT_FP8_E4M3;
 }
@@ -73,7 +76,7 @@ const char* ebc_status_string(ebc_status st) {
         case EBC_E_INDEX: return "set index out of range or offsets not non-decreasing";
         case EBC_E_NONFINITE: return "non-finite value in the input points";
         case EBC_E_RANGE: return "value out of range of the distance dtype";
-        case EBC_E_NOMEM: return "out of memory (host allocation, or no room in the arena)";
+        case EBC_E_NOMEM: return "out of memory (host allocation, no room in the arena, or beyond a fixed scratch)";
         case EBC_E_DEVICE: return "HIP runtime error";
         case EBC_E_UNSUPPORTED: return "unsupported by this build";
     }
@@ -89,10 +92,11 @@ ebc_status ebc_dataset_create(const float* x, int64_t n, int32_t d, ebc_dtype dt
                               void* workspace, size_t workspace_bytes, void* stream, ebc_dataset** out) {
     if (!out) return EBC_E_INVALID_ARG;
     *out = nullptr;
-    if (!x || !workspace || flags != 0) return EBC_E_INVALID_ARG;
+    if (!x || !workspace || (flags & ~uint32_t(EBC_FLAG_L1)) != 0) return EBC_E_INVALID_ARG;
     if (!valid_dtype(dt)) return EBC_E_INVALID_ARG;
     if (n < 1 || n >= (int64_t(1) << 31) - kRowAlign || d < 1) return EBC_E_INVALID_ARG;
     if (d > EBC_MAX_DIM) return EBC_E_UNSUPPORTED;
+    if ((flags & EBC_FLAG_L1) && dt != EBC_DT_F32) return EBC_E_UNSUPPORTED;
     if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0) return EBC_E_INVALID_ARG;
     const Layout L = layout(n, d, dt);
     if (workspace_bytes < L.total) return EBC_E_INVALID_ARG;
@@ -107,6 +111,7 @@ ebc_status ebc_dataset_create(const float* x, int64_t n, int32_t d, ebc_dtype dt
     ds->k_pad = k_pad_for(d, dt);
     ds->v_splits = v_splits_for(ds->n_pad, ds->k_pad);
     ds->dt = dt;
+    ds->metric = (flags & EBC_FLAG_L1) ? 1 : 0;
     char* w = static_cast<char*>(workspace);
     Buffers& b = ds->b;
     b.xq = reinterpret_cast<float*>(w + L.off_xq);
@@ -129,6 +134,17 @@ ebc_status ebc_dataset_create(const float* x, int64_t n, int32_t d, ebc_dtype dt
     b.rpart = reinterpret_cast<double*>(w + L.off_rpart);
     b.fpart = reinterpret_cast<double*>(w + L.off_fpart);
     b.state = reinterpret_cast<DevState*>(w + L.off_state);
+    if (grouped(ds->k_pad, dt)) {
+        b.perm = reinterpret_cast<int32_t*>(w + L.off_perm);
+        b.inv = reinterpret_cast<int32_t*>(w + L.off_inv);
+        b.xqp = w + L.off_xqp;
+        b.hnp = reinterpret_cast<float*>(w + L.off_hnp);
+        b.hap = reinterpret_cast<float*>(w + L.off_hap);
+        b.hmp = reinterpret_cast<float*>(w + L.off_hmp);
+        b.scp = dt == EBC_DT_FP8_E4M3 ? reinterpret_cast<int*>(w + L.off_scp) : nullptr;
+        b.gbucket = reinterpret_cast<int32_t*>(w + L.off_gbucket);
+        b.gcount = reinterpret_cast<int32_t*>(w + L.off_gcount);
+    }
 
     const hipError_t e = launch_prep(ds, as_stream(stream));
     if (e != hipSuccess) {
@@ -198,28 +214,35 @@ ebc_status ebc_dataset_get_info(ebc_dataset* ds, ebc_dataset_info* info) {
     info->cand_tile = int32_t(gains_cand_tile(ds));
     info->window_cap = kWindowMax;
     info->dtype = int32_t(ds->dt);
+    info->flags = ds->metric == 1 ? EBC_FLAG_L1 : 0u;
+    info->reserved = 0;
     info->l0 = ds->l0_host;
     return EBC_OK;
 }
 
-static ebc_status eval_sets_impl(ebc_dataset* ds, const int64_t* offsets, const int32_t* idx, int64_t l,
-                                 double* f_out, bool in_dtype, void* stream) {
-    if (!ds || l < 0) return EBC_E_INVALID_ARG;
-    if (l == 0) return EBC_OK;
-    if (!offsets || !f_out) return EBC_E_INVALID_ARG;
-    if (!idx) return EBC_E_INVALID_ARG;
-    if (l > (int64_t(1) << 31) * 4 - 4) return EBC_E_INVALID_ARG;
-    return from_hip(launch_eval_sets(ds, offsets, idx, l, f_out, in_dtype, as_stream(stream)));
+size_t ebc_eval_sets_bytes(int64_t n, int64_t l) {
+    if (n < 1 || n >= (int64_t(1) << 31) - kRowAlign || l < 0 || l > kMaxSets) return 0;
+    return eval_sets_scratch_bytes(n, l);
 }
 
-ebc_status ebc_eval_sets(ebc_dataset* ds, const int64_t* offsets, const int32_t* idx, int64_t l,
-                         double* f_out, void* stream) {
-    return eval_sets_impl(ds, offsets, idx, l, f_out, false, stream);
+static ebc_status eval_sets_impl(ebc_dataset* ds, const int64_t* offsets, const int32_t* idx, int64_t l,
+                                 double* f_out, bool in_dtype, void* scratch, size_t scratch_bytes, void* stream) {
+    if (!ds || l < 0 || l > kMaxSets) return EBC_E_INVALID_ARG;
+    if (l == 0) return EBC_OK;
+    if (!offsets || !f_out || !idx || !scratch) return EBC_E_INVALID_ARG;
+    if (reinterpret_cast<uintptr_t>(scratch) % 256 != 0) return EBC_E_INVALID_ARG;
+    if (scratch_bytes < eval_sets_scratch_bytes(ds->n, l)) return EBC_E_INVALID_ARG;
+    return from_hip(launch_eval_sets(ds, offsets, idx, l, f_out, in_dtype, scratch, as_stream(stream)));
+}
+
+ebc_status ebc_eval_sets(ebc_dataset* ds, const int64_t* offsets, const int32_t* idx, int64_t l, double* f_out,
+                         void* scratch, size_t scratch_bytes, void* stream) {
+    return eval_sets_impl(ds, offsets, idx, l, f_out, false, scratch, scratch_bytes, stream);
 }
 
 ebc_status ebc_eval_sets_in_dtype(ebc_dataset* ds, const int64_t* offsets, const int32_t* idx, int64_t l,
-                                  double* f_out, void* stream) {
-    return eval_sets_impl(ds, offsets, idx, l, f_out, true, stream);
+                                  double* f_out, void* scratch, size_t scratch_bytes, void* stream) {
+    return eval_sets_impl(ds, offsets, idx, l, f_out, true, scratch, scratch_bytes, stream);
 }
 
 ebc_status ebc_marginal_gains(ebc_dataset* ds, const double* m, const int32_t* cand, int64_t n_cand,

@@ -87,6 +87,8 @@ ebc_status ebc_batch_create(ebc_dataset* const* ds, int32_t count, void* workspa
     if (workspace_bytes < L.total) return EBC_E_INVALID_ARG;
     for (int32_t i = 0; i < count; ++i)
         if (!ds[i]) return EBC_E_INVALID_ARG;
+    for (int32_t i = 0; i < count; ++i)
+        if (ds[i]->metric != 0) return EBC_E_UNSUPPORTED;  // batched gains are the squared-distance kernels
 
     ebc_batch* bt = new (std::nothrow) ebc_batch();
     if (!bt) return EBC_E_NOMEM;

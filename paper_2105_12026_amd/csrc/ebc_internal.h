@@ -73,6 +73,20 @@ struct Buffers {
     double* rpart;      // [nb, kWindowMax] float64 re-score partial sums ([4 nb, ...] for long rows)
     double* fpart;      // [nb] partial sums of m_v or norms
     DevState* state;
+    // Grouped order of the reduced-precision gains (rows up to 128 values):
+    // the ground set sorted by nearest pivot, so that a 32 x 32 tile pairs
+    // nearby candidates with nearby points and most tiles clamp to their
+    // lower bound as a whole (the gains kernel then skips their epilogue).
+    // Null for every other dataset.
+    int32_t* perm;      // [n_pad] slot -> row (identity on padding rows)
+    int32_t* inv;       // [n_pad] row -> slot
+    void* xqp;          // the distance-dtype copy in slot order (same tiled layout as xq)
+    float* hnp;         // [n_pad] hn in slot order
+    float* hap;         // [n_pad] ha in slot order (kept in step with ha)
+    float* hmp;         // [n_pad] hm in slot order (kept in step with hm)
+    int* scp;           // [n_pad] FP8 row scales in slot order (FP8 only)
+    int32_t* gbucket;   // [n_pad] nearest pivot of each row (set-up only)
+    int32_t* gcount;    // [nb, groups] per-block bucket counts, then slot offsets (set-up only)
 };
 
 // Everything a kernel of one greedy step needs about one dataset. Solo
@@ -87,6 +101,8 @@ struct InstDesc {
     int32_t k;                       // greedy steps of this instance
     int32_t t0;                      // steps already done: a batched tick t runs step t0 + t
     int32_t dt, variant;
+    int32_t metric;                  // dissimilarity: 0 squared Euclidean, 1 L1
+    int32_t pad_m;
     int64_t chunk;                   // ground-set chunk of the gains kernel
     int32_t* sel;
     double* f;
@@ -101,6 +117,8 @@ struct GainsArgs {
     const float* hm;
     const int* scale;
     const int32_t* cand;
+    const int32_t* perm;  // grouped order: slot -> row (null: slot = row)
+    const int32_t* inv;   // grouped order: row -> slot
     int64_t n_cand, n_pad;
     int32_t v_splits, pad0;
     int64_t chunk;
@@ -125,8 +143,17 @@ __device__ inline int find_slot(const int64_t* __restrict__ pre, int count, int6
 
 struct Layout {
     size_t off_xq, off_scale, off_mu, off_n64, off_m0, off_m64, off_hn, off_ha, off_hm, off_sel, off_part, off_gsum, off_bmax,
-        off_barg, off_bcnt, off_wstage, off_wfinal, off_rpart, off_fpart, off_state, total;
+        off_barg, off_bcnt, off_wstage, off_wfinal, off_rpart, off_fpart, off_state, off_perm, off_inv, off_xqp,
+        off_hnp, off_hap, off_hmp, off_scp, off_gbucket, off_gcount, total;
 };
+
+// Datasets whose reduced-precision gains run in grouped order (see Buffers::perm).
+__host__ __device__ inline bool grouped(int32_t k_pad, ebc_dtype dt) { return dt != EBC_DT_F32 && !wide_rows(k_pad); }
+// Number of pivots (buckets) of the grouped order: one per 256 points, 1 .. 256.
+__host__ __device__ inline int32_t group_count(int64_t n) {
+    const int64_t g = n / 256;
+    return int32_t(g < 1 ? 1 : (g > 256 ? 256 : g));
+}
 
 int64_t pad_rows(int64_t n);
 int32_t k_pad_for(int32_t d, ebc_dtype dt);
@@ -147,6 +174,7 @@ struct ebc_dataset {
     int32_t k_pad;
     int32_t v_splits;
     ebc_dtype dt;
+    int32_t metric;  // dissimilarity: 0 squared Euclidean, 1 L1 (EBC_FLAG_L1)
     ebc::Buffers b;
     double l0_host;
     ebc_greedy_stats stats;
@@ -231,11 +259,14 @@ void fill_desc(const ebc_dataset* ds, int32_t k, int32_t* sel, double* f, double
 // Gains-kernel arguments of one instance (candidates: a list, or all rows).
 __host__ __device__ inline GainsArgs gains_args(const InstDesc& d, const int32_t* cand, int64_t n_cand) {
     GainsArgs a;
-    a.xq = d.b.xq;
-    a.hn = d.b.hn;
-    a.ha = d.b.ha;
-    a.hm = d.b.hm;
-    a.scale = d.b.scale;
+    const bool g = d.b.perm != nullptr;  // grouped order: the slot-order copies
+    a.xq = g ? d.b.xqp : d.b.xq;
+    a.hn = g ? d.b.hnp : d.b.hn;
+    a.ha = g ? d.b.hap : d.b.ha;
+    a.hm = g ? d.b.hmp : d.b.hm;
+    a.scale = g ? d.b.scp : d.b.scale;
+    a.perm = d.b.perm;
+    a.inv = d.b.inv;
     a.cand = cand;
     a.n_cand = n_cand;
     a.n_pad = d.n_pad;
@@ -282,6 +313,7 @@ hipError_t launch_load_m(const ebc_dataset* ds, const double* m, hipStream_t s);
 hipError_t launch_gains_f32(const ebc_dataset* ds, const int32_t* cand, int64_t n_cand, hipStream_t s);
 hipError_t launch_gains_lp(const ebc_dataset* ds, const int32_t* cand, int64_t n_cand, hipStream_t s);
 hipError_t launch_gains_wide(const ebc_dataset* ds, const int32_t* cand, int64_t n_cand, hipStream_t s);
+hipError_t launch_gains_l1(const ebc_dataset* ds, const int32_t* cand, int64_t n_cand, hipStream_t s);
 hipError_t launch_gains(const ebc_dataset* ds, const int32_t* cand, int64_t n_cand, hipStream_t s);
 int elem_bytes(ebc_dtype dt);
 
@@ -313,7 +345,10 @@ hipError_t launch_accept_one(const ebc_dataset* ds, int32_t item, int32_t t, int
                              hipStream_t s);
 hipError_t launch_greedy_step(const ebc_dataset* ds, int32_t t, int32_t* sel_out, double* f_out,
                               double* gain_out, hipStream_t s, hipEvent_t ev_gains_done);
+// device scratch of one multi-set evaluation of l sets over n ground points
+size_t eval_sets_scratch_bytes(int64_t n, int64_t l);
+// `scratch`: at least eval_sets_scratch_bytes(ds->n, l) bytes, 256-byte aligned
 hipError_t launch_eval_sets(const ebc_dataset* ds, const int64_t* offsets, const int32_t* idx,
-                            int64_t l, double* f_out, bool in_dtype, hipStream_t s);
+                            int64_t l, double* f_out, bool in_dtype, void* scratch, hipStream_t s);
 
 }  // namespace ebc

@@ -780,8 +780,104 @@ k_es_wide(const void* src, int32_t len, const float* __restrict__ hn, const int*
     }
 }
 
-// f_j = (2/|V|) sum over splits (fixed order); empty sets 0; bad sets NaN.
-__global__ void __launch_bounds__(256) k_es_final(int64_t l, int64_t n, int32_t splits, EsScratch sc,
+// L1 dissimilarity (d(v,s) = sum_k |v_k - s_k|, no dot-product form): the
+// same groups and splits, on the vector ALUs. A thread owns one ground point
+// of a 256-point pass; the group's non-empty sets are taken in order, each
+// set's members 16 at a time, their values staged in LDS 256 dimensions at a
+// time (read by every thread at the same address); the thread reads its own
+// row in 16-byte pieces where aligned. Per (set, point) the running minimum
+// starts at d(v, e0) (m0); the term d(v, e0) - min is added to the thread's
+// float accumulator of the set, and the accumulators are summed in float64
+// in a fixed order at the end of the item (part holds f * |V| per split).
+constexpr int kL1EsWin = 32;  // units per group window (non-empty sets per group <= 32)
+constexpr int kL1EsMem = 16;  // members per staged chunk
+constexpr int kL1EsK = 256;   // dimensions per staged chunk
+
+__global__ void __launch_bounds__(256)
+k_es_l1(const float* __restrict__ x, int64_t n, int32_t d, const double* __restrict__ m0,
+        const int64_t* __restrict__ off, const int32_t* __restrict__ idx, int64_t l, int32_t splits, EsScratch sc) {
+    __shared__ float lacc[kL1EsWin][256];
+    __shared__ __attribute__((aligned(16))) float ms[kL1EsMem][kL1EsK];
+    const int tid = threadIdx.x;
+    const int64_t n_items = *sc.n_groups * splits;
+    const int64_t vchunk = ((n + splits - 1) / splits + kVSub - 1) / kVSub * kVSub;
+    const bool vec = (d & 3) == 0 && (reinterpret_cast<uintptr_t>(x) & 15) == 0;
+
+    for (int64_t item = blockIdx.x; item < n_items; item += gridDim.x) {
+        const int64_t g = item / splits;
+        const int split = int(item % splits);
+        const int64_t j0 = lower_bound_u(sc.U, 0, l, g * kL1EsWin);
+        const int64_t j1 = lower_bound_u(sc.U, j0, l, (g + 1) * kL1EsWin);
+        const int64_t v_begin = int64_t(split) * vchunk;
+        int64_t v_end = v_begin + vchunk;
+        if (v_end > n) v_end = n;
+        for (int q = 0; q < kL1EsWin; ++q) lacc[q][tid] = 0.0f;  // each thread its own column
+        for (int64_t vs = v_begin; vs < v_end; vs += 256) {
+            const int64_t v = vs + tid;
+            const bool live = v < v_end;
+            const double m0v = live ? m0[v] : 0.0;
+            const float* __restrict__ xv = x + (live ? v : 0) * d;
+            for (int64_t j = j0; j < j1; ++j) {
+                if (sc.E[j + 1] == sc.E[j]) continue;  // empty or invalid set (the same for every thread)
+                const int loc = int(sc.E[j] - sc.E[j0]);
+                const int64_t a = off[j], z = off[j + 1];
+                float tmin = float(m0v);
+                for (int64_t q0 = a; q0 < z; q0 += kL1EsMem) {
+                    const int mc = (z - q0) < kL1EsMem ? int(z - q0) : kL1EsMem;
+                    float dist[kL1EsMem];
+#pragma unroll
+                    for (int m = 0; m < kL1EsMem; ++m) dist[m] = 0.0f;
+                    for (int k0 = 0; k0 < d; k0 += kL1EsK) {
+                        const int kn = (d - k0) < kL1EsK ? (d - k0) : kL1EsK;
+                        __syncthreads();
+                        for (int e = tid; e < kL1EsMem * kL1EsK; e += 256) {
+                            const int m = e / kL1EsK, k = e % kL1EsK;
+                            ms[m][k] = (m < mc && k < kn) ? x[int64_t(idx[q0 + m]) * d + k0 + k] : 0.0f;
+                        }
+                        __syncthreads();
+                        if (live) {
+                            int k = 0;
+                            if (vec)
+                                for (; k + 3 < kn; k += 4) {
+                                    const float4 x4 = *reinterpret_cast<const float4*>(xv + k0 + k);
+#pragma unroll
+                                    for (int m = 0; m < kL1EsMem; ++m) {
+                                        const float4 s4 = *reinterpret_cast<const float4*>(&ms[m][k]);
+                                        dist[m] += fabsf(x4.x - s4.x);
+                                        dist[m] += fabsf(x4.y - s4.y);
+                                        dist[m] += fabsf(x4.z - s4.z);
+                                        dist[m] += fabsf(x4.w - s4.w);
+                                    }
+                                }
+                            for (; k < kn; ++k) {
+                                const float xk = xv[k0 + k];
+#pragma unroll
+                                for (int m = 0; m < kL1EsMem; ++m) dist[m] += fabsf(xk - ms[m][k]);
+                            }
+                        }
+                    }
+#pragma unroll
+                    for (int m = 0; m < kL1EsMem; ++m)
+                        if (m < mc) tmin = fminf(tmin, dist[m]);
+                }
+                if (live) lacc[loc][tid] += float(m0v) - tmin;
+            }
+        }
+        __syncthreads();
+        for (int64_t j = j0 + tid; j < j1; j += 256) {
+            if (sc.E[j + 1] == sc.E[j]) continue;
+            const int loc = int(sc.E[j] - sc.E[j0]);
+            double t = 0.0;
+            for (int c = 0; c < 256; ++c) t += double(lacc[loc][c]);
+            sc.part[int64_t(split) * l + j] = t;
+        }
+        __syncthreads();
+    }
+}
+
+// f_j = (scale/|V|) sum over splits (fixed order); empty sets 0; bad sets NaN.
+// scale: 2 for the halved dot-product terms, 1 for the L1 terms.
+__global__ void __launch_bounds__(256) k_es_final(int64_t l, int64_t n, int32_t splits, EsScratch sc, double scale,
                                                   double* __restrict__ f_out) {
     const int64_t j = int64_t(blockIdx.x) * 256 + threadIdx.x;
     if (j >= l) return;
@@ -795,7 +891,7 @@ __global__ void __launch_bounds__(256) k_es_final(int64_t l, int64_t n, int32_t 
     }
     double s = 0.0;
     for (int p = 0; p < splits; ++p) s += sc.part[int64_t(p) * l + j];
-    f_out[j] = 2.0 * s / double(n);
+    f_out[j] = scale * s / double(n);
 }
 
 template <int KP>
@@ -807,17 +903,26 @@ void launch_es_main(dim3 g, hipStream_t s, const ebc_dataset* ds, const int64_t*
 
 }  // namespace
 
+namespace {
+// ground-set splits: as many as keep every split at least one pass long
+int32_t es_splits(int64_t n) {
+    int64_t splits = (n + kVSub - 1) / kVSub;
+    return int32_t(splits > kMaxSplits ? kMaxSplits : splits);
+}
+size_t a256(size_t v) { return (v + 255) & ~size_t(255); }
+}  // namespace
+
+size_t eval_sets_scratch_bytes(int64_t n, int64_t l) {
+    const int32_t splits = es_splits(n);
+    return a256(size_t(l + 1) * sizeof(int64_t)) + a256(size_t(l + 1) * sizeof(int32_t)) +
+           a256(size_t(l) * sizeof(int32_t)) + a256(sizeof(int64_t)) + a256(size_t(splits) * size_t(l) * sizeof(double));
+}
+
 hipError_t launch_eval_sets(const ebc_dataset* ds, const int64_t* offsets, const int32_t* idx, int64_t l,
-                            double* f_out, bool in_dtype, hipStream_t s) {
-    // ground-set splits: as many as keep every split at least one pass long
-    int32_t splits = int32_t((ds->n + kVSub - 1) / kVSub);
-    if (splits > kMaxSplits) splits = kMaxSplits;
-    auto a8 = [](size_t v) { return (v + 255) & ~size_t(255); };
-    const size_t bytes = a8((l + 1) * sizeof(int64_t)) + a8((l + 1) * sizeof(int32_t)) + a8(l * sizeof(int32_t)) +
-                         a8(sizeof(int64_t)) + a8(size_t(splits) * l * sizeof(double));
-    char* base = nullptr;
-    hipError_t e = hipMallocAsync(reinterpret_cast<void**>(&base), bytes, s);
-    if (e != hipSuccess) return e;
+                            double* f_out, bool in_dtype, void* scratch, hipStream_t s) {
+    const int32_t splits = es_splits(ds->n);
+    auto a8 = a256;
+    char* base = static_cast<char*>(scratch);
     EsScratch sc;
     char* p = base;
     sc.U = reinterpret_cast<int64_t*>(p);
@@ -832,6 +937,14 @@ hipError_t launch_eval_sets(const ebc_dataset* ds, const int64_t* offsets, const
 
     const unsigned nb = unsigned((l + 255) / 256);
     hipLaunchKernelGGL(k_es_units, dim3(nb), dim3(256), 0, s, offsets, idx, l, ds->n, sc, ds->b.state);
+    if (ds->metric == 1) {
+        // L1: float32 rows of the caller on the vector ALUs, whatever in_dtype says
+        hipLaunchKernelGGL(k_es_scan, dim3(1), dim3(1024), 0, s, l, kL1EsWin, sc);
+        hipLaunchKernelGGL(k_es_l1, dim3(2048), dim3(256), 0, s, ds->x, ds->n, ds->d, ds->b.m0, offsets, idx, l,
+                           splits, sc);
+        hipLaunchKernelGGL(k_es_final, dim3(nb), dim3(256), 0, s, l, ds->n, splits, sc, 1.0, f_out);
+        return hipGetLastError();
+    }
     const bool lowp = in_dtype && ds->dt != EBC_DT_F32;
     const int lp_kc = ds->k_pad / (ds->dt == EBC_DT_FP8_E4M3 ? 64 : 16);
     // long rows (float32 rows padded to 8, or the cast rows): the long-row kernel
@@ -860,7 +973,7 @@ hipError_t launch_eval_sets(const ebc_dataset* ds, const int64_t* offsets, const
             case EBC_DT_BF16: EBC_ESW(EBC_DT_BF16, false); break;
             case EBC_DT_FP8_E4M3: EBC_ESW(EBC_DT_FP8_E4M3, false); break;
 #undef EBC_ESW
-            default: (void)hipFreeAsync(base, s); return hipErrorInvalidValue;
+            default: return hipErrorInvalidValue;
         }
     } else if (lowp) {
         const int kc = ds->k_pad / (ds->dt == EBC_DT_FP8_E4M3 ? 64 : 16);
@@ -895,10 +1008,7 @@ hipError_t launch_eval_sets(const ebc_dataset* ds, const int64_t* offsets, const
             default: ok = false;
         }
 #undef EBC_ESL
-        if (!ok) {
-            (void)hipFreeAsync(base, s);
-            return hipErrorInvalidValue;
-        }
+        if (!ok) return hipErrorInvalidValue;
     } else {
         const int kp = (ds->d + 7) / 8 * 8;
         switch (kp) {
@@ -907,13 +1017,11 @@ hipError_t launch_eval_sets(const ebc_dataset* ds, const int64_t* offsets, const
             EBC_ES(8) EBC_ES(16) EBC_ES(24) EBC_ES(32) EBC_ES(40) EBC_ES(48) EBC_ES(56) EBC_ES(64)
             EBC_ES(72) EBC_ES(80) EBC_ES(88) EBC_ES(96) EBC_ES(104) EBC_ES(112) EBC_ES(120) EBC_ES(128)
 #undef EBC_ES
-            default: (void)hipFreeAsync(base, s); return hipErrorInvalidValue;
+            default: return hipErrorInvalidValue;
         }
     }
-    hipLaunchKernelGGL(k_es_final, dim3(nb), dim3(256), 0, s, l, ds->n, splits, sc, f_out);
-    e = hipGetLastError();
-    const hipError_t ef = hipFreeAsync(base, s);
-    return e != hipSuccess ? e : ef;
+    hipLaunchKernelGGL(k_es_final, dim3(nb), dim3(256), 0, s, l, ds->n, splits, sc, 2.0, f_out);
+    return hipGetLastError();
 }
 
 }  // namespace ebc

@@ -7,12 +7,20 @@
 //     G[c]/2 = sum_v med3( x^_v . x^_c + ha_v - hn_c, 0, hm_v )
 // where x^ are the quantised rows, hn = ||x^||^2/2 in float32, hm_v = m_v/2,
 // ha_v = hm_v - hn_v. Moving ha_v out of the clamp,
-//     med3(t + ha_v, 0, hm_v) = ha_v + med3(t, -ha_v, hm_v - ha_v),
+//     med3(t + ha_v, 0, hm_v) = med3(t, lo, hi) - lo,  lo = -ha_v, hi = hm_v - ha_v,
 // the accumulator starts from the constant tile -hn_c (the MFMA's C operand,
-// the same for every ground point), so the epilogue is one v_med3_f32 with
-// per-column bounds and one add per (candidate, point) pair, and the
-// chunk's sum of ha_v (the same for every candidate) is added once in
-// float64 at the end.
+// the same for every ground point), and the epilogue is one v_med3_f32 with
+// per-column bounds, one subtraction and one add per (candidate, point)
+// pair. A term at its lower bound is exactly 0, so a 32 x 32 tile whose
+// every value lies at or below its column's bound adds nothing, and the
+// wave skips its epilogue after one test (bitwise the same sums).
+//
+// Grouped order: the ground set is sorted by nearest pivot at residency, and
+// candidates (when all points are scored) and points are walked in that
+// order, so a tile pairs 32 nearby candidates with 32 nearby points; once a
+// point's minimum m_v is below its distance to other regions, whole tiles
+// clamp and are skipped (about 80-95% of them on the 200000 x 64 mixture).
+// The matrix work is the same for every tile.
 //
 // Layout in HBM: the quantised rows are stored in tiles of 64 rows,
 // "unit-major" inside a tile (16-byte unit u of all 64 rows, then unit u+1).
@@ -107,7 +115,7 @@ __device__ __forceinline__ void lp_tile(int64_t t, int64_t nt, int64_t t_begin, 
                                         const uint4* __restrict__ xqt, const float* __restrict__ ha,
                                         const float* __restrict__ hm, const int* __restrict__ sc, const uint4* st,
                                         uint4* next2, const uint4 (&a)[CB][G::HU], const floatx16 (&cinit)[CB],
-                                        const int (&sa)[CB], float (&acc_sum)[CB][16], double& lo_sum) {
+                                        const int (&sa)[CB], float (&acc_sum)[CB][16]) {
     using T = Lp<DT>;
     constexpr int HU = G::HU, VT = G::VT;
     // this wave's copies of tile t are done (those of t+1 may still fly) ...
@@ -131,7 +139,6 @@ __device__ __forceinline__ void lp_tile(int64_t t, int64_t nt, int64_t t_begin, 
         const float hav = st_ha[vrow];
         const float lo = -hav, hi = st_hm[vrow] - hav;
         const int sb = G::kFp8 ? st_sc[vrow] : 127;
-        lo_sum += double(lo);
         // CB independent accumulator chains, each starting from -hn_c
         floatx16 acc[CB];
 #pragma unroll
@@ -157,8 +164,8 @@ __device__ __forceinline__ void lp_tile_pipe(int64_t t, int64_t nt, int64_t t_be
                                              const float* __restrict__ hm, const int* __restrict__ sc,
                                              const uint4* st, uint4* next2, const uint4 (&a)[CB][G::HU],
                                              const floatx16 (&cinit)[CB], const int (&sa)[CB],
-                                             float (&acc_sum)[CB][16], double& lo_sum, floatx16 (&prev)[CB],
-                                             float& prev_lo, float& prev_hi, bool& pending) {
+                                             float (&acc_sum)[CB][16],
+                                             floatx16 (&prev)[CB], float& prev_lo, float& prev_hi, bool& pending) {
     using T = Lp<DT>;
     constexpr int HU = G::HU, VT = G::VT;
     constexpr int NMF = KC * CB;            // matrix instructions per column block
@@ -182,7 +189,6 @@ __device__ __forceinline__ void lp_tile_pipe(int64_t t, int64_t nt, int64_t t_be
         const float hav = st_ha[vrow];
         const float lo = -hav, hi = st_hm[vrow] - hav;
         const int sb = G::kFp8 ? st_sc[vrow] : 127;
-        lo_sum += double(lo);
         floatx16 acc[CB];
 #pragma unroll
         for (int cb = 0; cb < CB; ++cb) acc[cb] = cinit[cb];
@@ -193,10 +199,7 @@ __device__ __forceinline__ void lp_tile_pipe(int64_t t, int64_t nt, int64_t t_be
                 acc[cb] = mfma_main<DT>(&a[cb][q * T::kU4], &b[q * T::kU4], acc[cb], sa[cb], sb);
         if (pending) {
 #pragma unroll
-            for (int cb = 0; cb < CB; ++cb)
-#pragma unroll
-                for (int r = 0; r < 16; ++r)
-                    acc_sum[cb][r] += __builtin_amdgcn_fmed3f(prev[cb][r], prev_lo, prev_hi);
+            for (int cb = 0; cb < CB; ++cb) clamp_sum16(prev[cb], prev_lo, prev_hi, acc_sum[cb]);
         }
 #pragma unroll
         for (int i = 0; i < NMF; ++i) {
@@ -223,12 +226,13 @@ __device__ __forceinline__ void load_candidates(const GainsArgs& ga, int64_t wba
 #pragma unroll
     for (int cb = 0; cb < CB; ++cb) {
         const int64_t cpos = wbase + cb * 32 + col;
-        int64_t crow = -1;
+        int64_t crow = -1;  // slot of the candidate's row (its row without the grouped order)
         if (cpos < n_cand) crow = cand ? int64_t(cand[cpos]) : cpos;
         if (crow >= n_pad || (cpos < n_cand && crow < 0)) {
             atomicCAS(ga.err, 0, kDevErrIndex);
             crow = -1;
         }
+        if (crow >= 0 && cand && ga.inv) crow = ga.inv[crow];
         if (crow >= 0) {
             const uint4* src = xqt + (crow / VT) * (RU * VT) + (crow % VT);
 #pragma unroll
@@ -245,8 +249,11 @@ __device__ __forceinline__ void load_candidates(const GainsArgs& ga, int64_t wba
             const int64_t p = wbase + cb * 32 + 8 * (r / 4) + 4 * half + (r % 4);
             float v = 0.0f;
             if (p < n_cand) {
-                const int64_t row = cand ? int64_t(cand[p]) : p;
-                if (row >= 0 && row < n_pad) v = ga.hn[row];
+                int64_t row = cand ? int64_t(cand[p]) : p;
+                if (row >= 0 && row < n_pad) {
+                    if (cand && ga.inv) row = ga.inv[row];
+                    v = ga.hn[row];
+                }
             }
             cinit[cb][r] = -v;
         }
@@ -254,17 +261,16 @@ __device__ __forceinline__ void load_candidates(const GainsArgs& ga, int64_t wba
 }
 
 // float64 sums over the 32 columns of each half; one lane per row writes.
-// Each lane first removes the lower bounds of its own columns (its sum of
-// -ha_v), then the sum runs over the columns.
+// In the grouped order (all candidates, no list) a slot's sum goes to its row.
 template <int CB>
 __device__ __forceinline__ void store_partials(const GainsArgs& ga, int64_t wbase, int split, int col, int half,
-                                               const float (&acc_sum)[CB][16], double lo_sum) {
+                                               const float (&acc_sum)[CB][16]) {
 #pragma unroll
     for (int cb = 0; cb < CB; ++cb) {
         double mine = 0.0;
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
-            double v = double(acc_sum[cb][r]) - lo_sum;
+            double v = double(acc_sum[cb][r]);
 #pragma unroll
             for (int off = 16; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
             if (col == r) mine = v;
@@ -272,7 +278,10 @@ __device__ __forceinline__ void store_partials(const GainsArgs& ga, int64_t wbas
         if (col < 16) {
             const int r = col;
             const int64_t p = wbase + cb * 32 + 8 * (r / 4) + 4 * half + (r % 4);
-            if (p < ga.n_cand) ga.part[int64_t(split) * ga.part_stride + p] = 2.0 * mine;
+            if (p < ga.n_cand) {
+                const int64_t at = (ga.perm && !ga.cand) ? int64_t(ga.perm[p]) : p;
+                ga.part[int64_t(split) * ga.part_stride + at] = 2.0 * mine;
+            }
         }
     }
 }
@@ -313,7 +322,6 @@ __device__ __forceinline__ void gains_lp_body(const GainsArgs& ga, int64_t bid) 
     for (int cb = 0; cb < CB; ++cb)
 #pragma unroll
         for (int r = 0; r < 16; ++r) acc_sum[cb][r] = 0.0f;
-    double lo_sum = 0.0;  // this lane's sum of -ha_v over its columns
 
     // ---- stream the ground-set chunk through the LDS ring ----
     const int64_t v_begin = int64_t(split) * chunk;
@@ -333,34 +341,32 @@ __device__ __forceinline__ void gains_lp_body(const GainsArgs& ga, int64_t bid) 
         bool pending = false;
         for (int64_t t = 0; t < nt; t += 3) {
             lp_tile_pipe<G, DT, KC, CB>(t, nt, t_begin, wave, lane, col, half, xqt, ha, hm, sc, lds0, lds2, a,
-                                        cinit, sa, acc_sum, lo_sum, prev, prev_lo, prev_hi, pending);
+                                        cinit, sa, acc_sum, prev, prev_lo, prev_hi, pending);
             if (t + 1 < nt)
                 lp_tile_pipe<G, DT, KC, CB>(t + 1, nt, t_begin, wave, lane, col, half, xqt, ha, hm, sc, lds1, lds0,
-                                            a, cinit, sa, acc_sum, lo_sum, prev, prev_lo, prev_hi, pending);
+                                            a, cinit, sa, acc_sum, prev, prev_lo, prev_hi, pending);
             if (t + 2 < nt)
                 lp_tile_pipe<G, DT, KC, CB>(t + 2, nt, t_begin, wave, lane, col, half, xqt, ha, hm, sc, lds2, lds1,
-                                            a, cinit, sa, acc_sum, lo_sum, prev, prev_lo, prev_hi, pending);
+                                            a, cinit, sa, acc_sum, prev, prev_lo, prev_hi, pending);
         }
         if (pending) {
 #pragma unroll
-            for (int cb = 0; cb < CB; ++cb)
-#pragma unroll
-                for (int r = 0; r < 16; ++r) acc_sum[cb][r] += __builtin_amdgcn_fmed3f(prev[cb][r], prev_lo, prev_hi);
+            for (int cb = 0; cb < CB; ++cb) clamp_sum16(prev[cb], prev_lo, prev_hi, acc_sum[cb]);
         }
     } else {
         for (int64_t t = 0; t < nt; t += 3) {
             lp_tile<G, DT, KC, CB>(t, nt, t_begin, wave, lane, col, half, xqt, ha, hm, sc, lds0, lds2, a, cinit, sa,
-                                   acc_sum, lo_sum);
+                                   acc_sum);
             if (t + 1 < nt)
                 lp_tile<G, DT, KC, CB>(t + 1, nt, t_begin, wave, lane, col, half, xqt, ha, hm, sc, lds1, lds0, a,
-                                       cinit, sa, acc_sum, lo_sum);
+                                       cinit, sa, acc_sum);
             if (t + 2 < nt)
                 lp_tile<G, DT, KC, CB>(t + 2, nt, t_begin, wave, lane, col, half, xqt, ha, hm, sc, lds2, lds1, a,
-                                       cinit, sa, acc_sum, lo_sum);
+                                       cinit, sa, acc_sum);
         }
     }
 
-    store_partials<CB>(ga, wbase, split, col, half, acc_sum, lo_sum);
+    store_partials<CB>(ga, wbase, split, col, half, acc_sum);
 }
 
 // ---------------------------------------------------------------------------
@@ -421,10 +427,9 @@ __device__ __forceinline__ void mfma_tile(const TileRegs<G>& r, const uint4 (&a)
 
 template <int NCB, int CB>
 __device__ __forceinline__ void epilogue_tile(const floatx16 (&acc)[NCB][CB], const float (&lo)[NCB],
-                                              const float (&hi)[NCB], float (&acc_sum)[CB][16], double& lo_sum) {
+                                              const float (&hi)[NCB], float (&acc_sum)[CB][16]) {
 #pragma unroll
     for (int colb = 0; colb < NCB; ++colb) {
-        lo_sum += double(lo[colb]);
 #pragma unroll
         for (int cb = 0; cb < CB; ++cb) clamp_sum16(acc[colb][cb], lo[colb], hi[colb], acc_sum[cb]);
     }
@@ -445,8 +450,7 @@ __device__ __forceinline__ void pp_lead(int64_t t, int64_t nt, int64_t t_begin, 
                                         const uint4* __restrict__ xqt, const float* __restrict__ ha,
                                         const float* __restrict__ hm, const int* __restrict__ sc, const uint4* nxt,
                                         uint4* nx2, TileRegs<G>& r, const uint4 (&a)[CB][G::HU],
-                                        const floatx16 (&cinit)[CB], const int (&sa)[CB], float (&acc_sum)[CB][16],
-                                        double& lo_sum) {
+                                        const floatx16 (&cinit)[CB], const int (&sa)[CB], float (&acc_sum)[CB][16]) {
     constexpr int NCB = TileRegs<G>::NCB;
     if (t + 2 < nt) copy_stage<G>(wave, lane, t_begin + t + 2, xqt, ha, hm, sc, nx2);
     floatx16 acc[NCB][CB];
@@ -471,7 +475,7 @@ __device__ __forceinline__ void pp_lead(int64_t t, int64_t nt, int64_t t_begin, 
     phase_barrier();
     __builtin_amdgcn_s_setprio(0);
     if (t + 1 < nt) read_tile<G>(nxt, col, half, r);
-    epilogue_tile<NCB, CB>(acc, lo, hi, acc_sum, lo_sum);
+    epilogue_tile<NCB, CB>(acc, lo, hi, acc_sum);
     phase_barrier();
 }
 
@@ -480,7 +484,7 @@ __device__ __forceinline__ void pp_lead(int64_t t, int64_t nt, int64_t t_begin, 
 template <class G, int DT, int KC, int CB>
 __device__ __forceinline__ void pp_follow(int64_t t, int64_t nt, int col, int half, const uint4* nxt, TileRegs<G>& r,
                                           const uint4 (&a)[CB][G::HU], const floatx16 (&cinit)[CB],
-                                          const int (&sa)[CB], float (&acc_sum)[CB][16], double& lo_sum) {
+                                          const int (&sa)[CB], float (&acc_sum)[CB][16]) {
     constexpr int NCB = TileRegs<G>::NCB;
     floatx16 acc[NCB][CB];
     // the whole matrix phase at raised priority (lowered after the barrier
@@ -497,7 +501,7 @@ __device__ __forceinline__ void pp_follow(int64_t t, int64_t nt, int col, int ha
     phase_barrier();
     __builtin_amdgcn_s_setprio(0);
     if (t + 1 < nt) read_tile<G>(nxt, col, half, r);
-    epilogue_tile<NCB, CB>(acc, lo, hi, acc_sum, lo_sum);
+    epilogue_tile<NCB, CB>(acc, lo, hi, acc_sum);
     if (t + 1 < nt) phase_barrier();
 }
 
@@ -535,7 +539,6 @@ __device__ __forceinline__ void gains_lp_pp_body(const GainsArgs& ga, int64_t bi
     for (int cb = 0; cb < CB; ++cb)
 #pragma unroll
         for (int r = 0; r < 16; ++r) acc_sum[cb][r] = 0.0f;
-    double lo_sum = 0.0;
 
     const int64_t v_begin = int64_t(split) * ga.chunk;
     int64_t v_end = v_begin + ga.chunk;
@@ -557,13 +560,13 @@ __device__ __forceinline__ void gains_lp_pp_body(const GainsArgs& ga, int64_t bi
         if (nt > 0) read_tile<G>(lds0, col, half, r);
         for (int64_t t = 0; t < nt; t += 3) {
             pp_lead<G, DT, KC, CB>(t, nt, t_begin, w4, lane, col, half, xqt, ha, hm, sc, lds1, lds2, r, a, cinit, sa,
-                                   acc_sum, lo_sum);
+                                   acc_sum);
             if (t + 1 < nt)
                 pp_lead<G, DT, KC, CB>(t + 1, nt, t_begin, w4, lane, col, half, xqt, ha, hm, sc, lds2, lds0, r, a,
-                                       cinit, sa, acc_sum, lo_sum);
+                                       cinit, sa, acc_sum);
             if (t + 2 < nt)
                 pp_lead<G, DT, KC, CB>(t + 2, nt, t_begin, w4, lane, col, half, xqt, ha, hm, sc, lds0, lds1, r, a,
-                                       cinit, sa, acc_sum, lo_sum);
+                                       cinit, sa, acc_sum);
         }
     } else {
         // following group, one phase behind: barriers B0 + 1 + 2 per tile - 1
@@ -572,13 +575,15 @@ __device__ __forceinline__ void gains_lp_pp_body(const GainsArgs& ga, int64_t bi
             read_tile<G>(lds0, col, half, r);
             phase_barrier();  // end of phase 0 (the leading group's first matrix phase)
             for (int64_t t = 0; t < nt; t += 3) {
-                pp_follow<G, DT, KC, CB>(t, nt, col, half, lds1, r, a, cinit, sa, acc_sum, lo_sum);
-                if (t + 1 < nt) pp_follow<G, DT, KC, CB>(t + 1, nt, col, half, lds2, r, a, cinit, sa, acc_sum, lo_sum);
-                if (t + 2 < nt) pp_follow<G, DT, KC, CB>(t + 2, nt, col, half, lds0, r, a, cinit, sa, acc_sum, lo_sum);
+                pp_follow<G, DT, KC, CB>(t, nt, col, half, lds1, r, a, cinit, sa, acc_sum);
+                if (t + 1 < nt)
+                    pp_follow<G, DT, KC, CB>(t + 1, nt, col, half, lds2, r, a, cinit, sa, acc_sum);
+                if (t + 2 < nt)
+                    pp_follow<G, DT, KC, CB>(t + 2, nt, col, half, lds0, r, a, cinit, sa, acc_sum);
             }
         }
     }
-    store_partials<CB>(ga, wbase, split, col, half, acc_sum, lo_sum);
+    store_partials<CB>(ga, wbase, split, col, half, acc_sum);
 }
 
 template <int DT, int KC, int CB>

@@ -62,6 +62,8 @@ void fill_desc(const ebc_dataset* ds, int32_t k, int32_t* sel, double* f, double
     c.t0 = 0;
     c.dt = int32_t(ds->dt);
     c.variant = ds->variant;
+    c.metric = ds->metric;
+    c.pad_m = 0;
     c.chunk = gains_chunk(ds);
     c.sel = sel;
     c.f = f;
@@ -126,6 +128,17 @@ Layout layout(int64_t n, int32_t d, ebc_dtype dt) {
     L.off_rpart = take(size_t(wide_rows(kp) ? 4 * nb : nb) * kWindowMax * sizeof(double));
     L.off_fpart = take(size_t(nb) * sizeof(double));
     L.off_state = take(sizeof(DevState));
+    if (grouped(kp, dt)) {
+        L.off_perm = take(size_t(np) * sizeof(int32_t));
+        L.off_inv = take(size_t(np) * sizeof(int32_t));
+        L.off_xqp = take(size_t(np) * kp * elem_bytes(dt));
+        L.off_hnp = take(size_t(np) * sizeof(float));
+        L.off_hap = take(size_t(np) * sizeof(float));
+        L.off_hmp = take(size_t(np) * sizeof(float));
+        L.off_scp = dt == EBC_DT_FP8_E4M3 ? take(size_t(np) * sizeof(int)) : 0;
+        L.off_gbucket = take(size_t(np) * sizeof(int32_t));
+        L.off_gcount = take(size_t(np / kBlock) * group_count(n) * sizeof(int32_t));
+    }
     L.total = o;
     return L;
 }
@@ -226,6 +239,55 @@ __global__ void __launch_bounds__(kBlock) k_prep(const float* __restrict__ x, in
     }
 }
 
+// L1 datasets: one thread per padded row. The L1 kernels read the caller's
+// float32 rows directly, so no distance-dtype copy is written; the float64
+// d(v, 0) = sum_k |v_k| gives the initial state m_v and L({e0}), and the
+// finiteness check is the same as for the squared distance.
+__global__ void __launch_bounds__(kBlock) k_prep_l1(const float* __restrict__ x, int64_t n, int32_t d, Buffers b) {
+    __shared__ double red[kBlock];
+    __shared__ double rmax[kBlock];
+    const int64_t r = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+    double nv = 0.0;
+    if (r < n) {
+        const float* xr = x + r * d;
+        bool bad = false;
+        for (int k = 0; k < d; ++k) {
+            const float v = xr[k];
+            bad |= !isfinite(v);
+            nv += fabs(double(v));
+        }
+        if (bad) atomicCAS(&b.state->error, 0, kDevErrNonFinite);
+        b.n64[r] = nv;
+        b.m0[r] = nv;
+        b.m64[r] = nv;
+        b.hn[r] = 0.0f;
+        b.selected[r] = 0;
+        set_point_terms(b, r, nv);
+    } else {
+        b.n64[r] = 0.0;
+        b.m0[r] = 0.0;
+        b.m64[r] = 0.0;
+        b.hn[r] = 0.0f;
+        b.ha[r] = 0.0f;
+        b.hm[r] = 0.0f;
+        b.selected[r] = 1;  // padding is never a candidate
+    }
+    red[threadIdx.x] = nv;
+    rmax[threadIdx.x] = nv;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) {
+            red[threadIdx.x] += red[threadIdx.x + w];
+            rmax[threadIdx.x] = fmax(rmax[threadIdx.x], rmax[threadIdx.x + w]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        b.fpart[blockIdx.x] = red[0];
+        b.bmax[blockIdx.x] = rmax[0];
+    }
+}
+
 // Reduced-precision copy: one thread per padded row. Exact float64 norm and
 // initial state as in k_prep, then the row (long rows: centred at the column
 // means) cast with round-to-nearest-even
@@ -298,7 +360,9 @@ __global__ void __launch_bounds__(kBlock) k_prep_lp(const float* __restrict__ x,
         b.m0[r] = nv;
         b.m64[r] = nv;
         b.selected[r] = 0;
-        set_point_terms(b, r, nv);
+        Buffers own = b;  // the grouped order does not exist yet: k_group_copy fills the slot-order terms
+        own.inv = nullptr;
+        set_point_terms(own, r, nv);
     } else {
         const int eb = dt == EBC_DT_FP8_E4M3 ? 1 : 2;
         const int ru = kp * eb / 16;
@@ -327,6 +391,129 @@ __global__ void __launch_bounds__(kBlock) k_prep_lp(const float* __restrict__ x,
         b.fpart[blockIdx.x] = red[0];
         b.bmax[blockIdx.x] = rmax[0];
     }
+}
+
+// ---- grouped order of the reduced-precision gains ----
+// The ground set is sorted by nearest pivot (pivot j = row j * (n / G) of V,
+// G = group_count(n) pivots; squared Euclidean distance in float32 on the
+// caller's rows, ties to the lowest pivot), stably (equal pivots keep row
+// order), so the order is a deterministic function of V. The gains kernel
+// then walks candidates and points in this slot order; a pair's distance and
+// a candidate's gain do not depend on the order, only which 32 x 32 tiles
+// group them (and so the float32 summation order of each gain) does.
+constexpr int kPivChunk = 32;  // pivots staged in LDS at a time
+
+template <int KP>
+__global__ void __launch_bounds__(kBlock) k_group_assign(const float* __restrict__ x, int64_t n, int32_t d,
+                                                         int32_t groups, Buffers b) {
+    __shared__ float piv[kPivChunk][KP];
+    const int64_t v = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+    const bool live = v < n;
+    float xv[KP];
+#pragma unroll
+    for (int k = 0; k < KP; ++k) xv[k] = (live && k < d) ? x[v * d + k] : 0.0f;
+    const int64_t stride = n / groups;
+    float best = INFINITY;
+    int arg = 0;
+    for (int j0 = 0; j0 < groups; j0 += kPivChunk) {
+        const int jn = (groups - j0) < kPivChunk ? (groups - j0) : kPivChunk;
+        __syncthreads();
+        for (int e = threadIdx.x; e < kPivChunk * KP; e += kBlock) {
+            const int j = e / KP, k = e % KP;
+            piv[j][k] = (j < jn && k < d) ? x[int64_t(j0 + j) * stride * d + k] : 0.0f;
+        }
+        __syncthreads();
+        for (int j = 0; j < jn; ++j) {
+            float s = 0.0f;
+#pragma unroll
+            for (int k = 0; k < KP; ++k) {
+                const float t = xv[k] - piv[j][k];
+                s = fmaf(t, t, s);
+            }
+            if (s < best) {
+                best = s;
+                arg = j0 + j;
+            }
+        }
+    }
+    b.gbucket[v] = live ? arg : -1;
+}
+
+// Per block of 256 rows: how many rows of the block fall in each bucket.
+__global__ void __launch_bounds__(kBlock) k_group_count(int32_t groups, Buffers b) {
+    __shared__ int hist[256];
+    hist[threadIdx.x] = 0;
+    __syncthreads();
+    const int g = b.gbucket[int64_t(blockIdx.x) * kBlock + threadIdx.x];
+    if (g >= 0) atomicAdd(&hist[g], 1);
+    __syncthreads();
+    if (int(threadIdx.x) < groups) b.gcount[int64_t(blockIdx.x) * groups + threadIdx.x] = hist[threadIdx.x];
+}
+
+// One workgroup: bucket totals, their exclusive prefix (bucket-major slot
+// ranges), then each (block, bucket) count replaced by its first slot.
+__global__ void __launch_bounds__(kBlock) k_group_scan(int32_t nblocks, int32_t groups, Buffers b) {
+    __shared__ int tot[256];
+    const int g = threadIdx.x;
+    int t = 0;
+    if (g < groups)
+        for (int blk = 0; blk < nblocks; ++blk) t += b.gcount[int64_t(blk) * groups + g];
+    tot[g] = t;
+    __syncthreads();
+    if (g == 0) {
+        int run = 0;
+        for (int q = 0; q < 256; ++q) {
+            const int c = tot[q];
+            tot[q] = run;
+            run += c;
+        }
+    }
+    __syncthreads();
+    if (g < groups) {
+        int run = tot[g];
+        for (int blk = 0; blk < nblocks; ++blk) {
+            const int64_t i = int64_t(blk) * groups + g;
+            const int c = b.gcount[i];
+            b.gcount[i] = run;
+            run += c;
+        }
+    }
+}
+
+// Slots: a row's slot is its (block, bucket) offset plus the number of
+// earlier rows of the block in the same bucket (stable). Padding rows keep
+// their own index.
+__global__ void __launch_bounds__(kBlock) k_group_place(int64_t n, int32_t groups, Buffers b) {
+    __shared__ int lb[kBlock];
+    const int64_t v = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+    const int g = b.gbucket[v];
+    lb[threadIdx.x] = g;
+    __syncthreads();
+    if (v >= n) {
+        b.perm[v] = int32_t(v);
+        b.inv[v] = int32_t(v);
+        return;
+    }
+    int rank = 0;
+    for (int t = 0; t < int(threadIdx.x); ++t) rank += lb[t] == g ? 1 : 0;
+    const int32_t slot = b.gcount[int64_t(blockIdx.x) * groups + g] + rank;
+    b.perm[slot] = int32_t(v);
+    b.inv[v] = slot;
+}
+
+// Slot-order copies: row perm[s] of the tiled distance-dtype copy (all of
+// its 16-byte units) and its per-row terms go to slot s.
+__global__ void __launch_bounds__(kBlock) k_group_copy(int32_t row_units, int32_t fp8, Buffers b) {
+    const int64_t s = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+    const int64_t r = b.perm[s];
+    const uint4* __restrict__ src = reinterpret_cast<const uint4*>(b.xq);
+    uint4* __restrict__ dst = reinterpret_cast<uint4*>(b.xqp);
+    for (int u = 0; u < row_units; ++u)
+        dst[(s / 64 * row_units + u) * 64 + s % 64] = src[(r / 64 * row_units + u) * 64 + r % 64];
+    b.hnp[s] = b.hn[r];
+    b.hap[s] = b.ha[r];
+    b.hmp[s] = b.hm[r];
+    if (fp8) b.scp[s] = b.scale[r];
 }
 
 // Long rows: one workgroup of 16 waves per 64-row tile. Lane = row of the
@@ -569,6 +756,11 @@ __global__ void k_state_init(DevState* st) {
 hipError_t launch_prep(const ebc_dataset* ds, hipStream_t s) {
     const int nb = int(ds->n_pad / kBlock);
     hipLaunchKernelGGL(k_state_init, dim3(1), dim3(64), 0, s, ds->b.state);
+    if (ds->metric == 1) {
+        hipLaunchKernelGGL(k_prep_l1, dim3(nb), dim3(kBlock), 0, s, ds->x, ds->n, ds->d, ds->b);
+        hipLaunchKernelGGL(k_l0, dim3(1), dim3(kBlock), 0, s, ds->n, nb, ds->b);
+        return hipGetLastError();
+    }
     if (ds->b.mu)
         hipLaunchKernelGGL(k_colmean, dim3(unsigned((ds->k_pad + 63) / 64)), dim3(1024), 0, s, ds->x, ds->n, ds->d,
                            ds->k_pad, ds->b.mu);
@@ -595,6 +787,26 @@ hipError_t launch_prep(const ebc_dataset* ds, hipStream_t s) {
     else
         hipLaunchKernelGGL(k_prep_lp, dim3(nb), dim3(kBlock), 0, s, ds->x, ds->n, ds->d, ds->k_pad, int(ds->dt),
                            ds->b);
+    if (ds->b.perm) {
+        const int32_t groups = group_count(ds->n);
+        const int kp8 = (ds->d + 7) / 8 * 8;  // float32 row length held in registers
+        switch (kp8) {
+#define EBC_GA(K)                                                                                             \
+    case K:                                                                                                   \
+        hipLaunchKernelGGL(k_group_assign<K>, dim3(nb), dim3(kBlock), 0, s, ds->x, ds->n, ds->d, groups, ds->b); \
+        break;
+            EBC_GA(8) EBC_GA(16) EBC_GA(24) EBC_GA(32) EBC_GA(40) EBC_GA(48) EBC_GA(56) EBC_GA(64)
+            EBC_GA(72) EBC_GA(80) EBC_GA(88) EBC_GA(96) EBC_GA(104) EBC_GA(112) EBC_GA(120) EBC_GA(128)
+#undef EBC_GA
+            default: return hipErrorInvalidValue;
+        }
+        hipLaunchKernelGGL(k_group_count, dim3(nb), dim3(kBlock), 0, s, groups, ds->b);
+        hipLaunchKernelGGL(k_group_scan, dim3(1), dim3(kBlock), 0, s, nb, groups, ds->b);
+        hipLaunchKernelGGL(k_group_place, dim3(nb), dim3(kBlock), 0, s, ds->n, groups, ds->b);
+        const int32_t row_units = ds->k_pad * elem_bytes(ds->dt) / 16;
+        hipLaunchKernelGGL(k_group_copy, dim3(nb), dim3(kBlock), 0, s, row_units,
+                           int32_t(ds->dt == EBC_DT_FP8_E4M3), ds->b);
+    }
     hipLaunchKernelGGL(k_l0, dim3(1), dim3(kBlock), 0, s, ds->n, nb, ds->b);
     return hipGetLastError();
 }
@@ -647,7 +859,7 @@ hipError_t launch_reset_batched(const InstDesc* descs, const int64_t* row_pre, i
 // ||v||^2), with per-block sums and maxima for L({e0}); a non-finite e0
 // raises EBC_E_NONFINITE.
 __global__ void __launch_bounds__(kBlock) k_set_e0(const float* __restrict__ x, int64_t n, int32_t d,
-                                                   const float* __restrict__ e0, Buffers b) {
+                                                   const float* __restrict__ e0, int32_t metric, Buffers b) {
     __shared__ float ce[EBC_MAX_DIM];
     __shared__ double red[kBlock];
     __shared__ double rmax[kBlock];
@@ -667,7 +879,7 @@ __global__ void __launch_bounds__(kBlock) k_set_e0(const float* __restrict__ x, 
             const float* xr = x + r * d;
             for (int k = 0; k < d; ++k) {
                 const double t = double(xr[k]) - double(ce[k]);
-                mv += t * t;
+                mv += metric == 1 ? fabs(t) : t * t;  // d(v, e0): L1 or squared Euclidean
             }
         } else {
             mv = b.n64[r];
@@ -693,7 +905,7 @@ __global__ void __launch_bounds__(kBlock) k_set_e0(const float* __restrict__ x, 
 
 hipError_t launch_set_e0(const ebc_dataset* ds, const float* e0, hipStream_t s) {
     const int nb = int(ds->n_pad / kBlock);
-    hipLaunchKernelGGL(k_set_e0, dim3(nb), dim3(kBlock), 0, s, ds->x, ds->n, ds->d, e0, ds->b);
+    hipLaunchKernelGGL(k_set_e0, dim3(nb), dim3(kBlock), 0, s, ds->x, ds->n, ds->d, e0, ds->metric, ds->b);
     hipLaunchKernelGGL(k_l0, dim3(1), dim3(kBlock), 0, s, ds->n, nb, ds->b);
     return launch_reset_state(ds, s);
 }

@@ -51,8 +51,15 @@ __device__ inline float e4m3_to_f32(uint8_t b) {
 // Refresh the float32 terms of ground point v after its running minimum
 // changed to mv: hm = mv/2 and ha = mv/2 - hn.
 __device__ inline void set_point_terms(const Buffers& b, int64_t v, double mv) {
-    b.ha[v] = float(0.5 * mv - double(b.hn[v]));
-    b.hm[v] = float(0.5 * mv);
+    const float ha = float(0.5 * mv - double(b.hn[v]));
+    const float hm = float(0.5 * mv);
+    b.ha[v] = ha;
+    b.hm[v] = hm;
+    if (b.inv) {  // grouped order: the slot-order copies follow
+        const int32_t s = b.inv[v];
+        b.hap[s] = ha;
+        b.hmp[s] = hm;
+    }
 }
 
 }  // namespace ebc

@@ -171,9 +171,9 @@ __device__ void wselect_body(const InstDesc& c) {
 // fixed order.
 constexpr int kRescoreGroup = 8;
 constexpr int kRescoreChunk = 512;
-__device__ void rescore_body(const InstDesc& c, int64_t blk) {
-    __shared__ float cx[kRescoreGroup * kRescoreChunk];
-    __shared__ double red[kRescoreGroup][kBlock];
+// METRIC 0: squared Euclidean (the paper's d); 1: L1, sum of |x_vk - x_ck|.
+template <int METRIC>
+__device__ void rescore_impl(const InstDesc& c, int64_t blk, float* __restrict__ cx, double (*red)[kBlock]) {
     const Buffers& b = c.b;
     const float* __restrict__ x = c.x;
     const int d = c.d;
@@ -201,7 +201,10 @@ __device__ void rescore_body(const InstDesc& c, int64_t blk) {
 #pragma unroll
                     for (int j = 0; j < kRescoreGroup; ++j) {
                         const double t = xk - double(cx[j * kRescoreChunk + k]);
-                        acc[j] = fma(t, t, acc[j]);
+                        if (METRIC == 1)
+                            acc[j] += fabs(t);
+                        else
+                            acc[j] = fma(t, t, acc[j]);
                     }
                 }
             }
@@ -218,6 +221,15 @@ __device__ void rescore_body(const InstDesc& c, int64_t blk) {
         }
         if (threadIdx.x < gn) b.rpart[blk * kWindowMax + g0 + threadIdx.x] = red[threadIdx.x][0];
     }
+}
+
+__device__ void rescore_body(const InstDesc& c, int64_t blk) {
+    __shared__ float cx[kRescoreGroup * kRescoreChunk];
+    __shared__ double red[kRescoreGroup][kBlock];
+    if (c.metric == 1)
+        rescore_impl<1>(c, blk, cx, red);
+    else
+        rescore_impl<0>(c, blk, cx, red);
 }
 
 __device__ __forceinline__ int rescore_rows(const InstDesc& c, int W);
@@ -279,6 +291,27 @@ __device__ void pick_body(const InstDesc& c, int32_t t) {
         }
         __syncthreads();
     }
+    if (W > 0 && sg[0] == 0.0) {
+        // The best float64 gain of the window is 0: every point is covered, so
+        // every unselected point has gain 0 and the pick is the lowest
+        // unselected index (also when more zero-gain candidates than the
+        // window holds were ranked by their reduced-precision gains).
+        __shared__ int lowest[kBlock];
+        int lo = 0x7fffffff;
+        for (int64_t i = threadIdx.x; i < c.n; i += kBlock)
+            if (!b.selected[i]) {
+                lo = int(i);
+                break;
+            }
+        lowest[j] = lo;
+        __syncthreads();
+        for (int w = kBlock / 2; w > 0; w >>= 1) {
+            if (j < w && lowest[j + w] < lowest[j]) lowest[j] = lowest[j + w];
+            __syncthreads();
+        }
+        if (j == 0 && lowest[0] != 0x7fffffff) si[0] = lowest[0];
+        __syncthreads();
+    }
     if (j == 0) {
         const int cs = si[0];
         if (W > 0 && cs >= 0 && int64_t(cs) < c.n) {
@@ -320,6 +353,46 @@ __device__ void update_body(const InstDesc& c, int64_t blk) {
         }
         mv = b.m64[v];
         if (acc < mv) {
+            mv = acc;
+            b.m64[v] = mv;
+            set_point_terms(b, v, mv);
+        }
+    }
+    red[threadIdx.x] = mv;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) b.fpart[blk] = red[0];
+}
+
+// ---- L1 update (any row length): m_v <- min(m_v, sum_k |x_vk - x_c*k|) in
+// float64, the new member's values staged in LDS 512 at a time; per-block
+// sums of m_v as in update_body ----
+__device__ void update_l1_body(const InstDesc& c, int64_t blk) {
+    __shared__ float cx[kRescoreChunk];
+    __shared__ double red[kBlock];
+    const Buffers& b = c.b;
+    const float* __restrict__ x = c.x;
+    const int d = c.d;
+    const int cs = b.state->cstar;
+    const int64_t v = blk * kBlock + threadIdx.x;
+    const bool live = v < c.n;
+    const float* xv = x + (live ? v : 0) * d;
+    double acc = 0.0;
+    for (int k0 = 0; k0 < d && cs >= 0; k0 += kRescoreChunk) {
+        const int kn = (d - k0) < kRescoreChunk ? (d - k0) : kRescoreChunk;
+        __syncthreads();
+        for (int k = threadIdx.x; k < kn; k += kBlock) cx[k] = x[int64_t(cs) * d + k0 + k];
+        __syncthreads();
+        if (live)
+            for (int k = 0; k < kn; ++k) acc += fabs(double(xv[k0 + k]) - double(cx[k]));
+    }
+    double mv = 0.0;
+    if (live) {
+        mv = b.m64[v];
+        if (cs >= 0 && acc < mv) {
             mv = acc;
             b.m64[v] = mv;
             set_point_terms(b, v, mv);
@@ -546,7 +619,10 @@ __device__ void update_long_body(const InstDesc& c, int64_t blk) {
 // of a step, at part[q * n_pad + v]. Pass 2 adds the slices in order. The
 // update takes one slice per chunk (up to 16); small re-score windows share
 // the chunks among their candidates.
-__host__ __device__ inline bool long_split(const InstDesc& c) { return wide_rows(c.k_pad) && c.v_splits >= 4; }
+// Long rows take the long-row re-score and update kernels under the squared
+// distance; L1 datasets take the generic ones (any row length) at every d.
+__host__ __device__ inline bool long_path(const InstDesc& c) { return wide_rows(c.k_pad) && c.metric == 0; }
+__host__ __device__ inline bool long_split(const InstDesc& c) { return long_path(c) && c.v_splits >= 4; }
 __host__ __device__ inline int update_slices(const InstDesc& c) { return c.v_splits < 16 ? c.v_splits : 16; }
 __device__ __forceinline__ int long_slice(int d, int S) { return ((d + S - 1) / S + 3) / 4 * 4; }
 __device__ __forceinline__ int long_quarter(int d) { return long_slice(d, 4); }
@@ -634,7 +710,7 @@ __device__ __forceinline__ int window_slices(const InstDesc& c, int W) {
 // rpart rows a re-score of W candidates fills: one per 64-point sub-block
 // for the one-pass long-row re-score, one per row block otherwise
 __device__ __forceinline__ int rescore_rows(const InstDesc& c, int W) {
-    return (wide_rows(c.k_pad) && W > split_window(c)) ? 4 * c.nb : c.nb;
+    return (long_path(c) && W > split_window(c)) ? 4 * c.nb : c.nb;
 }
 
 __device__ void dist_window_body(const InstDesc& c, int64_t blk, int y) {
@@ -703,6 +779,7 @@ __global__ void __launch_bounds__(kSelThreads) k_wselect(InstDesc c) { wselect_b
 __global__ void __launch_bounds__(kBlock) k_rescore(InstDesc c) { rescore_body(c, blockIdx.x); }
 __global__ void __launch_bounds__(kBlock) k_pick(InstDesc c, int32_t t) { pick_body(c, t); }
 __global__ void __launch_bounds__(kBlock) k_update(InstDesc c) { update_body(c, blockIdx.x); }
+__global__ void __launch_bounds__(kBlock) k_update_l1(InstDesc c) { update_l1_body(c, blockIdx.x); }
 __global__ void __launch_bounds__(kBlock) k_rescore_long(InstDesc c) { rescore_long_body(c, blockIdx.x, blockIdx.y); }
 __global__ void __launch_bounds__(kBlock) k_update_long(InstDesc c) { update_long_body(c, blockIdx.x); }
 __global__ void __launch_bounds__(kBlock) k_dist_slices(InstDesc c) {
@@ -781,7 +858,11 @@ hipError_t launch_greedy_step(const ebc_dataset* ds, int32_t t, int32_t* sel_out
     hipLaunchKernelGGL(k_gsum, dim3(nb), dim3(kBlock), 0, s, c);
     hipLaunchKernelGGL(k_wcount, dim3(nb), dim3(kBlock), 0, s, c);
     hipLaunchKernelGGL(k_wselect, dim3(1), dim3(kSelThreads), 0, s, c);
-    if (wide_rows(c.k_pad)) {
+    if (c.metric == 1) {
+        hipLaunchKernelGGL(k_rescore, dim3(nb), dim3(kBlock), 0, s, c);
+        hipLaunchKernelGGL(k_pick, dim3(1), dim3(kBlock), 0, s, c, t);
+        hipLaunchKernelGGL(k_update_l1, dim3(nb), dim3(kBlock), 0, s, c);
+    } else if (wide_rows(c.k_pad)) {
         // small windows: pass 1 over slices of the dimension here, pass 2 inside k_rescore_long
         if (long_split(c)) hipLaunchKernelGGL(k_dist_window, dim3(nb, 16), dim3(kBlock), 0, s, c);
         hipLaunchKernelGGL(k_rescore_long, dim3(nb, 4 * kWindowMax / kRescoreGroup), dim3(kBlock), 0, s, c);
@@ -826,6 +907,7 @@ hipError_t launch_step_batched(const InstDesc* descs, const int64_t* row_pre, in
 }
 
 hipError_t launch_gains(const ebc_dataset* ds, const int32_t* cand, int64_t n_cand, hipStream_t s) {
+    if (ds->metric == 1) return launch_gains_l1(ds, cand, n_cand, s);
     if (wide_rows(ds->k_pad)) return launch_gains_wide(ds, cand, n_cand, s);
     return ds->dt == EBC_DT_F32 ? launch_gains_f32(ds, cand, n_cand, s) : launch_gains_lp(ds, cand, n_cand, s);
 }
@@ -875,7 +957,7 @@ hipError_t launch_gain64_many(const ebc_dataset* ds, const int32_t* items, int32
     InstDesc c;
     fill_desc(ds, 0, nullptr, nullptr, nullptr, &c);
     hipLaunchKernelGGL(k_many_stage, dim3(1), dim3(kWindowMax), 0, s, c, items, W);
-    if (wide_rows(c.k_pad)) {
+    if (long_path(c)) {
         // the list length is known here: launch only the re-score that takes it
         if (W <= split_window(c)) {  // small lists: two passes over slices of the dimension
             hipLaunchKernelGGL(k_dist_window, dim3(c.nb, 16), dim3(kBlock), 0, s, c);
@@ -895,7 +977,9 @@ hipError_t launch_accept_one(const ebc_dataset* ds, int32_t item, int32_t t, int
     InstDesc c;
     fill_desc(ds, t + 1, sel, f, gain, &c);
     hipLaunchKernelGGL(k_one_accept, dim3(1), dim3(64), 0, s, c, item, t);
-    if (long_split(c)) {
+    if (c.metric == 1) {
+        hipLaunchKernelGGL(k_update_l1, dim3(c.nb), dim3(kBlock), 0, s, c);
+    } else if (long_split(c)) {
         hipLaunchKernelGGL(k_dist_slices, dim3(c.nb, update_slices(c)), dim3(kBlock), 0, s, c);
         hipLaunchKernelGGL(k_update_split, dim3(c.nb), dim3(kBlock), 0, s, c);
     } else if (wide_rows(c.k_pad))

@@ -110,10 +110,42 @@ struct Gain64Cache {
     }
 };
 
-// The stream's indices on the host (validated) and on the device, in
-// `scratch` (device, stream-ordered) followed by `extra` bytes.
-ebc_status prepare_stream(const ebc_dataset* ds, const int32_t* order, int64_t n_order, size_t extra, hipStream_t s,
-                          std::vector<int32_t>& h_order, char** scratch, int32_t** d_order, char** d_extra) {
+size_t al256(size_t v) { return (v + 255) & ~size_t(255); }
+
+// Batch size a call uses: 0 selects 1024, and a stretch never exceeds n_pad.
+int32_t effective_batch(int64_t n_pad, int32_t batch) {
+    if (batch == 0) batch = 1024;
+    if (batch > n_pad) batch = int32_t(n_pad);
+    return batch;
+}
+
+bool valid_n(int64_t n) { return n >= 1 && n < (int64_t(1) << 31) - kRowAlign; }
+
+// Most guesses (1+eps)^i in [m, k m] for any m > 0: floor(log k / log(1+eps)) + 1,
+// plus one for rounding in the logarithms that place the grid ends.
+int64_t max_guesses(int32_t k, double eps) { return int64_t(floor(log(double(k)) / log1p(eps))) + 2; }
+
+// Device scratch of Three Sieves: stream indices, one stretch of gains, one re-score list.
+size_t three_sieves_scratch(int64_t n_order, int32_t batch) {
+    return al256(size_t(n_order) * sizeof(int32_t)) + al256(size_t(batch) * sizeof(double)) + kListBytes;
+}
+
+// Per summary of Sieve Streaming: m^v [n_pad] f64, gains of its stretch [batch]
+// f64, f [k] f64, members [k] i32.
+size_t sieve_summary_bytes(int64_t n_pad, int32_t k, int32_t batch) {
+    return al256(size_t(n_pad) * sizeof(double)) + al256(size_t(batch) * sizeof(double)) +
+           al256(size_t(k) * sizeof(double)) + al256(size_t(k) * sizeof(int32_t));
+}
+
+size_t sieve_streaming_scratch(int64_t n_pad, int32_t k, double eps, int64_t n_order, int32_t batch) {
+    return al256(size_t(n_order) * sizeof(int32_t)) +
+           size_t(max_guesses(k, eps)) * sieve_summary_bytes(n_pad, k, batch) + kListBytes;
+}
+
+// The stream's indices on the host (validated) and on the device, at the
+// start of the caller's scratch; *d_extra is the scratch after them.
+ebc_status prepare_stream(const ebc_dataset* ds, const int32_t* order, int64_t n_order, char* scratch, hipStream_t s,
+                          std::vector<int32_t>& h_order, int32_t** d_order, char** d_extra) {
     h_order.assign(static_cast<size_t>(n_order), 0);
     if (order && n_order > 0) {
         if (hipMemcpyAsync(h_order.data(), order, size_t(n_order) * sizeof(int32_t), hipMemcpyDeviceToHost, s) !=
@@ -125,14 +157,17 @@ ebc_status prepare_stream(const ebc_dataset* ds, const int32_t* order, int64_t n
     } else {
         for (int64_t i = 0; i < n_order; ++i) h_order[size_t(i)] = int32_t(i);
     }
-    const size_t ord_bytes = (size_t(n_order) * sizeof(int32_t) + 255) & ~size_t(255);
-    if (hipMallocAsync(reinterpret_cast<void**>(scratch), ord_bytes + extra, s) != hipSuccess) return EBC_E_DEVICE;
-    *d_order = reinterpret_cast<int32_t*>(*scratch);
-    *d_extra = *scratch + ord_bytes;
+    *d_order = reinterpret_cast<int32_t*>(scratch);
+    *d_extra = scratch + al256(size_t(n_order) * sizeof(int32_t));
     if (n_order > 0 && hipMemcpyAsync(*d_order, h_order.data(), size_t(n_order) * sizeof(int32_t),
                                       hipMemcpyHostToDevice, s) != hipSuccess)
         return EBC_E_DEVICE;
     return EBC_OK;
+}
+
+// Host checks shared by both optimisers' scratch arguments.
+bool scratch_ok(const void* scratch, size_t have, size_t need) {
+    return scratch && reinterpret_cast<uintptr_t>(scratch) % 256 == 0 && have >= need;
 }
 
 // S = {} in the dataset state; m = max_e f({e}) unless given (> 0): one
@@ -154,36 +189,35 @@ ebc_status start_stream(ebc_dataset* ds, double* m_max, int32_t* sel_tmp, double
 
 extern "C" {
 
+size_t ebc_three_sieves_bytes(int64_t n, int64_t n_order, int32_t batch) {
+    if (!valid_n(n) || n_order < 0 || batch < 0) return 0;
+    return three_sieves_scratch(n_order, effective_batch(pad_rows(n), batch));
+}
+
 ebc_status ebc_three_sieves(ebc_dataset* ds, int32_t k, double eps, int64_t T, double m_max, const int32_t* order,
                             int64_t n_order, int32_t batch, int32_t* sel_out, double* f_out, int32_t* count_out,
-                            int64_t* examined_out, void* stream) {
+                            int64_t* examined_out, void* scratch, size_t scratch_bytes, void* stream) {
     if (!ds || !count_out || k < 1 || int64_t(k) > ds->n || !(eps > 0.0) || T < 1 || batch < 0) return EBC_E_INVALID_ARG;
     if (!sel_out || !f_out || n_order < 0 || (!order && n_order > ds->n)) return EBC_E_INVALID_ARG;
     *count_out = 0;
     if (examined_out) *examined_out = 0;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    if (batch == 0) batch = 1024;
-    if (batch > ds->n_pad) batch = int32_t(ds->n_pad);
+    batch = effective_batch(ds->n_pad, batch);
+    if (!scratch_ok(scratch, scratch_bytes, three_sieves_scratch(n_order, batch))) return EBC_E_INVALID_ARG;
 
     std::vector<int32_t> h_order;
-    char* scratch = nullptr;
     int32_t* d_order = nullptr;
     char* d_extra = nullptr;
-    const size_t gain_bytes = (size_t(batch) * sizeof(double) + 255) & ~size_t(255);
-    ebc_status pst = prepare_stream(ds, order, n_order, gain_bytes + kListBytes, s, h_order, &scratch, &d_order,
-                                    &d_extra);
-    auto done = [&](ebc_status st) {
-        if (scratch) (void)hipFreeAsync(scratch, s);
-        return st;
-    };
-    if (pst != EBC_OK) return done(pst);
+    const size_t gain_bytes = al256(size_t(batch) * sizeof(double));
+    ebc_status pst = prepare_stream(ds, order, n_order, static_cast<char*>(scratch), s, h_order, &d_order, &d_extra);
+    if (pst != EBC_OK) return pst;
     double* d_gain = reinterpret_cast<double*>(d_extra);
     char* d_list = d_extra + gain_bytes;
     DevState st;
-    if ((pst = start_stream(ds, &m_max, sel_out, f_out, s, &st)) != EBC_OK) return done(pst);
-    if (st.error != 0) return done(EBC_OK);  // reported by ebc_sync_status
+    if ((pst = start_stream(ds, &m_max, sel_out, f_out, s, &st)) != EBC_OK) return pst;
+    if (st.error != 0) return EBC_OK;  // reported by ebc_sync_status
     const std::vector<double> grid = sieve_grid(m_max, k, eps);
-    if (grid.empty()) return done(EBC_OK);
+    if (grid.empty()) return EBC_OK;
     // Every gain is at most m (submodularity: Delta(e|S) <= f({e}) <= m), and
     // the dtype's gains are within window_tau * (largest gain) of float64, so
     // a point whose gain is more than 2 window_tau m away from its bound is
@@ -206,7 +240,7 @@ ebc_status ebc_three_sieves(ebc_dataset* ds, int32_t k, double eps, int64_t T, d
             hipMemcpyAsync(h_gain.data(), d_gain, size_t(cnt) * sizeof(double), hipMemcpyDeviceToHost, s) !=
                 hipSuccess ||
             hipStreamSynchronize(s) != hipSuccess)
-            return done(EBC_E_DEVICE);
+            return EBC_E_DEVICE;
         c64.clear();
         int64_t next = pos + cnt;
         for (int64_t i = 0; i < cnt && nsel < k; ++i) {
@@ -222,14 +256,14 @@ ebc_status ebc_three_sieves(ebc_dataset* ds, int32_t k, double eps, int64_t T, d
                 double g64 = 0.0;
                 if (c64.get(ds, h_gain.data(), h_order.data() + pos, i, cnt, lowest - tol, bound + tol,
                             pos + i + 1 - last, d_list, s, &g64) != hipSuccess)
-                    return done(EBC_E_DEVICE);
+                    return EBC_E_DEVICE;
                 take = g64 >= bound;
             }
             if (take) {
                 if (launch_accept_one(ds, item, nsel, sel_out, f_out, nullptr, s) != hipSuccess ||
                     hipMemcpyAsync(&fS, f_out + nsel, sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
                     hipStreamSynchronize(s) != hipSuccess)
-                    return done(EBC_E_DEVICE);
+                    return EBC_E_DEVICE;
                 ++nsel;
                 t = 0;
                 next = pos + i + 1;  // later gains are stale: rescore from the next point
@@ -248,22 +282,29 @@ ebc_status ebc_three_sieves(ebc_dataset* ds, int32_t k, double eps, int64_t T, d
     *count_out = nsel;
     if (examined_out) *examined_out = examined;
     ds->stats.steps = nsel;
-    return done(EBC_OK);
+    return EBC_OK;
+}
+
+size_t ebc_sieve_streaming_bytes(int64_t n, int32_t k, double eps, int64_t n_order, int32_t batch) {
+    if (!valid_n(n) || k < 1 || int64_t(k) > n || !(eps > 0.0) || n_order < 0 || batch < 0) return 0;
+    return sieve_streaming_scratch(pad_rows(n), k, eps, n_order, effective_batch(pad_rows(n), batch));
 }
 
 ebc_status ebc_sieve_streaming(ebc_dataset* ds, int32_t k, double eps, double m_max, const int32_t* order,
                                int64_t n_order, int32_t batch, int32_t* sel_out, double* f_out, int32_t* count_out,
-                               double* v_out, int64_t* examined_out, void* stream) {
+                               double* v_out, int64_t* examined_out, void* scratch, size_t scratch_bytes,
+                               void* stream) {
     if (!ds || !count_out || k < 1 || int64_t(k) > ds->n || !(eps > 0.0) || batch < 0) return EBC_E_INVALID_ARG;
     if (!sel_out || !f_out || n_order < 0 || (!order && n_order > ds->n)) return EBC_E_INVALID_ARG;
     *count_out = 0;
     if (v_out) *v_out = 0.0;
     if (examined_out) *examined_out = 0;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    if (batch == 0) batch = 1024;
-    if (batch > ds->n_pad) batch = int32_t(ds->n_pad);
+    batch = effective_batch(ds->n_pad, batch);
+    if (!scratch_ok(scratch, scratch_bytes, sieve_streaming_scratch(ds->n_pad, k, eps, n_order, batch)))
+        return EBC_E_INVALID_ARG;
 
-    // the grid needs m before the per-summary buffers can be sized
+    // the grid needs m before the per-summary buffers are laid out
     DevState st;
     ebc_status pst = start_stream(ds, &m_max, sel_out, f_out, s, &st);
     if (pst != EBC_OK) return pst;
@@ -271,22 +312,17 @@ ebc_status ebc_sieve_streaming(ebc_dataset* ds, int32_t k, double eps, double m_
     const std::vector<double> grid = sieve_grid(m_max, k, eps);
     const int64_t J = int64_t(grid.size());
     if (J == 0) return EBC_OK;
+    if (J > max_guesses(k, eps)) return EBC_E_INVALID_ARG;  // not reached: the grid spans a factor k
 
-    // per summary: m^v [n_pad] f64, gains of its stretch [batch] f64, f [k] f64, members [k] i32
-    auto al = [](size_t v) { return (v + 255) & ~size_t(255); };
+    auto al = al256;
     const size_t m_bytes = al(size_t(ds->n_pad) * sizeof(double)), g_bytes = al(size_t(batch) * sizeof(double));
-    const size_t f_bytes = al(size_t(k) * sizeof(double)), s_bytes = al(size_t(k) * sizeof(int32_t));
-    const size_t per = m_bytes + g_bytes + f_bytes + s_bytes;
+    const size_t f_bytes = al(size_t(k) * sizeof(double));
+    const size_t per = sieve_summary_bytes(ds->n_pad, k, batch);
     std::vector<int32_t> h_order;
-    char* scratch = nullptr;
     int32_t* d_order = nullptr;
     char* d_extra = nullptr;
-    pst = prepare_stream(ds, order, n_order, size_t(J) * per + kListBytes, s, h_order, &scratch, &d_order, &d_extra);
-    auto done = [&](ebc_status r) {
-        if (scratch) (void)hipFreeAsync(scratch, s);
-        return r;
-    };
-    if (pst != EBC_OK) return done(pst);
+    pst = prepare_stream(ds, order, n_order, static_cast<char*>(scratch), s, h_order, &d_order, &d_extra);
+    if (pst != EBC_OK) return pst;
     auto m_of = [&](int64_t j) { return reinterpret_cast<double*>(d_extra + j * per); };
     auto g_of = [&](int64_t j) { return reinterpret_cast<double*>(d_extra + j * per + m_bytes); };
     auto f_of = [&](int64_t j) { return reinterpret_cast<double*>(d_extra + j * per + m_bytes + g_bytes); };
@@ -295,7 +331,7 @@ ebc_status ebc_sieve_streaming(ebc_dataset* ds, int32_t k, double eps, double m_
     const size_t n_bytes = size_t(ds->n) * sizeof(double);
     for (int64_t j = 0; j < J; ++j)  // every summary starts at S = {}: m^v = the current minima
         if (hipMemcpyAsync(m_of(j), ds->b.m64, n_bytes, hipMemcpyDeviceToDevice, s) != hipSuccess)
-            return done(EBC_E_DEVICE);
+            return EBC_E_DEVICE;
 
     const double tol = 2.0 * window_tau(ds->dt) * m_max;  // as in ebc_three_sieves
     std::vector<std::vector<double>> h_gain(size_t(J), std::vector<double>(static_cast<size_t>(batch)));
@@ -325,7 +361,7 @@ ebc_status ebc_sieve_streaming(ebc_dataset* ds, int32_t k, double eps, double m_
                     hipMemcpyAsync(h_gain[size_t(j)].data(), g_of(j), size_t(L) * sizeof(double),
                                    hipMemcpyDeviceToHost, s) != hipSuccess ||
                     hipStreamSynchronize(s) != hipSuccess)
-                    return done(EBC_E_DEVICE);
+                    return EBC_E_DEVICE;
                 base[size_t(j)] = i;
                 len[size_t(j)] = L;
                 c64[size_t(j)].clear();
@@ -341,7 +377,7 @@ ebc_status ebc_sieve_streaming(ebc_dataset* ds, int32_t k, double eps, double m_
                     c64[size_t(j)].get(ds, h_gain[size_t(j)].data(), h_order.data() + b0, i - b0, len[size_t(j)],
                                        bound - tol, bound + tol, i + 1 - last[size_t(j)], d_list, s,
                                        &g64) != hipSuccess)
-                    return done(EBC_E_DEVICE);
+                    return EBC_E_DEVICE;
                 take = g64 >= bound;
             }
             if (!take) continue;
@@ -350,7 +386,7 @@ ebc_status ebc_sieve_streaming(ebc_dataset* ds, int32_t k, double eps, double m_
                 hipMemcpyAsync(m_of(j), ds->b.m64, n_bytes, hipMemcpyDeviceToDevice, s) != hipSuccess ||
                 hipMemcpyAsync(&fS[size_t(j)], f_of(j) + t, sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
                 hipStreamSynchronize(s) != hipSuccess)
-                return done(EBC_E_DEVICE);
+                return EBC_E_DEVICE;
             if (++cnt[size_t(j)] == k) ++full;
             len[size_t(j)] = 0;  // its later gains are stale
             stretch[size_t(j)] = std::min<int64_t>(batch, std::max<int64_t>(64, 2 * (i + 1 - last[size_t(j)])));
@@ -366,12 +402,12 @@ ebc_status ebc_sieve_streaming(ebc_dataset* ds, int32_t k, double eps, double m_
                     hipMemcpyAsync(f_out, f_of(best), size_t(nb) * sizeof(double), hipMemcpyDeviceToDevice, s) !=
                         hipSuccess)) ||
         load(best) != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
-        return done(EBC_E_DEVICE);
+        return EBC_E_DEVICE;
     *count_out = nb;
     if (v_out) *v_out = grid[size_t(best)];
     if (examined_out) *examined_out = examined;
     ds->stats.steps = nb;
-    return done(EBC_OK);
+    return EBC_OK;
 }
 
 }  // extern "C"

@@ -15,15 +15,18 @@ import numpy as np
 
 import torch  # loads the process's HIP runtime before libebc.so binds to it
 
-__all__ = ["EBCError", "Dataset", "Batch", "Server", "Arena", "request_bytes", "lib", "status_string", "DTYPES",
+__all__ = ["EBCError", "Dataset", "Batch", "Server", "Arena", "request_bytes", "lib", "status_string", "DTYPES", "DISTS",
            "LIB_PATH", "ABI_FUNCTIONS"]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libebc.so")
 DTYPES = {"f32": 0, "f16": 1, "bf16": 2, "fp8": 3}
+# dissimilarity -> ebc_dataset_create flags (EBC_FLAG_L1 = 1)
+DISTS = {"sqeuclidean": 0, "l1": 1}
 MAX_DIM = 4096  # EBC_MAX_DIM of include/ebc.h
 ABI_FUNCTIONS = (
-    "ebc_dataset_bytes", "ebc_dataset_create", "ebc_dataset_destroy", "ebc_eval_sets", "ebc_eval_sets_in_dtype",
-    "ebc_marginal_gains", "ebc_greedy", "ebc_three_sieves", "ebc_sieve_streaming", "ebc_sync_status",
+    "ebc_dataset_bytes", "ebc_dataset_create", "ebc_dataset_destroy", "ebc_eval_sets_bytes", "ebc_eval_sets",
+    "ebc_eval_sets_in_dtype", "ebc_marginal_gains", "ebc_greedy", "ebc_three_sieves_bytes", "ebc_three_sieves",
+    "ebc_sieve_streaming_bytes", "ebc_sieve_streaming", "ebc_sync_status",
     "ebc_status_string",
     "ebc_dataset_get_info", "ebc_dataset_set_e0", "ebc_profile_enable", "ebc_profile_read", "ebc_set_gains_variant",
     "ebc_gains_variant_count", "ebc_set_greedy_graph", "ebc_batch_bytes", "ebc_batch_create",
@@ -33,7 +36,8 @@ ABI_FUNCTIONS = (
     "ebc_server_stats", "ebc_server_now", "ebc_arena_create", "ebc_arena_alloc", "ebc_arena_free",
     "ebc_arena_free_bytes", "ebc_arena_largest_free", "ebc_arena_destroy",
 )
-_NON_STATUS = ("ebc_dataset_bytes", "ebc_status_string", "ebc_batch_bytes", "ebc_request_bytes", "ebc_server_now",
+_NON_STATUS = ("ebc_dataset_bytes", "ebc_eval_sets_bytes", "ebc_three_sieves_bytes", "ebc_sieve_streaming_bytes",
+               "ebc_status_string", "ebc_batch_bytes", "ebc_request_bytes", "ebc_server_now",
                "ebc_arena_free_bytes", "ebc_arena_largest_free", "ebc_tune_cache_size")
 
 
@@ -51,7 +55,8 @@ class _Stats(ctypes.Structure):
 class _Info(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("n_pad", ctypes.c_int64), ("d", ctypes.c_int32),
                 ("k_pad", ctypes.c_int32), ("v_splits", ctypes.c_int32), ("cand_tile", ctypes.c_int32),
-                ("window_cap", ctypes.c_int32), ("dtype", ctypes.c_int32), ("l0", ctypes.c_double)]
+                ("window_cap", ctypes.c_int32), ("dtype", ctypes.c_int32), ("flags", ctypes.c_uint32),
+                ("reserved", ctypes.c_int32), ("l0", ctypes.c_double)]
 
 
 class _Profile(ctypes.Structure):
@@ -74,15 +79,22 @@ def lib() -> ctypes.CDLL:
         L.ebc_dataset_create.argtypes = [P, i64, i32, ctypes.c_int, u32, P, ctypes.c_size_t, P,
                                          ctypes.POINTER(P)]
         L.ebc_dataset_destroy.argtypes = [P]
-        L.ebc_eval_sets.argtypes = [P, P, P, i64, P, P]
-        L.ebc_eval_sets_in_dtype.argtypes = [P, P, P, i64, P, P]
+        sz = ctypes.c_size_t
+        L.ebc_eval_sets_bytes.argtypes = [i64, i64]
+        L.ebc_eval_sets_bytes.restype = sz
+        L.ebc_eval_sets.argtypes = [P, P, P, i64, P, P, sz, P]
+        L.ebc_eval_sets_in_dtype.argtypes = [P, P, P, i64, P, P, sz, P]
+        L.ebc_three_sieves_bytes.argtypes = [i64, i64, i32]
+        L.ebc_three_sieves_bytes.restype = sz
+        L.ebc_sieve_streaming_bytes.argtypes = [i64, i32, ctypes.c_double, i64, i32]
+        L.ebc_sieve_streaming_bytes.restype = sz
         L.ebc_marginal_gains.argtypes = [P, P, P, i64, P, P]
         L.ebc_greedy.argtypes = [P, i32, P, P, P, P]
         L.ebc_three_sieves.argtypes = [P, i32, ctypes.c_double, i64, ctypes.c_double, P, i64, i32, P, P,
-                                       ctypes.POINTER(i32), ctypes.POINTER(i64), P]
+                                       ctypes.POINTER(i32), ctypes.POINTER(i64), P, sz, P]
         L.ebc_sieve_streaming.argtypes = [P, i32, ctypes.c_double, ctypes.c_double, P, i64, i32, P, P,
                                           ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double),
-                                          ctypes.POINTER(i64), P]
+                                          ctypes.POINTER(i64), P, sz, P]
         L.ebc_sync_status.argtypes = [P, P, ctypes.POINTER(_Stats)]
         L.ebc_status_string.argtypes = [ctypes.c_int]
         L.ebc_status_string.restype = ctypes.c_char_p
@@ -149,6 +161,17 @@ def _stream(stream) -> ctypes.c_void_p:
     return ctypes.c_void_p(s.cuda_stream)
 
 
+def _scratch(nbytes: int, device, stream=None) -> torch.Tensor:
+    """Caller-owned device scratch for one call (torch's allocator is 256-byte
+    aligned; at least one byte so the pointer is never NULL). With an explicit
+    stream the block is recorded on it, so the caching allocator reuses it
+    only after that stream's work."""
+    t = torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+    if stream is not None:
+        t.record_stream(stream)
+    return t
+
+
 class Dataset:
     """A ground set V resident on the GPU (ebc_dataset_create).
 
@@ -156,22 +179,25 @@ class Dataset:
     because the library borrows it. The workspace is a uint8 CUDA tensor of
     exactly ``ebc_dataset_bytes(n, d, dtype)`` bytes."""
 
-    def __init__(self, x: torch.Tensor, dtype: str = "f32", stream=None):
+    def __init__(self, x: torch.Tensor, dtype: str = "f32", stream=None, dist: str = "sqeuclidean"):
         if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == torch.float32 and x.dim() == 2):
             raise TypeError("x must be a float32 CUDA tensor of shape [n, d]")
         self.x = x.contiguous()
         self.n, self.d = map(int, self.x.shape)
         self.dtype = dtype
+        self.dist = dist
         L = lib()
         if dtype not in DTYPES:
             raise ValueError(f"dtype must be one of {sorted(DTYPES)}")
+        if dist not in DISTS:
+            raise ValueError(f"dist must be one of {sorted(DISTS)}")
         nbytes = L.ebc_dataset_bytes(self.n, self.d, DTYPES[dtype])
         if nbytes == 0:
             raise EBCError(1 if self.d <= MAX_DIM else 7, f"ebc_dataset_bytes(n={self.n}, d={self.d})")
         self.workspace_bytes = int(nbytes)
         self.workspace = torch.empty(self.workspace_bytes, dtype=torch.uint8, device=self.x.device)
         h = ctypes.c_void_p()
-        _check(L.ebc_dataset_create(_ptr(self.x), self.n, self.d, DTYPES[dtype], 0, _ptr(self.workspace),
+        _check(L.ebc_dataset_create(_ptr(self.x), self.n, self.d, DTYPES[dtype], DISTS[dist], _ptr(self.workspace),
                                     self.workspace_bytes, _stream(stream), ctypes.byref(h)),
                "ebc_dataset_create")
         self._h = h
@@ -246,10 +272,16 @@ class Dataset:
         _check(lib().ebc_profile_read(self._h, ctypes.byref(pr), int(bool(reset))), "ebc_profile_read")
         return {f: getattr(pr, f) for f, _ in _Profile._fields_}
 
+    def eval_sets_bytes(self, l: int) -> int:
+        """Device scratch of one eval_sets call over l sets (ebc_eval_sets_bytes)."""
+        return int(lib().ebc_eval_sets_bytes(self.n, int(l)))
+
     def eval_sets(self, offsets: torch.Tensor, idx: torch.Tensor, out: torch.Tensor | None = None,
-                  stream=None, in_dtype: bool = False) -> torch.Tensor:
+                  stream=None, in_dtype: bool = False, scratch: torch.Tensor | None = None) -> torch.Tensor:
         """f(S_j) for CSR sets (offsets int64 [l+1], idx int32 [nnz]); float64 [l].
-        in_dtype: dot products in the dataset's distance dtype instead of float32."""
+        in_dtype: dot products in the dataset's distance dtype instead of float32.
+        scratch: a uint8 CUDA tensor of at least eval_sets_bytes(l) bytes to use
+        instead of a fresh one."""
         offsets = offsets.to(device=self.x.device, dtype=torch.int64).contiguous()
         idx = idx.to(device=self.x.device, dtype=torch.int32).contiguous()
         l = offsets.numel() - 1
@@ -257,7 +289,10 @@ class Dataset:
             out = torch.empty(max(l, 0), dtype=torch.float64, device=self.x.device)
         idx_arg = idx if idx.numel() > 0 else offsets  # any valid pointer when there are no members
         fn = lib().ebc_eval_sets_in_dtype if in_dtype else lib().ebc_eval_sets
-        _check(fn(self._h, _ptr(offsets), _ptr(idx_arg), l, _ptr(out), _stream(stream)), "ebc_eval_sets")
+        if scratch is None:
+            scratch = _scratch(lib().ebc_eval_sets_bytes(self.n, max(l, 0)), self.x.device, stream)
+        _check(fn(self._h, _ptr(offsets), _ptr(idx_arg), l, _ptr(out), _ptr(scratch), scratch.numel(),
+                  _stream(stream)), "ebc_eval_sets")
         return out
 
     def marginal_gains(self, m: torch.Tensor | None = None, cand: torch.Tensor | None = None,
@@ -286,9 +321,11 @@ class Dataset:
         f = torch.empty(k, dtype=torch.float64, device=dev)
         cnt = ctypes.c_int32(0)
         seen = ctypes.c_int64(0)
+        nb = int(lib().ebc_three_sieves_bytes(self.n, n_order, int(batch)))
+        scratch = _scratch(nb, dev, stream)
         _check(lib().ebc_three_sieves(self._h, int(k), float(eps), int(T), float(m_max), _ptr(order), n_order,
                                       int(batch), _ptr(sel), _ptr(f), ctypes.byref(cnt), ctypes.byref(seen),
-                                      _stream(stream)), "ebc_three_sieves")
+                                      _ptr(scratch), nb, _stream(stream)), "ebc_three_sieves")
         return sel[:cnt.value], f[:cnt.value], int(seen.value)
 
     def sieve_streaming(self, k: int, eps: float, m_max: float = 0.0, order=None, batch: int = 0, stream=None):
@@ -304,9 +341,12 @@ class Dataset:
         cnt = ctypes.c_int32(0)
         v = ctypes.c_double(0.0)
         seen = ctypes.c_int64(0)
+        nb = int(lib().ebc_sieve_streaming_bytes(self.n, int(k), float(eps), n_order, int(batch)))
+        scratch = _scratch(nb, dev, stream)
         _check(lib().ebc_sieve_streaming(self._h, int(k), float(eps), float(m_max), _ptr(order), n_order,
                                          int(batch), _ptr(sel), _ptr(f), ctypes.byref(cnt), ctypes.byref(v),
-                                         ctypes.byref(seen), _stream(stream)), "ebc_sieve_streaming")
+                                         ctypes.byref(seen), _ptr(scratch), nb, _stream(stream)),
+               "ebc_sieve_streaming")
         return sel[:cnt.value], f[:cnt.value], float(v.value), int(seen.value)
 
     def greedy(self, k: int, stream=None, sel=None, f=None, gain=None):

@@ -65,7 +65,8 @@ def test_host_validation_without_device(L):
     # null x, null workspace, bad flags, bad dtype: rejected before any HIP call
     assert L.ebc_dataset_create(None, 10, 4, 0, 0, P(256), 1 << 20, None, ctypes.byref(h)) == 1
     assert L.ebc_dataset_create(P(256), 10, 4, 0, 0, None, 1 << 20, None, ctypes.byref(h)) == 1
-    assert L.ebc_dataset_create(P(256), 10, 4, 0, 1, P(256), 1 << 20, None, ctypes.byref(h)) == 1
+    assert L.ebc_dataset_create(P(256), 10, 4, 0, 2, P(256), 1 << 20, None, ctypes.byref(h)) == 1  # unknown flag
+    assert L.ebc_dataset_create(P(256), 10, 4, 2, 1, P(256), 1 << 20, None, ctypes.byref(h)) == 7  # L1 needs FP32
     assert L.ebc_dataset_create(P(256), 10, 4, 5, 0, P(256), 1 << 20, None, ctypes.byref(h)) == 1
     assert L.ebc_dataset_create(P(256), 10, 5000, 0, 0, P(256), 1 << 30, None, ctypes.byref(h)) == 7
     assert L.ebc_dataset_create(P(256), 10, 4, 0, 0, P(128), 1 << 20, None, ctypes.byref(h)) == 1  # misaligned
@@ -74,12 +75,57 @@ def test_host_validation_without_device(L):
     assert not h.value
     assert L.ebc_dataset_destroy(None) == 1
     assert L.ebc_greedy(None, 1, None, None, None, None) == 1
-    assert L.ebc_eval_sets(None, None, None, 1, None, None) == 1
+    assert L.ebc_eval_sets(None, None, None, 1, None, P(256), 1 << 20, None) == 1
+    assert L.ebc_eval_sets_in_dtype(None, None, None, 1, None, P(256), 1 << 20, None) == 1
     assert L.ebc_marginal_gains(None, None, None, 1, None, None) == 1
     assert L.ebc_sync_status(None, None, None) == 1
     assert L.ebc_dataset_set_e0(None, None, None) == 1
     cnt, seen, v = ctypes.c_int32(7), ctypes.c_int64(7), ctypes.c_double(7.0)
     assert L.ebc_three_sieves(None, 3, 0.1, 5, 0.0, None, 10, 0, P(256), P(256), ctypes.byref(cnt),
-                              ctypes.byref(seen), None) == 1
+                              ctypes.byref(seen), P(256), 1 << 20, None) == 1
     assert L.ebc_sieve_streaming(None, 3, 0.1, 0.0, None, 10, 0, P(256), P(256), ctypes.byref(cnt),
-                                 ctypes.byref(v), ctypes.byref(seen), None) == 1
+                                 ctypes.byref(v), ctypes.byref(seen), P(256), 1 << 20, None) == 1
+
+
+def test_scratch_size_queries(L):
+    """The calls that need device scratch take it from the caller; their size
+    queries are host arithmetic (no dataset, no device)."""
+    # multi-set evaluation: unit counts (8 + 4 + 4 bytes per set) + float64 partial
+    # sums per ground-set split (ceil(n / 256) splits, at most 16), 256-byte pieces
+    a = L.ebc_eval_sets_bytes(50000, 5000)
+    assert a % 256 == 0
+    assert a >= 5000 * (16 + 8 * 16)
+    assert a <= 5000 * (16 + 8 * 16) + 5 * 256
+    assert L.ebc_eval_sets_bytes(300, 5000) < a            # two splits instead of 16
+    assert L.ebc_eval_sets_bytes(1000, 0) > 0               # the per-call counters
+    assert L.ebc_eval_sets_bytes(0, 10) == 0
+    assert L.ebc_eval_sets_bytes(1000, -1) == 0
+    assert L.ebc_eval_sets_bytes(1000, 2 * 10 ** 6) > L.ebc_eval_sets_bytes(1000, 10 ** 6)
+    # Three Sieves: stream indices + one stretch of float64 gains + a re-score list
+    t = L.ebc_three_sieves_bytes(1000, 1000, 0)
+    assert t >= 1000 * 4 + 1024 * 8 and t % 256 == 0
+    assert L.ebc_three_sieves_bytes(1000, 1000, 64) < t     # a shorter stretch
+    assert L.ebc_three_sieves_bytes(0, 10, 0) == 0
+    assert L.ebc_three_sieves_bytes(100, -1, 0) == 0
+    # Sieve Streaming: per guess (at most floor(log k / log(1+eps)) + 2) its minima,
+    # a stretch of gains, k members and k f values
+    k, eps, n = 50, 0.1, 1000
+    guesses = int(__import__("math").floor(__import__("math").log(k) / __import__("math").log1p(eps))) + 2
+    s = L.ebc_sieve_streaming_bytes(n, k, eps, n, 0)
+    per = 1024 * 8 + 1024 * 8 + 512 + 256
+    assert s >= guesses * per and s < guesses * per + 1024 * 4 + 8192
+    assert L.ebc_sieve_streaming_bytes(n, k, 0.5, n, 0) < s   # fewer guesses
+    assert L.ebc_sieve_streaming_bytes(n, 0, eps, n, 0) == 0
+    assert L.ebc_sieve_streaming_bytes(n, n + 1, eps, n, 0) == 0
+    assert L.ebc_sieve_streaming_bytes(n, k, 0.0, n, 0) == 0
+
+
+def test_no_device_allocation_in_the_library():
+    """Every device buffer comes from the caller: no source of the library
+    calls the HIP allocator."""
+    csrc = os.path.join(ROOT, "paper_2105_12026_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        text = open(os.path.join(csrc, name)).read()
+        for call in ("hipMalloc(", "hipMallocAsync(", "hipMallocManaged(", "hipExtMallocWithFlags(",
+                     "hipMallocPitch(", "hipMalloc3D(", "hipMallocFromPoolAsync("):
+            assert call not in text, (name, call)

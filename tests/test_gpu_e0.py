@@ -10,7 +10,11 @@ from paper_2105_12026_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
 
-ES_TOL = {"bf16": 2e-2, "f16": 5e-3, "fp8": 1.5e-1}
+# multi-set f in the dataset dtype, |f - f_ref| / (|f_ref| + 1e-3 L({e0})):
+# BF16 and FP16 at the proposed bars; FP8 at 3e-2, 1.3x the largest error
+# measured over the committed cases (2.33e-2; about 0.4 of e4m3's unit
+# roundoff 2^-4, like the other dtypes' maxima relative to theirs)
+ES_TOL = {"bf16": 2e-3, "f16": 5e-4, "fp8": 3e-2}
 
 
 @pytest.fixture(scope="module")
@@ -78,7 +82,7 @@ def test_e0_eval_sets(env, ref, n, d, seed):
         f32 = ds.eval_sets(to, ti).cpu().numpy()
         ds.sync()
         assert np.all(f32[np.array(sizes) == 0] == 0.0)
-        assert np.all(np.abs(f32 - rf) <= 1e-5 * np.abs(rf) + 1e-6 * l0), dt
+        assert np.all(np.abs(f32 - rf) <= 1e-5 * np.abs(rf) + 1e-12 * l0), dt
         if dt != "f32":
             fl = ds.eval_sets(to, ti, in_dtype=True).cpu().numpy()
             ds.sync()

@@ -76,6 +76,33 @@ def test_lowprec_greedy_quality(env, ref, dt):
     assert gap <= GAP_TOL[dt]
 
 
+@pytest.mark.parametrize("dt", ["f32", "bf16", "f16", "fp8"])
+def test_zero_gain_steps_pick_lowest_unselected(env, ref, dt):
+    """20 distinct points, each present 15 times (300 rows), greedy to k = n:
+    after the 20 distinct points are picked every point is covered, and the
+    280 remaining steps have 280 .. 1 zero-gain candidates, more than the
+    256 the float64 window re-scores. Each such step must pick the lowest
+    unselected index (the oracle's reading), whatever the dtype."""
+    rng = np.random.default_rng(17)
+    base = (rng.standard_normal((20, 8)) * 4.0).astype(np.float32)
+    x = np.concatenate([base[rng.permutation(20)] for _ in range(15)])
+    n = x.shape[0]
+    print(f"[gpu-case] zero-gain steps {dt} n={n} k={n}", flush=True)
+    ds = _ds(env, x, dt)
+    sel, f, g = ds.greedy(n)
+    ds.sync()
+    sel, f, g = sel.cpu().numpy(), f.cpu().numpy(), g.cpu().numpy()
+    rsel, rf, rg = ref.greedy(x, n)
+    assert sorted(sel.tolist()) == list(range(n))
+    assert set(sel[:20].tolist()) == set(rsel[:20].tolist())   # one copy of each distinct point
+    assert sel[20:].tolist() == rsel[20:].tolist()               # then lowest unselected, in order
+    assert np.all(g[20:] == 0.0)
+    l0 = float(np.mean(np.sum(x.astype(np.float64) ** 2, axis=1)))
+    assert f[-1] == pytest.approx(l0, rel=1e-12)
+    if dt == "f32":
+        assert sel.tolist() == rsel.tolist()
+
+
 def test_f16_range_is_reported(env):
     _, ebc = env
     x = np.ones((40, 4), np.float32)
@@ -146,7 +173,7 @@ def test_full_size_greedy_against_oracle_run(env, ref, sweep200k, dt):
           f"quality gap {gap:.2e} window max {stats['window_max']}", flush=True)
     if dt == "f32":
         assert sel.tolist() == rsel.tolist()
-        np.testing.assert_allclose(f, rf, rtol=1e-5)
+        np.testing.assert_allclose(f, rf, rtol=1e-12)
         return
     l0 = float(np.mean(np.sum(p.x.astype(np.float64) ** 2, axis=1)))
     for t in (9, p.k - 1):
@@ -187,7 +214,11 @@ def test_every_variant_matches_oracle_and_variant0(env, ref, dt, n, d, seed):
             np.testing.assert_array_equal(g_all, base, err_msg=f"variant {v}")
 
 
-ES_TOL = {"bf16": 2e-2, "f16": 5e-3, "fp8": 1.5e-1}
+# multi-set f in the dataset dtype, |f - f_ref| / (|f_ref| + 1e-3 L({e0})):
+# BF16 and FP16 at the proposed bars; FP8 at 3e-2, 1.3x the largest error
+# measured over the committed cases (2.33e-2; about 0.4 of e4m3's unit
+# roundoff 2^-4, like the other dtypes' maxima relative to theirs)
+ES_TOL = {"bf16": 2e-3, "f16": 5e-4, "fp8": 3e-2}
 
 
 @pytest.mark.parametrize("dt", ["bf16", "f16", "fp8"])
@@ -220,4 +251,4 @@ def test_eval_sets_in_dtype(env, ref, dt, n, d, seed):
     rel = np.abs(f1 - rf) / (np.abs(rf) + 1e-3 * l0)
     print(f"[gpu-result] eval_sets in {dt} n={n} d={d}: max rel err {rel.max():.3e}", flush=True)
     assert rel.max() <= ES_TOL[dt]
-    assert np.all(np.abs(f32 - rf) <= 1e-5 * np.abs(rf) + 1e-6 * l0)
+    assert np.all(np.abs(f32 - rf) <= 1e-5 * np.abs(rf) + 1e-12 * l0)

@@ -1,7 +1,8 @@
 """Parity of the HIP path (through the C ABI) with the FP64 oracle.
 
 Tolerances (float32 distance path):
-  * f over sets and greedy f(S_t):  |f_gpu - f_ref| <= 1e-5 * |f_ref| (+1e-12 abs)
+  * f over sets:                    |f_gpu - f_ref| <= 1e-5 * |f_ref| (+1e-12 abs)
+  * greedy f(S_t):                  relative 1e-12 (f comes from the float64 minima m_v)
   * gain vectors:                   max_c |G_gpu - G_ref| <= 1e-5 * max_c |G_ref|
   * greedy selections:              identical to the oracle
 Every case prints its name before it touches the GPU.
@@ -19,6 +20,7 @@ pytestmark = pytest.mark.gpu
 
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 F_RTOL = 1e-5
+GREEDY_F_RTOL = 1e-12  # f(S_t) = L({e0}) - mean(m_v) with m_v float64 on both sides
 G_RTOL = 1e-5
 
 
@@ -63,8 +65,8 @@ def test_small_workload_against_golden(ebc, torch_dev):
     ds.sync()
     np.testing.assert_allclose(f.cpu().numpy(), gold["f_sets"], rtol=F_RTOL, atol=1e-12)
     assert sel.cpu().numpy().tolist() == gold["sel"]
-    np.testing.assert_allclose(fs.cpu().numpy(), gold["f"], rtol=F_RTOL)
-    np.testing.assert_allclose(gs.cpu().numpy(), gold["gain"], rtol=F_RTOL)
+    np.testing.assert_allclose(fs.cpu().numpy(), gold["f"], rtol=GREEDY_F_RTOL)
+    np.testing.assert_allclose(gs.cpu().numpy(), gold["gain"], rtol=1e-9)
 
 
 # ---------------------------------------------------------------------------
@@ -107,8 +109,8 @@ def test_greedy_matches_oracle(ebc, torch_dev, n, d, k, seed, ref):
     stats = ds.sync()
     rsel, rf, rg = ref.greedy(x, k)
     assert sel.cpu().numpy().tolist() == rsel.tolist()
-    np.testing.assert_allclose(f.cpu().numpy(), rf, rtol=F_RTOL)
-    np.testing.assert_allclose(g.cpu().numpy(), rg, rtol=F_RTOL, atol=1e-12 * rf[-1])
+    np.testing.assert_allclose(f.cpu().numpy(), rf, rtol=GREEDY_F_RTOL)
+    np.testing.assert_allclose(g.cpu().numpy(), rg, rtol=1e-9, atol=1e-12 * rf[-1])
     assert stats["window_overflow"] == 0 or k == n
 
 
@@ -139,7 +141,7 @@ def test_greedy_duplicates_and_zero_rows(ebc, torch_dev, ref):
     ds.sync()
     rsel, rf, _ = ref.greedy(x, 28)
     assert sel.cpu().numpy().tolist() == rsel.tolist()
-    np.testing.assert_allclose(f.cpu().numpy(), rf, rtol=F_RTOL)
+    np.testing.assert_allclose(f.cpu().numpy(), rf, rtol=GREEDY_F_RTOL)
     assert sorted(sel.cpu().tolist()) == list(range(28))
 
 
@@ -226,7 +228,7 @@ def test_eval_sets_many_sizes(ebc, torch_dev, ref, n, d, dt, seed):
     l0 = float(np.mean(np.sum(x.astype(np.float64) ** 2, axis=1)))
     assert np.all(f1[np.array(sizes) == 0] == 0.0)
     err = np.abs(f1 - rf)
-    assert np.all(err <= F_RTOL * np.abs(rf) + 1e-6 * l0), float(np.max(err / (np.abs(rf) + 1e-300)))
+    assert np.all(err <= F_RTOL * np.abs(rf) + 1e-12 * l0), float(np.max(err / (np.abs(rf) + 1e-300)))
 
 
 def test_eval_sets_bad_index_is_reported(ebc, torch_dev):
@@ -290,8 +292,8 @@ def test_full_size_greedy_against_golden(ebc, torch_dev, ref, gmm100k):
     sel, f, g = ds.greedy(p.k)
     stats = ds.sync()
     assert sel.cpu().numpy().tolist() == gold["sel"]
-    np.testing.assert_allclose(f.cpu().numpy(), gold["f"], rtol=F_RTOL)
-    np.testing.assert_allclose(g.cpu().numpy(), gold["gain"], rtol=F_RTOL)
+    np.testing.assert_allclose(f.cpu().numpy(), gold["f"], rtol=GREEDY_F_RTOL)
+    np.testing.assert_allclose(g.cpu().numpy(), gold["gain"], rtol=1e-9)
     assert stats["window_overflow"] == 0
     # gains at S_50 on a sample, against the oracle
     gl = ds.marginal_gains().cpu().numpy()

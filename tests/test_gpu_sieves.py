@@ -106,7 +106,7 @@ SS_CASES = [  # (kind, n, d, k, eps, stream, seed)
 ]
 
 
-@pytest.mark.parametrize("dt", ["f32", "bf16", "fp8"])
+@pytest.mark.parametrize("dt", ["f32", "bf16", "f16", "fp8"])
 @pytest.mark.parametrize("kind,n,d,k,eps,stream,seed", SS_CASES)
 def test_sieve_streaming_matches_oracle(env, dt, kind, n, d, k, eps, stream, seed):
     torch, _ = env
@@ -130,4 +130,4 @@ def test_sieve_streaming_matches_oracle(env, dt, kind, n, d, k, eps, stream, see
     ds.sync()
     m = O.min_dist_to_set(x, rsel)
     rg = O.gains(x, m, range(min(n, 64)))
-    assert np.max(np.abs(g - rg)) <= {"f32": 1e-5, "bf16": 1e-2, "fp8": 8e-2}[dt] * max(np.max(np.abs(rg)), 1e-300)
+    assert np.max(np.abs(g - rg)) <= {"f32": 1e-5, "bf16": 1e-2, "f16": 2e-3, "fp8": 8e-2}[dt] * max(np.max(np.abs(rg)), 1e-300)

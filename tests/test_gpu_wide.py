@@ -16,7 +16,11 @@ pytestmark = pytest.mark.gpu
 
 G_RTOL = 1e-5
 GAIN_TOL = {"bf16": 1e-2, "f16": 2e-3, "fp8": 8e-2}
-ES_TOL = {"bf16": 2e-2, "f16": 5e-3, "fp8": 1.5e-1}
+# multi-set f in the dataset dtype, |f - f_ref| / (|f_ref| + 1e-3 L({e0})):
+# BF16 and FP16 at the proposed bars; FP8 at 3e-2, 1.3x the largest error
+# measured over the committed cases (2.33e-2; about 0.4 of e4m3's unit
+# roundoff 2^-4, like the other dtypes' maxima relative to theirs)
+ES_TOL = {"bf16": 2e-3, "f16": 5e-4, "fp8": 3e-2}
 _REF_CACHE = {}
 
 
@@ -131,7 +135,7 @@ def test_wide_eval_sets(env, ref, kind, n, d, seed):
         f32 = ds.eval_sets(to, ti).cpu().numpy()
         ds.sync()
         assert np.all(f32[np.array(sizes) == 0] == 0.0)
-        assert np.all(np.abs(f32 - rf) <= 1e-5 * np.abs(rf) + 1e-6 * l0), dt
+        assert np.all(np.abs(f32 - rf) <= 1e-5 * np.abs(rf) + 1e-12 * l0), dt
         if dt != "f32":
             f1 = ds.eval_sets(to, ti, in_dtype=True).cpu().numpy()
             f2 = ds.eval_sets(to, ti, in_dtype=True).cpu().numpy()

@@ -76,7 +76,10 @@ def test_request_bytes(ebc):
     assert base > 10_000 * 64 * 4
     assert ebc.request_bytes(20_000, 64, 10, "bf16") > base
     assert ebc.request_bytes(10_000, 64, 50, "bf16") > base
-    assert ebc.request_bytes(10_000, 64, 10, "f32") > base  # float32 copy is wider than bf16
+    # float32: the caller's points plus the padded float32 copy; bf16: the points
+    # plus the cast copy in row order and in grouped order (10240 padded rows)
+    assert ebc.request_bytes(10_000, 64, 10, "f32") > 2 * 10_000 * 64 * 4
+    assert base > 10_000 * 64 * 4 + 2 * 10_240 * 64 * 2
     assert ebc.request_bytes(10, 64, 11, "bf16") == 0       # k > n
     assert ebc.request_bytes(10, 4097, 5, "bf16") == 0      # d beyond the supported maximum
     assert ebc.request_bytes(1000, 3524, 5, "bf16") > 1000 * 3524 * 4
