@@ -173,6 +173,30 @@ EBC_API ebc_status ebc_eval_sets(ebc_dataset* ds, const int64_t* offsets, const 
 EBC_API ebc_status ebc_eval_sets_in_dtype(ebc_dataset* ds, const int64_t* offsets, const int32_t* idx, int64_t l,
                                           double* f_out, void* scratch, size_t scratch_bytes, void* stream);
 
+/* Size of the library's fixed device scratch (per device, held until the
+ * process ends) that ebc_eval_sets_noalloc uses. */
+#define EBC_FIXED_SCRATCH_BYTES ((size_t)16 << 20)
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * f(S_j) as ebc_eval_sets (in_dtype = 0) or ebc_eval_sets_in_dtype
+ * (in_dtype = 1), bitwise, with the per-set tables in a fixed device array of
+ * EBC_FIXED_SCRATCH_BYTES owned by the library instead of a caller scratch.
+ *   offsets, idx, f_out [device] as for ebc_eval_sets; the caller still owns
+ *           inputs and outputs. The dataset must live on the current device.
+ * The call allocates nothing (no hipMalloc, no allocating library routine);
+ * the first call on a device looks up that device's copy of the array.
+ * Every call on one device shares that array and it keeps the last call's
+ * contents (nothing in it needs to start at zero): calls that overlap on one
+ * device, on different streams or threads, race and give wrong results.
+ * Errors: EBC_E_INVALID_ARG for null pointers, l < 0 or in_dtype not 0/1;
+ * EBC_E_NOMEM when ebc_eval_sets_bytes(n, l) > EBC_FIXED_SCRATCH_BYTES
+ * (about 110000 sets over a large ground set; nothing is enqueued);
+ * EBC_E_DEVICE if the array's address cannot be found or a launch fails;
+ * device-detected errors as for ebc_eval_sets. l = 0 is a no-op. */
+EBC_API ebc_status ebc_eval_sets_noalloc(ebc_dataset* ds, const int64_t* offsets, const int32_t* idx, int64_t l,
+                                         double* f_out, int32_t in_dtype, void* stream);
+
 /* Marginal gains Delta(c|S) = f(S u {c}) - f(S) (Sec. 3, Definition
  * "Discrete derivative") for candidates c, computed in the form
  * |V|^-1 sum_v max(0, m_v - d(v, c)) with m_v = min(||v||^2, min_{s in S} d(v,s)).

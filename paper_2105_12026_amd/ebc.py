@@ -23,6 +23,7 @@ DTYPES = {"f32": 0, "f16": 1, "bf16": 2, "fp8": 3}
 # dissimilarity -> ebc_dataset_create flags (EBC_FLAG_L1 = 1)
 DISTS = {"sqeuclidean": 0, "l1": 1}
 MAX_DIM = 4096  # EBC_MAX_DIM of include/ebc.h
+FIXED_SCRATCH_BYTES = 16 << 20  # EBC_FIXED_SCRATCH_BYTES of include/ebc.h
 ABI_FUNCTIONS = (
     "ebc_dataset_bytes", "ebc_dataset_create", "ebc_dataset_destroy", "ebc_eval_sets_bytes", "ebc_eval_sets",
     "ebc_eval_sets_in_dtype", "ebc_marginal_gains", "ebc_greedy", "ebc_three_sieves_bytes", "ebc_three_sieves",
@@ -34,7 +35,7 @@ ABI_FUNCTIONS = (
     "ebc_tune_cache_load", "ebc_tune_cache_save", "ebc_tune_cache_size", "ebc_request_bytes",
     "ebc_server_create", "ebc_server_destroy", "ebc_server_submit", "ebc_server_step", "ebc_server_poll",
     "ebc_server_stats", "ebc_server_now", "ebc_arena_create", "ebc_arena_alloc", "ebc_arena_free",
-    "ebc_arena_free_bytes", "ebc_arena_largest_free", "ebc_arena_destroy",
+    "ebc_arena_free_bytes", "ebc_arena_largest_free", "ebc_arena_destroy", "ebc_eval_sets_noalloc",
 )
 _NON_STATUS = ("ebc_dataset_bytes", "ebc_eval_sets_bytes", "ebc_three_sieves_bytes", "ebc_sieve_streaming_bytes",
                "ebc_status_string", "ebc_batch_bytes", "ebc_request_bytes", "ebc_server_now",
@@ -84,6 +85,7 @@ def lib() -> ctypes.CDLL:
         L.ebc_eval_sets_bytes.restype = sz
         L.ebc_eval_sets.argtypes = [P, P, P, i64, P, P, sz, P]
         L.ebc_eval_sets_in_dtype.argtypes = [P, P, P, i64, P, P, sz, P]
+        L.ebc_eval_sets_noalloc.argtypes = [P, P, P, i64, P, i32, P]
         L.ebc_three_sieves_bytes.argtypes = [i64, i64, i32]
         L.ebc_three_sieves_bytes.restype = sz
         L.ebc_sieve_streaming_bytes.argtypes = [i64, i32, ctypes.c_double, i64, i32]
@@ -293,6 +295,22 @@ class Dataset:
             scratch = _scratch(lib().ebc_eval_sets_bytes(self.n, max(l, 0)), self.x.device, stream)
         _check(fn(self._h, _ptr(offsets), _ptr(idx_arg), l, _ptr(out), _ptr(scratch), scratch.numel(),
                   _stream(stream)), "ebc_eval_sets")
+        return out
+
+    def eval_sets_noalloc(self, offsets: torch.Tensor, idx: torch.Tensor, out: torch.Tensor,
+                          stream=None, in_dtype: bool = False) -> torch.Tensor:
+        """f(S_j) as eval_sets, with the library's fixed device scratch instead of a
+        caller one (ebc_eval_sets_noalloc); ``out`` (float64 [l]) is required, and
+        offsets/idx must already be int64/int32 contiguous tensors on the device."""
+        for t, dt in ((offsets, torch.int64), (idx, torch.int32), (out, torch.float64)):
+            if t.dtype != dt or t.device != self.x.device or not t.is_contiguous():
+                raise ValueError(f"eval_sets_noalloc: expected a contiguous {dt} tensor on {self.x.device}")
+        l = offsets.numel() - 1
+        if out.numel() < max(l, 0):
+            raise ValueError("eval_sets_noalloc: out holds fewer than l values")
+        idx_arg = idx if idx.numel() > 0 else offsets  # any valid pointer when there are no members
+        _check(lib().ebc_eval_sets_noalloc(self._h, _ptr(offsets), _ptr(idx_arg), l, _ptr(out),
+                                           1 if in_dtype else 0, _stream(stream)), "ebc_eval_sets_noalloc")
         return out
 
     def marginal_gains(self, m: torch.Tensor | None = None, cand: torch.Tensor | None = None,
