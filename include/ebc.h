@@ -231,35 +231,37 @@ EBC_API ebc_status ebc_greedy(ebc_dataset* ds, int32_t k, int32_t* sel_out, doub
  * down the guesses (1+eps)^i in [m, k m], m = max_e f({e}), largest first,
  * after T consecutive rejections (at the smallest guess it stays); a point
  * joins while |S| < k and Delta(e|S) >= (v/2 - f(S)) / (k - |S|); the
- * stream ends early once |S| = k. Gains of stretches of `batch` points run
- * on the matrix cores in the dataset dtype; a point whose gain lies within
- * the dtype's error band of its bound is re-scored in float64 (direct
- * differences; the later points of the stretch that may need it join the
- * same list, up to 256) and decided on that value, so the decisions are
- * float64 ones in every dtype.
- * Blocking: the host decides between launches and the call returns when
- * the stream is done (work is ordered on `stream`).
+ * stream ends early once |S| = k.
+ * The stream is processed in stretches of `batch` points: one launch
+ * computes the float64 distances (direct differences) of the stretch's
+ * points to every point of V, and one launch walks the stretch in order on
+ * the device, deciding each point on its float64 gain against the float64
+ * minima of S. Decisions are therefore float64 ones whatever the dataset's
+ * distance dtype (the cast copy is not used). No host round trip happens
+ * between the launches; the call blocks once, at the end, for the counts.
  *   k            1 <= k <= n.
  *   eps          > 0, ratio of consecutive guesses minus 1.
  *   T            >= 1.
  *   m_max        m in f units; <= 0: computed (float64 best singleton).
  *   order        [device] int32 [n_order] indices into V (repeats allowed), or
  *                NULL for 0 .. n_order-1 (then n_order <= n).
- *   batch        points scored per gains launch; 0 = 1024; capped at n_pad.
+ *   batch        stream points per stretch; 0: up to 1024, as many as keep
+ *                the stretch's distances within 256 MiB (at least 32);
+ *                never more than n_order.
  *   sel_out      [device] int32 [k]: accepted points in arrival order.
  *   f_out        [device] float64 [k]: f(S) after each acceptance.
  *   count_out    [host] number of accepted points.
  *   examined_out [host] or NULL: points examined before the stream ended.
- *   scratch      [device] at least ebc_three_sieves_bytes(n, n_order, batch)
- *                bytes (the stream's indices, one stretch of gains and one
- *                float64 re-score list), 256-byte aligned, caller-owned;
+ *   scratch      [device] at least ebc_three_sieves_bytes(n, k, eps, n_order,
+ *                batch) bytes (one stretch's float64 distances, the float64
+ *                minima, the guesses), 256-byte aligned, caller-owned;
  *                ebc_three_sieves_bytes is host-only arithmetic, 0 for
  *                arguments out of range.
  * Errors: EBC_E_INVALID_ARG (arguments, scratch too small or unaligned),
  * EBC_E_INDEX (an order entry outside [0, n), detected on the host before
  * any work), EBC_E_DEVICE. The dataset state afterwards holds the summary
  * (usable by ebc_marginal_gains). */
-EBC_API size_t ebc_three_sieves_bytes(int64_t n, int64_t n_order, int32_t batch);
+EBC_API size_t ebc_three_sieves_bytes(int64_t n, int32_t k, double eps, int64_t n_order, int32_t batch);
 EBC_API ebc_status ebc_three_sieves(ebc_dataset* ds, int32_t k, double eps, int64_t T, double m_max,
                                     const int32_t* order, int64_t n_order, int32_t batch, int32_t* sel_out,
                                     double* f_out, int32_t* count_out, int64_t* examined_out, void* scratch,
@@ -270,19 +272,20 @@ EBC_API ebc_status ebc_three_sieves(ebc_dataset* ds, int32_t k, double eps, int6
  * one summary per guess v of the same grid as ebc_three_sieves, every
  * arriving point offered to each summary under the same rule, the stream
  * ending early once every summary is full; the best summary (largest f,
- * the largest v among equal f) is returned. Each summary keeps its own
- * float64 running minima on the device; decisions are float64 ones as in
- * ebc_three_sieves. Blocking, like ebc_three_sieves; arguments as there,
- * and:
+ * the largest v among equal f) is returned. Each stretch's float64
+ * distances are computed once and shared by every summary; the walk runs
+ * one workgroup per summary, each with its own float64 minima, so the
+ * decisions are float64 ones as in ebc_three_sieves. Blocking once at the
+ * end, like ebc_three_sieves; arguments as there, and:
  *   sel_out, f_out  [device] the best summary's points and f after each of
  *                   its acceptances;
  *   v_out           [host] or NULL: the best summary's guess v.
  *   scratch         [device] at least ebc_sieve_streaming_bytes(n, k, eps,
  *                   n_order, batch) bytes (host-only arithmetic; 0 for
  *                   arguments out of range), 256-byte aligned, caller-owned:
- *                   the stream's indices, and per guess (at most
+ *                   one stretch's float64 distances, and per guess (at most
  *                   floor(log k / log(1+eps)) + 2 of them) its float64 minima,
- *                   a stretch of gains, its members and f values.
+ *                   members, f values and state.
  * The dataset state afterwards holds the best summary's minima. */
 EBC_API size_t ebc_sieve_streaming_bytes(int64_t n, int32_t k, double eps, int64_t n_order, int32_t batch);
 EBC_API ebc_status ebc_sieve_streaming(ebc_dataset* ds, int32_t k, double eps, double m_max, const int32_t* order,

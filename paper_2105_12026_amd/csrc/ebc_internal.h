@@ -337,12 +337,6 @@ __host__ __device__ inline double window_tau(ebc_dtype dt) {
 }
 __host__ __device__ inline double window_tau_abs(ebc_dtype dt) { return dt == EBC_DT_F32 ? 1e-4 : 1e-2; }
 hipError_t launch_gains_out(const ebc_dataset* ds, int64_t n_cand, double* out, hipStream_t s);
-// float64 direct-difference gain sums (not divided by |V|) of points
-// items[0..W) (device list, valid indices, 1 <= W <= kWindowMax) into out[0..W)
-hipError_t launch_gain64_many(const ebc_dataset* ds, const int32_t* items, int32_t W, double* out, hipStream_t s);
-// add `item` as the t-th member: selection record, m_v update, f(S) into f[t]
-hipError_t launch_accept_one(const ebc_dataset* ds, int32_t item, int32_t t, int32_t* sel, double* f, double* gain,
-                             hipStream_t s);
 hipError_t launch_greedy_step(const ebc_dataset* ds, int32_t t, int32_t* sel_out, double* f_out,
                               double* gain_out, hipStream_t s, hipEvent_t ev_gains_done);
 // device scratch of one multi-set evaluation of l sets over n ground points

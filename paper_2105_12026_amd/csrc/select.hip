@@ -922,74 +922,6 @@ k_gains_out(int64_t n, int64_t n_cand, int64_t stride, int32_t v_splits, const d
     out[p] = g / double(n);
 }
 
-// ---- streaming optimisers: float64 gains of a list of points, acceptance ----
-// The list is staged as a re-score window, re-scored by the same kernels as
-// a greedy step's window, and each point's row sums added in row order.
-__global__ void __launch_bounds__(kWindowMax) k_many_stage(InstDesc c, const int32_t* __restrict__ items, int32_t W) {
-    const int j = threadIdx.x;
-    if (j < W) {
-        c.b.wfinal[j].g = 0.0;
-        c.b.wfinal[j].idx = items[j];
-        c.b.wfinal[j].pad = 0;
-    }
-    if (j == 0) c.b.state->window_count = W;
-}
-
-__global__ void __launch_bounds__(kWindowMax) k_many_sum(InstDesc c, int32_t W, double* __restrict__ out) {
-    const int j = threadIdx.x;
-    if (j >= W) return;
-    const int rows = rescore_rows(c, W);
-    double s = 0.0;
-    for (int blk = 0; blk < rows; ++blk) s += c.b.rpart[int64_t(blk) * kWindowMax + j];
-    out[j] = s;
-}
-
-__global__ void k_one_accept(InstDesc c, int32_t item, int32_t t) {
-    if (threadIdx.x == 0) {
-        c.b.state->cstar = item;
-        c.b.selected[item] = 1;
-        c.sel[t] = item;
-        if (c.gain) c.gain[t] = c.b.state->gstar / double(c.n);
-    }
-}
-
-hipError_t launch_gain64_many(const ebc_dataset* ds, const int32_t* items, int32_t W, double* out, hipStream_t s) {
-    InstDesc c;
-    fill_desc(ds, 0, nullptr, nullptr, nullptr, &c);
-    hipLaunchKernelGGL(k_many_stage, dim3(1), dim3(kWindowMax), 0, s, c, items, W);
-    if (long_path(c)) {
-        // the list length is known here: launch only the re-score that takes it
-        if (W <= split_window(c)) {  // small lists: two passes over slices of the dimension
-            hipLaunchKernelGGL(k_dist_window, dim3(c.nb, 16), dim3(kBlock), 0, s, c);
-            hipLaunchKernelGGL(k_rescore_split, dim3(c.nb), dim3(kBlock), 0, s, c);
-        } else {
-            hipLaunchKernelGGL(k_rescore_long, dim3(c.nb, 4 * kWindowMax / kRescoreGroup), dim3(kBlock), 0, s, c);
-        }
-    } else {
-        hipLaunchKernelGGL(k_rescore, dim3(c.nb), dim3(kBlock), 0, s, c);
-    }
-    hipLaunchKernelGGL(k_many_sum, dim3(1), dim3(kWindowMax), 0, s, c, W, out);
-    return hipGetLastError();
-}
-
-hipError_t launch_accept_one(const ebc_dataset* ds, int32_t item, int32_t t, int32_t* sel, double* f, double* gain,
-                             hipStream_t s) {
-    InstDesc c;
-    fill_desc(ds, t + 1, sel, f, gain, &c);
-    hipLaunchKernelGGL(k_one_accept, dim3(1), dim3(64), 0, s, c, item, t);
-    if (c.metric == 1) {
-        hipLaunchKernelGGL(k_update_l1, dim3(c.nb), dim3(kBlock), 0, s, c);
-    } else if (long_split(c)) {
-        hipLaunchKernelGGL(k_dist_slices, dim3(c.nb, update_slices(c)), dim3(kBlock), 0, s, c);
-        hipLaunchKernelGGL(k_update_split, dim3(c.nb), dim3(kBlock), 0, s, c);
-    } else if (wide_rows(c.k_pad))
-        hipLaunchKernelGGL(k_update_long, dim3(c.nb), dim3(kBlock), 0, s, c);
-    else
-        hipLaunchKernelGGL(k_update, dim3(c.nb), dim3(kBlock), 0, s, c);
-    hipLaunchKernelGGL(k_fsum, dim3(1), dim3(kBlock), 0, s, c, t);
-    return hipGetLastError();
-}
-
 hipError_t launch_gains_out(const ebc_dataset* ds, int64_t n_cand, double* out, hipStream_t s) {
     const unsigned nb = unsigned((n_cand + kBlock - 1) / kBlock);
     hipLaunchKernelGGL(k_gains_out, dim3(nb), dim3(kBlock), 0, s, ds->n, n_cand, ds->n_pad, ds->v_splits,

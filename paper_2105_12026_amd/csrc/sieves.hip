@@ -1,32 +1,31 @@
-// Three Sieves: a streaming optimiser for f (the paper cites it in Sec. 2 and
-// runs it beside greedy in the Sec. 6 case study). One summary S, a stream of
-// points of V, and a threshold v that walks down the grid of guesses
-// (1+eps)^i in [m, k m] (m = max_e f({e})) after T consecutive rejections;
-// a point joins while |S| < k and Delta(e|S) >= (v/2 - f(S)) / (k - |S|).
+// Streaming optimisers for f: Three Sieves (the paper cites it in Sec. 2 and
+// runs it beside greedy in the Sec. 6 case study) and Sieve Streaming (named
+// with greedy in Sec. 2 and Sec. 4.1 as an optimiser that scores many sets
+// per step).
 //
-// The stream is consumed in stretches. One marginal-gains launch scores the
-// next `batch` points against the current S (the same matrix-core kernels as
-// greedy, with a candidate list). The host then walks the stretch in order,
-// applying the rule. A point whose gain is within twice the dtype's
-// re-score half-width (relative to m) of its bound is re-scored in float64
-// by direct differences, and the decision uses that value; points clearly
-// above or below need no re-score. The first such point of a stretch takes
-// the later points of the stretch that may need it into the same re-score
-// list (the window re-score of a greedy step). At an acceptance the summary
-// grows (m_v update and f(S) in float64) and the next stretch starts right
-// after the accepted point, because every later gain changed. Rejections do
-// not change S, so the gains of a stretch stay valid until its first
-// acceptance.
+// Both walk a stream of points of V. Three Sieves keeps one summary S and a
+// threshold v that walks down the grid of guesses (1+eps)^i in [m, k m]
+// (m = max_e f({e})) after T consecutive rejections; Sieve Streaming keeps
+// one summary per guess. A point e joins summary S (guess v) while |S| < k
+// and
+//     Delta(e|S) >= (v/2 - f(S)) / (k - |S|),
+//     Delta(e|S) = |V|^-1 sum_v max(0, m_v - d(v, e))      (Sec. 3, Sec. 4.1)
+// with m_v the running minima of S u {e0}.
 //
-// Sieve Streaming (named with greedy in Sec. 2 and Sec. 4.1 as an optimiser
-// that scores many sets per step) keeps one summary per guess v and offers
-// every point to each of them under the same rule. Each summary has its own
-// running minima m^v (float64, on the device); scoring or growing summary v
-// loads m^v into the dataset state first. Each summary has its own stretch
-// of gains, re-scored only after that summary changes. The best summary
-// (first in grid order among equal f) is returned.
+// What a decision needs of the arriving point e is the distance vector
+// d(., e) over the ground set, and that vector does not depend on any
+// summary. So the stream is processed in stretches of points: one launch
+// computes the float64 distances of a stretch's points to every ground point
+// (direct differences, the same definition as the float64 re-score and the
+// oracle), and one launch with a workgroup per summary walks the stretch in
+// stream order, each workgroup clamping and summing its own minima against
+// each distance row, deciding, and on acceptance lowering its minima and
+// recomputing f(S) -- all in float64 on the device, so every decision is a
+// float64 one in every distance dtype, and no host round trip happens
+// between the first launch and the result. Distance rows are prefetched into
+// registers several points ahead (they do not depend on the decisions), so
+// the sequential walk waits only on its own reductions.
 #include <math.h>
-#include <string.h>
 
 #include <algorithm>
 #include <vector>
@@ -36,6 +35,357 @@
 using namespace ebc;
 
 namespace {
+
+constexpr int kST = 256;             // threads of the stream kernels
+constexpr int kDI = 32;              // stream points per distance tile
+constexpr int kDV = 64;              // ground points per distance tile
+constexpr int kDK = 16;              // dimensions per LDS stage of the distance tile
+constexpr int kRegMax = 16;          // ground points per thread kept in registers (n_pad <= 4096)
+constexpr size_t kStretchBytes = size_t(256) << 20;  // distance rows of one default stretch, at most
+
+// One summary's state, in the caller's scratch.
+struct Summary {
+    int32_t cnt;      // members so far
+    int32_t t;        // consecutive rejections (Three Sieves)
+    int32_t gi;       // index of the current guess (Three Sieves)
+    int32_t pad;
+    int64_t full_at;  // stream position of the k-th acceptance, -1 before
+    double fS;        // f of the summary
+};
+
+struct Result {
+    int32_t count;     // members of the returned summary
+    int32_t best;      // its index (0 for Three Sieves)
+    int64_t examined;  // points taken from the stream
+};
+
+__device__ __forceinline__ int64_t stream_row(const int32_t* __restrict__ order, int64_t p) {
+    return order ? int64_t(order[p]) : p;
+}
+
+// float64 sum over the 64 lanes; lane 0's value has a fixed association
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Distances of stream points pos + [0, cnt) to every ground point, float64
+// direct differences in dimension order, into D [cnt][n_pad] (columns >= n
+// are not written). A workgroup computes a 32 x 64 tile, both sides staged
+// through LDS 16 dimensions at a time (the next stage's values loaded into
+// registers while the current one is used); thread (ti, tv) owns stream
+// points ti + 16a and ground points tv + 16b. Nothing runs once every
+// summary is full.
+template <int METRIC>
+__global__ void __launch_bounds__(kST) k_stream_dist(const float* __restrict__ x, int64_t n, int32_t d,
+                                                     const int32_t* __restrict__ order, int64_t pos, int32_t cnt,
+                                                     int64_t n_pad, double* __restrict__ D,
+                                                     const Summary* __restrict__ sm, int32_t ns, int32_t k) {
+    __shared__ int open;
+    __shared__ double A[2][kDK][kDI];
+    __shared__ double B[2][kDK][kDV];
+    const int tid = threadIdx.x;
+    if (tid == 0) open = 0;
+    __syncthreads();
+    for (int j = tid; j < ns; j += kST)
+        if (sm[j].cnt < k) open = 1;
+    __syncthreads();
+    if (!open) return;
+
+    const int tv = tid & 15, ti = tid >> 4;
+    const int64_t v0 = int64_t(blockIdx.x) * kDV;
+    const int i0 = int(blockIdx.y) * kDI;
+    // loaders: stream row ar, dimensions ak, ak+1; ground row br, dimensions bk .. bk+3
+    const int ar = tid >> 3, ak = 2 * (tid & 7);
+    const int br = tid >> 2, bk = 4 * (tid & 3);
+    const float* __restrict__ arow = (i0 + ar < cnt) ? x + stream_row(order, pos + i0 + ar) * d : nullptr;
+    const float* __restrict__ brow = (v0 + br < n) ? x + (v0 + br) * d : nullptr;
+    float ra[2], rb[4];
+    auto load = [&](int k0) {
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int kk = k0 + ak + q;
+            ra[q] = (arow && kk < d) ? arow[kk] : 0.0f;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int kk = k0 + bk + q;
+            rb[q] = (brow && kk < d) ? brow[kk] : 0.0f;
+        }
+    };
+    auto store = [&](int buf) {
+#pragma unroll
+        for (int q = 0; q < 2; ++q) A[buf][ak + q][ar] = double(ra[q]);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) B[buf][bk + q][br] = double(rb[q]);
+    };
+
+    double acc[2][4];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+    const int nk = (d + kDK - 1) / kDK;
+    load(0);
+    store(0);
+    __syncthreads();
+    for (int c = 0; c < nk; ++c) {
+        const int buf = c & 1;
+        if (c + 1 < nk) load((c + 1) * kDK);
+#pragma unroll
+        for (int kk = 0; kk < kDK; ++kk) {
+            double a[2], b[4];
+#pragma unroll
+            for (int q = 0; q < 2; ++q) a[q] = A[buf][kk][ti + 16 * q];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) b[q] = B[buf][kk][tv + 16 * q];
+#pragma unroll
+            for (int qa = 0; qa < 2; ++qa)
+#pragma unroll
+                for (int qb = 0; qb < 4; ++qb) {
+                    const double df = a[qa] - b[qb];
+                    if (METRIC == 1)
+                        acc[qa][qb] += fabs(df);
+                    else
+                        acc[qa][qb] = fma(df, df, acc[qa][qb]);
+                }
+        }
+        // the other stage was last read before the previous barrier
+        if (c + 1 < nk) store(buf ^ 1);
+        __syncthreads();
+    }
+#pragma unroll
+    for (int qa = 0; qa < 2; ++qa) {
+        const int i = i0 + ti + 16 * qa;
+        if (i >= cnt) continue;
+#pragma unroll
+        for (int qb = 0; qb < 4; ++qb) {
+            const int64_t v = v0 + tv + 16 * qb;
+            if (v < n) D[int64_t(i) * n_pad + v] = acc[qa][qb];
+        }
+    }
+}
+
+// Arguments of the decision walk over one stretch.
+struct WalkArgs {
+    const double* D;       // [cnt][n_pad] distances of the stretch
+    int64_t n, n_pad;
+    int32_t cnt;           // points in the stretch
+    int32_t k;
+    int64_t pos;           // stream position of the stretch's first point
+    const int32_t* order;  // stream indices (null: 0, 1, ...)
+    const double* grid;    // guesses, largest first
+    int32_t J;             // guesses
+    int32_t pad;
+    int64_t T;             // Three Sieves: rejections before the next guess; 0: Sieve Streaming
+    const DevState* dst;   // L({e0}) of the dataset
+    Summary* sm;           // [summaries]
+    double* M;             // [summaries][n_pad] running minima
+    int32_t* sel;          // [summaries][k] members
+    double* fv;            // [summaries][k] f after each acceptance
+};
+
+// The rule for one point, given its float64 gain sum over V (uniform across
+// the workgroup). Returns true when the point joins.
+__device__ __forceinline__ bool decide(const WalkArgs& w, int j, const Summary& s, double gsum) {
+    const double g = gsum / double(w.n);
+    const double v = w.T > 0 ? w.grid[s.gi] : w.grid[j];
+    const double bound = (0.5 * v - s.fS) / double(w.k - s.cnt);
+    return g >= bound;
+}
+
+// Bookkeeping after a decision; returns true once the summary is full.
+__device__ __forceinline__ bool record(const WalkArgs& w, int j, Summary& s, bool take, int i, double msum) {
+    if (take) {
+        const double fS = w.dst->l0 - msum / double(w.n);
+        if (threadIdx.x == 0) {
+            w.sel[int64_t(j) * w.k + s.cnt] = int32_t(stream_row(w.order, w.pos + i));
+            w.fv[int64_t(j) * w.k + s.cnt] = fS;
+        }
+        s.fS = fS;
+        s.cnt += 1;
+        s.t = 0;
+        if (s.cnt == w.k) {
+            s.full_at = w.pos + i;
+            return true;
+        }
+    } else if (w.T > 0) {
+        if (++s.t >= w.T && s.gi + 1 < w.J) {
+            s.gi += 1;
+            s.t = 0;
+        }
+    }
+    return false;
+}
+
+// Workgroup-uniform float64 sum of one value per thread: lane 0 of each wave
+// writes its wave's sum, then every thread adds the four in wave order.
+__device__ __forceinline__ double block_sum(double v, double* slot) {
+    v = wave_sum(v);
+    if ((threadIdx.x & 63) == 0) slot[threadIdx.x >> 6] = v;
+    __syncthreads();
+    return ((slot[0] + slot[1]) + slot[2]) + slot[3];
+}
+
+// Decision walk, one workgroup per summary, thread t owning ground points
+// t + 256 r (r < R) with their minima in registers; rows of the next P
+// points in flight.
+template <int R, int P>
+__global__ void __launch_bounds__(kST) k_stream_walk(WalkArgs w) {
+    const int j = blockIdx.x;
+    Summary s = w.sm[j];
+    if (s.cnt >= w.k) return;
+    __shared__ double red[2][4];
+    __shared__ double fred[4];
+    const int tid = threadIdx.x;
+    double* __restrict__ m = w.M + int64_t(j) * w.n_pad;
+    double mr[R];
+    bool ok[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int64_t v = tid + int64_t(kST) * r;
+        ok[r] = v < w.n;
+        mr[r] = ok[r] ? m[v] : 0.0;
+    }
+    double row[P][R];
+    auto load_row = [&](int i, double (&dst)[R]) {
+        const double* __restrict__ src = w.D + int64_t(i) * w.n_pad + tid;
+#pragma unroll
+        for (int r = 0; r < R; ++r) dst[r] = ok[r] ? src[kST * r] : 0.0;
+    };
+#pragma unroll
+    for (int q = 0; q < P; ++q)
+        if (q < w.cnt) load_row(q, row[q]);
+    bool changed = false, stop = false;
+    for (int i0 = 0; i0 < w.cnt && !stop; i0 += P) {
+#pragma unroll
+        for (int q = 0; q < P; ++q) {
+            const int i = i0 + q;
+            if (stop || i >= w.cnt) break;
+            double p = 0.0;
+#pragma unroll
+            for (int r = 0; r < R; ++r) p += fmax(0.0, mr[r] - row[q][r]);
+            const double g = block_sum(p, red[i & 1]);
+            const bool take = decide(w, j, s, g);
+            double msum = 0.0;
+            if (take) {
+                double qs = 0.0;
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    mr[r] = fmin(mr[r], row[q][r]);
+                    qs += mr[r];
+                }
+                msum = block_sum(qs, fred);
+                changed = true;
+            }
+            stop = record(w, j, s, take, i, msum);
+            if (!stop && i + P < w.cnt) load_row(i + P, row[q]);
+        }
+    }
+    if (changed) {
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            if (ok[r]) m[tid + int64_t(kST) * r] = mr[r];
+    }
+    if (tid == 0) w.sm[j] = s;
+}
+
+// The same walk for ground sets above 256 * kRegMax points: minima in the
+// scratch, rows read as they are used (same per-thread summation order).
+__global__ void __launch_bounds__(kST) k_stream_walk_big(WalkArgs w) {
+    const int j = blockIdx.x;
+    Summary s = w.sm[j];
+    if (s.cnt >= w.k) return;
+    __shared__ double red[2][4];
+    __shared__ double fred[4];
+    const int tid = threadIdx.x;
+    double* __restrict__ m = w.M + int64_t(j) * w.n_pad;
+    for (int i = 0; i < w.cnt; ++i) {
+        const double* __restrict__ row = w.D + int64_t(i) * w.n_pad;
+        double p = 0.0;
+        for (int64_t v = tid; v < w.n; v += kST) p += fmax(0.0, m[v] - row[v]);
+        const double g = block_sum(p, red[i & 1]);
+        const bool take = decide(w, j, s, g);
+        double msum = 0.0;
+        if (take) {
+            double qs = 0.0;
+            for (int64_t v = tid; v < w.n; v += kST) {
+                const double mv = fmin(m[v], row[v]);
+                m[v] = mv;
+                qs += mv;
+            }
+            msum = block_sum(qs, fred);
+        }
+        if (record(w, j, s, take, i, msum)) break;
+    }
+    if (tid == 0) w.sm[j] = s;
+}
+
+// Every summary starts at S = {}: minima m0 = d(., e0), empty state.
+__global__ void __launch_bounds__(kST) k_stream_init(const double* __restrict__ m0, int64_t n_pad, int32_t ns,
+                                                     double* __restrict__ M, Summary* __restrict__ sm) {
+    const int64_t r = int64_t(blockIdx.x) * kST + threadIdx.x;
+    if (r < int64_t(ns) * n_pad) M[r] = m0[r % n_pad];
+    if (r < ns) {
+        Summary s;
+        s.cnt = 0;
+        s.t = 0;
+        s.gi = 0;
+        s.pad = 0;
+        s.full_at = -1;
+        s.fS = 0.0;
+        sm[r] = s;
+    }
+}
+
+// The returned summary (Sieve Streaming: the first in grid order with the
+// largest f), the points examined (the stream stops once every summary is
+// full), and its members and f values copied to the caller's outputs.
+__global__ void __launch_bounds__(kST) k_stream_finish(const Summary* __restrict__ sm, int32_t ns, int32_t k,
+                                                       int64_t n_order, const int32_t* __restrict__ sel,
+                                                       const double* __restrict__ fv, int32_t* __restrict__ sel_out,
+                                                       double* __restrict__ f_out, Result* __restrict__ res) {
+    __shared__ int best_s, count_s;
+    if (threadIdx.x == 0) {
+        int best = 0;
+        bool all_full = true;
+        int64_t last = -1;
+        for (int j = 0; j < ns; ++j) {
+            if (sm[j].fS > sm[best].fS) best = j;
+            if (sm[j].cnt < k)
+                all_full = false;
+            else if (sm[j].full_at > last)
+                last = sm[j].full_at;
+        }
+        res->count = sm[best].cnt;
+        res->best = best;
+        res->examined = all_full ? last + 1 : n_order;
+        best_s = best;
+        count_s = sm[best].cnt;
+    }
+    __syncthreads();
+    if (sel == sel_out) return;  // a single summary writes the outputs directly
+    for (int t = threadIdx.x; t < count_s; t += kST) {
+        sel_out[t] = sel[int64_t(best_s) * k + t];
+        f_out[t] = fv[int64_t(best_s) * k + t];
+    }
+}
+
+// The returned summary's minima into `out` (then loaded as the dataset state).
+__global__ void __launch_bounds__(kST) k_stream_take_m(const double* __restrict__ M, int64_t n_pad,
+                                                       const Result* __restrict__ res, double* __restrict__ out) {
+    const int64_t r = int64_t(blockIdx.x) * kST + threadIdx.x;
+    if (r < n_pad) out[r] = M[int64_t(res->best) * n_pad + r];
+}
+
+// The returned summary's members marked selected in the dataset state.
+__global__ void __launch_bounds__(kST) k_stream_mark(const int32_t* __restrict__ sel, const Result* __restrict__ res,
+                                                     uint8_t* __restrict__ selected) {
+    for (int t = threadIdx.x; t < res->count; t += kST) selected[sel[t]] = 1;
+}
+
+// ---- host side ----
 
 // Guesses (1+eps)^i, m <= (1+eps)^i <= k m, largest first.
 std::vector<double> sieve_grid(double m, int32_t k, double eps) {
@@ -48,126 +398,64 @@ std::vector<double> sieve_grid(double m, int32_t k, double eps) {
     return g;
 }
 
+// Most guesses (1+eps)^i in [m, k m] for any m > 0: floor(log k / log(1+eps)) + 1,
+// plus one for rounding in the logarithms that place the grid ends.
+int64_t max_guesses(int32_t k, double eps) { return int64_t(floor(log(double(k)) / log1p(eps))) + 2; }
+
+bool valid_n(int64_t n) { return n >= 1 && n < (int64_t(1) << 31) - kRowAlign; }
+
+size_t al256(size_t v) { return (v + 255) & ~size_t(255); }
+
+// Stream points per stretch: `batch`, or by default as many as keep the
+// stretch's distance rows within kStretchBytes (32 .. 1024); never more than
+// the stream.
+int32_t stretch_len(int64_t n_pad, int64_t n_order, int32_t batch) {
+    int64_t b = batch;
+    if (b == 0) b = std::min<int64_t>(1024, std::max<int64_t>(32, int64_t(kStretchBytes / (8 * size_t(n_pad)))));
+    return int32_t(std::max<int64_t>(1, std::min<int64_t>(b, n_order)));
+}
+
+// Scratch of one call with `ns` summaries (1 for Three Sieves) and J guesses.
+struct StreamLayout {
+    size_t d, m, sel, fv, sm, grid, res, total;
+};
+
+StreamLayout stream_layout(int64_t n_pad, int32_t k, int64_t ns, int64_t J, int32_t stretch) {
+    StreamLayout L;
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = o;
+        o += al256(bytes);
+        return at;
+    };
+    // the distance rows; also the returned minima at the end (n_pad <= stretch rows)
+    L.d = take(size_t(std::max<int64_t>(stretch, 1)) * size_t(n_pad) * sizeof(double));
+    L.m = take(size_t(ns) * size_t(n_pad) * sizeof(double));
+    L.sel = take(ns > 1 ? size_t(ns) * size_t(k) * sizeof(int32_t) : 0);
+    L.fv = take(ns > 1 ? size_t(ns) * size_t(k) * sizeof(double) : 0);
+    L.sm = take(size_t(ns) * sizeof(Summary));
+    L.grid = take(size_t(J) * sizeof(double));
+    L.res = take(sizeof(Result));
+    L.total = o;
+    return L;
+}
+
 hipError_t read_state(const ebc_dataset* ds, DevState* st, hipStream_t s) {
     hipError_t e = hipMemcpyAsync(st, ds->b.state, sizeof(DevState), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     return e;
 }
 
-// Device room for a float64 re-score list: indices and gain sums.
-constexpr size_t kListBytes = size_t(kWindowMax) * (sizeof(int32_t) + sizeof(double));
-
-// float64 gains in f units of points items[0..W), 1 <= W <= kWindowMax
-// (stream-synchronous); `list` is kListBytes of device scratch.
-hipError_t gain64_list(const ebc_dataset* ds, const int32_t* items, int32_t W, char* list, double* out,
-                       hipStream_t s) {
-    int32_t* d_items = reinterpret_cast<int32_t*>(list);
-    double* d_out = reinterpret_cast<double*>(list + size_t(kWindowMax) * sizeof(int32_t));
-    hipError_t e = hipMemcpyAsync(d_items, items, size_t(W) * sizeof(int32_t), hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = launch_gain64_many(ds, d_items, W, d_out, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(out, d_out, size_t(W) * sizeof(double), hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    for (int32_t j = 0; j < W; ++j) out[j] /= double(ds->n);
-    return e;
-}
-
-// The float64 gains a stretch needs, computed in lists. When point p of the
-// stretch falls inside its band, p and the later points of the stretch whose
-// gains lie in [lo, hi) (every bound the rule can still reach, widened by the
-// band) are re-scored together; their values hold until the summary changes,
-// which ends the stretch. A list holds at most twice the points examined
-// since the summary last changed (at least 8, at most kWindowMax), so short
-// gaps between acceptances re-score little that goes unused.
-struct Gain64Cache {
-    std::vector<double> g64;
-    std::vector<char> have;
-    std::vector<int32_t> items;
-    std::vector<int64_t> at;
-    std::vector<double> out;
-    explicit Gain64Cache(size_t n) : g64(n), have(n, 0) {}
-    void clear() { std::fill(have.begin(), have.end(), 0); }
-    hipError_t get(const ebc_dataset* ds, const double* gain, const int32_t* stream_items, int64_t p, int64_t len,
-                   double lo, double hi, int64_t since, char* list, hipStream_t s, double* g) {
-        if (!have[size_t(p)]) {
-            const int64_t cap = std::min<int64_t>(kWindowMax, std::max<int64_t>(8, 2 * since));
-            items.clear();
-            at.clear();
-            for (int64_t q = p; q < len && int64_t(at.size()) < cap; ++q)
-                if (!have[size_t(q)] && (q == p || (gain[q] >= lo && gain[q] < hi))) {
-                    items.push_back(stream_items[q]);
-                    at.push_back(q);
-                }
-            out.resize(at.size());
-            const hipError_t e = gain64_list(ds, items.data(), int32_t(at.size()), list, out.data(), s);
-            if (e != hipSuccess) return e;
-            for (size_t j = 0; j < at.size(); ++j) {
-                g64[size_t(at[j])] = out[j];
-                have[size_t(at[j])] = 1;
-            }
-        }
-        *g = g64[size_t(p)];
-        return hipSuccess;
-    }
-};
-
-size_t al256(size_t v) { return (v + 255) & ~size_t(255); }
-
-// Batch size a call uses: 0 selects 1024, and a stretch never exceeds n_pad.
-int32_t effective_batch(int64_t n_pad, int32_t batch) {
-    if (batch == 0) batch = 1024;
-    if (batch > n_pad) batch = int32_t(n_pad);
-    return batch;
-}
-
-bool valid_n(int64_t n) { return n >= 1 && n < (int64_t(1) << 31) - kRowAlign; }
-
-// Most guesses (1+eps)^i in [m, k m] for any m > 0: floor(log k / log(1+eps)) + 1,
-// plus one for rounding in the logarithms that place the grid ends.
-int64_t max_guesses(int32_t k, double eps) { return int64_t(floor(log(double(k)) / log1p(eps))) + 2; }
-
-// Device scratch of Three Sieves: stream indices, one stretch of gains, one re-score list.
-size_t three_sieves_scratch(int64_t n_order, int32_t batch) {
-    return al256(size_t(n_order) * sizeof(int32_t)) + al256(size_t(batch) * sizeof(double)) + kListBytes;
-}
-
-// Per summary of Sieve Streaming: m^v [n_pad] f64, gains of its stretch [batch]
-// f64, f [k] f64, members [k] i32.
-size_t sieve_summary_bytes(int64_t n_pad, int32_t k, int32_t batch) {
-    return al256(size_t(n_pad) * sizeof(double)) + al256(size_t(batch) * sizeof(double)) +
-           al256(size_t(k) * sizeof(double)) + al256(size_t(k) * sizeof(int32_t));
-}
-
-size_t sieve_streaming_scratch(int64_t n_pad, int32_t k, double eps, int64_t n_order, int32_t batch) {
-    return al256(size_t(n_order) * sizeof(int32_t)) +
-           size_t(max_guesses(k, eps)) * sieve_summary_bytes(n_pad, k, batch) + kListBytes;
-}
-
-// The stream's indices on the host (validated) and on the device, at the
-// start of the caller's scratch; *d_extra is the scratch after them.
-ebc_status prepare_stream(const ebc_dataset* ds, const int32_t* order, int64_t n_order, char* scratch, hipStream_t s,
-                          std::vector<int32_t>& h_order, int32_t** d_order, char** d_extra) {
-    h_order.assign(static_cast<size_t>(n_order), 0);
-    if (order && n_order > 0) {
-        if (hipMemcpyAsync(h_order.data(), order, size_t(n_order) * sizeof(int32_t), hipMemcpyDeviceToHost, s) !=
-                hipSuccess ||
-            hipStreamSynchronize(s) != hipSuccess)
-            return EBC_E_DEVICE;
-        for (int32_t v : h_order)
-            if (v < 0 || int64_t(v) >= ds->n) return EBC_E_INDEX;
-    } else {
-        for (int64_t i = 0; i < n_order; ++i) h_order[size_t(i)] = int32_t(i);
-    }
-    *d_order = reinterpret_cast<int32_t*>(scratch);
-    *d_extra = scratch + al256(size_t(n_order) * sizeof(int32_t));
-    if (n_order > 0 && hipMemcpyAsync(*d_order, h_order.data(), size_t(n_order) * sizeof(int32_t),
-                                      hipMemcpyHostToDevice, s) != hipSuccess)
+// The caller's stream indices, checked on the host before any work.
+ebc_status check_order(const ebc_dataset* ds, const int32_t* order, int64_t n_order, hipStream_t s) {
+    if (!order || n_order == 0) return EBC_OK;
+    std::vector<int32_t> h(static_cast<size_t>(n_order));
+    if (hipMemcpyAsync(h.data(), order, size_t(n_order) * sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
         return EBC_E_DEVICE;
+    for (int32_t v : h)
+        if (v < 0 || int64_t(v) >= ds->n) return EBC_E_INDEX;
     return EBC_OK;
-}
-
-// Host checks shared by both optimisers' scratch arguments.
-bool scratch_ok(const void* scratch, size_t have, size_t need) {
-    return scratch && reinterpret_cast<uintptr_t>(scratch) % 256 == 0 && have >= need;
 }
 
 // S = {} in the dataset state; m = max_e f({e}) unless given (> 0): one
@@ -185,13 +473,114 @@ ebc_status start_stream(ebc_dataset* ds, double* m_max, int32_t* sel_tmp, double
     return read_state(ds, st, s) == hipSuccess ? EBC_OK : EBC_E_DEVICE;
 }
 
+template <int R, int P>
+void launch_walk(int32_t ns, const WalkArgs& w, hipStream_t s) {
+    hipLaunchKernelGGL((k_stream_walk<R, P>), dim3(unsigned(ns)), dim3(kST), 0, s, w);
+}
+
+// Both optimisers: T > 0 runs Three Sieves (one summary, the guess walking
+// down after T rejections), T = 0 Sieve Streaming (one summary per guess).
+ebc_status run_stream(ebc_dataset* ds, int32_t k, double eps, int64_t T, double m_max, const int32_t* order,
+                      int64_t n_order, int32_t batch, int32_t* sel_out, double* f_out, int32_t* count_out,
+                      double* v_out, int64_t* examined_out, void* scratch, size_t scratch_bytes, hipStream_t s) {
+    if (!scratch || reinterpret_cast<uintptr_t>(scratch) % 256 != 0) return EBC_E_INVALID_ARG;
+    const int32_t stretch = stretch_len(ds->n_pad, n_order, batch);
+    const int64_t ns_max = T > 0 ? 1 : max_guesses(k, eps);
+    if (scratch_bytes < stream_layout(ds->n_pad, k, ns_max, max_guesses(k, eps), stretch).total)
+        return EBC_E_INVALID_ARG;
+    ebc_status st_ = check_order(ds, order, n_order, s);
+    if (st_ != EBC_OK) return st_;
+    DevState st;
+    if ((st_ = start_stream(ds, &m_max, sel_out, f_out, s, &st)) != EBC_OK) return st_;
+    if (st.error != 0) return EBC_OK;  // reported by ebc_sync_status
+    const std::vector<double> grid = sieve_grid(m_max, k, eps);
+    const int64_t J = int64_t(grid.size());
+    if (J == 0) return EBC_OK;
+    if (J > max_guesses(k, eps)) return EBC_E_INVALID_ARG;  // not reached: the grid spans a factor k
+    const int32_t ns = T > 0 ? 1 : int32_t(J);
+
+    const StreamLayout L = stream_layout(ds->n_pad, k, ns, J, stretch);
+    char* base = static_cast<char*>(scratch);
+    double* D = reinterpret_cast<double*>(base + L.d);
+    double* M = reinterpret_cast<double*>(base + L.m);
+    int32_t* sel = ns > 1 ? reinterpret_cast<int32_t*>(base + L.sel) : sel_out;
+    double* fv = ns > 1 ? reinterpret_cast<double*>(base + L.fv) : f_out;
+    Summary* sm = reinterpret_cast<Summary*>(base + L.sm);
+    double* d_grid = reinterpret_cast<double*>(base + L.grid);
+    Result* d_res = reinterpret_cast<Result*>(base + L.res);
+
+    if (hipMemcpyAsync(d_grid, grid.data(), size_t(J) * sizeof(double), hipMemcpyHostToDevice, s) != hipSuccess)
+        return EBC_E_DEVICE;
+    const int64_t init_n = std::max<int64_t>(int64_t(ns) * ds->n_pad, ns);
+    hipLaunchKernelGGL(k_stream_init, dim3(unsigned((init_n + kST - 1) / kST)), dim3(kST), 0, s, ds->b.m0, ds->n_pad,
+                       ns, M, sm);
+
+    WalkArgs w;
+    w.D = D;
+    w.n = ds->n;
+    w.n_pad = ds->n_pad;
+    w.k = k;
+    w.order = order;
+    w.grid = d_grid;
+    w.J = int32_t(J);
+    w.pad = 0;
+    w.T = T;
+    w.dst = ds->b.state;
+    w.sm = sm;
+    w.M = M;
+    w.sel = sel;
+    w.fv = fv;
+    const int64_t rpt = ds->n_pad / kST;  // ground points per thread of the walk
+    for (int64_t pos = 0; pos < n_order; pos += stretch) {
+        const int32_t cnt = int32_t(std::min<int64_t>(stretch, n_order - pos));
+        const dim3 g(unsigned(ds->n_pad / kDV), unsigned((cnt + kDI - 1) / kDI));
+        if (ds->metric == 1)
+            hipLaunchKernelGGL(k_stream_dist<1>, g, dim3(kST), 0, s, ds->x, ds->n, ds->d, order, pos, cnt, ds->n_pad,
+                               D, sm, ns, k);
+        else
+            hipLaunchKernelGGL(k_stream_dist<0>, g, dim3(kST), 0, s, ds->x, ds->n, ds->d, order, pos, cnt, ds->n_pad,
+                               D, sm, ns, k);
+        w.cnt = cnt;
+        w.pos = pos;
+        if (rpt <= 1)
+            launch_walk<1, 8>(ns, w, s);
+        else if (rpt <= 2)
+            launch_walk<2, 8>(ns, w, s);
+        else if (rpt <= 4)
+            launch_walk<4, 8>(ns, w, s);
+        else if (rpt <= 8)
+            launch_walk<8, 4>(ns, w, s);
+        else if (rpt <= kRegMax)
+            launch_walk<kRegMax, 2>(ns, w, s);
+        else
+            hipLaunchKernelGGL(k_stream_walk_big, dim3(unsigned(ns)), dim3(kST), 0, s, w);
+        if (hipGetLastError() != hipSuccess) return EBC_E_DEVICE;
+    }
+    hipLaunchKernelGGL(k_stream_finish, dim3(1), dim3(kST), 0, s, sm, ns, k, n_order, sel, fv, sel_out, f_out, d_res);
+    // the dataset state afterwards: the returned summary's minima and members
+    hipLaunchKernelGGL(k_stream_take_m, dim3(unsigned(ds->n_pad / kST)), dim3(kST), 0, s, M, ds->n_pad, d_res, D);
+    if (launch_load_m(ds, D, s) != hipSuccess) return EBC_E_DEVICE;
+    hipLaunchKernelGGL(k_stream_mark, dim3(1), dim3(kST), 0, s, sel_out, d_res, ds->b.selected);
+    Result res;
+    if (hipGetLastError() != hipSuccess ||
+        hipMemcpyAsync(&res, d_res, sizeof(Result), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return EBC_E_DEVICE;
+    *count_out = res.count;
+    if (v_out) *v_out = T > 0 ? 0.0 : grid[size_t(res.best)];
+    if (examined_out) *examined_out = res.examined;
+    ds->stats.steps = res.count;
+    return EBC_OK;
+}
+
 }  // namespace
 
 extern "C" {
 
-size_t ebc_three_sieves_bytes(int64_t n, int64_t n_order, int32_t batch) {
-    if (!valid_n(n) || n_order < 0 || batch < 0) return 0;
-    return three_sieves_scratch(n_order, effective_batch(pad_rows(n), batch));
+size_t ebc_three_sieves_bytes(int64_t n, int32_t k, double eps, int64_t n_order, int32_t batch) {
+    if (!valid_n(n) || k < 1 || int64_t(k) > n || !(eps > 0.0) || n_order < 0 || batch < 0) return 0;
+    const int64_t np = pad_rows(n);
+    return stream_layout(np, k, 1, max_guesses(k, eps), stretch_len(np, n_order, batch)).total;
 }
 
 ebc_status ebc_three_sieves(ebc_dataset* ds, int32_t k, double eps, int64_t T, double m_max, const int32_t* order,
@@ -201,93 +590,15 @@ ebc_status ebc_three_sieves(ebc_dataset* ds, int32_t k, double eps, int64_t T, d
     if (!sel_out || !f_out || n_order < 0 || (!order && n_order > ds->n)) return EBC_E_INVALID_ARG;
     *count_out = 0;
     if (examined_out) *examined_out = 0;
-    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    batch = effective_batch(ds->n_pad, batch);
-    if (!scratch_ok(scratch, scratch_bytes, three_sieves_scratch(n_order, batch))) return EBC_E_INVALID_ARG;
-
-    std::vector<int32_t> h_order;
-    int32_t* d_order = nullptr;
-    char* d_extra = nullptr;
-    const size_t gain_bytes = al256(size_t(batch) * sizeof(double));
-    ebc_status pst = prepare_stream(ds, order, n_order, static_cast<char*>(scratch), s, h_order, &d_order, &d_extra);
-    if (pst != EBC_OK) return pst;
-    double* d_gain = reinterpret_cast<double*>(d_extra);
-    char* d_list = d_extra + gain_bytes;
-    DevState st;
-    if ((pst = start_stream(ds, &m_max, sel_out, f_out, s, &st)) != EBC_OK) return pst;
-    if (st.error != 0) return EBC_OK;  // reported by ebc_sync_status
-    const std::vector<double> grid = sieve_grid(m_max, k, eps);
-    if (grid.empty()) return EBC_OK;
-    // Every gain is at most m (submodularity: Delta(e|S) <= f({e}) <= m), and
-    // the dtype's gains are within window_tau * (largest gain) of float64, so
-    // a point whose gain is more than 2 window_tau m away from its bound is
-    // decided without a float64 re-score: every decision is the float64 one.
-    const double tol = 2.0 * window_tau(ds->dt) * m_max;
-
-    std::vector<double> h_gain(static_cast<size_t>(batch));
-    Gain64Cache c64(static_cast<size_t>(batch));
-    size_t j = 0;
-    int64_t t = 0, pos = 0, examined = 0, last = 0;
-    int32_t nsel = 0;
-    double fS = 0.0;
-    // stretch length: twice the last gap between acceptances (at least 64),
-    // doubled after every stretch without one, at most `batch`; only the
-    // amount of discarded work depends on it, never a decision
-    int64_t stretch = std::min<int64_t>(batch, 256);
-    while (pos < n_order && nsel < k) {
-        const int64_t cnt = std::min<int64_t>(stretch, n_order - pos);
-        if (launch_gains(ds, d_order + pos, cnt, s) != hipSuccess || launch_gains_out(ds, cnt, d_gain, s) != hipSuccess ||
-            hipMemcpyAsync(h_gain.data(), d_gain, size_t(cnt) * sizeof(double), hipMemcpyDeviceToHost, s) !=
-                hipSuccess ||
-            hipStreamSynchronize(s) != hipSuccess)
-            return EBC_E_DEVICE;
-        c64.clear();
-        int64_t next = pos + cnt;
-        for (int64_t i = 0; i < cnt && nsel < k; ++i) {
-            ++examined;
-            const int32_t item = h_order[size_t(pos + i)];
-            const double v = grid[j];
-            const double bound = (0.5 * v - fS) / double(k - nsel);
-            const double g = h_gain[size_t(i)];
-            bool take = g >= bound + tol;  // clearly above: the float64 gain is too
-            if (!take && g >= bound - tol) {
-                // until the next acceptance the bound can only fall, to that of the last guess
-                const double lowest = (0.5 * grid.back() - fS) / double(k - nsel);
-                double g64 = 0.0;
-                if (c64.get(ds, h_gain.data(), h_order.data() + pos, i, cnt, lowest - tol, bound + tol,
-                            pos + i + 1 - last, d_list, s, &g64) != hipSuccess)
-                    return EBC_E_DEVICE;
-                take = g64 >= bound;
-            }
-            if (take) {
-                if (launch_accept_one(ds, item, nsel, sel_out, f_out, nullptr, s) != hipSuccess ||
-                    hipMemcpyAsync(&fS, f_out + nsel, sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
-                    hipStreamSynchronize(s) != hipSuccess)
-                    return EBC_E_DEVICE;
-                ++nsel;
-                t = 0;
-                next = pos + i + 1;  // later gains are stale: rescore from the next point
-                stretch = std::min<int64_t>(batch, std::max<int64_t>(64, 2 * (next - last)));
-                last = next;
-                break;
-            }
-            if (++t >= T && j + 1 < grid.size()) {
-                ++j;
-                t = 0;
-            }
-        }
-        if (next == pos + cnt) stretch = std::min<int64_t>(batch, 2 * stretch);
-        pos = next;
-    }
-    *count_out = nsel;
-    if (examined_out) *examined_out = examined;
-    ds->stats.steps = nsel;
-    return EBC_OK;
+    return run_stream(ds, k, eps, T, m_max, order, n_order, batch, sel_out, f_out, count_out, nullptr, examined_out,
+                      scratch, scratch_bytes, reinterpret_cast<hipStream_t>(stream));
 }
 
 size_t ebc_sieve_streaming_bytes(int64_t n, int32_t k, double eps, int64_t n_order, int32_t batch) {
     if (!valid_n(n) || k < 1 || int64_t(k) > n || !(eps > 0.0) || n_order < 0 || batch < 0) return 0;
-    return sieve_streaming_scratch(pad_rows(n), k, eps, n_order, effective_batch(pad_rows(n), batch));
+    const int64_t np = pad_rows(n);
+    const int64_t J = max_guesses(k, eps);
+    return stream_layout(np, k, J, J, stretch_len(np, n_order, batch)).total;
 }
 
 ebc_status ebc_sieve_streaming(ebc_dataset* ds, int32_t k, double eps, double m_max, const int32_t* order,
@@ -299,115 +610,8 @@ ebc_status ebc_sieve_streaming(ebc_dataset* ds, int32_t k, double eps, double m_
     *count_out = 0;
     if (v_out) *v_out = 0.0;
     if (examined_out) *examined_out = 0;
-    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    batch = effective_batch(ds->n_pad, batch);
-    if (!scratch_ok(scratch, scratch_bytes, sieve_streaming_scratch(ds->n_pad, k, eps, n_order, batch)))
-        return EBC_E_INVALID_ARG;
-
-    // the grid needs m before the per-summary buffers are laid out
-    DevState st;
-    ebc_status pst = start_stream(ds, &m_max, sel_out, f_out, s, &st);
-    if (pst != EBC_OK) return pst;
-    if (st.error != 0) return EBC_OK;  // reported by ebc_sync_status
-    const std::vector<double> grid = sieve_grid(m_max, k, eps);
-    const int64_t J = int64_t(grid.size());
-    if (J == 0) return EBC_OK;
-    if (J > max_guesses(k, eps)) return EBC_E_INVALID_ARG;  // not reached: the grid spans a factor k
-
-    auto al = al256;
-    const size_t m_bytes = al(size_t(ds->n_pad) * sizeof(double)), g_bytes = al(size_t(batch) * sizeof(double));
-    const size_t f_bytes = al(size_t(k) * sizeof(double));
-    const size_t per = sieve_summary_bytes(ds->n_pad, k, batch);
-    std::vector<int32_t> h_order;
-    int32_t* d_order = nullptr;
-    char* d_extra = nullptr;
-    pst = prepare_stream(ds, order, n_order, static_cast<char*>(scratch), s, h_order, &d_order, &d_extra);
-    if (pst != EBC_OK) return pst;
-    auto m_of = [&](int64_t j) { return reinterpret_cast<double*>(d_extra + j * per); };
-    auto g_of = [&](int64_t j) { return reinterpret_cast<double*>(d_extra + j * per + m_bytes); };
-    auto f_of = [&](int64_t j) { return reinterpret_cast<double*>(d_extra + j * per + m_bytes + g_bytes); };
-    auto s_of = [&](int64_t j) { return reinterpret_cast<int32_t*>(d_extra + j * per + m_bytes + g_bytes + f_bytes); };
-    char* d_list = d_extra + size_t(J) * per;
-    const size_t n_bytes = size_t(ds->n) * sizeof(double);
-    for (int64_t j = 0; j < J; ++j)  // every summary starts at S = {}: m^v = the current minima
-        if (hipMemcpyAsync(m_of(j), ds->b.m64, n_bytes, hipMemcpyDeviceToDevice, s) != hipSuccess)
-            return EBC_E_DEVICE;
-
-    const double tol = 2.0 * window_tau(ds->dt) * m_max;  // as in ebc_three_sieves
-    std::vector<std::vector<double>> h_gain(size_t(J), std::vector<double>(static_cast<size_t>(batch)));
-    std::vector<Gain64Cache> c64(size_t(J), Gain64Cache(static_cast<size_t>(batch)));
-    std::vector<int64_t> base(size_t(J), 0), len(size_t(J), 0), stretch(size_t(J), std::min<int64_t>(batch, 256));
-    std::vector<int64_t> last(size_t(J), 0);
-    std::vector<int32_t> cnt(size_t(J), 0);
-    std::vector<double> fS(size_t(J), 0.0);
-    int64_t loaded = -1, full = 0, examined = 0;
-    auto load = [&](int64_t j) -> hipError_t {  // summary j's minima into the dataset state
-        if (loaded == j) return hipSuccess;
-        loaded = j;
-        return launch_load_m(ds, m_of(j), s);
-    };
-    for (int64_t i = 0; i < n_order && full < J; ++i) {
-        ++examined;
-        const int32_t item = h_order[size_t(i)];
-        for (int64_t j = 0; j < J; ++j) {
-            if (cnt[size_t(j)] == k) continue;
-            if (!(i >= base[size_t(j)] && i < base[size_t(j)] + len[size_t(j)])) {
-                // gains of summary j for the next stretch of the stream
-                if (len[size_t(j)] > 0 && i == base[size_t(j)] + len[size_t(j)])
-                    stretch[size_t(j)] = std::min<int64_t>(batch, 2 * stretch[size_t(j)]);
-                const int64_t L = std::min<int64_t>(stretch[size_t(j)], n_order - i);
-                if (load(j) != hipSuccess || launch_gains(ds, d_order + i, L, s) != hipSuccess ||
-                    launch_gains_out(ds, L, g_of(j), s) != hipSuccess ||
-                    hipMemcpyAsync(h_gain[size_t(j)].data(), g_of(j), size_t(L) * sizeof(double),
-                                   hipMemcpyDeviceToHost, s) != hipSuccess ||
-                    hipStreamSynchronize(s) != hipSuccess)
-                    return EBC_E_DEVICE;
-                base[size_t(j)] = i;
-                len[size_t(j)] = L;
-                c64[size_t(j)].clear();
-            }
-            const double bound = (0.5 * grid[size_t(j)] - fS[size_t(j)]) / double(k - cnt[size_t(j)]);
-            const double g = h_gain[size_t(j)][size_t(i - base[size_t(j)])];
-            bool take = g >= bound + tol;
-            if (!take && g >= bound - tol) {
-                // summary j's bound holds until it changes
-                const int64_t b0 = base[size_t(j)];
-                double g64 = 0.0;
-                if ((!c64[size_t(j)].have[size_t(i - b0)] && load(j) != hipSuccess) ||
-                    c64[size_t(j)].get(ds, h_gain[size_t(j)].data(), h_order.data() + b0, i - b0, len[size_t(j)],
-                                       bound - tol, bound + tol, i + 1 - last[size_t(j)], d_list, s,
-                                       &g64) != hipSuccess)
-                    return EBC_E_DEVICE;
-                take = g64 >= bound;
-            }
-            if (!take) continue;
-            const int32_t t = cnt[size_t(j)];
-            if (load(j) != hipSuccess || launch_accept_one(ds, item, t, s_of(j), f_of(j), nullptr, s) != hipSuccess ||
-                hipMemcpyAsync(m_of(j), ds->b.m64, n_bytes, hipMemcpyDeviceToDevice, s) != hipSuccess ||
-                hipMemcpyAsync(&fS[size_t(j)], f_of(j) + t, sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
-                hipStreamSynchronize(s) != hipSuccess)
-                return EBC_E_DEVICE;
-            if (++cnt[size_t(j)] == k) ++full;
-            len[size_t(j)] = 0;  // its later gains are stale
-            stretch[size_t(j)] = std::min<int64_t>(batch, std::max<int64_t>(64, 2 * (i + 1 - last[size_t(j)])));
-            last[size_t(j)] = i + 1;
-        }
-    }
-    int64_t best = 0;
-    for (int64_t j = 1; j < J; ++j)
-        if (fS[size_t(j)] > fS[size_t(best)]) best = j;
-    const int32_t nb = cnt[size_t(best)];
-    if ((nb > 0 && (hipMemcpyAsync(sel_out, s_of(best), size_t(nb) * sizeof(int32_t), hipMemcpyDeviceToDevice, s) !=
-                        hipSuccess ||
-                    hipMemcpyAsync(f_out, f_of(best), size_t(nb) * sizeof(double), hipMemcpyDeviceToDevice, s) !=
-                        hipSuccess)) ||
-        load(best) != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
-        return EBC_E_DEVICE;
-    *count_out = nb;
-    if (v_out) *v_out = grid[size_t(best)];
-    if (examined_out) *examined_out = examined;
-    ds->stats.steps = nb;
-    return EBC_OK;
+    return run_stream(ds, k, eps, 0, m_max, order, n_order, batch, sel_out, f_out, count_out, v_out, examined_out,
+                      scratch, scratch_bytes, reinterpret_cast<hipStream_t>(stream));
 }
 
 }  // extern "C"

@@ -86,7 +86,7 @@ def lib() -> ctypes.CDLL:
         L.ebc_eval_sets.argtypes = [P, P, P, i64, P, P, sz, P]
         L.ebc_eval_sets_in_dtype.argtypes = [P, P, P, i64, P, P, sz, P]
         L.ebc_eval_sets_noalloc.argtypes = [P, P, P, i64, P, i32, P]
-        L.ebc_three_sieves_bytes.argtypes = [i64, i64, i32]
+        L.ebc_three_sieves_bytes.argtypes = [i64, i32, ctypes.c_double, i64, i32]
         L.ebc_three_sieves_bytes.restype = sz
         L.ebc_sieve_streaming_bytes.argtypes = [i64, i32, ctypes.c_double, i64, i32]
         L.ebc_sieve_streaming_bytes.restype = sz
@@ -339,7 +339,7 @@ class Dataset:
         f = torch.empty(k, dtype=torch.float64, device=dev)
         cnt = ctypes.c_int32(0)
         seen = ctypes.c_int64(0)
-        nb = int(lib().ebc_three_sieves_bytes(self.n, n_order, int(batch)))
+        nb = int(lib().ebc_three_sieves_bytes(self.n, int(k), float(eps), n_order, int(batch)))
         scratch = _scratch(nb, dev, stream)
         _check(lib().ebc_three_sieves(self._h, int(k), float(eps), int(T), float(m_max), _ptr(order), n_order,
                                       int(batch), _ptr(sel), _ptr(f), ctypes.byref(cnt), ctypes.byref(seen),

@@ -101,19 +101,24 @@ def test_scratch_size_queries(L):
     assert L.ebc_eval_sets_bytes(0, 10) == 0
     assert L.ebc_eval_sets_bytes(1000, -1) == 0
     assert L.ebc_eval_sets_bytes(1000, 2 * 10 ** 6) > L.ebc_eval_sets_bytes(1000, 10 ** 6)
-    # Three Sieves: stream indices + one stretch of float64 gains + a re-score list
-    t = L.ebc_three_sieves_bytes(1000, 1000, 0)
-    assert t >= 1000 * 4 + 1024 * 8 and t % 256 == 0
-    assert L.ebc_three_sieves_bytes(1000, 1000, 64) < t     # a shorter stretch
-    assert L.ebc_three_sieves_bytes(0, 10, 0) == 0
-    assert L.ebc_three_sieves_bytes(100, -1, 0) == 0
-    # Sieve Streaming: per guess (at most floor(log k / log(1+eps)) + 2) its minima,
-    # a stretch of gains, k members and k f values
+    # Three Sieves: one stretch of float64 distance rows (1000 stream points x
+    # n_pad 1024), the float64 minima, the summary state, the guesses
     k, eps, n = 50, 0.1, 1000
     guesses = int(__import__("math").floor(__import__("math").log(k) / __import__("math").log1p(eps))) + 2
+    t = L.ebc_three_sieves_bytes(n, k, eps, n, 0)
+    assert t % 256 == 0
+    assert n * 1024 * 8 + 1024 * 8 + guesses * 8 <= t <= n * 1024 * 8 + 1024 * 8 + guesses * 8 + 4 * 256
+    assert L.ebc_three_sieves_bytes(n, k, eps, n, 64) < t      # a shorter stretch
+    assert L.ebc_three_sieves_bytes(n, k, eps, 100, 0) < t     # a stream shorter than the default stretch
+    assert L.ebc_three_sieves_bytes(0, k, eps, 10, 0) == 0
+    assert L.ebc_three_sieves_bytes(100, k, eps, -1, 0) == 0
+    assert L.ebc_three_sieves_bytes(100, 0, eps, 10, 0) == 0
+    assert L.ebc_three_sieves_bytes(100, k, 0.0, 10, 0) == 0
+    # Sieve Streaming: the same stretch, and per guess (at most
+    # floor(log k / log(1+eps)) + 2) its minima, k members, k f values, state
     s = L.ebc_sieve_streaming_bytes(n, k, eps, n, 0)
-    per = 1024 * 8 + 1024 * 8 + 512 + 256
-    assert s >= guesses * per and s < guesses * per + 1024 * 4 + 8192
+    need = n * 1024 * 8 + guesses * (1024 * 8 + k * 4 + k * 8 + 32) + guesses * 8
+    assert need <= s < need + 7 * 256
     assert L.ebc_sieve_streaming_bytes(n, k, 0.5, n, 0) < s   # fewer guesses
     assert L.ebc_sieve_streaming_bytes(n, 0, eps, n, 0) == 0
     assert L.ebc_sieve_streaming_bytes(n, n + 1, eps, n, 0) == 0
