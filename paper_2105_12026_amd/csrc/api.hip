@@ -175,7 +175,7 @@ ebc_status ebc_set_gains_variant(ebc_dataset* ds, int32_t variant) {
     return EBC_OK;
 }
 
-int32_t ebc_gains_variant_count(ebc_dtype dt) { return dt == EBC_DT_F32 ? 1 : 4; }
+int32_t ebc_gains_variant_count(ebc_dtype dt) { return dt == EBC_DT_F32 ? 1 : 5; }
 
 ebc_status ebc_profile_enable(ebc_dataset* ds, int32_t on) {
     if (!ds) return EBC_E_INVALID_ARG;

@@ -586,6 +586,194 @@ __device__ __forceinline__ void gains_lp_pp_body(const GainsArgs& ga, int64_t bi
     store_partials<CB>(ga, wbase, split, col, half, acc_sum);
 }
 
+// ---------------------------------------------------------------------------
+// Interleaved variant (4): one wave keeps its matrix unit and its vector ALU
+// busy together. A column block's matrix instructions are issued alternately
+// with the bound test of the previous block's tiles (max over the 16 values
+// of each lane, one compare and a wave-wide ballot: all in one basic block,
+// so the scheduler can put the test between the MFMAs, where it runs while
+// they execute); the clamp-and-sum then runs only for a previous tile with a
+// value above its bound. Both column blocks' operands of a ground tile are
+// read from LDS right after the tile's barrier. The previous block's values
+// carry over tile boundaries, and the very first test sees -inf (no tile to
+// sum). Per-lane sums are added in column-block order with the same
+// arithmetic as clamp_sum16, so gains are bitwise those of the other
+// variants.
+// ---------------------------------------------------------------------------
+template <int CB>
+__device__ __forceinline__ void sp_test(const floatx16 (&acc)[CB], float lo, uint64_t (&hit)[CB]) {
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb) {
+        float m = fmaxf(fmaxf(acc[cb][0], acc[cb][1]), acc[cb][2]);
+#pragma unroll
+        for (int r = 3; r < 15; r += 2) m = fmaxf(fmaxf(m, acc[cb][r]), acc[cb][r + 1]);
+        m = fmaxf(m, acc[cb][15]);
+        hit[cb] = __builtin_amdgcn_ballot_w64(m > lo);
+    }
+}
+
+template <int CB>
+__device__ __forceinline__ void sp_sum(const floatx16 (&acc)[CB], float lo, float hi, const uint64_t (&hit)[CB],
+                                       float (&acc_sum)[CB][16]) {
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb) {
+        if (hit[cb] == 0) continue;
+        float t[16];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) t[r] = __builtin_amdgcn_fmed3f(acc[cb][r], lo, hi) - lo;
+        asm volatile(""
+                     : "+v"(t[0]), "+v"(t[1]), "+v"(t[2]), "+v"(t[3]), "+v"(t[4]), "+v"(t[5]), "+v"(t[6]),
+                       "+v"(t[7]), "+v"(t[8]), "+v"(t[9]), "+v"(t[10]), "+v"(t[11]), "+v"(t[12]), "+v"(t[13]),
+                       "+v"(t[14]), "+v"(t[15]));
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc_sum[cb][r] += t[r];
+    }
+}
+
+// One column block: MFMAs into acc, interleaved with the test of pacc (the
+// previous block, bounds plo/phi), then the previous block's clamp-and-sum
+// where the test found values above the bound.
+template <class G, int DT, int KC, int CB>
+__device__ __forceinline__ void sp_colb(const uint4 (&b)[G::HU], int sb, const uint4 (&a)[CB][G::HU],
+                                        const floatx16 (&cinit)[CB], const int (&sa)[CB], floatx16 (&acc)[CB],
+                                        const floatx16 (&pacc)[CB], float plo, float phi,
+                                        float (&acc_sum)[CB][16]) {
+    using T = Lp<DT>;
+    constexpr int NMF = KC * CB;     // matrix instructions of the block
+    constexpr int NVA = 12 * CB;     // test instructions of the previous block
+    constexpr int PER = (NVA + NMF - 1) / NMF;
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb) acc[cb] = cinit[cb];
+#pragma unroll
+    for (int q = 0; q < KC; ++q)
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) acc[cb] = mfma_main<DT>(&a[cb][q * T::kU4], &b[q * T::kU4], acc[cb], sa[cb], sb);
+    uint64_t hit[CB];
+    sp_test<CB>(pacc, plo, hit);
+#pragma unroll
+    for (int i = 0; i < NMF; ++i) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);    // one MFMA
+        __builtin_amdgcn_sched_group_barrier(0x002, PER, 0);  // then part of the test
+    }
+    uint64_t any = 0;
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb) any |= hit[cb];
+    if (any) sp_sum<CB>(pacc, plo, phi, hit, acc_sum);
+}
+
+// One ground tile (two column blocks) of the interleaved variant.
+template <class G, int DT, int KC, int CB>
+__device__ __forceinline__ void sp_tile(int64_t t, int64_t nt, int64_t t_begin, int wave, int lane, int col, int half,
+                                        const uint4* __restrict__ xqt, const float* __restrict__ ha,
+                                        const float* __restrict__ hm, const int* __restrict__ sc, const uint4* st,
+                                        uint4* next2, const uint4 (&a)[CB][G::HU], const floatx16 (&cinit)[CB],
+                                        const int (&sa)[CB], float (&acc_sum)[CB][16], floatx16 (&accA)[CB],
+                                        floatx16 (&accB)[CB], float& loB, float& hiB) {
+    constexpr int HU = G::HU, VT = G::VT;
+    static_assert(VT == 64, "two column blocks per ground tile");
+    if (t + 1 < nt)
+        wait_vmcnt<G::L>();
+    else
+        wait_vmcnt<0>();
+    ring_barrier();
+    if (t + 2 < nt) copy_stage<G>(wave, lane, t_begin + t + 2, xqt, ha, hm, sc, next2);
+    const float* st_ha = reinterpret_cast<const float*>(st + G::OFF_HA);
+    const float* st_hm = reinterpret_cast<const float*>(st + G::OFF_HM);
+    const int* st_sc = reinterpret_cast<const int*>(st + G::OFF_SC);
+    uint4 b0[HU], b1[HU];
+#pragma unroll
+    for (int u = 0; u < HU; ++u) b0[u] = st[(half * HU + u) * VT + col];
+#pragma unroll
+    for (int u = 0; u < HU; ++u) b1[u] = st[(half * HU + u) * VT + 32 + col];
+    const float ha0 = st_ha[col], hm0 = st_hm[col], ha1 = st_ha[32 + col], hm1 = st_hm[32 + col];
+    const int sb0 = G::kFp8 ? st_sc[col] : 127, sb1 = G::kFp8 ? st_sc[32 + col] : 127;
+    const float lo0 = -ha0, hi0 = hm0 - ha0;
+    // column block 0 (into accA) with the previous tile's block 1 (accB)
+    sp_colb<G, DT, KC, CB>(b0, sb0, a, cinit, sa, accA, accB, loB, hiB, acc_sum);
+    // column block 1 (into accB) with block 0 (accA)
+    sp_colb<G, DT, KC, CB>(b1, sb1, a, cinit, sa, accB, accA, lo0, hi0, acc_sum);
+    loB = -ha1;
+    hiB = hm1 - ha1;
+}
+
+template <int DT, int KC, int CB>
+__device__ __forceinline__ void gains_lp_sp_body(const GainsArgs& ga, int64_t bid) {
+    const uint4* __restrict__ xqt = static_cast<const uint4*>(ga.xq);
+    const float* __restrict__ ha = ga.ha;
+    const float* __restrict__ hm = ga.hm;
+    const int* __restrict__ sc = ga.scale;
+    using G = LpGeom<DT, KC, CB>;
+    using T = Lp<DT>;
+    constexpr int HU = G::HU, VT = G::VT;
+    static_assert(HU == KC * T::kU4, "lane half-row must hold KC chunks");
+
+    __shared__ uint4 lds0[G::STAGE];
+    __shared__ uint4 lds1[G::STAGE];
+    __shared__ uint4 lds2[G::STAGE];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform per wave: scalar copy branches
+    const int col = lane & 31;
+    const int half = lane >> 5;
+    const int split = int(bid % ga.v_splits);
+    const int64_t ctile = bid / ga.v_splits;
+    const int64_t wbase = ctile * G::CAND_TILE + int64_t(wave) * (32 * CB);
+
+    uint4 a[CB][HU];
+    floatx16 cinit[CB];
+    int sa[CB];
+    load_candidates<G, DT, CB>(ga, wbase, col, half, a, cinit, sa);
+    float acc_sum[CB][16];
+    floatx16 accA[CB], accB[CB];
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            acc_sum[cb][r] = 0.0f;
+            accB[cb][r] = -INFINITY;  // no previous block yet: its test finds nothing
+        }
+    float loB = 0.0f, hiB = 0.0f;
+
+    const int64_t v_begin = int64_t(split) * ga.chunk;
+    int64_t v_end = v_begin + ga.chunk;
+    if (v_end > ga.n_pad) v_end = ga.n_pad;
+    const int64_t t_begin = v_begin / VT;
+    const int64_t nt = v_end > v_begin ? (v_end - v_begin) / VT : 0;
+
+    if (nt > 0) copy_stage<G>(wave, lane, t_begin, xqt, ha, hm, sc, lds0);
+    if (nt > 1) copy_stage<G>(wave, lane, t_begin + 1, xqt, ha, hm, sc, lds1);
+    for (int64_t t = 0; t < nt; t += 3) {
+        sp_tile<G, DT, KC, CB>(t, nt, t_begin, wave, lane, col, half, xqt, ha, hm, sc, lds0, lds2, a, cinit, sa,
+                               acc_sum, accA, accB, loB, hiB);
+        if (t + 1 < nt)
+            sp_tile<G, DT, KC, CB>(t + 1, nt, t_begin, wave, lane, col, half, xqt, ha, hm, sc, lds1, lds0, a, cinit,
+                                   sa, acc_sum, accA, accB, loB, hiB);
+        if (t + 2 < nt)
+            sp_tile<G, DT, KC, CB>(t + 2, nt, t_begin, wave, lane, col, half, xqt, ha, hm, sc, lds2, lds1, a, cinit,
+                                   sa, acc_sum, accA, accB, loB, hiB);
+    }
+    // the last column block
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb) clamp_sum16(accB[cb], loB, hiB, acc_sum[cb]);
+    store_partials<CB>(ga, wbase, split, col, half, acc_sum);
+}
+
+template <int DT, int KC, int CB>
+__global__ void __launch_bounds__(256) k_gains_lp_sp(GainsArgs ga) {
+    gains_lp_sp_body<DT, KC, CB>(ga, blockIdx.x);
+}
+
+template <int DT, int KC, int CB>
+__global__ void __launch_bounds__(256)
+kb_gains_lp_sp(const InstDesc* __restrict__ descs, const int32_t* __restrict__ slot_inst,
+               const int64_t* __restrict__ wg_pre, int32_t slots, int32_t t) {
+    const int j = find_slot(wg_pre, slots, blockIdx.x);
+    const InstDesc c = descs[slot_inst[j]];
+    if (c.t0 + t >= c.k) return;
+    gains_lp_sp_body<DT, KC, CB>(gains_args(c, nullptr, c.n_pad), int64_t(blockIdx.x) - wg_pre[j]);
+}
+
 template <int DT, int KC, int CB>
 __global__ void __launch_bounds__(512) k_gains_lp_pp(GainsArgs ga) {
     gains_lp_pp_body<DT, KC, CB>(ga, blockIdx.x);
@@ -629,6 +817,16 @@ static void launch_lp_v(const ebc_dataset* ds, const int32_t* cand, int64_t n_ca
 }
 
 template <int DT, int KC, int CB>
+static void launch_lp_sp(const ebc_dataset* ds, const int32_t* cand, int64_t n_cand, hipStream_t s) {
+    using G = LpGeom<DT, KC, CB>;
+    const int64_t tiles = (n_cand + G::CAND_TILE - 1) / G::CAND_TILE;
+    InstDesc c;
+    fill_desc(ds, 0, nullptr, nullptr, nullptr, &c);
+    hipLaunchKernelGGL((k_gains_lp_sp<DT, KC, CB>), dim3(unsigned(tiles * ds->v_splits)), dim3(256), 0, s,
+                       gains_args(c, cand, n_cand));
+}
+
+template <int DT, int KC, int CB>
 static void launch_lp_pp(const ebc_dataset* ds, const int32_t* cand, int64_t n_cand, hipStream_t s) {
     using G = LpGeom<DT, KC, CB>;
     const int64_t tiles = (n_cand + 2 * G::CAND_TILE - 1) / (2 * G::CAND_TILE);
@@ -640,13 +838,14 @@ static void launch_lp_pp(const ebc_dataset* ds, const int32_t* cand, int64_t n_c
 
 // Variants: 4 waves with (32-row candidate blocks per wave, software-pipelined
 // epilogue) 0 = (2, no), 1 = (4, no), 2 = (2, yes); 3 = ping-pong, 8 waves
-// with pp_blocks(DT, KC) blocks each.
+// with pp_blocks(DT, KC) blocks each; 4 = interleaved test, 4 waves x 2 blocks.
 template <int DT, int KC>
 static void launch_lp(const ebc_dataset* ds, const int32_t* cand, int64_t n_cand, hipStream_t s) {
     switch (ds->variant) {
         case 1: launch_lp_v<DT, KC, 4, false>(ds, cand, n_cand, s); break;
         case 2: launch_lp_v<DT, KC, 2, true>(ds, cand, n_cand, s); break;
         case 3: launch_lp_pp<DT, KC, pp_blocks(DT, KC)>(ds, cand, n_cand, s); break;
+        case 4: launch_lp_sp<DT, KC, 2>(ds, cand, n_cand, s); break;
         default: launch_lp_v<DT, KC, 2, false>(ds, cand, n_cand, s); break;
     }
 }
@@ -703,6 +902,7 @@ static void launch_lp_b(int32_t variant, const InstDesc* descs, const int32_t* s
             hipLaunchKernelGGL((kb_gains_lp_pp<DT, KC, pp_blocks(DT, KC)>), g, dim3(512), 0, s, descs, slot_inst, wg_pre,
                                slots, t);
             break;
+        case 4: hipLaunchKernelGGL((kb_gains_lp_sp<DT, KC, 2>), g, b, 0, s, descs, slot_inst, wg_pre, slots, t); break;
         default: hipLaunchKernelGGL((kb_gains_lp<DT, KC, 2, false>), g, b, 0, s, descs, slot_inst, wg_pre, slots, t); break;
     }
 }
