@@ -220,7 +220,10 @@ def bench_serving(args):
         count = args.serving_requests
         stream = [payloads[i % pool_n] for i in range(count)]
         arr = workloads.poisson_arrivals(5 + j, frac * mu, count)
-        recs, t0 = serving.run_open_loop(sv, stream, arr, dtype=dt)
+        recs, t0 = serving.run_open_loop(
+            sv, stream, arr, dtype=dt,
+            progress=lambda done, total: print(f"# rate {frac} mu: {done}/{total} finished", file=sys.stderr,
+                                               flush=True))
         summ = serving.summarize(recs, t0)
         summ["offered_req_per_s"] = frac * mu
         rates[f"{frac}mu"] = {k: (round(v, 5) if isinstance(v, float) else v) for k, v in summ.items()}

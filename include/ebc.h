@@ -416,7 +416,9 @@ EBC_API ebc_status ebc_dataset_get_info(ebc_dataset* ds, ebc_dataset_info* info)
 /* Tile shape of the marginal-gains kernel for this dataset. Every variant
  * computes the same sums in the same order per (candidate, ground chunk), so
  * results do not depend on it; an autotuner picks the fastest per dtype and
- * size. Variants 0..ebc_gains_variant_count(dt)-1; 0 is the default. Rows
+ * size. Variants 0..ebc_gains_variant_count(dt)-1; the default is 0 for
+ * EBC_DT_F32 and 4 (bound test interleaved with the matrix work) for the
+ * reduced-precision dtypes. Rows
  * padded past 128 values have a single long-row kernel, which every
  * variant selects. */
 EBC_API ebc_status ebc_set_gains_variant(ebc_dataset* ds, int32_t variant);

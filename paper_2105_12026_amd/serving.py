@@ -55,14 +55,17 @@ def _collect(server, pending: dict, records: list, results: dict | None = None):
                 results[i] = r
 
 
-def run_open_loop(server, payloads, arrivals, dtype: str = "bf16", sleep=time.sleep, results: dict | None = None):
+def run_open_loop(server, payloads, arrivals, dtype: str = "bf16", sleep=time.sleep, results: dict | None = None,
+                  progress=None, progress_every: int = 250):
     """Open-loop stream: request i = payloads[i] = (x, k[, dtype]) arrives at
     ``arrivals[i]`` seconds after the start and is submitted, stamped with
     that arrival time, as soon as the driver reaches it; the server is ticked
     while it holds work, and the driver sleeps until the next arrival when it
     is idle. Returns the records (one per request, completion order) and the
     start time on the server clock. ``results`` (optional) receives each
-    finished request's poll() output, keyed by stream index."""
+    finished request's poll() output, keyed by stream index; ``progress``
+    (optional) is called with (finished, total) every ``progress_every``
+    finished requests."""
     arrivals = np.asarray(arrivals, dtype=np.float64)
     if len(arrivals) != len(payloads):
         raise ValueError("one arrival time per request")
@@ -86,7 +89,10 @@ def run_open_loop(server, payloads, arrivals, dtype: str = "bf16", sleep=time.sl
                 sleep(max(0.0, t0 + arrivals[i] - server.now()))
             continue
         if server.step() > 0:
+            before = len(records)
             _collect(server, pending, records, results)
+            if progress and len(records) // progress_every > before // progress_every:
+                progress(len(records), count)
     return records, t0
 
 

@@ -5,6 +5,7 @@ workloads. Nothing here touches the HIP library.
     python tests/golden/make_golden.py small      # seconds
     python tests/golden/make_golden.py gmm100k    # ~2 h on 8 cores (FP64 greedy, k=50)
     python tests/golden/make_golden.py sweep200k  # ~15 min on 8 cores (lazy FP64 greedy, k=100)
+    python tests/golden/make_golden.py batched_sample  # ~5 min on 8 cores (32 instances, lazy, k=20)
 
 Each JSON file records the generator, its seed, the SHA-256 of the float32
 input of record, the oracle entry point used, its thread count and wall time.
@@ -74,6 +75,26 @@ def sweep200k():
         "oracle": "oracle/ebc_ref.c ebc_ref_greedy_lazy (C, float64, direct differences, lazy re-evaluation)",
         "threads": ref.threads(), "seconds": time.time() - t0, "gain_evaluations": evals,
         "sel": sel.tolist(), "f": f.tolist(), "gain": g.tolist(),
+    })
+
+
+def batched_sample():
+    """The first 32 of the 512 batched instances (k = 20), each through the
+    lazy float64 greedy: the reference of the batched path's quality check."""
+    insts = W.batched_instances(seed=4, count=32)
+    t0 = time.time()
+    out = []
+    for p in insts:
+        sel, f, g, evals = ref.greedy_lazy(p.x, p.k)
+        out.append({"name": p.name, "seed": p.meta["seed"], "n": int(p.x.shape[0]), "d": int(p.x.shape[1]),
+                    "k": p.k, "sha256_x": W.sha256_of(p.x), "sel": sel.tolist(), "f": f.tolist(),
+                    "gain_evaluations": int(evals)})
+        print(p.name, p.x.shape, f"{time.time() - t0:.0f} s", flush=True)
+    _dump("batched512_first32_k20.json", {
+        "workload": "batched_instances(seed=4): instances 0..31 of 512 (n in [2000, 50000], d in "
+                    "{8, 16, 32, 64, 128}, 5-30 components), greedy k=20 each",
+        "oracle": "oracle/ebc_ref.c ebc_ref_greedy_lazy (C, float64, direct differences, lazy re-evaluation)",
+        "threads": ref.threads(), "seconds": time.time() - t0, "instances": out,
     })
 
 

@@ -2,7 +2,12 @@
 tick) against solo runs: selections, f and gains bitwise equal, for a mix of
 sizes, dimensions (short and long rows), distance dtypes, tile variants and k
 (including k = 0), eager and graph mode; the float32 instances also against
-the oracle."""
+the oracle. A sample of the 512-instance batched workload (its first 32
+instances, k = 20) against the stored float64 oracle runs: FP32 selections
+identical, BF16 quality gap at most 1e-3 with f exact for the chosen sets."""
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -31,8 +36,7 @@ def _make(env, spec, seed):
     n, d, dt, var, k = spec
     x = W.gaussian_mixture(np.random.default_rng(seed), n, d, 6).astype(np.float32)
     ds = ebc.Dataset(torch.from_numpy(x).cuda(), dtype=dt)
-    if var:
-        ds.set_variant(var)
+    ds.set_variant(var)
     return x, ds
 
 
@@ -112,3 +116,45 @@ def test_variants_are_bitwise_identical_and_autotune(env, dt, tmp_path):
     assert ebc.tune_cache_size() >= 1
     r2 = ds.autotune(reps=2)                  # served from the table
     assert r2["variant"] == r["variant"]
+
+
+def test_batched_sample_against_oracle(env, ref):
+    """The first 32 instances of the batched workload (n 2000..50000, d in
+    {8..128}), batched in one graph: FP32 picks the oracle's points in the
+    oracle's order; BF16 (the workload's dtype) reaches the oracle's f(S_20)
+    within 1e-3 relative, and its f values are those of its own selections
+    (float64 minima, checked with the C oracle)."""
+    torch, ebc = env
+    gold = json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                                       "batched512_first32_k20.json")))
+    insts = W.batched_instances(seed=4, count=32)
+    for p, g in zip(insts, gold["instances"]):
+        assert W.sha256_of(p.x) == g["sha256_x"], p.name
+    for dt in ("f32", "bf16"):
+        print(f"[gpu-case] batched sample of 32 instances, {dt}, graph mode", flush=True)
+        dss = [ebc.Dataset(torch.from_numpy(p.x).cuda(), dtype=dt) for p in insts]
+        batch = ebc.Batch(dss)
+        batch.set_graph(True)
+        outs = batch.greedy([p.k for p in insts])
+        for ds in dss:
+            ds.sync()
+        agree, gaps = [], []
+        for p, g, (sel, f, _) in zip(insts, gold["instances"], outs):
+            sel = sel.cpu().numpy()
+            f = f.cpu().numpy()
+            if dt == "f32":
+                assert sel.tolist() == g["sel"], p.name
+                np.testing.assert_allclose(f, g["f"], rtol=1e-12, err_msg=p.name)
+                continue
+            # f(S_t) of the BF16 run is the float64 f of its own sets
+            m = ref.min_dist(p.x, sel)
+            l0 = float(np.mean(ref.min_dist(p.x, [])))
+            np.testing.assert_allclose(f[-1], l0 - float(np.mean(m)), rtol=1e-10, err_msg=p.name)
+            gap = (g["f"][-1] - f[-1]) / g["f"][-1]
+            gaps.append(gap)
+            agree.append(len(set(sel.tolist()) & set(g["sel"])) / p.k)
+            assert gap <= 1e-3, (p.name, gap)
+        if dt == "bf16":
+            print(f"[gpu-result] batched BF16 sample: max quality gap {max(gaps):.2e}, "
+                  f"mean selection agreement {np.mean(agree):.3f}, min {min(agree):.2f}", flush=True)
+        del batch, dss
