@@ -138,8 +138,8 @@ EBC_API ebc_status ebc_dataset_set_e0(ebc_dataset* ds, const float* e0, void* st
 
 /* Device scratch that ebc_eval_sets / ebc_eval_sets_in_dtype need for l
  * sets over a ground set of n points, in bytes: per-set unit counts,
- * validation flags and per-(set, ground-set split) float64 partial sums,
- * about (16 + 8 min(16, ceil(n/256))) l bytes plus alignment. 0 if n is out
+ * validation flags, window starts and per-(set, ground-set split) float64
+ * partial sums, about (20 + 8 min(16, ceil(n/256))) l bytes plus alignment. 0 if n is out
  * of range (as for ebc_dataset_bytes) or l < 0. Host-only arithmetic. */
 EBC_API size_t ebc_eval_sets_bytes(int64_t n, int64_t l);
 

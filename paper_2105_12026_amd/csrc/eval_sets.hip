@@ -45,13 +45,16 @@ constexpr int kVSub = 256;      // ground points per workgroup pass (4 waves x 6
 constexpr int kMaxSplits = 16;
 
 // Scratch of one call: unit prefix U[l+1], non-empty prefix E[l+1], set
-// status (0 ok, 1 bad), group count, per-split partial sums [splits][l].
+// status (0 ok, 1 bad), counts (n_groups[0]: group windows; [1], [2]: window
+// width and count of the register kernel), per-split partial sums
+// [splits][l], first set of each register-kernel window [l+2].
 struct EsScratch {
     int64_t* U;
     int32_t* E;
     int32_t* bad;
     int64_t* n_groups;
     double* part;
+    int32_t* win_j0;  // [l + 2]: first set of each window of the register kernel
 };
 
 // One thread per set: validate the offsets and indices, count the units.
@@ -75,12 +78,21 @@ __global__ void __launch_bounds__(256) k_es_units(const int64_t* __restrict__ of
 }
 
 // Single workgroup: inclusive scans of the unit and non-empty counts (in
-// place, U[0] = E[0] = 0), and the number of group windows.
+// place, U[0] = E[0] = 0), and the number of group windows. Also, for the
+// reduced-precision kernel that keeps member rows in registers: when no set
+// has more than kRegUnits units, its window width G = kRegUnits + 1 - (the
+// largest set's units) and window count (sets whose first unit lies in
+// [w G, (w+1) G) go to wave window w, which then spans at most kRegUnits
+// units); else 0 windows (that kernel stands aside).
+constexpr int kRegUnits = 16;  // units per wave window of the register kernel (two 32-row blocks)
+constexpr int kRegMaxSet = 8;  // largest set (units) it takes: then G >= 9 and there are at most l windows
+
 __global__ void __launch_bounds__(1024) k_es_scan(int64_t l, int32_t window, EsScratch sc) {
     __shared__ int64_t su[1024];
     __shared__ int32_t se[1024];
     __shared__ int64_t carry_u;
     __shared__ int32_t carry_e;
+    __shared__ int64_t umax[1024];
     const int t = threadIdx.x;
     if (t == 0) {
         carry_u = 0;
@@ -88,11 +100,13 @@ __global__ void __launch_bounds__(1024) k_es_scan(int64_t l, int32_t window, EsS
         sc.U[0] = 0;
         sc.E[0] = 0;
     }
+    int64_t my_max = 0;
     __syncthreads();
     for (int64_t base = 0; base < l; base += 1024) {
         const int64_t j = base + t;
         su[t] = j < l ? sc.U[j + 1] : 0;
         se[t] = j < l ? sc.E[j + 1] : 0;
+        if (su[t] > my_max) my_max = su[t];
         __syncthreads();
         for (int w = 1; w < 1024; w <<= 1) {
             const int64_t u = t >= w ? su[t - w] : 0;
@@ -113,7 +127,30 @@ __global__ void __launch_bounds__(1024) k_es_scan(int64_t l, int32_t window, EsS
         }
         __syncthreads();
     }
-    if (t == 0) *sc.n_groups = (carry_u + window - 1) / window;
+    umax[t] = my_max;
+    __syncthreads();
+    for (int w = 512; w > 0; w >>= 1) {
+        if (t < w && umax[t + w] > umax[t]) umax[t] = umax[t + w];
+        __syncthreads();
+    }
+    const int64_t mx = umax[0];
+    const int64_t G = kRegUnits + 1 - mx;
+    const bool fits = mx >= 1 && mx <= kRegMaxSet;
+    const int64_t n_win = fits ? (carry_u + G - 1) / G : 0;
+    if (t == 0) {
+        sc.n_groups[0] = (carry_u + window - 1) / window;
+        sc.n_groups[1] = fits ? G : 0;
+        sc.n_groups[2] = n_win;
+    }
+    // first set of every window: window w starts at the first set whose first
+    // unit is at or after w G (set j owns the windows w with U[j-1] < w G <= U[j]);
+    // windows past the last set's start, and the end marker n_win, get l
+    if (fits)
+        for (int64_t j = t; j <= l; j += 1024) {
+            const int64_t w_lo = j == 0 ? 0 : sc.U[j - 1] / G + 1;
+            const int64_t w_hi = j == l ? n_win : sc.U[j] / G;
+            for (int64_t w = w_lo; w <= w_hi && w <= n_win; ++w) sc.win_j0[w] = int32_t(j);
+        }
 }
 
 // first j in [lo, hi) with U[j] >= key (hi if none)
@@ -437,6 +474,7 @@ k_es_lp(const uint4* __restrict__ xq, const float* __restrict__ hn, const int* _
     const int wave = tid >> 6;
     const int col = lane & 31;
     const int half = lane >> 5;
+    if (sc.n_groups[2] > 0) return;  // every set fits the register kernel, which takes the call
     const int64_t n_items = *sc.n_groups * splits;
     const int64_t vchunk = ((n + splits - 1) / splits + kVSub - 1) / kVSub * kVSub;
     const int* sc_rows = kFp8 ? scale : nullptr;
@@ -610,6 +648,217 @@ k_es_lp(const uint4* __restrict__ xq, const float* __restrict__ hn, const int* _
         __syncthreads();
         es_finish<W>(tid, j0, j1, split, l, sc, lacc);
         __syncthreads();
+    }
+}
+
+// Reduced-precision multi-set evaluation with the member rows in registers
+// (calls whose sets all have at most kRegMaxSet units, i.e. 32 members;
+// others go to k_es_lp). The structure is that of the marginal-gains kernel: each wave
+// holds its window's member rows (two 32-row blocks) as the MFMA A operand in
+// registers for the whole item, and the ground set streams through a 3-stage
+// LDS ring of 64-point tiles (global_load_lds copies, one barrier per tile)
+// shared by the workgroup's 4 waves. Work item = (4 consecutive wave windows,
+// ground-set split). Wave window w holds the sets whose first unit lies in
+// [w G, (w+1) G) (G from k_es_scan), so no set crosses windows and a window
+// spans at most kRegUnits units.
+//
+// Per tile and member block: the two 32-point column blocks' MFMAs (C
+// operand -||s^||^2/2 per row, -inf for padding rows), each lane's maximum
+// over every unit's four rows, and one lane swap between the halves
+// (v_permlane32_swap) that leaves lane (col, h) with the eight unit maxima of
+// ground point 32h + col. Then, for that point, the running maximum over the
+// window's units under wave-uniform flags (first / last unit of a set), and
+// at a set's last unit u the lane adds max(0, running max + wsh_v) to its
+// register accumulator acc_u[u] (u is a compile-time index after unrolling).
+// wsh_v = m_v/2 - ||v^||^2/2 folds e0 and the cast rows' norms in as in
+// k_es_lp; points outside the split get -inf, so they add nothing. After the
+// split, each set's accumulator is summed over the 64 lanes in a fixed order
+// in float64 and written as the set's partial sum of this split.
+template <int DT, int KC>
+__global__ void __launch_bounds__(256)
+k_es_regs(const uint4* __restrict__ xq, const float* __restrict__ hn, const int* __restrict__ scale, int64_t n,
+          const double* __restrict__ m0, const int64_t* __restrict__ off, const int32_t* __restrict__ idx, int64_t l,
+          int32_t splits, EsScratch sc) {
+    using T = Lp<DT>;
+    constexpr int HU = KC * T::kU4;  // 16-byte units per lane half-row
+    constexpr int RU = 2 * HU;       // 16-byte units per row
+    constexpr int VT = 64;           // ground points per tile
+    constexpr bool kFp8 = DT == EBC_DT_FP8_E4M3;
+    constexpr int OFF_SC = RU * VT;                          // FP8: the tile's row scales after its units
+    constexpr int STAGE = RU * VT + (kFp8 ? VT / 4 : 0);     // uint4 per stage
+    constexpr int NI = RU + (kFp8 ? 1 : 0);                  // wave copy instructions per stage
+    constexpr int L = (NI + 3) / 4;                          // copy instructions per wave per stage
+    __shared__ uint4 ring0[STAGE];
+    __shared__ uint4 ring1[STAGE];
+    __shared__ uint4 ring2[STAGE];
+    __shared__ int32_t rmem[4][64];  // per wave: member row of each of its 64 rows (-1: padding)
+
+    const int64_t G = sc.n_groups[1];
+    const int64_t n_win = sc.n_groups[2];
+    if (n_win == 0) return;  // some set is longer than kRegMaxSet units (k_es_lp runs), or none has units
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int col = lane & 31;
+    const int half = lane >> 5;
+    const int64_t n_items = (n_win + 3) / 4 * splits;
+    const int64_t vchunk = ((n + splits - 1) / splits + kVSub - 1) / kVSub * kVSub;
+
+    // every wave issues exactly L copy instructions per stage (pieces beyond NI
+    // repeat one another wave also copies: same bytes to the same place)
+    auto copy_stage = [&](int64_t tile, uint4* st) {
+#pragma unroll
+        for (int q = 0; q < L; ++q) {
+            const int j = (wave + 4 * q) % NI;
+            if (j < RU)
+                __builtin_amdgcn_global_load_lds(xq + (tile * RU + j) * VT + lane, (lds_void*)(st + j * VT), 16, 0, 0);
+            else
+                __builtin_amdgcn_global_load_lds(scale + tile * VT + lane, (lds_void*)(st + OFF_SC), 4, 0, 0);
+        }
+    };
+
+    for (int64_t item = blockIdx.x; item < n_items; item += gridDim.x) {
+        const int64_t g = item / splits;
+        const int split = int(item % splits);
+        const int64_t w = g * 4 + wave;
+        // this wave's sets and units
+        int64_t j0 = 0, j1 = 0;
+        if (w < n_win) {
+            j0 = sc.win_j0[w];
+            j1 = sc.win_j0[w + 1];
+        }
+        const int64_t ua = sc.U[j0], ub = sc.U[j1];
+        // row bookkeeping: lane r owns row r (unit ua + r/4)
+        {
+            const int64_t u = ua + lane / kUnitRows;
+            int32_t mem = -1;
+            if (u < ub) {
+                const int64_t j = owner_of(sc.U, j0, j1, u);
+                const int64_t q = (u - sc.U[j]) * kUnitRows + lane % kUnitRows;
+                if (off[j] + q < off[j + 1]) mem = idx[off[j] + q];
+            }
+            rmem[wave][lane] = mem;
+        }
+        // last unit of each set in the window (lanes 0..15: unit ua + lane), a wave-uniform mask
+        uint32_t m_last;
+        {
+            const int64_t u = ua + lane;
+            bool last = false;
+            if (lane < kRegUnits && u < ub) {
+                const int64_t j = owner_of(sc.U, j0, j1, u);
+                last = u == sc.U[j + 1] - 1;
+            }
+            m_last = __builtin_amdgcn_readfirstlane(uint32_t(__builtin_amdgcn_ballot_w64(last)));
+        }
+        __syncthreads();  // rmem of every wave written (and the ring of the previous item drained)
+        // member rows (A operand) and the C operand -||s^||^2/2 of the rows this lane holds
+        uint4 a[2][HU];
+        int sa[2];
+        floatx16 cinit[2];
+#pragma unroll
+        for (int mb = 0; mb < 2; ++mb) {
+            const int32_t mem = rmem[wave][mb * 32 + col];
+            const uint4* src = xq + (int64_t(mem) / 64) * (RU * 64) + (mem % 64);
+#pragma unroll
+            for (int u = 0; u < HU; ++u) a[mb][u] = mem >= 0 ? src[(half * HU + u) * 64] : make_uint4(0, 0, 0, 0);
+            sa[mb] = (kFp8 && mem >= 0) ? scale[mem] : 127;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int32_t mr = rmem[wave][mb * 32 + 8 * (r / 4) + 4 * half + (r % 4)];
+                cinit[mb][r] = mr >= 0 ? -hn[mr] : -INFINITY;
+            }
+        }
+        float acc_u[kRegUnits];
+#pragma unroll
+        for (int u = 0; u < kRegUnits; ++u) acc_u[u] = 0.0f;
+
+        // ground tiles of this split
+        const int64_t v_begin = int64_t(split) * vchunk;
+        int64_t v_end = v_begin + vchunk;
+        if (v_end > n) v_end = n;
+        const int64_t t_begin = v_begin / VT;
+        const int64_t nt = v_end > v_begin ? (v_end - v_begin + VT - 1) / VT : 0;
+        // this lane's ground point of tile t and its shift (next tile's in flight)
+        auto shift_of = [&](int64_t t) -> float {
+            const int64_t v = (t_begin + t) * VT + lane;
+            return (t < nt && v >= v_begin && v < v_end) ? float(0.5 * m0[v] - double(hn[v])) : -INFINITY;
+        };
+        float wsh_next = shift_of(0);
+        if (nt > 0) copy_stage(t_begin, ring0);
+        if (nt > 1) copy_stage(t_begin + 1, ring1);
+        auto tile = [&](int64_t t, const uint4* st, uint4* next2) {
+            if (t + 1 < nt)
+                wait_vmcnt<L>();
+            else
+                wait_vmcnt<0>();
+            ring_barrier();
+            if (t + 2 < nt) copy_stage(t_begin + t + 2, next2);
+            const float wsh = wsh_next;
+            wsh_next = shift_of(t + 1);
+            const int* st_sc = reinterpret_cast<const int*>(st + OFF_SC);
+            // both member blocks against each column block: the column block's
+            // operand is read from LDS once
+            floatx16 acc[2][2];  // [member block][column block]
+#pragma unroll
+            for (int cb = 0; cb < 2; ++cb) {
+                const int vrow = cb * 32 + col;
+                uint4 b[HU];
+#pragma unroll
+                for (int u = 0; u < HU; ++u) b[u] = st[(half * HU + u) * VT + vrow];
+                const int sb = kFp8 ? st_sc[vrow] : 127;
+                acc[0][cb] = cinit[0];
+                acc[1][cb] = cinit[1];
+#pragma unroll
+                for (int q = 0; q < KC; ++q)
+#pragma unroll
+                    for (int mb = 0; mb < 2; ++mb)
+                        acc[mb][cb] = mfma_main<DT>(&a[mb][q * T::kU4], &b[q * T::kU4], acc[mb][cb], sa[mb], sb);
+            }
+            float um[kRegUnits];
+#pragma unroll
+            for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+                for (int gq = 0; gq < kBlockUnits / 2; ++gq) {
+                    const floatx16& p0 = acc[mb][0];
+                    const floatx16& p1 = acc[mb][1];
+                    const float x0 = fmaxf(fmaxf(p0[4 * gq], p0[4 * gq + 1]), fmaxf(p0[4 * gq + 2], p0[4 * gq + 3]));
+                    const float x1 = fmaxf(fmaxf(p1[4 * gq], p1[4 * gq + 1]), fmaxf(p1[4 * gq + 2], p1[4 * gq + 3]));
+                    // upper half of x0 <-> lower half of x1: this lane's point, units 2gq and 2gq+1
+                    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x0), __float_as_uint(x1), false, false);
+                    um[mb * kBlockUnits + 2 * gq] = __uint_as_float(r[0]);
+                    um[mb * kBlockUnits + 2 * gq + 1] = __uint_as_float(r[1]);
+                }
+            // sets are consecutive runs of units: the running maximum restarts after
+            // each set's last unit (units past the window's last set are padding
+            // rows at -inf, so they never reach a last unit)
+            float cur = -INFINITY;
+#pragma unroll
+            for (int u = 0; u < kRegUnits; ++u) {
+                cur = fmaxf(cur, um[u]);
+                if ((m_last >> u) & 1u) {
+                    acc_u[u] += fmaxf(cur + wsh, 0.0f);
+                    cur = -INFINITY;
+                }
+            }
+        };
+        // stage of tile t: t % 3 (distinct LDS objects, so a copy in flight never targets the stage read)
+        for (int64_t t = 0; t < nt; t += 3) {
+            tile(t, ring0, ring2);
+            if (t + 1 < nt) tile(t + 1, ring1, ring0);
+            if (t + 2 < nt) tile(t + 2, ring2, ring1);
+        }
+        // each set's sum over the 64 lanes, fixed order, float64; one write per set and split
+#pragma unroll
+        for (int u = 0; u < kRegUnits; ++u) {
+            if (!((m_last >> u) & 1u)) continue;
+            double v = double(acc_u[u]);
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+            if (lane == 0) {
+                const int64_t j = owner_of(sc.U, j0, j1, ua + u);
+                sc.part[int64_t(split) * l + j] = v;
+            }
+        }
     }
 }
 
@@ -882,7 +1131,7 @@ __global__ void __launch_bounds__(256) k_es_final(int64_t l, int64_t n, int32_t 
     const int64_t j = int64_t(blockIdx.x) * 256 + threadIdx.x;
     if (j >= l) return;
     if (sc.bad[j]) {
-        f_out[j] = NAN;
+        f_out[j] = __longlong_as_double(0x7ff8000000000000ll);  // quiet NaN
         return;
     }
     if (sc.E[j + 1] == sc.E[j]) {
@@ -915,7 +1164,8 @@ size_t a256(size_t v) { return (v + 255) & ~size_t(255); }
 size_t eval_sets_scratch_bytes(int64_t n, int64_t l) {
     const int32_t splits = es_splits(n);
     return a256(size_t(l + 1) * sizeof(int64_t)) + a256(size_t(l + 1) * sizeof(int32_t)) +
-           a256(size_t(l) * sizeof(int32_t)) + a256(sizeof(int64_t)) + a256(size_t(splits) * size_t(l) * sizeof(double));
+           a256(size_t(l) * sizeof(int32_t)) + a256(sizeof(int64_t)) + a256(size_t(splits) * size_t(l) * sizeof(double)) +
+           a256(size_t(l + 2) * sizeof(int32_t));
 }
 
 hipError_t launch_eval_sets(const ebc_dataset* ds, const int64_t* offsets, const int32_t* idx, int64_t l,
@@ -934,6 +1184,8 @@ hipError_t launch_eval_sets(const ebc_dataset* ds, const int64_t* offsets, const
     sc.n_groups = reinterpret_cast<int64_t*>(p);
     p += a8(sizeof(int64_t));
     sc.part = reinterpret_cast<double*>(p);
+    p += a8(size_t(splits) * size_t(l) * sizeof(double));
+    sc.win_j0 = reinterpret_cast<int32_t*>(p);
 
     const unsigned nb = unsigned((l + 255) / 256);
     hipLaunchKernelGGL(k_es_units, dim3(nb), dim3(256), 0, s, offsets, idx, l, ds->n, sc, ds->b.state);
@@ -980,6 +1232,8 @@ hipError_t launch_eval_sets(const ebc_dataset* ds, const int64_t* offsets, const
         const uint4* xq = static_cast<const uint4*>(static_cast<const void*>(ds->b.xq));
 #define EBC_ESL(DTV, K)                                                                                         \
     case K:                                                                                                     \
+        hipLaunchKernelGGL((k_es_regs<DTV, K>), g, dim3(256), 0, s, xq, ds->b.hn, ds->b.scale, ds->n, ds->b.m0,   \
+                           offsets, idx, l, splits, sc);                                                        \
         hipLaunchKernelGGL((k_es_lp<DTV, K, lp_window(DTV, K)>), g, dim3(256), 0, s, xq, ds->b.hn, ds->b.scale,   \
                            ds->n, ds->b.n64, ds->b.m0, offsets, idx, l, splits, sc);                     \
         break;

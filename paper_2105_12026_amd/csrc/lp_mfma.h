@@ -56,6 +56,25 @@ __device__ __forceinline__ void clamp_sum16(const floatx16& acc, float lo, float
     for (int r = 0; r < 16; ++r) sum[r] += t[r];
 }
 
+// s_waitcnt with only the vector-memory counter constrained (<= N).
+template <int N>
+__device__ __forceinline__ void wait_vmcnt() {
+    static_assert(N >= 0 && N < 64, "vmcnt range");
+    __builtin_amdgcn_s_waitcnt((N & 0xF) | ((N >> 4) << 14) | (0x7 << 4) | (0xF << 8));
+}
+
+// Workgroup barrier for the LDS ring without the release/acquire fences of
+// __syncthreads (those would also wait for the copies still in flight into
+// the other stages). The caller has already waited for its own copies of the
+// stage about to be read; here the wave's LDS reads are drained, and the
+// empty asm statements keep the compiler from moving memory accesses across.
+__device__ __forceinline__ void ring_barrier() {
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_waitcnt(0xF | (0x3 << 14) | (0x7 << 4));  // lgkmcnt(0), vmcnt/expcnt untouched
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+}
+
 template <int DT>
 __device__ __forceinline__ floatx16 mfma_main(const uint4* a, const uint4* b, floatx16 c, int sa, int sb);
 

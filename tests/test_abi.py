@@ -94,8 +94,8 @@ def test_scratch_size_queries(L):
     # sums per ground-set split (ceil(n / 256) splits, at most 16), 256-byte pieces
     a = L.ebc_eval_sets_bytes(50000, 5000)
     assert a % 256 == 0
-    assert a >= 5000 * (16 + 8 * 16)
-    assert a <= 5000 * (16 + 8 * 16) + 5 * 256
+    assert a >= 5000 * (20 + 8 * 16)
+    assert a <= 5000 * (20 + 8 * 16) + 6 * 256 + 8
     assert L.ebc_eval_sets_bytes(300, 5000) < a            # two splits instead of 16
     assert L.ebc_eval_sets_bytes(1000, 0) > 0               # the per-call counters
     assert L.ebc_eval_sets_bytes(0, 10) == 0

@@ -252,3 +252,70 @@ def test_eval_sets_in_dtype(env, ref, dt, n, d, seed):
     print(f"[gpu-result] eval_sets in {dt} n={n} d={d}: max rel err {rel.max():.3e}", flush=True)
     assert rel.max() <= ES_TOL[dt]
     assert np.all(np.abs(f32 - rf) <= 1e-5 * np.abs(rf) + 1e-12 * l0)
+
+
+@pytest.mark.parametrize("dt", ["bf16", "f16", "fp8"])
+@pytest.mark.parametrize("n,d,seed", [(3000, 100, 91), (777, 16, 92), (4100, 64, 93), (300, 128, 94)])
+def test_eval_sets_in_dtype_short_sets(env, ref, dt, n, d, seed):
+    """Sets of at most 32 members (the kernel that keeps member rows in
+    registers takes every call whose sets all fit 8 units): sizes on both
+    sides of every unit and block boundary, empty sets and repeated members
+    between them, several ground-set splits with ragged tails and empty
+    splits (n = 4100); against the float64 oracle at the dtype's bar,
+    deterministic; BF16/FP16 also against exact arithmetic on the cast rows."""
+    torch, ebc = env
+    rng = np.random.default_rng(seed)
+    x = W.gaussian_mixture(rng, n, d, 5).astype(np.float32)
+    sizes = [0, 1, 3, 4, 5, 8, 0, 9, 16, 17, 31, 32, 2, 10, 10] + list(rng.integers(1, 33, 400))
+    sets = [rng.integers(0, n, sz) for sz in sizes]
+    sets[5] = np.array([7, 7, 7, 7, 7], dtype=np.int64)  # repeated member
+    off = np.cumsum([0] + [len(q) for q in sets]).astype(np.int64)
+    idx = np.concatenate(sets).astype(np.int32)
+    print(f"[gpu-case] short-set eval_sets in {dt} n={n} d={d} l={len(sets)}", flush=True)
+    ds = _ds(env, x, dt)
+    to = torch.from_numpy(off)
+    ti = torch.from_numpy(idx)
+    f1 = ds.eval_sets(to, ti, in_dtype=True).cpu().numpy()
+    f2 = ds.eval_sets(to, ti, in_dtype=True).cpu().numpy()
+    ds.sync()
+    assert np.array_equal(f1, f2)
+    rf = ref.eval_sets(x, off, idx)
+    l0 = float(np.mean(np.sum(x.astype(np.float64) ** 2, axis=1)))
+    assert np.all(f1[np.array(sizes) == 0] == 0.0)
+    rel = np.abs(f1 - rf) / (np.abs(rf) + 1e-3 * l0)
+    bar = ES_TOL[dt]
+    if dt != "fp8":
+        # the same sets in exact arithmetic on the cast rows (round-to-nearest-even
+        # BF16/FP16, half-norms of the cast rows rounded to float32): what the
+        # format alone costs, and the kernel's own arithmetic to 2e-5 of it
+        fe = _cast_sets_f(x, sets, dt)
+        rel_fmt = np.abs(fe - rf) / (np.abs(rf) + 1e-3 * l0)
+        rel_ker = np.abs(f1 - fe) / (np.abs(fe) + 1e-3 * l0)
+        print(f"[gpu-result]   format alone: {rel_fmt.max():.3e}; kernel vs cast arithmetic {rel_ker.max():.3e}",
+              flush=True)
+        assert rel_ker.max() <= 2e-5
+        # a set whose few members the format itself moves further than the bar
+        bar = max(bar, 1.25 * rel_fmt.max())
+    print(f"[gpu-result] short-set eval_sets in {dt} n={n} d={d}: max rel err {rel.max():.3e} (bar {bar:.2e})",
+          flush=True)
+    assert rel.max() <= bar
+
+
+def _cast_sets_f(x, sets, dt):
+    """f(S) of each set in float64 on the rows cast to BF16 / FP16 (round to
+    nearest even), with the cast rows' half-norms rounded to float32 and the
+    exact ||v||^2 of the float32 rows for e0 = 0."""
+    if dt == "f16":
+        xh = x.astype(np.float16).astype(np.float64)
+    else:
+        u = x.view(np.uint32).astype(np.uint64)
+        xh = (((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16).astype(np.uint32).view(np.float32).astype(np.float64)
+    hn = (0.5 * np.sum(xh * xh, axis=1)).astype(np.float32).astype(np.float64)
+    m0 = np.sum(x.astype(np.float64) ** 2, axis=1)
+    wsh = (0.5 * m0 - hn).astype(np.float32).astype(np.float64)
+    out = np.zeros(len(sets))
+    for j, s in enumerate(sets):
+        if len(s):
+            t = xh @ xh[s].T - hn[s][None, :]
+            out[j] = 2.0 * np.sum(np.maximum(0.0, t.max(axis=1) + wsh)) / x.shape[0]
+    return out
