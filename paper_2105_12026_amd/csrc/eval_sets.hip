@@ -836,6 +836,9 @@ k_es_regs(const uint4* __restrict__ xq, const float* __restrict__ hn, const int*
             for (int u = 0; u < kRegUnits; ++u) {
                 cur = fmaxf(cur, um[u]);
                 if ((m_last >> u) & 1u) {
+                    // a scalar branch, not selects over every unit (the empty
+                    // volatile statement keeps the compiler from speculating it)
+                    asm volatile("");
                     acc_u[u] += fmaxf(cur + wsh, 0.0f);
                     cur = -INFINITY;
                 }
