@@ -40,6 +40,10 @@ struct DevState {
     double tau;          // relative window half-width for the gains dtype
     double tau_abs;      // absolute window half-width, in units of nmax
     double nmax;         // max_v ||v||^2
+    int32_t gexp;        // 2^gexp >= m_v / 2 for every point and every m loaded since the dataset's
+                         // creation (raised, never lowered): the reduced-precision gains scale
+                         // their clamped terms by 2^-gexp into [0, 1]
+    int32_t pad1;
 };
 
 struct WindowEntry {
@@ -125,6 +129,7 @@ struct GainsArgs {
     double* part;
     int64_t part_stride;
     int* err;
+    const int32_t* gexp;  // DevState::gexp of the instance
 };
 
 // Block -> instance map of a batched launch: instance i owns blocks
@@ -276,6 +281,7 @@ __host__ __device__ inline GainsArgs gains_args(const InstDesc& d, const int32_t
     a.part = d.b.part;
     a.part_stride = d.n_pad;
     a.err = &d.b.state->error;
+    a.gexp = &d.b.state->gexp;
     return a;
 }
 

@@ -4,16 +4,21 @@
 //
 // Same quantity as the float32 kernel (G[c] = sum_v max(0, m_v - d(v,c)),
 // Sec. 3 discrete derivative, Sec. 4.1 per-point decomposition), halved:
-//     G[c]/2 = sum_v med3( x^_v . x^_c + ha_v - hn_c, 0, hm_v )
+//     G[c]/2 = sum_v max(0, x^_v . x^_c + ha_v - hn_c)
 // where x^ are the quantised rows, hn = ||x^||^2/2 in float32, hm_v = m_v/2,
-// ha_v = hm_v - hn_v. Moving ha_v out of the clamp,
-//     med3(t + ha_v, 0, hm_v) = med3(t, lo, hi) - lo,  lo = -ha_v, hi = hm_v - ha_v,
-// the accumulator starts from the constant tile -hn_c (the MFMA's C operand,
-// the same for every ground point), and the epilogue is one v_med3_f32 with
-// per-column bounds, one subtraction and one add per (candidate, point)
-// pair. A term at its lower bound is exactly 0, so a 32 x 32 tile whose
-// every value lies at or below its column's bound adds nothing, and the
-// wave skips its epilogue after one test (bitwise the same sums).
+// ha_v = hm_v - hn_v (the term is hm_v - d^(v,c)/2). The accumulator starts
+// from the constant tile -hn_c (the MFMA's C operand, the same for every
+// ground point), so with lo = -ha_v the term is max(0, acc - lo). The
+// epilogue scales it by s = 2^-e (2^e >= hm_v for every point, so the term
+// lies in [0, 1]) and takes it with one v_fma_f32 carrying the clamp bit,
+//     t = clamp(acc * s + ha_v * s, 0, 1),
+// then one add per (candidate, point) pair; the power-of-two scale is exact
+// and is undone in float64 when the sums are stored. The clamp at 1 stands
+// for the cap at hm_v, which only a computed distance below zero (rounding,
+// near-duplicate points) can reach. A term with acc <= lo is exactly 0, so a
+// 32 x 32 tile whose every value lies at or below its column's bound adds
+// nothing, and the wave skips its epilogue after one test (bitwise the same
+// sums).
 //
 // Grouped order: the ground set is sorted by nearest pivot at residency, and
 // candidates (when all points are scored) and points are walked in that
@@ -47,31 +52,26 @@ struct LpGeom {
     static constexpr int HU = RU / 2;                      // units per lane half-row
     static constexpr int VT = 64;                          // rows per tile
     static constexpr bool kFp8 = DT == EBC_DT_FP8_E4M3;
-    // LDS stage: [RU units x 64 rows][ha: 64 floats][hm: 64 floats][scale: 64 ints]
+    // LDS stage: [RU units x 64 rows][ha: 64 floats][scale: 64 ints]
     static constexpr int OFF_HA = RU * VT;
-    static constexpr int OFF_HM = OFF_HA + VT / 4;
-    static constexpr int OFF_SC = OFF_HM + VT / 4;
+    static constexpr int OFF_SC = OFF_HA + VT / 4;
     static constexpr int STAGE = OFF_SC + (kFp8 ? VT / 4 : 0);  // uint4 per stage
-    static constexpr int NI = RU + 2 + (kFp8 ? 1 : 0);         // wave copy instructions per stage
+    static constexpr int NI = RU + 1 + (kFp8 ? 1 : 0);         // wave copy instructions per stage
     static constexpr int L = (NI + 3) / 4;                      // copy instructions per wave per stage
     static constexpr int NBUF = 3;
     static constexpr int CAND_TILE = 4 * 32 * CB;
 };
 
 // Wave-wide copy of one piece of ground-set tile `tile` into LDS stage `st`.
-// Piece j: j < RU main unit j; then the 64 ha; then the 64 hm; then (FP8)
-// the 64 row scales.
+// Piece j: j < RU main unit j; then the 64 ha; then (FP8) the 64 row scales.
 template <class G>
 __device__ __forceinline__ void copy_piece(int j, int64_t tile, int lane, const uint4* __restrict__ xqt,
-                                           const float* __restrict__ ha, const float* __restrict__ hm,
-                                           const int* __restrict__ sc, uint4* st) {
+                                           const float* __restrict__ ha, const int* __restrict__ sc, uint4* st) {
     if (j < G::RU) {
         __builtin_amdgcn_global_load_lds(xqt + (tile * G::RU + j) * G::VT + lane, (lds_void*)(st + j * G::VT), 16,
                                          0, 0);
     } else if (j == G::RU) {
         __builtin_amdgcn_global_load_lds(ha + tile * G::VT + lane, (lds_void*)(st + G::OFF_HA), 4, 0, 0);
-    } else if (j == G::RU + 1) {
-        __builtin_amdgcn_global_load_lds(hm + tile * G::VT + lane, (lds_void*)(st + G::OFF_HM), 4, 0, 0);
     } else {
         __builtin_amdgcn_global_load_lds(sc + tile * G::VT + lane, (lds_void*)(st + G::OFF_SC), 4, 0, 0);
     }
@@ -82,10 +82,9 @@ __device__ __forceinline__ void copy_piece(int j, int64_t tile, int lane, const 
 // vector-memory counter is the same on every wave.
 template <class G>
 __device__ __forceinline__ void copy_stage(int wave, int lane, int64_t tile, const uint4* __restrict__ xqt,
-                                           const float* __restrict__ ha, const float* __restrict__ hm,
-                                           const int* __restrict__ sc, uint4* st) {
+                                           const float* __restrict__ ha, const int* __restrict__ sc, uint4* st) {
 #pragma unroll
-    for (int l = 0; l < G::L; ++l) copy_piece<G>((wave + 4 * l) % G::NI, tile, lane, xqt, ha, hm, sc, st);
+    for (int l = 0; l < G::L; ++l) copy_piece<G>((wave + 4 * l) % G::NI, tile, lane, xqt, ha, sc, st);
 }
 
 // One ground-set tile: wait for its copy, start the copy of the tile two
@@ -94,9 +93,9 @@ __device__ __forceinline__ void copy_stage(int wave, int lane, int64_t tile, con
 template <class G, int DT, int KC, int CB>
 __device__ __forceinline__ void lp_tile(int64_t t, int64_t nt, int64_t t_begin, int wave, int lane, int col, int half,
                                         const uint4* __restrict__ xqt, const float* __restrict__ ha,
-                                        const float* __restrict__ hm, const int* __restrict__ sc, const uint4* st,
+                                        const int* __restrict__ sc, const uint4* st,
                                         uint4* next2, const uint4 (&a)[CB][G::HU], const floatx16 (&cinit)[CB],
-                                        const int (&sa)[CB], float (&acc_sum)[CB][16]) {
+                                        const int (&sa)[CB], float (&acc_sum)[CB][16], float s) {
     using T = Lp<DT>;
     constexpr int HU = G::HU, VT = G::VT;
     // this wave's copies of tile t are done (those of t+1 may still fly) ...
@@ -107,9 +106,8 @@ __device__ __forceinline__ void lp_tile(int64_t t, int64_t nt, int64_t t_begin, 
     // ... and every wave's, and every wave finished reading tile t-1, whose
     // stage the next copy overwrites
     ring_barrier();
-    if (t + 2 < nt) copy_stage<G>(wave, lane, t_begin + t + 2, xqt, ha, hm, sc, next2);
+    if (t + 2 < nt) copy_stage<G>(wave, lane, t_begin + t + 2, xqt, ha, sc, next2);
     const float* st_ha = reinterpret_cast<const float*>(st + G::OFF_HA);
-    const float* st_hm = reinterpret_cast<const float*>(st + G::OFF_HM);
     const int* st_sc = reinterpret_cast<const int*>(st + G::OFF_SC);
 #pragma unroll
     for (int colb = 0; colb < VT / 32; ++colb) {
@@ -118,7 +116,7 @@ __device__ __forceinline__ void lp_tile(int64_t t, int64_t nt, int64_t t_begin, 
 #pragma unroll
         for (int u = 0; u < HU; ++u) b[u] = st[(half * HU + u) * VT + vrow];
         const float hav = st_ha[vrow];
-        const float lo = -hav, hi = st_hm[vrow] - hav;
+        const float lo = -hav, sh = hav * s;
         const int sb = G::kFp8 ? st_sc[vrow] : 127;
         // CB independent accumulator chains, each starting from -hn_c
         floatx16 acc[CB];
@@ -130,7 +128,7 @@ __device__ __forceinline__ void lp_tile(int64_t t, int64_t nt, int64_t t_begin, 
             for (int cb = 0; cb < CB; ++cb)
                 acc[cb] = mfma_main<DT>(&a[cb][q * T::kU4], &b[q * T::kU4], acc[cb], sa[cb], sb);
 #pragma unroll
-        for (int cb = 0; cb < CB; ++cb) clamp_sum16(acc[cb], lo, hi, acc_sum[cb]);
+        for (int cb = 0; cb < CB; ++cb) clamp_sum16(acc[cb], lo, s, sh, acc_sum[cb]);
     }
 }
 
@@ -142,11 +140,11 @@ __device__ __forceinline__ void lp_tile(int64_t t, int64_t nt, int64_t t_begin, 
 template <class G, int DT, int KC, int CB>
 __device__ __forceinline__ void lp_tile_pipe(int64_t t, int64_t nt, int64_t t_begin, int wave, int lane, int col,
                                              int half, const uint4* __restrict__ xqt, const float* __restrict__ ha,
-                                             const float* __restrict__ hm, const int* __restrict__ sc,
+                                             const int* __restrict__ sc,
                                              const uint4* st, uint4* next2, const uint4 (&a)[CB][G::HU],
                                              const floatx16 (&cinit)[CB], const int (&sa)[CB],
                                              float (&acc_sum)[CB][16],
-                                             floatx16 (&prev)[CB], float& prev_lo, float& prev_hi, bool& pending) {
+                                             floatx16 (&prev)[CB], float& prev_lo, float& prev_sh, bool& pending, float s) {
     using T = Lp<DT>;
     constexpr int HU = G::HU, VT = G::VT;
     constexpr int NMF = KC * CB;            // matrix instructions per column block
@@ -157,9 +155,8 @@ __device__ __forceinline__ void lp_tile_pipe(int64_t t, int64_t nt, int64_t t_be
     else
         wait_vmcnt<0>();
     ring_barrier();
-    if (t + 2 < nt) copy_stage<G>(wave, lane, t_begin + t + 2, xqt, ha, hm, sc, next2);
+    if (t + 2 < nt) copy_stage<G>(wave, lane, t_begin + t + 2, xqt, ha, sc, next2);
     const float* st_ha = reinterpret_cast<const float*>(st + G::OFF_HA);
-    const float* st_hm = reinterpret_cast<const float*>(st + G::OFF_HM);
     const int* st_sc = reinterpret_cast<const int*>(st + G::OFF_SC);
 #pragma unroll
     for (int colb = 0; colb < VT / 32; ++colb) {
@@ -168,7 +165,7 @@ __device__ __forceinline__ void lp_tile_pipe(int64_t t, int64_t nt, int64_t t_be
 #pragma unroll
         for (int u = 0; u < HU; ++u) b[u] = st[(half * HU + u) * VT + vrow];
         const float hav = st_ha[vrow];
-        const float lo = -hav, hi = st_hm[vrow] - hav;
+        const float lo = -hav, sh = hav * s;
         const int sb = G::kFp8 ? st_sc[vrow] : 127;
         floatx16 acc[CB];
 #pragma unroll
@@ -180,7 +177,7 @@ __device__ __forceinline__ void lp_tile_pipe(int64_t t, int64_t nt, int64_t t_be
                 acc[cb] = mfma_main<DT>(&a[cb][q * T::kU4], &b[q * T::kU4], acc[cb], sa[cb], sb);
         if (pending) {
 #pragma unroll
-            for (int cb = 0; cb < CB; ++cb) clamp_sum16(prev[cb], prev_lo, prev_hi, acc_sum[cb]);
+            for (int cb = 0; cb < CB; ++cb) clamp_sum16(prev[cb], prev_lo, s, prev_sh, acc_sum[cb]);
         }
 #pragma unroll
         for (int i = 0; i < NMF; ++i) {
@@ -190,7 +187,7 @@ __device__ __forceinline__ void lp_tile_pipe(int64_t t, int64_t nt, int64_t t_be
 #pragma unroll
         for (int cb = 0; cb < CB; ++cb) prev[cb] = acc[cb];
         prev_lo = lo;
-        prev_hi = hi;
+        prev_sh = sh;
         pending = true;
     }
 }
@@ -241,11 +238,12 @@ __device__ __forceinline__ void load_candidates(const GainsArgs& ga, int64_t wba
     }
 }
 
-// float64 sums over the 32 columns of each half; one lane per row writes.
+// float64 sums over the 32 columns of each half, scaled back by 2^ge; one
+// lane per row writes.
 // In the grouped order (all candidates, no list) a slot's sum goes to its row.
 template <int CB>
 __device__ __forceinline__ void store_partials(const GainsArgs& ga, int64_t wbase, int split, int col, int half,
-                                               const float (&acc_sum)[CB][16]) {
+                                               const float (&acc_sum)[CB][16], int ge) {
 #pragma unroll
     for (int cb = 0; cb < CB; ++cb) {
         double mine = 0.0;
@@ -261,7 +259,7 @@ __device__ __forceinline__ void store_partials(const GainsArgs& ga, int64_t wbas
             const int64_t p = wbase + cb * 32 + 8 * (r / 4) + 4 * half + (r % 4);
             if (p < ga.n_cand) {
                 const int64_t at = (ga.perm && !ga.cand) ? int64_t(ga.perm[p]) : p;
-                ga.part[int64_t(split) * ga.part_stride + at] = 2.0 * mine;
+                ga.part[int64_t(split) * ga.part_stride + at] = ldexp(2.0 * mine, ge);  // exact: a power of two
             }
         }
     }
@@ -271,8 +269,9 @@ template <int DT, int KC, int CB, bool PIPE>
 __device__ __forceinline__ void gains_lp_body(const GainsArgs& ga, int64_t bid) {
     const uint4* __restrict__ xqt = static_cast<const uint4*>(ga.xq);
     const float* __restrict__ ha = ga.ha;
-    const float* __restrict__ hm = ga.hm;
     const int* __restrict__ sc = ga.scale;
+    const int ge = *ga.gexp;                // 2^ge >= m_v / 2 for every point
+    const float s = ldexpf(1.0f, -ge);      // the epilogue's power-of-two scale
     const int64_t n_pad = ga.n_pad, chunk = ga.chunk;
     const int32_t v_splits = ga.v_splits;
     using G = LpGeom<DT, KC, CB>;
@@ -311,48 +310,48 @@ __device__ __forceinline__ void gains_lp_body(const GainsArgs& ga, int64_t bid) 
     const int64_t t_begin = v_begin / VT;
     const int64_t nt = v_end > v_begin ? (v_end - v_begin) / VT : 0;
 
-    if (nt > 0) copy_stage<G>(wave, lane, t_begin, xqt, ha, hm, sc, lds0);
-    if (nt > 1) copy_stage<G>(wave, lane, t_begin + 1, xqt, ha, hm, sc, lds1);
+    if (nt > 0) copy_stage<G>(wave, lane, t_begin, xqt, ha, sc, lds0);
+    if (nt > 1) copy_stage<G>(wave, lane, t_begin + 1, xqt, ha, sc, lds1);
     // three stages are three distinct LDS objects and the loop is unrolled
     // by three, so the compiler can see that the copy in flight never
     // targets the stage being read and does not wait for it
     if (PIPE) {
         floatx16 prev[CB];
-        float prev_lo = 0.0f, prev_hi = 0.0f;
+        float prev_lo = 0.0f, prev_sh = 0.0f;
         bool pending = false;
         for (int64_t t = 0; t < nt; t += 3) {
-            lp_tile_pipe<G, DT, KC, CB>(t, nt, t_begin, wave, lane, col, half, xqt, ha, hm, sc, lds0, lds2, a,
-                                        cinit, sa, acc_sum, prev, prev_lo, prev_hi, pending);
+            lp_tile_pipe<G, DT, KC, CB>(t, nt, t_begin, wave, lane, col, half, xqt, ha, sc, lds0, lds2, a,
+                                        cinit, sa, acc_sum, prev, prev_lo, prev_sh, pending, s);
             if (t + 1 < nt)
-                lp_tile_pipe<G, DT, KC, CB>(t + 1, nt, t_begin, wave, lane, col, half, xqt, ha, hm, sc, lds1, lds0,
-                                            a, cinit, sa, acc_sum, prev, prev_lo, prev_hi, pending);
+                lp_tile_pipe<G, DT, KC, CB>(t + 1, nt, t_begin, wave, lane, col, half, xqt, ha, sc, lds1, lds0,
+                                            a, cinit, sa, acc_sum, prev, prev_lo, prev_sh, pending, s);
             if (t + 2 < nt)
-                lp_tile_pipe<G, DT, KC, CB>(t + 2, nt, t_begin, wave, lane, col, half, xqt, ha, hm, sc, lds2, lds1,
-                                            a, cinit, sa, acc_sum, prev, prev_lo, prev_hi, pending);
+                lp_tile_pipe<G, DT, KC, CB>(t + 2, nt, t_begin, wave, lane, col, half, xqt, ha, sc, lds2, lds1,
+                                            a, cinit, sa, acc_sum, prev, prev_lo, prev_sh, pending, s);
         }
         if (pending) {
 #pragma unroll
-            for (int cb = 0; cb < CB; ++cb) clamp_sum16(prev[cb], prev_lo, prev_hi, acc_sum[cb]);
+            for (int cb = 0; cb < CB; ++cb) clamp_sum16(prev[cb], prev_lo, s, prev_sh, acc_sum[cb]);
         }
     } else {
         for (int64_t t = 0; t < nt; t += 3) {
-            lp_tile<G, DT, KC, CB>(t, nt, t_begin, wave, lane, col, half, xqt, ha, hm, sc, lds0, lds2, a, cinit, sa,
-                                   acc_sum);
+            lp_tile<G, DT, KC, CB>(t, nt, t_begin, wave, lane, col, half, xqt, ha, sc, lds0, lds2, a, cinit, sa,
+                                   acc_sum, s);
             if (t + 1 < nt)
-                lp_tile<G, DT, KC, CB>(t + 1, nt, t_begin, wave, lane, col, half, xqt, ha, hm, sc, lds1, lds0, a,
-                                       cinit, sa, acc_sum);
+                lp_tile<G, DT, KC, CB>(t + 1, nt, t_begin, wave, lane, col, half, xqt, ha, sc, lds1, lds0, a,
+                                       cinit, sa, acc_sum, s);
             if (t + 2 < nt)
-                lp_tile<G, DT, KC, CB>(t + 2, nt, t_begin, wave, lane, col, half, xqt, ha, hm, sc, lds2, lds1, a,
-                                       cinit, sa, acc_sum);
+                lp_tile<G, DT, KC, CB>(t + 2, nt, t_begin, wave, lane, col, half, xqt, ha, sc, lds2, lds1, a,
+                                       cinit, sa, acc_sum, s);
         }
     }
 
-    store_partials<CB>(ga, wbase, split, col, half, acc_sum);
+    store_partials<CB>(ga, wbase, split, col, half, acc_sum, ge);
 }
 
 // ---------------------------------------------------------------------------
 // Ping-pong variant: 8 waves, two per SIMD. At d = 64 in BF16 the epilogue
-// (one med3 and one add per pair, 4 cycles per wave instruction) costs as
+// (one clamped fma and one add per pair, 4 cycles per wave instruction) costs as
 // many cycles as the matrix instructions, and a single wave cannot keep
 // both busy because its epilogue depends on its own MFMA results. Here the
 // two waves of a SIMD belong to two groups that run half a period apart:
@@ -368,14 +367,13 @@ template <class G>
 struct TileRegs {
     static constexpr int NCB = G::VT / 32;
     uint4 b[NCB][G::HU];
-    float ha[NCB], hm[NCB];  // raw, so that no instruction waits for these reads before the next phase
+    float ha[NCB];  // raw, so that no instruction waits for this read before the next phase
     int sb[NCB];
 };
 
 template <class G>
 __device__ __forceinline__ void read_tile(const uint4* st, int col, int half, TileRegs<G>& r) {
     const float* st_ha = reinterpret_cast<const float*>(st + G::OFF_HA);
-    const float* st_hm = reinterpret_cast<const float*>(st + G::OFF_HM);
     const int* st_sc = reinterpret_cast<const int*>(st + G::OFF_SC);
 #pragma unroll
     for (int colb = 0; colb < TileRegs<G>::NCB; ++colb) {
@@ -383,7 +381,6 @@ __device__ __forceinline__ void read_tile(const uint4* st, int col, int half, Ti
 #pragma unroll
         for (int u = 0; u < G::HU; ++u) r.b[colb][u] = st[(half * G::HU + u) * G::VT + vrow];
         r.ha[colb] = st_ha[vrow];
-        r.hm[colb] = st_hm[vrow];
         r.sb[colb] = G::kFp8 ? st_sc[vrow] : 127;
     }
 }
@@ -408,11 +405,11 @@ __device__ __forceinline__ void mfma_tile(const TileRegs<G>& r, const uint4 (&a)
 
 template <int NCB, int CB>
 __device__ __forceinline__ void epilogue_tile(const floatx16 (&acc)[NCB][CB], const float (&lo)[NCB],
-                                              const float (&hi)[NCB], float (&acc_sum)[CB][16]) {
+                                              const float (&sh)[NCB], float s, float (&acc_sum)[CB][16]) {
 #pragma unroll
     for (int colb = 0; colb < NCB; ++colb) {
 #pragma unroll
-        for (int cb = 0; cb < CB; ++cb) clamp_sum16(acc[colb][cb], lo[colb], hi[colb], acc_sum[cb]);
+        for (int cb = 0; cb < CB; ++cb) clamp_sum16(acc[colb][cb], lo[colb], s, sh[colb], acc_sum[cb]);
     }
 }
 
@@ -429,22 +426,23 @@ __device__ __forceinline__ void phase_barrier() {
 template <class G, int DT, int KC, int CB>
 __device__ __forceinline__ void pp_lead(int64_t t, int64_t nt, int64_t t_begin, int wave, int lane, int col, int half,
                                         const uint4* __restrict__ xqt, const float* __restrict__ ha,
-                                        const float* __restrict__ hm, const int* __restrict__ sc, const uint4* nxt,
+                                        const int* __restrict__ sc, const uint4* nxt,
                                         uint4* nx2, TileRegs<G>& r, const uint4 (&a)[CB][G::HU],
-                                        const floatx16 (&cinit)[CB], const int (&sa)[CB], float (&acc_sum)[CB][16]) {
+                                        const floatx16 (&cinit)[CB], const int (&sa)[CB], float (&acc_sum)[CB][16],
+                                        float s) {
     constexpr int NCB = TileRegs<G>::NCB;
-    if (t + 2 < nt) copy_stage<G>(wave, lane, t_begin + t + 2, xqt, ha, hm, sc, nx2);
+    if (t + 2 < nt) copy_stage<G>(wave, lane, t_begin + t + 2, xqt, ha, sc, nx2);
     floatx16 acc[NCB][CB];
     // the whole matrix phase at raised priority (lowered after the barrier
     // that ends it), so each MFMA issues as soon as the matrix pipe takes it
     // even while the other wave has VALU work
     __builtin_amdgcn_s_setprio(1);
     mfma_tile<G, DT, KC, CB>(r, a, cinit, sa, acc);
-    float lo[NCB], hi[NCB];
+    float lo[NCB], sh[NCB];
 #pragma unroll
     for (int c = 0; c < NCB; ++c) {
         lo[c] = -r.ha[c];
-        hi[c] = r.hm[c] - r.ha[c];
+        sh[c] = r.ha[c] * s;
     }
     // this wave's copies of tile t+1 have landed (those of t+2 may still fly)
     if (t + 1 < nt) {
@@ -456,7 +454,7 @@ __device__ __forceinline__ void pp_lead(int64_t t, int64_t nt, int64_t t_begin, 
     phase_barrier();
     __builtin_amdgcn_s_setprio(0);
     if (t + 1 < nt) read_tile<G>(nxt, col, half, r);
-    epilogue_tile<NCB, CB>(acc, lo, hi, acc_sum);
+    epilogue_tile<NCB, CB>(acc, lo, sh, s, acc_sum);
     phase_barrier();
 }
 
@@ -465,7 +463,7 @@ __device__ __forceinline__ void pp_lead(int64_t t, int64_t nt, int64_t t_begin, 
 template <class G, int DT, int KC, int CB>
 __device__ __forceinline__ void pp_follow(int64_t t, int64_t nt, int col, int half, const uint4* nxt, TileRegs<G>& r,
                                           const uint4 (&a)[CB][G::HU], const floatx16 (&cinit)[CB],
-                                          const int (&sa)[CB], float (&acc_sum)[CB][16]) {
+                                          const int (&sa)[CB], float (&acc_sum)[CB][16], float s) {
     constexpr int NCB = TileRegs<G>::NCB;
     floatx16 acc[NCB][CB];
     // the whole matrix phase at raised priority (lowered after the barrier
@@ -473,16 +471,16 @@ __device__ __forceinline__ void pp_follow(int64_t t, int64_t nt, int col, int ha
     // even while the other wave has VALU work
     __builtin_amdgcn_s_setprio(1);
     mfma_tile<G, DT, KC, CB>(r, a, cinit, sa, acc);
-    float lo[NCB], hi[NCB];
+    float lo[NCB], sh[NCB];
 #pragma unroll
     for (int c = 0; c < NCB; ++c) {
         lo[c] = -r.ha[c];
-        hi[c] = r.hm[c] - r.ha[c];
+        sh[c] = r.ha[c] * s;
     }
     phase_barrier();
     __builtin_amdgcn_s_setprio(0);
     if (t + 1 < nt) read_tile<G>(nxt, col, half, r);
-    epilogue_tile<NCB, CB>(acc, lo, hi, acc_sum);
+    epilogue_tile<NCB, CB>(acc, lo, sh, s, acc_sum);
     if (t + 1 < nt) phase_barrier();
 }
 
@@ -490,8 +488,9 @@ template <int DT, int KC, int CB>
 __device__ __forceinline__ void gains_lp_pp_body(const GainsArgs& ga, int64_t bid) {
     const uint4* __restrict__ xqt = static_cast<const uint4*>(ga.xq);
     const float* __restrict__ ha = ga.ha;
-    const float* __restrict__ hm = ga.hm;
     const int* __restrict__ sc = ga.scale;
+    const int ge = *ga.gexp;                // 2^ge >= m_v / 2 for every point
+    const float s = ldexpf(1.0f, -ge);      // the epilogue's power-of-two scale
     using G = LpGeom<DT, KC, CB>;
     using T = Lp<DT>;
     constexpr int HU = G::HU, VT = G::VT;
@@ -531,8 +530,8 @@ __device__ __forceinline__ void gains_lp_pp_body(const GainsArgs& ga, int64_t bi
     if (grp == 0) {
         // leading group: issues every copy; barriers B0 + 2 per tile
         const int w4 = wave & 3;
-        if (nt > 0) copy_stage<G>(w4, lane, t_begin, xqt, ha, hm, sc, lds0);
-        if (nt > 1) copy_stage<G>(w4, lane, t_begin + 1, xqt, ha, hm, sc, lds1);
+        if (nt > 0) copy_stage<G>(w4, lane, t_begin, xqt, ha, sc, lds0);
+        if (nt > 1) copy_stage<G>(w4, lane, t_begin + 1, xqt, ha, sc, lds1);
         if (nt > 1)
             wait_vmcnt<G::L>();
         else
@@ -540,14 +539,14 @@ __device__ __forceinline__ void gains_lp_pp_body(const GainsArgs& ga, int64_t bi
         phase_barrier();  // B0: tile 0 in LDS
         if (nt > 0) read_tile<G>(lds0, col, half, r);
         for (int64_t t = 0; t < nt; t += 3) {
-            pp_lead<G, DT, KC, CB>(t, nt, t_begin, w4, lane, col, half, xqt, ha, hm, sc, lds1, lds2, r, a, cinit, sa,
-                                   acc_sum);
+            pp_lead<G, DT, KC, CB>(t, nt, t_begin, w4, lane, col, half, xqt, ha, sc, lds1, lds2, r, a, cinit, sa,
+                                   acc_sum, s);
             if (t + 1 < nt)
-                pp_lead<G, DT, KC, CB>(t + 1, nt, t_begin, w4, lane, col, half, xqt, ha, hm, sc, lds2, lds0, r, a,
-                                       cinit, sa, acc_sum);
+                pp_lead<G, DT, KC, CB>(t + 1, nt, t_begin, w4, lane, col, half, xqt, ha, sc, lds2, lds0, r, a,
+                                       cinit, sa, acc_sum, s);
             if (t + 2 < nt)
-                pp_lead<G, DT, KC, CB>(t + 2, nt, t_begin, w4, lane, col, half, xqt, ha, hm, sc, lds0, lds1, r, a,
-                                       cinit, sa, acc_sum);
+                pp_lead<G, DT, KC, CB>(t + 2, nt, t_begin, w4, lane, col, half, xqt, ha, sc, lds0, lds1, r, a,
+                                       cinit, sa, acc_sum, s);
         }
     } else {
         // following group, one phase behind: barriers B0 + 1 + 2 per tile - 1
@@ -556,15 +555,15 @@ __device__ __forceinline__ void gains_lp_pp_body(const GainsArgs& ga, int64_t bi
             read_tile<G>(lds0, col, half, r);
             phase_barrier();  // end of phase 0 (the leading group's first matrix phase)
             for (int64_t t = 0; t < nt; t += 3) {
-                pp_follow<G, DT, KC, CB>(t, nt, col, half, lds1, r, a, cinit, sa, acc_sum);
+                pp_follow<G, DT, KC, CB>(t, nt, col, half, lds1, r, a, cinit, sa, acc_sum, s);
                 if (t + 1 < nt)
-                    pp_follow<G, DT, KC, CB>(t + 1, nt, col, half, lds2, r, a, cinit, sa, acc_sum);
+                    pp_follow<G, DT, KC, CB>(t + 1, nt, col, half, lds2, r, a, cinit, sa, acc_sum, s);
                 if (t + 2 < nt)
-                    pp_follow<G, DT, KC, CB>(t + 2, nt, col, half, lds0, r, a, cinit, sa, acc_sum);
+                    pp_follow<G, DT, KC, CB>(t + 2, nt, col, half, lds0, r, a, cinit, sa, acc_sum, s);
             }
         }
     }
-    store_partials<CB>(ga, wbase, split, col, half, acc_sum);
+    store_partials<CB>(ga, wbase, split, col, half, acc_sum, ge);
 }
 
 // ---------------------------------------------------------------------------
@@ -594,14 +593,14 @@ __device__ __forceinline__ void sp_test(const floatx16 (&acc)[CB], float lo, uin
 }
 
 template <int CB>
-__device__ __forceinline__ void sp_sum(const floatx16 (&acc)[CB], float lo, float hi, const uint64_t (&hit)[CB],
+__device__ __forceinline__ void sp_sum(const floatx16 (&acc)[CB], float s, float sh, const uint64_t (&hit)[CB],
                                        float (&acc_sum)[CB][16]) {
 #pragma unroll
     for (int cb = 0; cb < CB; ++cb) {
         if (hit[cb] == 0) continue;
         float t[16];
 #pragma unroll
-        for (int r = 0; r < 16; ++r) t[r] = __builtin_amdgcn_fmed3f(acc[cb][r], lo, hi) - lo;
+        for (int r = 0; r < 16; ++r) t[r] = __builtin_amdgcn_fmed3f(fmaf(acc[cb][r], s, sh), 0.0f, 1.0f);
         asm volatile(""
                      : "+v"(t[0]), "+v"(t[1]), "+v"(t[2]), "+v"(t[3]), "+v"(t[4]), "+v"(t[5]), "+v"(t[6]),
                        "+v"(t[7]), "+v"(t[8]), "+v"(t[9]), "+v"(t[10]), "+v"(t[11]), "+v"(t[12]), "+v"(t[13]),
@@ -612,12 +611,12 @@ __device__ __forceinline__ void sp_sum(const floatx16 (&acc)[CB], float lo, floa
 }
 
 // One column block: MFMAs into acc, interleaved with the test of pacc (the
-// previous block, bounds plo/phi), then the previous block's clamp-and-sum
+// previous block, bound plo, shift psh), then the previous block's clamp-and-sum
 // where the test found values above the bound.
 template <class G, int DT, int KC, int CB>
 __device__ __forceinline__ void sp_colb(const uint4 (&b)[G::HU], int sb, const uint4 (&a)[CB][G::HU],
                                         const floatx16 (&cinit)[CB], const int (&sa)[CB], floatx16 (&acc)[CB],
-                                        const floatx16 (&pacc)[CB], float plo, float phi,
+                                        const floatx16 (&pacc)[CB], float plo, float psh, float s,
                                         float (&acc_sum)[CB][16]) {
     using T = Lp<DT>;
     constexpr int NMF = KC * CB;     // matrix instructions of the block
@@ -639,17 +638,17 @@ __device__ __forceinline__ void sp_colb(const uint4 (&b)[G::HU], int sb, const u
     uint64_t any = 0;
 #pragma unroll
     for (int cb = 0; cb < CB; ++cb) any |= hit[cb];
-    if (any) sp_sum<CB>(pacc, plo, phi, hit, acc_sum);
+    if (any) sp_sum<CB>(pacc, s, psh, hit, acc_sum);
 }
 
 // One ground tile (two column blocks) of the interleaved variant.
 template <class G, int DT, int KC, int CB>
 __device__ __forceinline__ void sp_tile(int64_t t, int64_t nt, int64_t t_begin, int wave, int lane, int col, int half,
                                         const uint4* __restrict__ xqt, const float* __restrict__ ha,
-                                        const float* __restrict__ hm, const int* __restrict__ sc, const uint4* st,
+                                        const int* __restrict__ sc, const uint4* st,
                                         uint4* next2, const uint4 (&a)[CB][G::HU], const floatx16 (&cinit)[CB],
                                         const int (&sa)[CB], float (&acc_sum)[CB][16], floatx16 (&accA)[CB],
-                                        floatx16 (&accB)[CB], float& loB, float& hiB) {
+                                        floatx16 (&accB)[CB], float& loB, float& shB, float s) {
     constexpr int HU = G::HU, VT = G::VT;
     static_assert(VT == 64, "two column blocks per ground tile");
     if (t + 1 < nt)
@@ -657,32 +656,32 @@ __device__ __forceinline__ void sp_tile(int64_t t, int64_t nt, int64_t t_begin, 
     else
         wait_vmcnt<0>();
     ring_barrier();
-    if (t + 2 < nt) copy_stage<G>(wave, lane, t_begin + t + 2, xqt, ha, hm, sc, next2);
+    if (t + 2 < nt) copy_stage<G>(wave, lane, t_begin + t + 2, xqt, ha, sc, next2);
     const float* st_ha = reinterpret_cast<const float*>(st + G::OFF_HA);
-    const float* st_hm = reinterpret_cast<const float*>(st + G::OFF_HM);
     const int* st_sc = reinterpret_cast<const int*>(st + G::OFF_SC);
     uint4 b0[HU], b1[HU];
 #pragma unroll
     for (int u = 0; u < HU; ++u) b0[u] = st[(half * HU + u) * VT + col];
 #pragma unroll
     for (int u = 0; u < HU; ++u) b1[u] = st[(half * HU + u) * VT + 32 + col];
-    const float ha0 = st_ha[col], hm0 = st_hm[col], ha1 = st_ha[32 + col], hm1 = st_hm[32 + col];
+    const float ha0 = st_ha[col], ha1 = st_ha[32 + col];
     const int sb0 = G::kFp8 ? st_sc[col] : 127, sb1 = G::kFp8 ? st_sc[32 + col] : 127;
-    const float lo0 = -ha0, hi0 = hm0 - ha0;
+    const float lo0 = -ha0, sh0 = ha0 * s;
     // column block 0 (into accA) with the previous tile's block 1 (accB)
-    sp_colb<G, DT, KC, CB>(b0, sb0, a, cinit, sa, accA, accB, loB, hiB, acc_sum);
+    sp_colb<G, DT, KC, CB>(b0, sb0, a, cinit, sa, accA, accB, loB, shB, s, acc_sum);
     // column block 1 (into accB) with block 0 (accA)
-    sp_colb<G, DT, KC, CB>(b1, sb1, a, cinit, sa, accB, accA, lo0, hi0, acc_sum);
+    sp_colb<G, DT, KC, CB>(b1, sb1, a, cinit, sa, accB, accA, lo0, sh0, s, acc_sum);
     loB = -ha1;
-    hiB = hm1 - ha1;
+    shB = ha1 * s;
 }
 
 template <int DT, int KC, int CB>
 __device__ __forceinline__ void gains_lp_sp_body(const GainsArgs& ga, int64_t bid) {
     const uint4* __restrict__ xqt = static_cast<const uint4*>(ga.xq);
     const float* __restrict__ ha = ga.ha;
-    const float* __restrict__ hm = ga.hm;
     const int* __restrict__ sc = ga.scale;
+    const int ge = *ga.gexp;                // 2^ge >= m_v / 2 for every point
+    const float s = ldexpf(1.0f, -ge);      // the epilogue's power-of-two scale
     using G = LpGeom<DT, KC, CB>;
     using T = Lp<DT>;
     constexpr int HU = G::HU, VT = G::VT;
@@ -714,7 +713,7 @@ __device__ __forceinline__ void gains_lp_sp_body(const GainsArgs& ga, int64_t bi
             acc_sum[cb][r] = 0.0f;
             accB[cb][r] = -INFINITY;  // no previous block yet: its test finds nothing
         }
-    float loB = 0.0f, hiB = 0.0f;
+    float loB = 0.0f, shB = 0.0f;
 
     const int64_t v_begin = int64_t(split) * ga.chunk;
     int64_t v_end = v_begin + ga.chunk;
@@ -722,22 +721,22 @@ __device__ __forceinline__ void gains_lp_sp_body(const GainsArgs& ga, int64_t bi
     const int64_t t_begin = v_begin / VT;
     const int64_t nt = v_end > v_begin ? (v_end - v_begin) / VT : 0;
 
-    if (nt > 0) copy_stage<G>(wave, lane, t_begin, xqt, ha, hm, sc, lds0);
-    if (nt > 1) copy_stage<G>(wave, lane, t_begin + 1, xqt, ha, hm, sc, lds1);
+    if (nt > 0) copy_stage<G>(wave, lane, t_begin, xqt, ha, sc, lds0);
+    if (nt > 1) copy_stage<G>(wave, lane, t_begin + 1, xqt, ha, sc, lds1);
     for (int64_t t = 0; t < nt; t += 3) {
-        sp_tile<G, DT, KC, CB>(t, nt, t_begin, wave, lane, col, half, xqt, ha, hm, sc, lds0, lds2, a, cinit, sa,
-                               acc_sum, accA, accB, loB, hiB);
+        sp_tile<G, DT, KC, CB>(t, nt, t_begin, wave, lane, col, half, xqt, ha, sc, lds0, lds2, a, cinit, sa,
+                               acc_sum, accA, accB, loB, shB, s);
         if (t + 1 < nt)
-            sp_tile<G, DT, KC, CB>(t + 1, nt, t_begin, wave, lane, col, half, xqt, ha, hm, sc, lds1, lds0, a, cinit,
-                                   sa, acc_sum, accA, accB, loB, hiB);
+            sp_tile<G, DT, KC, CB>(t + 1, nt, t_begin, wave, lane, col, half, xqt, ha, sc, lds1, lds0, a, cinit,
+                                   sa, acc_sum, accA, accB, loB, shB, s);
         if (t + 2 < nt)
-            sp_tile<G, DT, KC, CB>(t + 2, nt, t_begin, wave, lane, col, half, xqt, ha, hm, sc, lds2, lds1, a, cinit,
-                                   sa, acc_sum, accA, accB, loB, hiB);
+            sp_tile<G, DT, KC, CB>(t + 2, nt, t_begin, wave, lane, col, half, xqt, ha, sc, lds2, lds1, a, cinit,
+                                   sa, acc_sum, accA, accB, loB, shB, s);
     }
     // the last column block
 #pragma unroll
-    for (int cb = 0; cb < CB; ++cb) clamp_sum16(accB[cb], loB, hiB, acc_sum[cb]);
-    store_partials<CB>(ga, wbase, split, col, half, acc_sum);
+    for (int cb = 0; cb < CB; ++cb) clamp_sum16(accB[cb], loB, s, shB, acc_sum[cb]);
+    store_partials<CB>(ga, wbase, split, col, half, acc_sum, ge);
 }
 
 template <int DT, int KC, int CB>

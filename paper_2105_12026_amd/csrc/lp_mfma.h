@@ -29,17 +29,22 @@ struct Lp<EBC_DT_FP8_E4M3> {
     static constexpr int kElem = 1, kChunkK = 64, kU4 = 2;
 };
 
-// Clamp-and-sum of one 32x32 result tile for this lane: each term is
-// med3(acc, lo, hi) - lo, so a value at or below the lane's lower bound lo
-// adds exactly 0. A tile whose every value, in every lane, lies at or below
-// its lane's bound (the largest of the lane's 16 values, a ballot over the
-// wave) adds only zeros and is skipped: the same sums, bit for bit, so
-// whether a tile is skipped never changes a result. Otherwise the 16 clamps
-// and shifts are issued back to back into 16 registers (the empty asm
-// statement keeps them all live, so the compiler cannot reuse one
-// temporary and make every add wait for the term just before it), then the
-// 16 adds; the per-lane sum order is the same in every tile variant.
-__device__ __forceinline__ void clamp_sum16(const floatx16& acc, float lo, float hi, float (&sum)[16]) {
+// Clamp-and-sum of one 32x32 result tile for this lane. Each term is
+// clamp(s (acc - lo), 0, 1) with s = 2^-e a power of two and 2^e >= m_v / 2
+// for every point: one v_fma_f32 with the clamp bit, fed the per-column
+// shift sh = -lo s. Scaling by a power of two is exact, so each term is
+// s (acc - lo) rounded once, i.e. the scaled term max(0, m_v/2 - d^/2); the
+// upper bound 1 stands for the scaled m_v/2 and only binds when rounding
+// makes a computed distance negative. A value at or below the lane's lower
+// bound lo adds exactly 0, so a tile whose every value, in every lane, lies
+// at or below its lane's bound (the largest of the lane's 16 values, a ballot
+// over the wave) adds only zeros and is skipped: the same sums, bit for bit,
+// so whether a tile is skipped never changes a result. Otherwise the 16
+// terms are issued back to back into 16 registers (the empty asm statement
+// keeps them all live, so the compiler cannot reuse one temporary and make
+// every add wait for the term just before it), then the 16 adds; the
+// per-lane sum order is the same in every tile variant.
+__device__ __forceinline__ void clamp_sum16(const floatx16& acc, float lo, float s, float sh, float (&sum)[16]) {
     float m = fmaxf(fmaxf(acc[0], acc[1]), acc[2]);
 #pragma unroll
     for (int r = 3; r < 15; r += 2) m = fmaxf(fmaxf(m, acc[r]), acc[r + 1]);
@@ -47,7 +52,7 @@ __device__ __forceinline__ void clamp_sum16(const floatx16& acc, float lo, float
     if (__builtin_amdgcn_ballot_w64(m > lo) == 0) return;
     float t[16];
 #pragma unroll
-    for (int r = 0; r < 16; ++r) t[r] = __builtin_amdgcn_fmed3f(acc[r], lo, hi) - lo;
+    for (int r = 0; r < 16; ++r) t[r] = __builtin_amdgcn_fmed3f(fmaf(acc[r], s, sh), 0.0f, 1.0f);
     asm volatile(""
                  : "+v"(t[0]), "+v"(t[1]), "+v"(t[2]), "+v"(t[3]), "+v"(t[4]), "+v"(t[5]), "+v"(t[6]), "+v"(t[7]),
                    "+v"(t[8]), "+v"(t[9]), "+v"(t[10]), "+v"(t[11]), "+v"(t[12]), "+v"(t[13]), "+v"(t[14]),

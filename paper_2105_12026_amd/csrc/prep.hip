@@ -711,6 +711,16 @@ __global__ void __launch_bounds__(kBlock) k_norm_blocks(Buffers b) {
     }
 }
 
+// Raise DevState::gexp so that 2^gexp >= mmax / 2 (0 <= gexp <= 126, so the
+// scale 2^-gexp stays a normal float). Atomic: blocks of k_load_m race.
+__device__ inline void raise_gexp(DevState* st, double mmax) {
+    int e = 0;
+    if (mmax > 0.0) (void)frexp(0.5 * mmax, &e);  // 0.5 mmax < 2^e
+    if (!(mmax <= 1.0e300)) e = 126;             // non-finite (reported elsewhere) or huge
+    e = e < 0 ? 0 : (e > 126 ? 126 : e);
+    atomicMax(&st->gexp, e);
+}
+
 // One block: L({e0}) = |V|^-1 sum of the per-block norm sums (fixed order),
 // and the largest norm.
 __global__ void __launch_bounds__(kBlock) k_l0(int64_t n, int32_t nblocks, Buffers b) {
@@ -734,6 +744,7 @@ __global__ void __launch_bounds__(kBlock) k_l0(int64_t n, int32_t nblocks, Buffe
     if (threadIdx.x == 0) {
         b.state->l0 = red[0] / double(n);
         b.state->nmax = rmax[0];
+        raise_gexp(b.state, rmax[0]);
     }
 }
 
@@ -750,6 +761,8 @@ __global__ void k_state_init(DevState* st) {
         st->tau = 0.0;
         st->tau_abs = 0.0;
         st->nmax = 0.0;
+        st->gexp = 0;
+        st->pad1 = 0;
     }
 }
 
@@ -910,14 +923,24 @@ hipError_t launch_set_e0(const ebc_dataset* ds, const float* e0, hipStream_t s) 
     return launch_reset_state(ds, s);
 }
 
-// Replace the running minima by a caller-supplied m (float64, [n]).
+// Replace the running minima by a caller-supplied m (float64, [n]), and
+// raise the gains scale exponent to cover the largest of them.
 __global__ void __launch_bounds__(kBlock) k_load_m(int64_t n, const double* __restrict__ m, Buffers b) {
+    __shared__ double rmax[kBlock];
     const int64_t r = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+    double mv = 0.0;
     if (r < n) {
-        const double mv = m[r];
+        mv = m[r];
         b.m64[r] = mv;
         set_point_terms(b, r, mv);
     }
+    rmax[threadIdx.x] = mv;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) rmax[threadIdx.x] = fmax(rmax[threadIdx.x], rmax[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) raise_gexp(b.state, rmax[0]);
 }
 
 hipError_t launch_load_m(const ebc_dataset* ds, const double* m, hipStream_t s) {
