@@ -166,14 +166,62 @@ __device__ void wselect_body(const InstDesc& c) {
 
 // ---- rescore: float64 direct-difference gains of the window candidates ----
 // One thread per ground point, from the caller's float32 points; candidates
-// in groups of 8 staged in LDS, up to 512 dimensions at a time (long rows
-// take several passes, summed in dimension order); per-block sums in a
-// fixed order.
+// in groups of 8 staged in LDS as float64, up to 128 dimensions at a time
+// (longer rows take several passes, summed in dimension order); each thread
+// reads its own row in 16-byte pieces when rows are 16-byte aligned, four
+// pieces in flight (the other lanes' pieces of the same cache lines follow
+// in the next iterations); per-block sums in a fixed order.
 constexpr int kRescoreGroup = 8;
-constexpr int kRescoreChunk = 512;
+constexpr int kRescoreChunk = 128;
+
+// One dimension's term for the NJ staged candidates (stride kRescoreChunk):
+// squared difference (METRIC 0) or absolute difference (METRIC 1).
+template <int METRIC, int NJ>
+__device__ __forceinline__ void dim_terms(double xk, const double* __restrict__ cxk, double (&acc)[NJ]) {
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+        const double t = xk - cxk[j * kRescoreChunk];
+        if (METRIC == 1)
+            acc[j] += fabs(t);
+        else
+            acc[j] = fma(t, t, acc[j]);
+    }
+}
+
+// acc[j] += sum over k < kn, in k order, of the terms between row piece xv
+// (float32, global) and the staged candidates cx[j][0..kn).
+template <int METRIC, int NJ>
+__device__ __forceinline__ void row_terms(const float* __restrict__ xv, bool vec, int kn,
+                                          const double* __restrict__ cx, double (&acc)[NJ]) {
+    int k = 0;
+    if (vec) {
+        const float4* __restrict__ x4 = reinterpret_cast<const float4*>(xv);
+        for (; k + 16 <= kn; k += 16) {
+            float4 q[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) q[u] = x4[k / 4 + u];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                dim_terms<METRIC, NJ>(double(q[u].x), cx + k + 4 * u, acc);
+                dim_terms<METRIC, NJ>(double(q[u].y), cx + k + 4 * u + 1, acc);
+                dim_terms<METRIC, NJ>(double(q[u].z), cx + k + 4 * u + 2, acc);
+                dim_terms<METRIC, NJ>(double(q[u].w), cx + k + 4 * u + 3, acc);
+            }
+        }
+        for (; k + 4 <= kn; k += 4) {
+            const float4 q = x4[k / 4];
+            dim_terms<METRIC, NJ>(double(q.x), cx + k, acc);
+            dim_terms<METRIC, NJ>(double(q.y), cx + k + 1, acc);
+            dim_terms<METRIC, NJ>(double(q.z), cx + k + 2, acc);
+            dim_terms<METRIC, NJ>(double(q.w), cx + k + 3, acc);
+        }
+    }
+    for (; k < kn; ++k) dim_terms<METRIC, NJ>(double(xv[k]), cx + k, acc);
+}
+
 // METRIC 0: squared Euclidean (the paper's d); 1: L1, sum of |x_vk - x_ck|.
 template <int METRIC>
-__device__ void rescore_impl(const InstDesc& c, int64_t blk, float* __restrict__ cx, double (*red)[kBlock]) {
+__device__ void rescore_impl(const InstDesc& c, int64_t blk, double* __restrict__ cx, double (*red)[kBlock]) {
     const Buffers& b = c.b;
     const float* __restrict__ x = c.x;
     const int d = c.d;
@@ -181,7 +229,8 @@ __device__ void rescore_impl(const InstDesc& c, int64_t blk, float* __restrict__
     const int64_t v = blk * kBlock + threadIdx.x;
     const bool live = v < c.n;
     const double mv = live ? b.m64[v] : 0.0;
-    const float* xv = x + (live ? v : 0) * d;
+    const float* __restrict__ xv = x + (live ? v : 0) * d;
+    const bool vec = (d & 3) == 0 && (reinterpret_cast<uintptr_t>(x) & 15) == 0;
     for (int g0 = 0; g0 < W; g0 += kRescoreGroup) {
         const int gn = (W - g0) < kRescoreGroup ? (W - g0) : kRescoreGroup;
         double acc[kRescoreGroup];
@@ -190,24 +239,13 @@ __device__ void rescore_impl(const InstDesc& c, int64_t blk, float* __restrict__
         for (int k0 = 0; k0 < d; k0 += kRescoreChunk) {
             const int kn = (d - k0) < kRescoreChunk ? (d - k0) : kRescoreChunk;
             __syncthreads();
-            for (int e = threadIdx.x; e < gn * kn; e += kBlock) {
+            for (int e = threadIdx.x; e < kRescoreGroup * kn; e += kBlock) {
                 const int j = e / kn, k = e % kn;
-                cx[j * kRescoreChunk + k] = x[int64_t(b.wfinal[g0 + j].idx) * d + k0 + k];
+                // rows past the group's end repeat its first candidate (their sums are not used)
+                cx[j * kRescoreChunk + k] = double(x[int64_t(b.wfinal[g0 + (j < gn ? j : 0)].idx) * d + k0 + k]);
             }
             __syncthreads();
-            if (live) {
-                for (int k = 0; k < kn; ++k) {
-                    const double xk = double(xv[k0 + k]);
-#pragma unroll
-                    for (int j = 0; j < kRescoreGroup; ++j) {
-                        const double t = xk - double(cx[j * kRescoreChunk + k]);
-                        if (METRIC == 1)
-                            acc[j] += fabs(t);
-                        else
-                            acc[j] = fma(t, t, acc[j]);
-                    }
-                }
-            }
+            if (live) row_terms<METRIC, kRescoreGroup>(xv + k0, vec, kn, cx, acc);
         }
 #pragma unroll
         for (int j = 0; j < kRescoreGroup; ++j) red[j][threadIdx.x] = live ? fmax(0.0, mv - acc[j]) : 0.0;
@@ -224,7 +262,7 @@ __device__ void rescore_impl(const InstDesc& c, int64_t blk, float* __restrict__
 }
 
 __device__ void rescore_body(const InstDesc& c, int64_t blk) {
-    __shared__ float cx[kRescoreGroup * kRescoreChunk];
+    __shared__ double cx[kRescoreGroup * kRescoreChunk];
     __shared__ double red[kRescoreGroup][kBlock];
     if (c.metric == 1)
         rescore_impl<1>(c, blk, cx, red);
@@ -331,29 +369,27 @@ __device__ void pick_body(const InstDesc& c, int32_t t) {
 
 // ---- update: m_v <- min(m_v, d(v, c*)) in float64, per-block sums of m_v ----
 __device__ void update_body(const InstDesc& c, int64_t blk) {
-    __shared__ float cx[kNarrowMaxK];
+    static_assert(kNarrowMaxK <= kRescoreChunk, "short rows fit one staged piece");
+    __shared__ double cx[kRescoreChunk];
     __shared__ double red[kBlock];
     const Buffers& b = c.b;
     const float* __restrict__ x = c.x;
     const int d = c.d;
     const int cs = b.state->cstar;
     if (cs >= 0)
-        for (int k = threadIdx.x; k < d; k += kBlock) cx[k] = x[int64_t(cs) * d + k];
+        for (int k = threadIdx.x; k < d; k += kBlock) cx[k] = double(x[int64_t(cs) * d + k]);
     __syncthreads();
     const int64_t v = blk * kBlock + threadIdx.x;
     double mv = 0.0;
     if (v < c.n && cs < 0) {
         mv = b.m64[v];
     } else if (v < c.n) {
-        const float* xv = x + v * d;
-        double acc = 0.0;
-        for (int k = 0; k < d; ++k) {
-            const double t = double(xv[k]) - double(cx[k]);
-            acc = fma(t, t, acc);
-        }
+        const bool vec = (d & 3) == 0 && (reinterpret_cast<uintptr_t>(x) & 15) == 0;
+        double acc[1] = {0.0};
+        row_terms<0, 1>(x + v * d, vec, d, cx, acc);
         mv = b.m64[v];
-        if (acc < mv) {
-            mv = acc;
+        if (acc[0] < mv) {
+            mv = acc[0];
             b.m64[v] = mv;
             set_point_terms(b, v, mv);
         }
@@ -368,7 +404,7 @@ __device__ void update_body(const InstDesc& c, int64_t blk) {
 }
 
 // ---- L1 update (any row length): m_v <- min(m_v, sum_k |x_vk - x_c*k|) in
-// float64, the new member's values staged in LDS 512 at a time; per-block
+// float64, the new member's values staged in LDS 128 at a time; per-block
 // sums of m_v as in update_body ----
 __device__ void update_l1_body(const InstDesc& c, int64_t blk) {
     __shared__ float cx[kRescoreChunk];
