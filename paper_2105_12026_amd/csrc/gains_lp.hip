@@ -44,37 +44,54 @@
 namespace ebc {
 
 
-template <int DT, int KC, int CB>
+// Geometry of one kernel instance. A ring stage holds VT ground points: VT/64
+// consecutive 64-row HBM tiles (contiguous in memory, copied as they lie).
+template <int DT, int KC, int CB, int VTS = 64>
 struct LpGeom {
     using T = Lp<DT>;
     static constexpr int RB = KC * T::kChunkK * T::kElem;  // bytes per quantised row
     static constexpr int RU = RB / 16;                     // 16-byte units per row
     static constexpr int HU = RU / 2;                      // units per lane half-row
-    static constexpr int VT = 64;                          // rows per tile
+    static constexpr int HT = 64;                          // rows per tile in HBM
+    static constexpr int VT = VTS;                         // ground points per ring stage
+    static_assert(VT == 64 || VT == 128 || VT == 256, "stages of 64, 128 or 256 points");
+    static constexpr int NU = RU * (VT / 64);              // 1 KB unit pieces per stage
     static constexpr bool kFp8 = DT == EBC_DT_FP8_E4M3;
-    // LDS stage: [RU units x 64 rows][ha: 64 floats][scale: 64 ints]
-    static constexpr int OFF_HA = RU * VT;
+    // per-point pieces (ha, FP8 scales): one 16-byte-per-lane copy per 256
+    // points, else one 4-byte-per-lane copy per 64 points
+    static constexpr int PB = VT % 256 == 0 ? 16 : 4;       // bytes per lane of a per-point piece
+    static constexpr int PP = VT * 4 / (64 * PB);           // pieces per per-point array
+    // LDS stage: [VT/64 tiles][RU units][64 rows][ha: VT floats][scale: VT ints]
+    static constexpr int OFF_HA = NU * 64;
     static constexpr int OFF_SC = OFF_HA + VT / 4;
     static constexpr int STAGE = OFF_SC + (kFp8 ? VT / 4 : 0);  // uint4 per stage
-    static constexpr int NI = RU + 1 + (kFp8 ? 1 : 0);         // wave copy instructions per stage
+    static constexpr int NI = NU + PP * (kFp8 ? 2 : 1);        // wave copy instructions per stage
     static constexpr int L = (NI + 3) / 4;                      // copy instructions per wave per stage
     static constexpr int NBUF = 3;
     static constexpr int CAND_TILE = 4 * 32 * CB;
 };
 
-// Wave-wide copy of one piece of ground-set tile `tile` into LDS stage `st`.
-// Piece j: j < RU main unit j; then the 64 ha; then (FP8) the 64 row scales.
+// Wave-wide copy of one piece of ground-set stage `tile` into LDS stage `st`.
+// Piece j: j < NU unit piece j (a kilobyte of one 64-row tile); then the ha
+// pieces; then (FP8) the row-scale pieces.
 template <class G>
 __device__ __forceinline__ void copy_piece(int j, int64_t tile, int lane, const uint4* __restrict__ xqt,
                                            const float* __restrict__ ha, const int* __restrict__ sc, uint4* st) {
-    if (j < G::RU) {
-        __builtin_amdgcn_global_load_lds(xqt + (tile * G::RU + j) * G::VT + lane, (lds_void*)(st + j * G::VT), 16,
-                                         0, 0);
-    } else if (j == G::RU) {
-        __builtin_amdgcn_global_load_lds(ha + tile * G::VT + lane, (lds_void*)(st + G::OFF_HA), 4, 0, 0);
-    } else {
-        __builtin_amdgcn_global_load_lds(sc + tile * G::VT + lane, (lds_void*)(st + G::OFF_SC), 4, 0, 0);
+    if (j < G::NU) {
+        __builtin_amdgcn_global_load_lds(xqt + (tile * G::NU + j) * 64 + lane, (lds_void*)(st + j * 64), 16, 0, 0);
+        return;
     }
+    int k = j - G::NU;
+    const bool scale = k >= G::PP;
+    if (scale) k -= G::PP;
+    const void* src = scale ? static_cast<const void*>(sc + tile * G::VT) : static_cast<const void*>(ha + tile * G::VT);
+    uint4* dst = st + (scale ? G::OFF_SC : G::OFF_HA);
+    if (G::PB == 16)
+        __builtin_amdgcn_global_load_lds(static_cast<const uint4*>(src) + k * 64 + lane, (lds_void*)(dst + k * 64), 16,
+                                         0, 0);
+    else
+        __builtin_amdgcn_global_load_lds(static_cast<const float*>(src) + k * 64 + lane, (lds_void*)(dst + k * 16), 4,
+                                         0, 0);
 }
 
 // Every wave issues exactly L copy instructions per stage (some repeat a
@@ -197,7 +214,7 @@ __device__ __forceinline__ void lp_tile_pipe(int64_t t, int64_t nt, int64_t t_be
 template <class G, int DT, int CB>
 __device__ __forceinline__ void load_candidates(const GainsArgs& ga, int64_t wbase, int col, int half,
                                                 uint4 (&a)[CB][G::HU], floatx16 (&cinit)[CB], int (&sa)[CB]) {
-    constexpr int HU = G::HU, RU = G::RU, VT = G::VT;
+    constexpr int HU = G::HU, RU = G::RU, HT = G::HT;
     const uint4* __restrict__ xqt = static_cast<const uint4*>(ga.xq);
     const int32_t* __restrict__ cand = ga.cand;
     const int64_t n_cand = ga.n_cand, n_pad = ga.n_pad;
@@ -212,9 +229,9 @@ __device__ __forceinline__ void load_candidates(const GainsArgs& ga, int64_t wba
         }
         if (crow >= 0 && cand && ga.inv) crow = ga.inv[crow];
         if (crow >= 0) {
-            const uint4* src = xqt + (crow / VT) * (RU * VT) + (crow % VT);
+            const uint4* src = xqt + (crow / HT) * (RU * HT) + (crow % HT);
 #pragma unroll
-            for (int u = 0; u < HU; ++u) a[cb][u] = src[(half * HU + u) * VT];
+            for (int u = 0; u < HU; ++u) a[cb][u] = src[(half * HU + u) * HT];
             sa[cb] = G::kFp8 ? ga.scale[crow] : 127;
         } else {
 #pragma unroll
@@ -573,10 +590,11 @@ __device__ __forceinline__ void gains_lp_pp_body(const GainsArgs& ga, int64_t bi
 // of each lane, one compare and a wave-wide ballot: all in one basic block,
 // so the scheduler can put the test between the MFMAs, where it runs while
 // they execute); the clamp-and-sum then runs only for a previous tile with a
-// value above its bound. Both column blocks' operands of a ground tile are
-// read from LDS right after the tile's barrier. The previous block's values
-// carry over tile boundaries, and the very first test sees -inf (no tile to
-// sum). Per-lane sums are added in column-block order with the same
+// value above its bound. A ring stage holds wide_stage(DT, KC) points (one
+// barrier per stage); both column blocks' operands of each 64-point tile of
+// the stage are read from LDS together. The previous block's values carry
+// over tile and stage boundaries, and the very first test sees -inf (no tile
+// to sum). Per-lane sums are added in column-block order with the same
 // arithmetic as clamp_sum16, so gains are bitwise those of the other
 // variants.
 // ---------------------------------------------------------------------------
@@ -641,7 +659,8 @@ __device__ __forceinline__ void sp_colb(const uint4 (&b)[G::HU], int sb, const u
     if (any) sp_sum<CB>(pacc, s, psh, hit, acc_sum);
 }
 
-// One ground tile (two column blocks) of the interleaved variant.
+// One ring stage (VT/64 sub-tiles of two column blocks each) of the
+// interleaved variant.
 template <class G, int DT, int KC, int CB>
 __device__ __forceinline__ void sp_tile(int64_t t, int64_t nt, int64_t t_begin, int wave, int lane, int col, int half,
                                         const uint4* __restrict__ xqt, const float* __restrict__ ha,
@@ -649,8 +668,7 @@ __device__ __forceinline__ void sp_tile(int64_t t, int64_t nt, int64_t t_begin, 
                                         uint4* next2, const uint4 (&a)[CB][G::HU], const floatx16 (&cinit)[CB],
                                         const int (&sa)[CB], float (&acc_sum)[CB][16], floatx16 (&accA)[CB],
                                         floatx16 (&accB)[CB], float& loB, float& shB, float s) {
-    constexpr int HU = G::HU, VT = G::VT;
-    static_assert(VT == 64, "two column blocks per ground tile");
+    constexpr int HU = G::HU, RU = G::RU;
     if (t + 1 < nt)
         wait_vmcnt<G::L>();
     else
@@ -659,30 +677,34 @@ __device__ __forceinline__ void sp_tile(int64_t t, int64_t nt, int64_t t_begin, 
     if (t + 2 < nt) copy_stage<G>(wave, lane, t_begin + t + 2, xqt, ha, sc, next2);
     const float* st_ha = reinterpret_cast<const float*>(st + G::OFF_HA);
     const int* st_sc = reinterpret_cast<const int*>(st + G::OFF_SC);
-    uint4 b0[HU], b1[HU];
 #pragma unroll
-    for (int u = 0; u < HU; ++u) b0[u] = st[(half * HU + u) * VT + col];
+    for (int p = 0; p < G::VT / 64; ++p) {
+        const uint4* sub = st + p * RU * 64;  // 64-row tile p of the stage
+        uint4 b0[HU], b1[HU];
 #pragma unroll
-    for (int u = 0; u < HU; ++u) b1[u] = st[(half * HU + u) * VT + 32 + col];
-    const float ha0 = st_ha[col], ha1 = st_ha[32 + col];
-    const int sb0 = G::kFp8 ? st_sc[col] : 127, sb1 = G::kFp8 ? st_sc[32 + col] : 127;
-    const float lo0 = -ha0, sh0 = ha0 * s;
-    // column block 0 (into accA) with the previous tile's block 1 (accB)
-    sp_colb<G, DT, KC, CB>(b0, sb0, a, cinit, sa, accA, accB, loB, shB, s, acc_sum);
-    // column block 1 (into accB) with block 0 (accA)
-    sp_colb<G, DT, KC, CB>(b1, sb1, a, cinit, sa, accB, accA, lo0, sh0, s, acc_sum);
-    loB = -ha1;
-    shB = ha1 * s;
+        for (int u = 0; u < HU; ++u) b0[u] = sub[(half * HU + u) * 64 + col];
+#pragma unroll
+        for (int u = 0; u < HU; ++u) b1[u] = sub[(half * HU + u) * 64 + 32 + col];
+        const float ha0 = st_ha[p * 64 + col], ha1 = st_ha[p * 64 + 32 + col];
+        const int sb0 = G::kFp8 ? st_sc[p * 64 + col] : 127, sb1 = G::kFp8 ? st_sc[p * 64 + 32 + col] : 127;
+        const float lo0 = -ha0, sh0 = ha0 * s;
+        // column block 0 (into accA) with the previous block (accB)
+        sp_colb<G, DT, KC, CB>(b0, sb0, a, cinit, sa, accA, accB, loB, shB, s, acc_sum);
+        // column block 1 (into accB) with block 0 (accA)
+        sp_colb<G, DT, KC, CB>(b1, sb1, a, cinit, sa, accB, accA, lo0, sh0, s, acc_sum);
+        loB = -ha1;
+        shB = ha1 * s;
+    }
 }
 
-template <int DT, int KC, int CB>
+template <int DT, int KC, int CB, int VTS>
 __device__ __forceinline__ void gains_lp_sp_body(const GainsArgs& ga, int64_t bid) {
     const uint4* __restrict__ xqt = static_cast<const uint4*>(ga.xq);
     const float* __restrict__ ha = ga.ha;
     const int* __restrict__ sc = ga.scale;
     const int ge = *ga.gexp;                // 2^ge >= m_v / 2 for every point
     const float s = ldexpf(1.0f, -ge);      // the epilogue's power-of-two scale
-    using G = LpGeom<DT, KC, CB>;
+    using G = LpGeom<DT, KC, CB, VTS>;
     using T = Lp<DT>;
     constexpr int HU = G::HU, VT = G::VT;
     static_assert(HU == KC * T::kU4, "lane half-row must hold KC chunks");
@@ -739,19 +761,31 @@ __device__ __forceinline__ void gains_lp_sp_body(const GainsArgs& ga, int64_t bi
     store_partials<CB>(ga, wbase, split, col, half, acc_sum, ge);
 }
 
-template <int DT, int KC, int CB>
+template <int DT, int KC, int CB, int VTS>
 __global__ void __launch_bounds__(256) k_gains_lp_sp(GainsArgs ga) {
-    gains_lp_sp_body<DT, KC, CB>(ga, blockIdx.x);
+    gains_lp_sp_body<DT, KC, CB, VTS>(ga, blockIdx.x);
 }
 
-template <int DT, int KC, int CB>
+template <int DT, int KC, int CB, int VTS>
 __global__ void __launch_bounds__(256)
 kb_gains_lp_sp(const InstDesc* __restrict__ descs, const int32_t* __restrict__ slot_inst,
                const int64_t* __restrict__ wg_pre, int32_t slots, int32_t t) {
     const int j = find_slot(wg_pre, slots, blockIdx.x);
     const InstDesc c = descs[slot_inst[j]];
     if (c.t0 + t >= c.k) return;
-    gains_lp_sp_body<DT, KC, CB>(gains_args(c, nullptr, c.n_pad), int64_t(blockIdx.x) - wg_pre[j]);
+    gains_lp_sp_body<DT, KC, CB, VTS>(gains_args(c, nullptr, c.n_pad), int64_t(blockIdx.x) - wg_pre[j]);
+}
+
+// Ring-stage width of the interleaved variant by row length (16-byte units
+// per row, measured): 256 points for BF16/FP16 rows of 4 units, 128 for FP8
+// rows of 4 units and for rows of 8 units, else 64. Wider stages mean fewer
+// barriers and copy waits per matrix instruction; rows of 2 units measured
+// slower with them, and longer rows have no LDS left for them at two
+// workgroups per CU.
+constexpr int wide_stage(int DT, int KC) {
+    return (DT == EBC_DT_FP8_E4M3 ? 4 * KC : 2 * KC) == 4   ? (DT == EBC_DT_FP8_E4M3 ? 128 : 256)
+           : (DT == EBC_DT_FP8_E4M3 ? 4 * KC : 2 * KC) == 8 ? 128
+                                                            : 64;
 }
 
 template <int DT, int KC, int CB>
@@ -796,13 +830,13 @@ static void launch_lp_v(const ebc_dataset* ds, const int32_t* cand, int64_t n_ca
                        gains_args(c, cand, n_cand));
 }
 
-template <int DT, int KC, int CB>
+template <int DT, int KC, int CB, int VTS>
 static void launch_lp_sp(const ebc_dataset* ds, const int32_t* cand, int64_t n_cand, hipStream_t s) {
-    using G = LpGeom<DT, KC, CB>;
+    using G = LpGeom<DT, KC, CB, VTS>;
     const int64_t tiles = (n_cand + G::CAND_TILE - 1) / G::CAND_TILE;
     InstDesc c;
     fill_desc(ds, 0, nullptr, nullptr, nullptr, &c);
-    hipLaunchKernelGGL((k_gains_lp_sp<DT, KC, CB>), dim3(unsigned(tiles * ds->v_splits)), dim3(256), 0, s,
+    hipLaunchKernelGGL((k_gains_lp_sp<DT, KC, CB, VTS>), dim3(unsigned(tiles * ds->v_splits)), dim3(256), 0, s,
                        gains_args(c, cand, n_cand));
 }
 
@@ -818,14 +852,15 @@ static void launch_lp_pp(const ebc_dataset* ds, const int32_t* cand, int64_t n_c
 
 // Variants: 4 waves with (32-row candidate blocks per wave, software-pipelined
 // epilogue) 0 = (2, no), 1 = (4, no), 2 = (2, yes); 3 = ping-pong, 8 waves
-// with pp_blocks(DT, KC) blocks each; 4 = interleaved test, 4 waves x 2 blocks.
+// with pp_blocks(DT, KC) blocks each; 4 = interleaved test, 4 waves x 2 blocks,
+// ring stages of wide_stage(DT, KC) points.
 template <int DT, int KC>
 static void launch_lp(const ebc_dataset* ds, const int32_t* cand, int64_t n_cand, hipStream_t s) {
     switch (ds->variant) {
         case 1: launch_lp_v<DT, KC, 4, false>(ds, cand, n_cand, s); break;
         case 2: launch_lp_v<DT, KC, 2, true>(ds, cand, n_cand, s); break;
         case 3: launch_lp_pp<DT, KC, pp_blocks(DT, KC)>(ds, cand, n_cand, s); break;
-        case 4: launch_lp_sp<DT, KC, 2>(ds, cand, n_cand, s); break;
+        case 4: launch_lp_sp<DT, KC, 2, wide_stage(DT, KC)>(ds, cand, n_cand, s); break;
         default: launch_lp_v<DT, KC, 2, false>(ds, cand, n_cand, s); break;
     }
 }
@@ -882,7 +917,10 @@ static void launch_lp_b(int32_t variant, const InstDesc* descs, const int32_t* s
             hipLaunchKernelGGL((kb_gains_lp_pp<DT, KC, pp_blocks(DT, KC)>), g, dim3(512), 0, s, descs, slot_inst, wg_pre,
                                slots, t);
             break;
-        case 4: hipLaunchKernelGGL((kb_gains_lp_sp<DT, KC, 2>), g, b, 0, s, descs, slot_inst, wg_pre, slots, t); break;
+        case 4:
+            hipLaunchKernelGGL((kb_gains_lp_sp<DT, KC, 2, wide_stage(DT, KC)>), g, b, 0, s, descs, slot_inst, wg_pre,
+                               slots, t);
+            break;
         default: hipLaunchKernelGGL((kb_gains_lp<DT, KC, 2, false>), g, b, 0, s, descs, slot_inst, wg_pre, slots, t); break;
     }
 }
