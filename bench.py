@@ -675,7 +675,8 @@ def timed_greedy(ebc, torch, x, n, d, k, dtype, variant, steps, warmup, stream):
     if d > 128:
         kname = "k_gains_wide"
     else:
-        kname = "k_gains_f32" if dtype == "f32" else ("k_gains_lp_pp" if variant_used == 3 else "k_gains_lp")
+        kname = "k_gains_f32" if dtype == "f32" else \
+            {3: "k_gains_lp_pp", 4: "k_gains_lp_sp"}.get(variant_used, "k_gains_lp")
     roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak,
                 "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
                 "kernel": kname, "avg_launch_ms": round(gains_avg_ms, 4),
