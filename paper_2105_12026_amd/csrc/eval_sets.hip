@@ -769,8 +769,12 @@ k_es_regs(const uint4* __restrict__ xq, const float* __restrict__ hn, const int*
             }
         }
         float acc_u[kRegUnits];
+        float rs[kRegUnits];  // -inf at a set's first unit (the unit after a last one), else 0
 #pragma unroll
-        for (int u = 0; u < kRegUnits; ++u) acc_u[u] = 0.0f;
+        for (int u = 0; u < kRegUnits; ++u) {
+            acc_u[u] = 0.0f;
+            rs[u] = (u > 0 && ((m_last >> (u - 1)) & 1u)) ? -INFINITY : 0.0f;
+        }
 
         // ground tiles of this split
         const int64_t v_begin = int64_t(split) * vchunk;
@@ -792,9 +796,11 @@ k_es_regs(const uint4* __restrict__ xq, const float* __restrict__ hn, const int*
             else
                 wait_vmcnt<0>();
             ring_barrier();
-            if (t + 2 < nt) copy_stage(t_begin + t + 2, next2);
+            // the next tile's shift loads before this stage's copies: the wait
+            // above then leaves exactly the newest stage's copies in flight
             const float wsh = wsh_next;
             wsh_next = shift_of(t + 1);
+            if (t + 2 < nt) copy_stage(t_begin + t + 2, next2);
             const int* st_sc = reinterpret_cast<const int*>(st + OFF_SC);
             // both member blocks against each column block: the column block's
             // operand is read from LDS once
@@ -828,19 +834,23 @@ k_es_regs(const uint4* __restrict__ xq, const float* __restrict__ hn, const int*
                     um[mb * kBlockUnits + 2 * gq] = __uint_as_float(r[0]);
                     um[mb * kBlockUnits + 2 * gq + 1] = __uint_as_float(r[1]);
                 }
-            // sets are consecutive runs of units: the running maximum restarts after
-            // each set's last unit (units past the window's last set are padding
-            // rows at -inf, so they never reach a last unit)
+            // sets are consecutive runs of units: the running maximum restarts at
+            // each set's first unit (rs[u] = -inf there, else 0; units past the
+            // window's last set are padding rows at -inf, so they never reach a
+            // last unit)
             float cur = -INFINITY;
+            // the set ends as an opaque scalar per tile: the compiler tests its
+            // bits with scalar instructions instead of keeping per-unit lane masks
+            uint32_t ml = m_last;
+            asm volatile("" : "+s"(ml));
 #pragma unroll
             for (int u = 0; u < kRegUnits; ++u) {
-                cur = fmaxf(cur, um[u]);
-                if ((m_last >> u) & 1u) {
+                cur = fmaxf(cur + rs[u], um[u]);
+                if ((ml >> u) & 1u) {
                     // a scalar branch, not selects over every unit (the empty
                     // volatile statement keeps the compiler from speculating it)
                     asm volatile("");
                     acc_u[u] += fmaxf(cur + wsh, 0.0f);
-                    cur = -INFINITY;
                 }
             }
         };
