@@ -790,47 +790,53 @@ k_es_regs(const uint4* __restrict__ xq, const float* __restrict__ hn, const int*
         float wsh_next = shift_of(0);
         if (nt > 0) copy_stage(t_begin, ring0);
         if (nt > 1) copy_stage(t_begin + 1, ring1);
-        auto tile = [&](int64_t t, const uint4* st, uint4* next2) {
-            if (t + 1 < nt)
-                wait_vmcnt<L>();
-            else
-                wait_vmcnt<0>();
-            ring_barrier();
-            // the next tile's shift loads before this stage's copies: the wait
-            // above then leaves exactly the newest stage's copies in flight
-            const float wsh = wsh_next;
-            wsh_next = shift_of(t + 1);
-            if (t + 2 < nt) copy_stage(t_begin + t + 2, next2);
-            const int* st_sc = reinterpret_cast<const int*>(st + OFF_SC);
-            // both member blocks against each column block: the column block's
-            // operand is read from LDS once
-            floatx16 acc[2][2];  // [member block][column block]
+        // Software-pipelined over column blocks: while the MFMAs of column
+        // block 0 of tile t run, the lane takes the unit maxima of column
+        // block 1 of tile t-1, pairs them with those of its block 0 (taken
+        // while block 1's MFMAs ran) and closes tile t-1's sets; while the
+        // MFMAs of block 1 of tile t run, it takes the maxima of block 0 of
+        // tile t. Tile -1 is all -inf, so closing it adds +0 to every sum.
+        floatx16 acc[2][2];  // [member block][column block]
 #pragma unroll
-            for (int cb = 0; cb < 2; ++cb) {
-                const int vrow = cb * 32 + col;
-                uint4 b[HU];
+        for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
-                for (int u = 0; u < HU; ++u) b[u] = st[(half * HU + u) * VT + vrow];
-                const int sb = kFp8 ? st_sc[vrow] : 127;
-                acc[0][cb] = cinit[0];
-                acc[1][cb] = cinit[1];
+            for (int r = 0; r < 16; ++r) acc[mb][1][r] = -INFINITY;
+        float x0[8];  // unit maxima of column block 0 of the previous tile
 #pragma unroll
-                for (int q = 0; q < KC; ++q)
+        for (int i = 0; i < 8; ++i) x0[i] = -INFINITY;
+        float wsh_prev = 0.0f;
+        // maxima over each unit's four rows held by this lane, one column block
+        auto unit_max = [&](int cb, float (&x)[8]) {
 #pragma unroll
-                    for (int mb = 0; mb < 2; ++mb)
-                        acc[mb][cb] = mfma_main<DT>(&a[mb][q * T::kU4], &b[q * T::kU4], acc[mb][cb], sa[mb], sb);
-            }
+            for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+                for (int gq = 0; gq < kBlockUnits / 2; ++gq) {
+                    const floatx16& p = acc[mb][cb];
+                    x[mb * 4 + gq] = fmaxf(fmaxf(p[4 * gq], p[4 * gq + 1]), fmaxf(p[4 * gq + 2], p[4 * gq + 3]));
+                }
+        };
+        // the MFMAs of one column block (both member blocks) from operand b
+        auto mfma_block = [&](int cb, const uint4 (&b)[HU], int sb) {
+            acc[0][cb] = cinit[0];
+            acc[1][cb] = cinit[1];
+#pragma unroll
+            for (int q = 0; q < KC; ++q)
+#pragma unroll
+                for (int mb = 0; mb < 2; ++mb)
+                    acc[mb][cb] = mfma_main<DT>(&a[mb][q * T::kU4], &b[q * T::kU4], acc[mb][cb], sa[mb], sb);
+        };
+        constexpr int NMF = 2 * KC;  // matrix instructions per column block
+        // close the previous tile: pair its two column blocks' maxima (upper
+        // half of x0 <-> lower half of x1: this lane's point, units 2gq and
+        // 2gq+1), then the running maximum over units under the set-end mask
+        auto close_tile = [&](const float (&x1)[8], float wsh) {
             float um[kRegUnits];
 #pragma unroll
             for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
                 for (int gq = 0; gq < kBlockUnits / 2; ++gq) {
-                    const floatx16& p0 = acc[mb][0];
-                    const floatx16& p1 = acc[mb][1];
-                    const float x0 = fmaxf(fmaxf(p0[4 * gq], p0[4 * gq + 1]), fmaxf(p0[4 * gq + 2], p0[4 * gq + 3]));
-                    const float x1 = fmaxf(fmaxf(p1[4 * gq], p1[4 * gq + 1]), fmaxf(p1[4 * gq + 2], p1[4 * gq + 3]));
-                    // upper half of x0 <-> lower half of x1: this lane's point, units 2gq and 2gq+1
-                    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x0), __float_as_uint(x1), false, false);
+                    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x0[mb * 4 + gq]),
+                                                                    __float_as_uint(x1[mb * 4 + gq]), false, false);
                     um[mb * kBlockUnits + 2 * gq] = __uint_as_float(r[0]);
                     um[mb * kBlockUnits + 2 * gq + 1] = __uint_as_float(r[1]);
                 }
@@ -854,11 +860,54 @@ k_es_regs(const uint4* __restrict__ xq, const float* __restrict__ hn, const int*
                 }
             }
         };
+        auto tile = [&](int64_t t, const uint4* st, uint4* next2) {
+            if (t + 1 < nt)
+                wait_vmcnt<L>();
+            else
+                wait_vmcnt<0>();
+            ring_barrier();
+            // the next tile's shift loads before this stage's copies: the wait
+            // above then leaves exactly the newest stage's copies in flight
+            const float wsh = wsh_next;
+            wsh_next = shift_of(t + 1);
+            if (t + 2 < nt) copy_stage(t_begin + t + 2, next2);
+            const int* st_sc = reinterpret_cast<const int*>(st + OFF_SC);
+            uint4 b[HU];
+            // column block 0 of tile t, with the maxima of block 1 of tile t-1
+#pragma unroll
+            for (int u = 0; u < HU; ++u) b[u] = st[(half * HU + u) * VT + col];
+            float x1[8];
+            unit_max(1, x1);
+            mfma_block(0, b, kFp8 ? st_sc[col] : 127);
+#pragma unroll
+            for (int i = 0; i < NMF; ++i) {
+                __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // one MFMA
+                __builtin_amdgcn_sched_group_barrier(0x002, 2, 0);  // then part of the maxima
+            }
+            close_tile(x1, wsh_prev);
+            // column block 1 of tile t, with the maxima of block 0 of tile t
+#pragma unroll
+            for (int u = 0; u < HU; ++u) b[u] = st[(half * HU + u) * VT + 32 + col];
+            unit_max(0, x0);
+            mfma_block(1, b, kFp8 ? st_sc[32 + col] : 127);
+#pragma unroll
+            for (int i = 0; i < NMF; ++i) {
+                __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+                __builtin_amdgcn_sched_group_barrier(0x002, 2, 0);
+            }
+            wsh_prev = wsh;
+        };
         // stage of tile t: t % 3 (distinct LDS objects, so a copy in flight never targets the stage read)
         for (int64_t t = 0; t < nt; t += 3) {
             tile(t, ring0, ring2);
             if (t + 1 < nt) tile(t + 1, ring1, ring0);
             if (t + 2 < nt) tile(t + 2, ring2, ring1);
+        }
+        // the last tile
+        {
+            float x1[8];
+            unit_max(1, x1);
+            close_tile(x1, wsh_prev);
         }
         // each set's sum over the 64 lanes, fixed order, float64; one write per set and split
 #pragma unroll
