@@ -148,11 +148,12 @@ def bench_batched(args):
     for _ in range(args.warmup):
         outs = batch.greedy(ks)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        outs = batch.greedy(ks, outs=[(o[0], o[1], o[2]) for o in outs] if outs else None)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
+    with ClockSampler() as clk:
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            outs = batch.greedy(ks, outs=[(o[0], o[1], o[2]) for o in outs] if outs else None)
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
     for ds in dss:
         ds.sync()
     pairs = sum(pairs_per_greedy(p.n, p.k) for p in insts)
@@ -175,6 +176,10 @@ def bench_batched(args):
                      "frac": round(achieved / PEAK_TFLOPS[dt], 4), "traffic": None,
                      "kernel": "whole batched step (all kernels), algorithmic 2*d flops per pair"},
     }
+    ghz = clk.mean()
+    if ghz:
+        out["roofline"]["clock_ghz_sampled"] = round(ghz, 3)
+        out["roofline"]["frac_at_sampled_clock"] = round(achieved / (PEAK_TFLOPS[dt] * ghz / 2.4), 4)
     print(json.dumps(out), flush=True)
 
 
@@ -615,6 +620,64 @@ def parity_vs_golden(np, run, golden, dt):
             "reference": "tests/golden (float64 oracle run)"}
 
 
+class ClockSampler:
+    """Samples the GPU's graphics clock (amdsmi, mean over the XCDs) every
+    `period` seconds from a side thread while the timed region runs; mean()
+    is the average in GHz, or None when no sample could be read. Used to
+    state each roofline fraction also against the peak at the measured clock
+    (the published peaks assume 2.4 GHz)."""
+
+    def __init__(self, period: float = 0.01):
+        import threading
+        self.period, self.samples, self._stop = period, [], threading.Event()
+        self._thread = None
+        try:
+            import amdsmi
+            amdsmi.amdsmi_init()
+            self._smi = amdsmi
+            self._h = amdsmi.amdsmi_get_processor_handles()[0]
+        except Exception:
+            self._smi = None
+
+    def _read(self):
+        m = self._smi.amdsmi_get_gpu_metrics_info(self._h)
+        vals = m.get("current_gfxclks")
+        if not isinstance(vals, (list, tuple)):
+            vals = [m.get("current_gfxclk")]
+        vals = [float(v) for v in vals if isinstance(v, (int, float)) and 0 < v < 10000]
+        return sum(vals) / len(vals) / 1e3 if vals else None
+
+    def _run(self):
+        while not self._stop.is_set():
+            try:
+                v = self._read()
+                if v:
+                    self.samples.append(v)
+            except Exception:
+                return
+            self._stop.wait(self.period)
+
+    def __enter__(self):
+        import threading
+        if self._smi is not None:
+            self._thread = threading.Thread(target=self._run, daemon=True)
+            self._thread.start()
+        return self
+
+    def __exit__(self, *exc):
+        self._stop.set()
+        if self._thread is not None:
+            self._thread.join(timeout=2.0)
+        if self._smi is not None:
+            try:
+                self._smi.amdsmi_shut_down()
+            except Exception:
+                pass
+
+    def mean(self):
+        return sum(self.samples) / len(self.samples) if self.samples else None
+
+
 def timed_greedy(ebc, torch, x, n, d, k, dtype, variant, steps, warmup, stream):
     """`warmup` untimed then `steps` timed runs of one step (dataset residency
     + greedy k) in `dtype`, with the per-launch gains-kernel time from the
@@ -651,11 +714,12 @@ def timed_greedy(ebc, torch, x, n, d, k, dtype, variant, steps, warmup, stream):
         ds.sync()
     keep.clear()
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        keep.append(one_step(True))
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
+    with ClockSampler() as clk:
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            keep.append(one_step(True))
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
     prof = {"gains_ms": 0.0, "select_ms": 0.0, "gains_launches": 0, "steps": 0}
     window_max = 0
     for ds in keep:
@@ -681,6 +745,11 @@ def timed_greedy(ebc, torch, x, n, d, k, dtype, variant, steps, warmup, stream):
                 "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
                 "kernel": kname, "avg_launch_ms": round(gains_avg_ms, 4),
                 "flops_per_launch": flops_per_launch}
+    ghz = clk.mean()
+    if ghz:
+        # the same fraction against the peak scaled to the clock sampled during the timed runs
+        roofline["clock_ghz_sampled"] = round(ghz, 3)
+        roofline["frac_at_sampled_clock"] = round(achieved / (peak * ghz / 2.4), 4)
     return {"ms": elapsed * 1e3 / steps, "variant": variant_used, "window_max": window_max,
             "gains_ms_per_run": prof["gains_ms"] / steps, "select_ms_per_run": prof["select_ms"] / steps,
             "sel": sel.cpu().numpy().tolist(), "f": f.cpu().numpy().tolist(), "roofline": roofline}
