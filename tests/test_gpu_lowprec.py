@@ -184,11 +184,14 @@ def test_full_size_greedy_against_oracle_run(env, ref, sweep200k, dt):
 
 @pytest.mark.parametrize("dt", ["bf16", "f16", "fp8"])
 @pytest.mark.parametrize("n,d,seed", [(5, 3, 21), (700, 33, 22), (2049, 64, 23), (5000, 64, 24), (1300, 100, 25),
-                                      (900, 128, 26)])
+                                      (900, 128, 26), (1500, 32, 27), (9000, 24, 28)])
 def test_every_variant_matches_oracle_and_variant0(env, ref, dt, n, d, seed):
     """All tile variants (including the 8-wave ping-pong one, with one or two
-    candidate blocks per wave) give bitwise-equal gains, for all candidates
-    and for an unordered candidate list with repeats, within the oracle bar."""
+    candidate blocks per wave, and the interleaved one with its 64-, 128- and
+    256-point ring stages: d = 32 and 24 take 256 in BF16/FP16, with 1 and 8
+    ground-set chunks, the last one ragged) give bitwise-equal gains, for all
+    candidates and for an unordered candidate list with repeats, within the
+    oracle bar."""
     torch, ebc = env
     rng = np.random.default_rng(seed)
     x = W.gaussian_mixture(rng, n, d, 6).astype(np.float32)
