@@ -573,7 +573,9 @@ def main():
                    "speedup_vs_f32": round(ms_per_step / r["ms"], 3), "variant": r["variant"],
                    "window_max": r["window_max"],
                    "roofline": {k2: r["roofline"][k2] for k2 in ("kernel", "achieved", "peak", "frac",
-                                                                   "avg_launch_ms")}}
+                                                                   "avg_launch_ms", "clock_ghz_sampled",
+                                                                   "frac_at_sampled_clock")
+                                if k2 in r["roofline"]}}
             if golden is not None:
                 leg["parity"] = parity_vs_golden(np, r, golden, dt)
             legs[dt] = leg
