@@ -300,7 +300,9 @@ template <int KP>
 __global__ void __launch_bounds__(256)
 k_es_main(const float* __restrict__ x, int64_t n, int32_t d, const double* __restrict__ n64,
           const double* __restrict__ m0, const int64_t* __restrict__ off, const int32_t* __restrict__ idx, int64_t l, int32_t splits,
-          EsScratch sc) {
+          EsScratch sc, int32_t after_regs) {
+    // after k_es_regs32: that kernel took the call if every set fits its windows
+    if (after_regs && sc.n_groups[2] > 0) return;
     constexpr int KH = KP / 2;  // K values per lane half
     constexpr int S = KP + 4;   // LDS row stride (S/4 odd: conflict-free 16-byte reads)
     constexpr int PF = KP / 8;  // member-row values each thread gathers per block
@@ -924,6 +926,198 @@ k_es_regs(const uint4* __restrict__ xq, const float* __restrict__ hn, const int*
     }
 }
 
+// The float32 evaluation of an FP32 dataset with the member rows in
+// registers: the register kernel above with v_mfma_f32_32x32x2_f32 (64
+// cycles each, K = 2), taking the same calls (every set at most kRegMaxSet
+// units) and the same windows, work items, epilogue and per-set sums. The
+// dataset's float32 copy is row-major [n_pad, KP]; each lane copies its own
+// row's 16-byte units of a 64-point tile into the LDS stage (unit-major, so
+// the operand reads of a half-wave are 32 consecutive units), two stages of
+// KP/4 KB each. Lane half h takes K values h KP/2 .. (h+1) KP/2 - 1 of both
+// operands (one 16-byte unit feeds 4 MFMAs). A tile's epilogue costs about as
+// much as 3 of its 4 KP MFMAs, so it is not overlapped with them.
+template <int KP>
+__global__ void __launch_bounds__(256)
+k_es_regs32(const uint4* __restrict__ xq, const float* __restrict__ hn, int64_t n, const double* __restrict__ m0,
+            const int64_t* __restrict__ off, const int32_t* __restrict__ idx, int64_t l, int32_t splits,
+            EsScratch sc) {
+    // two stages of KP/4 KB within the 64 KB of LDS a workgroup can hold
+    static_assert(KP % 8 == 0 && KP <= 120, "rows of 8 .. 120 floats, a multiple of 8");
+    constexpr int RU = KP / 4;  // 16-byte units per row
+    constexpr int HU = RU / 2;  // units per lane half
+    constexpr int VT = 64;      // ground points per tile
+    constexpr int STAGE = RU * VT;
+    constexpr int L = (RU + 3) / 4;  // copy instructions per wave per stage
+    __shared__ uint4 ring0[STAGE];
+    __shared__ uint4 ring1[STAGE];
+    __shared__ int32_t rmem[4][64];
+
+    const int64_t G = sc.n_groups[1];
+    const int64_t n_win = sc.n_groups[2];
+    if (n_win == 0) return;  // some set is longer than kRegMaxSet units (k_es_main runs), or none has units
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int col = lane & 31;
+    const int half = lane >> 5;
+    const int64_t n_items = (n_win + 3) / 4 * splits;
+    const int64_t vchunk = ((n + splits - 1) / splits + kVSub - 1) / kVSub * kVSub;
+
+    // lane i copies unit j of row tile*64 + i (the rows are row-major); every
+    // wave issues exactly L copy instructions per stage (pieces beyond RU
+    // repeat one another wave also copies: same bytes to the same place)
+    auto copy_stage = [&](int64_t tile, uint4* st) {
+#pragma unroll
+        for (int q = 0; q < L; ++q) {
+            const int j = (wave + 4 * q) % RU;
+            __builtin_amdgcn_global_load_lds(xq + (tile * VT + lane) * RU + j, (lds_void*)(st + j * VT), 16, 0, 0);
+        }
+    };
+
+    for (int64_t item = blockIdx.x; item < n_items; item += gridDim.x) {
+        const int64_t g = item / splits;
+        const int split = int(item % splits);
+        const int64_t w = g * 4 + wave;
+        int64_t j0 = 0, j1 = 0;
+        if (w < n_win) {
+            j0 = sc.win_j0[w];
+            j1 = sc.win_j0[w + 1];
+        }
+        const int64_t ua = sc.U[j0], ub = sc.U[j1];
+        {
+            const int64_t u = ua + lane / kUnitRows;
+            int32_t mem = -1;
+            if (u < ub) {
+                const int64_t j = owner_of(sc.U, j0, j1, u);
+                const int64_t q = (u - sc.U[j]) * kUnitRows + lane % kUnitRows;
+                if (off[j] + q < off[j + 1]) mem = idx[off[j] + q];
+            }
+            rmem[wave][lane] = mem;
+        }
+        uint32_t m_last;
+        {
+            const int64_t u = ua + lane;
+            bool last = false;
+            if (lane < kRegUnits && u < ub) {
+                const int64_t j = owner_of(sc.U, j0, j1, u);
+                last = u == sc.U[j + 1] - 1;
+            }
+            m_last = __builtin_amdgcn_readfirstlane(uint32_t(__builtin_amdgcn_ballot_w64(last)));
+        }
+        __syncthreads();  // rmem of every wave written (and the ring of the previous item drained)
+        uint4 a[2][HU];
+        floatx16 cinit[2];
+#pragma unroll
+        for (int mb = 0; mb < 2; ++mb) {
+            const int32_t mem = rmem[wave][mb * 32 + col];
+            const uint4* src = xq + int64_t(mem < 0 ? 0 : mem) * RU + half * HU;
+#pragma unroll
+            for (int u = 0; u < HU; ++u) a[mb][u] = mem >= 0 ? src[u] : make_uint4(0, 0, 0, 0);
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int32_t mr = rmem[wave][mb * 32 + 8 * (r / 4) + 4 * half + (r % 4)];
+                cinit[mb][r] = mr >= 0 ? -hn[mr] : -INFINITY;
+            }
+        }
+        float acc_u[kRegUnits];
+        float rs[kRegUnits];  // -inf at a set's first unit (the unit after a last one), else 0
+#pragma unroll
+        for (int u = 0; u < kRegUnits; ++u) {
+            acc_u[u] = 0.0f;
+            rs[u] = (u > 0 && ((m_last >> (u - 1)) & 1u)) ? -INFINITY : 0.0f;
+        }
+
+        const int64_t v_begin = int64_t(split) * vchunk;
+        int64_t v_end = v_begin + vchunk;
+        if (v_end > n) v_end = n;
+        const int64_t t_begin = v_begin / VT;
+        const int64_t nt = v_end > v_begin ? (v_end - v_begin + VT - 1) / VT : 0;
+        auto shift_of = [&](int64_t t) -> float {
+            const int64_t v = (t_begin + t) * VT + lane;
+            return (t < nt && v >= v_begin && v < v_end) ? float(0.5 * m0[v] - double(hn[v])) : -INFINITY;
+        };
+        float wsh_next = shift_of(0);
+        if (nt > 0) copy_stage(t_begin, ring0);
+        auto tile = [&](int64_t t, const uint4* st, uint4* next) {
+            wait_vmcnt<0>();  // this tile's copies (issued one tile ago) and its shift loads
+            ring_barrier();   // ... of every wave; every wave is done reading the other stage
+            const float wsh = wsh_next;
+            wsh_next = shift_of(t + 1);
+            if (t + 1 < nt) copy_stage(t_begin + t + 1, next);
+            float xm[2][8];  // unit maxima per column block
+#pragma unroll
+            for (int cb = 0; cb < 2; ++cb) {
+                floatx16 acc[2] = {cinit[0], cinit[1]};
+#pragma unroll
+                for (int u = 0; u < HU; ++u) {
+                    const uint4 bq = st[(half * HU + u) * VT + cb * 32 + col];
+                    const float bv[4] = {__uint_as_float(bq.x), __uint_as_float(bq.y), __uint_as_float(bq.z),
+                                         __uint_as_float(bq.w)};
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+#pragma unroll
+                        for (int mb = 0; mb < 2; ++mb) {
+                            const uint4& aq = a[mb][u];
+                            const float av = e == 0 ? __uint_as_float(aq.x)
+                                             : e == 1 ? __uint_as_float(aq.y)
+                                             : e == 2 ? __uint_as_float(aq.z)
+                                                      : __uint_as_float(aq.w);
+                            acc[mb] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv[e], acc[mb], 0, 0, 0);
+                        }
+                }
+#pragma unroll
+                for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+                    for (int gq = 0; gq < kBlockUnits / 2; ++gq) {
+                        const floatx16& pq = acc[mb];
+                        xm[cb][mb * 4 + gq] =
+                            fmaxf(fmaxf(pq[4 * gq], pq[4 * gq + 1]), fmaxf(pq[4 * gq + 2], pq[4 * gq + 3]));
+                    }
+            }
+            // pair the column blocks (upper half of block 0 <-> lower half of
+            // block 1: this lane's point, units 2gq and 2gq+1), then the running
+            // maximum over units under the set-end mask (as in k_es_regs)
+            float um[kRegUnits];
+#pragma unroll
+            for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+                for (int gq = 0; gq < kBlockUnits / 2; ++gq) {
+                    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(xm[0][mb * 4 + gq]),
+                                                                    __float_as_uint(xm[1][mb * 4 + gq]), false, false);
+                    um[mb * kBlockUnits + 2 * gq] = __uint_as_float(r[0]);
+                    um[mb * kBlockUnits + 2 * gq + 1] = __uint_as_float(r[1]);
+                }
+            float cur = -INFINITY;
+            uint32_t ml = m_last;
+            asm volatile("" : "+s"(ml));
+#pragma unroll
+            for (int u = 0; u < kRegUnits; ++u) {
+                cur = fmaxf(cur + rs[u], um[u]);
+                if ((ml >> u) & 1u) {
+                    asm volatile("");
+                    acc_u[u] += fmaxf(cur + wsh, 0.0f);
+                }
+            }
+        };
+        // stage of tile t: t % 2 (distinct LDS objects)
+        for (int64_t t = 0; t < nt; t += 2) {
+            tile(t, ring0, ring1);
+            if (t + 1 < nt) tile(t + 1, ring1, ring0);
+        }
+#pragma unroll
+        for (int u = 0; u < kRegUnits; ++u) {
+            if (!((m_last >> u) & 1u)) continue;
+            double v = double(acc_u[u]);
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+            if (lane == 0) {
+                const int64_t j = owner_of(sc.U, j0, j1, ua + u);
+                sc.part[int64_t(split) * l + j] = v;
+            }
+        }
+    }
+}
+
 // Long rows (padded length above 128): the same work items, windows and
 // per-set sums as above, but no row is held whole. For every member block
 // each wave walks the dimension (row pieces straight from global memory,
@@ -1208,8 +1402,20 @@ __global__ void __launch_bounds__(256) k_es_final(int64_t l, int64_t n, int32_t 
 template <int KP>
 void launch_es_main(dim3 g, hipStream_t s, const ebc_dataset* ds, const int64_t* off, const int32_t* idx, int64_t l,
                     int32_t splits, const EsScratch& sc) {
+    // an FP32 dataset's own padded rows (up to 120 values): the register
+    // kernel first (it takes calls whose sets all have at most kRegMaxSet
+    // units), then k_es_main for the others; a reduced-precision dataset
+    // evaluated in float32, and 128-value rows, use k_es_main alone
+    bool own = false;
+    if constexpr (KP <= 120) {
+        own = ds->dt == EBC_DT_F32 && ds->k_pad == KP;
+        if (own)
+            hipLaunchKernelGGL((k_es_regs32<KP>), g, dim3(256), 0, s,
+                               static_cast<const uint4*>(static_cast<const void*>(ds->b.xq)), ds->b.hn, ds->n,
+                               ds->b.m0, off, idx, l, splits, sc);
+    }
     hipLaunchKernelGGL((k_es_main<KP>), g, dim3(256), 0, s, ds->x, ds->n, ds->d, ds->b.n64, ds->b.m0, off, idx, l,
-                       splits, sc);
+                       splits, sc, int32_t(own));
 }
 
 }  // namespace
