@@ -653,6 +653,107 @@ k_es_lp(const uint4* __restrict__ xq, const float* __restrict__ hn, const int* _
     }
 }
 
+// ---- shared parts of the register kernels (k_es_regs, k_es_regs32) ----
+
+// One wave's window: its sets [j0, j1) and units [ua, ub), the member row of
+// each of its 64 rows in rmem_w (lane r: row r, unit ua + r/4; -1 padding)
+// and the wave-uniform mask of the units that end a set (bit u: unit ua + u).
+struct RegWindow {
+    int64_t j0, j1, ua, ub;
+    uint32_t m_last;
+};
+
+__device__ __forceinline__ RegWindow reg_window(const EsScratch& sc, int64_t w, int64_t n_win, int lane,
+                                                const int64_t* __restrict__ off, const int32_t* __restrict__ idx,
+                                                int32_t* rmem_w) {
+    RegWindow r{0, 0, 0, 0, 0u};
+    if (w < n_win) {
+        r.j0 = sc.win_j0[w];
+        r.j1 = sc.win_j0[w + 1];
+    }
+    r.ua = sc.U[r.j0];
+    r.ub = sc.U[r.j1];
+    {
+        const int64_t u = r.ua + lane / kUnitRows;
+        int32_t mem = -1;
+        if (u < r.ub) {
+            const int64_t j = owner_of(sc.U, r.j0, r.j1, u);
+            const int64_t q = (u - sc.U[j]) * kUnitRows + lane % kUnitRows;
+            if (off[j] + q < off[j + 1]) mem = idx[off[j] + q];
+        }
+        rmem_w[lane] = mem;
+    }
+    {
+        const int64_t u = r.ua + lane;
+        bool last = false;
+        if (lane < kRegUnits && u < r.ub) {
+            const int64_t j = owner_of(sc.U, r.j0, r.j1, u);
+            last = u == sc.U[j + 1] - 1;
+        }
+        r.m_last = __builtin_amdgcn_readfirstlane(uint32_t(__builtin_amdgcn_ballot_w64(last)));
+    }
+    return r;
+}
+
+// rs[u] = -inf at a set's first unit (the unit after a last one), else 0
+__device__ __forceinline__ void reg_restarts(uint32_t m_last, float (&rs)[kRegUnits]) {
+#pragma unroll
+    for (int u = 0; u < kRegUnits; ++u) rs[u] = (u > 0 && ((m_last >> (u - 1)) & 1u)) ? -INFINITY : 0.0f;
+}
+
+// Close one tile: pair the unit maxima of its two column blocks (x0: block
+// 0, x1: block 1; upper half of x0 <-> lower half of x1, so lane (col, h)
+// gets the 8 + 8 unit maxima of ground point 32h + col), then the running
+// maximum over the window's units, restarting at each set's first unit, and
+// at a set's last unit u the lane adds max(0, running max + wsh) to acc_u[u].
+// Units past the window's last set are padding rows at -inf, so they never
+// reach a last unit.
+__device__ __forceinline__ void reg_close(const float (&x0)[8], const float (&x1)[8], const float (&rs)[kRegUnits],
+                                          uint32_t m_last, float wsh, float (&acc_u)[kRegUnits]) {
+    float um[kRegUnits];
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+        for (int gq = 0; gq < kBlockUnits / 2; ++gq) {
+            const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x0[mb * 4 + gq]),
+                                                            __float_as_uint(x1[mb * 4 + gq]), false, false);
+            um[mb * kBlockUnits + 2 * gq] = __uint_as_float(r[0]);
+            um[mb * kBlockUnits + 2 * gq + 1] = __uint_as_float(r[1]);
+        }
+    float cur = -INFINITY;
+    // the set ends as an opaque scalar per tile: the compiler tests its bits
+    // with scalar instructions instead of keeping per-unit lane masks
+    uint32_t ml = m_last;
+    asm volatile("" : "+s"(ml));
+#pragma unroll
+    for (int u = 0; u < kRegUnits; ++u) {
+        cur = fmaxf(cur + rs[u], um[u]);
+        if ((ml >> u) & 1u) {
+            // a scalar branch, not selects over every unit (the empty volatile
+            // statement keeps the compiler from speculating it)
+            asm volatile("");
+            acc_u[u] += fmaxf(cur + wsh, 0.0f);
+        }
+    }
+}
+
+// Each set's accumulator summed over the 64 lanes in a fixed order in
+// float64, one write per set and ground-set split.
+__device__ __forceinline__ void reg_write(const EsScratch& sc, const RegWindow& wv, const float (&acc_u)[kRegUnits],
+                                          int lane, int split, int64_t l) {
+#pragma unroll
+    for (int u = 0; u < kRegUnits; ++u) {
+        if (!((wv.m_last >> u) & 1u)) continue;
+        double v = double(acc_u[u]);
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+        if (lane == 0) {
+            const int64_t j = owner_of(sc.U, wv.j0, wv.j1, wv.ua + u);
+            sc.part[int64_t(split) * l + j] = v;
+        }
+    }
+}
+
 // Reduced-precision multi-set evaluation with the member rows in registers
 // (calls whose sets all have at most kRegMaxSet units, i.e. 32 members;
 // others go to k_es_lp). The structure is that of the marginal-gains kernel: each wave
@@ -695,7 +796,6 @@ k_es_regs(const uint4* __restrict__ xq, const float* __restrict__ hn, const int*
     __shared__ uint4 ring2[STAGE];
     __shared__ int32_t rmem[4][64];  // per wave: member row of each of its 64 rows (-1: padding)
 
-    const int64_t G = sc.n_groups[1];
     const int64_t n_win = sc.n_groups[2];
     if (n_win == 0) return;  // some set is longer than kRegMaxSet units (k_es_lp runs), or none has units
     const int tid = threadIdx.x;
@@ -723,35 +823,8 @@ k_es_regs(const uint4* __restrict__ xq, const float* __restrict__ hn, const int*
         const int64_t g = item / splits;
         const int split = int(item % splits);
         const int64_t w = g * 4 + wave;
-        // this wave's sets and units
-        int64_t j0 = 0, j1 = 0;
-        if (w < n_win) {
-            j0 = sc.win_j0[w];
-            j1 = sc.win_j0[w + 1];
-        }
-        const int64_t ua = sc.U[j0], ub = sc.U[j1];
-        // row bookkeeping: lane r owns row r (unit ua + r/4)
-        {
-            const int64_t u = ua + lane / kUnitRows;
-            int32_t mem = -1;
-            if (u < ub) {
-                const int64_t j = owner_of(sc.U, j0, j1, u);
-                const int64_t q = (u - sc.U[j]) * kUnitRows + lane % kUnitRows;
-                if (off[j] + q < off[j + 1]) mem = idx[off[j] + q];
-            }
-            rmem[wave][lane] = mem;
-        }
-        // last unit of each set in the window (lanes 0..15: unit ua + lane), a wave-uniform mask
-        uint32_t m_last;
-        {
-            const int64_t u = ua + lane;
-            bool last = false;
-            if (lane < kRegUnits && u < ub) {
-                const int64_t j = owner_of(sc.U, j0, j1, u);
-                last = u == sc.U[j + 1] - 1;
-            }
-            m_last = __builtin_amdgcn_readfirstlane(uint32_t(__builtin_amdgcn_ballot_w64(last)));
-        }
+        const RegWindow wv = reg_window(sc, w, n_win, lane, off, idx, rmem[wave]);
+        const uint32_t m_last = wv.m_last;
         __syncthreads();  // rmem of every wave written (and the ring of the previous item drained)
         // member rows (A operand) and the C operand -||s^||^2/2 of the rows this lane holds
         uint4 a[2][HU];
@@ -771,12 +844,10 @@ k_es_regs(const uint4* __restrict__ xq, const float* __restrict__ hn, const int*
             }
         }
         float acc_u[kRegUnits];
-        float rs[kRegUnits];  // -inf at a set's first unit (the unit after a last one), else 0
 #pragma unroll
-        for (int u = 0; u < kRegUnits; ++u) {
-            acc_u[u] = 0.0f;
-            rs[u] = (u > 0 && ((m_last >> (u - 1)) & 1u)) ? -INFINITY : 0.0f;
-        }
+        for (int u = 0; u < kRegUnits; ++u) acc_u[u] = 0.0f;
+        float rs[kRegUnits];
+        reg_restarts(m_last, rs);
 
         // ground tiles of this split
         const int64_t v_begin = int64_t(split) * vchunk;
@@ -828,40 +899,6 @@ k_es_regs(const uint4* __restrict__ xq, const float* __restrict__ hn, const int*
                     acc[mb][cb] = mfma_main<DT>(&a[mb][q * T::kU4], &b[q * T::kU4], acc[mb][cb], sa[mb], sb);
         };
         constexpr int NMF = 2 * KC;  // matrix instructions per column block
-        // close the previous tile: pair its two column blocks' maxima (upper
-        // half of x0 <-> lower half of x1: this lane's point, units 2gq and
-        // 2gq+1), then the running maximum over units under the set-end mask
-        auto close_tile = [&](const float (&x1)[8], float wsh) {
-            float um[kRegUnits];
-#pragma unroll
-            for (int mb = 0; mb < 2; ++mb)
-#pragma unroll
-                for (int gq = 0; gq < kBlockUnits / 2; ++gq) {
-                    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x0[mb * 4 + gq]),
-                                                                    __float_as_uint(x1[mb * 4 + gq]), false, false);
-                    um[mb * kBlockUnits + 2 * gq] = __uint_as_float(r[0]);
-                    um[mb * kBlockUnits + 2 * gq + 1] = __uint_as_float(r[1]);
-                }
-            // sets are consecutive runs of units: the running maximum restarts at
-            // each set's first unit (rs[u] = -inf there, else 0; units past the
-            // window's last set are padding rows at -inf, so they never reach a
-            // last unit)
-            float cur = -INFINITY;
-            // the set ends as an opaque scalar per tile: the compiler tests its
-            // bits with scalar instructions instead of keeping per-unit lane masks
-            uint32_t ml = m_last;
-            asm volatile("" : "+s"(ml));
-#pragma unroll
-            for (int u = 0; u < kRegUnits; ++u) {
-                cur = fmaxf(cur + rs[u], um[u]);
-                if ((ml >> u) & 1u) {
-                    // a scalar branch, not selects over every unit (the empty
-                    // volatile statement keeps the compiler from speculating it)
-                    asm volatile("");
-                    acc_u[u] += fmaxf(cur + wsh, 0.0f);
-                }
-            }
-        };
         auto tile = [&](int64_t t, const uint4* st, uint4* next2) {
             if (t + 1 < nt)
                 wait_vmcnt<L>();
@@ -886,7 +923,7 @@ k_es_regs(const uint4* __restrict__ xq, const float* __restrict__ hn, const int*
                 __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // one MFMA
                 __builtin_amdgcn_sched_group_barrier(0x002, 2, 0);  // then part of the maxima
             }
-            close_tile(x1, wsh_prev);
+            reg_close(x0, x1, rs, m_last, wsh_prev, acc_u);
             // column block 1 of tile t, with the maxima of block 0 of tile t
 #pragma unroll
             for (int u = 0; u < HU; ++u) b[u] = st[(half * HU + u) * VT + 32 + col];
@@ -909,20 +946,9 @@ k_es_regs(const uint4* __restrict__ xq, const float* __restrict__ hn, const int*
         {
             float x1[8];
             unit_max(1, x1);
-            close_tile(x1, wsh_prev);
+            reg_close(x0, x1, rs, m_last, wsh_prev, acc_u);
         }
-        // each set's sum over the 64 lanes, fixed order, float64; one write per set and split
-#pragma unroll
-        for (int u = 0; u < kRegUnits; ++u) {
-            if (!((m_last >> u) & 1u)) continue;
-            double v = double(acc_u[u]);
-#pragma unroll
-            for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-            if (lane == 0) {
-                const int64_t j = owner_of(sc.U, j0, j1, ua + u);
-                sc.part[int64_t(split) * l + j] = v;
-            }
-        }
+        reg_write(sc, wv, acc_u, lane, split, l);
     }
 }
 
@@ -952,7 +978,6 @@ k_es_regs32(const uint4* __restrict__ xq, const float* __restrict__ hn, int64_t 
     __shared__ uint4 ring1[STAGE];
     __shared__ int32_t rmem[4][64];
 
-    const int64_t G = sc.n_groups[1];
     const int64_t n_win = sc.n_groups[2];
     if (n_win == 0) return;  // some set is longer than kRegMaxSet units (k_es_main runs), or none has units
     const int tid = threadIdx.x;
@@ -978,32 +1003,8 @@ k_es_regs32(const uint4* __restrict__ xq, const float* __restrict__ hn, int64_t 
         const int64_t g = item / splits;
         const int split = int(item % splits);
         const int64_t w = g * 4 + wave;
-        int64_t j0 = 0, j1 = 0;
-        if (w < n_win) {
-            j0 = sc.win_j0[w];
-            j1 = sc.win_j0[w + 1];
-        }
-        const int64_t ua = sc.U[j0], ub = sc.U[j1];
-        {
-            const int64_t u = ua + lane / kUnitRows;
-            int32_t mem = -1;
-            if (u < ub) {
-                const int64_t j = owner_of(sc.U, j0, j1, u);
-                const int64_t q = (u - sc.U[j]) * kUnitRows + lane % kUnitRows;
-                if (off[j] + q < off[j + 1]) mem = idx[off[j] + q];
-            }
-            rmem[wave][lane] = mem;
-        }
-        uint32_t m_last;
-        {
-            const int64_t u = ua + lane;
-            bool last = false;
-            if (lane < kRegUnits && u < ub) {
-                const int64_t j = owner_of(sc.U, j0, j1, u);
-                last = u == sc.U[j + 1] - 1;
-            }
-            m_last = __builtin_amdgcn_readfirstlane(uint32_t(__builtin_amdgcn_ballot_w64(last)));
-        }
+        const RegWindow wv = reg_window(sc, w, n_win, lane, off, idx, rmem[wave]);
+        const uint32_t m_last = wv.m_last;
         __syncthreads();  // rmem of every wave written (and the ring of the previous item drained)
         uint4 a[2][HU];
         floatx16 cinit[2];
@@ -1020,12 +1021,10 @@ k_es_regs32(const uint4* __restrict__ xq, const float* __restrict__ hn, int64_t 
             }
         }
         float acc_u[kRegUnits];
-        float rs[kRegUnits];  // -inf at a set's first unit (the unit after a last one), else 0
 #pragma unroll
-        for (int u = 0; u < kRegUnits; ++u) {
-            acc_u[u] = 0.0f;
-            rs[u] = (u > 0 && ((m_last >> (u - 1)) & 1u)) ? -INFINITY : 0.0f;
-        }
+        for (int u = 0; u < kRegUnits; ++u) acc_u[u] = 0.0f;
+        float rs[kRegUnits];
+        reg_restarts(m_last, rs);
 
         const int64_t v_begin = int64_t(split) * vchunk;
         int64_t v_end = v_begin + vchunk;
@@ -1074,47 +1073,14 @@ k_es_regs32(const uint4* __restrict__ xq, const float* __restrict__ hn, int64_t 
                             fmaxf(fmaxf(pq[4 * gq], pq[4 * gq + 1]), fmaxf(pq[4 * gq + 2], pq[4 * gq + 3]));
                     }
             }
-            // pair the column blocks (upper half of block 0 <-> lower half of
-            // block 1: this lane's point, units 2gq and 2gq+1), then the running
-            // maximum over units under the set-end mask (as in k_es_regs)
-            float um[kRegUnits];
-#pragma unroll
-            for (int mb = 0; mb < 2; ++mb)
-#pragma unroll
-                for (int gq = 0; gq < kBlockUnits / 2; ++gq) {
-                    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(xm[0][mb * 4 + gq]),
-                                                                    __float_as_uint(xm[1][mb * 4 + gq]), false, false);
-                    um[mb * kBlockUnits + 2 * gq] = __uint_as_float(r[0]);
-                    um[mb * kBlockUnits + 2 * gq + 1] = __uint_as_float(r[1]);
-                }
-            float cur = -INFINITY;
-            uint32_t ml = m_last;
-            asm volatile("" : "+s"(ml));
-#pragma unroll
-            for (int u = 0; u < kRegUnits; ++u) {
-                cur = fmaxf(cur + rs[u], um[u]);
-                if ((ml >> u) & 1u) {
-                    asm volatile("");
-                    acc_u[u] += fmaxf(cur + wsh, 0.0f);
-                }
-            }
+            reg_close(xm[0], xm[1], rs, m_last, wsh, acc_u);
         };
         // stage of tile t: t % 2 (distinct LDS objects)
         for (int64_t t = 0; t < nt; t += 2) {
             tile(t, ring0, ring1);
             if (t + 1 < nt) tile(t + 1, ring1, ring0);
         }
-#pragma unroll
-        for (int u = 0; u < kRegUnits; ++u) {
-            if (!((m_last >> u) & 1u)) continue;
-            double v = double(acc_u[u]);
-#pragma unroll
-            for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-            if (lane == 0) {
-                const int64_t j = owner_of(sc.U, j0, j1, ua + u);
-                sc.part[int64_t(split) * l + j] = v;
-            }
-        }
+        reg_write(sc, wv, acc_u, lane, split, l);
     }
 }
 
