@@ -758,9 +758,9 @@ __device__ __forceinline__ void reg_write(const EsScratch& sc, const RegWindow& 
 // (calls whose sets all have at most kRegMaxSet units, i.e. 32 members;
 // others go to k_es_lp). The structure is that of the marginal-gains kernel: each wave
 // holds its window's member rows (two 32-row blocks) as the MFMA A operand in
-// registers for the whole item, and the ground set streams through a 3-stage
-// LDS ring of 64-point tiles (global_load_lds copies, one barrier per tile)
-// shared by the workgroup's 4 waves. Work item = (4 consecutive wave windows,
+// registers for the whole item, and the ground set streams through a 2-stage
+// LDS ring of 64-point tiles (global_load_lds copies of tile t+1 issued after
+// the barrier of tile t) shared by the workgroup's 4 waves. Work item = (4 consecutive wave windows,
 // ground-set split). Wave window w holds the sets whose first unit lies in
 // [w G, (w+1) G) (G from k_es_scan), so no set crosses windows and a window
 // spans at most kRegUnits units.
@@ -793,7 +793,6 @@ k_es_regs(const uint4* __restrict__ xq, const float* __restrict__ hn, const int*
     constexpr int L = (NI + 3) / 4;                          // copy instructions per wave per stage
     __shared__ uint4 ring0[STAGE];
     __shared__ uint4 ring1[STAGE];
-    __shared__ uint4 ring2[STAGE];
     __shared__ int32_t rmem[4][64];  // per wave: member row of each of its 64 rows (-1: padding)
 
     const int64_t n_win = sc.n_groups[2];
@@ -862,7 +861,6 @@ k_es_regs(const uint4* __restrict__ xq, const float* __restrict__ hn, const int*
         };
         float wsh_next = shift_of(0);
         if (nt > 0) copy_stage(t_begin, ring0);
-        if (nt > 1) copy_stage(t_begin + 1, ring1);
         // Software-pipelined over column blocks: while the MFMAs of column
         // block 0 of tile t run, the lane takes the unit maxima of column
         // block 1 of tile t-1, pairs them with those of its block 0 (taken
@@ -899,17 +897,12 @@ k_es_regs(const uint4* __restrict__ xq, const float* __restrict__ hn, const int*
                     acc[mb][cb] = mfma_main<DT>(&a[mb][q * T::kU4], &b[q * T::kU4], acc[mb][cb], sa[mb], sb);
         };
         constexpr int NMF = 2 * KC;  // matrix instructions per column block
-        auto tile = [&](int64_t t, const uint4* st, uint4* next2) {
-            if (t + 1 < nt)
-                wait_vmcnt<L>();
-            else
-                wait_vmcnt<0>();
-            ring_barrier();
-            // the next tile's shift loads before this stage's copies: the wait
-            // above then leaves exactly the newest stage's copies in flight
+        auto tile = [&](int64_t t, const uint4* st, uint4* next) {
+            wait_vmcnt<0>();  // this tile's copies (issued one tile ago) and its shift loads
+            ring_barrier();   // ... of every wave; every wave is done reading the other stage
             const float wsh = wsh_next;
             wsh_next = shift_of(t + 1);
-            if (t + 2 < nt) copy_stage(t_begin + t + 2, next2);
+            if (t + 1 < nt) copy_stage(t_begin + t + 1, next);
             const int* st_sc = reinterpret_cast<const int*>(st + OFF_SC);
             uint4 b[HU];
             // column block 0 of tile t, with the maxima of block 1 of tile t-1
@@ -936,11 +929,10 @@ k_es_regs(const uint4* __restrict__ xq, const float* __restrict__ hn, const int*
             }
             wsh_prev = wsh;
         };
-        // stage of tile t: t % 3 (distinct LDS objects, so a copy in flight never targets the stage read)
-        for (int64_t t = 0; t < nt; t += 3) {
-            tile(t, ring0, ring2);
+        // stage of tile t: t % 2 (distinct LDS objects)
+        for (int64_t t = 0; t < nt; t += 2) {
+            tile(t, ring0, ring1);
             if (t + 1 < nt) tile(t + 1, ring1, ring0);
-            if (t + 2 < nt) tile(t + 2, ring2, ring1);
         }
         // the last tile
         {
