@@ -33,9 +33,10 @@
 // kilobyte of a tile straight into LDS with no register staging, and the
 // MFMA operand reads from LDS are 32 consecutive 16-byte units per half-wave
 // (no bank conflicts). A workgroup (4 waves, 32*CB candidates per wave held
-// in registers) streams one chunk of the ground set through a 3-stage LDS
-// ring: the copy of tile t+2 is in flight while tile t is multiplied, with
-// one barrier per tile. MFMA tile: rows = candidates, columns = ground
+// in registers) streams one chunk of the ground set through an LDS ring,
+// one barrier per stage: variants 0-3 use three stages of 64 points (the
+// copy of tile t+2 in flight while tile t is multiplied), the interleaved
+// variant two stages of up to 256 points. MFMA tile: rows = candidates, columns = ground
 // points; each lane reads contiguous K from its half of a row (the order of
 // K inside a dot product is free as long as both operands use the same one).
 #include "ebc_internal.h"
@@ -67,7 +68,6 @@ struct LpGeom {
     static constexpr int STAGE = OFF_SC + (kFp8 ? VT / 4 : 0);  // uint4 per stage
     static constexpr int NI = NU + PP * (kFp8 ? 2 : 1);        // wave copy instructions per stage
     static constexpr int L = (NI + 3) / 4;                      // copy instructions per wave per stage
-    static constexpr int NBUF = 3;
     static constexpr int CAND_TILE = 4 * 32 * CB;
 };
 
@@ -591,8 +591,10 @@ __device__ __forceinline__ void gains_lp_pp_body(const GainsArgs& ga, int64_t bi
 // so the scheduler can put the test between the MFMAs, where it runs while
 // they execute); the clamp-and-sum then runs only for a previous tile with a
 // value above its bound. A ring stage holds wide_stage(DT, KC) points (one
-// barrier per stage); both column blocks' operands of each 64-point tile of
-// the stage are read from LDS together. The previous block's values carry
+// barrier per stage), and the ring has two stages: the copy of stage t+1 is
+// issued right after the barrier of stage t (three stages, with the copy of
+// t+2 in flight, measured 1-2% slower); both column blocks' operands of each
+// 64-point tile of the stage are read from LDS together. The previous block's values carry
 // over tile and stage boundaries, and the very first test sees -inf (no tile
 // to sum). Per-lane sums are added in column-block order with the same
 // arithmetic as clamp_sum16, so gains are bitwise those of the other
@@ -669,12 +671,9 @@ __device__ __forceinline__ void sp_tile(int64_t t, int64_t nt, int64_t t_begin, 
                                         const int (&sa)[CB], float (&acc_sum)[CB][16], floatx16 (&accA)[CB],
                                         floatx16 (&accB)[CB], float& loB, float& shB, float s) {
     constexpr int HU = G::HU, RU = G::RU;
-    if (t + 1 < nt)
-        wait_vmcnt<G::L>();
-    else
-        wait_vmcnt<0>();
-    ring_barrier();
-    if (t + 2 < nt) copy_stage<G>(wave, lane, t_begin + t + 2, xqt, ha, sc, next2);
+    wait_vmcnt<0>();  // this stage's copies, issued one stage ago
+    ring_barrier();   // ... of every wave; every wave is done reading the other stage
+    if (t + 1 < nt) copy_stage<G>(wave, lane, t_begin + t + 1, xqt, ha, sc, next2);
     const float* st_ha = reinterpret_cast<const float*>(st + G::OFF_HA);
     const int* st_sc = reinterpret_cast<const int*>(st + G::OFF_SC);
 #pragma unroll
@@ -711,7 +710,6 @@ __device__ __forceinline__ void gains_lp_sp_body(const GainsArgs& ga, int64_t bi
 
     __shared__ uint4 lds0[G::STAGE];
     __shared__ uint4 lds1[G::STAGE];
-    __shared__ uint4 lds2[G::STAGE];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -744,15 +742,11 @@ __device__ __forceinline__ void gains_lp_sp_body(const GainsArgs& ga, int64_t bi
     const int64_t nt = v_end > v_begin ? (v_end - v_begin) / VT : 0;
 
     if (nt > 0) copy_stage<G>(wave, lane, t_begin, xqt, ha, sc, lds0);
-    if (nt > 1) copy_stage<G>(wave, lane, t_begin + 1, xqt, ha, sc, lds1);
-    for (int64_t t = 0; t < nt; t += 3) {
-        sp_tile<G, DT, KC, CB>(t, nt, t_begin, wave, lane, col, half, xqt, ha, sc, lds0, lds2, a, cinit, sa,
+    for (int64_t t = 0; t < nt; t += 2) {
+        sp_tile<G, DT, KC, CB>(t, nt, t_begin, wave, lane, col, half, xqt, ha, sc, lds0, lds1, a, cinit, sa,
                                acc_sum, accA, accB, loB, shB, s);
         if (t + 1 < nt)
             sp_tile<G, DT, KC, CB>(t + 1, nt, t_begin, wave, lane, col, half, xqt, ha, sc, lds1, lds0, a, cinit,
-                                   sa, acc_sum, accA, accB, loB, shB, s);
-        if (t + 2 < nt)
-            sp_tile<G, DT, KC, CB>(t + 2, nt, t_begin, wave, lane, col, half, xqt, ha, sc, lds2, lds1, a, cinit,
                                    sa, acc_sum, accA, accB, loB, shB, s);
     }
     // the last column block
