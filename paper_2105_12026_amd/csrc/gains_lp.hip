@@ -34,9 +34,9 @@
 // MFMA operand reads from LDS are 32 consecutive 16-byte units per half-wave
 // (no bank conflicts). A workgroup (4 waves, 32*CB candidates per wave held
 // in registers) streams one chunk of the ground set through an LDS ring,
-// one barrier per stage: variants 0-3 use three stages of 64 points (the
-// copy of tile t+2 in flight while tile t is multiplied), the interleaved
-// variant two stages of up to 256 points. MFMA tile: rows = candidates, columns = ground
+// one barrier per stage: two stages (the copy of stage t+1 issued right
+// after the barrier of stage t, while stage t is multiplied) of 64 points,
+// up to 256 in the interleaved variant; the ping-pong variant keeps three. MFMA tile: rows = candidates, columns = ground
 // points; each lane reads contiguous K from its half of a row (the order of
 // K inside a dot product is free as long as both operands use the same one).
 #include "ebc_internal.h"
@@ -104,9 +104,9 @@ __device__ __forceinline__ void copy_stage(int wave, int lane, int64_t tile, con
     for (int l = 0; l < G::L; ++l) copy_piece<G>((wave + 4 * l) % G::NI, tile, lane, xqt, ha, sc, st);
 }
 
-// One ground-set tile: wait for its copy, start the copy of the tile two
-// ahead into `next2`, then the MFMAs and the fused clamp-and-sum epilogue
-// against the wave's candidate blocks.
+// One ground-set tile: wait for its copy, start the copy of the next tile
+// into the other stage `next2`, then the MFMAs and the fused clamp-and-sum
+// epilogue against the wave's candidate blocks.
 template <class G, int DT, int KC, int CB>
 __device__ __forceinline__ void lp_tile(int64_t t, int64_t nt, int64_t t_begin, int wave, int lane, int col, int half,
                                         const uint4* __restrict__ xqt, const float* __restrict__ ha,
@@ -115,15 +115,12 @@ __device__ __forceinline__ void lp_tile(int64_t t, int64_t nt, int64_t t_begin, 
                                         const int (&sa)[CB], float (&acc_sum)[CB][16], float s) {
     using T = Lp<DT>;
     constexpr int HU = G::HU, VT = G::VT;
-    // this wave's copies of tile t are done (those of t+1 may still fly) ...
-    if (t + 1 < nt)
-        wait_vmcnt<G::L>();
-    else
-        wait_vmcnt<0>();
+    // this wave's copies of tile t are done ...
+    wait_vmcnt<0>();
     // ... and every wave's, and every wave finished reading tile t-1, whose
     // stage the next copy overwrites
     ring_barrier();
-    if (t + 2 < nt) copy_stage<G>(wave, lane, t_begin + t + 2, xqt, ha, sc, next2);
+    if (t + 1 < nt) copy_stage<G>(wave, lane, t_begin + t + 1, xqt, ha, sc, next2);
     const float* st_ha = reinterpret_cast<const float*>(st + G::OFF_HA);
     const int* st_sc = reinterpret_cast<const int*>(st + G::OFF_SC);
 #pragma unroll
@@ -167,12 +164,9 @@ __device__ __forceinline__ void lp_tile_pipe(int64_t t, int64_t nt, int64_t t_be
     constexpr int NMF = KC * CB;            // matrix instructions per column block
     constexpr int NVA = 2 * 16 * CB;        // epilogue VALU instructions per column block
     constexpr int PER = (NVA + NMF - 1) / NMF;
-    if (t + 1 < nt)
-        wait_vmcnt<G::L>();
-    else
-        wait_vmcnt<0>();
+    wait_vmcnt<0>();
     ring_barrier();
-    if (t + 2 < nt) copy_stage<G>(wave, lane, t_begin + t + 2, xqt, ha, sc, next2);
+    if (t + 1 < nt) copy_stage<G>(wave, lane, t_begin + t + 1, xqt, ha, sc, next2);
     const float* st_ha = reinterpret_cast<const float*>(st + G::OFF_HA);
     const int* st_sc = reinterpret_cast<const int*>(st + G::OFF_SC);
 #pragma unroll
@@ -298,7 +292,6 @@ __device__ __forceinline__ void gains_lp_body(const GainsArgs& ga, int64_t bid) 
 
     __shared__ uint4 lds0[G::STAGE];
     __shared__ uint4 lds1[G::STAGE];
-    __shared__ uint4 lds2[G::STAGE];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -328,22 +321,18 @@ __device__ __forceinline__ void gains_lp_body(const GainsArgs& ga, int64_t bid) 
     const int64_t nt = v_end > v_begin ? (v_end - v_begin) / VT : 0;
 
     if (nt > 0) copy_stage<G>(wave, lane, t_begin, xqt, ha, sc, lds0);
-    if (nt > 1) copy_stage<G>(wave, lane, t_begin + 1, xqt, ha, sc, lds1);
-    // three stages are three distinct LDS objects and the loop is unrolled
-    // by three, so the compiler can see that the copy in flight never
-    // targets the stage being read and does not wait for it
+    // two stages are two distinct LDS objects and the loop is unrolled by
+    // two, so the compiler can see that the copy in flight never targets the
+    // stage being read and does not wait for it
     if (PIPE) {
         floatx16 prev[CB];
         float prev_lo = 0.0f, prev_sh = 0.0f;
         bool pending = false;
-        for (int64_t t = 0; t < nt; t += 3) {
-            lp_tile_pipe<G, DT, KC, CB>(t, nt, t_begin, wave, lane, col, half, xqt, ha, sc, lds0, lds2, a,
+        for (int64_t t = 0; t < nt; t += 2) {
+            lp_tile_pipe<G, DT, KC, CB>(t, nt, t_begin, wave, lane, col, half, xqt, ha, sc, lds0, lds1, a,
                                         cinit, sa, acc_sum, prev, prev_lo, prev_sh, pending, s);
             if (t + 1 < nt)
                 lp_tile_pipe<G, DT, KC, CB>(t + 1, nt, t_begin, wave, lane, col, half, xqt, ha, sc, lds1, lds0,
-                                            a, cinit, sa, acc_sum, prev, prev_lo, prev_sh, pending, s);
-            if (t + 2 < nt)
-                lp_tile_pipe<G, DT, KC, CB>(t + 2, nt, t_begin, wave, lane, col, half, xqt, ha, sc, lds2, lds1,
                                             a, cinit, sa, acc_sum, prev, prev_lo, prev_sh, pending, s);
         }
         if (pending) {
@@ -351,14 +340,11 @@ __device__ __forceinline__ void gains_lp_body(const GainsArgs& ga, int64_t bid) 
             for (int cb = 0; cb < CB; ++cb) clamp_sum16(prev[cb], prev_lo, s, prev_sh, acc_sum[cb]);
         }
     } else {
-        for (int64_t t = 0; t < nt; t += 3) {
-            lp_tile<G, DT, KC, CB>(t, nt, t_begin, wave, lane, col, half, xqt, ha, sc, lds0, lds2, a, cinit, sa,
+        for (int64_t t = 0; t < nt; t += 2) {
+            lp_tile<G, DT, KC, CB>(t, nt, t_begin, wave, lane, col, half, xqt, ha, sc, lds0, lds1, a, cinit, sa,
                                    acc_sum, s);
             if (t + 1 < nt)
                 lp_tile<G, DT, KC, CB>(t + 1, nt, t_begin, wave, lane, col, half, xqt, ha, sc, lds1, lds0, a,
-                                       cinit, sa, acc_sum, s);
-            if (t + 2 < nt)
-                lp_tile<G, DT, KC, CB>(t + 2, nt, t_begin, wave, lane, col, half, xqt, ha, sc, lds2, lds1, a,
                                        cinit, sa, acc_sum, s);
         }
     }
