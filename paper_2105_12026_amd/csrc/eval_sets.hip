@@ -45,8 +45,8 @@ constexpr int kVSub = 256;      // ground points per workgroup pass (4 waves x 6
 constexpr int kMaxSplits = 16;
 
 // Scratch of one call: unit prefix U[l+1], non-empty prefix E[l+1], set
-// status (0 ok, 1 bad), counts (n_groups[0]: group windows; [1], [2]: window
-// width and count of the register kernel), per-split partial sums
+// status (0 ok, 1 bad), counts (n_groups[0]: group windows; [1], [2], [3]:
+// window width, window count and rows per unit of the register kernels), per-split partial sums
 // [splits][l], first set of each register-kernel window [l+2].
 struct EsScratch {
     int64_t* U;
@@ -79,20 +79,29 @@ __global__ void __launch_bounds__(256) k_es_units(const int64_t* __restrict__ of
 
 // Single workgroup: inclusive scans of the unit and non-empty counts (in
 // place, U[0] = E[0] = 0), and the number of group windows. Also, for the
-// reduced-precision kernel that keeps member rows in registers: when no set
-// has more than kRegUnits units, its window width G = kRegUnits + 1 - (the
-// largest set's units) and window count (sets whose first unit lies in
-// [w G, (w+1) G) go to wave window w, which then spans at most kRegUnits
-// units); else 0 windows (that kernel stands aside).
+// kernels that keep member rows in registers: when no set has more than
+// kRegMaxSet units, their window width G = kRegUnits + 1 - (the largest
+// set's units) and window count (sets whose first unit lies in [w G, (w+1) G)
+// go to wave window w, which then spans at most kRegUnits units); else 0
+// windows (those kernels stand aside). n_groups[3] holds the rows per unit of
+// the windows: 4, or 2 when reg2 is set (a float32 call on the dataset's own
+// rows) and every non-empty set has kReg2MinRows .. 32 members. Then the
+// counts are rescanned as 2-row units and a window holds 32 of them: sets of
+// 10 members fill 10 rows instead of 12, and windows hold more whole sets.
 constexpr int kRegUnits = 16;  // units per wave window of the register kernel (two 32-row blocks)
 constexpr int kRegMaxSet = 8;  // largest set (units) it takes: then G >= 9 and there are at most l windows
+constexpr int kReg2Units = 32;    // 2-row units per window (the same two 32-row blocks)
+constexpr int kReg2MaxSet = 16;   // largest set in 2-row units (32 members)
+constexpr int kReg2MinRows = 3;   // smallest set: 2 units, so set ends are at least 2 units apart
 
-__global__ void __launch_bounds__(1024) k_es_scan(int64_t l, int32_t window, EsScratch sc) {
+__global__ void __launch_bounds__(1024) k_es_scan(int64_t l, int32_t window, EsScratch sc,
+                                                   const int64_t* __restrict__ off, int32_t reg2) {
     __shared__ int64_t su[1024];
     __shared__ int32_t se[1024];
     __shared__ int64_t carry_u;
     __shared__ int32_t carry_e;
     __shared__ int64_t umax[1024];
+    __shared__ int64_t umin[1024];
     const int t = threadIdx.x;
     if (t == 0) {
         carry_u = 0;
@@ -100,6 +109,35 @@ __global__ void __launch_bounds__(1024) k_es_scan(int64_t l, int32_t window, EsS
         sc.U[0] = 0;
         sc.E[0] = 0;
     }
+    // 2-row units: only if every non-empty valid set has 3 .. 32 members
+    bool two = false;
+    if (reg2) {
+        int64_t lo = INT64_MAX, hi = 0;
+        for (int64_t j = t; j < l; j += 1024) {
+            if (sc.bad[j]) continue;
+            const int64_t z = off[j + 1] - off[j];
+            if (z == 0) continue;
+            if (z < lo) lo = z;
+            if (z > hi) hi = z;
+        }
+        umin[t] = lo;
+        umax[t] = hi;
+        __syncthreads();
+        for (int w = 512; w > 0; w >>= 1) {
+            if (t < w) {
+                if (umax[t + w] > umax[t]) umax[t] = umax[t + w];
+                if (umin[t + w] < umin[t]) umin[t] = umin[t + w];
+            }
+            __syncthreads();
+        }
+        two = umax[0] >= kReg2MinRows && umax[0] <= 2 * kReg2MaxSet && umin[0] >= kReg2MinRows;
+        if (two)  // the same thread reads these counts in the scan below
+            for (int64_t j = t; j < l; j += 1024)
+                sc.U[j + 1] = sc.bad[j] ? 0 : (off[j + 1] - off[j] + 1) / 2;
+        __syncthreads();
+    }
+    const int64_t cap = two ? kReg2Units : kRegUnits;
+    const int64_t max_set = two ? kReg2MaxSet : kRegMaxSet;
     int64_t my_max = 0;
     __syncthreads();
     for (int64_t base = 0; base < l; base += 1024) {
@@ -134,13 +172,14 @@ __global__ void __launch_bounds__(1024) k_es_scan(int64_t l, int32_t window, EsS
         __syncthreads();
     }
     const int64_t mx = umax[0];
-    const int64_t G = kRegUnits + 1 - mx;
-    const bool fits = mx >= 1 && mx <= kRegMaxSet;
+    const int64_t G = cap + 1 - mx;
+    const bool fits = mx >= 1 && mx <= max_set;
     const int64_t n_win = fits ? (carry_u + G - 1) / G : 0;
     if (t == 0) {
         sc.n_groups[0] = (carry_u + window - 1) / window;
         sc.n_groups[1] = fits ? G : 0;
         sc.n_groups[2] = n_win;
+        sc.n_groups[3] = two ? 2 : kUnitRows;
     }
     // first set of every window: window w starts at the first set whose first
     // unit is at or after w G (set j owns the windows w with U[j-1] < w G <= U[j]);
@@ -656,16 +695,19 @@ k_es_lp(const uint4* __restrict__ xq, const float* __restrict__ hn, const int* _
 // ---- shared parts of the register kernels (k_es_regs, k_es_regs32) ----
 
 // One wave's window: its sets [j0, j1) and units [ua, ub), the member row of
-// each of its 64 rows in rmem_w (lane r: row r, unit ua + r/4; -1 padding)
-// and the wave-uniform mask of the units that end a set (bit u: unit ua + u).
+// each of its 64 rows in rmem_w (lane r: row r, unit ua + r/UR; -1 padding)
+// and the wave-uniform mask of the units that end a set (bit u: unit ua + u;
+// UR rows per unit, NU units per window).
 struct RegWindow {
     int64_t j0, j1, ua, ub;
     uint32_t m_last;
 };
 
+template <int UR = kUnitRows, int NU = kRegUnits>
 __device__ __forceinline__ RegWindow reg_window(const EsScratch& sc, int64_t w, int64_t n_win, int lane,
                                                 const int64_t* __restrict__ off, const int32_t* __restrict__ idx,
                                                 int32_t* rmem_w) {
+    static_assert(UR * NU == 64 && NU <= 32, "a window is 64 rows; one mask bit per unit");
     RegWindow r{0, 0, 0, 0, 0u};
     if (w < n_win) {
         r.j0 = sc.win_j0[w];
@@ -674,11 +716,11 @@ __device__ __forceinline__ RegWindow reg_window(const EsScratch& sc, int64_t w, 
     r.ua = sc.U[r.j0];
     r.ub = sc.U[r.j1];
     {
-        const int64_t u = r.ua + lane / kUnitRows;
+        const int64_t u = r.ua + lane / UR;
         int32_t mem = -1;
         if (u < r.ub) {
             const int64_t j = owner_of(sc.U, r.j0, r.j1, u);
-            const int64_t q = (u - sc.U[j]) * kUnitRows + lane % kUnitRows;
+            const int64_t q = (u - sc.U[j]) * UR + lane % UR;
             if (off[j] + q < off[j + 1]) mem = idx[off[j] + q];
         }
         rmem_w[lane] = mem;
@@ -686,7 +728,7 @@ __device__ __forceinline__ RegWindow reg_window(const EsScratch& sc, int64_t w, 
     {
         const int64_t u = r.ua + lane;
         bool last = false;
-        if (lane < kRegUnits && u < r.ub) {
+        if (lane < NU && u < r.ub) {
             const int64_t j = owner_of(sc.U, r.j0, r.j1, u);
             last = u == sc.U[j + 1] - 1;
         }
@@ -737,14 +779,52 @@ __device__ __forceinline__ void reg_close(const float (&x0)[8], const float (&x1
     }
 }
 
-// Each set's accumulator summed over the 64 lanes in a fixed order in
-// float64, one write per set and ground-set split.
-__device__ __forceinline__ void reg_write(const EsScratch& sc, const RegWindow& wv, const float (&acc_u)[kRegUnits],
+// The same for a window of 32 two-row units (x0, x1: the 8 + 8 two-row
+// maxima per lane of column block 0 / 1, index mb 8 + 2 g + e for rows
+// 8 g + 4 h + 2 e, +1 of member block mb, i.e. unit 4 g + 2 h + e of that
+// block). Every set spans at least two units, so two set ends are at least
+// two units apart and set ends of units u share accumulator u / 2 with no
+// other set. The restarts come from the scalar mask (-inf or 0 added in a
+// scalar register), not from a register array.
+__device__ __forceinline__ void reg_close2(const float (&x0)[16], const float (&x1)[16], uint32_t m_last, float wsh,
+                                           float (&acc_s)[kReg2Units / 2]) {
+    float um[kReg2Units];
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+        for (int g = 0; g < 4; ++g)
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+                const int k = mb * 8 + 2 * g + e;
+                const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x0[k]), __float_as_uint(x1[k]), false,
+                                                                false);
+                um[mb * 16 + 4 * g + e] = __uint_as_float(r[0]);
+                um[mb * 16 + 4 * g + 2 + e] = __uint_as_float(r[1]);
+            }
+    float cur = -INFINITY;
+    uint32_t ml = m_last;
+    asm volatile("" : "+s"(ml));
+#pragma unroll
+    for (int u = 0; u < kReg2Units; ++u) {
+        const float rs = (u > 0 && ((ml >> (u - 1)) & 1u)) ? -INFINITY : 0.0f;
+        cur = fmaxf(cur + rs, um[u]);
+        if ((ml >> u) & 1u) {
+            asm volatile("");
+            acc_s[u >> 1] += fmaxf(cur + wsh, 0.0f);
+        }
+    }
+}
+
+// Each set's accumulator (acc[u >> SH] for the set ending at unit u) summed
+// over the 64 lanes in a fixed order in float64, one write per set and
+// ground-set split.
+template <int NU = kRegUnits, int SH = 0>
+__device__ __forceinline__ void reg_write(const EsScratch& sc, const RegWindow& wv, const float (&acc_u)[NU >> SH],
                                           int lane, int split, int64_t l) {
 #pragma unroll
-    for (int u = 0; u < kRegUnits; ++u) {
+    for (int u = 0; u < NU; ++u) {
         if (!((wv.m_last >> u) & 1u)) continue;
-        double v = double(acc_u[u]);
+        double v = double(acc_u[u >> SH]);
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
         if (lane == 0) {
@@ -953,8 +1033,12 @@ k_es_regs(const uint4* __restrict__ xq, const float* __restrict__ hn, const int*
 // the operand reads of a half-wave are 32 consecutive units), two stages of
 // KP/4 KB each. Lane half h takes K values h KP/2 .. (h+1) KP/2 - 1 of both
 // operands (one 16-byte unit feeds 4 MFMAs). A tile's epilogue costs about as
-// much as 3 of its 4 KP MFMAs, so it is not overlapped with them.
-template <int KP>
+// much as 3 of its 4 KP MFMAs, so it is not overlapped with them. UR = rows
+// per unit of the call's windows: 4 (16 units per window), or 2 (32 units;
+// calls whose sets all have 3 .. 32 members, so a set of 10 fills 10 rows,
+// not 12); the instance of the other unit size returns at once. The member
+// rows' maxima and sums are the same in both, bit for bit.
+template <int KP, int UR>
 __global__ void __launch_bounds__(256)
 k_es_regs32(const uint4* __restrict__ xq, const float* __restrict__ hn, int64_t n, const double* __restrict__ m0,
             const int64_t* __restrict__ off, const int32_t* __restrict__ idx, int64_t l, int32_t splits,
@@ -970,8 +1054,13 @@ k_es_regs32(const uint4* __restrict__ xq, const float* __restrict__ hn, int64_t 
     __shared__ uint4 ring1[STAGE];
     __shared__ int32_t rmem[4][64];
 
+    static_assert(UR == 2 || UR == 4, "units of 2 or 4 rows");
+    constexpr int NU = 64 / UR;  // units per window
+    constexpr int NA = 16;       // per-lane set accumulators (UR 4: one per unit; UR 2: one per unit pair)
     const int64_t n_win = sc.n_groups[2];
-    if (n_win == 0) return;  // some set is longer than kRegMaxSet units (k_es_main runs), or none has units
+    // some set is longer than the window allows (k_es_main runs), none has
+    // units, or the windows are in the other unit size
+    if (n_win == 0 || sc.n_groups[3] != UR) return;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -995,7 +1084,7 @@ k_es_regs32(const uint4* __restrict__ xq, const float* __restrict__ hn, int64_t 
         const int64_t g = item / splits;
         const int split = int(item % splits);
         const int64_t w = g * 4 + wave;
-        const RegWindow wv = reg_window(sc, w, n_win, lane, off, idx, rmem[wave]);
+        const RegWindow wv = reg_window<UR, NU>(sc, w, n_win, lane, off, idx, rmem[wave]);
         const uint32_t m_last = wv.m_last;
         __syncthreads();  // rmem of every wave written (and the ring of the previous item drained)
         uint4 a[2][HU];
@@ -1012,11 +1101,11 @@ k_es_regs32(const uint4* __restrict__ xq, const float* __restrict__ hn, int64_t 
                 cinit[mb][r] = mr >= 0 ? -hn[mr] : -INFINITY;
             }
         }
-        float acc_u[kRegUnits];
+        float acc_u[NA];
 #pragma unroll
-        for (int u = 0; u < kRegUnits; ++u) acc_u[u] = 0.0f;
+        for (int u = 0; u < NA; ++u) acc_u[u] = 0.0f;
         float rs[kRegUnits];
-        reg_restarts(m_last, rs);
+        if constexpr (UR == 4) reg_restarts(m_last, rs);
 
         const int64_t v_begin = int64_t(split) * vchunk;
         int64_t v_end = v_begin + vchunk;
@@ -1035,7 +1124,7 @@ k_es_regs32(const uint4* __restrict__ xq, const float* __restrict__ hn, int64_t 
             const float wsh = wsh_next;
             wsh_next = shift_of(t + 1);
             if (t + 1 < nt) copy_stage(t_begin + t + 1, next);
-            float xm[2][8];  // unit maxima per column block
+            float xm[2][32 / UR];  // unit maxima per column block
 #pragma unroll
             for (int cb = 0; cb < 2; ++cb) {
                 floatx16 acc[2] = {cinit[0], cinit[1]};
@@ -1061,18 +1150,26 @@ k_es_regs32(const uint4* __restrict__ xq, const float* __restrict__ hn, int64_t 
 #pragma unroll
                     for (int gq = 0; gq < kBlockUnits / 2; ++gq) {
                         const floatx16& pq = acc[mb];
-                        xm[cb][mb * 4 + gq] =
-                            fmaxf(fmaxf(pq[4 * gq], pq[4 * gq + 1]), fmaxf(pq[4 * gq + 2], pq[4 * gq + 3]));
+                        if constexpr (UR == 4) {
+                            xm[cb][mb * 4 + gq] =
+                                fmaxf(fmaxf(pq[4 * gq], pq[4 * gq + 1]), fmaxf(pq[4 * gq + 2], pq[4 * gq + 3]));
+                        } else {
+                            xm[cb][mb * 8 + 2 * gq] = fmaxf(pq[4 * gq], pq[4 * gq + 1]);
+                            xm[cb][mb * 8 + 2 * gq + 1] = fmaxf(pq[4 * gq + 2], pq[4 * gq + 3]);
+                        }
                     }
             }
-            reg_close(xm[0], xm[1], rs, m_last, wsh, acc_u);
+            if constexpr (UR == 4)
+                reg_close(xm[0], xm[1], rs, m_last, wsh, acc_u);
+            else
+                reg_close2(xm[0], xm[1], m_last, wsh, acc_u);
         };
         // stage of tile t: t % 2 (distinct LDS objects)
         for (int64_t t = 0; t < nt; t += 2) {
             tile(t, ring0, ring1);
             if (t + 1 < nt) tile(t + 1, ring1, ring0);
         }
-        reg_write(sc, wv, acc_u, lane, split, l);
+        reg_write<NU, UR == 4 ? 0 : 1>(sc, wv, acc_u, lane, split, l);
     }
 }
 
@@ -1367,10 +1464,14 @@ void launch_es_main(dim3 g, hipStream_t s, const ebc_dataset* ds, const int64_t*
     bool own = false;
     if constexpr (KP <= 120) {
         own = ds->dt == EBC_DT_F32 && ds->k_pad == KP;
-        if (own)
-            hipLaunchKernelGGL((k_es_regs32<KP>), g, dim3(256), 0, s,
-                               static_cast<const uint4*>(static_cast<const void*>(ds->b.xq)), ds->b.hn, ds->n,
-                               ds->b.m0, off, idx, l, splits, sc);
+        if (own) {
+            // the scan chose 4- or 2-row units; the other instance returns at once
+            const uint4* xq = static_cast<const uint4*>(static_cast<const void*>(ds->b.xq));
+            hipLaunchKernelGGL((k_es_regs32<KP, 4>), g, dim3(256), 0, s, xq, ds->b.hn, ds->n, ds->b.m0, off, idx, l,
+                               splits, sc);
+            hipLaunchKernelGGL((k_es_regs32<KP, 2>), g, dim3(256), 0, s, xq, ds->b.hn, ds->n, ds->b.m0, off, idx, l,
+                               splits, sc);
+        }
     }
     hipLaunchKernelGGL((k_es_main<KP>), g, dim3(256), 0, s, ds->x, ds->n, ds->d, ds->b.n64, ds->b.m0, off, idx, l,
                        splits, sc, int32_t(own));
@@ -1417,7 +1518,7 @@ hipError_t launch_eval_sets(const ebc_dataset* ds, const int64_t* offsets, const
     hipLaunchKernelGGL(k_es_units, dim3(nb), dim3(256), 0, s, offsets, idx, l, ds->n, sc, ds->b.state);
     if (ds->metric == 1) {
         // L1: float32 rows of the caller on the vector ALUs, whatever in_dtype says
-        hipLaunchKernelGGL(k_es_scan, dim3(1), dim3(1024), 0, s, l, kL1EsWin, sc);
+        hipLaunchKernelGGL(k_es_scan, dim3(1), dim3(1024), 0, s, l, kL1EsWin, sc, offsets, 0);
         hipLaunchKernelGGL(k_es_l1, dim3(2048), dim3(256), 0, s, ds->x, ds->n, ds->d, ds->b.m0, offsets, idx, l,
                            splits, sc);
         hipLaunchKernelGGL(k_es_final, dim3(nb), dim3(256), 0, s, l, ds->n, splits, sc, 1.0, f_out);
@@ -1427,8 +1528,13 @@ hipError_t launch_eval_sets(const ebc_dataset* ds, const int64_t* offsets, const
     const int lp_kc = ds->k_pad / (ds->dt == EBC_DT_FP8_E4M3 ? 64 : 16);
     // long rows (float32 rows padded to 8, or the cast rows): the long-row kernel
     const bool wide = wide_rows(lowp ? ds->k_pad : (ds->d + 7) / 8 * 8);
+    // 2-row units are open to the float32 register kernel only (the dataset's
+    // own rows, up to 120 values): the same condition under which
+    // launch_es_main launches it
+    const int kp32 = (ds->d + 7) / 8 * 8;
+    const int32_t reg2 = (!lowp && !wide && ds->dt == EBC_DT_F32 && ds->k_pad == kp32 && kp32 <= 120) ? 1 : 0;
     hipLaunchKernelGGL(k_es_scan, dim3(1), dim3(1024), 0, s, l,
-                       (lowp && !wide) ? lp_window(ds->dt, lp_kc) : kWindow, sc);
+                       (lowp && !wide) ? lp_window(ds->dt, lp_kc) : kWindow, sc, offsets, reg2);
     // persistent grid over (group, split) items; the item count is read on the device
     const dim3 g = dim3(2048);
     if (wide) {

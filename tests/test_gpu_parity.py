@@ -231,6 +231,41 @@ def test_eval_sets_many_sizes(ebc, torch_dev, ref, n, d, dt, seed):
     assert np.all(err <= F_RTOL * np.abs(rf) + 1e-12 * l0), float(np.max(err / (np.abs(rf) + 1e-300)))
 
 
+@pytest.mark.parametrize("n,d,seed", [(3000, 100, 57), (1500, 37, 58), (700, 8, 59), (900, 120, 60)])
+def test_eval_sets_two_row_units(ebc, torch_dev, ref, n, d, seed):
+    """Float32 calls whose non-empty sets all have 3..32 members are evaluated
+    in windows of 2-row units; one set of 1 or 2 members puts the whole call
+    back on 4-row units, and one of 33 on the general kernel. Every set's f is
+    the same, bit for bit, in the first two, and all three match the oracle."""
+    torch, _ = torch_dev
+    rng = np.random.default_rng(seed)
+    x = W.gaussian_mixture(rng, n, d, 5).astype(np.float32)
+    sizes = [3, 4, 5, 10, 10, 31, 32, 0, 3, 17, 32, 32, 6, 0, 9]
+    sizes += list(rng.integers(3, 33, 400))
+    sets = [rng.choice(n, sz, replace=False) for sz in sizes]
+    ds = _ds(ebc, torch_dev, x)
+    l0 = float(np.mean(np.sum(x.astype(np.float64) ** 2, axis=1)))
+
+    def run(extra):
+        q = sets + ([np.arange(extra, dtype=np.int64) % n] if extra else [])
+        off = np.cumsum([0] + [len(v) for v in q]).astype(np.int64)
+        idx = np.concatenate(q).astype(np.int32)
+        _say(f"eval_sets 2-row units n={n} d={d} l={len(q)} extra set of {extra}")
+        f = ds.eval_sets(torch.from_numpy(off), torch.from_numpy(idx)).cpu().numpy()
+        ds.sync()
+        rf = ref.eval_sets(x, off, idx)
+        err = np.abs(f - rf)
+        assert np.all(err <= F_RTOL * np.abs(rf) + 1e-12 * l0), float(np.max(err / (np.abs(rf) + 1e-300)))
+        return f[: len(sets)]
+
+    f2 = run(0)
+    f4 = run(1)
+    assert np.array_equal(f2, f4)
+    assert np.array_equal(f2, run(2))
+    run(33)
+    assert np.all(f2[np.array(sizes) == 0] == 0.0)
+
+
 def test_eval_sets_bad_index_is_reported(ebc, torch_dev):
     torch, _ = torch_dev
     x = np.random.default_rng(61).standard_normal((50, 4)).astype(np.float32)
