@@ -20,6 +20,11 @@
 // the ground set; it streams that chunk through LDS in tiles of 64 points.
 // MFMA tile: rows = 32 candidates, columns = 32 ground points, K = the
 // dimension, split in two halves so that every lane reads contiguous K.
+// Rows are padded to KP (a multiple of 8); when the last 4 values of a row
+// are padding (TRIM: d <= KP - 4), the last two K steps pair values KH - 4,
+// KH - 3 (lane half 0) with KH - 2, KH - 1 (lane half 1) instead of running
+// two more steps whose half-1 values are all zeros: KH - 2 matrix
+// instructions per column block instead of KH (50 instead of 52 at d = 100).
 #include "ebc_internal.h"
 
 namespace ebc {
@@ -46,7 +51,7 @@ __device__ __forceinline__ PreVec<PER> load_rows(const float4* __restrict__ src,
     return pre;
 }
 
-template <int KP>
+template <int KP, bool TRIM>
 __device__ __forceinline__ void gains_f32_body(const GainsArgs& ga, int64_t bid) {
     const float* __restrict__ xq = static_cast<const float*>(ga.xq);
     const float* __restrict__ hn = ga.hn;
@@ -88,16 +93,24 @@ __device__ __forceinline__ void gains_f32_body(const GainsArgs& ga, int64_t bid)
         atomicCAS(err, 0, kDevErrIndex);
         crow = -1;
     }
+    constexpr int QF = TRIM ? KH / 4 - 1 : KH / 4;  // groups of 4 K steps on contiguous halves
     float a[KH];
     if (crow >= 0) {
         const float4* src = reinterpret_cast<const float4*>(xq + crow * KP + half * KH);
 #pragma unroll
-        for (int q = 0; q < KH / 4; ++q) {
+        for (int q = 0; q < QF; ++q) {
             const float4 t = src[q];
             a[4 * q + 0] = t.x;
             a[4 * q + 1] = t.y;
             a[4 * q + 2] = t.z;
             a[4 * q + 3] = t.w;
+        }
+        if constexpr (TRIM) {  // half 0: values KH-4, KH-3; half 1: KH-2, KH-1
+            const float2 t = *reinterpret_cast<const float2*>(xq + crow * KP + (half ? KH - 2 : KH - 4));
+            a[KH - 4] = t.x;
+            a[KH - 3] = t.y;
+            a[KH - 2] = 0.0f;
+            a[KH - 1] = 0.0f;
         }
     } else {
 #pragma unroll
@@ -169,12 +182,17 @@ __device__ __forceinline__ void gains_f32_body(const GainsArgs& ga, int64_t bid)
             for (int r = 0; r < 16; ++r) acc[r] = nhn[r] + hav;
             const float4* b4 = reinterpret_cast<const float4*>(lds_x + vrow * S + half * KH);
 #pragma unroll
-            for (int q = 0; q < KH / 4; ++q) {
+            for (int q = 0; q < QF; ++q) {
                 const float4 bv = b4[q];
                 acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a[4 * q + 0], bv.x, acc, 0, 0, 0);
                 acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a[4 * q + 1], bv.y, acc, 0, 0, 0);
                 acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a[4 * q + 2], bv.z, acc, 0, 0, 0);
                 acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a[4 * q + 3], bv.w, acc, 0, 0, 0);
+            }
+            if constexpr (TRIM) {
+                const float2 bv = *reinterpret_cast<const float2*>(lds_x + vrow * S + (half ? KH - 2 : KH - 4));
+                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a[KH - 4], bv.x, acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a[KH - 3], bv.y, acc, 0, 0, 0);
             }
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc_sum[r] += __builtin_amdgcn_fmed3f(acc[r], 0.0f, hmv);
@@ -199,9 +217,9 @@ __device__ __forceinline__ void gains_f32_body(const GainsArgs& ga, int64_t bid)
     }
 }
 
-template <int KP>
+template <int KP, bool TRIM>
 __global__ void __launch_bounds__(256) k_gains_f32(GainsArgs ga) {
-    gains_f32_body<KP>(ga, blockIdx.x);
+    gains_f32_body<KP, TRIM>(ga, blockIdx.x);
 }
 
 // Batched: workgroups wg_pre[j] .. wg_pre[j+1] serve descriptor slot_inst[j]
@@ -213,7 +231,7 @@ kb_gains_f32(const InstDesc* __restrict__ descs, const int32_t* __restrict__ slo
     const int j = find_slot(wg_pre, slots, blockIdx.x);
     const InstDesc c = descs[slot_inst[j]];
     if (c.t0 + t >= c.k) return;
-    gains_f32_body<KP>(gains_args(c, nullptr, c.n_pad), int64_t(blockIdx.x) - wg_pre[j]);
+    gains_f32_body<KP, false>(gains_args(c, nullptr, c.n_pad), int64_t(blockIdx.x) - wg_pre[j]);
 }
 
 template <int KP>
@@ -221,8 +239,13 @@ static void launch_kp(const ebc_dataset* ds, const int32_t* cand, int64_t n_cand
     const int64_t tiles = (n_cand + kGainsCandTile - 1) / kGainsCandTile;
     InstDesc c;
     fill_desc(ds, 0, nullptr, nullptr, nullptr, &c);
-    hipLaunchKernelGGL(k_gains_f32<KP>, dim3(unsigned(tiles * ds->v_splits)), dim3(256), 0, s,
-                       gains_args(c, cand, n_cand));
+    // the instances in a batch may differ in d, so only a solo launch trims
+    if (ds->d <= KP - 4)
+        hipLaunchKernelGGL((k_gains_f32<KP, true>), dim3(unsigned(tiles * ds->v_splits)), dim3(256), 0, s,
+                           gains_args(c, cand, n_cand));
+    else
+        hipLaunchKernelGGL((k_gains_f32<KP, false>), dim3(unsigned(tiles * ds->v_splits)), dim3(256), 0, s,
+                           gains_args(c, cand, n_cand));
 }
 
 #define EBC_F32_KPS(X) \
