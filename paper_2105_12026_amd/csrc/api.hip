@@ -109,8 +109,8 @@ ebc_status ebc_dataset_create(const float* x, int64_t n, int32_t d, ebc_dtype dt
     ds->n_pad = pad_rows(n);
     ds->d = d;
     ds->k_pad = k_pad_for(d, dt);
-    ds->v_splits = v_splits_for(ds->n_pad, ds->k_pad);
     ds->dt = dt;
+    ds->v_splits = v_splits_for(ds->n_pad, ds->k_pad, dt);
     ds->metric = (flags & EBC_FLAG_L1) ? 1 : 0;
     // reduced precision: the interleaved-test tile variant (bitwise the same
     // gains as every other variant, the fastest on the measured shapes)

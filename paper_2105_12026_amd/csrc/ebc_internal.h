@@ -162,7 +162,7 @@ __host__ __device__ inline int32_t group_count(int64_t n) {
 
 int64_t pad_rows(int64_t n);
 int32_t k_pad_for(int32_t d, ebc_dtype dt);
-int32_t v_splits_for(int64_t n_pad, int32_t k_pad);
+int32_t v_splits_for(int64_t n_pad, int32_t k_pad, ebc_dtype dt);
 Layout layout(int64_t n, int32_t d, ebc_dtype dt);
 
 }  // namespace ebc
