@@ -1032,13 +1032,15 @@ k_es_regs(const uint4* __restrict__ xq, const float* __restrict__ hn, const int*
 // row's 16-byte units of a 64-point tile into the LDS stage (unit-major, so
 // the operand reads of a half-wave are 32 consecutive units), two stages of
 // KP/4 KB each. Lane half h takes K values h KP/2 .. (h+1) KP/2 - 1 of both
-// operands (one 16-byte unit feeds 4 MFMAs). A tile's epilogue costs about as
+// operands (one 16-byte unit feeds 4 MFMAs; when the rows' last 4 slots are
+// padding, the last unit of half 0 feeds both halves in 2 MFMAs: values
+// KP/2-4, -3 on half 0 and KP/2-2, -1 on half 1). A tile's epilogue costs about as
 // much as 3 of its 4 KP MFMAs, so it is not overlapped with them. UR = rows
 // per unit of the call's windows: 4 (16 units per window), or 2 (32 units;
 // calls whose sets all have 3 .. 32 members, so a set of 10 fills 10 rows,
 // not 12); the instance of the other unit size returns at once. The member
 // rows' maxima and sums are the same in both, bit for bit.
-template <int KP, int UR>
+template <int KP, int UR, bool TRIM>
 __global__ void __launch_bounds__(256)
 k_es_regs32(const uint4* __restrict__ xq, const float* __restrict__ hn, int64_t n, const double* __restrict__ m0,
             const int64_t* __restrict__ off, const int32_t* __restrict__ idx, int64_t l, int32_t splits,
@@ -1095,6 +1097,10 @@ k_es_regs32(const uint4* __restrict__ xq, const float* __restrict__ hn, int64_t 
             const uint4* src = xq + int64_t(mem < 0 ? 0 : mem) * RU + half * HU;
 #pragma unroll
             for (int u = 0; u < HU; ++u) a[mb][u] = mem >= 0 ? src[u] : make_uint4(0, 0, 0, 0);
+            if constexpr (TRIM) {  // last step: half 0 takes values KP/2-4, -3, half 1 takes KP/2-2, -1
+                const uint4 t = mem >= 0 ? src[HU - 1 - half * HU] : make_uint4(0, 0, 0, 0);
+                a[mb][HU - 1] = half ? make_uint4(t.z, t.w, 0, 0) : t;
+            }
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
                 const int32_t mr = rmem[wave][mb * 32 + 8 * (r / 4) + 4 * half + (r % 4)];
@@ -1130,6 +1136,21 @@ k_es_regs32(const uint4* __restrict__ xq, const float* __restrict__ hn, int64_t 
                 floatx16 acc[2] = {cinit[0], cinit[1]};
 #pragma unroll
                 for (int u = 0; u < HU; ++u) {
+                    if (TRIM && u == HU - 1) {
+                        // the row's last 4 slots are padding: one unit (the
+                        // last of half 0) feeds both halves, 2 steps instead of 4
+                        const uint4 bq = st[(HU - 1) * VT + cb * 32 + col];
+                        const float b0 = __uint_as_float(half ? bq.z : bq.x);
+                        const float b1 = __uint_as_float(half ? bq.w : bq.y);
+#pragma unroll
+                        for (int mb = 0; mb < 2; ++mb) {
+                            acc[mb] = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a[mb][u].x), b0, acc[mb],
+                                                                           0, 0, 0);
+                            acc[mb] = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a[mb][u].y), b1, acc[mb],
+                                                                           0, 0, 0);
+                        }
+                        continue;
+                    }
                     const uint4 bq = st[(half * HU + u) * VT + cb * 32 + col];
                     const float bv[4] = {__uint_as_float(bq.x), __uint_as_float(bq.y), __uint_as_float(bq.z),
                                          __uint_as_float(bq.w)};
@@ -1467,10 +1488,17 @@ void launch_es_main(dim3 g, hipStream_t s, const ebc_dataset* ds, const int64_t*
         if (own) {
             // the scan chose 4- or 2-row units; the other instance returns at once
             const uint4* xq = static_cast<const uint4*>(static_cast<const void*>(ds->b.xq));
-            hipLaunchKernelGGL((k_es_regs32<KP, 4>), g, dim3(256), 0, s, xq, ds->b.hn, ds->n, ds->b.m0, off, idx, l,
-                               splits, sc);
-            hipLaunchKernelGGL((k_es_regs32<KP, 2>), g, dim3(256), 0, s, xq, ds->b.hn, ds->n, ds->b.m0, off, idx, l,
-                               splits, sc);
+            if (ds->d <= KP - 4) {  // the rows' last 4 slots are padding
+                hipLaunchKernelGGL((k_es_regs32<KP, 4, true>), g, dim3(256), 0, s, xq, ds->b.hn, ds->n, ds->b.m0, off,
+                                   idx, l, splits, sc);
+                hipLaunchKernelGGL((k_es_regs32<KP, 2, true>), g, dim3(256), 0, s, xq, ds->b.hn, ds->n, ds->b.m0, off,
+                                   idx, l, splits, sc);
+            } else {
+                hipLaunchKernelGGL((k_es_regs32<KP, 4, false>), g, dim3(256), 0, s, xq, ds->b.hn, ds->n, ds->b.m0, off,
+                                   idx, l, splits, sc);
+                hipLaunchKernelGGL((k_es_regs32<KP, 2, false>), g, dim3(256), 0, s, xq, ds->b.hn, ds->n, ds->b.m0, off,
+                                   idx, l, splits, sc);
+            }
         }
     }
     hipLaunchKernelGGL((k_es_main<KP>), g, dim3(256), 0, s, ds->x, ds->n, ds->d, ds->b.n64, ds->b.m0, off, idx, l,

@@ -231,12 +231,15 @@ def test_eval_sets_many_sizes(ebc, torch_dev, ref, n, d, dt, seed):
     assert np.all(err <= F_RTOL * np.abs(rf) + 1e-12 * l0), float(np.max(err / (np.abs(rf) + 1e-300)))
 
 
-@pytest.mark.parametrize("n,d,seed", [(3000, 100, 57), (1500, 37, 58), (700, 8, 59), (900, 120, 60)])
+@pytest.mark.parametrize("n,d,seed", [(3000, 100, 57), (1500, 37, 58), (700, 8, 59), (900, 120, 60), (800, 60, 61),
+                                      (600, 3, 62)])
 def test_eval_sets_two_row_units(ebc, torch_dev, ref, n, d, seed):
     """Float32 calls whose non-empty sets all have 3..32 members are evaluated
     in windows of 2-row units; one set of 1 or 2 members puts the whole call
     back on 4-row units, and one of 33 on the general kernel. Every set's f is
-    the same, bit for bit, in the first two, and all three match the oracle."""
+    the same, bit for bit, in the first two, and all three match the oracle.
+    Rows whose last 4 padded slots are empty (d = 100, 60, 3) take the
+    shortened last K step."""
     torch, _ = torch_dev
     rng = np.random.default_rng(seed)
     x = W.gaussian_mixture(rng, n, d, 5).astype(np.float32)
