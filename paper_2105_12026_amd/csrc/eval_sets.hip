@@ -335,7 +335,7 @@ __device__ __forceinline__ void es_finish(int tid, int64_t j0, int64_t j1, int s
     }
 }
 
-template <int KP>
+template <int KP, bool TRIM>
 __global__ void __launch_bounds__(256)
 k_es_main(const float* __restrict__ x, int64_t n, int32_t d, const double* __restrict__ n64,
           const double* __restrict__ m0, const int64_t* __restrict__ off, const int32_t* __restrict__ idx, int64_t l, int32_t splits,
@@ -346,6 +346,10 @@ k_es_main(const float* __restrict__ x, int64_t n, int32_t d, const double* __res
     constexpr int S = KP + 4;   // LDS row stride (S/4 odd: conflict-free 16-byte reads)
     constexpr int PF = KP / 8;  // member-row values each thread gathers per block
     static_assert(KP % 8 == 0, "row length must be a multiple of 8");
+    // TRIM (d <= KP - 4): the last 4 K values of lane half 1 are padding, so
+    // the last K group pairs values KH-4, KH-3 (half 0) with KH-2, KH-1
+    // (half 1) in 2 MFMAs instead of 4
+    constexpr int QF = TRIM ? KH / 4 - 1 : KH / 4;
     __shared__ float4 lds_m4[2][32 * S / 4];
     __shared__ BlockInfo info[3];
     __shared__ int64_t t_u[kTab + 1], t_off[kTab + 1];
@@ -397,7 +401,7 @@ k_es_main(const float* __restrict__ x, int64_t n, int32_t d, const double* __res
                         // rows 16-byte aligned: 4 values per load; a 4-group is
                         // either wholly inside the row or wholly padding
 #pragma unroll
-                        for (int s4 = 0; s4 < KH / 4; ++s4) {
+                        for (int s4 = 0; s4 < QF; ++s4) {
                             const int k = half * KH + 4 * s4;
                             float4 q = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
                             if (ok && k < d) q = *reinterpret_cast<const float4*>(x + v * d + k);
@@ -408,10 +412,17 @@ k_es_main(const float* __restrict__ x, int64_t n, int32_t d, const double* __res
                         }
                     } else {
 #pragma unroll
-                        for (int s = 0; s < KH; ++s) {
+                        for (int s = 0; s < 4 * QF; ++s) {
                             const int k = half * KH + s;
                             b[cb][s] = (ok && k < d) ? x[v * d + k] : 0.0f;
                         }
+                    }
+                    if constexpr (TRIM) {
+                        const int k = half ? KH - 2 : KH - 4;
+                        b[cb][KH - 4] = (ok && k < d) ? x[v * d + k] : 0.0f;
+                        b[cb][KH - 3] = (ok && k + 1 < d) ? x[v * d + k + 1] : 0.0f;
+                        b[cb][KH - 2] = 0.0f;
+                        b[cb][KH - 1] = 0.0f;
                     }
                 }
                 float cur[2] = {-INFINITY, -INFINITY};
@@ -454,7 +465,7 @@ k_es_main(const float* __restrict__ x, int64_t n, int32_t d, const double* __res
                         for (int r = 0; r < 16; ++r) acc[cb][r] = bi.row_c[8 * (r / 4) + 4 * half + (r % 4)];
                     const float* arow = reinterpret_cast<const float*>(lds_m4[rb]) + col * S + half * KH;
 #pragma unroll
-                    for (int s4 = 0; s4 < KH / 4; ++s4) {
+                    for (int s4 = 0; s4 < QF; ++s4) {
                         const float4 a4 = *reinterpret_cast<const float4*>(arow + 4 * s4);
                         const float av[4] = {a4.x, a4.y, a4.z, a4.w};
 #pragma unroll
@@ -463,6 +474,15 @@ k_es_main(const float* __restrict__ x, int64_t n, int32_t d, const double* __res
                             for (int cb = 0; cb < 2; ++cb)
                                 acc[cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[i], b[cb][4 * s4 + i], acc[cb], 0,
                                                                                0, 0);
+                    }
+                    if constexpr (TRIM) {
+                        const float2 a2 = *reinterpret_cast<const float2*>(reinterpret_cast<const float*>(lds_m4[rb]) +
+                                                                           col * S + (half ? KH - 2 : KH - 4));
+#pragma unroll
+                        for (int cb = 0; cb < 2; ++cb) {
+                            acc[cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a2.x, b[cb][KH - 4], acc[cb], 0, 0, 0);
+                            acc[cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a2.y, b[cb][KH - 3], acc[cb], 0, 0, 0);
+                        }
                     }
                     es_units<kWindow>(acc, bi.unit_flags, bi.unit_local, wsh, cur, half, col, lacc[wave]);
                     if (more) {
@@ -1501,8 +1521,12 @@ void launch_es_main(dim3 g, hipStream_t s, const ebc_dataset* ds, const int64_t*
             }
         }
     }
-    hipLaunchKernelGGL((k_es_main<KP>), g, dim3(256), 0, s, ds->x, ds->n, ds->d, ds->b.n64, ds->b.m0, off, idx, l,
-                       splits, sc, int32_t(own));
+    if (ds->d <= KP - 4)
+        hipLaunchKernelGGL((k_es_main<KP, true>), g, dim3(256), 0, s, ds->x, ds->n, ds->d, ds->b.n64, ds->b.m0, off,
+                           idx, l, splits, sc, int32_t(own));
+    else
+        hipLaunchKernelGGL((k_es_main<KP, false>), g, dim3(256), 0, s, ds->x, ds->n, ds->d, ds->b.n64, ds->b.m0, off,
+                           idx, l, splits, sc, int32_t(own));
 }
 
 }  // namespace
