@@ -888,11 +888,14 @@ k_es_regs(const uint4* __restrict__ xq, const float* __restrict__ hn, const int*
     constexpr int VT = 64;           // ground points per tile
     constexpr bool kFp8 = DT == EBC_DT_FP8_E4M3;
     constexpr int OFF_SC = RU * VT;                          // FP8: the tile's row scales after its units
-    constexpr int STAGE = RU * VT + (kFp8 ? VT / 4 : 0);     // uint4 per stage
-    constexpr int NI = RU + (kFp8 ? 1 : 0);                  // wave copy instructions per stage
-    constexpr int L = (NI + 3) / 4;                          // copy instructions per wave per stage
-    __shared__ uint4 ring0[STAGE];
-    __shared__ uint4 ring1[STAGE];
+    constexpr int STAGE1 = RU * VT + (kFp8 ? VT / 4 : 0);    // uint4 per 64-point tile
+    constexpr int NI = RU + (kFp8 ? 1 : 0);                  // wave copy instructions per tile
+    constexpr int L = (NI + 3) / 4;                          // copy instructions per wave per tile
+    // tiles per ring stage: two (one barrier per 128 points) when two
+    // stages of them fit the 64 KB a workgroup may hold
+    constexpr int SUBT = 4 * STAGE1 * 16 + 1024 <= 65536 ? 2 : 1;
+    __shared__ uint4 ring0[SUBT * STAGE1];
+    __shared__ uint4 ring1[SUBT * STAGE1];
     __shared__ int32_t rmem[4][64];  // per wave: member row of each of its 64 rows (-1: padding)
 
     const int64_t n_win = sc.n_groups[2];
@@ -959,8 +962,12 @@ k_es_regs(const uint4* __restrict__ xq, const float* __restrict__ hn, const int*
             const int64_t v = (t_begin + t) * VT + lane;
             return (t < nt && v >= v_begin && v < v_end) ? float(0.5 * m0[v] - double(hn[v])) : -INFINITY;
         };
-        float wsh_next = shift_of(0);
-        if (nt > 0) copy_stage(t_begin, ring0);
+        float wsh_nx[SUBT];  // shifts of the next stage's tiles (in flight)
+#pragma unroll
+        for (int q = 0; q < SUBT; ++q) wsh_nx[q] = shift_of(q);
+#pragma unroll
+        for (int q = 0; q < SUBT; ++q)
+            if (q < nt) copy_stage(t_begin + q, ring0 + q * STAGE1);
         // Software-pipelined over column blocks: while the MFMAs of column
         // block 0 of tile t run, the lane takes the unit maxima of column
         // block 1 of tile t-1, pairs them with those of its block 0 (taken
@@ -997,12 +1004,8 @@ k_es_regs(const uint4* __restrict__ xq, const float* __restrict__ hn, const int*
                     acc[mb][cb] = mfma_main<DT>(&a[mb][q * T::kU4], &b[q * T::kU4], acc[mb][cb], sa[mb], sb);
         };
         constexpr int NMF = 2 * KC;  // matrix instructions per column block
-        auto tile = [&](int64_t t, const uint4* st, uint4* next) {
-            wait_vmcnt<0>();  // this tile's copies (issued one tile ago) and its shift loads
-            ring_barrier();   // ... of every wave; every wave is done reading the other stage
-            const float wsh = wsh_next;
-            wsh_next = shift_of(t + 1);
-            if (t + 1 < nt) copy_stage(t_begin + t + 1, next);
+        // one 64-point tile from its place st in a stage
+        auto tile = [&](const uint4* st, float wsh) {
             const int* st_sc = reinterpret_cast<const int*>(st + OFF_SC);
             uint4 b[HU];
             // column block 0 of tile t, with the maxima of block 1 of tile t-1
@@ -1029,10 +1032,28 @@ k_es_regs(const uint4* __restrict__ xq, const float* __restrict__ hn, const int*
             }
             wsh_prev = wsh;
         };
-        // stage of tile t: t % 2 (distinct LDS objects)
-        for (int64_t t = 0; t < nt; t += 2) {
-            tile(t, ring0, ring1);
-            if (t + 1 < nt) tile(t + 1, ring1, ring0);
+        // ring stage t: tiles SUBT t .. SUBT t + SUBT - 1
+        auto stage = [&](int64_t t, const uint4* st, uint4* next) {
+            wait_vmcnt<0>();  // this stage's copies (issued one stage ago) and its shift loads
+            ring_barrier();   // ... of every wave; every wave is done reading the other stage
+            float wsh[SUBT];
+#pragma unroll
+            for (int q = 0; q < SUBT; ++q) {
+                wsh[q] = wsh_nx[q];
+                wsh_nx[q] = shift_of(SUBT * (t + 1) + q);
+            }
+#pragma unroll
+            for (int q = 0; q < SUBT; ++q)
+                if (SUBT * (t + 1) + q < nt) copy_stage(t_begin + SUBT * (t + 1) + q, next + q * STAGE1);
+#pragma unroll
+            for (int q = 0; q < SUBT; ++q)
+                if (q == 0 || SUBT * t + q < nt) tile(st + q * STAGE1, wsh[q]);
+        };
+        // stage t: ring t % 2 (distinct LDS objects)
+        const int64_t nst = (nt + SUBT - 1) / SUBT;
+        for (int64_t t = 0; t < nst; t += 2) {
+            stage(t, ring0, ring1);
+            if (t + 1 < nst) stage(t + 1, ring1, ring0);
         }
         // the last tile
         {
