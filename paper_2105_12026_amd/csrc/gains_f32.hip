@@ -131,6 +131,12 @@ __device__ __forceinline__ void gains_f32_body(const GainsArgs& ga, int64_t bid)
     float acc_sum[16];
 #pragma unroll
     for (int r = 0; r < 16; ++r) acc_sum[r] = 0.0f;
+    // the previous column block, its clamp-and-sum still to do (none yet:
+    // -inf clamps to +0, which leaves the sums as they are)
+    floatx16 accP;
+    float hmP = 0.0f;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) accP[r] = -INFINITY;
 
     // ---- stream the ground-set chunk ----
     const int64_t v_begin = int64_t(split) * chunk;
@@ -181,23 +187,39 @@ __device__ __forceinline__ void gains_f32_body(const GainsArgs& ga, int64_t bid)
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc[r] = nhn[r] + hav;
             const float4* b4 = reinterpret_cast<const float4*>(lds_x + vrow * S + half * KH);
+            // The previous block's clamp-and-sum is issued in slices between
+            // groups of this block's MFMAs (it does not depend on them, and
+            // the sums keep their block order); the next group's operand read
+            // is issued before each group.
+            constexpr int SL = QF > 0 ? (16 + QF - 1) / QF : 16;  // terms per group
+            float4 bv = b4[0];
 #pragma unroll
             for (int q = 0; q < QF; ++q) {
-                const float4 bv = b4[q];
+                const float4 bn = q + 1 < QF ? b4[q + 1] : bv;
                 acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a[4 * q + 0], bv.x, acc, 0, 0, 0);
                 acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a[4 * q + 1], bv.y, acc, 0, 0, 0);
                 acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a[4 * q + 2], bv.z, acc, 0, 0, 0);
                 acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a[4 * q + 3], bv.w, acc, 0, 0, 0);
+#pragma unroll
+                for (int r = q * SL; r < (q + 1) * SL && r < 16; ++r)
+                    acc_sum[r] += __builtin_amdgcn_fmed3f(accP[r], 0.0f, hmP);
+                __builtin_amdgcn_sched_barrier(0);
+                bv = bn;
             }
             if constexpr (TRIM) {
-                const float2 bv = *reinterpret_cast<const float2*>(lds_x + vrow * S + (half ? KH - 2 : KH - 4));
-                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a[KH - 4], bv.x, acc, 0, 0, 0);
-                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a[KH - 3], bv.y, acc, 0, 0, 0);
+                const float2 bt = *reinterpret_cast<const float2*>(lds_x + vrow * S + (half ? KH - 2 : KH - 4));
+                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a[KH - 4], bt.x, acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a[KH - 3], bt.y, acc, 0, 0, 0);
             }
 #pragma unroll
-            for (int r = 0; r < 16; ++r) acc_sum[r] += __builtin_amdgcn_fmed3f(acc[r], 0.0f, hmv);
+            for (int r = QF * SL; r < 16; ++r) acc_sum[r] += __builtin_amdgcn_fmed3f(accP[r], 0.0f, hmP);  // QF = 0
+            accP = acc;
+            hmP = hmv;
         }
     }
+    // the last block's clamp-and-sum
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc_sum[r] += __builtin_amdgcn_fmed3f(accP[r], 0.0f, hmP);
 
     // ---- sum over the 32 columns (ground points) of each half, in float64 ----
     // Lane (half*32 + r), r < 16, keeps the total of candidate row
