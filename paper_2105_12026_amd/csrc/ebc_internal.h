@@ -286,7 +286,7 @@ __host__ __device__ inline GainsArgs gains_args(const InstDesc& d, const int32_t
 }
 
 // Batched launches over a device table of descriptors (see ebc_batch).
-hipError_t launch_gains_f32_batched(int32_t k_pad, const InstDesc* descs, const int32_t* slot_inst,
+hipError_t launch_gains_f32_batched(int32_t k_pad, bool trim, const InstDesc* descs, const int32_t* slot_inst,
                                     const int64_t* wg_pre, int32_t slots, int64_t total_wgs, int32_t t,
                                     hipStream_t s);
 hipError_t launch_gains_lp_batched(int32_t dt, int32_t kc, int32_t variant, const InstDesc* descs,

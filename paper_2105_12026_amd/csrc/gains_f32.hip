@@ -246,14 +246,14 @@ __global__ void __launch_bounds__(256) k_gains_f32(GainsArgs ga) {
 
 // Batched: workgroups wg_pre[j] .. wg_pre[j+1] serve descriptor slot_inst[j]
 // (all candidates, in the same geometry as a solo launch).
-template <int KP>
+template <int KP, bool TRIM>
 __global__ void __launch_bounds__(256)
 kb_gains_f32(const InstDesc* __restrict__ descs, const int32_t* __restrict__ slot_inst,
              const int64_t* __restrict__ wg_pre, int32_t slots, int32_t t) {
     const int j = find_slot(wg_pre, slots, blockIdx.x);
     const InstDesc c = descs[slot_inst[j]];
     if (c.t0 + t >= c.k) return;
-    gains_f32_body<KP, false>(gains_args(c, nullptr, c.n_pad), int64_t(blockIdx.x) - wg_pre[j]);
+    gains_f32_body<KP, TRIM>(gains_args(c, nullptr, c.n_pad), int64_t(blockIdx.x) - wg_pre[j]);
 }
 
 template <int KP>
@@ -261,8 +261,7 @@ static void launch_kp(const ebc_dataset* ds, const int32_t* cand, int64_t n_cand
     const int64_t tiles = (n_cand + kGainsCandTile - 1) / kGainsCandTile;
     InstDesc c;
     fill_desc(ds, 0, nullptr, nullptr, nullptr, &c);
-    // the instances in a batch may differ in d, so only a solo launch trims
-    if (ds->d <= KP - 4)
+    if (ds->d <= KP - 4)  // the rows' last 4 padded slots are empty
         hipLaunchKernelGGL((k_gains_f32<KP, true>), dim3(unsigned(tiles * ds->v_splits)), dim3(256), 0, s,
                            gains_args(c, cand, n_cand));
     else
@@ -284,14 +283,19 @@ hipError_t launch_gains_f32(const ebc_dataset* ds, const int32_t* cand, int64_t 
     return hipGetLastError();
 }
 
-hipError_t launch_gains_f32_batched(int32_t k_pad, const InstDesc* descs, const int32_t* slot_inst,
+// trim: every instance of the bucket has d <= k_pad - 4 (the bucket key says so)
+hipError_t launch_gains_f32_batched(int32_t k_pad, bool trim, const InstDesc* descs, const int32_t* slot_inst,
                                     const int64_t* wg_pre, int32_t slots, int64_t total_wgs, int32_t t,
                                     hipStream_t s) {
     switch (k_pad) {
-#define EBC_KP(K)                                                                                          \
-    case K:                                                                                                \
-        hipLaunchKernelGGL(kb_gains_f32<K>, dim3(unsigned(total_wgs)), dim3(256), 0, s, descs, slot_inst, \
-                           wg_pre, slots, t);                                                              \
+#define EBC_KP(K)                                                                                             \
+    case K:                                                                                                   \
+        if (trim)                                                                                             \
+            hipLaunchKernelGGL((kb_gains_f32<K, true>), dim3(unsigned(total_wgs)), dim3(256), 0, s, descs,    \
+                               slot_inst, wg_pre, slots, t);                                                  \
+        else                                                                                                  \
+            hipLaunchKernelGGL((kb_gains_f32<K, false>), dim3(unsigned(total_wgs)), dim3(256), 0, s, descs,   \
+                               slot_inst, wg_pre, slots, t);                                                  \
         break;
         EBC_F32_KPS(EBC_KP)
 #undef EBC_KP

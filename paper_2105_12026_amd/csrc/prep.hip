@@ -43,9 +43,12 @@ int64_t gains_cand_tile(const ebc_dataset* ds) {
 }
 
 int32_t gains_bucket(const ebc_dataset* ds) {
-    // last digit: the tile variant (reduced precision) or, for long rows, the K split
+    // last digit: the tile variant (reduced precision), for long rows the K
+    // split, for float32 whether the rows' last 4 padded slots are empty (the
+    // kernel then shortens its last K step)
     if (wide_rows(ds->k_pad)) return int32_t(ds->dt) * 100000 + ds->k_pad * 10 + wide_ksplit(ds->n_pad);
-    return int32_t(ds->dt) * 100000 + ds->k_pad * 10 + (ds->dt == EBC_DT_F32 ? 0 : ds->variant);
+    const int32_t last = ds->dt == EBC_DT_F32 ? (ds->d <= ds->k_pad - 4 ? 1 : 0) : ds->variant;
+    return int32_t(ds->dt) * 100000 + ds->k_pad * 10 + last;
 }
 
 void fill_desc(const ebc_dataset* ds, int32_t k, int32_t* sel, double* f, double* gain, InstDesc* out) {
@@ -76,7 +79,7 @@ hipError_t launch_gains_batched(int32_t bucket, const InstDesc* descs, const int
     if (wide_rows(k_pad))
         return launch_gains_wide_batched(dt, variant, descs, slot_inst, wg_pre, slots, total_wgs, t, s);
     if (dt == EBC_DT_F32)
-        return launch_gains_f32_batched(k_pad, descs, slot_inst, wg_pre, slots, total_wgs, t, s);
+        return launch_gains_f32_batched(k_pad, variant == 1, descs, slot_inst, wg_pre, slots, total_wgs, t, s);
     const int32_t kc = k_pad / (dt == EBC_DT_FP8_E4M3 ? 64 : 16);
     return launch_gains_lp_batched(dt, kc, variant, descs, slot_inst, wg_pre, slots, total_wgs, t, s);
 }

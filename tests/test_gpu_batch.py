@@ -19,6 +19,8 @@ pytestmark = pytest.mark.gpu
 MIX = [(300, 16, "f32", 0, 5), (1000, 100, "bf16", 0, 7), (2500, 64, "bf16", 2, 12), (700, 5, "fp8", 0, 3),
        (1500, 33, "f16", 1, 0), (4000, 128, "f32", 0, 9), (257, 64, "bf16", 0, 4), (2049, 64, "fp8", 2, 6),
        (3100, 64, "bf16", 3, 8), (1800, 128, "fp8", 3, 5), (2300, 112, "f16", 3, 6),
+       # float32 rows whose last 4 padded slots are empty (shortened last K step)
+       (1300, 100, "f32", 0, 6), (800, 3, "f32", 0, 4),
        # long rows (padded length above 128)
        (1000, 300, "f32", 0, 6), (900, 200, "bf16", 1, 5), (500, 520, "fp8", 0, 4)]
 
