@@ -80,8 +80,21 @@ __device__ __forceinline__ void gains_f32_body(const GainsArgs& ga, int64_t bid)
     const int col = lane & 31;  // MFMA column within a 32-block
     const int half = lane >> 5;
 
-    const int split = int(bid % v_splits);
-    const int64_t ctile = bid / v_splits;
+    // (candidate tile, ground chunk) of this workgroup. Consecutive ids go to
+    // the 8 XCDs in turn; with 8 G chunks, XCD x takes chunks x, x + 8, ...
+    // one after the other (every candidate tile of chunk x first), so its L2
+    // holds one chunk's rows at a time. 8 chunks: chunk = id % 8.
+    int split;
+    int64_t ctile;
+    if (v_splits % 8 == 0) {
+        const int64_t ntiles = (n_cand + kGainsCandTile - 1) / kGainsCandTile;
+        const int64_t r = bid / 8;
+        split = int(bid % 8) + 8 * int(r / ntiles);
+        ctile = r % ntiles;
+    } else {
+        split = int(bid % v_splits);
+        ctile = bid / v_splits;
+    }
 
     // ---- candidate rows of this wave, in registers (MFMA A operand) ----
     const int64_t cpos = ctile * kGainsCandTile + wave * 32 + col;  // position in the candidate list
